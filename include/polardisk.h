@@ -1,0 +1,238 @@
+/*
+ * polardisk.h -- C ABI of the MI355X θ-scheme solver for the singular
+ * parabolic equation and the drift-diffusion continuity equation on the unit
+ * disk in polar coordinates (Zhang, Zhang, Song, Fang, "A Multidimensional
+ * Self-Adaptive Numerical Simulation Framework for Semiconductor Boltzmann
+ * Transport Equation", arXiv:2509.15879).
+ *
+ * What one time step computes.  With the implicit weight θ = 1 - a (a is the
+ * weight of the old level in scheme (2.5) of §2.1 and in the Ch. 3 scheme of
+ * §3.2.1) every step solves
+ *
+ *     (I/Δt + θ L_h) n^{k+1} = (I/Δt - (1-θ) L_h) n^k
+ *                              + (1-θ) S(t_k) + θ S(t_{k+1}) + boundary terms,
+ *
+ * i.e. the linear system (2.11)/(2.12) of §2.2 and its Ch. 3 form (§3.2.3).
+ * L_h is the conservative five-point polar operator: the diffusion part of
+ * ϖ_h (§3.2.1, which reduces to ℘_h of §2.1 for D = 1), a face-flux drift
+ * term for the vector field E = (E_r, E_θ), a reaction term b, and the
+ * control-volume origin closure of §3.2.2 (the Swarztrauber-Sweet row of
+ * §2.1 for D = 1, E = 0).  Meshes: the radial stretch (2.4), the angular and
+ * time stretches of §3.1, the comparison stretch (2.13), or explicit nodes.
+ *
+ * Conventions.
+ *  - Every function returns an int status: PD_OK (0) or a negative PD_E*
+ *    code (PD_PENDING = 1 only from pd_batch_poll).  Nothing throws or
+ *    aborts.  pd_last_error() returns a message for the calling thread's
+ *    last failure (valid until that thread's next call).
+ *  - Handles are opaque and owned by the library until pd_destroy /
+ *    pd_batch_destroy.  Inputs are copied at create/submit time, so the
+ *    caller may free them on return.  Output buffers belong to the caller.
+ *  - Node vectors have N = m*n + 1 entries (the origin plus m rings of n
+ *    angular nodes).  Layout PD_LAYOUT_RING: index 0 is the origin and node
+ *    (i, j), i = 1..m, j = 0..n-1, sits at 1 + (i-1)*n + j.  Layout
+ *    PD_LAYOUT_PAPER is the ordering of (2.12): index 0 is the origin and
+ *    (i, j) sits at 1 + j*m + (i-1).
+ *  - Face arrays are row-major.  Radial faces "i+1/2" (i = 0..m, face 0 joins
+ *    the origin to ring 1, face m joins ring m to the boundary r = 1) are
+ *    sampled at (r_{i+1/2}, θ_j) and stored at [i*n + j].  Angular faces
+ *    "j+1/2" of ring i (i = 1..m, joining (i, j) and (i, j+1 mod n)) are
+ *    sampled at (r_i, θ_{j+1/2}) and stored at [(i-1)*n + j].  The sample
+ *    points come from pd_mesh_coords.
+ *  - Pointers are host pointers unless a `device_ptrs`/`device_ptr` flag
+ *    says they are device pointers (for instance torch tensor data_ptr()).
+ *  - Errors: PD_EINVAL for bad arguments (m < 2, n < 4, θ outside (0, 1],
+ *    Δt <= 0, non-monotone explicit meshes, NULL where data is required),
+ *    PD_ENOMEM when device memory or the batch pool is exhausted, PD_EHIP
+ *    for a HIP runtime failure, PD_EBREAKDOWN / PD_ENOCONV when the Krylov
+ *    solve of some step broke down or hit its iteration cap, PD_EBUSY when an
+ *    instance is owned by a running batch.
+ */
+#ifndef POLARDISK_H
+#define POLARDISK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_instance pd_instance;
+typedef struct pd_batch pd_batch;
+
+enum {
+  PD_OK = 0,
+  PD_PENDING = 1,
+  PD_EINVAL = -1,
+  PD_ENOMEM = -2,
+  PD_EBREAKDOWN = -3,
+  PD_ENOCONV = -4,
+  PD_EHIP = -5,
+  PD_EBUSY = -6
+};
+
+typedef enum { PD_PARABOLIC = 0, PD_CONTINUITY = 1 } pd_pde;
+
+/* PD_FP64: every vector, coefficient and Krylov scalar in FP64.
+ * PD_MIXED: FP64 right-hand side, outer residual, origin-row sum and
+ * tridiagonal pivots; the inner BiCGSTAB (stencil, sweeps, vectors) runs in
+ * FP32 and is refined until the FP64 residual meets the tolerance.        */
+typedef enum { PD_FP64 = 0, PD_MIXED = 1 } pd_precision;
+
+enum { PD_MESH_UNIFORM = 0, PD_MESH_SINE = 1, PD_MESH_EXPLICIT = 2, PD_MESH_POLY = 3 };
+enum { PD_LAYOUT_RING = 0, PD_LAYOUT_PAPER = 1 };
+enum { PD_TIME_UNIFORM = 0, PD_TIME_SINE = 1, PD_TIME_TABLE = 2 };
+
+/* Mesh (§2.1 "region divided", §3.1 stretching equations).
+ *   r_kind: PD_MESH_UNIFORM r_i = i h; PD_MESH_SINE r_i = sin((i h)^p π/2)
+ *           (eq. (2.4)); PD_MESH_POLY r_i = 1 - (1 - i h)^{p+1} (eq. (2.13));
+ *           PD_MESH_EXPLICIT: r_explicit holds r_0..r_{m+1} (host, strictly
+ *           increasing, r_0 = 0, r_{m+1} = 1).  h = 1/(m+1).
+ *   th_kind: PD_MESH_UNIFORM θ_j = 2πj/n; PD_MESH_SINE θ_j = 2π sin((j/n)^q π/2)
+ *           (§3.1 angular stretch); PD_MESH_EXPLICIT: th_explicit holds
+ *           θ_0..θ_n (host, strictly increasing, θ_0 = 0, θ_n = 2π).
+ *   nr = m >= 2 unknown rings, ntheta = n >= 4 angular nodes.             */
+typedef struct {
+  int32_t nr, ntheta;
+  int32_t r_kind;
+  double p;
+  int32_t th_kind;
+  double q;
+  const double *r_explicit;
+  const double *th_explicit;
+} pd_mesh_desc;
+
+/* PDE data (eqs. (2.1)-(2.3), (3.1)-(3.4)): n_t + L n = S(t) with
+ * L n = -∇·(D∇n) + ∇·(nE) + b n and Dirichlet data N(t, θ) on r = 1.
+ *   pde:  PD_PARABOLIC or PD_CONTINUITY (informational; both use the arrays).
+ *   flux: 0 central drift average (n_P + n_Q)/2 (the origin choice of
+ *         §3.2.2), 1 upwind drift.
+ *   bc:   0 Dirichlet on r = 1, 1 zero flux through r = 1.
+ *   D_rface, Er_rface: (m+1)*n radial-face samples, NULL means D = 1 / E_r = 0.
+ *   D_tface, Et_tface: m*n angular-face samples, NULL means D = 1 / E_θ = 0.
+ *   b_node: N node values in `layout` (NULL means b = 0).
+ *   Time modes q = 0..nsrc-1 (nsrc <= 4): τ_q(t) = t^{tpow_q} exp(λ_q t),
+ *   S(t) = Σ_q τ_q(t) g_q with g: nsrc*N node values in `layout` (the origin
+ *   entry is the source's limit at r = 0, §3.2.2 source integral), and
+ *   N(t, θ_j) = Σ_q τ_q(t) nb_q[j] with nb: nsrc*n values (NULL means 0).
+ *   tpow may be NULL (all 0).
+ *   u0: N initial values in `layout` (eq. (2.10) / (3.3)).
+ *   device_ptrs: 1 if every array above is a device pointer.             */
+typedef struct {
+  int32_t pde;
+  int32_t flux;
+  int32_t bc;
+  int32_t layout;
+  int32_t device_ptrs;
+  const double *b_node;
+  const double *D_rface, *Er_rface;
+  const double *D_tface, *Et_tface;
+  int32_t nsrc;
+  const double *lambda;
+  const int32_t *tpow;
+  const double *g;
+  const double *nb;
+  const double *u0;
+} pd_problem_desc;
+
+/* Time levels (§2.1 Δt = T/K; §3.1 t_k = V(k T/K), V(t) = T sin((t/T)^l π/2);
+ * or an explicit table t_0..t_K, host, strictly increasing).  The solve
+ * starts from the instance's current state and time, which must equal t_0.
+ *   theta: implicit weight θ = 1 - a in (0, 1]; 0.5 is Crank-Nicolson,
+ *          1 is backward Euler.
+ *   tol:   per-step stopping tolerance on ||b - A x||_2 / ||b||_2 (FP64).
+ *   max_iters: cap on BiCGSTAB iterations per step (0: library default).  */
+typedef struct {
+  int32_t t_kind;
+  int32_t K;
+  double T, l;
+  const double *t_table;
+  double theta;
+  double tol;
+  int32_t max_iters;
+} pd_time_desc;
+
+typedef struct {
+  int32_t iters;        /* Krylov iterations (inner, for PD_MIXED)         */
+  int32_t refinements;  /* FP64 outer refinements (PD_MIXED), else 0       */
+  int32_t status;       /* PD_OK, PD_EBREAKDOWN or PD_ENOCONV              */
+  int32_t reserved;
+  double rel_resid;     /* final ||b - A x|| / ||b|| in FP64               */
+  double dt, t;         /* step size and the time reached                  */
+} pd_step_stats;
+
+/* Mesh nodes and face sample points of a mesh description: r_nodes r_0..r_{m+1}
+ * (m+2), r_faces r_{1/2}..r_{m+1/2} (m+1), th_nodes θ_0..θ_n (n+1), th_faces
+ * θ_{1/2}..θ_{n-1/2} (n), all host buffers owned by the caller (any may be
+ * NULL).  Pure host computation (§2.1, §3.1 mesh formulas).              */
+int pd_mesh_coords(const pd_mesh_desc *mesh, double *r_nodes, double *r_faces,
+                   double *th_nodes, double *th_faces);
+
+/* Creates an instance: builds the mesh, turns the sampled coefficients into
+ * face conductances and drift coefficients, uploads everything to the
+ * current HIP device, and sets the state to u0 at t = 0.  hip_stream may be
+ * NULL (the library then owns a default-priority stream).                */
+int pd_mesh_create(const pd_mesh_desc *mesh, const pd_problem_desc *problem,
+                   int32_t precision, void *hip_stream, pd_instance **out);
+
+/* One θ-scheme step from the current state at t_k to t_k + dt. */
+int pd_scheme_step(pd_instance *inst, double t_k, double dt, double theta, double tol,
+                   pd_step_stats *stats);
+
+/* All K steps of a time description; per_step (K entries) may be NULL. */
+int pd_solve_to_T(pd_instance *inst, const pd_time_desc *time, pd_step_stats *per_step);
+
+/* Advances several instances together: every kernel launch covers all of
+ * them (uneven sizes and PDE types allowed).  times[i] belongs to insts[i];
+ * final_stats (count entries, may be NULL) receives each instance's last
+ * step.  All instances must share one stream.  Results are identical to
+ * solving each instance alone.                                           */
+int pd_solve_batch(pd_instance *const *insts, int32_t count, const pd_time_desc *times,
+                   pd_step_stats *final_stats);
+
+/* Current state n^k (N values) in the requested layout. */
+int pd_get_solution(const pd_instance *inst, double *out, int32_t layout, int32_t device_ptr);
+
+/* Replaces the state by `in` (N values) at time t (checkpoint resume). */
+int pd_set_solution(pd_instance *inst, const double *in, int32_t layout, int32_t device_ptr,
+                    double t);
+
+/* Diagnostics on the same kernels the solver uses:
+ *   pd_apply_operator: y = (I/dt + θ L_h) x with the homogeneous boundary
+ *   (N = 0), in FP64 (precision 0) or through the FP32 inner stencil (1).
+ *   pd_assemble_rhs: the right-hand side of the step t_k -> t_k + dt from the
+ *   current state (§2.2 eq. (2.11), §3.2.3 e_ij).                         */
+int pd_apply_operator(pd_instance *inst, double dt, double theta, const double *x, double *y,
+                      int32_t layout, int32_t device_ptrs, int32_t precision);
+int pd_assemble_rhs(pd_instance *inst, double t_k, double dt, double theta, double *rhs,
+                    int32_t layout, int32_t device_ptr);
+
+/* Device bytes an instance of this mesh and precision occupies. */
+int pd_footprint(const pd_mesh_desc *mesh, int32_t nsrc, int32_t precision, size_t *bytes);
+
+int pd_destroy(pd_instance *inst);
+
+/* Serving: a request loop that admits solves by device-memory footprint into
+ * a pool of hbm_pool_bytes, runs every admitted request in the same batched
+ * launches (continuous batching: requests join and leave at time-level
+ * boundaries), and hands results back through pd_batch_poll.
+ * pd_batch_submit copies the inputs and never blocks on the GPU; it returns
+ * PD_ENOMEM if the request can never fit the pool.  pd_batch_poll returns
+ * PD_PENDING until the request is finished, then PD_OK (or the solve's
+ * error) and copies the final state (N values, ring layout, host) to out
+ * (may be NULL) and its statistics to summary (may be NULL); a finished
+ * ticket is released by the poll that reports it.                        */
+int pd_batch_create(size_t hbm_pool_bytes, int32_t max_slots, void *hip_stream, pd_batch **out);
+int pd_batch_submit(pd_batch *batch, const pd_mesh_desc *mesh, const pd_problem_desc *problem,
+                    const pd_time_desc *time, int32_t precision, uint64_t *ticket);
+int pd_batch_poll(pd_batch *batch, uint64_t ticket, double *out, pd_step_stats *summary);
+int pd_batch_destroy(pd_batch *batch);
+
+const char *pd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLARDISK_H */
