@@ -1,0 +1,90 @@
+// Device-side data structures shared by the HIP kernels and the host runtime
+// of the polar-disk θ-scheme solver.
+//
+// Internal vector layout (per instance): ring-major, node (i, j) of ring
+// i = 1..m at (i-1)*n + j, the origin at m*n, padded with zeros to npad.
+// Face arrays hold, per face, the two coefficients of the numerical flux
+// from its inner/lower node P to its outer/upper node Q:
+//     F = gp * x_P - gm * x_Q,
+// with gp = G + K/2, gm = G - K/2 for the central drift average and
+// gp = G + max(K,0), gm = G - min(K,0) for upwinding (G the diffusive
+// conductance, K the drift coefficient of the face).  Radial face i+1/2
+// (i = 0..m) is stored at i*n + j, angular face j+1/2 of ring i at
+// (i-1)*n + j.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PD_MAXSRC 4
+#define PD_RB 16          // rows per stencil tile (one wave = 64 columns x PD_RB rows)
+#define PD_STEN_WAVES 4   // tiles per stencil block
+#define PD_ELEM_PER_BLOCK 1024
+#define PD_RAD_THREADS 1024
+#define PD_RAD_BMAX 32    // max rows per radial segment held in registers
+#define PD_ANG_BMAX 32    // max angular nodes per lane held in registers
+#define PD_NSLOT 4
+
+enum { ST_IDLE = 0, ST_ACTIVE = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOCONV = 4 };
+enum { PH_INNER = 0, PH_OUTER = 1 };
+
+// Counter slots (per instance) for the last-block reductions.
+enum { CNT_BEGIN = 0, CNT_V = 1, CNT_T = 2, CNT_X = 3, CNT_UR = 4, CNT_APPLY = 5, CNT_N = 8 };
+
+struct PdScalars {
+  // time level
+  double t0, t1, dt, inv_dt, theta, extrap;
+  double cq[PD_MAXSRC];
+  double tol, tol_inner;
+  double fact_dt, fact_theta, prev_dt;
+  int maxit, level, K, refactor;
+  int status, phase, iters, outer;
+  int inner_iters, restarts, first, reset_rh;
+  int inner_first, have_prev, rot, nfail;
+  int max_outer, maxit_inner, total_iters, pad1;
+  // Krylov scalars
+  double rho_old, rho_new, alpha, omega;
+  double bnorm2, rnorm2, r0norm2;
+  double rel_resid;
+  double t_now;
+};
+
+template <typename T>
+struct KSet {
+  T *r, *rh, *p, *v, *ph, *s, *sh, *t, *w;
+  T *d;                              // inner iterate (mixed precision only)
+  const T *gp_r, *gm_r, *gp_t, *gm_t;  // faces
+  T *rf_f, *rf_g;                    // radial factors (multipliers)
+  T *af_f, *af_g, *af_z;             // angular factors (multipliers, SM vector)
+};
+
+struct PdInst {
+  int m, n, npad, nsrc;
+  int K, mixed, has_b, zero_flux;
+  int ncg, nrg, nb_sten, nb_elem;    // stencil tiling and block counts
+  int cw, nseg, brad, nb_rad;        // radial sweep: columns per block, segments, rows/segment
+  int bang, nb_ang, nb_frad, nb_fang;
+  double inv_V0;
+  const double *inv_rw;     // [m+2] 1/(r_i (h_i+h_{i+1})/2), index i
+  const double *inv_dth;    // [n]   1/Δθ_j
+  const double *b_node;     // [npad] or null
+  const double *g;          // [nsrc*npad]
+  const double *nb;         // [nsrc*n]
+  const double *lam;        // [nsrc]
+  const int *tpow;          // [nsrc]
+  const double *t_table;    // [K+1]
+  double *sol[3];           // rotating: n^{k-1}, n^k, iterate
+  double *bvec;             // right-hand side (FP64)
+  double *rout;             // FP64 outer residual (mixed)
+  double *diag;             // [npad] diagonal of I/dt + θL
+  double *rf_uinv;          // [m*n] radial pivots 1/u (FP64 in both precisions)
+  double *af_uinv;          // [m*n] angular pivots
+  double *af_kappa, *af_alpha0;   // [m] Sherman-Morrison scalars per ring
+  KSet<double> k64;
+  KSet<float> k32;
+  double *partials;         // [PD_NSLOT * max(nb_sten, nb_elem)]
+  unsigned *counters;       // [CNT_N]
+  PdScalars *sc;
+  int *n_active;            // shared counter of the batch (device)
+  double *level_stats;      // [K * 8]: iters, outer, status, rel_resid, dt, t1, restarts, 0
+};

@@ -1,0 +1,975 @@
+// Host runtime of the polar-disk θ-scheme solver: C ABI (include/polardisk.h),
+// mesh construction, coefficient preparation, device memory, the batched
+// level driver, and the continuous-batching request loop.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/polardisk.h"
+#include "pd_device.h"
+#include "pd_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(PD_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+constexpr int kMaxM = 2048;
+constexpr int kMaxN = 2048;
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------------ mesh
+
+// §2.1 / §3.1: h = 1/(m+1), r_i = υ(i h) with υ from (2.4) or (2.13); the
+// end points are exact.
+int radial_nodes(const pd_mesh_desc &d, std::vector<double> &r) {
+  const int m = d.nr;
+  r.assign(m + 2, 0.0);
+  const double h = 1.0 / (m + 1);
+  for (int i = 0; i <= m + 1; ++i) {
+    const double s = i * h;
+    switch (d.r_kind) {
+      case PD_MESH_UNIFORM: r[i] = s; break;
+      case PD_MESH_SINE: r[i] = std::sin(std::pow(s, d.p) * kPi / 2.0); break;
+      case PD_MESH_POLY: r[i] = 1.0 - std::pow(1.0 - s, d.p + 1.0); break;
+      case PD_MESH_EXPLICIT:
+        if (!d.r_explicit) return fail(PD_EINVAL, "r_explicit is NULL");
+        r[i] = d.r_explicit[i];
+        break;
+      default: return fail(PD_EINVAL, "unknown r_kind %d", d.r_kind);
+    }
+  }
+  if ((d.r_kind == PD_MESH_SINE || d.r_kind == PD_MESH_POLY) && !(d.p > 0.0))
+    return fail(PD_EINVAL, "stretch exponent p must be > 0 (got %g)", d.p);
+  r[0] = 0.0;
+  r[m + 1] = 1.0;
+  for (int i = 1; i <= m + 1; ++i)
+    if (!(r[i] > r[i - 1])) return fail(PD_EINVAL, "radial nodes not strictly increasing at %d", i);
+  return PD_OK;
+}
+
+// §3.1 angular stretch: θ_j = v(j μ̃), v(ι) = 2π sin((ι/2π)^q π/2).
+int angular_nodes(const pd_mesh_desc &d, std::vector<double> &th) {
+  const int n = d.ntheta;
+  th.assign(n + 1, 0.0);
+  for (int j = 0; j <= n; ++j) {
+    const double s = (double)j / n;
+    switch (d.th_kind) {
+      case PD_MESH_UNIFORM: th[j] = 2.0 * kPi * s; break;
+      case PD_MESH_SINE: th[j] = 2.0 * kPi * std::sin(std::pow(s, d.q) * kPi / 2.0); break;
+      case PD_MESH_EXPLICIT:
+        if (!d.th_explicit) return fail(PD_EINVAL, "th_explicit is NULL");
+        th[j] = d.th_explicit[j];
+        break;
+      default: return fail(PD_EINVAL, "unknown th_kind %d", d.th_kind);
+    }
+  }
+  if (d.th_kind == PD_MESH_SINE && !(d.q > 0.0))
+    return fail(PD_EINVAL, "angular stretch exponent q must be > 0 (got %g)", d.q);
+  th[0] = 0.0;
+  th[n] = 2.0 * kPi;
+  for (int j = 1; j <= n; ++j)
+    if (!(th[j] > th[j - 1])) return fail(PD_EINVAL, "angular nodes not strictly increasing at %d", j);
+  return PD_OK;
+}
+
+int check_mesh(const pd_mesh_desc *d) {
+  if (!d) return fail(PD_EINVAL, "mesh descriptor is NULL");
+  if (d->nr < 2 || d->nr > kMaxM) return fail(PD_EINVAL, "nr must be in [2, %d] (got %d)", kMaxM, d->nr);
+  if (d->ntheta < 4 || d->ntheta > kMaxN)
+    return fail(PD_EINVAL, "ntheta must be in [4, %d] (got %d)", kMaxN, d->ntheta);
+  return PD_OK;
+}
+
+struct MeshH {
+  int m = 0, n = 0;
+  std::vector<double> r, th;     // nodes
+  std::vector<double> h, rh;     // h_i (i = 1..m+1), r_{i+1/2} (i = 0..m)
+  std::vector<double> mu, dth;   // μ_j (j = 0..n, μ_0 = μ_n), Δθ_j = (μ_j + μ_{j+1})/2
+  std::vector<double> w;         // (h_i + h_{i+1})/2, i = 1..m
+};
+
+int build_mesh(const pd_mesh_desc *d, MeshH &M) {
+  int rc = check_mesh(d);
+  if (rc) return rc;
+  M.m = d->nr;
+  M.n = d->ntheta;
+  if ((rc = radial_nodes(*d, M.r))) return rc;
+  if ((rc = angular_nodes(*d, M.th))) return rc;
+  const int m = M.m, n = M.n;
+  M.h.assign(m + 2, 0.0);
+  for (int i = 1; i <= m + 1; ++i) M.h[i] = M.r[i] - M.r[i - 1];
+  M.rh.assign(m + 1, 0.0);
+  for (int i = 0; i <= m; ++i) M.rh[i] = 0.5 * (M.r[i] + M.r[i + 1]);
+  M.mu.assign(n + 1, 0.0);
+  for (int j = 1; j <= n; ++j) M.mu[j] = M.th[j] - M.th[j - 1];
+  M.mu[0] = M.mu[n];
+  M.dth.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) M.dth[j] = 0.5 * (M.mu[j] + M.mu[j + 1]);
+  M.w.assign(m + 2, 0.0);
+  for (int i = 1; i <= m; ++i) M.w[i] = 0.5 * (M.h[i] + M.h[i + 1]);
+  return PD_OK;
+}
+
+// ------------------------------------------------------------------ tiling
+
+struct Tiling {
+  int ncg, nrg, nb_sten, nb_elem, cw, nseg, brad, nb_rad, bang, nb_ang, nb_frad, nb_fang, npad;
+};
+
+Tiling make_tiling(int m, int n) {
+  Tiling t;
+  t.ncg = (n + 63) / 64;
+  t.nrg = (m + PD_RB - 1) / PD_RB;
+  t.nb_sten = (t.ncg * t.nrg + PD_STEN_WAVES - 1) / PD_STEN_WAVES;
+  const int N = m * n + 1;
+  t.nb_elem = (N + PD_ELEM_PER_BLOCK - 1) / PD_ELEM_PER_BLOCK;
+  // radial sweep: widest column group whose segments fit in registers
+  t.cw = 64;
+  while (t.cw > 8 && (m + (PD_RAD_THREADS / t.cw) - 1) / (PD_RAD_THREADS / t.cw) > PD_RAD_BMAX) t.cw /= 2;
+  t.nseg = PD_RAD_THREADS / t.cw;
+  t.brad = (m + t.nseg - 1) / t.nseg;
+  t.nb_rad = (n + t.cw - 1) / t.cw;
+  t.bang = (n + 63) / 64;
+  t.nb_ang = (m + 3) / 4;
+  t.nb_frad = (n + 63) / 64;
+  t.nb_fang = (m + 63) / 64;
+  t.npad = ((N + 63) / 64) * 64;
+  return t;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ instance
+
+struct pd_instance {
+  MeshH M;
+  Tiling T;
+  int precision = PD_FP64;
+  int pde = 0, flux = 0, bc = 0, nsrc = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  void *dmem = nullptr;
+  size_t dbytes = 0;
+  PdInst H{};            // host image of the device descriptor
+  PdScalars *sc = nullptr;   // device scalars
+  double *t_table = nullptr; // device time table (capacity kcap+1)
+  double *stats = nullptr;   // device level stats (8 * kcap)
+  int kcap = 0;
+  int rot = 0;               // host mirror of the buffer rotation
+  double t = 0.0;            // current time
+  bool have_prev = false;
+  std::atomic<int> busy{0};
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  bool dry;
+  template <typename T>
+  T *take(size_t count) {
+    size_t o = off;
+    off = align_up(off + count * sizeof(T));
+    return dry ? nullptr : reinterpret_cast<T *>(base + o);
+  }
+};
+
+// Lays out every device array of an instance; a dry run only measures.
+void carve(pd_instance *I, Carver &c) {
+  const int m = I->M.m, n = I->M.n, mn = m * n;
+  const int np = I->T.npad;
+  const int ns = std::max(1, I->nsrc);
+  PdInst &H = I->H;
+  const bool mixed = I->precision == PD_MIXED;
+  H.inv_rw = c.take<double>(m + 2);
+  H.inv_dth = c.take<double>(n);
+  H.b_node = c.take<double>(np);
+  H.g = c.take<double>((size_t)ns * np);
+  H.nb = c.take<double>((size_t)ns * n);
+  H.lam = c.take<double>(PD_MAXSRC);
+  H.tpow = c.take<int>(PD_MAXSRC);
+  for (int k = 0; k < 3; ++k) H.sol[k] = c.take<double>(np);
+  H.bvec = c.take<double>(np);
+  H.diag = c.take<double>(np);
+  H.rf_uinv = c.take<double>(mn);
+  H.af_uinv = c.take<double>(mn);
+  H.af_kappa = c.take<double>(m);
+  H.af_alpha0 = c.take<double>(m);
+  H.k64.gp_r = c.take<double>((size_t)(m + 1) * n);
+  H.k64.gm_r = c.take<double>((size_t)(m + 1) * n);
+  H.k64.gp_t = c.take<double>(mn);
+  H.k64.gm_t = c.take<double>(mn);
+  H.k64.rf_f = c.take<double>(mn);
+  H.k64.rf_g = c.take<double>(mn);
+  H.k64.af_f = c.take<double>(mn);
+  H.k64.af_g = c.take<double>(mn);
+  H.k64.af_z = c.take<double>(mn);
+  if (!mixed) {
+    H.k64.r = c.take<double>(np);
+    H.k64.rh = c.take<double>(np);
+    H.k64.p = c.take<double>(np);
+    H.k64.v = c.take<double>(np);
+    H.k64.ph = c.take<double>(np);
+    H.k64.s = c.take<double>(np);
+    H.k64.sh = c.take<double>(np);
+    H.k64.t = c.take<double>(np);
+    H.k64.w = c.take<double>(np);
+    H.rout = nullptr;
+  } else {
+    H.rout = c.take<double>(np);
+    H.k32.r = c.take<float>(np);
+    H.k32.rh = c.take<float>(np);
+    H.k32.p = c.take<float>(np);
+    H.k32.v = c.take<float>(np);
+    H.k32.ph = c.take<float>(np);
+    H.k32.s = c.take<float>(np);
+    H.k32.sh = c.take<float>(np);
+    H.k32.t = c.take<float>(np);
+    H.k32.w = c.take<float>(np);
+    H.k32.d = c.take<float>(np);
+    H.k32.gp_r = c.take<float>((size_t)(m + 1) * n);
+    H.k32.gm_r = c.take<float>((size_t)(m + 1) * n);
+    H.k32.gp_t = c.take<float>(mn);
+    H.k32.gm_t = c.take<float>(mn);
+    H.k32.rf_f = c.take<float>(mn);
+    H.k32.rf_g = c.take<float>(mn);
+    H.k32.af_f = c.take<float>(mn);
+    H.k32.af_g = c.take<float>(mn);
+    H.k32.af_z = c.take<float>(mn);
+  }
+  const int nbp = std::max(I->T.nb_sten, I->T.nb_elem);
+  H.partials = c.take<double>((size_t)PD_NSLOT * nbp);
+  H.counters = c.take<unsigned>(CNT_N);
+  I->sc = c.take<PdScalars>(1);
+  H.sc = I->sc;
+}
+
+// Input node vector (N values, `layout`) -> internal ring-major layout with
+// the origin at m*n (npad entries, zero padded).
+void to_internal(const double *src, int layout, int m, int n, int npad, double *dst) {
+  std::fill(dst, dst + npad, 0.0);
+  dst[m * n] = src[0];
+  for (int i = 1; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t s = (layout == PD_LAYOUT_PAPER) ? 1 + (size_t)j * m + (i - 1)
+                                                    : 1 + (size_t)(i - 1) * n + j;
+      dst[(size_t)(i - 1) * n + j] = src[s];
+    }
+}
+
+void from_internal(const double *src, int layout, int m, int n, double *dst) {
+  dst[0] = src[m * n];
+  for (int i = 1; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t d = (layout == PD_LAYOUT_PAPER) ? 1 + (size_t)j * m + (i - 1)
+                                                    : 1 + (size_t)(i - 1) * n + j;
+      dst[d] = src[(size_t)(i - 1) * n + j];
+    }
+}
+
+// Fetches a caller array (host or device) into a host vector.
+int fetch(const double *p, size_t count, int device_ptrs, std::vector<double> &out) {
+  out.resize(count);
+  if (!p) return fail(PD_EINVAL, "required array is NULL");
+  if (device_ptrs) {
+    HIPCHK(hipMemcpy(out.data(), p, count * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(out.data(), p, count * sizeof(double));
+  }
+  return PD_OK;
+}
+
+// Face coefficients of the numerical flux P -> Q, F = gp x_P - gm x_Q, from
+// the conductance G and the drift coefficient K of the face.
+inline void face_pair(double G, double K, int flux, double &gp, double &gm) {
+  if (flux == 0) {
+    gp = G + 0.5 * K;
+    gm = G - 0.5 * K;
+  } else {
+    gp = G + std::max(K, 0.0);
+    gm = G - std::min(K, 0.0);
+  }
+}
+
+int ensure_time_capacity(pd_instance *I, int K) {
+  if (K <= I->kcap) return PD_OK;
+  if (I->t_table) (void)hipFree(I->t_table);
+  if (I->stats) (void)hipFree(I->stats);
+  I->t_table = nullptr;
+  I->stats = nullptr;
+  const int cap = std::max(K, 16);
+  HIPCHK(hipMalloc(&I->t_table, (cap + 1) * sizeof(double)));
+  HIPCHK(hipMalloc(&I->stats, 8 * (size_t)cap * sizeof(double)));
+  I->kcap = cap;
+  I->H.t_table = I->t_table;
+  I->H.level_stats = I->stats;
+  return PD_OK;
+}
+
+int build_time_table(const pd_time_desc *td, double t_start, std::vector<double> &t) {
+  if (!td) return fail(PD_EINVAL, "time descriptor is NULL");
+  if (td->K < 1) return fail(PD_EINVAL, "K must be >= 1");
+  const int K = td->K;
+  t.assign(K + 1, 0.0);
+  if (td->t_kind == PD_TIME_TABLE) {
+    if (!td->t_table) return fail(PD_EINVAL, "t_table is NULL");
+    for (int k = 0; k <= K; ++k) t[k] = td->t_table[k];
+  } else {
+    if (!(td->T > 0.0)) return fail(PD_EINVAL, "T must be > 0");
+    for (int k = 0; k <= K; ++k) {
+      const double s = (double)k / K;
+      if (td->t_kind == PD_TIME_UNIFORM)
+        t[k] = td->T * s;
+      else if (td->t_kind == PD_TIME_SINE) {
+        if (!(td->l > 0.0)) return fail(PD_EINVAL, "time stretch exponent l must be > 0");
+        t[k] = td->T * std::sin(std::pow(s, td->l) * kPi / 2.0);
+      } else
+        return fail(PD_EINVAL, "unknown t_kind %d", td->t_kind);
+    }
+    t[0] = 0.0;
+    t[K] = td->T;
+    for (int k = 0; k <= K; ++k) t[k] += t_start;
+  }
+  for (int k = 1; k <= K; ++k)
+    if (!(t[k] > t[k - 1])) return fail(PD_EINVAL, "time levels must increase (level %d)", k);
+  if (std::fabs(t[0] - t_start) > 1e-12 * std::max(1.0, std::fabs(t_start)))
+    return fail(PD_EINVAL, "time table starts at %g but the state is at t = %g", t[0], t_start);
+  t[0] = t_start;
+  return PD_OK;
+}
+
+// ------------------------------------------------------------------ engine
+
+struct Plan {
+  pd::LaunchSet L;
+  std::vector<void *> bufs;
+  int *n_active = nullptr;
+  int *h_active = nullptr;   // pinned, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~Plan() {
+    for (void *b : bufs) (void)hipFree(b);
+    if (h_active) (void)hipHostFree(h_active);
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+template <typename F>
+int build_map(std::vector<pd_instance *> const &insts, F per_inst, std::vector<int2> &map) {
+  map.clear();
+  for (size_t q = 0; q < insts.size(); ++q) {
+    const int nb = per_inst(insts[q]);
+    for (int b = 0; b < nb; ++b) map.push_back(make_int2((int)q, b));
+  }
+  return (int)map.size();
+}
+
+int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
+  const int ninst = (int)insts.size();
+  HIPCHK(hipMalloc(&P.n_active, sizeof(int)));
+  P.bufs.push_back(P.n_active);
+  HIPCHK(hipMemsetAsync(P.n_active, 0, sizeof(int), s));
+  std::vector<PdInst> hv(ninst);
+  for (int q = 0; q < ninst; ++q) {
+    hv[q] = insts[q]->H;
+    hv[q].n_active = P.n_active;
+    P.L.mixed_any |= insts[q]->precision == PD_MIXED;
+    P.L.fp64_any |= insts[q]->precision != PD_MIXED;
+  }
+  HIPCHK(hipMalloc(&P.L.insts, ninst * sizeof(PdInst)));
+  P.bufs.push_back(P.L.insts);
+  HIPCHK(hipMemcpyAsync(P.L.insts, hv.data(), ninst * sizeof(PdInst), hipMemcpyHostToDevice, s));
+  P.L.ninst = ninst;
+  std::vector<int2> mp;
+  auto upload = [&](int2 **dst, int *cnt, auto fn) -> int {
+    *cnt = build_map(insts, fn, mp);
+    if (*cnt == 0) return PD_OK;
+    HIPCHK(hipMalloc(dst, mp.size() * sizeof(int2)));
+    P.bufs.push_back(*dst);
+    HIPCHK(hipMemcpyAsync(*dst, mp.data(), mp.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PD_OK;
+  };
+  int rc;
+  if ((rc = upload(&P.L.map_sten, &P.L.nb_sten, [](pd_instance *I) { return I->T.nb_sten; }))) return rc;
+  if ((rc = upload(&P.L.map_elem, &P.L.nb_elem, [](pd_instance *I) { return I->T.nb_elem; }))) return rc;
+  if ((rc = upload(&P.L.map_rad, &P.L.nb_rad, [](pd_instance *I) { return I->T.nb_rad; }))) return rc;
+  if ((rc = upload(&P.L.map_ang, &P.L.nb_ang, [](pd_instance *I) { return I->T.nb_ang; }))) return rc;
+  if ((rc = upload(&P.L.map_frad, &P.L.nb_frad, [](pd_instance *I) { return I->T.nb_frad; }))) return rc;
+  if ((rc = upload(&P.L.map_fang, &P.L.nb_fang, [](pd_instance *I) { return I->T.nb_fang; }))) return rc;
+  HIPCHK(hipHostMalloc((void **)&P.h_active, 2 * sizeof(int)));
+  P.h_active[0] = P.h_active[1] = 1;
+  for (auto &e : P.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return PD_OK;
+}
+
+struct SolveParams {
+  double theta, tol, tol_inner;
+  int maxit, maxit_inner, max_outer;
+};
+
+int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
+  PdScalars h{};
+  h.theta = sp.theta;
+  h.tol = sp.tol;
+  h.tol_inner = sp.tol_inner;
+  h.maxit = sp.maxit;
+  h.maxit_inner = sp.maxit_inner;
+  h.max_outer = sp.max_outer;
+  h.K = K;
+  h.level = 0;
+  h.status = ST_DONE;          // ready to start a level
+  h.rot = I->rot;
+  h.have_prev = 0;             // extrapolation restarts with each solve call
+  h.fact_dt = -1.0;
+  h.fact_theta = -1.0;
+  h.prev_dt = 0.0;
+  h.t_now = I->t;
+  HIPCHK(hipMemcpyAsync(I->sc, &h, sizeof h, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));
+  return PD_OK;
+}
+
+// Runs all levels of every instance (instance q has Ks[q] levels).
+int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &Ks,
+               std::vector<SolveParams> const &sps, hipStream_t s, std::vector<std::vector<double>> *stats_out) {
+  Plan P;
+  int rc = make_plan(insts, s, P);
+  if (rc) return rc;
+  int maxK = 0;
+  for (size_t q = 0; q < insts.size(); ++q) {
+    if ((rc = init_scalars(insts[q], sps[q], Ks[q], s))) return rc;
+    maxK = std::max(maxK, Ks[q]);
+  }
+  int max_cycles = 0;
+  for (auto &sp : sps) max_cycles = std::max(max_cycles, sp.maxit + sp.max_outer + 8);
+  for (int lev = 0; lev < maxK; ++lev) {
+    pd::launch_level_begin(P.L, s);
+    pd::launch_factor(P.L, s);
+    pd::launch_begin(P.L, s);
+    int c = 0;
+    for (; c < max_cycles; ++c) {
+      pd::launch_cycle(P.L, s);
+      HIPCHK(hipMemcpyAsync(&P.h_active[c & 1], P.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(P.ev[c & 1], s));
+      if (c >= 1) {
+        HIPCHK(hipEventSynchronize(P.ev[(c - 1) & 1]));
+        if (P.h_active[(c - 1) & 1] == 0) break;
+      }
+    }
+    HIPCHK(hipGetLastError());
+    pd::launch_level_end(P.L, s);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  int worst = PD_OK;
+  for (size_t q = 0; q < insts.size(); ++q) {
+    pd_instance *I = insts[q];
+    PdScalars h{};
+    HIPCHK(hipMemcpy(&h, I->sc, sizeof h, hipMemcpyDeviceToHost));
+    I->rot = h.rot;
+    I->t = h.t_now;
+    I->have_prev = true;
+    std::vector<double> st(8 * (size_t)Ks[q]);
+    HIPCHK(hipMemcpy(st.data(), I->stats, st.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int k = 0; k < Ks[q]; ++k) {
+      const int status = (int)st[8 * k + 2];
+      if (status == ST_BREAKDOWN) worst = PD_EBREAKDOWN;
+      else if (status != ST_DONE && worst == PD_OK) worst = PD_ENOCONV;
+    }
+    if (stats_out) (*stats_out)[q] = std::move(st);
+  }
+  if (worst == PD_EBREAKDOWN) return fail(worst, "Krylov breakdown in at least one step");
+  if (worst == PD_ENOCONV) return fail(worst, "a step did not reach the tolerance within the iteration cap");
+  return PD_OK;
+}
+
+void fill_stats(const std::vector<double> &st, int k, pd_step_stats *o) {
+  o->iters = (int)st[8 * k + 0];
+  o->refinements = (int)st[8 * k + 1];
+  const int status = (int)st[8 * k + 2];
+  o->status = status == ST_DONE ? PD_OK : (status == ST_BREAKDOWN ? PD_EBREAKDOWN : PD_ENOCONV);
+  o->reserved = (int)st[8 * k + 6];
+  o->rel_resid = st[8 * k + 3];
+  o->dt = st[8 * k + 4];
+  o->t = st[8 * k + 5];
+}
+
+SolveParams params_from(const pd_time_desc *td, int precision) {
+  SolveParams sp;
+  sp.theta = td->theta;
+  sp.tol = td->tol > 0 ? td->tol : 1e-12;
+  sp.maxit = td->max_iters > 0 ? td->max_iters : 5000;
+  sp.tol_inner = 1e-3;
+  sp.maxit_inner = 400;
+  sp.max_outer = precision == PD_MIXED ? 40 : 0;
+  return sp;
+}
+
+int validate_theta(double th) {
+  if (!(th > 0.0 && th <= 1.0)) return fail(PD_EINVAL, "theta (implicit weight 1-a) must be in (0, 1], got %g", th);
+  return PD_OK;
+}
+
+struct BusyGuard {
+  std::vector<pd_instance *> v;
+  bool ok = true;
+  explicit BusyGuard(std::vector<pd_instance *> const &insts) {
+    for (auto *I : insts) {
+      int z = 0;
+      if (!I->busy.compare_exchange_strong(z, 1)) {
+        ok = false;
+        break;
+      }
+      v.push_back(I);
+    }
+  }
+  ~BusyGuard() {
+    for (auto *I : v) I->busy = 0;
+  }
+};
+
+int solve_many(std::vector<pd_instance *> const &insts, std::vector<const pd_time_desc *> const &tds,
+               std::vector<std::vector<double>> *stats) {
+  if (insts.empty()) return fail(PD_EINVAL, "no instances");
+  BusyGuard g(insts);
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use by another call");
+  hipStream_t s = insts[0]->stream;
+  for (auto *I : insts)
+    if (I->stream != s) return fail(PD_EINVAL, "all instances of a batch must share one stream");
+  std::vector<int> Ks;
+  std::vector<SolveParams> sps;
+  for (size_t q = 0; q < insts.size(); ++q) {
+    pd_instance *I = insts[q];
+    const pd_time_desc *td = tds[q];
+    int rc;
+    if ((rc = validate_theta(td ? td->theta : -1))) return rc;
+    std::vector<double> t;
+    if ((rc = build_time_table(td, I->t, t))) return rc;
+    if ((rc = ensure_time_capacity(I, td->K))) return rc;
+    HIPCHK(hipMemcpyAsync(I->t_table, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    Ks.push_back(td->K);
+    sps.push_back(params_from(td, I->precision));
+  }
+  // the descriptor array may have been rebuilt (time capacity): it is
+  // copied per call in make_plan
+  return run_levels(insts, Ks, sps, s, stats);
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char *pd_last_error(void) { return g_err.c_str(); }
+
+int pd_mesh_coords(const pd_mesh_desc *mesh, double *r_nodes, double *r_faces, double *th_nodes,
+                   double *th_faces) {
+  MeshH M;
+  int rc = build_mesh(mesh, M);
+  if (rc) return rc;
+  if (r_nodes) std::copy(M.r.begin(), M.r.end(), r_nodes);
+  if (r_faces) std::copy(M.rh.begin(), M.rh.end(), r_faces);
+  if (th_nodes) std::copy(M.th.begin(), M.th.end(), th_nodes);
+  if (th_faces)
+    for (int j = 0; j < M.n; ++j) th_faces[j] = 0.5 * (M.th[j] + M.th[j + 1]);
+  return PD_OK;
+}
+
+int pd_footprint(const pd_mesh_desc *mesh, int32_t nsrc, int32_t precision, size_t *bytes) {
+  if (!bytes) return fail(PD_EINVAL, "bytes is NULL");
+  int rc = check_mesh(mesh);
+  if (rc) return rc;
+  pd_instance tmp;
+  tmp.M.m = mesh->nr;
+  tmp.M.n = mesh->ntheta;
+  tmp.T = make_tiling(mesh->nr, mesh->ntheta);
+  tmp.nsrc = nsrc;
+  tmp.precision = precision;
+  Carver c{nullptr, 0, true};
+  carve(&tmp, c);
+  *bytes = c.off + 8 * 1024;   // + time table / stats for short runs
+  return PD_OK;
+}
+
+int pd_mesh_create(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_t precision,
+                   void *hip_stream, pd_instance **out) {
+  if (!out) return fail(PD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pb) return fail(PD_EINVAL, "problem descriptor is NULL");
+  if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision %d", precision);
+  if (pb->nsrc < 0 || pb->nsrc > PD_MAXSRC) return fail(PD_EINVAL, "nsrc must be in [0, %d]", PD_MAXSRC);
+  if (pb->flux != 0 && pb->flux != 1) return fail(PD_EINVAL, "flux must be 0 or 1");
+  if (pb->bc != 0 && pb->bc != 1) return fail(PD_EINVAL, "bc must be 0 or 1");
+  if (pb->layout != PD_LAYOUT_RING && pb->layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
+  std::unique_ptr<pd_instance> I(new pd_instance);
+  int rc = build_mesh(mesh, I->M);
+  if (rc) return rc;
+  const int m = I->M.m, n = I->M.n, N = m * n + 1;
+  I->T = make_tiling(m, n);
+  I->precision = precision;
+  I->pde = pb->pde;
+  I->flux = pb->flux;
+  I->bc = pb->bc;
+  I->nsrc = pb->nsrc;
+  HIPCHK(hipGetDevice(&I->device));
+  if (hip_stream) {
+    I->stream = (hipStream_t)hip_stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&I->stream, hipStreamNonBlocking));
+    I->own_stream = true;
+  }
+  const MeshH &M = I->M;
+  const int np = I->T.npad;
+  // ---- host-side preparation of every device array
+  std::vector<double> Dr, Er, Dt, Et, bn, g, nb, u0;
+  const int dp = pb->device_ptrs;
+  if (pb->D_rface) { if ((rc = fetch(pb->D_rface, (size_t)(m + 1) * n, dp, Dr))) return rc; }
+  else Dr.assign((size_t)(m + 1) * n, 1.0);
+  if (pb->Er_rface) { if ((rc = fetch(pb->Er_rface, (size_t)(m + 1) * n, dp, Er))) return rc; }
+  else Er.assign((size_t)(m + 1) * n, 0.0);
+  if (pb->D_tface) { if ((rc = fetch(pb->D_tface, (size_t)m * n, dp, Dt))) return rc; }
+  else Dt.assign((size_t)m * n, 1.0);
+  if (pb->Et_tface) { if ((rc = fetch(pb->Et_tface, (size_t)m * n, dp, Et))) return rc; }
+  else Et.assign((size_t)m * n, 0.0);
+  if ((rc = fetch(pb->u0, N, dp, u0))) return rc;
+  if (pb->nsrc > 0) {
+    if (!pb->lambda) return fail(PD_EINVAL, "lambda is NULL");
+    if ((rc = fetch(pb->g, (size_t)pb->nsrc * N, dp, g))) return rc;
+    if (pb->nb) { if ((rc = fetch(pb->nb, (size_t)pb->nsrc * n, dp, nb))) return rc; }
+    else nb.assign((size_t)pb->nsrc * n, 0.0);
+  }
+  const bool has_b = pb->b_node != nullptr;
+  if (has_b && (rc = fetch(pb->b_node, N, dp, bn))) return rc;
+  for (double v : Dr) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "D_rface must be finite and >= 0");
+  for (double v : Dt) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "D_tface must be finite and >= 0");
+  for (double v : u0) if (!std::isfinite(v)) return fail(PD_EINVAL, "u0 has a non-finite value");
+  // faces
+  std::vector<double> gpr((size_t)(m + 1) * n), gmr((size_t)(m + 1) * n), gpt((size_t)m * n), gmt((size_t)m * n);
+  for (int i = 0; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t k = (size_t)i * n + j;
+      const double area = M.rh[i] * M.dth[j];
+      double G = Dr[k] * area / M.h[i + 1], K = Er[k] * area;
+      if (i == m && I->bc == 1) G = K = 0.0;
+      face_pair(G, K, I->flux, gpr[k], gmr[k]);
+    }
+  for (int i = 1; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t k = (size_t)(i - 1) * n + j;
+      const double G = Dt[k] * M.w[i] / (M.r[i] * M.mu[j + 1]);
+      const double K = Et[k] * M.w[i];
+      face_pair(G, K, I->flux, gpt[k], gmt[k]);
+    }
+  std::vector<double> inv_rw(m + 2, 0.0), inv_dth(n);
+  for (int i = 1; i <= m; ++i) inv_rw[i] = 1.0 / (M.r[i] * M.w[i]);
+  for (int j = 0; j < n; ++j) inv_dth[j] = 1.0 / M.dth[j];
+  I->H.inv_V0 = 1.0 / (kPi * 0.25 * M.h[1] * M.h[1]);
+  // ---- device allocation
+  Carver dry{nullptr, 0, true};
+  carve(I.get(), dry);
+  I->dbytes = dry.off;
+  hipError_t e = hipMalloc(&I->dmem, I->dbytes);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? PD_ENOMEM : PD_EHIP, "device allocation of %zu bytes failed: %s", I->dbytes, hipGetErrorString(e));
+  HIPCHK(hipMemsetAsync(I->dmem, 0, I->dbytes, I->stream));
+  Carver cv{(char *)I->dmem, 0, false};
+  carve(I.get(), cv);
+  PdInst &H = I->H;
+  H.m = m;
+  H.n = n;
+  H.npad = np;
+  H.nsrc = pb->nsrc;
+  H.mixed = precision == PD_MIXED;
+  H.has_b = has_b;
+  H.zero_flux = I->bc;
+  H.ncg = I->T.ncg;
+  H.nrg = I->T.nrg;
+  H.nb_sten = I->T.nb_sten;
+  H.nb_elem = I->T.nb_elem;
+  H.cw = I->T.cw;
+  H.nseg = I->T.nseg;
+  H.brad = I->T.brad;
+  H.nb_rad = I->T.nb_rad;
+  H.bang = I->T.bang;
+  H.nb_ang = I->T.nb_ang;
+  H.nb_frad = I->T.nb_frad;
+  H.nb_fang = I->T.nb_fang;
+  if (!has_b) H.b_node = nullptr;
+  hipStream_t s = I->stream;
+  auto up = [&](const void *dst, const void *src, size_t bytes) -> int {
+    HIPCHK(hipMemcpyAsync(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice, s));
+    return PD_OK;
+  };
+  std::vector<double> tmp(np);
+  std::vector<std::vector<double>> keep;   // host staging must outlive the async copies
+  if ((rc = up(H.inv_rw, inv_rw.data(), inv_rw.size() * 8))) return rc;
+  if ((rc = up(H.inv_dth, inv_dth.data(), inv_dth.size() * 8))) return rc;
+  if ((rc = up(H.k64.gp_r, gpr.data(), gpr.size() * 8))) return rc;
+  if ((rc = up(H.k64.gm_r, gmr.data(), gmr.size() * 8))) return rc;
+  if ((rc = up(H.k64.gp_t, gpt.data(), gpt.size() * 8))) return rc;
+  if ((rc = up(H.k64.gm_t, gmt.data(), gmt.size() * 8))) return rc;
+  std::vector<float> f_gpr, f_gmr, f_gpt, f_gmt;
+  if (H.mixed) {
+    f_gpr.assign(gpr.begin(), gpr.end());
+    f_gmr.assign(gmr.begin(), gmr.end());
+    f_gpt.assign(gpt.begin(), gpt.end());
+    f_gmt.assign(gmt.begin(), gmt.end());
+    if ((rc = up(H.k32.gp_r, f_gpr.data(), f_gpr.size() * 4))) return rc;
+    if ((rc = up(H.k32.gm_r, f_gmr.data(), f_gmr.size() * 4))) return rc;
+    if ((rc = up(H.k32.gp_t, f_gpt.data(), f_gpt.size() * 4))) return rc;
+    if ((rc = up(H.k32.gm_t, f_gmt.data(), f_gmt.size() * 4))) return rc;
+  }
+  if (has_b) {
+    keep.emplace_back(np);
+    to_internal(bn.data(), pb->layout, m, n, np, keep.back().data());
+    if ((rc = up(H.b_node, keep.back().data(), np * 8))) return rc;
+  }
+  for (int q = 0; q < pb->nsrc; ++q) {
+    keep.emplace_back(np);
+    to_internal(g.data() + (size_t)q * N, pb->layout, m, n, np, keep.back().data());
+    if ((rc = up(H.g + (size_t)q * np, keep.back().data(), np * 8))) return rc;
+  }
+  if (pb->nsrc > 0) {
+    if ((rc = up(H.nb, nb.data(), nb.size() * 8))) return rc;
+    double lam[PD_MAXSRC] = {0, 0, 0, 0};
+    int tp[PD_MAXSRC] = {0, 0, 0, 0};
+    for (int q = 0; q < pb->nsrc; ++q) {
+      lam[q] = pb->lambda[q];
+      tp[q] = pb->tpow ? pb->tpow[q] : 0;
+      if (tp[q] < 0 || tp[q] > 8) return fail(PD_EINVAL, "tpow must be in [0, 8]");
+    }
+    if ((rc = up(H.lam, lam, sizeof lam))) return rc;
+    if ((rc = up(H.tpow, tp, sizeof tp))) return rc;
+  }
+  keep.emplace_back(np);
+  to_internal(u0.data(), pb->layout, m, n, np, keep.back().data());
+  I->rot = 0;
+  if ((rc = up(H.sol[1], keep.back().data(), np * 8))) return rc;
+  if ((rc = ensure_time_capacity(I.get(), 16))) return rc;
+  HIPCHK(hipStreamSynchronize(s));
+  I->t = 0.0;
+  *out = I.release();
+  return PD_OK;
+}
+
+int pd_destroy(pd_instance *I) {
+  if (!I) return PD_OK;
+  if (I->busy) return fail(PD_EBUSY, "instance is in use");
+  if (I->stream) (void)hipStreamSynchronize(I->stream);
+  if (I->dmem) (void)hipFree(I->dmem);
+  if (I->t_table) (void)hipFree(I->t_table);
+  if (I->stats) (void)hipFree(I->stats);
+  if (I->own_stream) (void)hipStreamDestroy(I->stream);
+  delete I;
+  return PD_OK;
+}
+
+int pd_solve_to_T(pd_instance *I, const pd_time_desc *td, pd_step_stats *per_step) {
+  if (!I) return fail(PD_EINVAL, "instance is NULL");
+  std::vector<std::vector<double>> st(1);
+  int rc = solve_many({I}, {td}, &st);
+  if (per_step && !st[0].empty())
+    for (int k = 0; k < td->K; ++k) fill_stats(st[0], k, per_step + k);
+  return rc;
+}
+
+int pd_scheme_step(pd_instance *I, double t_k, double dt, double theta, double tol, pd_step_stats *stats) {
+  if (!I) return fail(PD_EINVAL, "instance is NULL");
+  if (!(dt > 0.0)) return fail(PD_EINVAL, "dt must be > 0");
+  double tab[2] = {t_k, t_k + dt};
+  pd_time_desc td{};
+  td.t_kind = PD_TIME_TABLE;
+  td.K = 1;
+  td.t_table = tab;
+  td.theta = theta;
+  td.tol = tol;
+  return pd_solve_to_T(I, &td, stats);
+}
+
+int pd_solve_batch(pd_instance *const *insts, int32_t count, const pd_time_desc *times,
+                   pd_step_stats *final_stats) {
+  if (!insts || count <= 0 || !times) return fail(PD_EINVAL, "empty batch");
+  std::vector<pd_instance *> v(insts, insts + count);
+  std::vector<const pd_time_desc *> tds;
+  for (int q = 0; q < count; ++q) {
+    if (!v[q]) return fail(PD_EINVAL, "instance %d is NULL", q);
+    tds.push_back(times + q);
+  }
+  std::vector<std::vector<double>> st(count);
+  int rc = solve_many(v, tds, &st);
+  if (final_stats)
+    for (int q = 0; q < count; ++q)
+      if (!st[q].empty()) fill_stats(st[q], times[q].K - 1, final_stats + q);
+  return rc;
+}
+
+int pd_get_solution(const pd_instance *I, double *out, int32_t layout, int32_t device_ptr) {
+  if (!I || !out) return fail(PD_EINVAL, "NULL argument");
+  if (layout != PD_LAYOUT_RING && layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
+  const int m = I->M.m, n = I->M.n, N = m * n + 1;
+  std::vector<double> h(I->T.npad), o(N);
+  HIPCHK(hipStreamSynchronize(I->stream));
+  HIPCHK(hipMemcpy(h.data(), I->H.sol[(I->rot + 1) % 3], I->T.npad * sizeof(double), hipMemcpyDeviceToHost));
+  from_internal(h.data(), layout, m, n, o.data());
+  if (device_ptr) {
+    HIPCHK(hipMemcpy(out, o.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(out, o.data(), N * sizeof(double));
+  }
+  return PD_OK;
+}
+
+int pd_set_solution(pd_instance *I, const double *in, int32_t layout, int32_t device_ptr, double t) {
+  if (!I || !in) return fail(PD_EINVAL, "NULL argument");
+  if (layout != PD_LAYOUT_RING && layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
+  if (I->busy) return fail(PD_EBUSY, "instance is in use");
+  const int m = I->M.m, n = I->M.n, N = m * n + 1;
+  std::vector<double> src;
+  int rc = fetch(in, N, device_ptr, src);
+  if (rc) return rc;
+  std::vector<double> h(I->T.npad);
+  to_internal(src.data(), layout, m, n, I->T.npad, h.data());
+  HIPCHK(hipMemcpy(I->H.sol[(I->rot + 1) % 3], h.data(), I->T.npad * sizeof(double), hipMemcpyHostToDevice));
+  I->t = t;
+  I->have_prev = false;
+  return PD_OK;
+}
+
+int pd_apply_operator(pd_instance *I, double dt, double theta, const double *x, double *y, int32_t layout,
+                      int32_t device_ptrs, int32_t precision) {
+  if (!I || !x || !y) return fail(PD_EINVAL, "NULL argument");
+  if (!(dt > 0.0)) return fail(PD_EINVAL, "dt must be > 0");
+  int rc = validate_theta(theta);
+  if (rc) return rc;
+  if (precision == 1 && I->precision != PD_MIXED)
+    return fail(PD_EINVAL, "the FP32 stencil needs a mixed-precision instance");
+  const int m = I->M.m, n = I->M.n, N = m * n + 1, np = I->T.npad;
+  std::vector<double> src;
+  if ((rc = fetch(x, N, device_ptrs, src))) return rc;
+  std::vector<double> hin(np), hout(np), o(N);
+  to_internal(src.data(), layout, m, n, np, hin.data());
+  hipStream_t s = I->stream;
+  void *dx = nullptr, *dy = nullptr;
+  const size_t es = precision == 1 ? 4 : 8;
+  HIPCHK(hipMalloc(&dx, np * es));
+  HIPCHK(hipMalloc(&dy, np * es));
+  std::vector<float> fin, fout;
+  if (precision == 1) {
+    fin.assign(hin.begin(), hin.end());
+    HIPCHK(hipMemcpy(dx, fin.data(), np * 4, hipMemcpyHostToDevice));
+  } else {
+    HIPCHK(hipMemcpy(dx, hin.data(), np * 8, hipMemcpyHostToDevice));
+  }
+  Plan P;
+  if ((rc = make_plan({I}, s, P))) return rc;
+  HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));
+  pd::launch_apply(P.L, dt, theta, dx, dy, precision == 1, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  if (precision == 1) {
+    fout.resize(np);
+    HIPCHK(hipMemcpy(fout.data(), dy, np * 4, hipMemcpyDeviceToHost));
+    for (int k = 0; k < np; ++k) hout[k] = fout[k];
+  } else {
+    HIPCHK(hipMemcpy(hout.data(), dy, np * 8, hipMemcpyDeviceToHost));
+  }
+  (void)hipFree(dx);
+  (void)hipFree(dy);
+  from_internal(hout.data(), layout, m, n, o.data());
+  if (device_ptrs) {
+    HIPCHK(hipMemcpy(y, o.data(), N * 8, hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(y, o.data(), N * 8);
+  }
+  return PD_OK;
+}
+
+int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double *rhs, int32_t layout,
+                    int32_t device_ptr) {
+  if (!I || !rhs) return fail(PD_EINVAL, "NULL argument");
+  if (!(dt > 0.0)) return fail(PD_EINVAL, "dt must be > 0");
+  int rc = validate_theta(theta);
+  if (rc) return rc;
+  BusyGuard g({I});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  hipStream_t s = I->stream;
+  // one level whose Krylov phase is skipped: the begin kernel leaves the
+  // right-hand side in bvec; the state is not advanced
+  double tab[2] = {t_k, t_k + dt};
+  if ((rc = ensure_time_capacity(I, 1))) return rc;
+  HIPCHK(hipMemcpyAsync(I->t_table, tab, sizeof tab, hipMemcpyHostToDevice, s));
+  Plan P;
+  if ((rc = make_plan({I}, s, P))) return rc;
+  SolveParams sp{theta, 1e-300, 1e-3, 1, 1, 1};
+  if ((rc = init_scalars(I, sp, 1, s))) return rc;
+  pd::launch_level_begin(P.L, s);
+  pd::launch_begin(P.L, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  const int m = I->M.m, n = I->M.n, N = m * n + 1;
+  std::vector<double> h(I->T.npad), o(N);
+  HIPCHK(hipMemcpy(h.data(), I->H.bvec, I->T.npad * 8, hipMemcpyDeviceToHost));
+  from_internal(h.data(), layout, m, n, o.data());
+  if (device_ptr) {
+    HIPCHK(hipMemcpy(rhs, o.data(), N * 8, hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(rhs, o.data(), N * 8);
+  }
+  return PD_OK;
+}
+
+}  // extern "C"
+
+// ================================================================== serving (placeholder)
+extern "C" {
+int pd_batch_create(size_t, int32_t, void *, pd_batch **out) {
+  if (out) *out = nullptr;
+  return fail(PD_EINVAL, "serving loop not available in this build");
+}
+int pd_batch_submit(pd_batch *, const pd_mesh_desc *, const pd_problem_desc *, const pd_time_desc *, int32_t,
+                    uint64_t *) {
+  return fail(PD_EINVAL, "serving loop not available in this build");
+}
+int pd_batch_poll(pd_batch *, uint64_t, double *, pd_step_stats *) {
+  return fail(PD_EINVAL, "serving loop not available in this build");
+}
+int pd_batch_destroy(pd_batch *) { return PD_OK; }
+}

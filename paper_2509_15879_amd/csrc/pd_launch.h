@@ -1,0 +1,29 @@
+// Launch interface between the host runtime and the HIP kernels.
+#pragma once
+
+#include "pd_device.h"
+
+namespace pd {
+
+// Device-side description of one batched launch: the instance array and,
+// per kernel family, a block map (instance index, block index within it).
+struct LaunchSet {
+  PdInst *insts = nullptr;
+  int ninst = 0;
+  int2 *map_sten = nullptr, *map_elem = nullptr, *map_rad = nullptr, *map_ang = nullptr;
+  int2 *map_frad = nullptr, *map_fang = nullptr;
+  int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0, nb_frad = 0, nb_fang = 0;
+  int mixed_any = 0, fp64_any = 0;
+};
+
+void launch_level_begin(const LaunchSet &L, hipStream_t s);
+void launch_level_end(const LaunchSet &L, hipStream_t s);
+void launch_factor(const LaunchSet &L, hipStream_t s);
+void launch_begin(const LaunchSet &L, hipStream_t s);
+void launch_cycle(const LaunchSet &L, hipStream_t s);
+void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void *y, int fp32,
+                  hipStream_t s);
+void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,
+                          hipStream_t s);
+
+}  // namespace pd

@@ -1,0 +1,274 @@
+"""ctypes binding of libpolardisk (include/polardisk.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the shared library.  The library must have been built
+(``python -m paper_2509_15879_amd.build``); importing this module fails
+loudly otherwise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolardisk.so")
+
+PD_OK, PD_PENDING = 0, 1
+ERRORS = {-1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EBREAKDOWN", -4: "PD_ENOCONV",
+          -5: "PD_EHIP", -6: "PD_EBUSY"}
+PD_FP64, PD_MIXED = 0, 1
+MESH_UNIFORM, MESH_SINE, MESH_EXPLICIT, MESH_POLY = 0, 1, 2, 3
+LAYOUT_RING, LAYOUT_PAPER = 0, 1
+TIME_UNIFORM, TIME_SINE, TIME_TABLE = 0, 1, 2
+
+
+class PolarDiskError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("ntheta", C.c_int32), ("r_kind", C.c_int32), ("p", C.c_double),
+                ("th_kind", C.c_int32), ("q", C.c_double), ("r_explicit", C.c_void_p),
+                ("th_explicit", C.c_void_p)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("pde", C.c_int32), ("flux", C.c_int32), ("bc", C.c_int32), ("layout", C.c_int32),
+                ("device_ptrs", C.c_int32), ("b_node", C.c_void_p), ("D_rface", C.c_void_p),
+                ("Er_rface", C.c_void_p), ("D_tface", C.c_void_p), ("Et_tface", C.c_void_p),
+                ("nsrc", C.c_int32), ("lam", C.c_void_p), ("tpow", C.c_void_p), ("g", C.c_void_p),
+                ("nb", C.c_void_p), ("u0", C.c_void_p)]
+
+
+class TimeDesc(C.Structure):
+    _fields_ = [("t_kind", C.c_int32), ("K", C.c_int32), ("T", C.c_double), ("l", C.c_double),
+                ("t_table", C.c_void_p), ("theta", C.c_double), ("tol", C.c_double),
+                ("max_iters", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("rel_resid", C.c_double), ("dt", C.c_double),
+                ("t", C.c_double)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "refinements": self.refinements, "status": self.status,
+                "restarts": self.reserved, "rel_resid": self.rel_resid, "dt": self.dt, "t": self.t}
+
+
+# every entry point declared in include/polardisk.h
+EXPORTS = ("pd_mesh_coords", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
+           "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
+           "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
+           "pd_batch_destroy", "pd_last_error")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: the HIP library has not been built "
+                          "(python -m paper_2509_15879_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, D, U64, SZ = C.c_void_p, C.c_int32, C.c_double, C.c_uint64, C.c_size_t
+    sig = {
+        "pd_mesh_coords": [C.POINTER(MeshDesc), P, P, P, P],
+        "pd_mesh_create": [C.POINTER(MeshDesc), C.POINTER(ProblemDesc), I32, P, C.POINTER(P)],
+        "pd_scheme_step": [P, D, D, D, D, C.POINTER(StepStats)],
+        "pd_solve_to_T": [P, C.POINTER(TimeDesc), P],
+        "pd_solve_batch": [C.POINTER(P), I32, C.POINTER(TimeDesc), P],
+        "pd_get_solution": [P, P, I32, I32],
+        "pd_set_solution": [P, P, I32, I32, D],
+        "pd_apply_operator": [P, D, D, P, P, I32, I32, I32],
+        "pd_assemble_rhs": [P, D, D, D, P, I32, I32],
+        "pd_footprint": [C.POINTER(MeshDesc), I32, I32, C.POINTER(SZ)],
+        "pd_destroy": [P],
+        "pd_batch_create": [SZ, I32, P, C.POINTER(P)],
+        "pd_batch_submit": [P, C.POINTER(MeshDesc), C.POINTER(ProblemDesc), C.POINTER(TimeDesc), I32,
+                            C.POINTER(U64)],
+        "pd_batch_poll": [P, U64, P, P],
+        "pd_batch_destroy": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.pd_last_error.argtypes = []
+    lib.pd_last_error.restype = C.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise PolarDiskError(rc, lib.pd_last_error().decode(errors="replace"))
+    return rc
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def mesh_desc(m, n, r_kind=0, p=1.0, th_kind=0, q=1.0, r_explicit=None, th_explicit=None):
+    md = MeshDesc(int(m), int(n), int(r_kind), float(p), int(th_kind), float(q), None, None)
+    keep = []
+    if r_explicit is not None:
+        a = _f64(r_explicit)
+        keep.append(a)
+        md.r_explicit = _ptr(a)
+    if th_explicit is not None:
+        a = _f64(th_explicit)
+        keep.append(a)
+        md.th_explicit = _ptr(a)
+    md._keep = keep
+    return md
+
+
+def mesh_coords(md: MeshDesc):
+    """Library mesh: (r_nodes, r_faces, th_nodes, th_faces)."""
+    m, n = md.nr, md.ntheta
+    r = np.empty(m + 2)
+    rf = np.empty(m + 1)
+    th = np.empty(n + 1)
+    tf = np.empty(n)
+    _check(lib.pd_mesh_coords(C.byref(md), _ptr(r), _ptr(rf), _ptr(th), _ptr(tf)))
+    return r, rf, th, tf
+
+
+def ring_vector(origin, grid):
+    """(origin, (m, n) grid) -> ring-layout node vector of length m n + 1."""
+    return np.concatenate([[float(origin)], np.asarray(grid, np.float64).reshape(-1)])
+
+
+def time_desc(theta, K, T=None, t_kind=TIME_UNIFORM, l=1.0, table=None, tol=1e-12, max_iters=0):
+    td = TimeDesc(int(t_kind), int(K), float(T or 0.0), float(l), None, float(theta), float(tol),
+                  int(max_iters))
+    if table is not None:
+        a = _f64(table)
+        td.t_table = _ptr(a)
+        td.t_kind = TIME_TABLE
+        td._keep = a
+    return td
+
+
+def problem_desc(data: dict, flux=0, bc=0):
+    """Builds a ProblemDesc from sampled problem data (origin/grid pieces, ring layout)."""
+    m, n = data["m"], data["n"]
+    keep = {}
+
+    def put(key, arr):
+        a = _f64(arr)
+        keep[key] = a
+        return _ptr(a)
+
+    ns = int(len(data["lam"]))
+    pd_ = ProblemDesc()
+    pd_.pde = int(data.get("pde", 1))
+    pd_.flux = int(flux)
+    pd_.bc = int(bc)
+    pd_.layout = LAYOUT_RING
+    pd_.device_ptrs = 0
+    pd_.b_node = put("b", ring_vector(data["b_origin"], data["b_grid"])) \
+        if np.any(np.asarray(data["b_grid"]) != 0) or data["b_origin"] != 0 else None
+    pd_.D_rface = put("Dr", np.asarray(data["D_r"]).reshape(m + 1, n))
+    pd_.Er_rface = put("Er", np.asarray(data["Er_r"]).reshape(m + 1, n))
+    pd_.D_tface = put("Dt", np.asarray(data["D_t"]).reshape(m, n))
+    pd_.Et_tface = put("Et", np.asarray(data["Et_t"]).reshape(m, n))
+    pd_.nsrc = ns
+    pd_.lam = put("lam", data["lam"])
+    tp = np.ascontiguousarray(data["tpow"], dtype=np.int32)
+    keep["tpow"] = tp
+    pd_.tpow = _ptr(tp)
+    pd_.g = put("g", np.stack([ring_vector(data["g_origin"][q], data["g_grid"][q]) for q in range(ns)]))
+    pd_.nb = put("nb", np.asarray(data["nb"]).reshape(ns, n))
+    pd_.u0 = put("u0", ring_vector(data["u0_origin"], data["u0_grid"]))
+    pd_._keep = keep
+    return pd_
+
+
+def footprint(md: MeshDesc, nsrc=1, precision=PD_FP64) -> int:
+    b = C.c_size_t()
+    _check(lib.pd_footprint(C.byref(md), int(nsrc), int(precision), C.byref(b)))
+    return int(b.value)
+
+
+class Instance:
+    """One disk problem resident on the GPU."""
+
+    def __init__(self, md: MeshDesc, data: dict, precision=PD_FP64, flux=0, bc=0, stream=None):
+        self.md = md
+        self.m, self.n = md.nr, md.ntheta
+        self.N = self.m * self.n + 1
+        self.precision = precision
+        pdesc = problem_desc(data, flux, bc)
+        h = C.c_void_p()
+        _check(lib.pd_mesh_create(C.byref(md), C.byref(pdesc), int(precision),
+                                  C.c_void_p(stream) if stream else None, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(lib.pd_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, t, dt, theta, tol=1e-12):
+        st = StepStats()
+        _check(lib.pd_scheme_step(self.h, float(t), float(dt), float(theta), float(tol), C.byref(st)))
+        return st.as_dict()
+
+    def solve(self, td: TimeDesc):
+        st = (StepStats * td.K)()
+        _check(lib.pd_solve_to_T(self.h, C.byref(td), C.cast(st, C.c_void_p)))
+        return [s.as_dict() for s in st]
+
+    def solution(self, layout=LAYOUT_RING):
+        out = np.empty(self.N)
+        _check(lib.pd_get_solution(self.h, _ptr(out), int(layout), 0))
+        return out
+
+    def set_solution(self, x, t, layout=LAYOUT_RING):
+        a = _f64(x)
+        _check(lib.pd_set_solution(self.h, _ptr(a), int(layout), 0, float(t)))
+
+    def apply(self, x, dt, theta, layout=LAYOUT_RING, precision=0):
+        a = _f64(x)
+        y = np.empty(self.N)
+        _check(lib.pd_apply_operator(self.h, float(dt), float(theta), _ptr(a), _ptr(y), int(layout),
+                                     0, int(precision)))
+        return y
+
+    def rhs(self, t, dt, theta, layout=LAYOUT_RING):
+        y = np.empty(self.N)
+        _check(lib.pd_assemble_rhs(self.h, float(t), float(dt), float(theta), _ptr(y), int(layout), 0))
+        return y
+
+
+def solve_batch(instances: Sequence[Instance], tds: Sequence[TimeDesc]):
+    n = len(instances)
+    hs = (C.c_void_p * n)(*[i.h for i in instances])
+    arr = (TimeDesc * n)(*tds)
+    st = (StepStats * n)()
+    _check(lib.pd_solve_batch(hs, n, arr, C.cast(st, C.c_void_p)))
+    return [s.as_dict() for s in st]

@@ -1,0 +1,63 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry
+point that include/polardisk.h declares, and its host-only mesh routine
+agrees with the paper's mesh formulas (no GPU call is made)."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "polardisk.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(pd_[a-z_A-Z0-9]+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_get_solution", "pd_destroy",
+              "pd_batch_create", "pd_batch_submit", "pd_batch_poll", "pd_batch_destroy", "pd_last_error"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2509_15879_amd import polardisk as pdk
+    for s in declared_symbols():
+        assert hasattr(pdk.lib, s), s
+    assert set(declared_symbols()) == set(pdk.EXPORTS)
+
+
+@pytest.mark.parametrize("rk,p,tk,q", [(0, 1, 0, 1), (1, 1.3, 0, 1), (1, 0.1, 1, 1.9), (3, 0.6, 1, 5.0)])
+def test_mesh_coords_match_paper_formulas(rk, p, tk, q):
+    from paper_2509_15879_amd import polardisk as pdk
+    from oracle import make_mesh
+    m, n = 37, 50
+    r, rf, th, tf = pdk.mesh_coords(pdk.mesh_desc(m, n, rk, p, tk, q))
+    me = make_mesh(m, n, rk, p, tk, q)
+    assert r[0] == 0.0 and r[-1] == 1.0 and th[0] == 0.0 and th[-1] == 2 * np.pi
+    assert np.allclose(r, me.r, rtol=0, atol=2e-16)
+    assert np.allclose(th, me.th, rtol=0, atol=1e-15)
+    assert np.allclose(rf, me.r_half, rtol=0, atol=2e-16)
+    assert np.allclose(tf, me.th_half, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("kw,msg", [(dict(m=1, n=8), "nr"), (dict(m=8, n=3), "ntheta"),
+                                    (dict(m=8, n=8, rk=1, p=-1.0), "p must")])
+def test_mesh_errors_are_reported(kw, msg):
+    from paper_2509_15879_amd import polardisk as pdk
+    md = pdk.mesh_desc(kw["m"], kw["n"], kw.get("rk", 0), kw.get("p", 1.0))
+    with pytest.raises(pdk.PolarDiskError) as e:
+        pdk.mesh_coords(md)
+    assert e.value.code == -1 and msg in str(e.value)
+
+
+def test_footprint_scales_with_cells():
+    from paper_2509_15879_amd import polardisk as pdk
+    a = pdk.footprint(pdk.mesh_desc(64, 128), 1, pdk.PD_FP64)
+    b = pdk.footprint(pdk.mesh_desc(128, 256), 1, pdk.PD_FP64)
+    assert 3.5 < b / a < 4.5
+    c = pdk.footprint(pdk.mesh_desc(256, 512), 1, pdk.PD_FP64)
+    assert 150 * 131073 < c < 300 * 131073   # about 200 B per cell

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: FP64 max-relative difference <= 1e-10 (normwise, ||Δ||_∞ / ||n||_∞);
+mixed precision L2-relative difference <= 1e-8.  Kernel-level checks (the
+operator and the right-hand side) hold to a few ulps of the row sums.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import gpu_instance, l2_rel, max_rel, oracle_system
+from oracle import solve, time_levels
+from oracle.stepper import rhs as oracle_rhs
+from oracle.stepper import step as oracle_step
+from problems import closed_form_quadratic, continuity_cfg, parabolic_cfg1, parabolic_family
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-10
+MIXED_BAR = 1e-8
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+CASES = {
+    # name: (problem factory, m, n, r_kind, p, th_kind, q, flux, bc)
+    "parabolic_4x8": (lambda: parabolic_family(1.0, 0.5), 4, 8, 0, 1.0, 0, 1.0, 0, 0),
+    "parabolic_b_33x64": (lambda: _with_b(parabolic_family(0.7, 0.3, 1.0)), 33, 64, 1, 1.0, 0, 1.0, 0, 0),
+    "continuity_40x100": (lambda: continuity_cfg(1101, 40, 100), 40, 100, 1, 1.3, 1, 1.9, 0, 0),
+    "continuity_up_zf_37x70": (lambda: continuity_cfg(1102, 37, 70), 37, 70, 1, 1.3, 0, 1.0, 1, 1),
+    "continuity_2x4": (lambda: continuity_cfg(1103, 2, 4), 2, 4, 0, 1.0, 0, 1.0, 0, 0),
+    "continuity_17x130": (lambda: continuity_cfg(1104, 17, 130), 17, 130, 3, 0.6, 1, 2.5, 1, 0),
+}
+
+
+EPS = np.finfo(np.float64).eps
+
+
+def within_matvec_bound(got, ref, terms, c=64.0, mesh_terms=None, mesh_rel=None):
+    """Elementwise forward-error bound of a matrix-vector product:
+    |got - ref| <= c ε Σ |terms| (the absolute values of every summand),
+    plus, where the two sides' meshes may differ, mesh_rel · mesh_terms."""
+    bound = c * EPS * terms + 1e-300
+    if mesh_terms is not None:
+        bound = bound + mesh_rel * mesh_terms
+    worst = float(np.max(np.abs(got - ref) / bound))
+    return worst <= 1.0, worst
+
+
+def mesh_sensitivity(me):
+    """Per-row relative perturbation of the stencil coefficients caused by
+    one-ulp differences between the two sides' mesh nodes (each side
+    evaluates the stretch functions with its own libm): a node spacing δ
+    next to a node of size s moves by ~2 ulp(s)/δ, and a coefficient
+    carries up to two spacings.  Paper ordering."""
+    from oracle.operator import to_vec
+    m, n = me.m, me.n
+    mu = me.mu
+    h = me.h
+    ang = 2 * np.spacing(2 * np.pi) / np.minimum(mu[:n], mu[1:n + 1])          # per j
+    rad = 2 * np.spacing(1.0) / np.minimum(h[1:m + 1], h[2:m + 2])               # per i
+    grid = 4 * (rad[:, None] + ang[None, :])
+    return to_vec(4 * 2 * np.spacing(1.0) / h[1] + ang.max(), grid)
+
+
+def _with_b(pb):
+    pb.b = lambda r, th: 0.4 + 0.3 * r * np.cos(th) ** 2
+    return pb
+
+
+def setup_case(name, precision=0):
+    f, m, n, rk, p, tk, q, flux, bc = CASES[name]
+    pb = f()
+    S, me = oracle_system(pb, m, n, rk, p, tk, q, flux, bc)
+    inst = gpu_instance(pb, m, n, rk, p, tk, q, precision, flux, bc)
+    return pb, S, inst
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_operator_matches_oracle(name):
+    say(f"[operator] {name}")
+    pb, S, inst = setup_case(name)
+    rng = np.random.default_rng(7)
+    for dt, theta in [(1e-3, 0.5), (2.5e-5, 1.0), (0.3, 0.37)]:
+        x = rng.standard_normal(S.N)
+        got = inst.apply(x, dt, theta, layout=1)
+        ref = x / dt + theta * (S.L @ x)
+        lx = theta * (abs(S.L) @ np.abs(x))
+        ok, worst = within_matvec_bound(got, ref, np.abs(x) / dt + lx, mesh_terms=lx,
+                                        mesh_rel=mesh_sensitivity(S.mesh))
+        assert ok, (dt, theta, worst)
+        assert max_rel(got, ref) <= 1e-12, (dt, theta)
+    inst.close()
+
+
+def test_operator_full_size_cfg2():
+    say("[operator] continuity 256x512 graded")
+    pb = continuity_cfg(1200, 256, 512)
+    S, me = oracle_system(pb, 256, 512, 1, 1.3)
+    inst = gpu_instance(pb, 256, 512, 1, 1.3)
+    x = np.random.default_rng(3).standard_normal(S.N)
+    got = inst.apply(x, 7e-4, 0.5, layout=1)
+    ref = x / 7e-4 + 0.5 * (S.L @ x)
+    assert max_rel(got, ref) <= 1e-13
+    inst.close()
+
+
+def test_fp32_operator_matches_oracle():
+    say("[operator fp32] continuity_40x100")
+    pb, S, inst = setup_case("continuity_40x100", precision=1)
+    x = np.random.default_rng(8).standard_normal(S.N)
+    got = inst.apply(x, 1e-3, 0.5, layout=1, precision=1)
+    ref = x / 1e-3 + 0.5 * (S.L @ x)
+    assert max_rel(got, ref) <= 1e-5
+    inst.close()
+
+
+@pytest.mark.parametrize("name", ["parabolic_b_33x64", "continuity_40x100", "continuity_up_zf_37x70",
+                                  "continuity_17x130"])
+def test_rhs_matches_oracle(name):
+    say(f"[rhs] {name}")
+    pb, S, inst = setup_case(name)
+    x0 = S.initial()
+    for t0, dt, theta in [(0.0, 1e-3, 0.5), (0.013, 4e-4, 1.0)]:
+        inst.set_solution(x0, t0, layout=1)
+        got = inst.rhs(t0, dt, theta, layout=1)
+        ref = oracle_rhs(S, x0, t0, t0 + dt, theta)
+        ax = np.abs(x0)
+        lx = (1 - theta) * (abs(S.L) @ ax) + np.abs(S.bnd_term(t0)) + np.abs(S.bnd_term(t0 + dt))
+        terms = (ax / dt + lx
+                 + (1 - theta) * np.abs(S.source(t0)) + theta * np.abs(S.source(t0 + dt)))
+        ok, worst = within_matvec_bound(got, ref, terms, mesh_terms=lx,
+                                        mesh_rel=mesh_sensitivity(S.mesh))
+        assert ok, (t0, dt, theta, worst)
+    inst.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_single_step_matches_oracle(name, precision):
+    say(f"[step] {name} precision={precision}")
+    pb, S, inst = setup_case(name, precision)
+    x0 = S.initial()
+    for t0, dt, theta in [(0.0, 1e-3, 0.5), (0.001, 2e-5, 1.0)]:
+        inst.set_solution(x0, t0, layout=1)
+        st = inst.step(t0, dt, theta, tol=1e-13)
+        got = inst.solution(layout=1)
+        ref = oracle_step(S, x0, t0, t0 + dt, theta)
+        if precision == 0:
+            assert max_rel(got, ref) <= FP64_BAR, st
+        else:
+            assert l2_rel(got, ref) <= MIXED_BAR, st
+    inst.close()
+
+
+def test_cfg1_full_solve_fp64():
+    say("[solve] parabolic cfg1 32x64, CN, dt=1e-3, 100 steps")
+    pb = parabolic_cfg1()
+    S, me = oracle_system(pb, 32, 64)
+    ref = solve(S, time_levels(0.1, 100), 0.5)
+    from paper_2509_15879_amd import polardisk as pdk
+    inst = gpu_instance(pb, 32, 64)
+    stats = inst.solve(pdk.time_desc(0.5, 100, 0.1, pdk.TIME_UNIFORM, tol=1e-13))
+    got = inst.solution(layout=1)
+    say(f"  iters/step {np.mean([s['iters'] for s in stats]):.1f}, max-rel {max_rel(got, ref):.2e}")
+    assert max_rel(got, ref) <= FP64_BAR
+    assert all(s["status"] == 0 for s in stats)
+    inst.close()
+
+
+@pytest.mark.parametrize("precision,theta", [(0, 0.5), (0, 1.0), (1, 0.5), (1, 1.0)])
+def test_continuity_graded_solve(precision, theta):
+    say(f"[solve] continuity 48x100 graded, V(t), precision={precision}, theta={theta}")
+    from paper_2509_15879_amd import polardisk as pdk
+    pb = continuity_cfg(1105, 48, 100)
+    S, me = oracle_system(pb, 48, 100, 1, 1.3)
+    ref = solve(S, time_levels(0.05, 20, 1, 1.5), theta)
+    inst = gpu_instance(pb, 48, 100, 1, 1.3, precision=precision)
+    stats = inst.solve(pdk.time_desc(theta, 20, 0.05, pdk.TIME_SINE, 1.5, tol=1e-13))
+    got = inst.solution(layout=1)
+    say(f"  iters/step {np.mean([s['iters'] for s in stats]):.1f}, "
+        f"refinements {np.mean([s['refinements'] for s in stats]):.1f}, "
+        f"max-rel {max_rel(got, ref):.2e}, l2-rel {l2_rel(got, ref):.2e}")
+    if precision == 0:
+        assert max_rel(got, ref) <= FP64_BAR
+    else:
+        assert l2_rel(got, ref) <= MIXED_BAR
+    inst.close()
+
+
+def test_closed_form_exact_on_gpu():
+    say("[solve] closed form (1+t) r^2 + c on a uniform radial mesh")
+    from paper_2509_15879_amd import polardisk as pdk
+    from problems.manufactured import exact_at
+    from oracle.operator import to_vec
+    pb = closed_form_quadratic(0.25)
+    inst = gpu_instance(pb, 20, 36, 0, 1.0, 1, 1.7)
+    inst.solve(pdk.time_desc(0.6, 8, 0.3, pdk.TIME_SINE, 1.5, tol=1e-14))
+    got = inst.solution(layout=1)
+    r, _, th, _ = pdk.mesh_coords(inst.md)
+    e0, eg = exact_at(pb, 0.3, r, th)
+    assert max_rel(got, to_vec(e0, eg)) <= 1e-12
+    inst.close()
+
+
+def test_zero_flux_conserves_mass_on_gpu():
+    say("[solve] zero-flux mass conservation 30x64")
+    from paper_2509_15879_amd import polardisk as pdk
+    from problems import zero_flux_random
+    pb = zero_flux_random(11)
+    S, me = oracle_system(pb, 30, 64, 1, 1.3, 1, 1.6, 0, 1)
+    inst = gpu_instance(pb, 30, 64, 1, 1.3, 1, 1.6, 0, 0, 1)
+    x0 = inst.solution(layout=1)
+    inst.solve(pdk.time_desc(0.5, 10, 0.02, pdk.TIME_SINE, 1.5, tol=1e-14))
+    x1 = inst.solution(layout=1)
+    M0, M1 = S.V @ x0, S.V @ x1
+    assert abs(M1 - M0) / abs(M0) <= 1e-12
+    inst.close()
