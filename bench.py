@@ -1,0 +1,261 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the polar-disk θ-scheme solver on one MI355X.
+
+Workload (one "step" = one pass of the whole hot path over one batch): the
+drift-diffusion continuity problem on a 256 x 512 polar mesh graded towards
+r = 0 and r = 1 (radial stretch (2.4), p = 1.3), seeded diffusivity
+D = 1 + ½ sin(kθ) r² and Fourier-Bessel drift E = -∇ψ, manufactured exact
+solution, time levels t_k = T sin((k/K)^l π/2) with T = 0.05, K = 100,
+l = 1.5 (Δt from 1.4e-5 to 7.1e-4), five seeds x θ ∈ {0.5, 1}: ten instances
+of 131,073 unknowns, all advanced from t = 0 to T in the same batched
+launches.  Metric: cell-updates/s = Σ unknowns x levels / wall time, with
+every instance's result within 1e-8 (L2-relative) of a fully converged FP64
+solution.  The oracle (FP64 sparse LU on the host) is timed beside it on a
+bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+M, N_TH, P_STRETCH, T_END, K_LEVELS, L_TIME = 256, 512, 1.3, 0.05, 100, 1.5
+SEEDS = (1200, 1201, 1202, 1203, 1204)
+THETAS = (0.5, 1.0)
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unknown of one launch (w: storage bytes of the
+# Krylov data, pivots are FP64): what the kernel must read and write once.
+def bytes_per_cell(family, w):
+    return {
+        "sten_v": 7 * w,            # x, 4 face coefficients, r̂ in; v out
+        "sten_t": 7 * w,            # x, 4 faces, s in; t out
+        "rad": (7 * w + 8 + 6 * w + 8) / 2.0,   # mean of the p- and s-sweeps
+        "ang": 5 * w + 8,           # w, f, g, z in + pivot; out
+        "update": 8 * w,            # p̂, ŝ, x, s, t, r̂ in; x, r out
+    }[family]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_instances(pdk, precision, stream):
+    from problems import continuity_cfg, sample
+    insts, tds, u0s = [], [], []
+    for seed in SEEDS:
+        for th in THETAS:
+            pb = continuity_cfg(seed, M, N_TH, th, P_STRETCH, T_END, K_LEVELS, L_TIME)
+            md = pdk.mesh_desc(M, N_TH, pdk.MESH_SINE, P_STRETCH)
+            data = sample(pb, *pdk.mesh_coords(md))
+            inst = pdk.Instance(md, data, precision, stream=stream)
+            insts.append(inst)
+            u0s.append(pdk.ring_vector(data["u0_origin"], data["u0_grid"]))
+            tds.append((th, pb))
+    return insts, tds, u0s
+
+
+def time_descs(pdk, tds, tol):
+    return [pdk.time_desc(th, K_LEVELS, T_END, pdk.TIME_SINE, L_TIME, tol=tol) for th, _ in tds]
+
+
+def reset(insts, u0s):
+    for inst, u0 in zip(insts, u0s):
+        inst.set_solution(u0, 0.0)
+
+
+def cpu_baseline(levels, gpu_states):
+    """The oracle on a bounded sample: one instance (seed 1200, θ = 0.5), the
+    first `levels` time levels, one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import assemble, make_mesh, solve, time_levels
+    from problems import continuity_cfg, sample
+    pb = continuity_cfg(SEEDS[0], M, N_TH, THETAS[0], P_STRETCH, T_END, K_LEVELS, L_TIME)
+    t_all = time_levels(T_END, K_LEVELS, 1, L_TIME)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        me = make_mesh(M, N_TH, 1, P_STRETCH)
+        S = assemble(me, sample(pb, *me.sample_points()))
+        x = solve(S, t_all[:levels + 1], THETAS[0])
+        el = time.perf_counter() - t0
+    cells = M * N_TH + 1
+    ref = gpu_states
+    err = float(np.max(np.abs(ref - x)) / np.max(np.abs(x))) if ref is not None else None
+    return {
+        "value": cells * levels / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+        "sample": (f"seed {SEEDS[0]}, theta {THETAS[0]}, first {levels} of {K_LEVELS} levels "
+                   f"({cells} unknowns; mesh, sampling, assembly, one SuperLU factorisation and "
+                   f"solve per level; {el:.1f} s)"),
+        "gpu_vs_oracle_max_rel": err,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--tol", type=float, default=4e-12)
+    ap.add_argument("--oracle-levels", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(instances are independent; a multi-GPU run would shard them by footprint)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_15879_amd import polardisk as pdk
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    prec = pdk.PD_MIXED if args.precision == "mixed" else pdk.PD_FP64
+
+    log("building instances ...")
+    insts, tds, u0s = build_instances(pdk, prec, stream)
+    cells = sum(i.N for i in insts)
+
+    # fully converged FP64 reference of every instance
+    log("reference solve (FP64, tol 1e-13) ...")
+    refs_insts = insts if prec == pdk.PD_FP64 else build_instances(pdk, pdk.PD_FP64, stream)[0]
+    reset(refs_insts, u0s)
+    pdk.solve_batch(refs_insts, time_descs(pdk, tds, 1e-13))
+    refs = [i.solution() for i in refs_insts]
+    # GPU state after the oracle's sample levels (instance 0), for the sampled parity
+    from oracle import time_levels
+    t_all = time_levels(T_END, K_LEVELS, 1, L_TIME)
+    inst0 = refs_insts[0]
+    inst0.set_solution(u0s[0], 0.0)
+    inst0.solve(pdk.time_desc(THETAS[0], args.oracle_levels, table=t_all[:args.oracle_levels + 1],
+                              tol=1e-13))
+    sample_state = inst0.solution(pdk.LAYOUT_PAPER)
+
+    descs = time_descs(pdk, tds, args.tol)
+    for w in range(args.warmup):
+        reset(insts, u0s)
+        pdk.solve_batch(insts, descs)
+    torch.cuda.synchronize()
+
+    pdk.kernel_timing(True, reset=True)
+    lat, stats = [], None
+    for s in range(args.steps):
+        reset(insts, u0s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = pdk.solve_batch(insts, descs)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        log(f"step {s}: {lat[-1] * 1e3:.1f} ms")
+    kms, kcnt = pdk.kernel_timing(False, reset=True)
+    ms_per_step = 1e3 * float(np.mean(lat))
+    value = cells * K_LEVELS / (ms_per_step / 1e3)
+
+    # accuracy of the timed result against the converged FP64 solution
+    errs_l2, errs_max = [], []
+    for inst, ref in zip(insts, refs):
+        x = inst.solution()
+        errs_l2.append(float(np.linalg.norm(x - ref) / np.linalg.norm(ref)))
+        errs_max.append(float(np.max(np.abs(x - ref)) / np.max(np.abs(ref))))
+    valid = max(errs_l2) <= 1e-8
+
+    # roofline of the dominant kernel family (live HIP-event timing)
+    w = 4 if prec == pdk.PD_MIXED else 8
+    iters = [sum(s["iters"] for s in st) for st in stats]         # per instance, per step
+    inst_cells = [i.N for i in insts]
+    cell_iters = sum(c * it for c, it in zip(inst_cells, iters)) * args.steps
+    fam_bytes = {
+        "sten_v": cell_iters * bytes_per_cell("sten_v", w),
+        "sten_t": cell_iters * bytes_per_cell("sten_t", w),
+        "rad": 2 * cell_iters * bytes_per_cell("rad", w),
+        "ang": 2 * cell_iters * bytes_per_cell("ang", w),
+        "update": cell_iters * bytes_per_cell("update", w),
+    }
+    dom = max(fam_bytes, key=lambda f: kms[f])
+    achieved = fam_bytes[dom] / (kms[dom] / 1e3) / 1e9
+    roofline = {
+        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "launches": int(kcnt[dom]), "avg_launch_us": round(1e3 * kms[dom] / max(1, kcnt[dom]), 2),
+        "bytes_per_launch": round(fam_bytes[dom] / max(1, kcnt[dom])),
+        "kernel_ms": {k: round(v, 2) for k, v in kms.items()},
+        "kernel_share": round(float(sum(kms.values())) / ms_per_step / args.steps, 3),
+    }
+
+    out = {
+        "metric": "cell-updates/s (cells×steps/s) at 1e-8 rel err vs FP64; p50/p99 solve latency",
+        "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w == 8 else "f32+f64",
+        "data": "synthetic (seeded manufactured continuity problems)",
+        "config": {
+            "workload": ("continuity drift-diffusion, 256x512 polar mesh graded (p=1.3), "
+                         "100 sine-stretched levels to T=0.05, 5 seeds x theta {0.5,1} = 10 "
+                         "instances batched"),
+            "instances": len(insts), "m": M, "n": N_TH, "unknowns_per_instance": M * N_TH + 1,
+            "levels": K_LEVELS, "tol_per_step": args.tol, "precision": args.precision,
+            "parallelism": "single GPU, batched instances",
+        },
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+        "accuracy": {"l2_rel_vs_fp64_converged_max": max(errs_l2),
+                     "max_rel_vs_fp64_converged_max": max(errs_max), "valid": valid},
+        "iters_per_level_mean": round(float(np.mean(iters)) / K_LEVELS, 2),
+        "roofline": roofline,
+    }
+
+    if not args.no_variants:
+        # same workload, one instance at a time (FP64) and batched mixed precision
+        var = {}
+        t0 = time.perf_counter()
+        for inst, u0, d in zip(insts if prec == pdk.PD_FP64 else refs_insts, u0s,
+                               time_descs(pdk, tds, args.tol)):
+            inst.set_solution(u0, 0.0)
+            torch.cuda.synchronize()
+            inst.solve(d)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        var["fp64_one_instance_at_a_time"] = {"value": round(cells * K_LEVELS / el, 1),
+                                              "ms": round(1e3 * el, 1)}
+        if prec == pdk.PD_FP64:
+            mix, _, _ = build_instances(pdk, pdk.PD_MIXED, stream)
+            mdesc = time_descs(pdk, tds, args.tol)
+            reset(mix, u0s)
+            pdk.solve_batch(mix, mdesc)
+            reset(mix, u0s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mst = pdk.solve_batch(mix, mdesc)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            me = max(float(np.linalg.norm(i.solution() - r) / np.linalg.norm(r)) for i, r in zip(mix, refs))
+            var["mixed_batched"] = {"value": round(cells * K_LEVELS / el, 1), "ms": round(1e3 * el, 1),
+                                    "l2_rel_vs_fp64_converged_max": me,
+                                    "inner_iters_per_level": round(float(np.mean(
+                                        [sum(s["iters"] for s in st) for st in mst])) / K_LEVELS, 2),
+                                    "refinements_per_level": round(float(np.mean(
+                                        [sum(s["refinements"] for s in st) for st in mst])) / K_LEVELS, 2)}
+            for i in mix:
+                i.close()
+        out["variants"] = var
+
+    if not args.no_cpu_baseline:
+        log("oracle sample ...")
+        out["cpu_baseline"] = cpu_baseline(args.oracle_levels, sample_state)
+
+    for i in insts:
+        i.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -141,7 +141,9 @@ typedef struct {
  * starts from the instance's current state and time, which must equal t_0.
  *   theta: implicit weight θ = 1 - a in (0, 1]; 0.5 is Crank-Nicolson,
  *          1 is backward Euler.
- *   tol:   per-step stopping tolerance on ||b - A x||_2 / ||b||_2 (FP64).
+ *   tol:   per-step stopping tolerance on the diagonally scaled residual
+ *          ||D^{-1}(b - A x)||_2 / ||D^{-1} b||_2 (FP64), D = diag(A); every
+ *          row weighs alike, whatever the local mesh spacing.
  *   max_iters: cap on BiCGSTAB iterations per step (0: library default).  */
 typedef struct {
   int32_t t_kind;
@@ -158,7 +160,7 @@ typedef struct {
   int32_t refinements;  /* FP64 outer refinements (PD_MIXED), else 0       */
   int32_t status;       /* PD_OK, PD_EBREAKDOWN or PD_ENOCONV              */
   int32_t reserved;
-  double rel_resid;     /* final ||b - A x|| / ||b|| in FP64               */
+  double rel_resid;     /* final scaled relative residual (see tol)        */
   double dt, t;         /* step size and the time reached                  */
 } pd_step_stats;
 
@@ -172,7 +174,9 @@ int pd_mesh_coords(const pd_mesh_desc *mesh, double *r_nodes, double *r_faces,
 /* Creates an instance: builds the mesh, turns the sampled coefficients into
  * face conductances and drift coefficients, uploads everything to the
  * current HIP device, and sets the state to u0 at t = 0.  hip_stream may be
- * NULL (the library then owns a default-priority stream).                */
+ * NULL: the instance then uses a default-priority stream the library owns,
+ * one per device and shared by every such instance (so they can be
+ * batched together).                                                     */
 int pd_mesh_create(const pd_mesh_desc *mesh, const pd_problem_desc *problem,
                    int32_t precision, void *hip_stream, pd_instance **out);
 
@@ -184,12 +188,13 @@ int pd_scheme_step(pd_instance *inst, double t_k, double dt, double theta, doubl
 int pd_solve_to_T(pd_instance *inst, const pd_time_desc *time, pd_step_stats *per_step);
 
 /* Advances several instances together: every kernel launch covers all of
- * them (uneven sizes and PDE types allowed).  times[i] belongs to insts[i];
- * final_stats (count entries, may be NULL) receives each instance's last
- * step.  All instances must share one stream.  Results are identical to
- * solving each instance alone.                                           */
+ * them (uneven sizes and PDE types allowed).  times[q] belongs to insts[q];
+ * per_step (count pointers, may be NULL; each per_step[q] NULL or an array
+ * of times[q].K entries) receives every step's statistics.  All instances
+ * must share one stream.  Results equal those of solving each instance
+ * alone (the reductions of an instance depend only on its own tiling).   */
 int pd_solve_batch(pd_instance *const *insts, int32_t count, const pd_time_desc *times,
-                   pd_step_stats *final_stats);
+                   pd_step_stats *const *per_step);
 
 /* Current state n^k (N values) in the requested layout. */
 int pd_get_solution(const pd_instance *inst, double *out, int32_t layout, int32_t device_ptr);
@@ -228,6 +233,15 @@ int pd_batch_submit(pd_batch *batch, const pd_mesh_desc *mesh, const pd_problem_
                     const pd_time_desc *time, int32_t precision, uint64_t *ticket);
 int pd_batch_poll(pd_batch *batch, uint64_t ticket, double *out, pd_step_stats *summary);
 int pd_batch_destroy(pd_batch *batch);
+
+/* Kernel timing (diagnostics).  While enabled, every kernel launch of the
+ * solver is bracketed by HIP events on its stream and its duration is
+ * added to its family's total (families PD_KF_*; a level is synchronised
+ * after it ends so the events can be read).  total_ms / launches (PD_KF_N
+ * entries each, may be NULL) receive the totals since the last reset.    */
+enum { PD_KF_BEGIN = 0, PD_KF_FACTOR = 1, PD_KF_RAD = 2, PD_KF_ANG = 3, PD_KF_STEN_V = 4,
+       PD_KF_STEN_T = 5, PD_KF_UPDATE = 6, PD_KF_REFINE = 7, PD_KF_CONTROL = 8, PD_KF_N = 9 };
+int pd_kernel_timing(int32_t enable, int32_t reset, double *total_ms, int64_t *launches);
 
 const char *pd_last_error(void);
 

@@ -54,6 +54,7 @@ struct KSet {
   T *r, *rh, *p, *v, *ph, *s, *sh, *t, *w;
   T *d;                              // inner iterate (mixed precision only)
   const T *gp_r, *gm_r, *gp_t, *gm_t;  // faces
+  const T *inv_d;                    // 1/diag(A): the Krylov iteration runs on D^{-1}A
   T *rf_f, *rf_g;                    // radial factors (multipliers)
   T *af_f, *af_g, *af_z;             // angular factors (multipliers, SM vector)
 };
@@ -77,6 +78,8 @@ struct PdInst {
   double *bvec;             // right-hand side (FP64)
   double *rout;             // FP64 outer residual (mixed)
   double *diag;             // [npad] diagonal of I/dt + θL
+  double *inv_diag;         // [npad] its reciprocal (k64.inv_d)
+  float *inv_diag32;        // [npad] FP32 copy (k32.inv_d, mixed precision)
   double *rf_uinv;          // [m*n] radial pivots 1/u (FP64 in both precisions)
   double *af_uinv;          // [m*n] angular pivots
   double *af_kappa, *af_alpha0;   // [m] Sherman-Morrison scalars per ring

@@ -228,6 +228,10 @@ void carve(pd_instance *I, Carver &c) {
   for (int k = 0; k < 3; ++k) H.sol[k] = c.take<double>(np);
   H.bvec = c.take<double>(np);
   H.diag = c.take<double>(np);
+  H.inv_diag = c.take<double>(np);
+  H.k64.inv_d = H.inv_diag;
+  H.inv_diag32 = mixed ? c.take<float>(np) : nullptr;
+  H.k32.inv_d = H.inv_diag32;
   H.rf_uinv = c.take<double>(mn);
   H.af_uinv = c.take<double>(mn);
   H.af_kappa = c.take<double>(m);
@@ -375,6 +379,64 @@ int build_time_table(const pd_time_desc *td, double t_start, std::vector<double>
   return PD_OK;
 }
 
+// ------------------------------------------------------------------ timing
+
+struct EventTimer : pd::KTimer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, hipEvent_t>> open;
+  struct Rec { int f; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  double total_ms[PD_KF_N] = {};
+  int64_t launches[PD_KF_N] = {};
+  hipEvent_t take() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  void mark(int f, bool start, hipStream_t s) override {
+    hipEvent_t e = take();
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    if (start) {
+      open.push_back({f, e});
+    } else if (!open.empty() && open.back().first == f) {
+      pending.push_back({f, open.back().second, e});
+      open.pop_back();
+    } else {
+      pool.push_back(e);
+    }
+  }
+  // Reads every finished pair (the caller has synchronised the stream).
+  void harvest() {
+    for (auto &r : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        total_ms[r.f] += ms;
+        launches[r.f] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    for (int k = 0; k < PD_KF_N; ++k) {
+      total_ms[k] = 0;
+      launches[k] = 0;
+    }
+  }
+  ~EventTimer() override {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+EventTimer *g_event_timer = nullptr;
+
 // ------------------------------------------------------------------ engine
 
 struct Plan {
@@ -496,6 +558,10 @@ int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &
     }
     HIPCHK(hipGetLastError());
     pd::launch_level_end(P.L, s);
+    if (g_event_timer && pd::g_timer) {
+      HIPCHK(hipStreamSynchronize(s));
+      g_event_timer->harvest();
+    }
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -654,8 +720,19 @@ int pd_mesh_create(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_t 
   if (hip_stream) {
     I->stream = (hipStream_t)hip_stream;
   } else {
-    HIPCHK(hipStreamCreateWithFlags(&I->stream, hipStreamNonBlocking));
-    I->own_stream = true;
+    // one library-owned stream per device for every instance created
+    // without a stream, so that such instances can be batched together
+    static std::mutex mu;
+    static std::map<int, hipStream_t> shared;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = shared.find(I->device);
+    if (it == shared.end()) {
+      hipStream_t st;
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      it = shared.emplace(I->device, st).first;
+    }
+    I->stream = it->second;
+    I->own_stream = false;
   }
   const MeshH &M = I->M;
   const int np = I->T.npad;
@@ -825,7 +902,7 @@ int pd_scheme_step(pd_instance *I, double t_k, double dt, double theta, double t
 }
 
 int pd_solve_batch(pd_instance *const *insts, int32_t count, const pd_time_desc *times,
-                   pd_step_stats *final_stats) {
+                   pd_step_stats *const *per_step) {
   if (!insts || count <= 0 || !times) return fail(PD_EINVAL, "empty batch");
   std::vector<pd_instance *> v(insts, insts + count);
   std::vector<const pd_time_desc *> tds;
@@ -835,10 +912,29 @@ int pd_solve_batch(pd_instance *const *insts, int32_t count, const pd_time_desc 
   }
   std::vector<std::vector<double>> st(count);
   int rc = solve_many(v, tds, &st);
-  if (final_stats)
+  if (per_step)
     for (int q = 0; q < count; ++q)
-      if (!st[q].empty()) fill_stats(st[q], times[q].K - 1, final_stats + q);
+      if (per_step[q] && !st[q].empty())
+        for (int k = 0; k < times[q].K; ++k) fill_stats(st[q], k, per_step[q] + k);
   return rc;
+}
+
+int pd_kernel_timing(int32_t enable, int32_t reset, double *total_ms, int64_t *launches) {
+  if (enable && !g_event_timer) g_event_timer = new EventTimer;
+  if (g_event_timer) {
+    if (total_ms)
+      for (int k = 0; k < PD_KF_N; ++k) total_ms[k] = g_event_timer->total_ms[k];
+    if (launches)
+      for (int k = 0; k < PD_KF_N; ++k) launches[k] = g_event_timer->launches[k];
+    if (reset) g_event_timer->reset();
+  } else {
+    if (total_ms)
+      for (int k = 0; k < PD_KF_N; ++k) total_ms[k] = 0;
+    if (launches)
+      for (int k = 0; k < PD_KF_N; ++k) launches[k] = 0;
+  }
+  pd::g_timer = enable ? g_event_timer : nullptr;
+  return PD_OK;
 }
 
 int pd_get_solution(const pd_instance *I, double *out, int32_t layout, int32_t device_ptr) {
@@ -941,6 +1037,7 @@ int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double 
   SolveParams sp{theta, 1e-300, 1e-3, 1, 1, 1};
   if ((rc = init_scalars(I, sp, 1, s))) return rc;
   pd::launch_level_begin(P.L, s);
+  pd::launch_factor(P.L, s);
   pd::launch_begin(P.L, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

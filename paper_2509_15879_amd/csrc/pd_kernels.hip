@@ -16,12 +16,16 @@
 //   BiCGSTAB cycles k_rad -> k_ang -> k_sten<V> -> k_rad -> k_ang -> k_sten<T> -> k_elem_x
 //   (mixed precision: k_sten<UR> refines in FP64 between FP32 inner solves)
 //   k_level_end
-// The preconditioner is the alternating-line product
-//   M = (D + R) D^{-1} (D + Θ),  M^{-1} y = (I + D^{-1}Θ)^{-1} (D + R)^{-1} y,
-// where D is the diagonal of A = I/Δt + θ L_h, R its radial (same-column)
-// couplings and Θ its angular (same-ring, periodic) couplings; the origin
-// row is scaled by its diagonal.  The radial blocks are the tridiagonal A_j
-// of (2.12).
+// The Krylov iteration runs on the diagonally scaled system D^{-1}A x = D^{-1}b
+// (D the diagonal of A = I/Δt + θ L_h), whose residual weighs every row
+// alike: the unscaled residual is dominated by the few rows next to r = 1
+// (and next to the origin) whose coefficients grow like 1/h² on graded
+// meshes.  The preconditioner of the scaled system is the alternating-line
+// product
+//   M = (I + D^{-1}R)(I + D^{-1}Θ),  M^{-1} y = (I + D^{-1}Θ)^{-1} (I + D^{-1}R)^{-1} y,
+// with R the radial (same-column) couplings and Θ the angular (same-ring,
+// periodic) couplings of A; the origin row is left as is (unit diagonal).
+// The radial blocks are the tridiagonal A_j of (2.12).
 //
 // Arithmetic is FP64 throughout; the FP32 inner solve of the mixed-precision
 // mode only stores its vectors, faces and multipliers in FP32 (pivots stay
@@ -218,10 +222,11 @@ __device__ __forceinline__ double diag_at(const PdInst &I, int i, int j, double 
   return inv_dt + th * v;
 }
 
-// Radial-line LU of (D + R) for column j:  rows i = 1..m, diagonal d_i,
-// sub-diagonal a_i = -θ gp_r(i-1/2)/V (i >= 2), super c_i = -θ gm_r(i+1/2)/V.
-// Stored: uinv_i = 1/u_i, f_i = a_i/u_i, g_i = c_i/u_i, so that
-// forward  w_i = uinv_i y_i - f_i w_{i-1},  backward  x_i = w_i - g_i x_{i+1}.
+// Radial-line LU of (I + D^{-1}R) for column j:  rows i = 1..m, diagonal 1,
+// sub-diagonal a_i = -θ gp_r(i-1/2)/(V d_i) (i >= 2), super
+// c_i = -θ gm_r(i+1/2)/(V d_i).  Stored: uinv_i = 1/u_i, f_i = a_i/u_i,
+// g_i = c_i/u_i, so that forward  w_i = uinv_i y_i - f_i w_{i-1},
+// backward  x_i = w_i - g_i x_{i+1}.  Also stores d and 1/d.
 __global__ void k_fact_rad(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
@@ -235,12 +240,15 @@ __global__ void k_fact_rad(const PdInst *insts, const int2 *map) {
     for (int i = 1; i <= m; ++i) {
       const int idx = (i - 1) * n + j;
       const double d = diag_at(I, i, j, inv_dt, th);
-      const double ivV = I.inv_rw[i] * I.inv_dth[j];
+      const double id = 1.0 / d;
+      const double ivV = I.inv_rw[i] * I.inv_dth[j] * id;
       const double a = (i >= 2) ? -th * ivV * I.k64.gp_r[(i - 1) * n + j] : 0.0;
       const double c = (i < m) ? -th * ivV * I.k64.gm_r[i * n + j] : 0.0;
-      const double u = d - a * c_prev / u_prev;
+      const double u = 1.0 - a * c_prev / u_prev;
       const double ui = 1.0 / u;
       I.diag[idx] = d;
+      I.inv_diag[idx] = id;
+      if (I.mixed) I.inv_diag32[idx] = (float)id;
       I.rf_uinv[idx] = ui;
       I.k64.rf_f[idx] = a * ui;
       I.k64.rf_g[idx] = c * ui;
@@ -257,7 +265,10 @@ __global__ void k_fact_rad(const PdInst *insts, const int2 *map) {
     for (int jj = 0; jj < n; ++jj) s += I.k64.gp_r[jj];
     double v = I.inv_V0 * s;
     if (I.has_b) v += I.b_node[m * n];
-    I.diag[m * n] = inv_dt + th * v;
+    const double d0 = inv_dt + th * v;
+    I.diag[m * n] = d0;
+    I.inv_diag[m * n] = 1.0 / d0;
+    if (I.mixed) I.inv_diag32[m * n] = (float)(1.0 / d0);
   }
 }
 
@@ -469,18 +480,20 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
             const double xg = ex ? xc[0] + rho * (xc[0] - xc[1]) : xc[0];
             const double Lg = ex ? Lx[0] + rho * (Lx[0] - Lx[1]) : Lx[0];
             const double r = b - (inv_dt * xg + th * Lg);
+            const double idg = I.inv_diag[idx];
+            const double rs = r * idg, bs = b * idg;
             I.bvec[idx] = b;
             x0[idx] = xg;
             if (I.mixed) {
               I.rout[idx] = r;
-              I.k32.r[idx] = (float)r;
-              I.k32.rh[idx] = (float)r;
+              I.k32.r[idx] = (float)rs;
+              I.k32.rh[idx] = (float)rs;
             } else {
-              I.k64.r[idx] = r;
-              I.k64.rh[idx] = r;
+              I.k64.r[idx] = rs;
+              I.k64.rh[idx] = rs;
             }
-            acc[0] += b * b;
-            acc[1] += r * r;
+            acc[0] += bs * bs;
+            acc[1] += rs * rs;
           });
     acc[2] = S0[0];
     acc[3] = S0[1];
@@ -496,17 +509,19 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       const double xg = ex ? xk0 + rho * (xk0 - xkm0) : xk0;
       const double Lg = ex ? L0 + rho * (L0 - L1) : L0;
       const double r = b - (inv_dt * xg + th * Lg);
+      const double idg = I.inv_diag[orig];
+      const double rs = r * idg, bs = b * idg;
       I.bvec[orig] = b;
       x0[orig] = xg;
       if (I.mixed) {
         I.rout[orig] = r;
-        I.k32.r[orig] = (float)r;
-        I.k32.rh[orig] = (float)r;
+        I.k32.r[orig] = (float)rs;
+        I.k32.rh[orig] = (float)rs;
       } else {
-        I.k64.r[orig] = r;
-        I.k64.rh[orig] = r;
+        I.k64.r[orig] = rs;
+        I.k64.rh[orig] = rs;
       }
-      const double bb = tot[0] + b * b, rr = tot[1] + r * r;
+      const double bb = tot[0] + bs * bs, rr = tot[1] + rs * rs;
       sc->bnorm2 = bb;
       sc->rnorm2 = rr;
       sc->r0norm2 = rr;
@@ -529,7 +544,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (wave_on)
       sten_tile<TK, TK, 1>(I, KS.gp_r, KS.gm_r, KS.gp_t, KS.gm_t, X, cg, rg, S0,
                            [&](int, int, int idx, const double *xc, const double *Lx) {
-                             const double y = inv_dt * xc[0] + th * Lx[0];
+                             const double y = (inv_dt * xc[0] + th * Lx[0]) * ld(KS.inv_d, idx);
                              const TK ys = (TK)y;
                              yout[idx] = ys;
                              const double yd = (double)ys;
@@ -543,7 +558,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
         threadIdx.x == 0) {
       const double bo = I.has_b ? I.b_node[orig] : 0.0;
       const double x0 = ld(xin, orig);
-      const double y0 = inv_dt * x0 + th * (I.inv_V0 * tot[2] + bo * x0);
+      const double y0 = (inv_dt * x0 + th * (I.inv_V0 * tot[2] + bo * x0)) * ld(KS.inv_d, orig);
       const TK ys = (TK)y0;
       yout[orig] = ys;
       const double yd = (double)ys;
@@ -583,11 +598,12 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       sten_tile<double, float, 1>(I, I.k64.gp_r, I.k64.gm_r, I.k64.gp_t, I.k64.gm_t, X, cg, rg, S0,
                                   [&](int, int, int idx, const double *xc, const double *Lx) {
                                     const double r = I.rout[idx] - (inv_dt * xc[0] + th * Lx[0]);
+                                    const double rs = r * I.inv_diag[idx];
                                     I.rout[idx] = r;
                                     x[idx] += xc[0];
-                                    I.k32.r[idx] = (float)r;
-                                    I.k32.rh[idx] = (float)r;
-                                    acc[0] += r * r;
+                                    I.k32.r[idx] = (float)rs;
+                                    I.k32.rh[idx] = (float)rs;
+                                    acc[0] += rs * rs;
                                   });
     acc[1] = S0[0];
     double tot[2];
@@ -596,11 +612,12 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       const double bo = I.has_b ? I.b_node[orig] : 0.0;
       const double d0 = (double)I.k32.d[orig];
       const double r = I.rout[orig] - (inv_dt * d0 + th * (I.inv_V0 * tot[1] + bo * d0));
+      const double rs = r * I.inv_diag[orig];
       I.rout[orig] = r;
       x[orig] += d0;
-      I.k32.r[orig] = (float)r;
-      I.k32.rh[orig] = (float)r;
-      const double rr = tot[0] + r * r;
+      I.k32.r[orig] = (float)rs;
+      I.k32.rh[orig] = (float)rs;
+      const double rr = tot[0] + rs * rs;
       sc->rnorm2 = rr;
       sc->outer += 1;
       sc->rel_resid = sqrt(rr / sc->bnorm2);
@@ -688,11 +705,10 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
     }
   };
 
-  // origin (one thread of the instance's first block)
+  // origin (one thread of the instance's first block): unit diagonal
   if (mp.y == 0 && threadIdx.x == 0) {
     const int o = m * n;
-    const double y = input(o);
-    out[o] = (T)(y / I.diag[o]);
+    out[o] = (T)input(o);
   }
 
   // forward local pass
@@ -944,36 +960,56 @@ __global__ void k_clear_reset(PdInst *insts, int ninst) {
 
 namespace pd {
 
+KTimer *g_timer = nullptr;
+
 static inline dim3 g1(int n) { return dim3((unsigned)n); }
 
+struct Mark {
+  int f;
+  hipStream_t s;
+  Mark(int fam, hipStream_t st) : f(fam), s(st) {
+    if (g_timer) g_timer->mark(f, true, s);
+  }
+  ~Mark() {
+    if (g_timer) g_timer->mark(f, false, s);
+  }
+};
+enum { KF_BEGIN = 0, KF_FACTOR = 1, KF_RAD = 2, KF_ANG = 3, KF_STEN_V = 4, KF_STEN_T = 5,
+       KF_UPDATE = 6, KF_REFINE = 7, KF_CONTROL = 8 };
+
 void launch_level_begin(const LaunchSet &L, hipStream_t s) {
+  Mark mk(KF_CONTROL, s);
   k_level_begin<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
 }
 void launch_level_end(const LaunchSet &L, hipStream_t s) {
+  Mark mk(KF_CONTROL, s);
   k_level_end<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
 }
 void launch_factor(const LaunchSet &L, hipStream_t s) {
+  Mark mk(KF_FACTOR, s);
   if (L.nb_frad) k_fact_rad<<<g1(L.nb_frad), 64, 0, s>>>(L.insts, L.map_frad);
   if (L.nb_fang) k_fact_ang<<<g1(L.nb_fang), 64, 0, s>>>(L.insts, L.map_fang);
 }
 void launch_begin(const LaunchSet &L, hipStream_t s) {
+  Mark mk(KF_BEGIN, s);
   k_sten<double, SM_BEGIN><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr);
 }
 
 template <typename T>
 static void cycle_t(const LaunchSet &L, hipStream_t s) {
-  k_rad<T, RM_P><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, nullptr, nullptr);
-  k_clear_reset<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
-  k_ang<T, AM_P><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, nullptr, nullptr);
-  k_sten<T, SM_V><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr);
-  k_rad<T, RM_S><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, nullptr, nullptr);
-  k_ang<T, AM_S><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, nullptr, nullptr);
-  k_sten<T, SM_T><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr);
-  k_elem_x<T><<<g1(L.nb_elem), 256, 0, s>>>(L.insts, L.map_elem);
+  { Mark mk(KF_RAD, s); k_rad<T, RM_P><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, nullptr, nullptr); }
+  { Mark mk(KF_CONTROL, s); k_clear_reset<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst); }
+  { Mark mk(KF_ANG, s); k_ang<T, AM_P><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, nullptr, nullptr); }
+  { Mark mk(KF_STEN_V, s); k_sten<T, SM_V><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr); }
+  { Mark mk(KF_RAD, s); k_rad<T, RM_S><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, nullptr, nullptr); }
+  { Mark mk(KF_ANG, s); k_ang<T, AM_S><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, nullptr, nullptr); }
+  { Mark mk(KF_STEN_T, s); k_sten<T, SM_T><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr); }
+  { Mark mk(KF_UPDATE, s); k_elem_x<T><<<g1(L.nb_elem), 256, 0, s>>>(L.insts, L.map_elem); }
 }
 
 void launch_cycle(const LaunchSet &L, hipStream_t s) {
   if (L.mixed_any) {
+    Mark mk(KF_REFINE, s);
     k_sten<float, SM_UR><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr);
   }
   if (L.mixed_any && !L.fp64_any) {

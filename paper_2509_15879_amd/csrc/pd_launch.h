@@ -16,6 +16,13 @@ struct LaunchSet {
   int mixed_any = 0, fp64_any = 0;
 };
 
+// Optional per-family event timing of launches (diagnostics).
+struct KTimer {
+  virtual void mark(int family, bool start, hipStream_t s) = 0;
+  virtual ~KTimer() {}
+};
+extern KTimer *g_timer;
+
 void launch_level_begin(const LaunchSet &L, hipStream_t s);
 void launch_level_end(const LaunchSet &L, hipStream_t s);
 void launch_factor(const LaunchSet &L, hipStream_t s);

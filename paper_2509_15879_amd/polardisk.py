@@ -66,7 +66,9 @@ class StepStats(C.Structure):
 EXPORTS = ("pd_mesh_coords", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
-           "pd_batch_destroy", "pd_last_error")
+           "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
+
+KERNEL_FAMILIES = ("begin", "factor", "rad", "ang", "sten_v", "sten_t", "update", "refine", "control")
 
 
 def _load():
@@ -92,6 +94,7 @@ def _load():
                             C.POINTER(U64)],
         "pd_batch_poll": [P, U64, P, P],
         "pd_batch_destroy": [P],
+        "pd_kernel_timing": [I32, I32, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -266,9 +269,19 @@ class Instance:
 
 
 def solve_batch(instances: Sequence[Instance], tds: Sequence[TimeDesc]):
+    """Advances all instances together; returns every step's statistics per instance."""
     n = len(instances)
     hs = (C.c_void_p * n)(*[i.h for i in instances])
     arr = (TimeDesc * n)(*tds)
-    st = (StepStats * n)()
-    _check(lib.pd_solve_batch(hs, n, arr, C.cast(st, C.c_void_p)))
-    return [s.as_dict() for s in st]
+    sts = [(StepStats * td.K)() for td in tds]
+    ptrs = (C.c_void_p * n)(*[C.cast(s, C.c_void_p) for s in sts])
+    _check(lib.pd_solve_batch(hs, n, arr, ptrs))
+    return [[s.as_dict() for s in st] for st in sts]
+
+
+def kernel_timing(enable: bool, reset: bool = False):
+    """Per-family kernel time (ms) and launch counts since the last reset."""
+    ms = np.zeros(len(KERNEL_FAMILIES))
+    cnt = np.zeros(len(KERNEL_FAMILIES), dtype=np.int64)
+    _check(lib.pd_kernel_timing(int(enable), int(reset), _ptr(ms), _ptr(cnt)))
+    return dict(zip(KERNEL_FAMILIES, ms)), dict(zip(KERNEL_FAMILIES, cnt))
