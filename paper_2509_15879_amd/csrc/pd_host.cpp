@@ -156,16 +156,16 @@ Tiling make_tiling(int m, int n) {
   t.nb_sten = (t.ncg * t.nrg + PD_STEN_WAVES - 1) / PD_STEN_WAVES;
   const int N = m * n + 1;
   t.nb_elem = (N + PD_ELEM_PER_BLOCK - 1) / PD_ELEM_PER_BLOCK;
-  // radial sweep: widest column group whose segments fit in registers
-  t.cw = 64;
-  while (t.cw > 8 && (m + (PD_RAD_THREADS / t.cw) - 1) / (PD_RAD_THREADS / t.cw) > PD_RAD_BMAX) t.cw /= 2;
+  // radial sweep and factorisation: 16 columns (one 128-byte line of FP64)
+  // per block, 64 segments per column
+  t.cw = 16;
   t.nseg = PD_RAD_THREADS / t.cw;
   t.brad = (m + t.nseg - 1) / t.nseg;
   t.nb_rad = (n + t.cw - 1) / t.cw;
   t.bang = (n + 63) / 64;
   t.nb_ang = (m + 3) / 4;
-  t.nb_frad = (n + 63) / 64;
-  t.nb_fang = (m + 63) / 64;
+  t.nb_frad = t.nb_rad;
+  t.nb_fang = t.nb_ang;
   t.npad = ((N + 63) / 64) * 64;
   return t;
 }
@@ -474,6 +474,8 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
     hv[q].n_active = P.n_active;
     P.L.mixed_any |= insts[q]->precision == PD_MIXED;
     P.L.fp64_any |= insts[q]->precision != PD_MIXED;
+    P.L.max_brad = std::max(P.L.max_brad, insts[q]->T.brad);
+    P.L.max_bang = std::max(P.L.max_bang, insts[q]->T.bang);
   }
   HIPCHK(hipMalloc(&P.L.insts, ninst * sizeof(PdInst)));
   P.bufs.push_back(P.L.insts);
@@ -494,8 +496,6 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
   if ((rc = upload(&P.L.map_elem, &P.L.nb_elem, [](pd_instance *I) { return I->T.nb_elem; }))) return rc;
   if ((rc = upload(&P.L.map_rad, &P.L.nb_rad, [](pd_instance *I) { return I->T.nb_rad; }))) return rc;
   if ((rc = upload(&P.L.map_ang, &P.L.nb_ang, [](pd_instance *I) { return I->T.nb_ang; }))) return rc;
-  if ((rc = upload(&P.L.map_frad, &P.L.nb_frad, [](pd_instance *I) { return I->T.nb_frad; }))) return rc;
-  if ((rc = upload(&P.L.map_fang, &P.L.nb_fang, [](pd_instance *I) { return I->T.nb_fang; }))) return rc;
   HIPCHK(hipHostMalloc((void **)&P.h_active, 2 * sizeof(int)));
   P.h_active[0] = P.h_active[1] = 1;
   for (auto &e : P.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));

@@ -10,8 +10,8 @@
 // One time level (scheme (2.5) of §2.1, Ch. 3 scheme of §3.2.1, system
 // (2.11)/(2.12)) is
 //   k_level_begin   per-instance set-up: Δt, θ, source weights, extrapolation
-//   k_fact_rad      radial-line LU of (D + R) per θ-column (when Δt/θ change)
-//   k_fact_ang      ring-periodic LU of (I + D^{-1} Θ) per ring, Sherman-Morrison
+//   k_fact_rad      radial-line LU of (I + D^{-1}R) per θ-column (when Δt/θ change)
+//   k_fact_ang      ring-periodic LU of (I + D^{-1}Θ) per ring, Sherman-Morrison
 //   k_sten<BEGIN>   rhs, extrapolated initial guess and its residual
 //   BiCGSTAB cycles k_rad -> k_ang -> k_sten<V> -> k_rad -> k_ang -> k_sten<T> -> k_elem_x
 //   (mixed precision: k_sten<UR> refines in FP64 between FP32 inner solves)
@@ -27,26 +27,43 @@
 // periodic) couplings of A; the origin row is left as is (unit diagonal).
 // The radial blocks are the tridiagonal A_j of (2.12).
 //
+// Both tridiagonal families are solved by segmented scans: a thread owns a
+// contiguous segment of a line, substitutes locally in registers, and the
+// segments are joined by composing their affine maps w -> P w + e (forward
+// and backward substitution) or their 2x2 continuant matrices (the pivot
+// recurrence of the factorisation).  Radial lines join through LDS across
+// the waves of a block; rings join across the lanes of one wave.
+//
 // Arithmetic is FP64 throughout; the FP32 inner solve of the mixed-precision
 // mode only stores its vectors, faces and multipliers in FP32 (pivots stay
-// FP64).
+// FP64).  Pointers taken from the instance descriptor are handed to the
+// bodies as restrict-qualified global-address-space pointers, so that loads
+// of different arrays can be in flight together.
 
 #include "pd_device.h"
 
 #include <math.h>
 
+#define GAS __attribute__((address_space(1)))
+
 namespace pd {
 
 // ------------------------------------------------------------------ helpers
+
+template <class T>
+__device__ __forceinline__ GAS T *G(T *p) {
+  return (GAS T *)p;
+}
+template <class T>
+__device__ __forceinline__ const GAS T *G(const T *p) {
+  return (const GAS T *)p;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-
-template <typename T>
-__device__ __forceinline__ double ld(const T *p, int i) { return (double)p[i]; }
 
 __device__ __forceinline__ double tau_q(double lam, int tp, double t) {
   double v = exp(lam * t);
@@ -141,6 +158,14 @@ __device__ __forceinline__ const KSet<double> &kset<double>(const PdInst &I) { r
 template <>
 __device__ __forceinline__ const KSet<float> &kset<float>(const PdInst &I) { return I.k32; }
 
+// Composition of affine maps u -> P u + e:  (P2, e2) ∘ (P1, e1).
+struct Aff {
+  double P, e;
+};
+__device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
+  return {later.P * earlier.P, later.P * earlier.e + later.e};
+}
+
 // ------------------------------------------------------------ level control
 
 // Per-instance set-up of a time level t_k -> t_{k+1} (one thread per instance).
@@ -209,66 +234,129 @@ __global__ void k_level_end(PdInst *insts, int ninst) {
 }
 
 // ------------------------------------------------------------ factorisations
+//
+// Radial lines of (I + D^{-1}R), column j, rows i = 1..m: diagonal 1,
+// sub-diagonal a_i = -θ gp_r(i-1/2)/(V_i d_i) (i >= 2), super-diagonal
+// c_i = -θ gm_r(i+1/2)/(V_i d_i) (i < m).  Pivots u_1 = 1,
+// u_i = 1 - a_i c_{i-1}/u_{i-1}.  Stored: uinv_i = 1/u_i, f_i = a_i/u_i,
+// g_i = c_i/u_i, so that forward  w_i = uinv_i y_i - f_i w_{i-1}  and
+// backward  x_i = w_i - g_i x_{i+1}.  Also stores d and 1/d.
+//
+// The pivot recurrence is the ratio u_i = q_i/q_{i-1} of the continuants
+// q_i = q_{i-1} - a_i c_{i-1} q_{i-2}, a linear recurrence: each segment
+// multiplies its 2x2 matrices [[1, -a_i c_{i-1}], [1, 0]] (rescaled to stay
+// in range), the segments' products are chained through LDS to give every
+// segment its incoming u, and each segment then runs the pivot recurrence
+// on its own rows.
 
-// Diagonal of A = I/dt + θ L_h at ring node (i, j) (i = 1..m).
-__device__ __forceinline__ double diag_at(const PdInst &I, int i, int j, double inv_dt, double th) {
-  const int n = I.n;
+struct RadRow {
+  double d, a, c;   // diagonal of A, scaled sub and super entries
+};
+
+__device__ __forceinline__ RadRow rad_row(const PdInst &I, int i, int j, double inv_dt, double th) {
+  const int m = I.m, n = I.n;
   const int jl = (j == 0) ? n - 1 : j - 1;
-  const double *gpr = I.k64.gp_r, *gmr = I.k64.gm_r, *gpt = I.k64.gp_t, *gmt = I.k64.gm_t;
+  const GAS double *gpr = G(I.k64.gp_r), *gmr = G(I.k64.gm_r);
+  const GAS double *gpt = G(I.k64.gp_t), *gmt = G(I.k64.gm_t);
   const int row = (i - 1) * n;
-  double s = gpr[i * n + j] + gmr[(i - 1) * n + j] + gpt[row + j] + gmt[row + jl];
-  double v = I.inv_rw[i] * I.inv_dth[j] * s;
-  if (I.has_b) v += I.b_node[row + j];
-  return inv_dt + th * v;
+  const double gpo = gpr[i * n + j], gmo = gmr[i * n + j];
+  const double gpi = gpr[(i - 1) * n + j], gmi = gmr[(i - 1) * n + j];
+  const double ivV = G(I.inv_rw)[i] * G(I.inv_dth)[j];
+  double v = ivV * (gpo + gmi + gpt[row + j] + gmt[row + jl]);
+  if (I.has_b) v += G(I.b_node)[row + j];
+  RadRow R;
+  R.d = inv_dt + th * v;
+  const double s = th * ivV / R.d;
+  R.a = (i >= 2) ? -s * gpi : 0.0;
+  R.c = (i < m) ? -s * gmo : 0.0;
+  return R;
 }
 
-// Radial-line LU of (I + D^{-1}R) for column j:  rows i = 1..m, diagonal 1,
-// sub-diagonal a_i = -θ gp_r(i-1/2)/(V d_i) (i >= 2), super
-// c_i = -θ gm_r(i+1/2)/(V d_i).  Stored: uinv_i = 1/u_i, f_i = a_i/u_i,
-// g_i = c_i/u_i, so that forward  w_i = uinv_i y_i - f_i w_{i-1},
-// backward  x_i = w_i - g_i x_{i+1}.  Also stores d and 1/d.
-__global__ void k_fact_rad(const PdInst *insts, const int2 *map) {
+struct Mat2 {
+  double a, b, c, d;   // [[a, b], [c, d]]
+};
+__device__ __forceinline__ Mat2 mul2(Mat2 x, Mat2 y) {
+  return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
+}
+__device__ __forceinline__ Mat2 norm2(Mat2 x) {
+  const double s = fmax(fmax(fabs(x.a), fabs(x.b)), fmax(fabs(x.c), fabs(x.d)));
+  const double k = (s > 0.0) ? 1.0 / s : 1.0;
+  return {x.a * k, x.b * k, x.c * k, x.d * k};
+}
+
+__global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   const PdScalars *sc = I.sc;
   if (sc->status != ST_ACTIVE || !sc->refactor) return;
-  const int j = mp.y * blockDim.x + threadIdx.x;
-  const int m = I.m, n = I.n;
+  const int m = I.m, n = I.n, cw = I.cw, B = I.brad;
+  const int c = threadIdx.x % cw, seg = threadIdx.x / cw;
+  const int j = mp.y * cw + c;
+  const bool act = j < n;
+  const int k0 = seg * B;                          // first 0-based row of the segment
+  const int cnt = act ? max(0, min(B, m - k0)) : 0;
   const double th = sc->theta, inv_dt = sc->inv_dt;
-  if (j < n) {
-    double u_prev = 1.0, c_prev = 0.0;
-    for (int i = 1; i <= m; ++i) {
-      const int idx = (i - 1) * n + j;
-      const double d = diag_at(I, i, j, inv_dt, th);
-      const double id = 1.0 / d;
-      const double ivV = I.inv_rw[i] * I.inv_dth[j] * id;
-      const double a = (i >= 2) ? -th * ivV * I.k64.gp_r[(i - 1) * n + j] : 0.0;
-      const double c = (i < m) ? -th * ivV * I.k64.gm_r[i * n + j] : 0.0;
-      const double u = 1.0 - a * c_prev / u_prev;
-      const double ui = 1.0 / u;
-      I.diag[idx] = d;
-      I.inv_diag[idx] = id;
-      if (I.mixed) I.inv_diag32[idx] = (float)id;
-      I.rf_uinv[idx] = ui;
-      I.k64.rf_f[idx] = a * ui;
-      I.k64.rf_g[idx] = c * ui;
-      if (I.mixed) {
-        I.k32.rf_f[idx] = (float)(a * ui);
-        I.k32.rf_g[idx] = (float)(c * ui);
-      }
-      u_prev = u;
-      c_prev = c;
+
+  __shared__ double lm[4][PD_RAD_THREADS];
+  // super entry of the row before the segment
+  double c_prev = 0.0;
+  if (cnt > 0 && k0 >= 1) c_prev = rad_row(I, k0, j, inv_dt, th).c;
+  // segment product of continuant matrices
+  Mat2 Mp{1.0, 0.0, 0.0, 1.0};
+  double cp = c_prev;
+  for (int k = 0; k < cnt; ++k) {
+    const RadRow R = rad_row(I, k0 + k + 1, j, inv_dt, th);
+    const Mat2 Mi{1.0, -R.a * cp, 1.0, 0.0};
+    Mp = norm2(mul2(Mi, Mp));
+    cp = R.c;
+  }
+  lm[0][threadIdx.x] = Mp.a;
+  lm[1][threadIdx.x] = Mp.b;
+  lm[2][threadIdx.x] = Mp.c;
+  lm[3][threadIdx.x] = Mp.d;
+  __syncthreads();
+  // incoming (q_{k0}, q_{k0-1}) from the products of the earlier segments
+  double q1 = 1.0, q0 = 0.0;
+  for (int s2 = 0; s2 < seg; ++s2) {
+    const int t = s2 * cw + c;
+    const double n1 = lm[0][t] * q1 + lm[1][t] * q0;
+    const double n0 = lm[2][t] * q1 + lm[3][t] * q0;
+    const double sc2 = fmax(fabs(n1), fabs(n0));
+    q1 = n1 / sc2;
+    q0 = n0 / sc2;
+  }
+  double u_prev = (q0 != 0.0) ? q1 / q0 : 1.0;
+  cp = c_prev;
+  GAS double *dg = G(I.diag), *idg = G(I.inv_diag), *uinv = G(I.rf_uinv);
+  GAS double *ff = G(I.k64.rf_f), *gg = G(I.k64.rf_g);
+  for (int k = 0; k < cnt; ++k) {
+    const int i = k0 + k + 1;
+    const RadRow R = rad_row(I, i, j, inv_dt, th);
+    const double u = 1.0 - R.a * cp / u_prev;
+    const double ui = 1.0 / u;
+    const int idx = (i - 1) * n + j;
+    dg[idx] = R.d;
+    idg[idx] = 1.0 / R.d;
+    uinv[idx] = ui;
+    ff[idx] = R.a * ui;
+    gg[idx] = R.c * ui;
+    if (I.mixed) {
+      G(I.inv_diag32)[idx] = (float)(1.0 / R.d);
+      G(I.k32.rf_f)[idx] = (float)(R.a * ui);
+      G(I.k32.rf_g)[idx] = (float)(R.c * ui);
     }
+    u_prev = u;
+    cp = R.c;
   }
   if (mp.y == 0 && threadIdx.x == 0) {
     double s = 0.0;
-    for (int jj = 0; jj < n; ++jj) s += I.k64.gp_r[jj];
+    for (int jj = 0; jj < n; ++jj) s += G(I.k64.gp_r)[jj];
     double v = I.inv_V0 * s;
-    if (I.has_b) v += I.b_node[m * n];
+    if (I.has_b) v += G(I.b_node)[m * n];
     const double d0 = inv_dt + th * v;
-    I.diag[m * n] = d0;
-    I.inv_diag[m * n] = 1.0 / d0;
-    if (I.mixed) I.inv_diag32[m * n] = (float)(1.0 / d0);
+    dg[m * n] = d0;
+    idg[m * n] = 1.0 / d0;
+    if (I.mixed) G(I.inv_diag32)[m * n] = (float)(1.0 / d0);
   }
 }
 
@@ -279,64 +367,160 @@ __global__ void k_fact_rad(const PdInst *insts, const int2 *map) {
 // non-periodic T0 has diagonal 2 at row 0 and 1 + γ_{n-1} α_0 at row n-1;
 // z = T0^{-1} u and κ = 1/(1 + z_0 - α_0 z_{n-1}) are stored so that
 // x = y - κ (y_0 - α_0 y_{n-1}) z with y = T0^{-1} d.
-__global__ void k_fact_ang(const PdInst *insts, const int2 *map) {
+// One wave per ring; lane L owns the nodes [L*bang, (L+1)*bang).
+
+__device__ __forceinline__ void ang_coef(const PdInst &I, int i, int j, double th, double &al,
+                                         double &ga) {
+  const int n = I.n;
+  const int row = (i - 1) * n;
+  const int jl = (j == 0) ? n - 1 : j - 1;
+  const double s = -th * G(I.inv_rw)[i] * G(I.inv_dth)[j] / G(I.diag)[row + j];
+  al = s * G(I.k64.gp_t)[row + jl];
+  ga = s * G(I.k64.gm_t)[row + j];
+}
+
+template <int BM>
+__global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   const PdScalars *sc = I.sc;
   if (sc->status != ST_ACTIVE || !sc->refactor) return;
-  const int i = mp.y * blockDim.x + threadIdx.x + 1;
-  const int m = I.m, n = I.n;
-  if (i > m) return;
+  const int m = I.m, n = I.n, B = I.bang;
+  const int lane = threadIdx.x & 63;
+  const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
+  if (i > m) return;                                  // whole wave exits together
   const double th = sc->theta;
   const int row = (i - 1) * n;
-  const double irw = I.inv_rw[i];
-  auto alpha_j = [&](int j) {
-    const int jl = (j == 0) ? n - 1 : j - 1;
-    return -th * irw * I.inv_dth[j] * I.k64.gp_t[row + jl] / I.diag[row + j];
-  };
-  auto gamma_j = [&](int j) {
-    return -th * irw * I.inv_dth[j] * I.k64.gm_t[row + j] / I.diag[row + j];
-  };
-  const double a0 = alpha_j(0);
-  const double gl = gamma_j(n - 1);
-  // factor T0 and solve T0 z = u on the fly (forward), then backward for z
-  double u_prev = 1.0, c_prev = 0.0, zf_prev = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double a = (j >= 1) ? alpha_j(j) : 0.0;
-    const double c = (j < n - 1) ? gamma_j(j) : 0.0;
-    double dj = 1.0;
-    if (j == 0) dj = 2.0;
-    if (j == n - 1) dj = 1.0 + gl * a0;
-    const double u = dj - a * c_prev / u_prev;
-    const double ui = 1.0 / u;
-    const double f = a * ui, g = c * ui;
-    I.af_uinv[row + j] = ui;
-    I.k64.af_f[row + j] = f;
-    I.k64.af_g[row + j] = g;
-    const double uj = (j == 0) ? -1.0 : ((j == n - 1) ? gl : 0.0);
-    const double zf = ui * uj - f * zf_prev;   // forward substitution of u
-    I.k64.af_z[row + j] = zf;
-    zf_prev = zf;
-    u_prev = u;
-    c_prev = c;
-  }
-  double xn = 0.0;
-  double z0 = 0.0, zl = 0.0;
-  for (int j = n - 1; j >= 0; --j) {
-    const double x = I.k64.af_z[row + j] - I.k64.af_g[row + j] * xn;
-    I.k64.af_z[row + j] = x;
-    if (j == n - 1) zl = x;
-    if (j == 0) z0 = x;
-    xn = x;
-  }
-  I.af_kappa[i - 1] = 1.0 / (1.0 + z0 - a0 * zl);
-  I.af_alpha0[i - 1] = a0;
-  if (I.mixed) {
-    for (int j = 0; j < n; ++j) {
-      I.k32.af_f[row + j] = (float)I.k64.af_f[row + j];
-      I.k32.af_g[row + j] = (float)I.k64.af_g[row + j];
-      I.k32.af_z[row + j] = (float)I.k64.af_z[row + j];
+  const int j0 = lane * B;
+  const int cnt = max(0, min(B, n - j0));
+  double a0, gl, tmp;
+  ang_coef(I, i, 0, th, a0, tmp);
+  ang_coef(I, i, n - 1, th, tmp, gl);
+
+  double al[BM] = {}, ga[BM] = {}, dd[BM] = {};
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      const int j = j0 + k;
+      ang_coef(I, i, j, th, al[k], ga[k]);
+      dd[k] = (j == 0) ? 2.0 : ((j == n - 1) ? 1.0 + gl * a0 : 1.0);
+      if (j == 0) al[k] = 0.0;          // T0 drops the corners
+      if (j == n - 1) ga[k] = 0.0;
     }
+  }
+  // γ of the row before this lane's segment
+  double gprev = 0.0;
+  if (cnt > 0 && j0 >= 1) {
+    double t0;
+    ang_coef(I, i, j0 - 1, th, t0, gprev);
+  }
+  // segment continuant product, then an exclusive scan over the lanes
+  Mat2 Mp{1.0, 0.0, 0.0, 1.0};
+  double cp = gprev;
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      const Mat2 Mi{dd[k], -al[k] * cp, 1.0, 0.0};
+      Mp = norm2(mul2(Mi, Mp));
+      cp = ga[k];
+    }
+  }
+  Mat2 S = Mp;   // inclusive product over lanes 0..lane (later lanes on the left)
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    Mat2 o{__shfl_up(S.a, d, 64), __shfl_up(S.b, d, 64), __shfl_up(S.c, d, 64), __shfl_up(S.d, d, 64)};
+    if (lane >= d) S = norm2(mul2(S, o));
+  }
+  Mat2 E{__shfl_up(S.a, 1, 64), __shfl_up(S.b, 1, 64), __shfl_up(S.c, 1, 64), __shfl_up(S.d, 1, 64)};
+  // incoming (q_{j0-1}, q_{j0-2}) = E (1, 0)
+  double q1 = E.a, q0 = E.c;
+  if (lane == 0) {
+    q1 = 1.0;
+    q0 = 0.0;
+  }
+  double u_prev = (q0 != 0.0) ? q1 / q0 : 1.0;
+  cp = gprev;
+  double fl[BM] = {}, gf[BM] = {}, ul[BM] = {};
+  GAS double *uinv = G(I.af_uinv), *ff = G(I.k64.af_f), *gg = G(I.k64.af_g), *zz = G(I.k64.af_z);
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      const double u = dd[k] - al[k] * cp / u_prev;
+      const double ui = 1.0 / u;
+      ul[k] = ui;
+      fl[k] = al[k] * ui;
+      gf[k] = ga[k] * ui;
+      uinv[row + j0 + k] = ui;
+      ff[row + j0 + k] = fl[k];
+      gg[row + j0 + k] = gf[k];
+      u_prev = u;
+      cp = ga[k];
+    }
+  }
+  // z = T0^{-1} u, u = (-1, 0, ..., 0, γ_{n-1}): forward then backward scans
+  double wl[BM] = {};
+  Aff A{1.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      const int j = j0 + k;
+      const double uj = (j == 0) ? -1.0 : ((j == n - 1) ? gl : 0.0);
+      A.e = ul[k] * uj - fl[k] * A.e;
+      A.P *= -fl[k];
+      wl[k] = A.e;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const Aff o{__shfl_up(A.P, d, 64), __shfl_up(A.e, d, 64)};
+    if (lane >= d) A = compose(A, o);
+  }
+  double Win = __shfl_up(A.e, 1, 64);
+  if (lane == 0) Win = 0.0;
+  double P = 1.0;
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      P *= -fl[k];
+      wl[k] += P * Win;
+    }
+  }
+  Aff Bk{1.0, 0.0};
+#pragma unroll
+  for (int k = BM - 1; k >= 0; --k) {
+    if (k < cnt) {
+      Bk.e = wl[k] - gf[k] * Bk.e;
+      Bk.P *= -gf[k];
+      wl[k] = Bk.e;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const Aff o{__shfl_down(Bk.P, d, 64), __shfl_down(Bk.e, d, 64)};
+    if (lane + d < 64) Bk = compose(Bk, o);
+  }
+  double Xin = __shfl_down(Bk.e, 1, 64);
+  if (lane == 63) Xin = 0.0;
+  double Q = 1.0, zlast = 0.0;
+#pragma unroll
+  for (int k = BM - 1; k >= 0; --k) {
+    if (k < cnt) {
+      Q *= -gf[k];
+      wl[k] += Q * Xin;
+      zz[row + j0 + k] = wl[k];
+      if (j0 + k == n - 1) zlast = wl[k];
+      if (I.mixed) {
+        G(I.k32.af_f)[row + j0 + k] = (float)fl[k];
+        G(I.k32.af_g)[row + j0 + k] = (float)gf[k];
+        G(I.k32.af_z)[row + j0 + k] = (float)wl[k];
+      }
+    }
+  }
+  const double z0 = __shfl(wl[0], 0, 64);
+  const double zl = __shfl(zlast, (n - 1) / B, 64);
+  if (lane == 0) {
+    G(I.af_kappa)[i - 1] = 1.0 / (1.0 + z0 - a0 * zl);
+    G(I.af_alpha0)[i - 1] = a0;
   }
 }
 
@@ -344,67 +528,124 @@ __global__ void k_fact_ang(const PdInst *insts, const int2 *map) {
 //
 // One wave owns 64 consecutive θ-columns and PD_RB consecutive rings and
 // marches outward in r, keeping the radial neighbours and the shared radial
-// faces in registers; the θ-neighbours come from the adjacent lanes by
-// cross-lane permutes, and only the two wave-edge columns (including the
-// periodic seam j = n-1 <-> 0) are fetched from memory.  The origin row is a
-// sum over ring 1 accumulated per block and closed by the instance's last
-// block.
+// faces in registers and fetching the next ring while it computes the
+// current one.  The θ-neighbours come from the adjacent lanes by cross-lane
+// permutes; the columns just outside the wave (including the periodic seam
+// j = n-1 <-> 0) are fetched for all of the tile's rings at once and handed
+// out row by row.  The origin row is a sum over ring 1, accumulated per
+// block and closed by the instance's last block.
+
+struct TileGeo {
+  int m, n, lane, j, jc, i0, i1, jl0, jr0;
+  bool act, need_l, need_r;
+};
+
+__device__ __forceinline__ TileGeo tile_geo(int m, int n, int cg, int rg) {
+  TileGeo g;
+  g.m = m;
+  g.n = n;
+  g.lane = threadIdx.x & 63;
+  g.j = cg * 64 + g.lane;
+  g.act = g.j < n;
+  g.jc = g.act ? g.j : n - 1;
+  const int jfirst = cg * 64, jlast = min(cg * 64 + 63, n - 1);
+  g.jl0 = (jfirst == 0) ? n - 1 : jfirst - 1;
+  g.jr0 = (jlast == n - 1) ? 0 : jlast + 1;
+  g.need_l = g.lane == 0;
+  g.need_r = g.j == jlast;
+  g.i0 = rg * PD_RB + 1;
+  g.i1 = min(g.i0 + PD_RB - 1, m);
+  return g;
+}
 
 template <typename TF, typename TX, int NV, class Epi>
-__device__ __forceinline__ void sten_tile(const PdInst &I, const TF *gp_r, const TF *gm_r,
-                                          const TF *gp_t, const TF *gm_t, const TX *const (&X)[NV],
-                                          int cg, int rg, double (&S0)[NV], Epi &&epi) {
-  const int m = I.m, n = I.n, lane = threadIdx.x & 63;
-  const int j = cg * 64 + lane;
-  const bool act = j < n;
-  const int jc = act ? j : n - 1;
-  const int jl = (jc == 0) ? n - 1 : jc - 1;
-  const int jr = (jc == n - 1) ? 0 : jc + 1;
-  const bool need_l = (lane == 0);
-  const bool need_r = (lane == 63) || (j + 1 >= n);
-  const int i0 = rg * PD_RB + 1;
-  const int i1 = min(i0 + PD_RB - 1, m);
-  const double idth = I.inv_dth[jc];
+__device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__restrict__ gp_r,
+                                          const GAS TF *__restrict__ gm_r,
+                                          const GAS TF *__restrict__ gp_t,
+                                          const GAS TF *__restrict__ gm_t,
+                                          const GAS TX *__restrict__ X0,
+                                          const GAS TX *__restrict__ X1,
+                                          const GAS double *__restrict__ inv_rw,
+                                          const GAS double *__restrict__ inv_dth,
+                                          const GAS double *__restrict__ bnode, double (&S0)[NV],
+                                          Epi &&epi) {
+  const int m = g.m, n = g.n, jc = g.jc;
+  const int i0 = g.i0, i1 = g.i1, nr = i1 - i0 + 1;
   const int orig = m * n;
-
-  double xb[NV], xc[NV];
+  const GAS TX *X[2] = {X0, X1};
+  const double idth = inv_dth[jc];
+  // wave-edge columns for every row of the tile
+  const int hr = (g.lane < nr) ? (i0 - 1 + g.lane) * n : (i0 - 1) * n;
+  double hxl[NV], hxr[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    xb[v] = (i0 == 1) ? ld(X[v], orig) : ld(X[v], (i0 - 2) * n + jc);
-    xc[v] = ld(X[v], (i0 - 1) * n + jc);
+    hxl[v] = (double)X[v][hr + g.jl0];
+    hxr[v] = (double)X[v][hr + g.jr0];
   }
-  double gpi = ld(gp_r, (i0 - 1) * n + jc), gmi = ld(gm_r, (i0 - 1) * n + jc);
+  const double hgpl = (double)gp_t[hr + g.jl0], hgml = (double)gm_t[hr + g.jl0];
+
+  double xb[NV], xc[NV], xa[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    xb[v] = (i0 == 1) ? (double)X[v][orig] : (double)X[v][(i0 - 2) * n + jc];
+    xc[v] = (double)X[v][(i0 - 1) * n + jc];
+    xa[v] = (i0 < m) ? (double)X[v][i0 * n + jc] : 0.0;
+  }
+  double gpi = (double)gp_r[(i0 - 1) * n + jc], gmi = (double)gm_r[(i0 - 1) * n + jc];
+  double gpo = (double)gp_r[i0 * n + jc], gmo = (double)gm_r[i0 * n + jc];
+  double gpt = (double)gp_t[(i0 - 1) * n + jc], gmt = (double)gm_t[(i0 - 1) * n + jc];
+  double bP = bnode ? bnode[(i0 - 1) * n + jc] : 0.0;
+  double ivr = inv_rw[i0];
   for (int i = i0; i <= i1; ++i) {
-    const int row = (i - 1) * n;
-    const double gpo = ld(gp_r, i * n + jc), gmo = ld(gm_r, i * n + jc);
-    const double gpt = ld(gp_t, row + jc), gmt = ld(gm_t, row + jc);
-    double gptl = __shfl_up(gpt, 1, 64), gmtl = __shfl_up(gmt, 1, 64);
-    if (need_l) {
-      gptl = ld(gp_t, row + jl);
-      gmtl = ld(gm_t, row + jl);
+    // prefetch ring i+1
+    double nxa[NV], ngpo = 0.0, ngmo = 0.0, ngpt = 0.0, ngmt = 0.0, nb = 0.0, nivr = 0.0;
+    const bool more = i < i1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) nxa[v] = (more && i + 1 < m) ? (double)X[v][(i + 1) * n + jc] : 0.0;
+    if (more) {
+      ngpo = (double)gp_r[(i + 1) * n + jc];
+      ngmo = (double)gm_r[(i + 1) * n + jc];
+      ngpt = (double)gp_t[i * n + jc];
+      ngmt = (double)gm_t[i * n + jc];
+      nb = bnode ? bnode[i * n + jc] : 0.0;
+      nivr = inv_rw[i + 1];
     }
-    const double ivV = I.inv_rw[i] * idth;
-    const double bP = I.has_b ? I.b_node[row + jc] : 0.0;
-    double Lx[NV], xa[NV];
+    const int row = (i - 1) * n;
+    const int hi = i - i0;
+    double gptl = __shfl_up(gpt, 1, 64), gmtl = __shfl_up(gmt, 1, 64);
+    const double hgp = __shfl(hgpl, hi, 64), hgm = __shfl(hgml, hi, 64);
+    if (g.need_l) {
+      gptl = hgp;
+      gmtl = hgm;
+    }
+    const double ivV = ivr * idth;
+    double Lx[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      xa[v] = (i < m) ? ld(X[v], i * n + jc) : 0.0;
       double xl = __shfl_up(xc[v], 1, 64), xr = __shfl_down(xc[v], 1, 64);
-      if (need_l) xl = ld(X[v], row + jl);
-      if (need_r) xr = ld(X[v], row + jr);
+      const double hl = __shfl(hxl[v], hi, 64), hrr = __shfl(hxr[v], hi, 64);
+      if (g.need_l) xl = hl;
+      if (g.need_r) xr = hrr;
       const double fs = gpo * xc[v] - gmo * xa[v] + gmi * xc[v] - gpi * xb[v] + gpt * xc[v] -
                         gmt * xr + gmtl * xc[v] - gptl * xl;
       Lx[v] = ivV * fs + bP * xc[v];
-      if (i == 1 && act) S0[v] += gpi * xb[v] - gmi * xc[v];
+      if (i == 1 && g.act) S0[v] += gpi * xb[v] - gmi * xc[v];
     }
-    if (act) epi(i, jc, row + jc, xc, Lx);
+    if (g.act) epi(i, jc, row + jc, xc, Lx);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       xb[v] = xc[v];
       xc[v] = xa[v];
+      xa[v] = nxa[v];
     }
     gpi = gpo;
     gmi = gmo;
+    gpo = ngpo;
+    gmo = ngmo;
+    gpt = ngpt;
+    gmt = ngmt;
+    bP = nb;
+    ivr = nivr;
   }
 }
 
@@ -413,10 +654,10 @@ enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4 };
 // Stencil kernels.  TK: storage type of the Krylov set the mode works on.
 //  SM_APPLY: y = x/dt + θ L x (diagnostic; dt, θ, x, y passed explicitly)
 //  SM_BEGIN: b = x^k/dt - (1-θ) L x^k + Σ_q c_q g_q + boundary;
-//            x0 = x^k + ρ (x^k - x^{k-1});  r = b - A x0;  r̂ = r
-//  SM_V:     v = A p̂,  partial r̂·v
-//  SM_T:     t = A ŝ,  partials t·s, t·t
-//  SM_UR:    (mixed) r ← r - A d in FP64, x ← x + d; r32 = r̂32 = r
+//            x0 = x^k + ρ (x^k - x^{k-1});  r = D^{-1}(b - A x0);  r̂ = r
+//  SM_V:     v = D^{-1} A p̂,  partial r̂·v
+//  SM_T:     t = D^{-1} A ŝ,  partials t·s, t·t
+//  SM_UR:    (mixed) r ← r - A d in FP64, x ← x + d; r32 = r̂32 = D^{-1} r
 template <typename TK, int MODE>
 __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *map, double a_dt,
                                               double a_th, const TK *ax, TK *ay) {
@@ -436,20 +677,24 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
   const int cg = wave_on ? tile % I.ncg : 0, rg = wave_on ? tile / I.ncg : 0;
   const int m = I.m, n = I.n, orig = m * n;
   const KSet<TK> &KS = kset<TK>(I);
+  const TileGeo geo = tile_geo(m, n, cg, rg);
+  const GAS double *inv_rw = G(I.inv_rw), *inv_dth = G(I.inv_dth);
+  const GAS double *bnode = I.has_b ? G(I.b_node) : nullptr;
 
   if (MODE == SM_APPLY) {
     const double inv_dt = 1.0 / a_dt, th = a_th;
     double S0[1] = {0.0};
-    const TK *X[1] = {ax};
+    GAS TK *y = G(ay);
     if (wave_on)
-      sten_tile<TK, TK, 1>(I, KS.gp_r, KS.gm_r, KS.gp_t, KS.gm_t, X, cg, rg, S0,
+      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(ax), G(ax), inv_rw,
+                           inv_dth, bnode, S0,
                            [&](int, int, int idx, const double *xc, const double *Lx) {
-                             ay[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
+                             y[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
                            });
     double tot[1];
     if (block_commit<1>(S0, I.partials, I.nb_sten, mp.y, I.counters + CNT_APPLY, tot) &&
         threadIdx.x == 0) {
-      const double x0 = ld(ax, orig);
+      const double x0 = (double)ax[orig];
       const double bo = I.has_b ? I.b_node[orig] : 0.0;
       ay[orig] = (TK)(inv_dt * x0 + th * (I.inv_V0 * tot[0] + bo * x0));
     }
@@ -462,35 +707,40 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     const bool ex = rho != 0.0;
     double cq[PD_MAXSRC];
     for (int s = 0; s < PD_MAXSRC; ++s) cq[s] = sc->cq[s];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // ||b||^2, ||r||^2, S0(x^k), S0(x^{k-1})
+    const int nsrc = I.nsrc, npad = I.npad;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // ||D^-1 b||^2, ||D^-1 r||^2, S0(x^k), S0(x^{k-1})
     double S0[2] = {0.0, 0.0};
-    const double *X[2] = {xk, ex ? xkm : xk};
-    const double *gpr = I.k64.gp_r, *gmr = I.k64.gm_r;
+    const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb), *idg = G(I.inv_diag);
+    GAS double *bv = G(I.bvec), *xo = G(x0);
+    GAS double *rout = G(I.rout);
+    GAS double *r64 = G(I.k64.r), *rh64 = G(I.k64.rh);
+    GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh);
+    const bool mixed = I.mixed;
     if (wave_on)
       sten_tile<double, double, 2>(
-          I, gpr, gmr, I.k64.gp_t, I.k64.gm_t, X, cg, rg, S0,
-          [&](int i, int j, int idx, const double *xc, const double *Lx) {
+          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk), G(ex ? xkm : xk),
+          inv_rw, inv_dth, bnode, S0, [&](int i, int j, int idx, const double *xc, const double *Lx) {
             double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
-            for (int s = 0; s < I.nsrc; ++s) b += cq[s] * I.g[s * I.npad + idx];
+            for (int s = 0; s < nsrc; ++s) b += cq[s] * gsrc[s * npad + idx];
             if (i == m) {
               double Nm = 0.0;
-              for (int s = 0; s < I.nsrc; ++s) Nm += cq[s] * I.nb[s * n + j];
-              b += I.inv_rw[i] * I.inv_dth[j] * gmr[m * n + j] * Nm;
+              for (int s = 0; s < nsrc; ++s) Nm += cq[s] * nbv[s * n + j];
+              b += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
             }
             const double xg = ex ? xc[0] + rho * (xc[0] - xc[1]) : xc[0];
             const double Lg = ex ? Lx[0] + rho * (Lx[0] - Lx[1]) : Lx[0];
             const double r = b - (inv_dt * xg + th * Lg);
-            const double idg = I.inv_diag[idx];
-            const double rs = r * idg, bs = b * idg;
-            I.bvec[idx] = b;
-            x0[idx] = xg;
-            if (I.mixed) {
-              I.rout[idx] = r;
-              I.k32.r[idx] = (float)rs;
-              I.k32.rh[idx] = (float)rs;
+            const double id = idg[idx];
+            const double rs = r * id, bs = b * id;
+            bv[idx] = b;
+            xo[idx] = xg;
+            if (mixed) {
+              rout[idx] = r;
+              r32[idx] = (float)rs;
+              rh32[idx] = (float)rs;
             } else {
-              I.k64.r[idx] = rs;
-              I.k64.rh[idx] = rs;
+              r64[idx] = rs;
+              rh64[idx] = rs;
             }
             acc[0] += bs * bs;
             acc[1] += rs * rs;
@@ -505,15 +755,15 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       const double L0 = I.inv_V0 * tot[2] + bo * xk0;
       const double L1 = I.inv_V0 * tot[3] + bo * xkm0;
       double b = inv_dt * xk0 - (1.0 - th) * L0;
-      for (int s = 0; s < I.nsrc; ++s) b += cq[s] * I.g[s * I.npad + orig];
+      for (int s = 0; s < nsrc; ++s) b += cq[s] * I.g[s * npad + orig];
       const double xg = ex ? xk0 + rho * (xk0 - xkm0) : xk0;
       const double Lg = ex ? L0 + rho * (L0 - L1) : L0;
       const double r = b - (inv_dt * xg + th * Lg);
-      const double idg = I.inv_diag[orig];
-      const double rs = r * idg, bs = b * idg;
+      const double id = I.inv_diag[orig];
+      const double rs = r * id, bs = b * id;
       I.bvec[orig] = b;
       x0[orig] = xg;
-      if (I.mixed) {
+      if (mixed) {
         I.rout[orig] = r;
         I.k32.r[orig] = (float)rs;
         I.k32.rh[orig] = (float)rs;
@@ -538,17 +788,20 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     const TK *xin = (MODE == SM_V) ? KS.ph : KS.sh;
     TK *yout = (MODE == SM_V) ? KS.v : KS.t;
     const TK *other = (MODE == SM_V) ? KS.rh : KS.s;
+    GAS TK *yo = G(yout);
+    const GAS TK *ot = G(other);
+    const GAS TK *idg = G(KS.inv_d);
     double acc[3] = {0.0, 0.0, 0.0};
     double S0[1] = {0.0};
-    const TK *X[1] = {xin};
     if (wave_on)
-      sten_tile<TK, TK, 1>(I, KS.gp_r, KS.gm_r, KS.gp_t, KS.gm_t, X, cg, rg, S0,
+      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(xin), G(xin),
+                           inv_rw, inv_dth, bnode, S0,
                            [&](int, int, int idx, const double *xc, const double *Lx) {
-                             const double y = (inv_dt * xc[0] + th * Lx[0]) * ld(KS.inv_d, idx);
+                             const double y = (inv_dt * xc[0] + th * Lx[0]) * (double)idg[idx];
                              const TK ys = (TK)y;
-                             yout[idx] = ys;
+                             yo[idx] = ys;
                              const double yd = (double)ys;
-                             acc[0] += ld(other, idx) * yd;
+                             acc[0] += (double)ot[idx] * yd;
                              acc[1] += yd * yd;
                            });
     acc[2] = S0[0];
@@ -557,12 +810,12 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                         I.counters + (MODE == SM_V ? CNT_V : CNT_T), tot) &&
         threadIdx.x == 0) {
       const double bo = I.has_b ? I.b_node[orig] : 0.0;
-      const double x0 = ld(xin, orig);
-      const double y0 = (inv_dt * x0 + th * (I.inv_V0 * tot[2] + bo * x0)) * ld(KS.inv_d, orig);
+      const double x0 = (double)xin[orig];
+      const double y0 = (inv_dt * x0 + th * (I.inv_V0 * tot[2] + bo * x0)) * (double)KS.inv_d[orig];
       const TK ys = (TK)y0;
       yout[orig] = ys;
       const double yd = (double)ys;
-      const double dot = tot[0] + ld(other, orig) * yd;
+      const double dot = tot[0] + (double)other[orig] * yd;
       const double yy = tot[1] + yd * yd;
       if (MODE == SM_V) {
         // α = ρ / (r̂·v)
@@ -591,18 +844,22 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     // FP64 operator applied to the FP32 correction d
     const double inv_dt = sc->inv_dt, th = sc->theta;
     double *x = I.sol[(sc->rot + 2) % 3];
+    GAS double *xg = G(x), *rout = G(I.rout);
+    const GAS double *idg = G(I.inv_diag);
+    GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh);
     double acc[2] = {0.0, 0.0};
     double S0[1] = {0.0};
-    const float *X[1] = {I.k32.d};
     if (wave_on)
-      sten_tile<double, float, 1>(I, I.k64.gp_r, I.k64.gm_r, I.k64.gp_t, I.k64.gm_t, X, cg, rg, S0,
+      sten_tile<double, float, 1>(geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t),
+                                  G((const float *)I.k32.d), G((const float *)I.k32.d), inv_rw,
+                                  inv_dth, bnode, S0,
                                   [&](int, int, int idx, const double *xc, const double *Lx) {
-                                    const double r = I.rout[idx] - (inv_dt * xc[0] + th * Lx[0]);
-                                    const double rs = r * I.inv_diag[idx];
-                                    I.rout[idx] = r;
-                                    x[idx] += xc[0];
-                                    I.k32.r[idx] = (float)rs;
-                                    I.k32.rh[idx] = (float)rs;
+                                    const double r = rout[idx] - (inv_dt * xc[0] + th * Lx[0]);
+                                    const double rs = r * idg[idx];
+                                    rout[idx] = r;
+                                    xg[idx] += xc[0];
+                                    r32[idx] = (float)rs;
+                                    rh32[idx] = (float)rs;
                                     acc[0] += rs * rs;
                                   });
     acc[1] = S0[0];
@@ -642,14 +899,14 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
 
 // ------------------------------------------------------------ radial sweep
 //
-// w = (D + R)^{-1} y for every θ-column of an instance.  A block owns cw
+// w = (I + D^{-1}R)^{-1} y for every θ-column of an instance.  A block owns cw
 // consecutive columns; its 1024 threads split every column into nseg
 // segments of brad rows (lane = column within the block, segment = the rest
 // of the thread index).  Each thread runs the forward and backward
 // substitution of its segment locally, holding the segment in registers;
-// the segments are then joined by composing their affine maps
-// w -> P w + e across segments through LDS (a segmented scan), and each
-// thread corrects its rows.  The origin is scaled by its diagonal.
+// the segments are then joined by composing their affine maps across
+// segments through LDS, and each thread corrects its rows.  The origin row
+// passes through (unit diagonal).
 //
 // RM_P:  y = p = r + β (p - ω v)   (p = r on a (re)start; r̂ = r on a restart)
 // RM_S:  y = s = r - α v
@@ -657,7 +914,106 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
 
 enum { RM_P = 0, RM_S = 1, RM_PLAIN = 2 };
 
-template <typename T, int MODE>
+template <typename T, int MODE, int BM>
+__device__ __forceinline__ void rad_body(int m, int n, int cw, int B, int nseg, int j, int c, int seg,
+                                         int cnt, bool origin_thread, double beta, double omega,
+                                         double alpha, bool first, bool reset,
+                                         const GAS T *__restrict__ r, GAS T *__restrict__ p,
+                                         const GAS T *__restrict__ v, GAS T *__restrict__ rh,
+                                         GAS T *__restrict__ s, const GAS T *__restrict__ pin,
+                                         GAS T *__restrict__ out,
+                                         const GAS double *__restrict__ uinv,
+                                         const GAS T *__restrict__ f, const GAS T *__restrict__ g) {
+  __shared__ double lds_a[PD_RAD_THREADS];
+  __shared__ double lds_b[PD_RAD_THREADS];
+  const int i_begin = seg * B;
+
+  // the sweep's right-hand side at idx; `own` says the row belongs to this
+  // thread (loads are clamped and always issued, stores only for own rows)
+  auto input = [&](int idx, bool own) -> double {
+    if (MODE == RM_P) {
+      const double rr = (double)r[idx];
+      const double pv = (double)p[idx], vv = (double)v[idx];
+      const double pp = first ? rr : rr + beta * (pv - omega * vv);
+      const T ps = (T)pp;
+      if (own) {
+        p[idx] = ps;
+        if (reset) rh[idx] = (T)rr;
+      }
+      return (double)ps;
+    } else if (MODE == RM_S) {
+      const double ss = (double)r[idx] - alpha * (double)v[idx];
+      const T sv = (T)ss;
+      if (own) s[idx] = sv;
+      return (double)sv;
+    } else {
+      return (double)pin[idx];
+    }
+  };
+
+  if (origin_thread) out[m * n] = (T)input(m * n, true);
+
+  // forward local pass: loads first (clamped rows, masked), then the recurrence
+  double wl[BM] = {}, fl[BM] = {};
+  // threads without rows (segment past row m, column past n) read row 0
+  const int klast = cnt > 0 ? cnt - 1 : 0;
+  const int rb = cnt > 0 ? i_begin : 0;
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    const int idx = (rb + min(k, klast)) * n + j;
+    const double y = input(idx, k < cnt);
+    wl[k] = k < cnt ? uinv[idx] * y : 0.0;
+    fl[k] = k < cnt ? (double)f[idx] : 0.0;
+  }
+  Aff A{1.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      A.e = wl[k] - fl[k] * A.e;
+      A.P *= -fl[k];
+      wl[k] = A.e;
+    }
+  }
+  lds_a[threadIdx.x] = A.e;
+  lds_b[threadIdx.x] = A.P;
+  __syncthreads();
+  double Win = 0.0;
+  for (int s2 = 0; s2 < seg; ++s2) Win = lds_b[s2 * cw + c] * Win + lds_a[s2 * cw + c];
+  __syncthreads();
+  // fix-up of the forward pass, then the local backward pass
+  double P = 1.0;
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    P *= -fl[k];
+    wl[k] += P * Win;
+    const double gv = (double)g[(rb + min(k, klast)) * n + j];
+    fl[k] = k < cnt ? gv : 0.0;                    // reuse the registers for g
+  }
+  Aff Bk{1.0, 0.0};
+#pragma unroll
+  for (int k = BM - 1; k >= 0; --k) {
+    if (k < cnt) {
+      Bk.e = wl[k] - fl[k] * Bk.e;
+      Bk.P *= -fl[k];
+      wl[k] = Bk.e;
+    }
+  }
+  lds_a[threadIdx.x] = Bk.e;
+  lds_b[threadIdx.x] = Bk.P;
+  __syncthreads();
+  double Xin = 0.0;
+  for (int s2 = nseg - 1; s2 > seg; --s2) Xin = lds_b[s2 * cw + c] * Xin + lds_a[s2 * cw + c];
+  double Q = 1.0;
+#pragma unroll
+  for (int k = BM - 1; k >= 0; --k) {
+    if (k < cnt) {
+      Q *= -fl[k];
+      out[(i_begin + k) * n + j] = (T)(wl[k] + Q * Xin);
+    }
+  }
+}
+
+template <typename T, int MODE, int BM>
 __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, const int2 *map,
                                                         const T *plain_in, T *plain_out) {
   const int2 mp = map[blockIdx.x];
@@ -669,12 +1025,7 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
   const int c = threadIdx.x % cw, seg = threadIdx.x / cw;
   const int j = mp.y * cw + c;
   const bool act = j < n;
-  const int i_begin = seg * B;                       // 0-based row
-  const int cnt = act ? max(0, min(B, m - i_begin)) : 0;
-
-  __shared__ double lds_a[PD_RAD_THREADS];
-  __shared__ double lds_b[PD_RAD_THREADS];
-
+  const int cnt = act ? max(0, min(B, m - seg * B)) : 0;
   double beta = 0.0, omega = 0.0, alpha = 0.0;
   bool first = false, reset = false;
   if (MODE == RM_P) {
@@ -686,85 +1037,10 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
     alpha = sc->alpha;
   }
   T *out = (MODE == RM_PLAIN) ? plain_out : KS.w;
-
-  auto input = [&](int idx) -> double {
-    if (MODE == RM_P) {
-      const double r = ld(KS.r, idx);
-      double p = first ? r : r + beta * (ld(KS.p, idx) - omega * ld(KS.v, idx));
-      const T ps = (T)p;
-      KS.p[idx] = ps;
-      if (reset) KS.rh[idx] = (T)r;
-      return (double)ps;
-    } else if (MODE == RM_S) {
-      const double s = ld(KS.r, idx) - alpha * ld(KS.v, idx);
-      const T ss = (T)s;
-      KS.s[idx] = ss;
-      return (double)ss;
-    } else {
-      return ld(plain_in, idx);
-    }
-  };
-
-  // origin (one thread of the instance's first block): unit diagonal
-  if (mp.y == 0 && threadIdx.x == 0) {
-    const int o = m * n;
-    out[o] = (T)input(o);
-  }
-
-  // forward local pass
-  double wl[PD_RAD_BMAX] = {};
-  double W = 0.0, P = 1.0;
-#pragma unroll
-  for (int k = 0; k < PD_RAD_BMAX; ++k) {
-    if (k < cnt) {
-      const int idx = (i_begin + k) * n + j;
-      const double y = input(idx);
-      const double f = ld(KS.rf_f, idx);
-      W = I.rf_uinv[idx] * y - f * W;
-      P *= -f;
-      wl[k] = W;
-    }
-  }
-  lds_a[threadIdx.x] = W;
-  lds_b[threadIdx.x] = P;
-  __syncthreads();
-  double Win = 0.0;
-  for (int s2 = 0; s2 < seg; ++s2) Win = lds_b[s2 * cw + c] * Win + lds_a[s2 * cw + c];
-  __syncthreads();
-  // fix-up of the forward pass, then local backward pass
-  P = 1.0;
-#pragma unroll
-  for (int k = 0; k < PD_RAD_BMAX; ++k) {
-    if (k < cnt) {
-      P *= -ld(KS.rf_f, (i_begin + k) * n + j);
-      wl[k] += P * Win;
-    }
-  }
-  double X = 0.0, Q = 1.0;
-#pragma unroll
-  for (int k = PD_RAD_BMAX - 1; k >= 0; --k) {
-    if (k < cnt) {
-      const double g = ld(KS.rf_g, (i_begin + k) * n + j);
-      X = wl[k] - g * X;
-      Q *= -g;
-      wl[k] = X;
-    }
-  }
-  lds_a[threadIdx.x] = X;
-  lds_b[threadIdx.x] = Q;
-  __syncthreads();
-  const int nseg = I.nseg;
-  double Xin = 0.0;
-  for (int s2 = nseg - 1; s2 > seg; --s2) Xin = lds_b[s2 * cw + c] * Xin + lds_a[s2 * cw + c];
-  Q = 1.0;
-#pragma unroll
-  for (int k = PD_RAD_BMAX - 1; k >= 0; --k) {
-    if (k < cnt) {
-      const int idx = (i_begin + k) * n + j;
-      Q *= -ld(KS.rf_g, idx);
-      out[idx] = (T)(wl[k] + Q * Xin);
-    }
-  }
+  rad_body<T, MODE, BM>(m, n, cw, B, I.nseg, act ? j : 0, c, seg, cnt, mp.y == 0 && threadIdx.x == 0,
+                    beta, omega, alpha, first, reset, G((const T *)KS.r), G(KS.p),
+                    G((const T *)KS.v), G(KS.rh), G(KS.s), G(plain_in), G(out), G(I.rf_uinv),
+                    G((const T *)KS.rf_f), G((const T *)KS.rf_g));
 }
 
 // ------------------------------------------------------------ angular sweep
@@ -778,98 +1054,107 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
 // AM_P: input w, output p̂ (origin copied);  AM_S: output ŝ;  AM_PLAIN: diagnostic.
 enum { AM_P = 0, AM_S = 1, AM_PLAIN = 2 };
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *map,
-                                             const T *plain_in, T *plain_out) {
-  const int2 mp = map[blockIdx.x];
-  const PdInst &I = insts[mp.x];
-  const PdScalars *sc = I.sc;
-  if (MODE != AM_PLAIN && (!inner_active(sc) || !prec_match<T>(I))) return;
-  const KSet<T> &KS = kset<T>(I);
-  const int m = I.m, n = I.n, B = I.bang;
-  const int lane = threadIdx.x & 63;
-  const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
-  if (i > m) return;                                 // whole wave exits together
-  const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
-  T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
+template <typename T, int BM>
+__device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, double kappa,
+                                         double alpha0, const GAS T *__restrict__ in,
+                                         GAS T *__restrict__ out,
+                                         const GAS double *__restrict__ uinv,
+                                         const GAS T *__restrict__ f, const GAS T *__restrict__ g,
+                                         const GAS T *__restrict__ z) {
   const int row = (i - 1) * n;
   const int j0 = lane * B;
   const int cnt = max(0, min(B, n - j0));
-
   if (i == 1 && lane == 0) out[m * n] = in[m * n];
 
-  double wl[PD_ANG_BMAX] = {};
-  double W = 0.0, P = 1.0;
+  double wl[BM] = {}, fl[BM] = {};
+  const int klast = cnt > 0 ? cnt - 1 : 0;
+  const int jb = cnt > 0 ? j0 : 0;
 #pragma unroll
-  for (int k = 0; k < PD_ANG_BMAX; ++k) {
+  for (int k = 0; k < BM; ++k) {
+    const int idx = row + jb + min(k, klast);
+    const double wv = uinv[idx] * (double)in[idx], fv = (double)f[idx];
+    wl[k] = k < cnt ? wv : 0.0;
+    fl[k] = k < cnt ? fv : 0.0;
+  }
+  Aff A{1.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
     if (k < cnt) {
-      const int idx = row + j0 + k;
-      const double f = ld(KS.af_f, idx);
-      W = I.af_uinv[idx] * ld(in, idx) - f * W;
-      P *= -f;
-      wl[k] = W;
+      A.e = wl[k] - fl[k] * A.e;
+      A.P *= -fl[k];
+      wl[k] = A.e;
     }
   }
-  // inclusive prefix composition of (P, W) over lanes
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const double Pp = __shfl_up(P, d, 64), Wp = __shfl_up(W, d, 64);
-    if (lane >= d) {
-      W = P * Wp + W;
-      P = P * Pp;
-    }
+    const Aff o{__shfl_up(A.P, d, 64), __shfl_up(A.e, d, 64)};
+    if (lane >= d) A = compose(A, o);
   }
-  double Win = __shfl_up(W, 1, 64);
+  double Win = __shfl_up(A.e, 1, 64);
   if (lane == 0) Win = 0.0;
-  P = 1.0;
+  double P = 1.0;
+  double zl[BM] = {};
 #pragma unroll
-  for (int k = 0; k < PD_ANG_BMAX; ++k) {
-    if (k < cnt) {
-      P *= -ld(KS.af_f, row + j0 + k);
-      wl[k] += P * Win;
-    }
+  for (int k = 0; k < BM; ++k) {
+    P *= -fl[k];
+    wl[k] += P * Win;
+    const int idx = row + jb + min(k, klast);
+    const double gv = (double)g[idx], zv = (double)z[idx];
+    fl[k] = k < cnt ? gv : 0.0;
+    zl[k] = k < cnt ? zv : 0.0;
   }
-  double X = 0.0, Q = 1.0;
+  Aff Bk{1.0, 0.0};
 #pragma unroll
-  for (int k = PD_ANG_BMAX - 1; k >= 0; --k) {
+  for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      const double g = ld(KS.af_g, row + j0 + k);
-      X = wl[k] - g * X;
-      Q *= -g;
-      wl[k] = X;
+      Bk.e = wl[k] - fl[k] * Bk.e;
+      Bk.P *= -fl[k];
+      wl[k] = Bk.e;
     }
   }
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const double Qn = __shfl_down(Q, d, 64), Xn = __shfl_down(X, d, 64);
-    if (lane + d < 64) {
-      X = Q * Xn + X;
-      Q = Q * Qn;
-    }
+    const Aff o{__shfl_down(Bk.P, d, 64), __shfl_down(Bk.e, d, 64)};
+    if (lane + d < 64) Bk = compose(Bk, o);
   }
-  double Xin = __shfl_down(X, 1, 64);
+  double Xin = __shfl_down(Bk.e, 1, 64);
   if (lane == 63) Xin = 0.0;
-  Q = 1.0;
-  double ylast = 0.0;
+  double Q = 1.0, ylast = 0.0;
 #pragma unroll
-  for (int k = PD_ANG_BMAX - 1; k >= 0; --k) {
+  for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      Q *= -ld(KS.af_g, row + j0 + k);
+      Q *= -fl[k];
       wl[k] += Q * Xin;
       if (j0 + k == n - 1) ylast = wl[k];
     }
   }
-  const int llast = (n - 1) / B;
   const double y0 = __shfl(wl[0], 0, 64);
-  const double yl = __shfl(ylast, llast, 64);
-  const double sfac = I.af_kappa[i - 1] * (y0 - I.af_alpha0[i - 1] * yl);
+  const double yl = __shfl(ylast, (n - 1) / B, 64);
+  const double sfac = kappa * (y0 - alpha0 * yl);
 #pragma unroll
-  for (int k = 0; k < PD_ANG_BMAX; ++k) {
-    if (k < cnt) {
-      const int idx = row + j0 + k;
-      out[idx] = (T)(wl[k] - sfac * ld(KS.af_z, idx));
-    }
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) out[row + j0 + k] = (T)(wl[k] - sfac * zl[k]);
   }
+}
+
+template <typename T, int MODE, int BM>
+__global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *map,
+                                             const T *plain_in, T *plain_out) {
+  const int2 mp = map[blockIdx.x];
+  const PdInst &I = insts[mp.x];
+  PdScalars *sc = I.sc;
+  if (MODE != AM_PLAIN && (!inner_active(sc) || !prec_match<T>(I))) return;
+  const KSet<T> &KS = kset<T>(I);
+  const int m = I.m, n = I.n;
+  const int lane = threadIdx.x & 63;
+  const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
+  // the restart flag was consumed by the radial sweep that ran before
+  if (MODE == AM_P && mp.y == 0 && threadIdx.x == 0) sc->reset_rh = 0;
+  if (i > m) return;                                 // whole wave exits together
+  const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
+  T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
+  ang_body<T, BM>(m, n, I.bang, i, lane, I.af_kappa[i - 1], I.af_alpha0[i - 1], G(in), G(out),
+              G(I.af_uinv), G((const T *)KS.af_f), G((const T *)KS.af_g), G((const T *)KS.af_z));
 }
 
 // ------------------------------------------------------------ update kernel
@@ -879,6 +1164,42 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
 // breakdown or restart for the instance.
 
 template <typename T>
+__device__ __forceinline__ void elem_body(int N, int base, double al, double om, bool setx,
+                                          const GAS T *__restrict__ ph, const GAS T *__restrict__ sh,
+                                          const GAS T *__restrict__ s, const GAS T *__restrict__ t,
+                                          const GAS T *__restrict__ rh, GAS T *__restrict__ x,
+                                          GAS T *__restrict__ r, double (&acc)[2]) {
+  constexpr int E = PD_ELEM_PER_BLOCK / 256;
+  double vph[E], vsh[E], vs[E], vt[E], vrh[E], vx[E];
+  // clamped indices: every load is issued unconditionally, tails masked
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int idx = base + k * 256 + threadIdx.x;
+    const int li = idx < N ? idx : N - 1;
+    vph[k] = (double)ph[li];
+    vsh[k] = (double)sh[li];
+    vs[k] = (double)s[li];
+    vt[k] = (double)t[li];
+    vrh[k] = (double)rh[li];
+    vx[k] = (double)x[li];
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int idx = base + k * 256 + threadIdx.x;
+    const double xv = setx ? 0.0 : vx[k];
+    const T xs = (T)(xv + al * vph[k] + om * vsh[k]);
+    const T rs = (T)(vs[k] - om * vt[k]);
+    const double rd = (double)rs;
+    if (idx < N) {
+      x[idx] = xs;
+      r[idx] = rs;
+      acc[0] += vrh[k] * rd;
+      acc[1] += rd * rd;
+    }
+  }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
@@ -886,24 +1207,10 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   if (!inner_active(sc) || !prec_match<T>(I)) return;
   const KSet<T> &KS = kset<T>(I);
   T *x = iterate_ptr<T>(I, sc);
-  const double al = sc->alpha, om = sc->omega;
-  const bool setx = sc->inner_first;
-  const int N = I.m * I.n + 1;
   double acc[2] = {0.0, 0.0};
-  const int base = mp.y * PD_ELEM_PER_BLOCK;
-#pragma unroll
-  for (int k = 0; k < PD_ELEM_PER_BLOCK / 256; ++k) {
-    const int idx = base + k * 256 + threadIdx.x;
-    if (idx < N) {
-      const double dx = al * ld(KS.ph, idx) + om * ld(KS.sh, idx);
-      x[idx] = (T)(setx ? dx : ld(x, idx) + dx);
-      const T rs = (T)(ld(KS.s, idx) - om * ld(KS.t, idx));
-      KS.r[idx] = rs;
-      const double rd = (double)rs;
-      acc[0] += ld(KS.rh, idx) * rd;
-      acc[1] += rd * rd;
-    }
-  }
+  elem_body<T>(I.m * I.n + 1, mp.y * PD_ELEM_PER_BLOCK, sc->alpha, sc->omega, sc->inner_first != 0,
+               G((const T *)KS.ph), G((const T *)KS.sh), G((const T *)KS.s), G((const T *)KS.t),
+               G((const T *)KS.rh), G(x), G(KS.r), acc);
   double tot[2];
   if (block_commit<2>(acc, I.partials, I.nb_elem, mp.y, I.counters + CNT_X, tot) &&
       threadIdx.x == 0) {
@@ -944,14 +1251,6 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   }
 }
 
-// Clears the restart flag after the radial sweep that consumed it; resets
-// counters of an instance after an aborted launch.
-__global__ void k_clear_reset(PdInst *insts, int ninst) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= ninst) return;
-  insts[q].sc->reset_rh = 0;
-}
-
 }  // namespace pd
 
 // ------------------------------------------------------------ launchers
@@ -985,24 +1284,45 @@ void launch_level_end(const LaunchSet &L, hipStream_t s) {
   Mark mk(KF_CONTROL, s);
   k_level_end<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
 }
+// Register-array length of the segmented sweeps: the smallest of 4, 8, 16,
+// 32 that holds the longest segment of the batch.
+static inline int seg_len(int b) { return b <= 4 ? 4 : (b <= 8 ? 8 : (b <= 16 ? 16 : 32)); }
+
+#define PD_DISPATCH_BM(b, CALL)          \
+  switch (seg_len(b)) {                  \
+    case 4: { constexpr int BM = 4; CALL; } break;   \
+    case 8: { constexpr int BM = 8; CALL; } break;   \
+    case 16: { constexpr int BM = 16; CALL; } break; \
+    default: { constexpr int BM = 32; CALL; } break; \
+  }
+
 void launch_factor(const LaunchSet &L, hipStream_t s) {
   Mark mk(KF_FACTOR, s);
-  if (L.nb_frad) k_fact_rad<<<g1(L.nb_frad), 64, 0, s>>>(L.insts, L.map_frad);
-  if (L.nb_fang) k_fact_ang<<<g1(L.nb_fang), 64, 0, s>>>(L.insts, L.map_fang);
+  if (L.nb_rad) k_fact_rad<<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad);
+  if (L.nb_ang)
+    PD_DISPATCH_BM(L.max_bang, (k_fact_ang<BM><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang)));
 }
 void launch_begin(const LaunchSet &L, hipStream_t s) {
   Mark mk(KF_BEGIN, s);
   k_sten<double, SM_BEGIN><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr);
 }
 
+template <typename T, int MODE>
+static void rad(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
+  PD_DISPATCH_BM(L.max_brad, (k_rad<T, MODE, BM><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, in, out)));
+}
+template <typename T, int MODE>
+static void ang(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
+  PD_DISPATCH_BM(L.max_bang, (k_ang<T, MODE, BM><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, in, out)));
+}
+
 template <typename T>
 static void cycle_t(const LaunchSet &L, hipStream_t s) {
-  { Mark mk(KF_RAD, s); k_rad<T, RM_P><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, nullptr, nullptr); }
-  { Mark mk(KF_CONTROL, s); k_clear_reset<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst); }
-  { Mark mk(KF_ANG, s); k_ang<T, AM_P><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, nullptr, nullptr); }
+  { Mark mk(KF_RAD, s); rad<T, RM_P>(L, s); }
+  { Mark mk(KF_ANG, s); ang<T, AM_P>(L, s); }
   { Mark mk(KF_STEN_V, s); k_sten<T, SM_V><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr); }
-  { Mark mk(KF_RAD, s); k_rad<T, RM_S><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, nullptr, nullptr); }
-  { Mark mk(KF_ANG, s); k_ang<T, AM_S><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, nullptr, nullptr); }
+  { Mark mk(KF_RAD, s); rad<T, RM_S>(L, s); }
+  { Mark mk(KF_ANG, s); ang<T, AM_S>(L, s); }
   { Mark mk(KF_STEN_T, s); k_sten<T, SM_T><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr); }
   { Mark mk(KF_UPDATE, s); k_elem_x<T><<<g1(L.nb_elem), 256, 0, s>>>(L.insts, L.map_elem); }
 }
@@ -1036,8 +1356,8 @@ void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void 
 
 void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,
                           hipStream_t s) {
-  k_rad<double, RM_PLAIN><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, x, tmp);
-  k_ang<double, AM_PLAIN><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, tmp, y);
+  rad<double, RM_PLAIN>(L, s, x, tmp);
+  ang<double, AM_PLAIN>(L, s, tmp, y);
 }
 
 }  // namespace pd
