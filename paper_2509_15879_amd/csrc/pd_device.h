@@ -27,8 +27,10 @@
 
 enum { ST_IDLE = 0, ST_ACTIVE = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOCONV = 4 };
 enum { PH_INNER = 0, PH_OUTER = 1 };
+// What the next radial p-sweep closes: an update step, a level's begin, a refinement.
+enum { PEND_UPDATE = 0, PEND_BEGIN = 1, PEND_REFINE = 2 };
 
-// Counter slots (per instance) for the last-block reductions.
+// Counter slots (per instance; kept for the layout of older tools).
 enum { CNT_BEGIN = 0, CNT_V = 1, CNT_T = 2, CNT_X = 3, CNT_UR = 4, CNT_APPLY = 5, CNT_N = 8 };
 
 struct PdScalars {
@@ -42,11 +44,14 @@ struct PdScalars {
   int inner_iters, restarts, first, reset_rh;
   int inner_first, have_prev, rot, nfail;
   int max_outer, maxit_inner, total_iters, pad1;
+  int pend, restarted;      // what the next radial p-sweep closes; restart flag
   // Krylov scalars
+  double rho_next, rho_cur; // ρ of this iteration (set by the p-sweep), of the last (by the s-sweep)
   double rho_old, rho_new, alpha, omega;
   double bnorm2, rnorm2, r0norm2;
   double rel_resid;
   double t_now;
+  double rout0[2];          // FP64 outer residual at the origin (mixed), by refinement parity
 };
 
 template <typename T>
@@ -85,7 +90,9 @@ struct PdInst {
   double *af_kappa, *af_alpha0;   // [m] Sherman-Morrison scalars per ring
   KSet<double> k64;
   KSet<float> k32;
-  double *partials;         // [PD_NSLOT * max(nb_sten, nb_elem)]
+  double *partials;         // per-block partial sums, one region per producer:
+  double *part_b, *part_v, *part_t, *part_ur, *part_a;   // [slots * nb_sten]
+  double *part_x;                                        // [2 * nb_elem]
   unsigned *counters;       // [CNT_N]
   PdScalars *sc;
   int *n_active;            // shared counter of the batch (device)

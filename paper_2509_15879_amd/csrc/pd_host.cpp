@@ -11,6 +11,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -278,8 +279,14 @@ void carve(pd_instance *I, Carver &c) {
     H.k32.af_g = c.take<float>(mn);
     H.k32.af_z = c.take<float>(mn);
   }
-  const int nbp = std::max(I->T.nb_sten, I->T.nb_elem);
-  H.partials = c.take<double>((size_t)PD_NSLOT * nbp);
+  const int nbs = I->T.nb_sten;
+  H.part_b = c.take<double>(4 * (size_t)nbs);
+  H.part_v = c.take<double>(2 * (size_t)nbs);
+  H.part_t = c.take<double>(3 * (size_t)nbs);
+  H.part_ur = c.take<double>(2 * (size_t)nbs);
+  H.part_a = c.take<double>(1 * (size_t)nbs);
+  H.part_x = c.take<double>(2 * (size_t)I->T.nb_elem);
+  H.partials = H.part_b;
   H.counters = c.take<unsigned>(CNT_N);
   I->sc = c.take<PdScalars>(1);
   H.sc = I->sc;
@@ -542,18 +549,57 @@ int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &
   }
   int max_cycles = 0;
   for (auto &sp : sps) max_cycles = std::max(max_cycles, sp.maxit + sp.max_outer + 8);
+  // The Krylov cycles of a level repeat identically: capture kCyclesPerGraph
+  // of them, followed by the read-back of the active-instance counter, into
+  // one HIP graph and replay it until every instance has finished the level
+  // (one graph of look-ahead; a launch for finished instances is a no-op).
+  // Per-kernel event timing needs the plain launches.
+  const bool use_graph = !pd::g_timer && !getenv("PD_NO_GRAPH");
+  constexpr int kCyclesPerGraph = 2;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraph_t &g;
+    hipGraphExec_t &e;
+    ~GraphGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gguard{graph, gexec};
+  if (use_graph) {
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < kCyclesPerGraph; ++c) pd::launch_cycle(P.L, s);
+    hipError_t ce = hipMemcpyAsync(&P.h_active[0], P.n_active, sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (ce != hipSuccess || ee != hipSuccess)
+      return fail(PD_EHIP, "graph capture failed: %s / %s", hipGetErrorString(ce), hipGetErrorString(ee));
+    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
   for (int lev = 0; lev < maxK; ++lev) {
     pd::launch_level_begin(P.L, s);
     pd::launch_factor(P.L, s);
     pd::launch_begin(P.L, s);
-    int c = 0;
-    for (; c < max_cycles; ++c) {
-      pd::launch_cycle(P.L, s);
-      HIPCHK(hipMemcpyAsync(&P.h_active[c & 1], P.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipEventRecord(P.ev[c & 1], s));
-      if (c >= 1) {
-        HIPCHK(hipEventSynchronize(P.ev[(c - 1) & 1]));
-        if (P.h_active[(c - 1) & 1] == 0) break;
+    if (use_graph) {
+      const int max_launch = (max_cycles + kCyclesPerGraph - 1) / kCyclesPerGraph;
+      for (int c = 0; c < max_launch; ++c) {
+        HIPCHK(hipGraphLaunch(gexec, s));
+        HIPCHK(hipEventRecord(P.ev[c & 1], s));
+        if (c >= 1) {
+          // the slot holds the count after launch c-1 or a later one: the
+          // count never grows inside a level, so 0 means the level is done
+          HIPCHK(hipEventSynchronize(P.ev[(c - 1) & 1]));
+          if (__atomic_load_n(&P.h_active[0], __ATOMIC_ACQUIRE) == 0) break;
+        }
+      }
+    } else {
+      for (int c = 0; c < max_cycles; ++c) {
+        pd::launch_cycle(P.L, s);
+        HIPCHK(hipMemcpyAsync(&P.h_active[c & 1], P.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(P.ev[c & 1], s));
+        if (c >= 1) {
+          HIPCHK(hipEventSynchronize(P.ev[(c - 1) & 1]));
+          if (P.h_active[(c - 1) & 1] == 0) break;
+        }
       }
     }
     HIPCHK(hipGetLastError());
@@ -1039,6 +1085,7 @@ int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double 
   pd::launch_level_begin(P.L, s);
   pd::launch_factor(P.L, s);
   pd::launch_begin(P.L, s);
+  pd::launch_begin_origin(P.L, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   const int m = I->M.m, n = I->M.n, N = m * n + 1;

@@ -2,10 +2,14 @@
 //
 // Every kernel is batched: a block map turns blockIdx.x into (instance,
 // local block), so one launch advances every instance of a batch, whatever
-// its mesh size or PDE type.  Per-instance Krylov scalars live in device
-// memory and are finalised by the last block of each reducing kernel, in a
-// fixed order that depends only on the instance's own tiling (a result does
-// not depend on which other instances share the launch).
+// its mesh size or PDE type.  Reductions never synchronise blocks inside a
+// launch: a reducing kernel leaves one partial sum per block and slot, and
+// the next kernel that needs the total (always a later launch on the same
+// stream, so no fence is needed) sums the partials in a fixed order in every
+// block.  Block 0 of that kernel records the instance's Krylov scalars and
+// status, writing only fields that kernel does not read.  The order of every
+// sum depends only on the instance's own tiling, so a result does not depend
+// on which other instances share the launch.
 //
 // One time level (scheme (2.5) of §2.1, Ch. 3 scheme of §3.2.1, system
 // (2.11)/(2.12)) is
@@ -71,57 +75,56 @@ __device__ __forceinline__ double tau_q(double lam, int tp, double t) {
   return v;
 }
 
-// Block-wide reduction of NS partial sums into a per-instance partial array,
-// followed by a deterministic reduction of all partials by the last block of
-// the instance.  Returns true in that last block, with the totals in tot.
+// Per-block partial sums of a reducing kernel: one value per slot and block,
+// written by thread 0 with plain stores (the consumer is a later launch).
 template <int NS>
-__device__ bool block_commit(double (&v)[NS], double *part, int nblk, int blk, unsigned *counter,
-                             double (&tot)[NS]) {
+__device__ __forceinline__ void produce(double (&v)[NS], double *part, int nblk, int blk) {
   __shared__ double red[NS][16];
-  __shared__ int s_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    double x = wave_sum(v[k]);
+    const double x = wave_sum(v[k]);
     if (lane == 0) red[k][wave] = x;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += red[k][w];
-      __hip_atomic_store(&part[k * nblk + blk], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      double sum = 0.0;
+      for (int w = 0; w < nw; ++w) sum += red[k][w];
+      part[k * nblk + blk] = sum;
     }
-    __threadfence();
-    unsigned t = atomicAdd(counter, 1u);
-    s_last = (t == (unsigned)(nblk - 1)) ? 1 : 0;
   }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  double acc[NS];
+}
+
+// Total of a producer's partials: wave 0 sums them in a fixed order (lane
+// strided, then a butterfly) and the block shares the result.  Every thread
+// of the block must call it.
+template <int NS>
+__device__ __forceinline__ void consume(const double *part, int nblk, double (&tot)[NS]) {
+  __shared__ double sh[NS];
+  if (threadIdx.x < 64) {
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-      s += __hip_atomic_load(&part[k * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    acc[k] = wave_sum(s);
-  }
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) red[k][wave] = acc[k];
+    for (int k = 0; k < NS; ++k) {
+      double sum = 0.0;
+      for (int b = threadIdx.x; b < nblk; b += 64) sum += part[k * nblk + b];
+      sum = wave_sum(sum);
+      if (threadIdx.x == 0) sh[k] = sum;
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[k][w];
-    tot[k] = s;
-  }
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
-  return true;
+  for (int k = 0; k < NS; ++k) tot[k] = sh[k];
+}
+
+// One snapshot of an instance's status per block: block 0 of a kernel may
+// change the status while other blocks of the same launch start, and all
+// threads of a block must take the same path through its barriers.
+__device__ __forceinline__ int block_status(const PdScalars *sc) {
+  __shared__ int st;
+  if (threadIdx.x == 0) st = sc->status;
+  __syncthreads();
+  return st;
 }
 
 __device__ __forceinline__ void finish_instance(const PdInst &I, PdScalars *sc, int status) {
@@ -190,15 +193,17 @@ __global__ void k_level_begin(PdInst *insts, int ninst) {
   sc->status = ST_ACTIVE;
   atomicAdd(I.n_active, 1);
   sc->phase = PH_INNER;
+  sc->pend = PEND_BEGIN;
+  sc->restarted = 0;
   sc->iters = 0;
   sc->outer = 0;
   sc->inner_iters = 0;
   sc->restarts = 0;
   sc->first = 1;
   sc->reset_rh = 0;
-  sc->inner_first = I.mixed ? 1 : 0;
+  sc->inner_first = 1;
   sc->alpha = sc->omega = 1.0;
-  sc->rho_old = sc->rho_new = 1.0;
+  sc->rho_old = sc->rho_new = sc->rho_next = sc->rho_cur = 1.0;
 }
 
 // Records the level, rotates the solution buffers (iterate -> n^{k+1}).
@@ -221,6 +226,10 @@ __global__ void k_level_end(PdInst *insts, int ninst) {
   sc->total_iters += sc->iters;
   const bool ok = sc->status == ST_DONE;
   if (!ok) sc->nfail += 1;
+  if (sc->status == ST_ACTIVE) {       // stopped by the host's cycle cap
+    st[2] = ST_NOCONV;
+    atomicSub(I.n_active, 1);
+  }
   sc->rot = (sc->rot + 1) % 3;       // old iterate slot becomes n^k
   sc->prev_dt = sc->dt;
   sc->have_prev = 1;
@@ -651,31 +660,118 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
 
 enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4 };
 
+// Origin rows, closed by a later kernel from the producers' partial sums
+// (the ring-1 face sums S0 and the ring parts of the norms).
+
+// Level begin at the origin: rhs b_0, extrapolated guess, scaled residual.
+struct OriginBegin {
+  double b, xg, r, rs, bb, rr;
+};
+__device__ __forceinline__ OriginBegin origin_begin(const PdInst &I, const PdScalars *sc,
+                                                    const double (&tot)[4]) {
+  const int orig = I.m * I.n;
+  const double inv_dt = sc->inv_dt, th = sc->theta, rho = sc->extrap;
+  const bool ex = rho != 0.0;
+  const double *xk = I.sol[(sc->rot + 1) % 3], *xkm = I.sol[sc->rot % 3];
+  const double bo = I.has_b ? I.b_node[orig] : 0.0;
+  const double xk0 = xk[orig], xkm0 = ex ? xkm[orig] : xk0;
+  const double L0 = I.inv_V0 * tot[2] + bo * xk0;
+  const double L1 = I.inv_V0 * tot[3] + bo * xkm0;
+  double b = inv_dt * xk0 - (1.0 - th) * L0;
+  for (int q = 0; q < I.nsrc; ++q) b += sc->cq[q] * I.g[q * I.npad + orig];
+  OriginBegin O;
+  O.b = b;
+  O.xg = ex ? xk0 + rho * (xk0 - xkm0) : xk0;
+  const double Lg = ex ? L0 + rho * (L0 - L1) : L0;
+  O.r = b - (inv_dt * O.xg + th * Lg);
+  const double id = I.inv_diag[orig];
+  O.rs = O.r * id;
+  const double bs = b * id;
+  O.bb = tot[0] + bs * bs;
+  O.rr = tot[1] + O.rs * O.rs;
+  return O;
+}
+__device__ __forceinline__ void origin_begin_store(const PdInst &I, const PdScalars *sc,
+                                                   const OriginBegin &O) {
+  const int orig = I.m * I.n;
+  I.bvec[orig] = O.b;
+  I.sol[(sc->rot + 2) % 3][orig] = O.xg;
+  if (I.mixed) {
+    I.k32.r[orig] = (float)O.rs;
+    I.k32.rh[orig] = (float)O.rs;
+  } else {
+    I.k64.r[orig] = O.rs;
+    I.k64.rh[orig] = O.rs;
+  }
+}
+
+// Refinement at the origin: r_0 <- r_0 - (A d)_0, with the previous r_0 kept
+// in the scalars (slot by refinement parity, so the kernel that reads one
+// slot writes the other).
+struct OriginRefine {
+  double d0, r, rs, rr;
+};
+__device__ __forceinline__ OriginRefine origin_refine(const PdInst &I, const PdScalars *sc,
+                                                      const double (&tot)[2]) {
+  const int orig = I.m * I.n;
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  const double bo = I.has_b ? I.b_node[orig] : 0.0;
+  OriginRefine O;
+  O.d0 = (double)I.k32.d[orig];
+  const double rprev = sc->rout0[(sc->outer + 1) & 1];
+  O.r = rprev - (inv_dt * O.d0 + th * (I.inv_V0 * tot[1] + bo * O.d0));
+  O.rs = O.r * I.inv_diag[orig];
+  O.rr = tot[0] + O.rs * O.rs;
+  return O;
+}
+
+// A row at the origin: (I/dt + θL)_0 x, scaled by 1/d_0.
+template <typename TK>
+__device__ __forceinline__ double origin_apply(const PdInst &I, double inv_dt, double th, double x0,
+                                               double S0, double invd0) {
+  const double bo = I.has_b ? I.b_node[I.m * I.n] : 0.0;
+  return (inv_dt * x0 + th * (I.inv_V0 * S0 + bo * x0)) * invd0;
+}
+
 // Stencil kernels.  TK: storage type of the Krylov set the mode works on.
-//  SM_APPLY: y = x/dt + θ L x (diagnostic; dt, θ, x, y passed explicitly)
+// Ring rows only; the origin row is closed by the consumer of the partials.
+//  SM_APPLY: y = x/dt + θ L x (diagnostic; partial S0)
 //  SM_BEGIN: b = x^k/dt - (1-θ) L x^k + Σ_q c_q g_q + boundary;
 //            x0 = x^k + ρ (x^k - x^{k-1});  r = D^{-1}(b - A x0);  r̂ = r
-//  SM_V:     v = D^{-1} A p̂,  partial r̂·v
-//  SM_T:     t = D^{-1} A ŝ,  partials t·s, t·t
-//  SM_UR:    (mixed) r ← r - A d in FP64, x ← x + d; r32 = r̂32 = D^{-1} r
+//            partials ||D^{-1}b||², ||r||², S0(x^k), S0(x^{k-1})
+//  SM_V:     v = D^{-1} A p̂,  partials r̂·v, S0(p̂)
+//  SM_T:     t = D^{-1} A ŝ,  partials t·s, t·t, S0(ŝ)
+//  SM_UR:    (mixed, when the inner solve has converged) r <- r - A d in
+//            FP64, x <- x + d, r32 = r̂32 = D^{-1} r; partials ||r32||², S0(d)
 template <typename TK, int MODE>
 __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *map, double a_dt,
                                               double a_th, const TK *ax, TK *ay) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
-  if (MODE == SM_V || MODE == SM_T) {
-    if (!inner_active(sc) || !prec_match<TK>(I)) return;
-  } else if (MODE == SM_BEGIN) {
-    if (sc->status != ST_ACTIVE) return;
-  } else if (MODE == SM_UR) {
-    if (sc->status != ST_ACTIVE || sc->phase != PH_OUTER) return;
+  if (MODE != SM_APPLY) {
+    if (sc->status != ST_ACTIVE) return;     // no block of this kernel changes the status
+    if ((MODE == SM_V || MODE == SM_T) && !prec_match<TK>(I)) return;
+    if (MODE == SM_UR && !I.mixed) return;
+  }
+  if (MODE == SM_UR) {
+    // refine once the inner solve has iterated and met its tolerance
+    if (sc->inner_iters == 0) return;
+    double tot[2];
+    consume<2>(I.part_x, I.nb_elem, tot);
+    const bool due = tot[1] <= sc->tol_inner * sc->tol_inner * sc->r0norm2 ||
+                     sc->inner_iters >= sc->maxit_inner || sc->iters >= sc->maxit || !(tot[1] == tot[1]);
+    if (!due) return;
+    if (mp.y == 0 && threadIdx.x == 0) {
+      sc->pend = PEND_REFINE;
+      sc->outer = sc->outer + 1;
+    }
   }
   const int wave = threadIdx.x >> 6;
   const int tile = mp.y * PD_STEN_WAVES + wave;
   const bool wave_on = tile < I.ncg * I.nrg;
   const int cg = wave_on ? tile % I.ncg : 0, rg = wave_on ? tile / I.ncg : 0;
-  const int m = I.m, n = I.n, orig = m * n;
+  const int m = I.m, n = I.n;
   const KSet<TK> &KS = kset<TK>(I);
   const TileGeo geo = tile_geo(m, n, cg, rg);
   const GAS double *inv_rw = G(I.inv_rw), *inv_dth = G(I.inv_dth);
@@ -691,13 +787,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                            [&](int, int, int idx, const double *xc, const double *Lx) {
                              y[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
                            });
-    double tot[1];
-    if (block_commit<1>(S0, I.partials, I.nb_sten, mp.y, I.counters + CNT_APPLY, tot) &&
-        threadIdx.x == 0) {
-      const double x0 = (double)ax[orig];
-      const double bo = I.has_b ? I.b_node[orig] : 0.0;
-      ay[orig] = (TK)(inv_dt * x0 + th * (I.inv_V0 * tot[0] + bo * x0));
-    }
+    produce<1>(S0, I.part_a, I.nb_sten, mp.y);
   } else if (MODE == SM_BEGIN) {
     // FP64 operator on x^k and x^{k-1}
     const double inv_dt = sc->inv_dt, th = sc->theta, rho = sc->extrap;
@@ -706,7 +796,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     double *x0 = I.sol[(sc->rot + 2) % 3];
     const bool ex = rho != 0.0;
     double cq[PD_MAXSRC];
-    for (int s = 0; s < PD_MAXSRC; ++s) cq[s] = sc->cq[s];
+    for (int q = 0; q < PD_MAXSRC; ++q) cq[q] = sc->cq[q];
     const int nsrc = I.nsrc, npad = I.npad;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};   // ||D^-1 b||^2, ||D^-1 r||^2, S0(x^k), S0(x^{k-1})
     double S0[2] = {0.0, 0.0};
@@ -721,10 +811,10 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
           geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk), G(ex ? xkm : xk),
           inv_rw, inv_dth, bnode, S0, [&](int i, int j, int idx, const double *xc, const double *Lx) {
             double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
-            for (int s = 0; s < nsrc; ++s) b += cq[s] * gsrc[s * npad + idx];
+            for (int q = 0; q < nsrc; ++q) b += cq[q] * gsrc[q * npad + idx];
             if (i == m) {
               double Nm = 0.0;
-              for (int s = 0; s < nsrc; ++s) Nm += cq[s] * nbv[s * n + j];
+              for (int q = 0; q < nsrc; ++q) Nm += cq[q] * nbv[q * n + j];
               b += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
             }
             const double xg = ex ? xc[0] + rho * (xc[0] - xc[1]) : xc[0];
@@ -747,42 +837,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
           });
     acc[2] = S0[0];
     acc[3] = S0[1];
-    double tot[4];
-    if (block_commit<4>(acc, I.partials, I.nb_sten, mp.y, I.counters + CNT_BEGIN, tot) &&
-        threadIdx.x == 0) {
-      const double bo = I.has_b ? I.b_node[orig] : 0.0;
-      const double xk0 = xk[orig], xkm0 = ex ? xkm[orig] : xk0;
-      const double L0 = I.inv_V0 * tot[2] + bo * xk0;
-      const double L1 = I.inv_V0 * tot[3] + bo * xkm0;
-      double b = inv_dt * xk0 - (1.0 - th) * L0;
-      for (int s = 0; s < nsrc; ++s) b += cq[s] * I.g[s * npad + orig];
-      const double xg = ex ? xk0 + rho * (xk0 - xkm0) : xk0;
-      const double Lg = ex ? L0 + rho * (L0 - L1) : L0;
-      const double r = b - (inv_dt * xg + th * Lg);
-      const double id = I.inv_diag[orig];
-      const double rs = r * id, bs = b * id;
-      I.bvec[orig] = b;
-      x0[orig] = xg;
-      if (mixed) {
-        I.rout[orig] = r;
-        I.k32.r[orig] = (float)rs;
-        I.k32.rh[orig] = (float)rs;
-      } else {
-        I.k64.r[orig] = rs;
-        I.k64.rh[orig] = rs;
-      }
-      const double bb = tot[0] + bs * bs, rr = tot[1] + rs * rs;
-      sc->bnorm2 = bb;
-      sc->rnorm2 = rr;
-      sc->r0norm2 = rr;
-      sc->rho_new = rr;
-      sc->rel_resid = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-      if (!(rr == rr) || !(bb == bb)) {
-        finish_instance(I, sc, ST_BREAKDOWN);
-      } else if (rr <= sc->tol * sc->tol * bb) {
-        finish_instance(I, sc, ST_DONE);
-      }
-    }
+    produce<4>(acc, I.part_b, I.nb_sten, mp.y);
   } else if (MODE == SM_V || MODE == SM_T) {
     const double inv_dt = sc->inv_dt, th = sc->theta;
     const TK *xin = (MODE == SM_V) ? KS.ph : KS.sh;
@@ -804,41 +859,12 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                              acc[0] += (double)ot[idx] * yd;
                              acc[1] += yd * yd;
                            });
-    acc[2] = S0[0];
-    double tot[3];
-    if (block_commit<3>(acc, I.partials, I.nb_sten, mp.y,
-                        I.counters + (MODE == SM_V ? CNT_V : CNT_T), tot) &&
-        threadIdx.x == 0) {
-      const double bo = I.has_b ? I.b_node[orig] : 0.0;
-      const double x0 = (double)xin[orig];
-      const double y0 = (inv_dt * x0 + th * (I.inv_V0 * tot[2] + bo * x0)) * (double)KS.inv_d[orig];
-      const TK ys = (TK)y0;
-      yout[orig] = ys;
-      const double yd = (double)ys;
-      const double dot = tot[0] + (double)other[orig] * yd;
-      const double yy = tot[1] + yd * yd;
-      if (MODE == SM_V) {
-        // α = ρ / (r̂·v)
-        if (!(dot == dot)) {
-          finish_instance(I, sc, ST_BREAKDOWN);
-        } else if (fabs(dot) <= 1e-300 || fabs(sc->rho_new) <= 1e-300) {
-          sc->alpha = 0.0;
-          sc->reset_rh = 1;     // restart: r̂ = r, p = r
-        } else {
-          sc->alpha = sc->rho_new / dot;
-        }
-        sc->first = 0;
-      } else {
-        // ω = (t·s)/(t·t)
-        if (!(dot == dot) || !(yy == yy)) {
-          finish_instance(I, sc, ST_BREAKDOWN);
-        } else if (yy <= 1e-300) {
-          sc->omega = 0.0;
-          sc->reset_rh = 1;
-        } else {
-          sc->omega = dot / yy;
-        }
-      }
+    if (MODE == SM_V) {
+      double pv[2] = {acc[0], S0[0]};
+      produce<2>(pv, I.part_v, I.nb_sten, mp.y);
+    } else {
+      acc[2] = S0[0];
+      produce<3>(acc, I.part_t, I.nb_sten, mp.y);
     }
   } else if (MODE == SM_UR) {
     // FP64 operator applied to the FP32 correction d
@@ -863,38 +889,36 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                                     acc[0] += rs * rs;
                                   });
     acc[1] = S0[0];
-    double tot[2];
-    if (block_commit<2>(acc, I.partials, I.nb_sten, mp.y, I.counters + CNT_UR, tot) &&
-        threadIdx.x == 0) {
-      const double bo = I.has_b ? I.b_node[orig] : 0.0;
-      const double d0 = (double)I.k32.d[orig];
-      const double r = I.rout[orig] - (inv_dt * d0 + th * (I.inv_V0 * tot[1] + bo * d0));
-      const double rs = r * I.inv_diag[orig];
-      I.rout[orig] = r;
-      x[orig] += d0;
-      I.k32.r[orig] = (float)rs;
-      I.k32.rh[orig] = (float)rs;
-      const double rr = tot[0] + rs * rs;
-      sc->rnorm2 = rr;
-      sc->outer += 1;
-      sc->rel_resid = sqrt(rr / sc->bnorm2);
-      if (!(rr == rr)) {
-        finish_instance(I, sc, ST_BREAKDOWN);
-      } else if (rr <= sc->tol * sc->tol * sc->bnorm2) {
-        finish_instance(I, sc, ST_DONE);
-      } else if (sc->outer >= sc->max_outer) {
-        finish_instance(I, sc, ST_NOCONV);
-      } else {
-        sc->phase = PH_INNER;
-        sc->first = 1;
-        sc->inner_first = 1;
-        sc->inner_iters = 0;
-        sc->r0norm2 = rr;
-        sc->rho_new = rr;
-        sc->alpha = sc->omega = 1.0;
-      }
-    }
+    produce<2>(acc, I.part_ur, I.nb_sten, mp.y);
   }
+}
+
+// Origin of a diagnostic operator apply (one thread per instance).
+template <typename TK>
+__global__ void k_apply_origin(const PdInst *insts, int ninst, double a_dt, double a_th, const TK *ax,
+                               TK *ay) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ninst) return;
+  const PdInst &I = insts[q];
+  double s0 = 0.0;
+  for (int b = 0; b < I.nb_sten; ++b) s0 += I.part_a[b];
+  const int orig = I.m * I.n;
+  ay[orig] = (TK)origin_apply<TK>(I, 1.0 / a_dt, a_th, (double)ax[orig], s0, 1.0);
+}
+
+// Origin of the level begin without a Krylov phase (right-hand side only).
+__global__ void k_begin_origin(const PdInst *insts, int ninst) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ninst) return;
+  const PdInst &I = insts[q];
+  double tot[4];
+  for (int k = 0; k < 4; ++k) {
+    double sum = 0.0;
+    for (int b = 0; b < I.nb_sten; ++b) sum += I.part_b[k * I.nb_sten + b];
+    tot[k] = sum;
+  }
+  const OriginBegin O = origin_begin(I, I.sc, tot);
+  origin_begin_store(I, I.sc, O);
 }
 
 // ------------------------------------------------------------ radial sweep
@@ -1019,28 +1043,124 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
-  if (MODE != RM_PLAIN && (!inner_active(sc) || !prec_match<T>(I))) return;
+  if (MODE != RM_PLAIN) {
+    if (!prec_match<T>(I)) return;
+    if (block_status(sc) != ST_ACTIVE) return;   // the p- and s-sweeps change the status
+  }
   const KSet<T> &KS = kset<T>(I);
-  const int m = I.m, n = I.n, cw = I.cw, B = I.brad;
+  const int m = I.m, n = I.n, orig = m * n, cw = I.cw, B = I.brad;
+  const bool b0 = mp.y == 0 && threadIdx.x == 0;
+  double beta = 0.0, omega = 0.0, alpha = 0.0;
+  bool first = false, reset = false;
+  if (MODE == RM_P) {
+    // close what the previous launches left: a level begin, a refinement or
+    // an update step (ρ = r̂·r, convergence, restart, β)
+    int st = ST_ACTIVE;
+    double rho = 0.0, rel = -1.0;
+    const int pend = sc->pend;
+    if (pend == PEND_BEGIN) {
+      double tot[4];
+      consume<4>(I.part_b, I.nb_sten, tot);
+      const OriginBegin O = origin_begin(I, sc, tot);
+      if (b0) {
+        origin_begin_store(I, sc, O);
+        sc->bnorm2 = O.bb;
+        sc->r0norm2 = O.rr;
+        sc->inner_first = 1;
+        sc->inner_iters = 0;
+        sc->rout0[0] = O.r;
+      }
+      rho = O.rr;
+      first = true;
+      rel = O.bb > 0.0 ? sqrt(O.rr / O.bb) : 0.0;
+      if (!(O.rr == O.rr) || !(O.bb == O.bb)) st = ST_BREAKDOWN;
+      else if (O.rr <= sc->tol * sc->tol * O.bb) st = ST_DONE;
+    } else if (pend == PEND_REFINE) {
+      double tot[2];
+      consume<2>(I.part_ur, I.nb_sten, tot);
+      const OriginRefine O = origin_refine(I, sc, tot);
+      if (b0) {
+        sc->rout0[sc->outer & 1] = O.r;
+        I.sol[(sc->rot + 2) % 3][orig] += O.d0;
+        I.k32.r[orig] = (float)O.rs;
+        I.k32.rh[orig] = (float)O.rs;
+        sc->r0norm2 = O.rr;
+        sc->inner_first = 1;
+        sc->inner_iters = 0;
+      }
+      rho = O.rr;
+      first = true;
+      rel = sqrt(O.rr / sc->bnorm2);
+      if (!(O.rr == O.rr)) st = ST_BREAKDOWN;
+      else if (O.rr <= sc->tol * sc->tol * sc->bnorm2) st = ST_DONE;
+      else if (sc->outer >= sc->max_outer || sc->iters >= sc->maxit) st = ST_NOCONV;
+    } else {
+      double tot[2];
+      consume<2>(I.part_x, I.nb_elem, tot);
+      const double rr = tot[1];
+      rho = tot[0];
+      if (!(rr == rr) || !(rho == rho)) {
+        st = ST_BREAKDOWN;
+      } else if (!I.mixed) {
+        rel = sqrt(rr / sc->bnorm2);
+        if (rr <= sc->tol * sc->tol * sc->bnorm2) st = ST_DONE;
+        else if (sc->iters >= sc->maxit) st = ST_NOCONV;
+      }
+      if (st == ST_ACTIVE) {
+        if (sc->reset_rh || fabs(rho) <= 1e-30 * rr) {
+          first = true;                  // restart from the iterate: r̂ = r, p = r
+          reset = true;
+          rho = rr;
+          if (b0) sc->restarted = 1;
+        } else {
+          beta = (rho / sc->rho_cur) * (sc->alpha / sc->omega);
+        }
+      }
+      if (b0) sc->inner_first = 0;
+    }
+    omega = sc->omega;
+    if (b0) {
+      sc->rho_next = rho;
+      if (rel >= 0.0) sc->rel_resid = rel;
+      if (st != ST_ACTIVE) finish_instance(I, sc, st);
+    }
+    if (st != ST_ACTIVE) return;
+  } else if (MODE == RM_S) {
+    // α = ρ / (r̂·v), closing the v-stencil with its origin row
+    double tot[2];
+    consume<2>(I.part_v, I.nb_sten, tot);
+    const double ph0 = (double)KS.ph[orig];
+    const T v0 = (T)origin_apply<T>(I, sc->inv_dt, sc->theta, ph0, tot[1], (double)KS.inv_d[orig]);
+    const double dot = tot[0] + (double)KS.rh[orig] * (double)v0;
+    const double rho = sc->rho_next;
+    int st = ST_ACTIVE;
+    bool brk = false;
+    if (!(dot == dot)) {
+      st = ST_BREAKDOWN;
+    } else if (fabs(dot) <= 1e-300 || fabs(rho) <= 1e-300) {
+      alpha = 0.0;                         // restart at the next p-sweep
+      brk = true;
+    } else {
+      alpha = rho / dot;
+    }
+    if (b0) {
+      KS.v[orig] = v0;
+      sc->alpha = alpha;
+      sc->rho_cur = rho;
+      if (brk) sc->reset_rh = 1;
+      if (st != ST_ACTIVE) finish_instance(I, sc, st);
+    }
+    if (st != ST_ACTIVE) return;
+  }
   const int c = threadIdx.x % cw, seg = threadIdx.x / cw;
   const int j = mp.y * cw + c;
   const bool act = j < n;
   const int cnt = act ? max(0, min(B, m - seg * B)) : 0;
-  double beta = 0.0, omega = 0.0, alpha = 0.0;
-  bool first = false, reset = false;
-  if (MODE == RM_P) {
-    first = sc->first || sc->reset_rh;
-    reset = sc->reset_rh;
-    omega = sc->omega;
-    beta = first ? 0.0 : (sc->rho_new / sc->rho_old) * (sc->alpha / sc->omega);
-  } else if (MODE == RM_S) {
-    alpha = sc->alpha;
-  }
   T *out = (MODE == RM_PLAIN) ? plain_out : KS.w;
-  rad_body<T, MODE, BM>(m, n, cw, B, I.nseg, act ? j : 0, c, seg, cnt, mp.y == 0 && threadIdx.x == 0,
-                    beta, omega, alpha, first, reset, G((const T *)KS.r), G(KS.p),
-                    G((const T *)KS.v), G(KS.rh), G(KS.s), G(plain_in), G(out), G(I.rf_uinv),
-                    G((const T *)KS.rf_f), G((const T *)KS.rf_g));
+  rad_body<T, MODE, BM>(m, n, cw, B, I.nseg, act ? j : 0, c, seg, cnt, b0, beta, omega, alpha, first,
+                        reset, G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s),
+                        G(plain_in), G(out), G(I.rf_uinv), G((const T *)KS.rf_f),
+                        G((const T *)KS.rf_g));
 }
 
 // ------------------------------------------------------------ angular sweep
@@ -1148,8 +1268,16 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
   const int m = I.m, n = I.n;
   const int lane = threadIdx.x & 63;
   const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
-  // the restart flag was consumed by the radial sweep that ran before
-  if (MODE == AM_P && mp.y == 0 && threadIdx.x == 0) sc->reset_rh = 0;
+  // the p-sweep before this launch consumed the restart flag and the
+  // pending closure; only this block's thread 0 touches these fields here
+  if (MODE == AM_P && mp.y == 0 && threadIdx.x == 0) {
+    if (sc->restarted) {
+      sc->restarts += 1;
+      sc->restarted = 0;
+    }
+    sc->reset_rh = 0;
+    sc->pend = PEND_UPDATE;
+  }
   if (i > m) return;                                 // whole wave exits together
   const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
   T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
@@ -1164,7 +1292,8 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
 // breakdown or restart for the instance.
 
 template <typename T>
-__device__ __forceinline__ void elem_body(int N, int base, double al, double om, bool setx,
+__device__ __forceinline__ void elem_body(int N, int base, double al, double om, bool setx, int orig,
+                                          double t0,
                                           const GAS T *__restrict__ ph, const GAS T *__restrict__ sh,
                                           const GAS T *__restrict__ s, const GAS T *__restrict__ t,
                                           const GAS T *__restrict__ rh, GAS T *__restrict__ x,
@@ -1179,7 +1308,7 @@ __device__ __forceinline__ void elem_body(int N, int base, double al, double om,
     vph[k] = (double)ph[li];
     vsh[k] = (double)sh[li];
     vs[k] = (double)s[li];
-    vt[k] = (double)t[li];
+    vt[k] = (idx == orig) ? t0 : (double)t[li];
     vrh[k] = (double)rh[li];
     vx[k] = (double)x[li];
   }
@@ -1204,51 +1333,42 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
-  if (!inner_active(sc) || !prec_match<T>(I)) return;
+  if (!prec_match<T>(I)) return;
+  if (block_status(sc) != ST_ACTIVE) return;   // this kernel changes the status
   const KSet<T> &KS = kset<T>(I);
-  T *x = iterate_ptr<T>(I, sc);
-  double acc[2] = {0.0, 0.0};
-  elem_body<T>(I.m * I.n + 1, mp.y * PD_ELEM_PER_BLOCK, sc->alpha, sc->omega, sc->inner_first != 0,
-               G((const T *)KS.ph), G((const T *)KS.sh), G((const T *)KS.s), G((const T *)KS.t),
-               G((const T *)KS.rh), G(x), G(KS.r), acc);
-  double tot[2];
-  if (block_commit<2>(acc, I.partials, I.nb_elem, mp.y, I.counters + CNT_X, tot) &&
-      threadIdx.x == 0) {
-    const double rr = tot[1];
+  const int orig = I.m * I.n;
+  const bool b0 = mp.y == 0 && threadIdx.x == 0;
+  // ω = (t·s)/(t·t), closing the t-stencil with its origin row
+  double tot[3];
+  consume<3>(I.part_t, I.nb_sten, tot);
+  const T t0 = (T)origin_apply<T>(I, sc->inv_dt, sc->theta, (double)KS.sh[orig], tot[2],
+                                  (double)KS.inv_d[orig]);
+  const double s0 = (double)KS.s[orig];
+  const double ts = tot[0] + s0 * (double)t0, tt = tot[1] + (double)t0 * (double)t0;
+  double om = 0.0;
+  int st = ST_ACTIVE;
+  bool brk = false;
+  if (!(ts == ts) || !(tt == tt)) {
+    st = ST_BREAKDOWN;
+  } else if (tt <= 1e-300) {
+    brk = true;                           // x += α p̂ only; restart at the next p-sweep
+  } else {
+    om = ts / tt;
+  }
+  if (b0) {
+    sc->omega = om;
     sc->iters += 1;
     sc->inner_iters += 1;
-    sc->inner_first = 0;
-    sc->rho_old = sc->rho_new;
-    sc->rho_new = tot[0];
-    sc->rnorm2 = rr;
-    if (!(rr == rr) || !(tot[0] == tot[0])) {
-      finish_instance(I, sc, ST_BREAKDOWN);
-      return;
-    }
-    if (!I.mixed) {
-      sc->rel_resid = sqrt(rr / sc->bnorm2);
-      if (rr <= sc->tol * sc->tol * sc->bnorm2) {
-        finish_instance(I, sc, ST_DONE);
-        return;
-      }
-      if (sc->iters >= sc->maxit) {
-        finish_instance(I, sc, ST_NOCONV);
-        return;
-      }
-    } else {
-      if (rr <= sc->tol_inner * sc->tol_inner * sc->r0norm2 || sc->inner_iters >= sc->maxit_inner ||
-          sc->iters >= sc->maxit) {
-        sc->phase = PH_OUTER;
-      }
-    }
-    if (sc->reset_rh || fabs(tot[0]) <= 1e-30 * rr) {
-      // restart from the current iterate: r̂ = r, p = r
-      sc->reset_rh = 1;
-      sc->restarts += 1;
-      sc->rho_new = rr;
-      if (sc->restarts > 50) finish_instance(I, sc, ST_BREAKDOWN);
-    }
+    if (brk) sc->reset_rh = 1;
+    if (st != ST_ACTIVE) finish_instance(I, sc, st);
   }
+  if (st != ST_ACTIVE) return;
+  T *x = iterate_ptr<T>(I, sc);
+  double acc[2] = {0.0, 0.0};
+  elem_body<T>(orig + 1, mp.y * PD_ELEM_PER_BLOCK, sc->alpha, om, I.mixed && sc->inner_first != 0,
+               orig, (double)t0, G((const T *)KS.ph), G((const T *)KS.sh), G((const T *)KS.s),
+               G((const T *)KS.t), G((const T *)KS.rh), G(x), G(KS.r), acc);
+  produce<2>(acc, I.part_x, I.nb_elem, mp.y);
 }
 
 }  // namespace pd
@@ -1346,12 +1466,21 @@ void launch_cycle(const LaunchSet &L, hipStream_t s) {
 
 void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void *y, int fp32,
                   hipStream_t s) {
-  if (fp32)
+  if (fp32) {
     k_sten<float, SM_APPLY><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, dt, th,
                                                           (const float *)x, (float *)y);
-  else
+    k_apply_origin<float><<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst, dt, th,
+                                                             (const float *)x, (float *)y);
+  } else {
     k_sten<double, SM_APPLY><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, dt, th,
                                                            (const double *)x, (double *)y);
+    k_apply_origin<double><<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst, dt, th,
+                                                              (const double *)x, (double *)y);
+  }
+}
+
+void launch_begin_origin(const LaunchSet &L, hipStream_t s) {
+  k_begin_origin<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
 }
 
 void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,

@@ -96,3 +96,24 @@ def test_mixed_matches_fp64_on_cfg2_shape():
     assert l2_rel(xb, xa) <= 1e-9
     a.close()
     b.close()
+
+
+def test_graph_replay_equals_plain_launches(monkeypatch):
+    """The captured cycle graph, replayed many times per level with eager
+    launches and synchronisations in between, gives exactly the results of
+    plain launches."""
+    say("[batch] graph replay vs plain launches")
+    from paper_2509_15879_amd import polardisk as pdk
+    res = {}
+    for mode in ("graph", "plain"):
+        if mode == "plain":
+            monkeypatch.setenv("PD_NO_GRAPH", "1")
+        else:
+            monkeypatch.delenv("PD_NO_GRAPH", raising=False)
+        pairs = make_set((0, 1, 0))
+        pdk.solve_batch([p[0] for p in pairs], [p[1] for p in pairs])
+        res[mode] = [p[0].solution() for p in pairs]
+        for p in pairs:
+            p[0].close()
+    for a, b in zip(res["graph"], res["plain"]):
+        assert np.array_equal(a, b)
