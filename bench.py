@@ -26,19 +26,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-M, N_TH, P_STRETCH, T_END, K_LEVELS, L_TIME = 256, 512, 1.3, 0.05, 100, 1.5
-SEEDS = (1200, 1201, 1202, 1203, 1204)
-THETAS = (0.5, 1.0)
+from problems.workloads import CFG2, CFG2_SEEDS as SEEDS, CFG2_THETAS as THETAS, cfg2_batch  # noqa: E402
+
+M, N_TH, P_STRETCH, T_END, K_LEVELS, L_TIME = (CFG2[k] for k in ("m", "n", "p", "T", "K", "l"))
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per unknown of one launch (w: storage bytes of the
 # Krylov data, pivots are FP64): what the kernel must read and write once.
+KERNEL_NAMES = {
+    "sten_v": "k_sten<T, SM_V>", "sten_t": "k_sten<T, SM_T>", "rad_p": "k_rad<T, RM_P, BM>",
+    "rad_s": "k_rad<T, RM_S, BM>", "ang_p": "k_ang<T, AM_P, BM>", "ang_s": "k_ang<T, AM_S, BM>",
+    "update": "k_elem_x<T>",
+}
+
+
+# HBM bytes per active unknown that each kernel moved (FETCH_SIZE and
+# WRITE_SIZE counters, calibrated on a copy of known size), valid for the
+# kernel source with this SHA-1 only; any other source reports traffic null.
+TRAFFIC_SOURCE_SHA1 = "507088c5efcf47b92caaf58e6b94d77b2654ad2e"
+TRAFFIC_B_PER_CELL = {"rad_p": 63.67, "ang_p": 61.70, "sten_v": 71.69, "rad_s": 56.27,
+                      "ang_s": 61.09, "sten_t": 71.54, "update": 64.36}
+
+
+def kernel_source_sha1():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2509_15879_amd", "csrc", "pd_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
 def bytes_per_cell(family, w):
     return {
-        "sten_v": 7 * w,            # x, 4 face coefficients, r̂ in; v out
-        "sten_t": 7 * w,            # x, 4 faces, s in; t out
-        "rad": (7 * w + 8 + 6 * w + 8) / 2.0,   # mean of the p- and s-sweeps
-        "ang": 5 * w + 8,           # w, f, g, z in + pivot; out
+        "sten_v": 8 * w,            # p̂, 4 face coefficients, 1/diag, r̂ in; v out
+        "sten_t": 8 * w,            # ŝ, 4 faces, 1/diag, s in; t out
+        "rad_p": 7 * w + 8,         # r, p, v, f, g, pivot in; p, w out
+        "rad_s": 6 * w + 8,         # r, v, f, g, pivot in; s, w out
+        "ang_p": 5 * w + 8,         # w, f, g, z, pivot in; p̂ out
+        "ang_s": 5 * w + 8,         # w, f, g, z, pivot in; ŝ out
         "update": 8 * w,            # p̂, ŝ, x, s, t, r̂ in; x, r out
     }[family]
 
@@ -48,17 +72,15 @@ def log(*a):
 
 
 def build_instances(pdk, precision, stream):
-    from problems import continuity_cfg, sample
+    from problems import sample
     insts, tds, u0s = [], [], []
-    for seed in SEEDS:
-        for th in THETAS:
-            pb = continuity_cfg(seed, M, N_TH, th, P_STRETCH, T_END, K_LEVELS, L_TIME)
-            md = pdk.mesh_desc(M, N_TH, pdk.MESH_SINE, P_STRETCH)
-            data = sample(pb, *pdk.mesh_coords(md))
-            inst = pdk.Instance(md, data, precision, stream=stream)
-            insts.append(inst)
-            u0s.append(pdk.ring_vector(data["u0_origin"], data["u0_grid"]))
-            tds.append((th, pb))
+    for seed, th, pb in cfg2_batch():
+        md = pdk.mesh_desc(M, N_TH, pdk.MESH_SINE, P_STRETCH)
+        data = sample(pb, *pdk.mesh_coords(md))
+        inst = pdk.Instance(md, data, precision, stream=stream)
+        insts.append(inst)
+        u0s.append(pdk.ring_vector(data["u0_origin"], data["u0_grid"]))
+        tds.append((th, pb))
     return insts, tds, u0s
 
 
@@ -132,8 +154,7 @@ def main():
     pdk.solve_batch(refs_insts, time_descs(pdk, tds, 1e-13))
     refs = [i.solution() for i in refs_insts]
     # GPU state after the oracle's sample levels (instance 0), for the sampled parity
-    from oracle import time_levels
-    t_all = time_levels(T_END, K_LEVELS, 1, L_TIME)
+    t_all = pdk.time_levels(pdk.time_desc(THETAS[0], K_LEVELS, T_END, pdk.TIME_SINE, L_TIME))
     inst0 = refs_insts[0]
     inst0.set_solution(u0s[0], 0.0)
     inst0.solve(pdk.time_desc(THETAS[0], args.oracle_levels, table=t_all[:args.oracle_levels + 1],
@@ -166,9 +187,9 @@ def main():
         errs_max.append(float(np.max(np.abs(x - ref)) / np.max(np.abs(ref))))
     valid = max(errs_l2) <= 1e-8
 
-    # roofline of the dominant kernel family: one more step of the same
-    # workload with every launch bracketed by HIP events on its stream (the
-    # timed steps replay captured graphs, where per-launch events cannot go)
+    # roofline of the dominant kernel: one more step of the same workload
+    # with every launch stamped by a start and a stop event of its own
+    # dispatch (the timed steps replay captured graphs, which carry none)
     reset(insts, u0s)
     torch.cuda.synchronize()
     pdk.kernel_timing(True, reset=True)
@@ -181,24 +202,23 @@ def main():
     iters = [sum(s["iters"] for s in st) for st in pstats]      # per instance
     inst_cells = [i.N for i in insts]
     cell_iters = sum(c * it for c, it in zip(inst_cells, iters))
-    fam_bytes = {
-        "sten_v": cell_iters * bytes_per_cell("sten_v", w),
-        "sten_t": cell_iters * bytes_per_cell("sten_t", w),
-        "rad": 2 * cell_iters * bytes_per_cell("rad", w),
-        "ang": 2 * cell_iters * bytes_per_cell("ang", w),
-        "update": cell_iters * bytes_per_cell("update", w),
-    }
+    fam_bytes = {f: cell_iters * bytes_per_cell(f, w) for f in KERNEL_NAMES}
     dom = max(fam_bytes, key=lambda f: kms[f])
     achieved = fam_bytes[dom] / (kms[dom] / 1e3) / 1e9
+    traffic = None
+    if w == 8 and kernel_source_sha1() == TRAFFIC_SOURCE_SHA1:
+        traffic = round(TRAFFIC_B_PER_CELL[dom] * cell_iters / max(1, kcnt[dom]))
     roofline = {
-        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
         "launches": int(kcnt[dom]), "avg_launch_us": round(1e3 * kms[dom] / max(1, kcnt[dom]), 2),
         "bytes_per_launch": round(fam_bytes[dom] / max(1, kcnt[dom])),
-        "family_gbs": {f: round(fam_bytes[f] / (kms[f] / 1e3) / 1e9, 1) for f in fam_bytes if kms[f] > 0},
+        "kernel_gbs": {f: round(fam_bytes[f] / (kms[f] / 1e3) / 1e9, 1) for f in fam_bytes if kms[f] > 0},
+        "kernel_avg_us": {f: round(1e3 * kms[f] / kcnt[f], 2) for f in kms if kcnt[f] > 0},
         "kernel_ms": {k: round(v, 2) for k, v in kms.items()},
         "profiled_step_ms": round(prof_ms, 1),
-        "measured_on": "an extra step with per-launch HIP events (plain launches)",
+        "measured_on": "an extra step, each launch stamped by its own start/stop events",
     }
 
     out = {

@@ -171,6 +171,14 @@ typedef struct {
 int pd_mesh_coords(const pd_mesh_desc *mesh, double *r_nodes, double *r_faces,
                    double *th_nodes, double *th_faces);
 
+/* The time levels t_0..t_K (K+1 values, host buffer owned by the caller)
+ * that a solve with this descriptor advances through from t_start: the
+ * sine-stretched schedule t_k = t_start + T sin((k/K)^l π/2) (§3.1), the
+ * uniform one, or the explicit table (then t_0 must equal t_start).
+ * PD_EINVAL for K < 1, T <= 0, l <= 0 or levels that do not increase.
+ * Pure host computation.                                                  */
+int pd_time_levels(const pd_time_desc *time, double t_start, double *out);
+
 /* Creates an instance: builds the mesh, turns the sampled coefficients into
  * face conductances and drift coefficients, uploads everything to the
  * current HIP device, and sets the state to u0 at t = 0.  hip_stream may be
@@ -235,12 +243,16 @@ int pd_batch_poll(pd_batch *batch, uint64_t ticket, double *out, pd_step_stats *
 int pd_batch_destroy(pd_batch *batch);
 
 /* Kernel timing (diagnostics).  While enabled, every kernel launch of the
- * solver is bracketed by HIP events on its stream and its duration is
- * added to its family's total (families PD_KF_*; a level is synchronised
- * after it ends so the events can be read).  total_ms / launches (PD_KF_N
- * entries each, may be NULL) receive the totals since the last reset.    */
-enum { PD_KF_BEGIN = 0, PD_KF_FACTOR = 1, PD_KF_RAD = 2, PD_KF_ANG = 3, PD_KF_STEN_V = 4,
-       PD_KF_STEN_T = 5, PD_KF_UPDATE = 6, PD_KF_REFINE = 7, PD_KF_CONTROL = 8, PD_KF_N = 9 };
+ * solver goes through hipExtLaunchKernel with a start and a stop event that
+ * the dispatch itself stamps, so each launch's execution time (no launch
+ * gaps) is added to its family's total (families PD_KF_*: one per kernel of
+ * the Krylov cycle; a level is synchronised after it ends so the events can
+ * be read, and captured graphs are not used meanwhile).  total_ms /
+ * launches (PD_KF_N entries each, may be NULL) receive the totals since the
+ * last reset.                                                             */
+enum { PD_KF_BEGIN = 0, PD_KF_FACTOR = 1, PD_KF_RAD_P = 2, PD_KF_ANG_P = 3, PD_KF_STEN_V = 4,
+       PD_KF_RAD_S = 5, PD_KF_ANG_S = 6, PD_KF_STEN_T = 7, PD_KF_UPDATE = 8, PD_KF_REFINE = 9,
+       PD_KF_CONTROL = 10, PD_KF_N = 11 };
 int pd_kernel_timing(int32_t enable, int32_t reset, double *total_ms, int64_t *launches);
 
 const char *pd_last_error(void);

@@ -390,7 +390,6 @@ int build_time_table(const pd_time_desc *td, double t_start, std::vector<double>
 
 struct EventTimer : pd::KTimer {
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<int, hipEvent_t>> open;
   struct Rec { int f; hipEvent_t a, b; };
   std::vector<Rec> pending;
   double total_ms[PD_KF_N] = {};
@@ -405,18 +404,18 @@ struct EventTimer : pd::KTimer {
     pool.pop_back();
     return e;
   }
-  void mark(int f, bool start, hipStream_t s) override {
-    hipEvent_t e = take();
-    if (!e) return;
-    (void)hipEventRecord(e, s);
-    if (start) {
-      open.push_back({f, e});
-    } else if (!open.empty() && open.back().first == f) {
-      pending.push_back({f, open.back().second, e});
-      open.pop_back();
-    } else {
-      pool.push_back(e);
+  bool pair(int f, hipEvent_t *a, hipEvent_t *b) override {
+    hipEvent_t e0 = take();
+    if (!e0) return false;
+    hipEvent_t e1 = take();
+    if (!e1) {
+      pool.push_back(e0);
+      return false;
     }
+    pending.push_back({f, e0, e1});
+    *a = e0;
+    *b = e1;
+    return true;
   }
   // Reads every finished pair (the caller has synchronised the stream).
   void harvest() {
@@ -712,6 +711,19 @@ int solve_many(std::vector<pd_instance *> const &insts, std::vector<const pd_tim
 extern "C" {
 
 const char *pd_last_error(void) { return g_err.c_str(); }
+
+int pd_time_levels(const pd_time_desc *td, double t_start, double *out) {
+  try {
+    if (!out) return fail(PD_EINVAL, "output buffer is NULL");
+    std::vector<double> t;
+    int rc = build_time_table(td, t_start, t);
+    if (rc) return rc;
+    std::copy(t.begin(), t.end(), out);
+    return PD_OK;
+  } catch (...) {
+    return fail(PD_EINVAL, "unexpected host exception");
+  }
+}
 
 int pd_mesh_coords(const pd_mesh_desc *mesh, double *r_nodes, double *r_faces, double *th_nodes,
                    double *th_faces) {

@@ -46,6 +46,8 @@
 
 #include "pd_device.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 #define GAS __attribute__((address_space(1)))
@@ -1383,26 +1385,25 @@ KTimer *g_timer = nullptr;
 
 static inline dim3 g1(int n) { return dim3((unsigned)n); }
 
-struct Mark {
-  int f;
-  hipStream_t s;
-  Mark(int fam, hipStream_t st) : f(fam), s(st) {
-    if (g_timer) g_timer->mark(f, true, s);
-  }
-  ~Mark() {
-    if (g_timer) g_timer->mark(f, false, s);
-  }
-};
-enum { KF_BEGIN = 0, KF_FACTOR = 1, KF_RAD = 2, KF_ANG = 3, KF_STEN_V = 4, KF_STEN_T = 5,
-       KF_UPDATE = 6, KF_REFINE = 7, KF_CONTROL = 8 };
+// Launches a kernel; while kernel timing is on, through hipExtLaunchKernel
+// with a pair of events that the dispatch itself stamps.
+template <typename... KArgs, typename... Args>
+static inline void go(int fam, void (*k)(KArgs...), dim3 grid, dim3 block, hipStream_t s,
+                      Args... args) {
+  hipEvent_t a, b;
+  if (g_timer && g_timer->pair(fam, &a, &b))
+    hipExtLaunchKernelGGL(k, grid, block, 0, s, a, b, 0, args...);
+  else
+    k<<<grid, block, 0, s>>>(args...);
+}
+enum { KF_BEGIN = 0, KF_FACTOR = 1, KF_RAD_P = 2, KF_ANG_P = 3, KF_STEN_V = 4, KF_RAD_S = 5,
+       KF_ANG_S = 6, KF_STEN_T = 7, KF_UPDATE = 8, KF_REFINE = 9, KF_CONTROL = 10 };
 
 void launch_level_begin(const LaunchSet &L, hipStream_t s) {
-  Mark mk(KF_CONTROL, s);
-  k_level_begin<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
+  go(KF_CONTROL, k_level_begin, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
 }
 void launch_level_end(const LaunchSet &L, hipStream_t s) {
-  Mark mk(KF_CONTROL, s);
-  k_level_end<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
+  go(KF_CONTROL, k_level_end, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
 }
 // Register-array length of the segmented sweeps: the smallest of 4, 8, 16,
 // 32 that holds the longest segment of the batch.
@@ -1417,41 +1418,42 @@ static inline int seg_len(int b) { return b <= 4 ? 4 : (b <= 8 ? 8 : (b <= 16 ? 
   }
 
 void launch_factor(const LaunchSet &L, hipStream_t s) {
-  Mark mk(KF_FACTOR, s);
-  if (L.nb_rad) k_fact_rad<<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad);
+  if (L.nb_rad) go(KF_FACTOR, k_fact_rad, g1(L.nb_rad), dim3(PD_RAD_THREADS), s, L.insts, L.map_rad);
   if (L.nb_ang)
-    PD_DISPATCH_BM(L.max_bang, (k_fact_ang<BM><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang)));
+    PD_DISPATCH_BM(L.max_bang, (go(KF_FACTOR, k_fact_ang<BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang)));
 }
 void launch_begin(const LaunchSet &L, hipStream_t s) {
-  Mark mk(KF_BEGIN, s);
-  k_sten<double, SM_BEGIN><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr);
+  go(KF_BEGIN, k_sten<double, SM_BEGIN>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
+     (const double *)nullptr, (double *)nullptr);
 }
 
 template <typename T, int MODE>
 static void rad(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
-  PD_DISPATCH_BM(L.max_brad, (k_rad<T, MODE, BM><<<g1(L.nb_rad), PD_RAD_THREADS, 0, s>>>(L.insts, L.map_rad, in, out)));
+  PD_DISPATCH_BM(L.max_brad, (go(MODE == RM_S ? KF_RAD_S : KF_RAD_P, k_rad<T, MODE, BM>, g1(L.nb_rad), dim3(PD_RAD_THREADS), s, L.insts, L.map_rad, in, out)));
 }
 template <typename T, int MODE>
 static void ang(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
-  PD_DISPATCH_BM(L.max_bang, (k_ang<T, MODE, BM><<<g1(L.nb_ang), 256, 0, s>>>(L.insts, L.map_ang, in, out)));
+  PD_DISPATCH_BM(L.max_bang, (go(MODE == AM_S ? KF_ANG_S : KF_ANG_P, k_ang<T, MODE, BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang, in, out)));
+}
+template <typename T, int MODE>
+static void sten(int fam, const LaunchSet &L, hipStream_t s) {
+  go(fam, k_sten<T, MODE>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
+     (const T *)nullptr, (T *)nullptr);
 }
 
 template <typename T>
 static void cycle_t(const LaunchSet &L, hipStream_t s) {
-  { Mark mk(KF_RAD, s); rad<T, RM_P>(L, s); }
-  { Mark mk(KF_ANG, s); ang<T, AM_P>(L, s); }
-  { Mark mk(KF_STEN_V, s); k_sten<T, SM_V><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr); }
-  { Mark mk(KF_RAD, s); rad<T, RM_S>(L, s); }
-  { Mark mk(KF_ANG, s); ang<T, AM_S>(L, s); }
-  { Mark mk(KF_STEN_T, s); k_sten<T, SM_T><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr); }
-  { Mark mk(KF_UPDATE, s); k_elem_x<T><<<g1(L.nb_elem), 256, 0, s>>>(L.insts, L.map_elem); }
+  rad<T, RM_P>(L, s);
+  ang<T, AM_P>(L, s);
+  sten<T, SM_V>(KF_STEN_V, L, s);
+  rad<T, RM_S>(L, s);
+  ang<T, AM_S>(L, s);
+  sten<T, SM_T>(KF_STEN_T, L, s);
+  go(KF_UPDATE, k_elem_x<T>, g1(L.nb_elem), dim3(256), s, L.insts, L.map_elem);
 }
 
 void launch_cycle(const LaunchSet &L, hipStream_t s) {
-  if (L.mixed_any) {
-    Mark mk(KF_REFINE, s);
-    k_sten<float, SM_UR><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, 0, 0, nullptr, nullptr);
-  }
+  if (L.mixed_any) sten<float, SM_UR>(KF_REFINE, L, s);
   if (L.mixed_any && !L.fp64_any) {
     cycle_t<float>(L, s);
   } else if (!L.mixed_any) {
@@ -1466,21 +1468,22 @@ void launch_cycle(const LaunchSet &L, hipStream_t s) {
 
 void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void *y, int fp32,
                   hipStream_t s) {
+  const dim3 go_orig((L.ninst + 63) / 64);
   if (fp32) {
-    k_sten<float, SM_APPLY><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, dt, th,
-                                                          (const float *)x, (float *)y);
-    k_apply_origin<float><<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst, dt, th,
-                                                             (const float *)x, (float *)y);
+    go(KF_CONTROL, k_sten<float, SM_APPLY>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, dt, th,
+       (const float *)x, (float *)y);
+    go(KF_CONTROL, k_apply_origin<float>, go_orig, dim3(64), s, L.insts, L.ninst, dt, th,
+       (const float *)x, (float *)y);
   } else {
-    k_sten<double, SM_APPLY><<<g1(L.nb_sten), 256, 0, s>>>(L.insts, L.map_sten, dt, th,
-                                                           (const double *)x, (double *)y);
-    k_apply_origin<double><<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst, dt, th,
-                                                              (const double *)x, (double *)y);
+    go(KF_CONTROL, k_sten<double, SM_APPLY>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, dt, th,
+       (const double *)x, (double *)y);
+    go(KF_CONTROL, k_apply_origin<double>, go_orig, dim3(64), s, L.insts, L.ninst, dt, th,
+       (const double *)x, (double *)y);
   }
 }
 
 void launch_begin_origin(const LaunchSet &L, hipStream_t s) {
-  k_begin_origin<<<(L.ninst + 63) / 64, 64, 0, s>>>(L.insts, L.ninst);
+  go(KF_BEGIN, k_begin_origin, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
 }
 
 void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,

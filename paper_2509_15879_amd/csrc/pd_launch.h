@@ -19,7 +19,10 @@ struct LaunchSet {
 
 // Optional per-family event timing of launches (diagnostics).
 struct KTimer {
-  virtual void mark(int family, bool start, hipStream_t s) = 0;
+  // Two events that the next launch of `family` stamps with its own start
+  // and end (hipExtLaunchKernel), so that their difference is the kernel's
+  // execution time alone.
+  virtual bool pair(int family, hipEvent_t *start, hipEvent_t *stop) = 0;
   virtual ~KTimer() {}
 };
 extern KTimer *g_timer;

@@ -63,12 +63,13 @@ class StepStats(C.Structure):
 
 
 # every entry point declared in include/polardisk.h
-EXPORTS = ("pd_mesh_coords", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
+EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
            "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
 
-KERNEL_FAMILIES = ("begin", "factor", "rad", "ang", "sten_v", "sten_t", "update", "refine", "control")
+KERNEL_FAMILIES = ("begin", "factor", "rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t",
+                   "update", "refine", "control")
 
 
 def _load():
@@ -79,6 +80,7 @@ def _load():
     P, I32, D, U64, SZ = C.c_void_p, C.c_int32, C.c_double, C.c_uint64, C.c_size_t
     sig = {
         "pd_mesh_coords": [C.POINTER(MeshDesc), P, P, P, P],
+        "pd_time_levels": [C.POINTER(TimeDesc), D, P],
         "pd_mesh_create": [C.POINTER(MeshDesc), C.POINTER(ProblemDesc), I32, P, C.POINTER(P)],
         "pd_scheme_step": [P, D, D, D, D, C.POINTER(StepStats)],
         "pd_solve_to_T": [P, C.POINTER(TimeDesc), P],
@@ -162,6 +164,13 @@ def time_desc(theta, K, T=None, t_kind=TIME_UNIFORM, l=1.0, table=None, tol=1e-1
         td.t_kind = TIME_TABLE
         td._keep = a
     return td
+
+
+def time_levels(td: TimeDesc, t_start=0.0):
+    """The K+1 time levels a solve with `td` advances through from t_start."""
+    out = np.empty(td.K + 1)
+    _check(lib.pd_time_levels(C.byref(td), float(t_start), _ptr(out)))
+    return out
 
 
 def problem_desc(data: dict, flux=0, bc=0):

@@ -1,0 +1,68 @@
+"""A short run of the benchmark workload for hardware-counter profiling.
+
+    python -m paper_2509_15879_amd.profile_workload [--levels L] [--copy-mib M]
+
+Advances the ten 256 x 512 continuity instances of the benchmark through the
+first L time levels with plain kernel launches (no captured graphs, so every
+dispatch is counted on its own), then copies an M MiB device buffer, filled
+and then pushed out of the caches, once with torch: a kernel that reads and
+writes exactly M MiB, against which the profiler's byte counters are
+calibrated.  Under rocprofv3 --pmc each pass
+takes seconds.
+"""
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--levels", type=int, default=2)
+    ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    args = ap.parse_args()
+    os.environ["PD_NO_GRAPH"] = "1"
+
+    import torch
+    from problems import sample
+    from problems.workloads import CFG2, cfg2_batch
+    from paper_2509_15879_amd import polardisk as pdk
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    prec = pdk.PD_MIXED if args.precision == "mixed" else pdk.PD_FP64
+    c = CFG2
+    insts, descs = [], []
+    for seed, th, pb in cfg2_batch():
+        md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
+        insts.append(pdk.Instance(md, sample(pb, *pdk.mesh_coords(md)), prec, stream=stream))
+        full = pdk.time_desc(th, c["K"], c["T"], pdk.TIME_SINE, c["l"], tol=4e-12)
+        descs.append(full)
+    print(f"[profile] {len(insts)} instances, {args.levels} levels", flush=True)
+    t = pdk.time_levels(descs[0])[:args.levels + 1]
+    descs = [pdk.time_desc(d.theta, args.levels, table=t, tol=4e-12) for d in descs]
+    stats = pdk.solve_batch(insts, descs)
+    torch.cuda.synchronize()
+    print("[profile] iterations per level:", [[s["iters"] for s in st] for st in stats], flush=True)
+    # calibration: fill a source, push it out of every cache by filling a
+    # buffer four times the size, then copy it once
+    n = args.copy_mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    evict = torch.full((4 * n,), 2.0, dtype=torch.float32, device="cuda")
+    del evict
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[profile] copied {args.copy_mib} MiB (last dispatch)", flush=True)
+    for i in insts:
+        i.close()
+
+
+if __name__ == "__main__":
+    main()

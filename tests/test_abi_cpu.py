@@ -61,3 +61,24 @@ def test_footprint_scales_with_cells():
     assert 3.5 < b / a < 4.5
     c = pdk.footprint(pdk.mesh_desc(256, 512), 1, pdk.PD_FP64)
     assert 150 * 131073 < c < 300 * 131073   # about 200 B per cell
+
+
+@pytest.mark.parametrize("kind,K,T,l", [(1, 100, 0.05, 1.5), (1, 7, 1.0, 1.0), (0, 40, 0.3, 1.0)])
+def test_time_levels_match_the_schedule(kind, K, T, l):
+    """The library's time levels equal the oracle's schedule t_k = T sin((k/K)^l π/2)
+    (or the uniform one), shifted by the start time."""
+    from paper_2509_15879_amd import polardisk as pdk
+    from oracle import time_levels
+    got = pdk.time_levels(pdk.time_desc(0.5, K, T, kind, l), t_start=0.0)
+    ref = time_levels(T, K, kind, l)
+    assert np.allclose(got, ref, rtol=1e-15, atol=1e-17) and got[-1] == T
+    shifted = pdk.time_levels(pdk.time_desc(0.5, K, T, kind, l), t_start=0.25)
+    assert np.allclose(shifted, 0.25 + ref, rtol=1e-15)
+
+
+def test_time_levels_errors():
+    from paper_2509_15879_amd import polardisk as pdk
+    with pytest.raises(pdk.PolarDiskError, match="T must be"):
+        pdk.time_levels(pdk.time_desc(0.5, 10, 0.0, pdk.TIME_SINE, 1.5))
+    with pytest.raises(pdk.PolarDiskError, match="increase"):
+        pdk.time_levels(pdk.time_desc(0.5, 2, table=[0.0, 0.2, 0.1]))
