@@ -17,9 +17,9 @@
 #include <stdint.h>
 
 #define PD_MAXSRC 4
-#define PD_RB 16          // rows per stencil tile (one wave = 64 columns x PD_RB rows)
-#define PD_STEN_WAVES 4   // tiles per stencil block
-#define PD_ELEM_PER_BLOCK 4096
+#define PD_RB 4           // rings per stencil wave (one wave = 64 columns x PD_RB rings)
+#define PD_STEN_WAVES 4   // waves per stencil block, stacked over consecutive rings
+#define PD_ELEM_PER_BLOCK 2048
 #define PD_RAD_THREADS 1024
 #define PD_RAD_BMAX 32    // max rows per radial segment held in registers
 #define PD_ANG_BMAX 32    // max angular nodes per lane held in registers

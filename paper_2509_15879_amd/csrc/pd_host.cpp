@@ -154,7 +154,7 @@ Tiling make_tiling(int m, int n) {
   Tiling t;
   t.ncg = (n + 63) / 64;
   t.nrg = (m + PD_RB - 1) / PD_RB;
-  t.nb_sten = (t.ncg * t.nrg + PD_STEN_WAVES - 1) / PD_STEN_WAVES;
+  t.nb_sten = t.ncg * ((t.nrg + PD_STEN_WAVES - 1) / PD_STEN_WAVES);
   const int N = m * n + 1;
   t.nb_elem = (N + PD_ELEM_PER_BLOCK - 1) / PD_ELEM_PER_BLOCK;
   // radial sweep and factorisation: 16 columns (one 128-byte line of FP64)
@@ -215,6 +215,7 @@ struct Carver {
 // Lays out every device array of an instance; a dry run only measures.
 void carve(pd_instance *I, Carver &c) {
   const int m = I->M.m, n = I->M.n, mn = m * n;
+  const int ma = m * 64 * I->T.bang;   // angular factors, ring stride 64*bang
   const int np = I->T.npad;
   const int ns = std::max(1, I->nsrc);
   PdInst &H = I->H;
@@ -234,7 +235,7 @@ void carve(pd_instance *I, Carver &c) {
   H.inv_diag32 = mixed ? c.take<float>(np) : nullptr;
   H.k32.inv_d = H.inv_diag32;
   H.rf_uinv = c.take<double>(mn);
-  H.af_uinv = c.take<double>(mn);
+  H.af_uinv = c.take<double>(ma);
   H.af_kappa = c.take<double>(m);
   H.af_alpha0 = c.take<double>(m);
   H.k64.gp_r = c.take<double>((size_t)(m + 1) * n);
@@ -243,9 +244,9 @@ void carve(pd_instance *I, Carver &c) {
   H.k64.gm_t = c.take<double>(mn);
   H.k64.rf_f = c.take<double>(mn);
   H.k64.rf_g = c.take<double>(mn);
-  H.k64.af_f = c.take<double>(mn);
-  H.k64.af_g = c.take<double>(mn);
-  H.k64.af_z = c.take<double>(mn);
+  H.k64.af_f = c.take<double>(ma);
+  H.k64.af_g = c.take<double>(ma);
+  H.k64.af_z = c.take<double>(ma);
   if (!mixed) {
     H.k64.r = c.take<double>(np);
     H.k64.rh = c.take<double>(np);
@@ -275,9 +276,9 @@ void carve(pd_instance *I, Carver &c) {
     H.k32.gm_t = c.take<float>(mn);
     H.k32.rf_f = c.take<float>(mn);
     H.k32.rf_g = c.take<float>(mn);
-    H.k32.af_f = c.take<float>(mn);
-    H.k32.af_g = c.take<float>(mn);
-    H.k32.af_z = c.take<float>(mn);
+    H.k32.af_f = c.take<float>(ma);
+    H.k32.af_g = c.take<float>(ma);
+    H.k32.af_z = c.take<float>(ma);
   }
   const int nbs = I->T.nb_sten;
   H.part_b = c.take<double>(4 * (size_t)nbs);
@@ -480,9 +481,15 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
     hv[q].n_active = P.n_active;
     P.L.mixed_any |= insts[q]->precision == PD_MIXED;
     P.L.fp64_any |= insts[q]->precision != PD_MIXED;
-    P.L.max_brad = std::max(P.L.max_brad, insts[q]->T.brad);
     P.L.max_bang = std::max(P.L.max_bang, insts[q]->T.bang);
   }
+  // radial sweeps: 512-thread blocks (32 segments per column, two blocks per
+  // CU) while every segment stays within 8 rows, else 1024 threads (64
+  // segments)
+  int mmax = 0;
+  for (auto *I : insts) mmax = std::max(mmax, I->M.m);
+  P.L.rad_threads = (mmax + 31) / 32 <= 8 ? 512 : 1024;
+  P.L.max_brad = (mmax + P.L.rad_threads / 16 - 1) / (P.L.rad_threads / 16);
   HIPCHK(hipMalloc(&P.L.insts, ninst * sizeof(PdInst)));
   P.bufs.push_back(P.L.insts);
   HIPCHK(hipMemcpyAsync(P.L.insts, hv.data(), ninst * sizeof(PdInst), hipMemcpyHostToDevice, s));

@@ -378,7 +378,10 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts
 // non-periodic T0 has diagonal 2 at row 0 and 1 + γ_{n-1} α_0 at row n-1;
 // z = T0^{-1} u and κ = 1/(1 + z_0 - α_0 z_{n-1}) are stored so that
 // x = y - κ (y_0 - α_0 y_{n-1}) z with y = T0^{-1} d.
-// One wave per ring; lane L owns the nodes [L*bang, (L+1)*bang).
+// One wave per ring; lane L owns the nodes [L*bang, (L+1)*bang).  The
+// multipliers, pivots and z of a ring are stored in the sweep's own order:
+// node L*bang + k at (i-1)*64*bang + 64*k + L (a ring stride of 64*bang),
+// so that the sweep reads them with coalesced loads.
 
 __device__ __forceinline__ void ang_coef(const PdInst &I, int i, int j, double th, double &al,
                                          double &ga) {
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
   const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
   if (i > m) return;                                  // whole wave exits together
   const double th = sc->theta;
-  const int row = (i - 1) * n;
+  const int frow = (i - 1) * 64 * B;   // ring i in the sweep's layout
   const int j0 = lane * B;
   const int cnt = max(0, min(B, n - j0));
   double a0, gl, tmp;
@@ -461,9 +464,9 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
       ul[k] = ui;
       fl[k] = al[k] * ui;
       gf[k] = ga[k] * ui;
-      uinv[row + j0 + k] = ui;
-      ff[row + j0 + k] = fl[k];
-      gg[row + j0 + k] = gf[k];
+      uinv[frow + 64 * k + lane] = ui;
+      ff[frow + 64 * k + lane] = fl[k];
+      gg[frow + 64 * k + lane] = gf[k];
       u_prev = u;
       cp = ga[k];
     }
@@ -518,12 +521,12 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
     if (k < cnt) {
       Q *= -gf[k];
       wl[k] += Q * Xin;
-      zz[row + j0 + k] = wl[k];
+      zz[frow + 64 * k + lane] = wl[k];
       if (j0 + k == n - 1) zlast = wl[k];
       if (I.mixed) {
-        G(I.k32.af_f)[row + j0 + k] = (float)fl[k];
-        G(I.k32.af_g)[row + j0 + k] = (float)gf[k];
-        G(I.k32.af_z)[row + j0 + k] = (float)wl[k];
+        G(I.k32.af_f)[frow + 64 * k + lane] = (float)fl[k];
+        G(I.k32.af_g)[frow + 64 * k + lane] = (float)gf[k];
+        G(I.k32.af_z)[frow + 64 * k + lane] = (float)wl[k];
       }
     }
   }
@@ -539,12 +542,23 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
 //
 // One wave owns 64 consecutive θ-columns and PD_RB consecutive rings and
 // marches outward in r, keeping the radial neighbours and the shared radial
-// faces in registers and fetching the next ring while it computes the
-// current one.  The θ-neighbours come from the adjacent lanes by cross-lane
-// permutes; the columns just outside the wave (including the periodic seam
-// j = n-1 <-> 0) are fetched for all of the tile's rings at once and handed
-// out row by row.  The origin row is a sum over ring 1, accumulated per
-// block and closed by the instance's last block.
+// faces in registers and fetching the next ring (stencil operands and the
+// epilogue's own operands) while it computes the current one.  A block
+// stacks PD_STEN_WAVES such waves on top of each other, so the rings one
+// wave reads beyond its own are mostly read by its neighbour in the same CU.
+// The θ-neighbours come from the adjacent lanes by cross-lane permutes; the
+// columns just outside the wave (including the periodic seam j = n-1 <-> 0)
+// are fetched for all of the tile's rings at once and handed out row by row.
+// The origin row is a sum over ring 1, left as a per-block partial.
+
+struct Nil {};
+struct Pre2 {
+  double a, b;
+};
+struct Pre3 {
+  double a, b, c;
+};
+__device__ __forceinline__ Nil no_pre(int) { return Nil{}; }
 
 struct TileGeo {
   int m, n, lane, j, jc, i0, i1, jl0, jr0;
@@ -569,7 +583,9 @@ __device__ __forceinline__ TileGeo tile_geo(int m, int n, int cg, int rg) {
   return g;
 }
 
-template <typename TF, typename TX, int NV, class Epi>
+// pre(idx) loads what the epilogue needs at node idx (one ring ahead);
+// epi(i, j, idx, x, Lx, pre) finishes node idx.
+template <typename TF, typename TX, int NV, class Pre, class Epi>
 __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__restrict__ gp_r,
                                           const GAS TF *__restrict__ gm_r,
                                           const GAS TF *__restrict__ gp_t,
@@ -579,7 +595,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
                                           const GAS double *__restrict__ inv_rw,
                                           const GAS double *__restrict__ inv_dth,
                                           const GAS double *__restrict__ bnode, double (&S0)[NV],
-                                          Epi &&epi) {
+                                          Pre &&pre, Epi &&epi) {
   const int m = g.m, n = g.n, jc = g.jc;
   const int i0 = g.i0, i1 = g.i1, nr = i1 - i0 + 1;
   const int orig = m * n;
@@ -607,10 +623,12 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
   double gpt = (double)gp_t[(i0 - 1) * n + jc], gmt = (double)gm_t[(i0 - 1) * n + jc];
   double bP = bnode ? bnode[(i0 - 1) * n + jc] : 0.0;
   double ivr = inv_rw[i0];
+  auto pc = pre((i0 - 1) * n + jc);
   for (int i = i0; i <= i1; ++i) {
     // prefetch ring i+1
     double nxa[NV], ngpo = 0.0, ngmo = 0.0, ngpt = 0.0, ngmt = 0.0, nb = 0.0, nivr = 0.0;
     const bool more = i < i1;
+    const auto pn = pre((more ? i : i - 1) * n + jc);
 #pragma unroll
     for (int v = 0; v < NV; ++v) nxa[v] = (more && i + 1 < m) ? (double)X[v][(i + 1) * n + jc] : 0.0;
     if (more) {
@@ -642,7 +660,8 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
       Lx[v] = ivV * fs + bP * xc[v];
       if (i == 1 && g.act) S0[v] += gpi * xb[v] - gmi * xc[v];
     }
-    if (g.act) epi(i, jc, row + jc, xc, Lx);
+    if (g.act) epi(i, jc, row + jc, xc, Lx, pc);
+    pc = pn;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       xb[v] = xc[v];
@@ -769,10 +788,11 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       sc->outer = sc->outer + 1;
     }
   }
+  // block mp.y: column group mp.y % ncg, waves stacked over row groups
   const int wave = threadIdx.x >> 6;
-  const int tile = mp.y * PD_STEN_WAVES + wave;
-  const bool wave_on = tile < I.ncg * I.nrg;
-  const int cg = wave_on ? tile % I.ncg : 0, rg = wave_on ? tile / I.ncg : 0;
+  const int rg0 = (mp.y / I.ncg) * PD_STEN_WAVES + wave;
+  const bool wave_on = rg0 < I.nrg;
+  const int cg = mp.y % I.ncg, rg = wave_on ? rg0 : 0;
   const int m = I.m, n = I.n;
   const KSet<TK> &KS = kset<TK>(I);
   const TileGeo geo = tile_geo(m, n, cg, rg);
@@ -785,8 +805,8 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     GAS TK *y = G(ay);
     if (wave_on)
       sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(ax), G(ax), inv_rw,
-                           inv_dth, bnode, S0,
-                           [&](int, int, int idx, const double *xc, const double *Lx) {
+                           inv_dth, bnode, S0, no_pre,
+                           [&](int, int, int idx, const double *xc, const double *Lx, Nil) {
                              y[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
                            });
     produce<1>(S0, I.part_a, I.nb_sten, mp.y);
@@ -811,7 +831,8 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (wave_on)
       sten_tile<double, double, 2>(
           geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk), G(ex ? xkm : xk),
-          inv_rw, inv_dth, bnode, S0, [&](int i, int j, int idx, const double *xc, const double *Lx) {
+          inv_rw, inv_dth, bnode, S0, no_pre,
+          [&](int i, int j, int idx, const double *xc, const double *Lx, Nil) {
             double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
             for (int q = 0; q < nsrc; ++q) b += cq[q] * gsrc[q * npad + idx];
             if (i == m) {
@@ -853,12 +874,13 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (wave_on)
       sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(xin), G(xin),
                            inv_rw, inv_dth, bnode, S0,
-                           [&](int, int, int idx, const double *xc, const double *Lx) {
-                             const double y = (inv_dt * xc[0] + th * Lx[0]) * (double)idg[idx];
+                           [&](int idx) { return Pre2{(double)idg[idx], (double)ot[idx]}; },
+                           [&](int, int, int idx, const double *xc, const double *Lx, Pre2 q) {
+                             const double y = (inv_dt * xc[0] + th * Lx[0]) * q.a;
                              const TK ys = (TK)y;
                              yo[idx] = ys;
                              const double yd = (double)ys;
-                             acc[0] += (double)ot[idx] * yd;
+                             acc[0] += q.b * yd;
                              acc[1] += yd * yd;
                            });
     if (MODE == SM_V) {
@@ -881,11 +903,12 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       sten_tile<double, float, 1>(geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t),
                                   G((const float *)I.k32.d), G((const float *)I.k32.d), inv_rw,
                                   inv_dth, bnode, S0,
-                                  [&](int, int, int idx, const double *xc, const double *Lx) {
-                                    const double r = rout[idx] - (inv_dt * xc[0] + th * Lx[0]);
-                                    const double rs = r * idg[idx];
+                                  [&](int idx) { return Pre3{rout[idx], idg[idx], xg[idx]}; },
+                                  [&](int, int, int idx, const double *xc, const double *Lx, Pre3 q) {
+                                    const double r = q.a - (inv_dt * xc[0] + th * Lx[0]);
+                                    const double rs = r * q.b;
                                     rout[idx] = r;
-                                    xg[idx] += xc[0];
+                                    xg[idx] = q.c + xc[0];
                                     r32[idx] = (float)rs;
                                     rh32[idx] = (float)rs;
                                     acc[0] += rs * rs;
@@ -926,13 +949,15 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
 // ------------------------------------------------------------ radial sweep
 //
 // w = (I + D^{-1}R)^{-1} y for every θ-column of an instance.  A block owns cw
-// consecutive columns; its 1024 threads split every column into nseg
-// segments of brad rows (lane = column within the block, segment = the rest
-// of the thread index).  Each thread runs the forward and backward
-// substitution of its segment locally, holding the segment in registers;
-// the segments are then joined by composing their affine maps across
-// segments through LDS, and each thread corrects its rows.  The origin row
-// passes through (unit diagonal).
+// (= 16) consecutive columns; its 1024 threads split every column into 64
+// segments of brad rows: thread t takes column t % 16 and segment t / 16, so
+// a wave holds 4 consecutive segments of 16 columns (four 128-byte row
+// pieces per load).  Every operand of a thread's rows is loaded at the start,
+// before the launch's partial sums are read.  Each thread runs the forward
+// and backward substitution of its segment in registers; the segments' affine
+// maps are joined by a scan over the 4 segments of a wave (lane shuffles),
+// then over the 16 waves of the block (wave totals through LDS), and each
+// thread corrects its rows.  The origin row passes through (unit diagonal).
 //
 // RM_P:  y = p = r + β (p - ω v)   (p = r on a (re)start; r̂ = r on a restart)
 // RM_S:  y = s = r - α v
@@ -940,108 +965,168 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
 
 enum { RM_P = 0, RM_S = 1, RM_PLAIN = 2 };
 
+template <int BM>
+struct RadRegs {
+  double a[BM], b[BM];          // P: r, p - ω v   S: r, v   PLAIN: x
+  double u[BM], f[BM], g[BM];   // pivot inverse and multipliers
+};
+
 template <typename T, int MODE, int BM>
-__device__ __forceinline__ void rad_body(int m, int n, int cw, int B, int nseg, int j, int c, int seg,
-                                         int cnt, bool origin_thread, double beta, double omega,
-                                         double alpha, bool first, bool reset,
-                                         const GAS T *__restrict__ r, GAS T *__restrict__ p,
-                                         const GAS T *__restrict__ v, GAS T *__restrict__ rh,
-                                         GAS T *__restrict__ s, const GAS T *__restrict__ pin,
-                                         GAS T *__restrict__ out,
+__device__ __forceinline__ void rad_load(int n, int j, int rb, int klast, double omega,
+                                         const GAS T *__restrict__ a, const GAS T *__restrict__ b,
+                                         const GAS T *__restrict__ c,
                                          const GAS double *__restrict__ uinv,
-                                         const GAS T *__restrict__ f, const GAS T *__restrict__ g) {
-  __shared__ double lds_a[PD_RAD_THREADS];
-  __shared__ double lds_b[PD_RAD_THREADS];
-  const int i_begin = seg * B;
-
-  // the sweep's right-hand side at idx; `own` says the row belongs to this
-  // thread (loads are clamped and always issued, stores only for own rows)
-  auto input = [&](int idx, bool own) -> double {
-    if (MODE == RM_P) {
-      const double rr = (double)r[idx];
-      const double pv = (double)p[idx], vv = (double)v[idx];
-      const double pp = first ? rr : rr + beta * (pv - omega * vv);
-      const T ps = (T)pp;
-      if (own) {
-        p[idx] = ps;
-        if (reset) rh[idx] = (T)rr;
-      }
-      return (double)ps;
-    } else if (MODE == RM_S) {
-      const double ss = (double)r[idx] - alpha * (double)v[idx];
-      const T sv = (T)ss;
-      if (own) s[idx] = sv;
-      return (double)sv;
-    } else {
-      return (double)pin[idx];
-    }
-  };
-
-  if (origin_thread) out[m * n] = (T)input(m * n, true);
-
-  // forward local pass: loads first (clamped rows, masked), then the recurrence
-  double wl[BM] = {}, fl[BM] = {};
-  // threads without rows (segment past row m, column past n) read row 0
-  const int klast = cnt > 0 ? cnt - 1 : 0;
-  const int rb = cnt > 0 ? i_begin : 0;
+                                         const GAS T *__restrict__ f, const GAS T *__restrict__ g,
+                                         RadRegs<BM> &R) {
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
+    // rows past the segment's end repeat its last row (clamped, always issued)
     const int idx = (rb + min(k, klast)) * n + j;
-    const double y = input(idx, k < cnt);
-    wl[k] = k < cnt ? uinv[idx] * y : 0.0;
-    fl[k] = k < cnt ? (double)f[idx] : 0.0;
+    R.a[k] = (double)a[idx];
+    if (MODE == RM_P) R.b[k] = (double)b[idx] - omega * (double)c[idx];
+    if (MODE == RM_S) R.b[k] = (double)b[idx];
+    R.u[k] = uinv[idx];
+    R.f[k] = (double)f[idx];
+  }
+}
+
+// The backward multipliers, loaded once the launch's partial sums are read
+// (they are first needed after the forward join, and holding them through
+// the closure of the p-sweep would cost registers).
+template <typename T, int BM>
+__device__ __forceinline__ void rad_load_g(int n, int j, int rb, int klast,
+                                           const GAS T *__restrict__ g, RadRegs<BM> &R) {
+#pragma unroll
+  for (int k = 0; k < BM; ++k) R.g[k] = (double)g[(rb + min(k, klast)) * n + j];
+}
+
+// Joins of the segments of a block's columns (NW waves, 4 segments of the
+// 16 columns per wave).  Forward: the value entering segment s from above is
+// the composition of the maps of segments 0..s-1 applied to 0; backward: of
+// the segments below s.  lane/16 is the segment within the wave.
+template <int NW>
+__device__ __forceinline__ double rad_join(Aff A, bool fwd, int c, int lane, int wave,
+                                           double (&lp)[NW][16], double (&le)[NW][16]) {
+  const int sub = lane >> 4;
+  // inclusive scan over the wave's 4 segments
+#pragma unroll
+  for (int d = 1; d < 4; d <<= 1) {
+    const Aff o = fwd ? Aff{__shfl_up(A.P, 16 * d, 64), __shfl_up(A.e, 16 * d, 64)}
+                      : Aff{__shfl_down(A.P, 16 * d, 64), __shfl_down(A.e, 16 * d, 64)};
+    if (fwd ? sub >= d : sub + d < 4) A = compose(A, o);
+  }
+  // the part of the wave before (forward) or after (backward) the segment
+  const Aff ex = fwd ? Aff{__shfl_up(A.P, 16, 64), __shfl_up(A.e, 16, 64)}
+                     : Aff{__shfl_down(A.P, 16, 64), __shfl_down(A.e, 16, 64)};
+  const bool edge = fwd ? sub == 0 : sub == 3;
+  if (sub == (fwd ? 3 : 0)) {
+    lp[wave][c] = A.P;
+    le[wave][c] = A.e;
+  }
+  __syncthreads();
+  double W = 0.0;
+  if (fwd) {
+    for (int w = 0; w < wave; ++w) W = lp[w][c] * W + le[w][c];
+  } else {
+    for (int w = NW - 1; w > wave; --w) W = lp[w][c] * W + le[w][c];
+  }
+  __syncthreads();   // the tables are reused by the next join
+  return edge ? W : ex.P * W + ex.e;
+}
+
+template <typename T, int MODE, int BM, int NT>
+__device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begin, int cnt,
+                                          bool origin_thread, double beta, double omega,
+                                          double alpha, bool first, bool reset, RadRegs<BM> &R,
+                                          const GAS T *__restrict__ r, GAS T *__restrict__ p,
+                                          const GAS T *__restrict__ v, GAS T *__restrict__ rh,
+                                          GAS T *__restrict__ s, const GAS T *__restrict__ pin,
+                                          GAS T *__restrict__ out) {
+  constexpr int NW = NT / 64;
+  __shared__ double lp[NW][16], le[NW][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  // RM_P: b = p - ω v, so that p = r + β b
+  auto input = [&](double a, double b) -> T {
+    if (MODE == RM_P) return (T)(first ? a : a + beta * b);
+    if (MODE == RM_S) return (T)(a - alpha * b);
+    return (T)a;
+  };
+  if (origin_thread) {
+    const int o = m * n;
+    if (MODE == RM_P) {
+      const T ps = input((double)r[o], (double)p[o] - omega * (double)v[o]);
+      p[o] = ps;
+      if (reset) rh[o] = r[o];
+      out[o] = ps;
+    } else if (MODE == RM_S) {
+      const T ss = input((double)r[o], (double)v[o]);
+      s[o] = ss;
+      out[o] = ss;
+    } else {
+      out[o] = pin[o];
+    }
+  }
+
+  // right-hand side of the sweep (stored in the Krylov vector it defines),
+  // then the local forward pass
+  double wl[BM];
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    const T ys = input(R.a[k], R.b[k]);
+    if (k < cnt) {
+      const int idx = (i_begin + k) * n + j;
+      if (MODE == RM_P) {
+        p[idx] = ys;
+        if (reset) rh[idx] = (T)R.a[k];
+      } else if (MODE == RM_S) {
+        s[idx] = ys;
+      }
+    }
+    wl[k] = k < cnt ? R.u[k] * (double)ys : 0.0;
+    if (k >= cnt) R.f[k] = 0.0;   // the forward fix-up then leaves such rows alone
   }
   Aff A{1.0, 0.0};
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     if (k < cnt) {
-      A.e = wl[k] - fl[k] * A.e;
-      A.P *= -fl[k];
+      A.e = wl[k] - R.f[k] * A.e;
+      A.P *= -R.f[k];
       wl[k] = A.e;
     }
   }
-  lds_a[threadIdx.x] = A.e;
-  lds_b[threadIdx.x] = A.P;
-  __syncthreads();
-  double Win = 0.0;
-  for (int s2 = 0; s2 < seg; ++s2) Win = lds_b[s2 * cw + c] * Win + lds_a[s2 * cw + c];
-  __syncthreads();
-  // fix-up of the forward pass, then the local backward pass
+  const double Win = rad_join<NW>(A, true, c, lane, wave, lp, le);
   double P = 1.0;
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
-    P *= -fl[k];
+    P *= -R.f[k];
     wl[k] += P * Win;
-    const double gv = (double)g[(rb + min(k, klast)) * n + j];
-    fl[k] = k < cnt ? gv : 0.0;                    // reuse the registers for g
   }
   Aff Bk{1.0, 0.0};
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      Bk.e = wl[k] - fl[k] * Bk.e;
-      Bk.P *= -fl[k];
+      Bk.e = wl[k] - R.g[k] * Bk.e;
+      Bk.P *= -R.g[k];
       wl[k] = Bk.e;
     }
   }
-  lds_a[threadIdx.x] = Bk.e;
-  lds_b[threadIdx.x] = Bk.P;
-  __syncthreads();
-  double Xin = 0.0;
-  for (int s2 = nseg - 1; s2 > seg; --s2) Xin = lds_b[s2 * cw + c] * Xin + lds_a[s2 * cw + c];
+  const double Xin = rad_join<NW>(Bk, false, c, lane, wave, lp, le);
   double Q = 1.0;
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      Q *= -fl[k];
+      Q *= -R.g[k];
       out[(i_begin + k) * n + j] = (T)(wl[k] + Q * Xin);
     }
   }
 }
 
-template <typename T, int MODE, int BM>
-__global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, const int2 *map,
-                                                        const T *plain_in, T *plain_out) {
+// NT threads per block (512 or 1024): 16 columns x NT/16 segments; at most
+// 128 VGPRs, so that two 512-thread blocks share a CU.
+template <typename T, int MODE, int BM, int NT>
+__global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *map,
+                                                      const T *plain_in, T *plain_out) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
@@ -1050,8 +1135,28 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
     if (block_status(sc) != ST_ACTIVE) return;   // the p- and s-sweeps change the status
   }
   const KSet<T> &KS = kset<T>(I);
-  const int m = I.m, n = I.n, orig = m * n, cw = I.cw, B = I.brad;
+  constexpr int cw = 16, NSEG = NT / 16;
+  const int m = I.m, n = I.n, orig = m * n, B = (m + NSEG - 1) / NSEG;
   const bool b0 = mp.y == 0 && threadIdx.x == 0;
+  // this thread's rows: column j, segment seg (threads without rows read row 0)
+  const int c = threadIdx.x % cw, seg = threadIdx.x / cw;
+  const int j = mp.y * cw + c;
+  const bool act = j < n;
+  const int cnt = act ? max(0, min(B, m - seg * B)) : 0;
+  const int jj = act ? j : 0;
+  const int rb = cnt > 0 ? seg * B : 0, klast = cnt > 0 ? cnt - 1 : 0;
+  RadRegs<BM> R;
+  auto load = [&]() {
+    const T *a = (MODE == RM_PLAIN) ? plain_in : KS.r;
+    const T *bb = (MODE == RM_P) ? KS.p : KS.v;
+    rad_load<T, MODE, BM>(n, jj, rb, klast, sc->omega, G(a), G((const T *)bb), G((const T *)KS.v),
+                          G(I.rf_uinv), G((const T *)KS.rf_f), G((const T *)KS.rf_g), R);
+  };
+  // the loads are issued before the partial sums are read, except on the
+  // rare closures of a level begin or a refinement, whose origin arithmetic
+  // would otherwise hold registers together with them
+  const int pend = (MODE == RM_P) ? sc->pend : PEND_UPDATE;
+  if (pend == PEND_UPDATE) load();
   double beta = 0.0, omega = 0.0, alpha = 0.0;
   bool first = false, reset = false;
   if (MODE == RM_P) {
@@ -1059,7 +1164,6 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
     // an update step (ρ = r̂·r, convergence, restart, β)
     int st = ST_ACTIVE;
     double rho = 0.0, rel = -1.0;
-    const int pend = sc->pend;
     if (pend == PEND_BEGIN) {
       double tot[4];
       consume<4>(I.part_b, I.nb_sten, tot);
@@ -1154,27 +1258,34 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_rad(const PdInst *insts, con
     }
     if (st != ST_ACTIVE) return;
   }
-  const int c = threadIdx.x % cw, seg = threadIdx.x / cw;
-  const int j = mp.y * cw + c;
-  const bool act = j < n;
-  const int cnt = act ? max(0, min(B, m - seg * B)) : 0;
+  if (pend != PEND_UPDATE) load();
+  rad_load_g<T, BM>(n, jj, rb, klast, G((const T *)KS.rf_g), R);
   T *out = (MODE == RM_PLAIN) ? plain_out : KS.w;
-  rad_body<T, MODE, BM>(m, n, cw, B, I.nseg, act ? j : 0, c, seg, cnt, b0, beta, omega, alpha, first,
-                        reset, G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s),
-                        G(plain_in), G(out), G(I.rf_uinv), G((const T *)KS.rf_f),
-                        G((const T *)KS.rf_g));
+  rad_solve<T, MODE, BM, NT>(m, n, jj, c, seg * B, cnt, b0, beta, omega, alpha, first, reset, R,
+                         G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s),
+                         G(plain_in), G(out));
 }
 
 // ------------------------------------------------------------ angular sweep
 //
 // z = (I + D^{-1}Θ)^{-1} w for every ring: one wave per ring, lane L owns
-// the bang consecutive nodes j in [L*bang, (L+1)*bang).  Local substitution
-// in registers, then the lanes' affine maps are composed by a Kogge-Stone
-// scan across the wave (prefix for the forward, suffix for the backward
-// substitution), then the Sherman-Morrison correction closes the period.
+// the bang consecutive nodes j in [L*bang, (L+1)*bang).  The ring's input is
+// read with coalesced loads and handed to the owning lanes through LDS (and
+// the result back the same way); the factors are stored in the lanes' order
+// and read directly.  Local substitution in registers, then the lanes' affine
+// maps are composed by a Kogge-Stone scan across the wave (prefix for the
+// forward, suffix for the backward substitution), then the Sherman-Morrison
+// correction closes the period.
 //
 // AM_P: input w, output p̂ (origin copied);  AM_S: output ŝ;  AM_PLAIN: diagnostic.
 enum { AM_P = 0, AM_S = 1, AM_PLAIN = 2 };
+
+// Orders the LDS accesses of one wave (its lanes exchange values through LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T, int BM>
 __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, double kappa,
@@ -1182,22 +1293,47 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
                                          GAS T *__restrict__ out,
                                          const GAS double *__restrict__ uinv,
                                          const GAS T *__restrict__ f, const GAS T *__restrict__ g,
-                                         const GAS T *__restrict__ z) {
-  const int row = (i - 1) * n;
+                                         const GAS T *__restrict__ z, double *tb) {
+  const int row = (i - 1) * n, frow = (i - 1) * 64 * B;
   const int j0 = lane * B;
   const int cnt = max(0, min(B, n - j0));
   if (i == 1 && lane == 0) out[m * n] = in[m * n];
 
-  double wl[BM] = {}, fl[BM] = {};
-  const int klast = cnt > 0 ? cnt - 1 : 0;
-  const int jb = cnt > 0 ? j0 : 0;
+  // every load first: the ring's input (coalesced, node lane + 64k) and this
+  // lane's factors (node j0 + k, stored at 64k + lane)
+  double xin[BM], ul[BM], fl[BM], gl[BM], zl[BM];
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
-    const int idx = row + jb + min(k, klast);
-    const double wv = uinv[idx] * (double)in[idx], fv = (double)f[idx];
-    wl[k] = k < cnt ? wv : 0.0;
-    fl[k] = k < cnt ? fv : 0.0;
+    if (k < B) {
+      const int jn = min(lane + 64 * k, n - 1);
+      const int fi = frow + 64 * k + lane;
+      xin[k] = (double)in[row + jn];
+      ul[k] = uinv[fi];
+      fl[k] = (double)f[fi];
+      gl[k] = (double)g[fi];
+      zl[k] = (double)z[fi];
+    } else {
+      xin[k] = ul[k] = fl[k] = gl[k] = zl[k] = 0.0;
+    }
   }
+  // node j sits at j + j/B in LDS: lane L's nodes are contiguous, one gap after each lane
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    const int j = lane + 64 * k;
+    if (k < B && j < n) tb[j + j / B] = xin[k];
+  }
+  wave_sync();
+  double wl[BM];
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    const bool own = k < cnt;
+    wl[k] = own ? ul[k] * tb[lane * (B + 1) + k] : 0.0;
+    fl[k] = own ? fl[k] : 0.0;
+    gl[k] = own ? gl[k] : 0.0;
+    zl[k] = own ? zl[k] : 0.0;
+  }
+  wave_sync();
+
   Aff A{1.0, 0.0};
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
@@ -1215,22 +1351,17 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
   double Win = __shfl_up(A.e, 1, 64);
   if (lane == 0) Win = 0.0;
   double P = 1.0;
-  double zl[BM] = {};
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     P *= -fl[k];
     wl[k] += P * Win;
-    const int idx = row + jb + min(k, klast);
-    const double gv = (double)g[idx], zv = (double)z[idx];
-    fl[k] = k < cnt ? gv : 0.0;
-    zl[k] = k < cnt ? zv : 0.0;
   }
   Aff Bk{1.0, 0.0};
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      Bk.e = wl[k] - fl[k] * Bk.e;
-      Bk.P *= -fl[k];
+      Bk.e = wl[k] - gl[k] * Bk.e;
+      Bk.P *= -gl[k];
       wl[k] = Bk.e;
     }
   }
@@ -1245,7 +1376,7 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      Q *= -fl[k];
+      Q *= -gl[k];
       wl[k] += Q * Xin;
       if (j0 + k == n - 1) ylast = wl[k];
     }
@@ -1253,9 +1384,15 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
   const double y0 = __shfl(wl[0], 0, 64);
   const double yl = __shfl(ylast, (n - 1) / B, 64);
   const double sfac = kappa * (y0 - alpha0 * yl);
+  // back to node order through LDS, then coalesced stores
+#pragma unroll
+  for (int k = 0; k < BM; ++k)
+    if (k < cnt) tb[lane * (B + 1) + k] = wl[k] - sfac * zl[k];
+  wave_sync();
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
-    if (k < cnt) out[row + j0 + k] = (T)(wl[k] - sfac * zl[k]);
+    const int j = lane + 64 * k;
+    if (k < B && j < n) out[row + j] = (T)tb[j + j / B];
   }
 }
 
@@ -1281,10 +1418,12 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
     sc->pend = PEND_UPDATE;
   }
   if (i > m) return;                                 // whole wave exits together
+  __shared__ double tbuf[4][64 * (BM + 1)];          // one exchange buffer per wave
   const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
   T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
   ang_body<T, BM>(m, n, I.bang, i, lane, I.af_kappa[i - 1], I.af_alpha0[i - 1], G(in), G(out),
-              G(I.af_uinv), G((const T *)KS.af_f), G((const T *)KS.af_g), G((const T *)KS.af_z));
+                  G(I.af_uinv), G((const T *)KS.af_f), G((const T *)KS.af_g), G((const T *)KS.af_z),
+                  tbuf[threadIdx.x >> 6]);
 }
 
 // ------------------------------------------------------------ update kernel
@@ -1293,38 +1432,48 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
 // r = s - ω t, partials r̂·r and r·r; the last block decides convergence,
 // breakdown or restart for the instance.
 
-template <typename T>
-__device__ __forceinline__ void elem_body(int N, int base, double al, double om, bool setx, int orig,
-                                          double t0,
-                                          const GAS T *__restrict__ ph, const GAS T *__restrict__ sh,
-                                          const GAS T *__restrict__ s, const GAS T *__restrict__ t,
-                                          const GAS T *__restrict__ rh, GAS T *__restrict__ x,
-                                          GAS T *__restrict__ r, double (&acc)[2]) {
-  constexpr int E = PD_ELEM_PER_BLOCK / 256;
-  double vph[E], vsh[E], vs[E], vt[E], vrh[E], vx[E];
-  // clamped indices: every load is issued unconditionally, tails masked
+template <int E>
+struct ElemRegs {
+  double ph[E], sh[E], s[E], t[E], rh[E], x[E];
+};
+
+// Every operand of the thread's E unknowns (clamped indices: every load is
+// issued unconditionally, tails masked later).
+template <typename T, int E>
+__device__ __forceinline__ void elem_load(int N, int base, const GAS T *__restrict__ ph,
+                                          const GAS T *__restrict__ sh, const GAS T *__restrict__ s,
+                                          const GAS T *__restrict__ t, const GAS T *__restrict__ rh,
+                                          const GAS T *__restrict__ x, ElemRegs<E> &R) {
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int idx = base + k * 256 + threadIdx.x;
     const int li = idx < N ? idx : N - 1;
-    vph[k] = (double)ph[li];
-    vsh[k] = (double)sh[li];
-    vs[k] = (double)s[li];
-    vt[k] = (idx == orig) ? t0 : (double)t[li];
-    vrh[k] = (double)rh[li];
-    vx[k] = (double)x[li];
+    R.ph[k] = (double)ph[li];
+    R.sh[k] = (double)sh[li];
+    R.s[k] = (double)s[li];
+    R.t[k] = (double)t[li];
+    R.rh[k] = (double)rh[li];
+    R.x[k] = (double)x[li];
   }
+}
+
+template <typename T, int E>
+__device__ __forceinline__ void elem_update(int N, int base, double al, double om, bool setx,
+                                            int orig, double t0, const ElemRegs<E> &R,
+                                            GAS T *__restrict__ x, GAS T *__restrict__ r,
+                                            double (&acc)[2]) {
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int idx = base + k * 256 + threadIdx.x;
-    const double xv = setx ? 0.0 : vx[k];
-    const T xs = (T)(xv + al * vph[k] + om * vsh[k]);
-    const T rs = (T)(vs[k] - om * vt[k]);
+    const double tv = (idx == orig) ? t0 : R.t[k];
+    const double xv = setx ? 0.0 : R.x[k];
+    const T xs = (T)(xv + al * R.ph[k] + om * R.sh[k]);
+    const T rs = (T)(R.s[k] - om * tv);
     const double rd = (double)rs;
     if (idx < N) {
       x[idx] = xs;
       r[idx] = rs;
-      acc[0] += vrh[k] * rd;
+      acc[0] += R.rh[k] * rd;
       acc[1] += rd * rd;
     }
   }
@@ -1332,6 +1481,7 @@ __device__ __forceinline__ void elem_body(int N, int base, double al, double om,
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 *map) {
+  constexpr int E = PD_ELEM_PER_BLOCK / 256;
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
@@ -1340,6 +1490,12 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   const KSet<T> &KS = kset<T>(I);
   const int orig = I.m * I.n;
   const bool b0 = mp.y == 0 && threadIdx.x == 0;
+  T *x = iterate_ptr<T>(I, sc);
+  const int base = mp.y * PD_ELEM_PER_BLOCK;
+  // the vectors first, then the partial sums of the t-stencil
+  ElemRegs<E> R;
+  elem_load<T, E>(orig + 1, base, G((const T *)KS.ph), G((const T *)KS.sh), G((const T *)KS.s),
+                  G((const T *)KS.t), G((const T *)KS.rh), G((const T *)x), R);
   // ω = (t·s)/(t·t), closing the t-stencil with its origin row
   double tot[3];
   consume<3>(I.part_t, I.nb_sten, tot);
@@ -1365,11 +1521,9 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
     if (st != ST_ACTIVE) finish_instance(I, sc, st);
   }
   if (st != ST_ACTIVE) return;
-  T *x = iterate_ptr<T>(I, sc);
   double acc[2] = {0.0, 0.0};
-  elem_body<T>(orig + 1, mp.y * PD_ELEM_PER_BLOCK, sc->alpha, om, I.mixed && sc->inner_first != 0,
-               orig, (double)t0, G((const T *)KS.ph), G((const T *)KS.sh), G((const T *)KS.s),
-               G((const T *)KS.t), G((const T *)KS.rh), G(x), G(KS.r), acc);
+  elem_update<T, E>(orig + 1, base, sc->alpha, om, I.mixed && sc->inner_first != 0, orig, (double)t0,
+                    R, G(x), G(KS.r), acc);
   produce<2>(acc, I.part_x, I.nb_elem, mp.y);
 }
 
@@ -1429,7 +1583,12 @@ void launch_begin(const LaunchSet &L, hipStream_t s) {
 
 template <typename T, int MODE>
 static void rad(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
-  PD_DISPATCH_BM(L.max_brad, (go(MODE == RM_S ? KF_RAD_S : KF_RAD_P, k_rad<T, MODE, BM>, g1(L.nb_rad), dim3(PD_RAD_THREADS), s, L.insts, L.map_rad, in, out)));
+  const int fam = MODE == RM_S ? KF_RAD_S : KF_RAD_P;
+  if (L.rad_threads == 512) {
+    PD_DISPATCH_BM(L.max_brad, (go(fam, k_rad<T, MODE, BM, 512>, g1(L.nb_rad), dim3(512), s, L.insts, L.map_rad, in, out)));
+  } else {
+    PD_DISPATCH_BM(L.max_brad, (go(fam, k_rad<T, MODE, BM, 1024>, g1(L.nb_rad), dim3(1024), s, L.insts, L.map_rad, in, out)));
+  }
 }
 template <typename T, int MODE>
 static void ang(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {

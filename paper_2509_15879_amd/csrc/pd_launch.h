@@ -15,6 +15,7 @@ struct LaunchSet {
   int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0, nb_frad = 0, nb_fang = 0;
   int mixed_any = 0, fp64_any = 0;
   int max_brad = 1, max_bang = 1;   // longest radial segment / angular lane span
+  int rad_threads = 1024;           // block size of the radial sweeps (512 or 1024)
 };
 
 // Optional per-family event timing of launches (diagnostics).
