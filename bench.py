@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--tol", type=float, default=4e-12)
-    ap.add_argument("--oracle-levels", type=int, default=6)
+    ap.add_argument("--oracle-levels", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
