@@ -226,20 +226,56 @@ int pd_footprint(const pd_mesh_desc *mesh, int32_t nsrc, int32_t precision, size
 
 int pd_destroy(pd_instance *inst);
 
-/* Serving: a request loop that admits solves by device-memory footprint into
- * a pool of hbm_pool_bytes, runs every admitted request in the same batched
- * launches (continuous batching: requests join and leave at time-level
- * boundaries), and hands results back through pd_batch_poll.
- * pd_batch_submit copies the inputs and never blocks on the GPU; it returns
- * PD_ENOMEM if the request can never fit the pool.  pd_batch_poll returns
- * PD_PENDING until the request is finished, then PD_OK (or the solve's
- * error) and copies the final state (N values, ring layout, host) to out
- * (may be NULL) and its statistics to summary (may be NULL); a finished
- * ticket is released by the poll that reports it.                        */
+/* Serving: a request loop with continuous batching.  pd_batch_create starts
+ * a host worker thread that owns a HIP stream (the caller's, or its own when
+ * hip_stream is NULL) and a device-memory budget of hbm_pool_bytes.
+ *   pd_batch_submit copies the request's inputs (host or device arrays, as
+ *   the problem says) and returns at once with a ticket; it never waits on
+ *   the GPU.  PD_ENOMEM if the request alone exceeds the pool, PD_EINVAL for
+ *   inputs pd_mesh_create or pd_solve_to_T would reject.  The request starts
+ *   from its u0 at t = 0 and advances through the time levels of `time`.
+ *   The worker admits pending requests in arrival order at time-level
+ *   boundaries while fewer than max_slots are active and their footprints
+ *   (pd_footprint plus the time table) fit the pool; every admitted request
+ *   then takes its levels in the same batched launches as the others
+ *   (requests of any mesh size, PDE and precision mix), and leaves the batch
+ *   when its last level ends.  A request's result does not depend on which
+ *   others share its launches (every reduction and sweep of an instance
+ *   depends only on the instance).
+ *   pd_batch_poll returns PD_PENDING while the request is queued or running;
+ *   then its outcome (PD_OK, or the first error of its solve), copies the
+ *   final state (N values in the problem's layout, host buffer owned by the
+ *   caller, may be NULL) to out and its summary to summary (may be NULL);
+ *   the poll that reports an outcome releases the ticket (later polls of it
+ *   return PD_EINVAL).
+ *   pd_batch_stats fills the loop's counters.
+ *   pd_batch_destroy stops the worker at the next level boundary, drops
+ *   unfinished requests and frees everything.  The calls are thread safe.  */
+typedef struct {
+  int32_t status;        /* outcome, as returned by the poll                */
+  int32_t levels;        /* time levels taken                               */
+  int32_t iters;         /* Krylov iterations summed over the levels        */
+  int32_t refinements;   /* FP64 refinements summed over the levels (mixed) */
+  double max_rel_resid;  /* largest final scaled residual of a level        */
+  double t;              /* time reached                                    */
+  double queue_s;        /* submit -> admission, seconds (host clock)       */
+  double latency_s;      /* submit -> result ready, seconds                 */
+} pd_request_summary;
+
+typedef struct {
+  int32_t pending;       /* submitted, not yet admitted                     */
+  int32_t active;        /* admitted, stepping                              */
+  int32_t peak_active;   /* most requests active at once                    */
+  int32_t reserved;
+  uint64_t submitted, completed, levels_run, plans_built;
+  size_t used_bytes, peak_bytes;   /* admitted footprint, now and at most   */
+} pd_batch_info;
+
 int pd_batch_create(size_t hbm_pool_bytes, int32_t max_slots, void *hip_stream, pd_batch **out);
 int pd_batch_submit(pd_batch *batch, const pd_mesh_desc *mesh, const pd_problem_desc *problem,
                     const pd_time_desc *time, int32_t precision, uint64_t *ticket);
-int pd_batch_poll(pd_batch *batch, uint64_t ticket, double *out, pd_step_stats *summary);
+int pd_batch_poll(pd_batch *batch, uint64_t ticket, double *out, pd_request_summary *summary);
+int pd_batch_stats(pd_batch *batch, pd_batch_info *info);
 int pd_batch_destroy(pd_batch *batch);
 
 /* Kernel timing (diagnostics).  While enabled, every kernel launch of the

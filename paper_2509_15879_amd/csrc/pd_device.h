@@ -96,5 +96,6 @@ struct PdInst {
   unsigned *counters;       // [CNT_N]
   PdScalars *sc;
   int *n_active;            // shared counter of the batch (device)
+  int *lvl_out;             // (levels done, status) written at each level end
   double *level_stats;      // [K * 8]: iters, outer, status, rel_resid, dt, t1, restarts, 0
 };

@@ -451,6 +451,7 @@ struct Plan {
   std::vector<void *> bufs;
   int *n_active = nullptr;
   int *h_active = nullptr;   // pinned, 2 slots
+  int *lvl = nullptr;        // device: (levels done, status) per instance
   hipEvent_t ev[2] = {nullptr, nullptr};
   ~Plan() {
     for (void *b : bufs) (void)hipFree(b);
@@ -475,21 +476,22 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
   HIPCHK(hipMalloc(&P.n_active, sizeof(int)));
   P.bufs.push_back(P.n_active);
   HIPCHK(hipMemsetAsync(P.n_active, 0, sizeof(int), s));
+  HIPCHK(hipMalloc(&P.lvl, 2 * (size_t)ninst * sizeof(int)));
+  P.bufs.push_back(P.lvl);
+  HIPCHK(hipMemsetAsync(P.lvl, 0, 2 * (size_t)ninst * sizeof(int), s));
   std::vector<PdInst> hv(ninst);
   for (int q = 0; q < ninst; ++q) {
     hv[q] = insts[q]->H;
     hv[q].n_active = P.n_active;
+    hv[q].lvl_out = P.lvl + 2 * q;
     P.L.mixed_any |= insts[q]->precision == PD_MIXED;
     P.L.fp64_any |= insts[q]->precision != PD_MIXED;
     P.L.max_bang = std::max(P.L.max_bang, insts[q]->T.bang);
   }
-  // radial sweeps: 512-thread blocks (32 segments per column, two blocks per
-  // CU) while every segment stays within 8 rows, else 1024 threads (64
-  // segments)
-  int mmax = 0;
-  for (auto *I : insts) mmax = std::max(mmax, I->M.m);
-  P.L.rad_threads = (mmax + 31) / 32 <= 8 ? 512 : 1024;
-  P.L.max_brad = (mmax + P.L.rad_threads / 16 - 1) / (P.L.rad_threads / 16);
+  for (auto *I : insts) {
+    const int c = pd::rad_class(I->M.m);
+    P.L.max_brs[c] = std::max(P.L.max_brs[c], pd::rad_rows(I->M.m));
+  }
   HIPCHK(hipMalloc(&P.L.insts, ninst * sizeof(PdInst)));
   P.bufs.push_back(P.L.insts);
   HIPCHK(hipMemcpyAsync(P.L.insts, hv.data(), ninst * sizeof(PdInst), hipMemcpyHostToDevice, s));
@@ -508,6 +510,10 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
   if ((rc = upload(&P.L.map_sten, &P.L.nb_sten, [](pd_instance *I) { return I->T.nb_sten; }))) return rc;
   if ((rc = upload(&P.L.map_elem, &P.L.nb_elem, [](pd_instance *I) { return I->T.nb_elem; }))) return rc;
   if ((rc = upload(&P.L.map_rad, &P.L.nb_rad, [](pd_instance *I) { return I->T.nb_rad; }))) return rc;
+  for (int c = 0; c < 2; ++c)
+    if ((rc = upload(&P.L.map_rs[c], &P.L.nb_rs[c],
+                     [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? I->T.nb_rad : 0; })))
+      return rc;
   if ((rc = upload(&P.L.map_ang, &P.L.nb_ang, [](pd_instance *I) { return I->T.nb_ang; }))) return rc;
   HIPCHK(hipHostMalloc((void **)&P.h_active, 2 * sizeof(int)));
   P.h_active[0] = P.h_active[1] = 1;
@@ -542,96 +548,137 @@ int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   return PD_OK;
 }
 
-// Runs all levels of every instance (instance q has Ks[q] levels).
-int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &Ks,
-               std::vector<SolveParams> const &sps, hipStream_t s, std::vector<std::vector<double>> *stats_out) {
-  Plan P;
-  int rc = make_plan(insts, s, P);
-  if (rc) return rc;
-  int maxK = 0;
-  for (size_t q = 0; q < insts.size(); ++q) {
-    if ((rc = init_scalars(insts[q], sps[q], Ks[q], s))) return rc;
-    maxK = std::max(maxK, Ks[q]);
-  }
-  int max_cycles = 0;
-  for (auto &sp : sps) max_cycles = std::max(max_cycles, sp.maxit + sp.max_outer + 8);
-  // The Krylov cycles of a level repeat identically: capture kCyclesPerGraph
-  // of them, followed by the read-back of the active-instance counter, into
-  // one HIP graph and replay it until every instance has finished the level
-  // (one graph of look-ahead; a launch for finished instances is a no-op).
-  // Per-kernel event timing needs the plain launches.
-  const bool use_graph = !pd::g_timer && !getenv("PD_NO_GRAPH");
-  constexpr int kCyclesPerGraph = 2;
+// A set of instances advancing level by level in shared launches.  The
+// Krylov cycles of a level repeat identically: kCyclesPerGraph of them,
+// followed by the read-back of the active-instance counter, are captured in
+// one HIP graph and replayed until every instance has finished the level
+// (one graph of look-ahead; a launch for finished instances is a no-op).
+// Per-kernel event timing needs the plain launches.
+struct Engine {
+  static constexpr int kCyclesPerGraph = 2;
+  hipStream_t s = nullptr;
+  std::unique_ptr<Plan> P;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  struct GraphGuard {
-    hipGraph_t &g;
-    hipGraphExec_t &e;
-    ~GraphGuard() {
-      if (e) (void)hipGraphExecDestroy(e);
-      if (g) (void)hipGraphDestroy(g);
-    }
-  } gguard{graph, gexec};
-  if (use_graph) {
-    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < kCyclesPerGraph; ++c) pd::launch_cycle(P.L, s);
-    hipError_t ce = hipMemcpyAsync(&P.h_active[0], P.n_active, sizeof(int), hipMemcpyDeviceToHost, s);
-    hipError_t ee = hipStreamEndCapture(s, &graph);
-    if (ce != hipSuccess || ee != hipSuccess)
-      return fail(PD_EHIP, "graph capture failed: %s / %s", hipGetErrorString(ce), hipGetErrorString(ee));
-    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  bool use_graph = false;
+  int max_cycles = 0;
+  int ninst = 0;
+
+  void release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    P.reset();
   }
-  for (int lev = 0; lev < maxK; ++lev) {
-    pd::launch_level_begin(P.L, s);
-    pd::launch_factor(P.L, s);
-    pd::launch_begin(P.L, s);
+  ~Engine() { release(); }
+
+  int build(std::vector<pd_instance *> const &insts, int cycles_cap, hipStream_t st) {
+    release();
+    s = st;
+    ninst = (int)insts.size();
+    max_cycles = cycles_cap;
+    P.reset(new Plan);
+    int rc = make_plan(insts, s, *P);
+    if (rc) return rc;
+    use_graph = !pd::g_timer && !getenv("PD_NO_GRAPH");
+    if (use_graph) {
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int c = 0; c < kCyclesPerGraph; ++c) pd::launch_cycle(P->L, s);
+      hipError_t ce = hipMemcpyAsync(&P->h_active[0], P->n_active, sizeof(int), hipMemcpyDeviceToHost, s);
+      hipError_t ee = hipStreamEndCapture(s, &graph);
+      if (ce != hipSuccess || ee != hipSuccess)
+        return fail(PD_EHIP, "graph capture failed: %s / %s", hipGetErrorString(ce), hipGetErrorString(ee));
+      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
+    return PD_OK;
+  }
+
+  // One time level of every instance that is not idle.
+  int level() {
+    Plan &Q = *P;
+    pd::launch_level_begin(Q.L, s);
+    pd::launch_factor(Q.L, s);
+    pd::launch_begin(Q.L, s);
     if (use_graph) {
       const int max_launch = (max_cycles + kCyclesPerGraph - 1) / kCyclesPerGraph;
       for (int c = 0; c < max_launch; ++c) {
         HIPCHK(hipGraphLaunch(gexec, s));
-        HIPCHK(hipEventRecord(P.ev[c & 1], s));
+        HIPCHK(hipEventRecord(Q.ev[c & 1], s));
         if (c >= 1) {
           // the slot holds the count after launch c-1 or a later one: the
           // count never grows inside a level, so 0 means the level is done
-          HIPCHK(hipEventSynchronize(P.ev[(c - 1) & 1]));
-          if (__atomic_load_n(&P.h_active[0], __ATOMIC_ACQUIRE) == 0) break;
+          HIPCHK(hipEventSynchronize(Q.ev[(c - 1) & 1]));
+          if (__atomic_load_n(&Q.h_active[0], __ATOMIC_ACQUIRE) == 0) break;
         }
       }
     } else {
       for (int c = 0; c < max_cycles; ++c) {
-        pd::launch_cycle(P.L, s);
-        HIPCHK(hipMemcpyAsync(&P.h_active[c & 1], P.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(P.ev[c & 1], s));
+        pd::launch_cycle(Q.L, s);
+        HIPCHK(hipMemcpyAsync(&Q.h_active[c & 1], Q.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(Q.ev[c & 1], s));
         if (c >= 1) {
-          HIPCHK(hipEventSynchronize(P.ev[(c - 1) & 1]));
-          if (P.h_active[(c - 1) & 1] == 0) break;
+          HIPCHK(hipEventSynchronize(Q.ev[(c - 1) & 1]));
+          if (Q.h_active[(c - 1) & 1] == 0) break;
         }
       }
     }
     HIPCHK(hipGetLastError());
-    pd::launch_level_end(P.L, s);
+    pd::launch_level_end(Q.L, s);
     if (g_event_timer && pd::g_timer) {
       HIPCHK(hipStreamSynchronize(s));
       g_event_timer->harvest();
     }
+    return PD_OK;
   }
+
+  // (levels done, status) of every instance after the last level (synchronises).
+  int levels_done(std::vector<int> &out) {
+    out.resize(2 * (size_t)ninst);
+    HIPCHK(hipMemcpyAsync(out.data(), P->lvl, out.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PD_OK;
+  }
+};
+
+int cycles_cap(SolveParams const &sp) { return sp.maxit + sp.max_outer + 8; }
+
+// Per-level statistics of an instance after a solve: 8 doubles per level.
+int read_level_stats(pd_instance *I, int K, std::vector<double> &st, int &worst) {
+  PdScalars h{};
+  HIPCHK(hipMemcpy(&h, I->sc, sizeof h, hipMemcpyDeviceToHost));
+  I->rot = h.rot;
+  I->t = h.t_now;
+  I->have_prev = true;
+  st.assign(8 * (size_t)K, 0.0);
+  HIPCHK(hipMemcpy(st.data(), I->stats, st.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int k = 0; k < K; ++k) {
+    const int status = (int)st[8 * k + 2];
+    if (status == ST_BREAKDOWN) worst = PD_EBREAKDOWN;
+    else if (status != ST_DONE && worst == PD_OK) worst = PD_ENOCONV;
+  }
+  return PD_OK;
+}
+
+// Runs all levels of every instance (instance q has Ks[q] levels).
+int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &Ks,
+               std::vector<SolveParams> const &sps, hipStream_t s, std::vector<std::vector<double>> *stats_out) {
+  int rc, maxK = 0, cap = 0;
+  for (size_t q = 0; q < insts.size(); ++q) {
+    if ((rc = init_scalars(insts[q], sps[q], Ks[q], s))) return rc;
+    maxK = std::max(maxK, Ks[q]);
+    cap = std::max(cap, cycles_cap(sps[q]));
+  }
+  Engine E;
+  if ((rc = E.build(insts, cap, s))) return rc;
+  for (int lev = 0; lev < maxK; ++lev)
+    if ((rc = E.level())) return rc;
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   int worst = PD_OK;
   for (size_t q = 0; q < insts.size(); ++q) {
-    pd_instance *I = insts[q];
-    PdScalars h{};
-    HIPCHK(hipMemcpy(&h, I->sc, sizeof h, hipMemcpyDeviceToHost));
-    I->rot = h.rot;
-    I->t = h.t_now;
-    I->have_prev = true;
-    std::vector<double> st(8 * (size_t)Ks[q]);
-    HIPCHK(hipMemcpy(st.data(), I->stats, st.size() * sizeof(double), hipMemcpyDeviceToHost));
-    for (int k = 0; k < Ks[q]; ++k) {
-      const int status = (int)st[8 * k + 2];
-      if (status == ST_BREAKDOWN) worst = PD_EBREAKDOWN;
-      else if (status != ST_DONE && worst == PD_OK) worst = PD_ENOCONV;
-    }
+    std::vector<double> st;
+    if ((rc = read_level_stats(insts[q], Ks[q], st, worst))) return rc;
     if (stats_out) (*stats_out)[q] = std::move(st);
   }
   if (worst == PD_EBREAKDOWN) return fail(worst, "Krylov breakdown in at least one step");
@@ -1121,18 +1168,347 @@ int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double 
 
 }  // extern "C"
 
-// ================================================================== serving (placeholder)
+// ================================================================== serving
+//
+// Continuous batching: a worker thread steps every admitted request one
+// time level at a time in shared launches (Engine); between levels it
+// retires finished requests and admits queued ones (arrival order, while
+// the slot count and the memory pool allow), rebuilding the launch plan
+// whenever the set changed.
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t ticket = 0;
+  pd_mesh_desc mesh{};
+  std::vector<double> r_expl, th_expl;
+  pd_problem_desc pb{};
+  std::vector<double> b, Dr, Er, Dt, Et, lam, g, nb, u0;
+  std::vector<int32_t> tpow;
+  std::vector<double> ttab;   // the K+1 levels from t = 0
+  int precision = PD_FP64;
+  int K = 0, N = 0;
+  size_t footprint = 0;
+  SolveParams sp{};
+  pd_instance *inst = nullptr;
+  int status = PD_PENDING;
+  std::string err;
+  std::vector<double> result;
+  pd_request_summary sum{};
+  Clock::time_point t_submit, t_admit;
+};
+
+double seconds(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+// Copies an optional input array (count values) into `keep`; the copy's
+// address replaces the caller's pointer.
+int keep_copy(const double *&p, size_t count, int device_ptrs, std::vector<double> &keep) {
+  if (!p) return PD_OK;
+  int rc = fetch(p, count, device_ptrs, keep);
+  if (rc) return rc;
+  p = keep.data();
+  return PD_OK;
+}
+
+}  // namespace
+
+struct pd_batch {
+  size_t pool = 0;
+  int max_slots = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request *> pending;                         // arrival order
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;     // every unreported ticket
+  uint64_t next = 1;
+  bool stop = false;
+  pd_batch_info info{};
+  std::thread worker;
+};
+
+namespace {
+
+// Creates the request's instance on the loop's stream and readies its solve.
+int admit_request(pd_batch *B, Request *R) {
+  int rc = pd_mesh_create(&R->mesh, &R->pb, R->precision, B->stream, &R->inst);
+  if (rc) return rc;
+  pd_instance *I = R->inst;
+  if ((rc = ensure_time_capacity(I, R->K))) return rc;
+  HIPCHK(hipMemcpyAsync(I->t_table, R->ttab.data(), R->ttab.size() * sizeof(double), hipMemcpyHostToDevice,
+                        B->stream));
+  return init_scalars(I, R->sp, R->K, B->stream);
+}
+
+// Collects a finished request's result and statistics (its first `levels`
+// levels were taken) and frees its instance.
+void retire_request(pd_batch *B, Request *R, int rc, int levels) {
+  int worst = PD_OK;
+  std::string err;
+  if (rc) err = g_err;
+  if (!rc && R->inst && levels > 0) {
+    std::vector<double> st;
+    rc = read_level_stats(R->inst, levels, st, worst);
+    if (!rc) {
+      pd_request_summary &S = R->sum;
+      for (int k = 0; k < levels; ++k) {
+        S.levels = k + 1;
+        S.iters += (int)st[8 * k + 0];
+        S.refinements += (int)st[8 * k + 1];
+        S.max_rel_resid = std::max(S.max_rel_resid, st[8 * k + 3]);
+        S.t = st[8 * k + 5];
+      }
+      R->result.resize(R->N);
+      rc = pd_get_solution(R->inst, R->result.data(), R->pb.layout, 0);
+    }
+    if (rc) err = g_err;
+    if (!rc && worst != PD_OK) {
+      rc = worst;
+      err = worst == PD_EBREAKDOWN ? "Krylov breakdown in a step"
+                                   : "a step did not reach the tolerance within the iteration cap";
+    }
+  }
+  if (R->inst) (void)pd_destroy(R->inst);
+  R->inst = nullptr;
+  const auto now = Clock::now();
+  std::lock_guard<std::mutex> lk(B->mu);
+  R->sum.status = rc;
+  R->sum.queue_s = seconds(R->t_submit, R->t_admit);
+  R->sum.latency_s = seconds(R->t_submit, now);
+  R->err = err;
+  R->status = rc;
+  B->info.used_bytes -= R->footprint;
+  B->info.active -= 1;
+  B->info.completed += 1;
+}
+
+void serve(pd_batch *B) {
+  (void)hipSetDevice(B->device);
+  Engine E;
+  std::vector<Request *> active;
+  std::vector<int> lv;
+  bool dirty = false;
+  for (;;) {
+    std::vector<Request *> admit;
+    {
+      std::unique_lock<std::mutex> lk(B->mu);
+      B->cv.wait(lk, [&] { return B->stop || !active.empty() || !B->pending.empty(); });
+      if (B->stop) break;
+      while (!B->pending.empty() && (int)(active.size() + admit.size()) < B->max_slots &&
+             B->info.used_bytes + B->pending.front()->footprint <= B->pool) {
+        Request *R = B->pending.front();
+        B->pending.pop_front();
+        B->info.used_bytes += R->footprint;
+        B->info.peak_bytes = std::max(B->info.peak_bytes, B->info.used_bytes);
+        B->info.pending -= 1;
+        B->info.active += 1;
+        admit.push_back(R);
+      }
+      B->info.peak_active = std::max(B->info.peak_active, B->info.active);
+    }
+    for (Request *R : admit) {
+      R->t_admit = Clock::now();
+      const int rc = admit_request(B, R);
+      if (rc) {
+        retire_request(B, R, rc, 0);
+      } else {
+        active.push_back(R);
+        dirty = true;
+      }
+    }
+    if (active.empty()) continue;
+    int rc = PD_OK;
+    if (dirty) {
+      std::vector<pd_instance *> insts;
+      int cap = 0;
+      for (Request *R : active) {
+        insts.push_back(R->inst);
+        cap = std::max(cap, cycles_cap(R->sp));
+      }
+      rc = E.build(insts, cap, B->stream);
+      dirty = false;
+      std::lock_guard<std::mutex> lk(B->mu);
+      B->info.plans_built += 1;
+    }
+    if (!rc) rc = E.level();
+    if (!rc) rc = E.levels_done(lv);
+    if (rc) {
+      // a failure of the loop itself ends every active request
+      E.release();
+      for (Request *R : active) retire_request(B, R, rc, 0);
+      active.clear();
+      continue;
+    }
+    std::vector<Request *> keep;
+    for (size_t q = 0; q < active.size(); ++q) {
+      Request *R = active[q];
+      if (lv[2 * q] >= R->K || lv[2 * q + 1] != ST_DONE) {
+        retire_request(B, R, PD_OK, lv[2 * q]);
+        dirty = true;
+      } else {
+        keep.push_back(R);
+      }
+    }
+    active.swap(keep);
+    if (active.empty()) E.release();
+    std::lock_guard<std::mutex> lk(B->mu);
+    B->info.levels_run += 1;
+  }
+  E.release();
+  for (Request *R : active)
+    if (R->inst) (void)pd_destroy(R->inst);
+}
+
+}  // namespace
+
 extern "C" {
-int pd_batch_create(size_t, int32_t, void *, pd_batch **out) {
-  if (out) *out = nullptr;
-  return fail(PD_EINVAL, "serving loop not available in this build");
+
+int pd_batch_create(size_t hbm_pool_bytes, int32_t max_slots, void *hip_stream, pd_batch **out) {
+  if (!out) return fail(PD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hbm_pool_bytes == 0) return fail(PD_EINVAL, "hbm_pool_bytes must be > 0");
+  if (max_slots < 1) return fail(PD_EINVAL, "max_slots must be >= 1");
+  std::unique_ptr<pd_batch> B(new pd_batch);
+  B->pool = hbm_pool_bytes;
+  B->max_slots = max_slots;
+  HIPCHK(hipGetDevice(&B->device));
+  if (hip_stream) {
+    B->stream = (hipStream_t)hip_stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
+    B->own_stream = true;
+  }
+  pd_batch *raw = B.get();
+  try {
+    B->worker = std::thread(serve, raw);
+  } catch (...) {
+    if (B->own_stream) (void)hipStreamDestroy(B->stream);
+    return fail(PD_EINVAL, "could not start the serving thread");
+  }
+  *out = B.release();
+  return PD_OK;
 }
-int pd_batch_submit(pd_batch *, const pd_mesh_desc *, const pd_problem_desc *, const pd_time_desc *, int32_t,
-                    uint64_t *) {
-  return fail(PD_EINVAL, "serving loop not available in this build");
+
+int pd_batch_submit(pd_batch *B, const pd_mesh_desc *mesh, const pd_problem_desc *pb, const pd_time_desc *td,
+                    int32_t precision, uint64_t *ticket) {
+  try {
+    if (!B || !mesh || !pb || !td || !ticket) return fail(PD_EINVAL, "NULL argument");
+    if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision %d", precision);
+    int rc = check_mesh(mesh);
+    if (rc) return rc;
+    if ((rc = validate_theta(td->theta))) return rc;
+    if (pb->nsrc < 0 || pb->nsrc > PD_MAXSRC) return fail(PD_EINVAL, "nsrc must be in [0, %d]", PD_MAXSRC);
+    if (pb->flux != 0 && pb->flux != 1) return fail(PD_EINVAL, "flux must be 0 or 1");
+    if (pb->bc != 0 && pb->bc != 1) return fail(PD_EINVAL, "bc must be 0 or 1");
+    if (pb->layout != PD_LAYOUT_RING && pb->layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
+    if (!pb->u0) return fail(PD_EINVAL, "u0 is NULL");
+    if (pb->nsrc > 0 && (!pb->lambda || !pb->g)) return fail(PD_EINVAL, "lambda and g are required when nsrc > 0");
+    std::unique_ptr<Request> R(new Request);
+    const int m = mesh->nr, n = mesh->ntheta, N = m * n + 1;
+    R->N = N;
+    R->precision = precision;
+    R->mesh = *mesh;
+    if (mesh->r_kind == PD_MESH_EXPLICIT) {
+      R->r_expl.assign(mesh->r_explicit, mesh->r_explicit + m + 2);
+      R->mesh.r_explicit = R->r_expl.data();
+    }
+    if (mesh->th_kind == PD_MESH_EXPLICIT) {
+      R->th_expl.assign(mesh->th_explicit, mesh->th_explicit + n + 1);
+      R->mesh.th_explicit = R->th_expl.data();
+    }
+    R->pb = *pb;
+    pd_problem_desc &P = R->pb;
+    const int dp = pb->device_ptrs;
+    const size_t nr_f = (size_t)(m + 1) * n, nt_f = (size_t)m * n;
+    if ((rc = keep_copy(P.b_node, N, dp, R->b))) return rc;
+    if ((rc = keep_copy(P.D_rface, nr_f, dp, R->Dr))) return rc;
+    if ((rc = keep_copy(P.Er_rface, nr_f, dp, R->Er))) return rc;
+    if ((rc = keep_copy(P.D_tface, nt_f, dp, R->Dt))) return rc;
+    if ((rc = keep_copy(P.Et_tface, nt_f, dp, R->Et))) return rc;
+    if ((rc = keep_copy(P.u0, N, dp, R->u0))) return rc;
+    if (pb->nsrc > 0) {
+      R->lam.assign(pb->lambda, pb->lambda + pb->nsrc);   // host array (as for create)
+      P.lambda = R->lam.data();
+      if (pb->tpow) {
+        R->tpow.assign(pb->tpow, pb->tpow + pb->nsrc);
+        P.tpow = R->tpow.data();
+      }
+      if ((rc = keep_copy(P.g, (size_t)pb->nsrc * N, dp, R->g))) return rc;
+      if ((rc = keep_copy(P.nb, (size_t)pb->nsrc * n, dp, R->nb))) return rc;
+    } else {
+      P.lambda = nullptr;
+      P.tpow = nullptr;
+      P.g = nullptr;
+      P.nb = nullptr;
+    }
+    P.device_ptrs = 0;
+    if ((rc = build_time_table(td, 0.0, R->ttab))) return rc;
+    R->K = td->K;
+    R->sp = params_from(td, precision);
+    size_t fp = 0;
+    if ((rc = pd_footprint(mesh, pb->nsrc, precision, &fp))) return rc;
+    R->footprint = fp + (9 * (size_t)std::max(R->K, 16) + 1) * sizeof(double);
+    if (R->footprint > B->pool)
+      return fail(PD_ENOMEM, "request needs %zu bytes, the pool holds %zu", R->footprint, B->pool);
+    {
+      std::lock_guard<std::mutex> lk(B->mu);
+      if (B->stop) return fail(PD_EINVAL, "batch is shutting down");
+      R->ticket = B->next++;
+      R->t_submit = Clock::now();
+      *ticket = R->ticket;
+      B->pending.push_back(R.get());
+      B->reqs.emplace(R->ticket, std::move(R));
+      B->info.pending += 1;
+      B->info.submitted += 1;
+    }
+    B->cv.notify_all();
+    return PD_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(PD_ENOMEM, "host allocation failed");
+  }
 }
-int pd_batch_poll(pd_batch *, uint64_t, double *, pd_step_stats *) {
-  return fail(PD_EINVAL, "serving loop not available in this build");
+
+int pd_batch_poll(pd_batch *B, uint64_t ticket, double *out, pd_request_summary *summary) {
+  if (!B) return fail(PD_EINVAL, "batch is NULL");
+  std::unique_ptr<Request> R;
+  {
+    std::lock_guard<std::mutex> lk(B->mu);
+    auto it = B->reqs.find(ticket);
+    if (it == B->reqs.end()) return fail(PD_EINVAL, "unknown or already reported ticket %llu", (unsigned long long)ticket);
+    if (it->second->status == PD_PENDING) return PD_PENDING;
+    R = std::move(it->second);
+    B->reqs.erase(it);
+  }
+  if (summary) *summary = R->sum;
+  if (R->status == PD_OK && out) std::memcpy(out, R->result.data(), R->result.size() * sizeof(double));
+  if (R->status < 0) return fail(R->status, "%s", R->err.c_str());
+  return R->status;
 }
-int pd_batch_destroy(pd_batch *) { return PD_OK; }
+
+int pd_batch_stats(pd_batch *B, pd_batch_info *info) {
+  if (!B || !info) return fail(PD_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(B->mu);
+  *info = B->info;
+  return PD_OK;
 }
+
+int pd_batch_destroy(pd_batch *B) {
+  if (!B) return PD_OK;
+  {
+    std::lock_guard<std::mutex> lk(B->mu);
+    B->stop = true;
+  }
+  B->cv.notify_all();
+  if (B->worker.joinable()) B->worker.join();
+  if (B->stream) (void)hipStreamSynchronize(B->stream);
+  if (B->own_stream) (void)hipStreamDestroy(B->stream);
+  delete B;
+  return PD_OK;
+}
+
+}  // extern "C"

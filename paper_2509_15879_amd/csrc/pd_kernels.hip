@@ -242,6 +242,10 @@ __global__ void k_level_end(PdInst *insts, int ninst) {
     sc->fact_theta = sc->theta;
   }
   sc->status = (ok && k + 1 < sc->K) ? ST_DONE : ST_IDLE;
+  if (I.lvl_out) {
+    I.lvl_out[0] = k + 1;
+    I.lvl_out[1] = ok ? ST_DONE : (int)st[2];
+  }
 }
 
 // ------------------------------------------------------------ factorisations
@@ -1584,10 +1588,11 @@ void launch_begin(const LaunchSet &L, hipStream_t s) {
 template <typename T, int MODE>
 static void rad(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
   const int fam = MODE == RM_S ? KF_RAD_S : KF_RAD_P;
-  if (L.rad_threads == 512) {
-    PD_DISPATCH_BM(L.max_brad, (go(fam, k_rad<T, MODE, BM, 512>, g1(L.nb_rad), dim3(512), s, L.insts, L.map_rad, in, out)));
-  } else {
-    PD_DISPATCH_BM(L.max_brad, (go(fam, k_rad<T, MODE, BM, 1024>, g1(L.nb_rad), dim3(1024), s, L.insts, L.map_rad, in, out)));
+  if (L.nb_rs[0]) {
+    PD_DISPATCH_BM(L.max_brs[0], (go(fam, k_rad<T, MODE, BM, 512>, g1(L.nb_rs[0]), dim3(512), s, L.insts, L.map_rs[0], in, out)));
+  }
+  if (L.nb_rs[1]) {
+    PD_DISPATCH_BM(L.max_brs[1], (go(fam, k_rad<T, MODE, BM, 1024>, g1(L.nb_rs[1]), dim3(1024), s, L.insts, L.map_rs[1], in, out)));
   }
 }
 template <typename T, int MODE>

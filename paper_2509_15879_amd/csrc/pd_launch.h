@@ -14,9 +14,19 @@ struct LaunchSet {
   int2 *map_frad = nullptr, *map_fang = nullptr;
   int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0, nb_frad = 0, nb_fang = 0;
   int mixed_any = 0, fp64_any = 0;
-  int max_brad = 1, max_bang = 1;   // longest radial segment / angular lane span
-  int rad_threads = 1024;           // block size of the radial sweeps (512 or 1024)
+  int max_bang = 1;                 // longest angular lane span of the batch
+  // Radial sweeps, two classes by ring count: 512-thread blocks (32 segments
+  // per column) for m <= 256, 1024-thread blocks (64 segments) above.  The
+  // class depends on the instance alone, so its arithmetic does not depend
+  // on the rest of the batch.
+  int2 *map_rs[2] = {nullptr, nullptr};
+  int nb_rs[2] = {0, 0};
+  int max_brs[2] = {1, 1};          // longest radial segment per class
 };
+
+// Radial-sweep class of an instance with m rings and the rows per segment.
+inline int rad_class(int m) { return (m + 31) / 32 <= 8 ? 0 : 1; }
+inline int rad_rows(int m) { return rad_class(m) == 0 ? (m + 31) / 32 : (m + 63) / 64; }
 
 // Optional per-family event timing of launches (diagnostics).
 struct KTimer {

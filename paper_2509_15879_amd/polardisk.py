@@ -62,10 +62,30 @@ class StepStats(C.Structure):
                 "restarts": self.reserved, "rel_resid": self.rel_resid, "dt": self.dt, "t": self.t}
 
 
+class RequestSummary(C.Structure):
+    _fields_ = [("status", C.c_int32), ("levels", C.c_int32), ("iters", C.c_int32),
+                ("refinements", C.c_int32), ("max_rel_resid", C.c_double), ("t", C.c_double),
+                ("queue_s", C.c_double), ("latency_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("pending", C.c_int32), ("active", C.c_int32), ("peak_active", C.c_int32),
+                ("reserved", C.c_int32), ("submitted", C.c_uint64), ("completed", C.c_uint64),
+                ("levels_run", C.c_uint64), ("plans_built", C.c_uint64), ("used_bytes", C.c_size_t),
+                ("peak_bytes", C.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 # every entry point declared in include/polardisk.h
 EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
+           "pd_batch_stats",
            "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
 
 KERNEL_FAMILIES = ("begin", "factor", "rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t",
@@ -94,7 +114,8 @@ def _load():
         "pd_batch_create": [SZ, I32, P, C.POINTER(P)],
         "pd_batch_submit": [P, C.POINTER(MeshDesc), C.POINTER(ProblemDesc), C.POINTER(TimeDesc), I32,
                             C.POINTER(U64)],
-        "pd_batch_poll": [P, U64, P, P],
+        "pd_batch_poll": [P, U64, P, C.POINTER(RequestSummary)],
+        "pd_batch_stats": [P, C.POINTER(BatchInfo)],
         "pd_batch_destroy": [P],
         "pd_kernel_timing": [I32, I32, P, P],
     }
@@ -286,6 +307,64 @@ def solve_batch(instances: Sequence[Instance], tds: Sequence[TimeDesc]):
     ptrs = (C.c_void_p * n)(*[C.cast(s, C.c_void_p) for s in sts])
     _check(lib.pd_solve_batch(hs, n, arr, ptrs))
     return [[s.as_dict() for s in st] for st in sts]
+
+
+class Batch:
+    """Serving loop: requests of any size, PDE and precision are submitted at
+    any time and advanced together, level by level, in shared launches."""
+
+    def __init__(self, pool_bytes: int, max_slots: int, stream=None):
+        h = C.c_void_p()
+        _check(lib.pd_batch_create(C.c_size_t(int(pool_bytes)), int(max_slots),
+                                   C.c_void_p(stream) if stream else None, C.byref(h)))
+        self.h = h
+        self.sizes = {}
+
+    def submit(self, md: MeshDesc, data: dict, td: TimeDesc, precision=PD_FP64, flux=0, bc=0) -> int:
+        pdesc = problem_desc(data, flux, bc)
+        t = C.c_uint64()
+        _check(lib.pd_batch_submit(self.h, C.byref(md), C.byref(pdesc), C.byref(td), int(precision),
+                                   C.byref(t)))
+        self.sizes[t.value] = md.nr * md.ntheta + 1
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (solution, summary); raises on a failed solve."""
+        out = np.empty(self.sizes[ticket])
+        sm = RequestSummary()
+        rc = lib.pd_batch_poll(self.h, C.c_uint64(ticket), _ptr(out), C.byref(sm))
+        if rc == PD_PENDING:
+            return None
+        del self.sizes[ticket]
+        _check(rc)
+        return out, sm.as_dict()
+
+    def wait(self, ticket: int, timeout: float = 120.0, interval: float = 1e-3):
+        import time as _time
+        t_end = _time.monotonic() + timeout
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if _time.monotonic() > t_end:
+                raise TimeoutError(f"ticket {ticket} still pending after {timeout} s")
+            _time.sleep(interval)
+
+    def stats(self) -> dict:
+        info = BatchInfo()
+        _check(lib.pd_batch_stats(self.h, C.byref(info)))
+        return info.as_dict()
+
+    def close(self):
+        if self.h:
+            _check(lib.pd_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def kernel_timing(enable: bool, reset: bool = False):
