@@ -226,6 +226,47 @@ int pd_footprint(const pd_mesh_desc *mesh, int32_t nsrc, int32_t precision, size
 
 int pd_destroy(pd_instance *inst);
 
+/* Adaptivity.  The paper's adaptivity is the choice of the exponent p of
+ * the radial stretch (2.4) (α = pσ in Theorem 2.1); how a run picks or
+ * changes p is left open (§4.2).  These calls supply the indicator and the
+ * transfer; the caller samples its problem on the new mesh and creates the
+ * new instance itself (coefficients are caller data).
+ *
+ * pd_error_indicator: at every ring node of the current state (time of the
+ * last solve), from the second divided differences on the mesh,
+ *   δ_r² n = 2[(n_{i+1,j}-n_{i,j})/h_{i+1} - (n_{i,j}-n_{i-1,j})/h_i]/(h_i+h_{i+1}),
+ *   δ_θ² n = 2[(n_{i,j+1}-n_{i,j})/μ_{j+1} - (n_{i,j}-n_{i,j-1})/μ_j]/(μ_j+μ_{j+1}),
+ * (ring 0 the origin, ring m+1 the Dirichlet value, or ring m again for
+ * zero flux; j periodic):  η_ij = max(ĥ_i² |δ_r² n|, Δθ_j² |δ_θ² n|),
+ * ĥ_i = (h_i+h_{i+1})/2, Δθ_j = (μ_j+μ_{j+1})/2.  kappa (m values, may be
+ * NULL) receives κ_i = max_j |δ_r² n|; eta (m*n values, ring-major
+ * (i-1)*n + j, may be NULL) the indicator.  Among the stretches (2.4) with
+ * the same m and the exponents p_candidates, out->p_best minimises the
+ * predicted largest radial indicator P(p) = max_k ĥ'_k² κ(r'_k) (κ linear
+ * in r between nodes; the first of equal ones); out->recommend is 1 when
+ * P(p_best) <= 0.8 P(p_current).  Host buffers owned by the caller.        */
+typedef struct {
+  double eta_max, eta_sum;
+  int32_t i_max, j_max;      /* ring 1..m and angle index of eta_max (first) */
+  double p_best;
+  double pred_best, pred_current;
+  int32_t recommend;
+  int32_t reserved;
+} pd_indicator;
+int pd_error_indicator(pd_instance *inst, double p_current, const double *p_candidates,
+                       int32_t n_candidates, double *kappa, double *eta, pd_indicator *out);
+
+/* pd_remesh_transfer: sets the state of `to` (another mesh of the same
+ * problem and boundary condition) from the current state of `from` by
+ * tensor cubic Lagrange interpolation: radially along each θ-line of
+ * `from` on the nodes r = 0 (the origin value), r_1..r_m and, for
+ * Dirichlet data, r = 1 (the boundary value at the current time), each
+ * target radius taking the four consecutive nodes around it (shifted
+ * inwards at the ends); then periodically in θ.  The origin value is kept;
+ * `to` takes the time of `from` and restarts its extrapolated guesses.
+ * PD_EINVAL for zero flux with m < 3 or instances on different devices.   */
+int pd_remesh_transfer(pd_instance *from, pd_instance *to);
+
 /* Serving: a request loop with continuous batching.  pd_batch_create starts
  * a host worker thread that owns a HIP stream (the caller's, or its own when
  * hip_stream is NULL) and a device-memory budget of hbm_pool_bytes.

@@ -73,6 +73,8 @@ struct PdInst {
   double inv_V0;
   const double *inv_rw;     // [m+2] 1/(r_i (h_i+h_{i+1})/2), index i
   const double *inv_dth;    // [n]   1/Δθ_j
+  const double *r_nodes;    // [m+2] r_0..r_{m+1}
+  const double *th_nodes;   // [n+1] θ_0..θ_n
   const double *b_node;     // [npad] or null
   const double *g;          // [nsrc*npad]
   const double *nb;         // [nsrc*n]

@@ -222,6 +222,8 @@ void carve(pd_instance *I, Carver &c) {
   const bool mixed = I->precision == PD_MIXED;
   H.inv_rw = c.take<double>(m + 2);
   H.inv_dth = c.take<double>(n);
+  H.r_nodes = c.take<double>(m + 2);
+  H.th_nodes = c.take<double>(n + 1);
   H.b_node = c.take<double>(np);
   H.g = c.take<double>((size_t)ns * np);
   H.nb = c.take<double>((size_t)ns * n);
@@ -931,6 +933,8 @@ int pd_mesh_create(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_t 
   std::vector<std::vector<double>> keep;   // host staging must outlive the async copies
   if ((rc = up(H.inv_rw, inv_rw.data(), inv_rw.size() * 8))) return rc;
   if ((rc = up(H.inv_dth, inv_dth.data(), inv_dth.size() * 8))) return rc;
+  if ((rc = up(H.r_nodes, M.r.data(), M.r.size() * 8))) return rc;
+  if ((rc = up(H.th_nodes, M.th.data(), M.th.size() * 8))) return rc;
   if ((rc = up(H.k64.gp_r, gpr.data(), gpr.size() * 8))) return rc;
   if ((rc = up(H.k64.gm_r, gmr.data(), gmr.size() * 8))) return rc;
   if ((rc = up(H.k64.gp_t, gpt.data(), gpt.size() * 8))) return rc;
@@ -1163,6 +1167,125 @@ int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double 
   } else {
     std::memcpy(rhs, o.data(), N * 8);
   }
+  return PD_OK;
+}
+
+}  // extern "C"
+
+// ================================================================== adaptivity
+
+namespace {
+
+// Nodes of the radial stretch (2.4) with exponent p: r_i = sin((i h)^p π/2).
+std::vector<double> sine_nodes(int m, double p) {
+  std::vector<double> r(m + 2);
+  const double h = 1.0 / (m + 1);
+  for (int i = 0; i <= m + 1; ++i) r[i] = std::sin(std::pow(i * h, p) * kPi / 2.0);
+  r[0] = 0.0;
+  r[m + 1] = 1.0;
+  return r;
+}
+
+// κ at v by linear interpolation between (xs[k], ys[k]), constant beyond the ends.
+double interp_linear(const std::vector<double> &xs, const std::vector<double> &ys, double v) {
+  if (v <= xs.front()) return ys.front();
+  if (v >= xs.back()) return ys.back();
+  const size_t k = std::upper_bound(xs.begin(), xs.end(), v) - xs.begin();   // xs[k-1] <= v < xs[k]
+  const double w = (v - xs[k - 1]) / (xs[k] - xs[k - 1]);
+  return ys[k - 1] + w * (ys[k] - ys[k - 1]);
+}
+
+// Predicted largest radial indicator max_k ĥ'_k² κ(r'_k) of the stretch with exponent p.
+double predicted_max(const std::vector<double> &r_old, const std::vector<double> &kappa, int m, double p) {
+  const std::vector<double> r = sine_nodes(m, p);
+  std::vector<double> xs(r_old.begin() + 1, r_old.end() - 1);   // r_1..r_m
+  double best = 0.0;
+  for (int k = 1; k <= m; ++k) {
+    const double hl = 0.5 * ((r[k] - r[k - 1]) + (r[k + 1] - r[k]));
+    best = std::max(best, hl * hl * interp_linear(xs, kappa, r[k]));
+  }
+  return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pd_error_indicator(pd_instance *I, double p_current, const double *p_candidates, int32_t n_candidates,
+                       double *kappa, double *eta, pd_indicator *out) {
+  if (!I || !out) return fail(PD_EINVAL, "NULL argument");
+  if (n_candidates < 0 || (n_candidates > 0 && !p_candidates)) return fail(PD_EINVAL, "bad candidate list");
+  for (int c = 0; c < n_candidates; ++c)
+    if (!(p_candidates[c] > 0.0)) return fail(PD_EINVAL, "stretch exponents must be > 0");
+  if (!(p_current > 0.0)) return fail(PD_EINVAL, "p_current must be > 0");
+  BusyGuard g({I});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  const int m = I->M.m, n = I->M.n;
+  hipStream_t s = I->stream;
+  double *dbuf = nullptr;
+  const size_t ring_vals = 4 * (size_t)m, eta_vals = eta ? (size_t)m * n : 0;
+  HIPCHK(hipMalloc(&dbuf, (ring_vals + eta_vals) * sizeof(double)));
+  struct Free {
+    double *p;
+    ~Free() { (void)hipFree(p); }
+  } fr{dbuf};
+  const PdInst &H = I->H;
+  pd::launch_indicator(H.sol[(I->rot + 1) % 3], m, n, H.r_nodes, H.th_nodes, H.nb, H.lam, H.tpow, H.nsrc,
+                       I->t, I->bc == 0 ? 1 : 0, dbuf, eta ? dbuf + ring_vals : nullptr, s);
+  HIPCHK(hipGetLastError());
+  std::vector<double> ring(ring_vals);
+  HIPCHK(hipMemcpyAsync(ring.data(), dbuf, ring_vals * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (eta) HIPCHK(hipMemcpyAsync(eta, dbuf + ring_vals, eta_vals * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  pd_indicator R{};
+  R.eta_max = -1.0;
+  std::vector<double> kap(m);
+  for (int i = 1; i <= m; ++i) {
+    const double *q = &ring[4 * (size_t)(i - 1)];
+    kap[i - 1] = q[0];
+    if (q[1] > R.eta_max) {
+      R.eta_max = q[1];
+      R.i_max = i;
+      R.j_max = (int)q[2];
+    }
+    R.eta_sum += q[3];
+  }
+  if (kappa) std::copy(kap.begin(), kap.end(), kappa);
+  R.p_best = p_current;
+  R.pred_current = predicted_max(I->M.r, kap, m, p_current);
+  R.pred_best = R.pred_current;
+  bool found = false;
+  for (int c = 0; c < n_candidates; ++c) {
+    const double v = predicted_max(I->M.r, kap, m, p_candidates[c]);
+    if (!found || v < R.pred_best) {
+      R.pred_best = v;
+      R.p_best = p_candidates[c];
+      found = true;
+    }
+  }
+  R.recommend = (found && R.pred_best <= 0.8 * R.pred_current) ? 1 : 0;
+  *out = R;
+  return PD_OK;
+}
+
+int pd_remesh_transfer(pd_instance *from, pd_instance *to) {
+  if (!from || !to) return fail(PD_EINVAL, "NULL argument");
+  if (from == to) return fail(PD_EINVAL, "source and target must differ");
+  if (from->device != to->device) return fail(PD_EINVAL, "instances live on different devices");
+  if (from->bc != to->bc) return fail(PD_EINVAL, "boundary conditions differ");
+  if (from->bc == 1 && from->M.m < 3) return fail(PD_EINVAL, "zero-flux transfer needs m >= 3");
+  BusyGuard g({from, to});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  HIPCHK(hipStreamSynchronize(from->stream));
+  const PdInst &A = from->H;
+  const PdInst &B = to->H;
+  pd::launch_transfer(A.sol[(from->rot + 1) % 3], from->M.m, from->M.n, A.r_nodes, A.th_nodes, A.nb, A.lam,
+                      A.tpow, A.nsrc, from->t, from->bc == 0 ? 1 : 0, B.r_nodes, B.th_nodes, to->M.m, to->M.n,
+                      B.sol[(to->rot + 1) % 3], to->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(to->stream));
+  to->t = from->t;
+  to->have_prev = false;
   return PD_OK;
 }
 

@@ -1531,6 +1531,164 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   produce<2>(acc, I.part_x, I.nb_elem, mp.y);
 }
 
+// ------------------------------------------------------------ adaptivity
+//
+// Error indicator and state transfer between meshes (the paper ties its
+// adaptivity to the exponent p of the stretch (2.4), α = pσ of Theorem 2.1,
+// and leaves the indicator open).  Indicator at ring node (i, j) from the
+// second divided differences on the non-uniform mesh:
+//   δ_r² n = 2[(n_{i+1,j} - n_{i,j})/h_{i+1} - (n_{i,j} - n_{i-1,j})/h_i]/(h_i + h_{i+1})
+//   δ_θ² n = 2[(n_{i,j+1} - n_{i,j})/μ_{j+1} - (n_{i,j} - n_{i,j-1})/μ_j]/(μ_j + μ_{j+1})
+// with ring 0 the origin, ring m+1 the Dirichlet value N(t, θ_j) (zero flux:
+// ring m repeated) and j periodic;
+//   η = max(ĥ_i² |δ_r² n|, Δθ_j² |δ_θ² n|),  ĥ_i = (h_i + h_{i+1})/2,  Δθ_j = (μ_j + μ_{j+1})/2.
+// One wave per ring; per ring: κ_i = max_j |δ_r² n|, max_j η (first j of
+// the maximum) and Σ_j η, summed in a fixed order.
+
+__device__ __forceinline__ double boundary_value(const double *nb, const double *lam, const int *tpow,
+                                                 int nsrc, int n, int j, double t) {
+  double v = 0.0;
+  for (int q = 0; q < nsrc; ++q) v += tau_q(lam[q], tpow[q], t) * nb[q * n + j];
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_indicator(const double *__restrict__ x, int m, int n,
+                                                   const double *__restrict__ r,
+                                                   const double *__restrict__ th,
+                                                   const double *nb, const double *lam,
+                                                   const int *tpow, int nsrc, double t, int dirichlet,
+                                                   double *__restrict__ ring_out,
+                                                   double *__restrict__ eta_out) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6) + 1;
+  if (i > m) return;                                   // whole wave exits together
+  const double hi = r[i] - r[i - 1], ho = r[i + 1] - r[i];
+  const double hloc = 0.5 * (hi + ho);
+  const double x0 = x[m * n];
+  double kap = 0.0, emax = -1.0, esum = 0.0;
+  int jmax = 0;
+  for (int j = lane; j < n; j += 64) {
+    const double c = x[(i - 1) * n + j];
+    const double below = (i == 1) ? x0 : x[(i - 2) * n + j];
+    double above;
+    if (i < m) above = x[i * n + j];
+    else above = dirichlet ? boundary_value(nb, lam, tpow, nsrc, n, j, t) : c;
+    const double d2r = 2.0 * ((above - c) / ho - (c - below) / hi) / (hi + ho);
+    const int jl = (j == 0) ? n - 1 : j - 1, jr = (j == n - 1) ? 0 : j + 1;
+    const double mu_j = (j == 0) ? th[n] - th[n - 1] : th[j] - th[j - 1];   // μ_0 = μ_n
+    const double mu_j1 = th[j + 1] - th[j];
+    const double left = x[(i - 1) * n + jl], right = x[(i - 1) * n + jr];
+    const double d2t = 2.0 * ((right - c) / mu_j1 - (c - left) / mu_j) / (mu_j + mu_j1);
+    const double dth = 0.5 * (mu_j + mu_j1);
+    const double e = fmax(hloc * hloc * fabs(d2r), dth * dth * fabs(d2t));
+    if (eta_out) eta_out[(i - 1) * n + j] = e;
+    kap = fmax(kap, fabs(d2r));
+    if (e > emax) {
+      emax = e;
+      jmax = j;
+    }
+    esum += e;
+  }
+  // wave reductions: max with the first index of the maximum, fixed-order sum
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    kap = fmax(kap, __shfl_xor(kap, o, 64));
+    const double eo = __shfl_xor(emax, o, 64);
+    const int jo = __shfl_xor(jmax, o, 64);
+    if (eo > emax || (eo == emax && jo < jmax)) {
+      emax = eo;
+      jmax = jo;
+    }
+  }
+  esum = wave_sum(esum);
+  if (lane == 0) {
+    ring_out[4 * (i - 1) + 0] = kap;
+    ring_out[4 * (i - 1) + 1] = emax;
+    ring_out[4 * (i - 1) + 2] = (double)jmax;
+    ring_out[4 * (i - 1) + 3] = esum;
+  }
+}
+
+// Cubic Lagrange polynomial through (xs[a], ys[a]), a = 0..3, at x.
+__device__ __forceinline__ double lagrange4(const double (&xs)[4], const double (&ys)[4], double x) {
+  double total = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double w = 1.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b != a) w *= (x - xs[b]) / (xs[a] - xs[b]);
+    total += w * ys[a];
+  }
+  return total;
+}
+
+// First of the four consecutive entries of nodes[0..cnt) whose middle
+// interval holds v (shifted inwards at the ends); nodes increasing.
+__device__ __forceinline__ int window4(const double *nodes, int cnt, double v) {
+  int lo = 0, hi = cnt - 1;               // last k with nodes[k] <= v, clamped to [0, cnt-2]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (nodes[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  int k = (v >= nodes[cnt - 1]) ? cnt - 2 : lo;
+  k = min(max(k, 0), cnt - 2);
+  return min(max(k - 1, 0), cnt - 4);
+}
+
+// State transfer: tensor cubic Lagrange, radial along each old θ-line on
+// the nodes 0 (origin value), r_1..r_m and, for Dirichlet data, 1 (boundary
+// value), then periodic in θ.  One thread per target ring node; the origin
+// value is kept.
+__global__ __launch_bounds__(256) void k_transfer(const double *__restrict__ x, int m, int n,
+                                                  const double *__restrict__ r,
+                                                  const double *__restrict__ th,
+                                                  const double *nb, const double *lam,
+                                                  const int *tpow, int nsrc, double t, int dirichlet,
+                                                  const double *__restrict__ r2,
+                                                  const double *__restrict__ th2, int m2, int n2,
+                                                  double *__restrict__ y) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id == 0) y[m2 * n2] = x[m * n];
+  if (id >= m2 * n2) return;
+  const int i2 = id / n2 + 1, j2 = id % n2;
+  const double rq = r2[i2], tq = th2[j2];
+  const int cnt = dirichlet ? m + 2 : m + 1;           // radial nodes r_0..r_{m(+1)}
+  const int k = window4(r, cnt, rq);
+  double rs[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) rs[a] = r[k + a];
+  // the old node at or before tq: the last j with th[j] <= tq among 0..n-1
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (th[mid] <= tq) lo = mid;
+    else hi = mid;
+  }
+  const int jb = lo;
+  double ts[4], col[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int jj = jb - 1 + s;
+    const int wrap = (jj < 0) ? -1 : (jj >= n ? 1 : 0);
+    const int j = jj - wrap * n;
+    ts[s] = th[j] + 2.0 * 3.14159265358979323846 * wrap;
+    double ys[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int ii = k + a;                            // radial node index
+      double v;
+      if (ii == 0) v = x[m * n];
+      else if (ii <= m) v = x[(ii - 1) * n + j];
+      else v = boundary_value(nb, lam, tpow, nsrc, n, j, t);
+      ys[a] = v;
+    }
+    col[s] = lagrange4(rs, ys, rq);
+  }
+  y[(i2 - 1) * n2 + j2] = lagrange4(ts, col, tq);
+}
+
 }  // namespace pd
 
 // ------------------------------------------------------------ launchers
@@ -1648,6 +1806,21 @@ void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void 
 
 void launch_begin_origin(const LaunchSet &L, hipStream_t s) {
   go(KF_BEGIN, k_begin_origin, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
+}
+
+void launch_indicator(const double *x, int m, int n, const double *r, const double *th,
+                      const double *nb, const double *lam, const int *tpow, int nsrc, double t,
+                      int dirichlet, double *ring_out, double *eta_out, hipStream_t s) {
+  go(KF_CONTROL, k_indicator, dim3((m + 3) / 4), dim3(256), s, x, m, n, r, th, nb, lam, tpow, nsrc, t,
+     dirichlet, ring_out, eta_out);
+}
+
+void launch_transfer(const double *x, int m, int n, const double *r, const double *th, const double *nb,
+                     const double *lam, const int *tpow, int nsrc, double t, int dirichlet,
+                     const double *r2, const double *th2, int m2, int n2, double *y, hipStream_t s) {
+  const int cnt = m2 * n2;
+  go(KF_CONTROL, k_transfer, dim3((cnt + 255) / 256), dim3(256), s, x, m, n, r, th, nb, lam, tpow, nsrc, t,
+     dirichlet, r2, th2, m2, n2, y);
 }
 
 void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,

@@ -46,6 +46,12 @@ void launch_begin_origin(const LaunchSet &L, hipStream_t s);
 void launch_cycle(const LaunchSet &L, hipStream_t s);
 void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void *y, int fp32,
                   hipStream_t s);
+void launch_indicator(const double *x, int m, int n, const double *r, const double *th,
+                      const double *nb, const double *lam, const int *tpow, int nsrc, double t,
+                      int dirichlet, double *ring_out, double *eta_out, hipStream_t s);
+void launch_transfer(const double *x, int m, int n, const double *r, const double *th, const double *nb,
+                     const double *lam, const int *tpow, int nsrc, double t, int dirichlet,
+                     const double *r2, const double *th2, int m2, int n2, double *y, hipStream_t s);
 void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,
                           hipStream_t s);
 

@@ -81,11 +81,20 @@ class BatchInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class Indicator(C.Structure):
+    _fields_ = [("eta_max", C.c_double), ("eta_sum", C.c_double), ("i_max", C.c_int32),
+                ("j_max", C.c_int32), ("p_best", C.c_double), ("pred_best", C.c_double),
+                ("pred_current", C.c_double), ("recommend", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 # every entry point declared in include/polardisk.h
 EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
-           "pd_batch_stats",
+           "pd_batch_stats", "pd_error_indicator", "pd_remesh_transfer",
            "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
 
 KERNEL_FAMILIES = ("begin", "factor", "rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t",
@@ -116,6 +125,8 @@ def _load():
                             C.POINTER(U64)],
         "pd_batch_poll": [P, U64, P, C.POINTER(RequestSummary)],
         "pd_batch_stats": [P, C.POINTER(BatchInfo)],
+        "pd_error_indicator": [P, D, P, I32, P, P, C.POINTER(Indicator)],
+        "pd_remesh_transfer": [P, P],
         "pd_batch_destroy": [P],
         "pd_kernel_timing": [I32, I32, P, P],
     }
@@ -307,6 +318,26 @@ def solve_batch(instances: Sequence[Instance], tds: Sequence[TimeDesc]):
     ptrs = (C.c_void_p * n)(*[C.cast(s, C.c_void_p) for s in sts])
     _check(lib.pd_solve_batch(hs, n, arr, ptrs))
     return [[s.as_dict() for s in st] for st in sts]
+
+
+def error_indicator(inst: "Instance", p_current: float, candidates=(), want_eta=False):
+    """Indicator of the instance's current state and the recommended radial stretch."""
+    cand = _f64(list(candidates)) if len(candidates) else None
+    kappa = np.empty(inst.m)
+    eta = np.empty(inst.m * inst.n) if want_eta else None
+    res = Indicator()
+    _check(lib.pd_error_indicator(inst.h, float(p_current), _ptr(cand) if cand is not None else None,
+                                  len(candidates), _ptr(kappa), _ptr(eta) if eta is not None else None,
+                                  C.byref(res)))
+    out = res.as_dict()
+    out["kappa"] = kappa
+    out["eta"] = eta.reshape(inst.m, inst.n) if eta is not None else None
+    return out
+
+
+def remesh_transfer(src: "Instance", dst: "Instance"):
+    """Sets dst's state (another mesh of the same problem) from src's by cubic interpolation."""
+    _check(lib.pd_remesh_transfer(src.h, dst.h))
 
 
 class Batch:
