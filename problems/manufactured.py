@@ -239,31 +239,43 @@ def paper_continuity_ex1():
 
 # --------------------------------------------------------------- continuity
 
+def _per_ring(f, r):
+    """f(r) for an array of radii; on a grid whose rows hold one radius each
+    (a meshgrid over rings), f is evaluated once per row and broadcast."""
+    r = np.asarray(r, float)
+    if r.ndim == 2 and r.shape[1] > 1 and np.all(r == r[:, :1]):
+        return np.broadcast_to(f(r[:, :1]), r.shape)
+    return f(r)
+
+
 def _bessel_potential(modes):
     """ψ = Σ A J_k(α r) cos(kθ + φ) with α = j_{k,1}; returns callables for
     ψ_r, ψ_θ / r, Δψ, and ∇ψ at the origin (Cartesian)."""
     alph = [float(jn_zeros(k, 1)[0]) for (_, k, _) in modes]
 
+    def J(k, a, r):
+        return _per_ring(lambda rr: jv(k, a * rr), r)
+
     def psi(r, th):
-        return sum(A * jv(k, a * r) * np.cos(k * th + ph) for (A, k, ph), a in zip(modes, alph))
+        return sum(A * J(k, a, r) * np.cos(k * th + ph) for (A, k, ph), a in zip(modes, alph))
 
     def psi_r(r, th):
-        return sum(A * a * jvp(k, a * r, 1) * np.cos(k * th + ph)
+        return sum(A * a * _per_ring(lambda rr: jvp(k, a * rr, 1), r) * np.cos(k * th + ph)
                    for (A, k, ph), a in zip(modes, alph))
 
     def psi_t_over_r(r, th):
         # (1/r) ∂ψ/∂θ; J_k(αr)/r -> α/2 (k = 1) or 0 (k != 1) at r = 0
         tot = 0.0
-        safe = np.where(r > 0, r, 1.0)
         for (A, k, ph), a in zip(modes, alph):
             if k == 0:
                 continue
-            jr = np.where(r > 0, jv(k, a * r) / safe, (a / 2.0) if k == 1 else 0.0)
+            lim = (a / 2.0) if k == 1 else 0.0
+            jr = _per_ring(lambda rr: np.where(rr > 0, jv(k, a * rr) / np.where(rr > 0, rr, 1.0), lim), r)
             tot = tot - A * k * jr * np.sin(k * th + ph)
         return tot
 
     def lap_psi(r, th):
-        return sum(-(a * a) * A * jv(k, a * r) * np.cos(k * th + ph)
+        return sum(-(a * a) * A * J(k, a, r) * np.cos(k * th + ph)
                    for (A, k, ph), a in zip(modes, alph))
 
     def grad0():

@@ -17,3 +17,14 @@ def cfg2_batch():
     c = CFG2
     return [(s, th, continuity_cfg(s, c["m"], c["n"], th, c["p"], c["T"], c["K"], c["l"]))
             for s in CFG2_SEEDS for th in CFG2_THETAS]
+
+
+# 1024 x 2048 graded continuity problem (2,097,153 unknowns), θ = 0.5, fixed
+# Δt = 2.5e-4, 200 levels: the precision comparison (FP64 against FP32 inner
+# iterations with FP64 refinement).
+CFG3 = dict(m=1024, n=2048, p=1.3, theta=0.5, dt=2.5e-4, K=200, seed=1300)
+
+
+def cfg3_problem():
+    c = CFG3
+    return continuity_cfg(c["seed"], c["m"], c["n"], c["theta"], c["p"], c["dt"] * c["K"], c["K"], 1.0, 0)
