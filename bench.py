@@ -130,6 +130,71 @@ def precision_variant(pdk, stream, tol):
     return out
 
 
+def uneven_variant(pdk, stream, tol, sample_alone=32):
+    """512 uneven instances (m log-uniform in [32, 512], n in [64, 1024], half
+    parabolic, half drift-diffusion, θ in [0.5, 1], fixed Δt = 5e-4, 100
+    levels): the mixed-precision batch under the autotuned schedule against
+    a converged FP64 batch, and FP64 one instance at a time on a sample."""
+    import torch
+    from paper_2509_15879_amd import autotune
+    from problems import sample
+    from problems.workloads import CFG4, cfg4_batch
+    c = CFG4
+    specs = cfg4_batch()
+    datas, mds, tds = [], [], []
+    for q, m, n, theta, pb in specs:
+        md = pdk.mesh_desc(m, n, pdk.MESH_SINE, c["p"])
+        mds.append(md)
+        datas.append(sample(pb, *pdk.mesh_coords(md)))
+        tds.append(pdk.time_desc(theta, c["K"], c["dt"] * c["K"], pdk.TIME_UNIFORM, tol=tol))
+    cells = sum(m * n + 1 for _, m, n, _, _ in specs)
+
+    def make(prec):
+        return [pdk.Instance(md, d, prec, stream=stream) for md, d in zip(mds, datas)]
+
+    ref_insts = make(pdk.PD_FP64)
+    ref_tds = [pdk.time_desc(td.theta, td.K, td.T, pdk.TIME_UNIFORM, tol=1e-13) for td in tds]
+    pdk.solve_batch(ref_insts, ref_tds)
+    refs = [i.solution() for i in ref_insts]
+    # FP64, one instance at a time, on the first `sample_alone` instances
+    alone_cells, t_alone = 0, 0.0
+    for k, (inst, d, td) in enumerate(zip(ref_insts[:sample_alone], datas, tds)):
+        inst.set_solution(pdk.ring_vector(d["u0_origin"], d["u0_grid"]), 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inst.solve(td)
+        torch.cuda.synchronize()
+        t_alone += time.perf_counter() - t0
+        alone_cells += inst.N
+    for i in ref_insts:
+        i.close()
+    insts = make(pdk.PD_MIXED)
+    u0s = [pdk.ring_vector(d["u0_origin"], d["u0_grid"]) for d in datas]
+    tuned = autotune.tune(insts, tds, levels=3, sync=torch.cuda.synchronize)
+    for inst, u0 in zip(insts, u0s):
+        inst.set_solution(u0, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = pdk.solve_batch(insts, tds)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    errs = [float(np.linalg.norm(i.solution() - r) / np.linalg.norm(r)) for i, r in zip(insts, refs)]
+    for i in insts:
+        i.close()
+    return {
+        "workload": ("512 instances, m log-uniform [32,512], n log-uniform [64,1024], half parabolic / "
+                     "half drift-diffusion, theta U[0.5,1], dt=5e-4 fixed, 100 levels"),
+        "cells": cells,
+        "mixed_batched": {"value": round(cells * c["K"] / el, 1), "ms": round(1e3 * el, 1),
+                          "schedule": list(tuned["best"]), "autotune_ms_first_3_levels": tuned["ms"],
+                          "l2_rel_vs_fp64_converged_max": max(errs),
+                          "inner_iters_per_level_mean": round(float(np.mean(
+                              [np.mean([s["iters"] for s in x]) for x in st])), 2)},
+        "fp64_one_instance_at_a_time": {"value": round(alone_cells * c["K"] / t_alone, 1),
+                                        "sample": f"first {sample_alone} instances"},
+    }
+
+
 def cpu_baseline(levels, gpu_states):
     """The oracle on a bounded sample: one instance (seed 1200, θ = 0.5), the
     first `levels` time levels, one thread."""
@@ -199,6 +264,12 @@ def main():
     sample_state = inst0.solution(pdk.LAYOUT_PAPER)
 
     descs = time_descs(pdk, tds, args.tol)
+    # launch schedule (stream groups, cycles per graph) chosen by the
+    # autotuner on the first levels of this batch, outside the timed region
+    from paper_2509_15879_amd import autotune
+    reset(insts, u0s)
+    tuned = autotune.tune(insts, descs, levels=3, sync=torch.cuda.synchronize)
+    log(f"schedule {tuned['best']} from {tuned['ms']}")
     for w in range(args.warmup):
         reset(insts, u0s)
         pdk.solve_batch(insts, descs)
@@ -227,14 +298,19 @@ def main():
     # roofline of the dominant kernel: one more step of the same workload
     # with every launch stamped by a start and a stop event of its own
     # dispatch (the timed steps replay captured graphs, which carry none)
+    # (one stream group, so that no other launch shares the GPU with the one
+    # being stamped)
     reset(insts, u0s)
     torch.cuda.synchronize()
+    timed_schedule = pdk.get_schedule()
+    pdk.set_schedule(1, timed_schedule["cycles_per_graph"])
     pdk.kernel_timing(True, reset=True)
     t0 = time.perf_counter()
     pstats = pdk.solve_batch(insts, descs)
     torch.cuda.synchronize()
     prof_ms = 1e3 * (time.perf_counter() - t0)
     kms, kcnt = pdk.kernel_timing(False, reset=True)
+    pdk.set_schedule(timed_schedule["groups"], timed_schedule["cycles_per_graph"])
     w = 4 if prec == pdk.PD_MIXED else 8
     iters = [sum(s["iters"] for s in st) for st in pstats]      # per instance
     inst_cells = [i.N for i in insts]
@@ -271,6 +347,8 @@ def main():
             "instances": len(insts), "m": M, "n": N_TH, "unknowns_per_instance": M * N_TH + 1,
             "levels": K_LEVELS, "tol_per_step": args.tol, "precision": args.precision,
             "parallelism": "single GPU, batched instances",
+            "schedule": {"groups": tuned["best"][0], "cycles_per_graph": tuned["best"][1],
+                         "autotune_ms_first_3_levels": tuned["ms"]},
         },
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
@@ -298,6 +376,8 @@ def main():
             mix, _, _ = build_instances(pdk, pdk.PD_MIXED, stream)
             mdesc = time_descs(pdk, tds, args.tol)
             reset(mix, u0s)
+            mtuned = autotune.tune(mix, mdesc, levels=3, sync=torch.cuda.synchronize)
+            reset(mix, u0s)
             pdk.solve_batch(mix, mdesc)
             reset(mix, u0s)
             torch.cuda.synchronize()
@@ -307,6 +387,7 @@ def main():
             el = time.perf_counter() - t0
             me = max(float(np.linalg.norm(i.solution() - r) / np.linalg.norm(r)) for i, r in zip(mix, refs))
             var["mixed_batched"] = {"value": round(cells * K_LEVELS / el, 1), "ms": round(1e3 * el, 1),
+                                    "schedule": list(mtuned["best"]),
                                     "l2_rel_vs_fp64_converged_max": me,
                                     "inner_iters_per_level": round(float(np.mean(
                                         [sum(s["iters"] for s in st) for st in mst])) / K_LEVELS, 2),
@@ -315,6 +396,8 @@ def main():
             for i in mix:
                 i.close()
         log("precision configuration 1024x2048 ...")
+        log("uneven batch of 512 ...")
+        var["uneven_512"] = uneven_variant(pdk, stream, args.tol)
         # the finer mesh amplifies the residual more: 1e-12 meets the 1e-8 bar there
         var["precision_1024x2048"] = precision_variant(pdk, stream, 1e-12)
         out["variants"] = var

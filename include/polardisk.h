@@ -207,6 +207,10 @@ int pd_solve_batch(pd_instance *const *insts, int32_t count, const pd_time_desc 
 /* Current state n^k (N values) in the requested layout. */
 int pd_get_solution(const pd_instance *inst, double *out, int32_t layout, int32_t device_ptr);
 
+/* The time of the instance's current state (0 after create, else the last
+ * level reached or the time given to pd_set_solution).                   */
+int pd_get_time(const pd_instance *inst, double *t);
+
 /* Replaces the state by `in` (N values) at time t (checkpoint resume). */
 int pd_set_solution(pd_instance *inst, const double *in, int32_t layout, int32_t device_ptr,
                     double t);
@@ -318,6 +322,21 @@ int pd_batch_submit(pd_batch *batch, const pd_mesh_desc *mesh, const pd_problem_
 int pd_batch_poll(pd_batch *batch, uint64_t ticket, double *out, pd_request_summary *summary);
 int pd_batch_stats(pd_batch *batch, pd_batch_info *info);
 int pd_batch_destroy(pd_batch *batch);
+
+/* Launch schedule (process-wide default for later solves and serving
+ * plans).  groups: a batch is split into this many parts (by cells, largest
+ * first, each to the part with the fewest), each stepping on its own stream
+ * (the instances' stream and library-owned streams of default priority), so
+ * that the parts' launches overlap; results do not depend on it.
+ * cycles_per_graph: Krylov cycles per captured HIP graph (a part's
+ * active-instance count is read back after each graph).  NULL restores
+ * groups = 1, cycles_per_graph = 2.  PD_EINVAL outside [1, 8] / [1, 16].  */
+typedef struct {
+  int32_t groups;
+  int32_t cycles_per_graph;
+} pd_schedule;
+int pd_set_schedule(const pd_schedule *schedule);
+int pd_get_schedule(pd_schedule *schedule);
 
 /* Kernel timing (diagnostics).  While enabled, every kernel launch of the
  * solver goes through hipExtLaunchKernel with a start and a stop event that

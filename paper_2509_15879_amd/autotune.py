@@ -1,0 +1,76 @@
+"""Autotuner of the launch schedule of a batch.
+
+A batch's best schedule (how many stream groups it is split into, how many
+Krylov cycles one captured graph holds) depends on its instance sizes,
+precisions and convergence behaviour.  `tune` times the first levels of the
+batch's own solve under every candidate schedule, starting each time from
+the batch's current state (saved and restored, so tuning leaves no trace),
+then sets the fastest as the library's default and returns the table.
+Results are cached per batch signature (instance sizes and precisions).
+"""
+
+from __future__ import annotations
+
+import time
+from typing import Dict, List, Sequence, Tuple
+
+from . import polardisk as pdk
+
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 2), (2, 2), (3, 2), (2, 4), (3, 4), (1, 4))
+
+_cache: Dict[tuple, dict] = {}
+
+
+def signature(insts: Sequence["pdk.Instance"]) -> tuple:
+    return tuple(sorted((i.m, i.n, int(i.precision)) for i in insts))
+
+
+def _first_levels(td: "pdk.TimeDesc", t0: float, levels: int) -> "pdk.TimeDesc":
+    t = pdk.time_levels(td, t0)[:levels + 1]
+    return pdk.time_desc(td.theta, len(t) - 1, table=t, tol=td.tol, max_iters=td.max_iters)
+
+
+def tune(insts: Sequence["pdk.Instance"], tds: Sequence["pdk.TimeDesc"], levels: int = 3,
+         candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 2,
+         sync=None, use_cache: bool = True) -> dict:
+    """Chooses and sets the fastest schedule for advancing `insts` through
+    `tds`; returns {"best": (groups, cycles_per_graph), "ms": {...}}.
+
+    sync: callable that waits for the device (e.g. torch.cuda.synchronize);
+    the library's own calls already return after the work is done."""
+    key = signature(insts)
+    if use_cache and key in _cache:
+        best = _cache[key]["best"]
+        pdk.set_schedule(*best)
+        return _cache[key]
+    saved = [(i.solution(), i.time) for i in insts]
+    short = [_first_levels(td, t, levels) for td, (_, t) in zip(tds, saved)]
+    ms: Dict[Tuple[int, int], float] = {}
+    try:
+        for cand in candidates:
+            pdk.set_schedule(*cand)
+            best_t = float("inf")
+            for rep in range(repeats + 1):                # first run warms the plan up
+                for inst, (x, t) in zip(insts, saved):
+                    inst.set_solution(x, t)
+                if sync:
+                    sync()
+                t0 = time.perf_counter()
+                pdk.solve_batch(insts, short)
+                if sync:
+                    sync()
+                if rep:
+                    best_t = min(best_t, time.perf_counter() - t0)
+            ms[cand] = 1e3 * best_t
+    finally:
+        for inst, (x, t) in zip(insts, saved):
+            inst.set_solution(x, t)
+    best = min(ms, key=ms.get)
+    pdk.set_schedule(*best)
+    out = {"best": best, "ms": {f"{g}x{c}": round(v, 3) for (g, c), v in ms.items()}, "levels": levels}
+    _cache[key] = out
+    return out
+
+
+def tuned_schedules() -> List[dict]:
+    return [dict(signature=k, **v) for k, v in _cache.items()]

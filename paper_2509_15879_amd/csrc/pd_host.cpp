@@ -550,85 +550,193 @@ int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   return PD_OK;
 }
 
+// Library-owned helper streams (default priority), one pool per device,
+// created on first use and kept for the life of the process.
+hipStream_t helper_stream(int device, int k) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, hipStream_t> pool;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(device, k);
+  auto it = pool.find(key);
+  if (it != pool.end()) return it->second;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  pool.emplace(key, st);
+  return st;
+}
+
+// Launch schedule of an engine: how many stream groups a batch is split
+// into and how many Krylov cycles one captured graph holds.
+struct Schedule {
+  int groups = 1;
+  int cycles_per_graph = 2;
+};
+
+std::atomic<int> g_sched_groups{1}, g_sched_cpg{2};
+
+Schedule default_schedule() {
+  Schedule sc;
+  sc.groups = g_sched_groups.load();
+  sc.cycles_per_graph = g_sched_cpg.load();
+  return sc;
+}
+
 // A set of instances advancing level by level in shared launches.  The
-// Krylov cycles of a level repeat identically: kCyclesPerGraph of them,
-// followed by the read-back of the active-instance counter, are captured in
-// one HIP graph and replayed until every instance has finished the level
-// (one graph of look-ahead; a launch for finished instances is a no-op).
-// Per-kernel event timing needs the plain launches.
+// batch is split into `groups` parts (by cells, largest first, to the part
+// with the fewest), each with its own launch plan on its own stream, so that
+// one part's launch ramps and tails overlap the other parts' work; group 0
+// runs on the caller's stream, which every level forks from and joins.  The
+// Krylov cycles of a level repeat identically: cycles_per_graph of them,
+// followed by the read-back of the part's active-instance counter, are
+// captured in one HIP graph per part and replayed until the part has
+// finished the level (one graph of look-ahead; a launch for finished
+// instances is a no-op).  Per-kernel event timing needs plain launches.
 struct Engine {
-  static constexpr int kCyclesPerGraph = 2;
+  struct Group {
+    hipStream_t s = nullptr;
+    std::unique_ptr<Plan> P;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> members;   // engine instance indices, in plan order
+  };
   hipStream_t s = nullptr;
-  std::unique_ptr<Plan> P;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  std::vector<Group> G;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
   bool use_graph = false;
   int max_cycles = 0;
   int ninst = 0;
+  int cpg = 2;
 
   void release() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
-    P.reset();
+    for (auto &g : G) {
+      if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      if (g.s && g.s != s) (void)hipStreamSynchronize(g.s);
+      g.P.reset();
+    }
+    G.clear();
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (auto e : join_ev) (void)hipEventDestroy(e);
+    fork_ev = nullptr;
+    join_ev.clear();
   }
   ~Engine() { release(); }
 
-  int build(std::vector<pd_instance *> const &insts, int cycles_cap, hipStream_t st) {
+  int build(std::vector<pd_instance *> const &insts, int cycles_cap, hipStream_t st, Schedule sch = {}) {
     release();
     s = st;
     ninst = (int)insts.size();
     max_cycles = cycles_cap;
-    P.reset(new Plan);
-    int rc = make_plan(insts, s, *P);
-    if (rc) return rc;
+    cpg = std::max(1, sch.cycles_per_graph);
+    const int ng = std::max(1, std::min(sch.groups, ninst));
+    int device = 0;
+    HIPCHK(hipGetDevice(&device));
+    // partition by cells, largest first, each to the part with the fewest
+    std::vector<int> order(ninst);
+    for (int q = 0; q < ninst; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return (int64_t)insts[x]->M.m * insts[x]->M.n > (int64_t)insts[y]->M.m * insts[y]->M.n;
+    });
+    G.resize(ng);
+    std::vector<int64_t> load(ng, 0);
+    for (int q : order) {
+      int g = 0;
+      for (int k = 1; k < ng; ++k)
+        if (load[k] < load[g]) g = k;
+      G[g].members.push_back(q);
+      load[g] += (int64_t)insts[q]->M.m * insts[q]->M.n;
+    }
+    for (auto &g : G) std::sort(g.members.begin(), g.members.end());
+    HIPCHK(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+    join_ev.assign(ng, nullptr);
+    for (auto &e : join_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     use_graph = !pd::g_timer && !getenv("PD_NO_GRAPH");
-    if (use_graph) {
-      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      for (int c = 0; c < kCyclesPerGraph; ++c) pd::launch_cycle(P->L, s);
-      hipError_t ce = hipMemcpyAsync(&P->h_active[0], P->n_active, sizeof(int), hipMemcpyDeviceToHost, s);
-      hipError_t ee = hipStreamEndCapture(s, &graph);
-      if (ce != hipSuccess || ee != hipSuccess)
-        return fail(PD_EHIP, "graph capture failed: %s / %s", hipGetErrorString(ce), hipGetErrorString(ee));
-      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    for (int k = 0; k < ng; ++k) {
+      Group &g = G[k];
+      g.s = (k == 0) ? s : helper_stream(device, k);
+      if (!g.s) return fail(PD_EHIP, "could not create a helper stream");
+      std::vector<pd_instance *> part;
+      for (int q : g.members) part.push_back(insts[q]);
+      g.P.reset(new Plan);
+      int rc = make_plan(part, g.s, *g.P);
+      if (rc) return rc;
+      if (use_graph) {
+        HIPCHK(hipStreamBeginCapture(g.s, hipStreamCaptureModeThreadLocal));
+        for (int c = 0; c < cpg; ++c) pd::launch_cycle(g.P->L, g.s);
+        hipError_t ce = hipMemcpyAsync(&g.P->h_active[0], g.P->n_active, sizeof(int), hipMemcpyDeviceToHost, g.s);
+        hipError_t ee = hipStreamEndCapture(g.s, &g.graph);
+        if (ce != hipSuccess || ee != hipSuccess)
+          return fail(PD_EHIP, "graph capture failed: %s / %s", hipGetErrorString(ce), hipGetErrorString(ee));
+        HIPCHK(hipGraphInstantiate(&g.gexec, g.graph, nullptr, nullptr, 0));
+      }
     }
     return PD_OK;
   }
 
   // One time level of every instance that is not idle.
   int level() {
-    Plan &Q = *P;
-    pd::launch_level_begin(Q.L, s);
-    pd::launch_factor(Q.L, s);
-    pd::launch_begin(Q.L, s);
+    const int ng = (int)G.size();
+    // fork: every part sees the work queued before on the caller's stream
+    HIPCHK(hipEventRecord(fork_ev, s));
+    for (int k = 1; k < ng; ++k) HIPCHK(hipStreamWaitEvent(G[k].s, fork_ev, 0));
+    for (auto &g : G) {
+      pd::launch_level_begin(g.P->L, g.s);
+      pd::launch_factor(g.P->L, g.s);
+      pd::launch_begin(g.P->L, g.s);
+    }
+    std::vector<char> live(ng, 1);
+    int left = ng;
     if (use_graph) {
-      const int max_launch = (max_cycles + kCyclesPerGraph - 1) / kCyclesPerGraph;
-      for (int c = 0; c < max_launch; ++c) {
-        HIPCHK(hipGraphLaunch(gexec, s));
-        HIPCHK(hipEventRecord(Q.ev[c & 1], s));
-        if (c >= 1) {
-          // the slot holds the count after launch c-1 or a later one: the
-          // count never grows inside a level, so 0 means the level is done
-          HIPCHK(hipEventSynchronize(Q.ev[(c - 1) & 1]));
-          if (__atomic_load_n(&Q.h_active[0], __ATOMIC_ACQUIRE) == 0) break;
+      const int max_launch = (max_cycles + cpg - 1) / cpg;
+      for (int c = 0; c < max_launch && left > 0; ++c) {
+        for (int k = 0; k < ng; ++k) {
+          if (!live[k]) continue;
+          HIPCHK(hipGraphLaunch(G[k].gexec, G[k].s));
+          HIPCHK(hipEventRecord(G[k].P->ev[c & 1], G[k].s));
+        }
+        if (c < 1) continue;
+        for (int k = 0; k < ng; ++k) {
+          if (!live[k]) continue;
+          // the slot holds the part's count after launch c-1 or a later one:
+          // the count never grows inside a level, so 0 means the part is done
+          HIPCHK(hipEventSynchronize(G[k].P->ev[(c - 1) & 1]));
+          if (__atomic_load_n(&G[k].P->h_active[0], __ATOMIC_ACQUIRE) == 0) {
+            live[k] = 0;
+            --left;
+          }
         }
       }
     } else {
-      for (int c = 0; c < max_cycles; ++c) {
-        pd::launch_cycle(Q.L, s);
-        HIPCHK(hipMemcpyAsync(&Q.h_active[c & 1], Q.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(Q.ev[c & 1], s));
-        if (c >= 1) {
+      for (int c = 0; c < max_cycles && left > 0; ++c) {
+        for (int k = 0; k < ng; ++k) {
+          if (!live[k]) continue;
+          Plan &Q = *G[k].P;
+          pd::launch_cycle(Q.L, G[k].s);
+          HIPCHK(hipMemcpyAsync(&Q.h_active[c & 1], Q.n_active, sizeof(int), hipMemcpyDeviceToHost, G[k].s));
+          HIPCHK(hipEventRecord(Q.ev[c & 1], G[k].s));
+        }
+        if (c < 1) continue;
+        for (int k = 0; k < ng; ++k) {
+          if (!live[k]) continue;
+          Plan &Q = *G[k].P;
           HIPCHK(hipEventSynchronize(Q.ev[(c - 1) & 1]));
-          if (Q.h_active[(c - 1) & 1] == 0) break;
+          if (Q.h_active[(c - 1) & 1] == 0) {
+            live[k] = 0;
+            --left;
+          }
         }
       }
     }
     HIPCHK(hipGetLastError());
-    pd::launch_level_end(Q.L, s);
+    for (auto &g : G) pd::launch_level_end(g.P->L, g.s);
+    // join: the caller's stream waits for every part
+    for (int k = 1; k < ng; ++k) {
+      HIPCHK(hipEventRecord(join_ev[k], G[k].s));
+      HIPCHK(hipStreamWaitEvent(s, join_ev[k], 0));
+    }
     if (g_event_timer && pd::g_timer) {
-      HIPCHK(hipStreamSynchronize(s));
+      for (auto &g : G) HIPCHK(hipStreamSynchronize(g.s));
       g_event_timer->harvest();
     }
     return PD_OK;
@@ -636,9 +744,16 @@ struct Engine {
 
   // (levels done, status) of every instance after the last level (synchronises).
   int levels_done(std::vector<int> &out) {
-    out.resize(2 * (size_t)ninst);
-    HIPCHK(hipMemcpyAsync(out.data(), P->lvl, out.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    out.assign(2 * (size_t)ninst, 0);
+    for (auto &g : G) {
+      std::vector<int> part(2 * g.members.size());
+      HIPCHK(hipMemcpyAsync(part.data(), g.P->lvl, part.size() * sizeof(int), hipMemcpyDeviceToHost, g.s));
+      HIPCHK(hipStreamSynchronize(g.s));
+      for (size_t k = 0; k < g.members.size(); ++k) {
+        out[2 * (size_t)g.members[k]] = part[2 * k];
+        out[2 * (size_t)g.members[k] + 1] = part[2 * k + 1];
+      }
+    }
     return PD_OK;
   }
 };
@@ -672,7 +787,7 @@ int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &
     cap = std::max(cap, cycles_cap(sps[q]));
   }
   Engine E;
-  if ((rc = E.build(insts, cap, s))) return rc;
+  if ((rc = E.build(insts, cap, s, default_schedule()))) return rc;
   for (int lev = 0; lev < maxK; ++lev)
     if ((rc = E.level())) return rc;
   HIPCHK(hipGetLastError());
@@ -767,6 +882,27 @@ int solve_many(std::vector<pd_instance *> const &insts, std::vector<const pd_tim
 extern "C" {
 
 const char *pd_last_error(void) { return g_err.c_str(); }
+
+int pd_set_schedule(const pd_schedule *sc) {
+  if (!sc) {
+    g_sched_groups = 1;
+    g_sched_cpg = 2;
+    return PD_OK;
+  }
+  if (sc->groups < 1 || sc->groups > 8) return fail(PD_EINVAL, "groups must be in [1, 8]");
+  if (sc->cycles_per_graph < 1 || sc->cycles_per_graph > 16)
+    return fail(PD_EINVAL, "cycles_per_graph must be in [1, 16]");
+  g_sched_groups = sc->groups;
+  g_sched_cpg = sc->cycles_per_graph;
+  return PD_OK;
+}
+
+int pd_get_schedule(pd_schedule *sc) {
+  if (!sc) return fail(PD_EINVAL, "NULL argument");
+  sc->groups = g_sched_groups.load();
+  sc->cycles_per_graph = g_sched_cpg.load();
+  return PD_OK;
+}
 
 int pd_time_levels(const pd_time_desc *td, double t_start, double *out) {
   try {
@@ -1066,6 +1202,12 @@ int pd_get_solution(const pd_instance *I, double *out, int32_t layout, int32_t d
   } else {
     std::memcpy(out, o.data(), N * sizeof(double));
   }
+  return PD_OK;
+}
+
+int pd_get_time(const pd_instance *I, double *t) {
+  if (!I || !t) return fail(PD_EINVAL, "NULL argument");
+  *t = I->t;
   return PD_OK;
 }
 
@@ -1453,7 +1595,7 @@ void serve(pd_batch *B) {
         insts.push_back(R->inst);
         cap = std::max(cap, cycles_cap(R->sp));
       }
-      rc = E.build(insts, cap, B->stream);
+      rc = E.build(insts, cap, B->stream, default_schedule());
       dirty = false;
       std::lock_guard<std::mutex> lk(B->mu);
       B->info.plans_built += 1;

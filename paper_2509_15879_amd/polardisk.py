@@ -94,7 +94,8 @@ class Indicator(C.Structure):
 EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
-           "pd_batch_stats", "pd_error_indicator", "pd_remesh_transfer",
+           "pd_batch_stats", "pd_error_indicator", "pd_remesh_transfer", "pd_set_schedule",
+           "pd_get_schedule", "pd_get_time",
            "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
 
 KERNEL_FAMILIES = ("begin", "factor", "rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t",
@@ -127,6 +128,9 @@ def _load():
         "pd_batch_stats": [P, C.POINTER(BatchInfo)],
         "pd_error_indicator": [P, D, P, I32, P, P, C.POINTER(Indicator)],
         "pd_remesh_transfer": [P, P],
+        "pd_set_schedule": [P],
+        "pd_get_time": [P, P],
+        "pd_get_schedule": [P],
         "pd_batch_destroy": [P],
         "pd_kernel_timing": [I32, I32, P, P],
     }
@@ -292,6 +296,12 @@ class Instance:
         _check(lib.pd_get_solution(self.h, _ptr(out), int(layout), 0))
         return out
 
+    @property
+    def time(self) -> float:
+        t = C.c_double()
+        _check(lib.pd_get_time(self.h, C.byref(t)))
+        return t.value
+
     def set_solution(self, x, t, layout=LAYOUT_RING):
         a = _f64(x)
         _check(lib.pd_set_solution(self.h, _ptr(a), int(layout), 0, float(t)))
@@ -396,6 +406,22 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Schedule(C.Structure):
+    _fields_ = [("groups", C.c_int32), ("cycles_per_graph", C.c_int32)]
+
+
+def set_schedule(groups=1, cycles_per_graph=2):
+    """Default launch schedule of later solves: stream groups and cycles per graph."""
+    sc = Schedule(int(groups), int(cycles_per_graph))
+    _check(lib.pd_set_schedule(C.byref(sc)))
+
+
+def get_schedule():
+    sc = Schedule()
+    _check(lib.pd_get_schedule(C.byref(sc)))
+    return {"groups": sc.groups, "cycles_per_graph": sc.cycles_per_graph}
 
 
 def kernel_timing(enable: bool, reset: bool = False):

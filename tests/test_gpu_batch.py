@@ -117,3 +117,44 @@ def test_graph_replay_equals_plain_launches(monkeypatch):
             p[0].close()
     for a, b in zip(res["graph"], res["plain"]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("schedule", [(2, 2), (3, 1), (2, 4)])
+def test_stream_groups_give_identical_results(schedule):
+    """A batch split over several streams (and any cycles per graph) gives
+    exactly the results of one stream."""
+    say(f"[batch] schedule {schedule} vs (1, 2)")
+    from paper_2509_15879_amd import polardisk as pdk
+    res = {}
+    try:
+        for sch in ((1, 2), schedule):
+            pdk.set_schedule(*sch)
+            pairs = make_set((0, 1, 0))
+            pdk.solve_batch([p[0] for p in pairs], [p[1] for p in pairs])
+            res[sch] = [p[0].solution() for p in pairs]
+            for p in pairs:
+                p[0].close()
+    finally:
+        pdk.set_schedule(1, 2)
+    for a, b in zip(res[(1, 2)], res[schedule]):
+        assert np.array_equal(a, b)
+
+
+def test_autotune_leaves_the_state_and_picks_a_timed_candidate():
+    say("[batch] autotuner")
+    from paper_2509_15879_amd import autotune
+    from paper_2509_15879_amd import polardisk as pdk
+    pairs = make_set()
+    insts, tds = [p[0] for p in pairs], [p[1] for p in pairs]
+    before = [i.solution() for i in insts]
+    try:
+        out = autotune.tune(insts, tds, levels=2, candidates=((1, 2), (2, 2), (2, 4)),
+                            use_cache=False)
+        assert tuple(out["best"]) in ((1, 2), (2, 2), (2, 4)) and len(out["ms"]) == 3
+        assert pdk.get_schedule() == {"groups": out["best"][0], "cycles_per_graph": out["best"][1]}
+        for i, x in zip(insts, before):
+            assert np.array_equal(i.solution(), x) and i.time == 0.0
+    finally:
+        pdk.set_schedule(1, 2)
+        for i in insts:
+            i.close()
