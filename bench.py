@@ -195,6 +195,70 @@ def uneven_variant(pdk, stream, tol, sample_alone=32):
     }
 
 
+def serving_variant(pdk, duration=8.0, check=6):
+    """The serving loop under a Poisson request stream (200 requests/s for
+    `duration` seconds, mixed precision): latency percentiles, aggregate
+    throughput and utilisation; `check` requests are compared with the same
+    solve alone in FP64 at a tight tolerance."""
+    from problems import sample
+    from problems.workloads import CFG5, cfg5_arrivals, cfg5_templates
+    c = CFG5
+    temps = []
+    for m, n, pb in cfg5_templates():
+        md = pdk.mesh_desc(m, n, pdk.MESH_SINE, c["p"])
+        temps.append((md, sample(pb, *pdk.mesh_coords(md)), m * n + 1))
+    arr = cfg5_arrivals(duration)
+    B = pdk.Batch(200 << 30, 4096)
+    tickets, sub_t = [], []
+    t_start = time.perf_counter()
+    for (ta, k, theta, tol, K) in arr:
+        now = time.perf_counter() - t_start
+        if ta > now:
+            time.sleep(ta - now)
+        md, data, N = temps[k]
+        td = pdk.time_desc(theta, K, K * c["dt"], pdk.TIME_UNIFORM, tol=tol)
+        tickets.append(B.submit(md, data, td, pdk.PD_MIXED))
+    results = {}
+    while len(results) < len(tickets):
+        for tk in tickets:
+            if tk not in results:
+                r = B.poll(tk)
+                if r is not None:
+                    results[tk] = r
+        time.sleep(2e-4)
+    t_end = time.perf_counter()
+    info = B.stats()
+    B.close()
+    lat = np.array([results[tk][1]["latency_s"] for tk in tickets])
+    work = sum(temps[k][2] * K for (_, k, _, _, K) in arr)
+    wall = t_end - t_start
+    # accuracy of a few served results against FP64 alone at a tight tolerance
+    errs = {}
+    for idx in np.linspace(0, len(arr) - 1, check).astype(int):
+        ta, k, theta, tol, K = arr[idx]
+        md, data, N = temps[k]
+        inst = pdk.Instance(md, data, pdk.PD_FP64)
+        inst.solve(pdk.time_desc(theta, K, K * c["dt"], pdk.TIME_UNIFORM, tol=1e-13))
+        ref = inst.solution()
+        inst.close()
+        x = results[tickets[idx]][0]
+        errs.setdefault(f"tol {tol:g}", []).append(float(np.linalg.norm(x - ref) / np.linalg.norm(ref)))
+    return {
+        "workload": (f"Poisson arrivals {c['rate']:g}/s for {duration:g} s, {len(arr)} requests from "
+                     f"{len(temps)} templates (m log-U[32,1024], n log-U[64,2048], PDE 50/50), "
+                     "theta U[0.5,1], tol 1e-6 or 1e-8, T log-U[5e-3,5e-2] at dt=1e-3, mixed precision"),
+        "requests": len(arr),
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+        "value": round(work / wall, 1), "unit": "cell-updates/s",
+        "offered_cell_updates_per_s": round(work / duration, 1),
+        "utilisation": round((work / duration) / (work / wall), 3),
+        "wall_s": round(wall, 2),
+        "peak_active": info["peak_active"], "plans_built": info["plans_built"],
+        "l2_rel_vs_fp64_alone_sample": {k: max(v) for k, v in errs.items()},
+    }
+
+
 def cpu_baseline(levels, gpu_states):
     """The oracle on a bounded sample: one instance (seed 1200, θ = 0.5), the
     first `levels` time levels, one thread."""
@@ -396,6 +460,8 @@ def main():
             for i in mix:
                 i.close()
         log("precision configuration 1024x2048 ...")
+        log("serving stream ...")
+        var["serving"] = serving_variant(pdk)
         log("uneven batch of 512 ...")
         var["uneven_512"] = uneven_variant(pdk, stream, args.tol)
         # the finer mesh amplifies the residual more: 1e-12 meets the 1e-8 bar there

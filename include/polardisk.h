@@ -312,7 +312,7 @@ typedef struct {
   int32_t active;        /* admitted, stepping                              */
   int32_t peak_active;   /* most requests active at once                    */
   int32_t reserved;
-  uint64_t submitted, completed, levels_run, plans_built;
+  uint64_t submitted, completed, slices_run, plans_built;
   size_t used_bytes, peak_bytes;   /* admitted footprint, now and at most   */
 } pd_batch_info;
 

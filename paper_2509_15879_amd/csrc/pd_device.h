@@ -29,6 +29,9 @@ enum { ST_IDLE = 0, ST_ACTIVE = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOCONV = 4 
 enum { PH_INNER = 0, PH_OUTER = 1 };
 // What the next radial p-sweep closes: an update step, a level's begin, a refinement.
 enum { PEND_UPDATE = 0, PEND_BEGIN = 1, PEND_REFINE = 2 };
+// Stage of an instance's level: its factorisation and right-hand side are
+// due (START), or it is iterating (ITER).
+enum { STAGE_ITER = 0, STAGE_START = 1 };
 
 // Counter slots (per instance; kept for the layout of older tools).
 enum { CNT_BEGIN = 0, CNT_V = 1, CNT_T = 2, CNT_X = 3, CNT_UR = 4, CNT_APPLY = 5, CNT_N = 8 };
@@ -45,6 +48,7 @@ struct PdScalars {
   int inner_first, have_prev, rot, nfail;
   int max_outer, maxit_inner, total_iters, pad1;
   int pend, restarted;      // what the next radial p-sweep closes; restart flag
+  int stage, in_level;      // STAGE_* of the level under way; a level has been started
   // Krylov scalars
   double rho_next, rho_cur; // ρ of this iteration (set by the p-sweep), of the last (by the s-sweep)
   double rho_old, rho_new, alpha, omega;

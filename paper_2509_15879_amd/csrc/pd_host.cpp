@@ -547,6 +547,8 @@ int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   h.t_now = I->t;
   HIPCHK(hipMemcpyAsync(I->sc, &h, sizeof h, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));
+  // levels never taken read as not done
+  if (I->stats) HIPCHK(hipMemsetAsync(I->stats, 0, 8 * (size_t)K * sizeof(double), s));
   return PD_OK;
 }
 
@@ -581,16 +583,20 @@ Schedule default_schedule() {
   return sc;
 }
 
-// A set of instances advancing level by level in shared launches.  The
-// batch is split into `groups` parts (by cells, largest first, to the part
-// with the fewest), each with its own launch plan on its own stream, so that
-// one part's launch ramps and tails overlap the other parts' work; group 0
-// runs on the caller's stream, which every level forks from and joins.  The
-// Krylov cycles of a level repeat identically: cycles_per_graph of them,
-// followed by the read-back of the part's active-instance counter, are
-// captured in one HIP graph per part and replayed until the part has
-// finished the level (one graph of look-ahead; a launch for finished
-// instances is a no-op).  Per-kernel event timing needs plain launches.
+// A set of instances advancing through their time levels in shared
+// launches, each at its own pace (asynchronous levels: an instance whose
+// level has ended starts its next one at the next round, whatever the
+// others are doing).  A round is the level-control head (control kernel,
+// factorisations and right-hand sides of the instances starting a level)
+// and cycles_per_graph Krylov cycles; it is captured, with the read-back of
+// the active-instance counter, in one HIP graph and replayed until every
+// instance has taken all its levels (one graph of look-ahead; launches for
+// finished instances are no-ops).  The batch is split into `groups` parts
+// (by cells, largest first, to the part with the fewest), each with its own
+// launch plan and graph on its own stream, so that one part's launch ramps
+// and tails overlap the other parts' work; group 0 runs on the caller's
+// stream, which every run forks from and joins.  Per-kernel event timing
+// needs plain launches.
 struct Engine {
   struct Group {
     hipStream_t s = nullptr;
@@ -661,9 +667,11 @@ struct Engine {
       g.P.reset(new Plan);
       int rc = make_plan(part, g.s, *g.P);
       if (rc) return rc;
+      // every member still has levels to take
+      HIPCHK(hipMemsetD32Async((hipDeviceptr_t)g.P->n_active, (int)part.size(), 1, g.s));
       if (use_graph) {
         HIPCHK(hipStreamBeginCapture(g.s, hipStreamCaptureModeThreadLocal));
-        for (int c = 0; c < cpg; ++c) pd::launch_cycle(g.P->L, g.s);
+        pd::launch_round(g.P->L, cpg, g.s);
         hipError_t ce = hipMemcpyAsync(&g.P->h_active[0], g.P->n_active, sizeof(int), hipMemcpyDeviceToHost, g.s);
         hipError_t ee = hipStreamEndCapture(g.s, &g.graph);
         if (ce != hipSuccess || ee != hipSuccess)
@@ -674,75 +682,57 @@ struct Engine {
     return PD_OK;
   }
 
-  // One time level of every instance that is not idle.
-  int level() {
+  // Replays cycles until every part's active-instance count reaches 0 (all
+  // instances have taken all their levels) or max_cycles cycles have been
+  // launched; returns whether everything finished.  Work stays queued on
+  // the parts' streams; the caller's stream is joined to them.
+  int run(long max_cycles_run, bool *finished) {
     const int ng = (int)G.size();
-    // fork: every part sees the work queued before on the caller's stream
     HIPCHK(hipEventRecord(fork_ev, s));
     for (int k = 1; k < ng; ++k) HIPCHK(hipStreamWaitEvent(G[k].s, fork_ev, 0));
-    for (auto &g : G) {
-      pd::launch_level_begin(g.P->L, g.s);
-      pd::launch_factor(g.P->L, g.s);
-      pd::launch_begin(g.P->L, g.s);
-    }
     std::vector<char> live(ng, 1);
     int left = ng;
-    if (use_graph) {
-      const int max_launch = (max_cycles + cpg - 1) / cpg;
-      for (int c = 0; c < max_launch && left > 0; ++c) {
-        for (int k = 0; k < ng; ++k) {
-          if (!live[k]) continue;
+    const long max_launch = (max_cycles_run + cpg - 1) / cpg;   // rounds of cpg cycles
+    for (long c = 0; c < max_launch && left > 0; ++c) {
+      for (int k = 0; k < ng; ++k) {
+        if (!live[k]) continue;
+        Plan &Q = *G[k].P;
+        if (use_graph) {
           HIPCHK(hipGraphLaunch(G[k].gexec, G[k].s));
-          HIPCHK(hipEventRecord(G[k].P->ev[c & 1], G[k].s));
+        } else {
+          pd::launch_round(Q.L, cpg, G[k].s);
+          HIPCHK(hipMemcpyAsync(&Q.h_active[c & 1], Q.n_active, sizeof(int), hipMemcpyDeviceToHost, G[k].s));
         }
-        if (c < 1) continue;
-        for (int k = 0; k < ng; ++k) {
-          if (!live[k]) continue;
-          // the slot holds the part's count after launch c-1 or a later one:
-          // the count never grows inside a level, so 0 means the part is done
-          HIPCHK(hipEventSynchronize(G[k].P->ev[(c - 1) & 1]));
-          if (__atomic_load_n(&G[k].P->h_active[0], __ATOMIC_ACQUIRE) == 0) {
-            live[k] = 0;
-            --left;
-          }
+        HIPCHK(hipEventRecord(Q.ev[c & 1], G[k].s));
+      }
+      if (c < 1) continue;
+      for (int k = 0; k < ng; ++k) {
+        if (!live[k]) continue;
+        Plan &Q = *G[k].P;
+        // the slot holds the part's count after launch c-1 or a later one;
+        // the count never grows, so 0 means the part is done
+        HIPCHK(hipEventSynchronize(Q.ev[(c - 1) & 1]));
+        const int na = use_graph ? __atomic_load_n(&Q.h_active[0], __ATOMIC_ACQUIRE) : Q.h_active[(c - 1) & 1];
+        if (na == 0) {
+          live[k] = 0;
+          --left;
         }
       }
-    } else {
-      for (int c = 0; c < max_cycles && left > 0; ++c) {
-        for (int k = 0; k < ng; ++k) {
-          if (!live[k]) continue;
-          Plan &Q = *G[k].P;
-          pd::launch_cycle(Q.L, G[k].s);
-          HIPCHK(hipMemcpyAsync(&Q.h_active[c & 1], Q.n_active, sizeof(int), hipMemcpyDeviceToHost, G[k].s));
-          HIPCHK(hipEventRecord(Q.ev[c & 1], G[k].s));
-        }
-        if (c < 1) continue;
-        for (int k = 0; k < ng; ++k) {
-          if (!live[k]) continue;
-          Plan &Q = *G[k].P;
-          HIPCHK(hipEventSynchronize(Q.ev[(c - 1) & 1]));
-          if (Q.h_active[(c - 1) & 1] == 0) {
-            live[k] = 0;
-            --left;
-          }
-        }
+      if (g_event_timer && pd::g_timer) {
+        for (auto &g : G) HIPCHK(hipStreamSynchronize(g.s));
+        g_event_timer->harvest();
       }
     }
     HIPCHK(hipGetLastError());
-    for (auto &g : G) pd::launch_level_end(g.P->L, g.s);
-    // join: the caller's stream waits for every part
     for (int k = 1; k < ng; ++k) {
       HIPCHK(hipEventRecord(join_ev[k], G[k].s));
       HIPCHK(hipStreamWaitEvent(s, join_ev[k], 0));
     }
-    if (g_event_timer && pd::g_timer) {
-      for (auto &g : G) HIPCHK(hipStreamSynchronize(g.s));
-      g_event_timer->harvest();
-    }
+    if (finished) *finished = left == 0;
     return PD_OK;
   }
 
-  // (levels done, status) of every instance after the last level (synchronises).
+  // (levels done, left-the-batch flag) of every instance (synchronises).
   int levels_done(std::vector<int> &out) {
     out.assign(2 * (size_t)ninst, 0);
     for (auto &g : G) {
@@ -788,10 +778,12 @@ int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &
   }
   Engine E;
   if ((rc = E.build(insts, cap, s, default_schedule()))) return rc;
-  for (int lev = 0; lev < maxK; ++lev)
-    if ((rc = E.level())) return rc;
+  bool finished = false;
+  if ((rc = E.run((long)maxK * cap + 2 * maxK, &finished))) return rc;
   HIPCHK(hipGetLastError());
+  for (auto &g : E.G) HIPCHK(hipStreamSynchronize(g.s));
   HIPCHK(hipStreamSynchronize(s));
+  if (!finished) return fail(PD_ENOCONV, "the batch did not finish within its cycle cap");
   int worst = PD_OK;
   for (size_t q = 0; q < insts.size(); ++q) {
     std::vector<double> st;
@@ -877,6 +869,194 @@ int solve_many(std::vector<pd_instance *> const &insts, std::vector<const pd_tim
 
 }  // namespace
 
+// ------------------------------------------------------------------ instance set-up
+//
+// Creating an instance has a host part (mesh, face coefficients, layout
+// changes: no device call) and a device part (allocation and uploads), so
+// that a serving loop can prepare requests on the submitting thread and
+// only upload them when it admits them.
+
+// Host staging of every array an instance uploads.
+struct HostImage {
+  std::vector<double> inv_rw, inv_dth, r, th;
+  std::vector<double> gpr, gmr, gpt, gmt;
+  std::vector<float> f_gpr, f_gmr, f_gpt, f_gmt;
+  std::vector<double> b_int, g_int, nb, u0_int;
+  double lam[PD_MAXSRC] = {0, 0, 0, 0};
+  int tp[PD_MAXSRC] = {0, 0, 0, 0};
+  bool has_b = false;
+};
+
+int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_t precision,
+                     std::unique_ptr<pd_instance> &out, std::unique_ptr<HostImage> &img_out) {
+  if (!pb) return fail(PD_EINVAL, "problem descriptor is NULL");
+  if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision %d", precision);
+  if (pb->nsrc < 0 || pb->nsrc > PD_MAXSRC) return fail(PD_EINVAL, "nsrc must be in [0, %d]", PD_MAXSRC);
+  if (pb->flux != 0 && pb->flux != 1) return fail(PD_EINVAL, "flux must be 0 or 1");
+  if (pb->bc != 0 && pb->bc != 1) return fail(PD_EINVAL, "bc must be 0 or 1");
+  if (pb->layout != PD_LAYOUT_RING && pb->layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
+  std::unique_ptr<pd_instance> I(new pd_instance);
+  std::unique_ptr<HostImage> img(new HostImage);
+  HostImage &X = *img;
+  int rc = build_mesh(mesh, I->M);
+  if (rc) return rc;
+  const int m = I->M.m, n = I->M.n, N = m * n + 1;
+  I->T = make_tiling(m, n);
+  I->precision = precision;
+  I->pde = pb->pde;
+  I->flux = pb->flux;
+  I->bc = pb->bc;
+  I->nsrc = pb->nsrc;
+  const MeshH &M = I->M;
+  const int np = I->T.npad;
+  std::vector<double> Dr, Er, Dt, Et, bn, g, u0;
+  const int dp = pb->device_ptrs;
+  if (pb->D_rface) { if ((rc = fetch(pb->D_rface, (size_t)(m + 1) * n, dp, Dr))) return rc; }
+  else Dr.assign((size_t)(m + 1) * n, 1.0);
+  if (pb->Er_rface) { if ((rc = fetch(pb->Er_rface, (size_t)(m + 1) * n, dp, Er))) return rc; }
+  else Er.assign((size_t)(m + 1) * n, 0.0);
+  if (pb->D_tface) { if ((rc = fetch(pb->D_tface, (size_t)m * n, dp, Dt))) return rc; }
+  else Dt.assign((size_t)m * n, 1.0);
+  if (pb->Et_tface) { if ((rc = fetch(pb->Et_tface, (size_t)m * n, dp, Et))) return rc; }
+  else Et.assign((size_t)m * n, 0.0);
+  if ((rc = fetch(pb->u0, N, dp, u0))) return rc;
+  if (pb->nsrc > 0) {
+    if (!pb->lambda) return fail(PD_EINVAL, "lambda is NULL");
+    if ((rc = fetch(pb->g, (size_t)pb->nsrc * N, dp, g))) return rc;
+    if (pb->nb) { if ((rc = fetch(pb->nb, (size_t)pb->nsrc * n, dp, X.nb))) return rc; }
+    else X.nb.assign((size_t)pb->nsrc * n, 0.0);
+    for (int q = 0; q < pb->nsrc; ++q) {
+      X.lam[q] = pb->lambda[q];
+      X.tp[q] = pb->tpow ? pb->tpow[q] : 0;
+      if (X.tp[q] < 0 || X.tp[q] > 8) return fail(PD_EINVAL, "tpow must be in [0, 8]");
+    }
+  }
+  X.has_b = pb->b_node != nullptr;
+  if (X.has_b && (rc = fetch(pb->b_node, N, dp, bn))) return rc;
+  for (double v : Dr) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "D_rface must be finite and >= 0");
+  for (double v : Dt) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "D_tface must be finite and >= 0");
+  for (double v : u0) if (!std::isfinite(v)) return fail(PD_EINVAL, "u0 has a non-finite value");
+  // faces
+  X.gpr.resize((size_t)(m + 1) * n);
+  X.gmr.resize((size_t)(m + 1) * n);
+  X.gpt.resize((size_t)m * n);
+  X.gmt.resize((size_t)m * n);
+  for (int i = 0; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t k = (size_t)i * n + j;
+      const double area = M.rh[i] * M.dth[j];
+      double G = Dr[k] * area / M.h[i + 1], K = Er[k] * area;
+      if (i == m && I->bc == 1) G = K = 0.0;
+      face_pair(G, K, I->flux, X.gpr[k], X.gmr[k]);
+    }
+  for (int i = 1; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t k = (size_t)(i - 1) * n + j;
+      const double G = Dt[k] * M.w[i] / (M.r[i] * M.mu[j + 1]);
+      const double K = Et[k] * M.w[i];
+      face_pair(G, K, I->flux, X.gpt[k], X.gmt[k]);
+    }
+  X.inv_rw.assign(m + 2, 0.0);
+  X.inv_dth.resize(n);
+  for (int i = 1; i <= m; ++i) X.inv_rw[i] = 1.0 / (M.r[i] * M.w[i]);
+  for (int j = 0; j < n; ++j) X.inv_dth[j] = 1.0 / M.dth[j];
+  X.r = M.r;
+  X.th = M.th;
+  I->H.inv_V0 = 1.0 / (kPi * 0.25 * M.h[1] * M.h[1]);
+  if (precision == PD_MIXED) {
+    X.f_gpr.assign(X.gpr.begin(), X.gpr.end());
+    X.f_gmr.assign(X.gmr.begin(), X.gmr.end());
+    X.f_gpt.assign(X.gpt.begin(), X.gpt.end());
+    X.f_gmt.assign(X.gmt.begin(), X.gmt.end());
+  }
+  if (X.has_b) {
+    X.b_int.resize(np);
+    to_internal(bn.data(), pb->layout, m, n, np, X.b_int.data());
+  }
+  X.g_int.resize((size_t)pb->nsrc * np);
+  for (int q = 0; q < pb->nsrc; ++q)
+    to_internal(g.data() + (size_t)q * N, pb->layout, m, n, np, X.g_int.data() + (size_t)q * np);
+  X.u0_int.resize(np);
+  to_internal(u0.data(), pb->layout, m, n, np, X.u0_int.data());
+  out = std::move(I);
+  img_out = std::move(img);
+  return PD_OK;
+}
+
+// Device allocation and uploads of a prepared instance on I->stream
+// (returns once the uploads are done; the image may then be dropped).
+int upload_instance(pd_instance *I, const HostImage &X) {
+  const int m = I->M.m, n = I->M.n;
+  const int np = I->T.npad;
+  Carver dry{nullptr, 0, true};
+  carve(I, dry);
+  I->dbytes = dry.off;
+  hipError_t e = hipMalloc(&I->dmem, I->dbytes);
+  if (e != hipSuccess) {
+    I->dmem = nullptr;
+    return fail(e == hipErrorOutOfMemory ? PD_ENOMEM : PD_EHIP, "device allocation of %zu bytes failed: %s",
+                I->dbytes, hipGetErrorString(e));
+  }
+  hipStream_t s = I->stream;
+  HIPCHK(hipMemsetAsync(I->dmem, 0, I->dbytes, s));
+  Carver cv{(char *)I->dmem, 0, false};
+  carve(I, cv);
+  PdInst &H = I->H;
+  H.m = m;
+  H.n = n;
+  H.npad = np;
+  H.nsrc = I->nsrc;
+  H.mixed = I->precision == PD_MIXED;
+  H.has_b = X.has_b;
+  H.zero_flux = I->bc;
+  H.ncg = I->T.ncg;
+  H.nrg = I->T.nrg;
+  H.nb_sten = I->T.nb_sten;
+  H.nb_elem = I->T.nb_elem;
+  H.cw = I->T.cw;
+  H.nseg = I->T.nseg;
+  H.brad = I->T.brad;
+  H.nb_rad = I->T.nb_rad;
+  H.bang = I->T.bang;
+  H.nb_ang = I->T.nb_ang;
+  H.nb_frad = I->T.nb_frad;
+  H.nb_fang = I->T.nb_fang;
+  if (!X.has_b) H.b_node = nullptr;
+  auto up = [&](const void *dst, const void *src, size_t bytes) -> int {
+    if (bytes == 0) return PD_OK;
+    HIPCHK(hipMemcpyAsync(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice, s));
+    return PD_OK;
+  };
+  int rc;
+  if ((rc = up(H.inv_rw, X.inv_rw.data(), X.inv_rw.size() * 8))) return rc;
+  if ((rc = up(H.inv_dth, X.inv_dth.data(), X.inv_dth.size() * 8))) return rc;
+  if ((rc = up(H.r_nodes, X.r.data(), X.r.size() * 8))) return rc;
+  if ((rc = up(H.th_nodes, X.th.data(), X.th.size() * 8))) return rc;
+  if ((rc = up(H.k64.gp_r, X.gpr.data(), X.gpr.size() * 8))) return rc;
+  if ((rc = up(H.k64.gm_r, X.gmr.data(), X.gmr.size() * 8))) return rc;
+  if ((rc = up(H.k64.gp_t, X.gpt.data(), X.gpt.size() * 8))) return rc;
+  if ((rc = up(H.k64.gm_t, X.gmt.data(), X.gmt.size() * 8))) return rc;
+  if (H.mixed) {
+    if ((rc = up(H.k32.gp_r, X.f_gpr.data(), X.f_gpr.size() * 4))) return rc;
+    if ((rc = up(H.k32.gm_r, X.f_gmr.data(), X.f_gmr.size() * 4))) return rc;
+    if ((rc = up(H.k32.gp_t, X.f_gpt.data(), X.f_gpt.size() * 4))) return rc;
+    if ((rc = up(H.k32.gm_t, X.f_gmt.data(), X.f_gmt.size() * 4))) return rc;
+  }
+  if (X.has_b && (rc = up(H.b_node, X.b_int.data(), (size_t)np * 8))) return rc;
+  if ((rc = up(H.g, X.g_int.data(), X.g_int.size() * 8))) return rc;
+  if (I->nsrc > 0) {
+    if ((rc = up(H.nb, X.nb.data(), X.nb.size() * 8))) return rc;
+    if ((rc = up(H.lam, X.lam, sizeof X.lam))) return rc;
+    if ((rc = up(H.tpow, X.tp, sizeof X.tp))) return rc;
+  }
+  I->rot = 0;
+  if ((rc = up(H.sol[1], X.u0_int.data(), (size_t)np * 8))) return rc;
+  if ((rc = ensure_time_capacity(I, 16))) return rc;
+  HIPCHK(hipStreamSynchronize(s));
+  I->t = 0.0;
+  return PD_OK;
+}
+
 // ================================================================== C ABI
 
 extern "C" {
@@ -950,22 +1130,10 @@ int pd_mesh_create(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_t 
                    void *hip_stream, pd_instance **out) {
   if (!out) return fail(PD_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!pb) return fail(PD_EINVAL, "problem descriptor is NULL");
-  if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision %d", precision);
-  if (pb->nsrc < 0 || pb->nsrc > PD_MAXSRC) return fail(PD_EINVAL, "nsrc must be in [0, %d]", PD_MAXSRC);
-  if (pb->flux != 0 && pb->flux != 1) return fail(PD_EINVAL, "flux must be 0 or 1");
-  if (pb->bc != 0 && pb->bc != 1) return fail(PD_EINVAL, "bc must be 0 or 1");
-  if (pb->layout != PD_LAYOUT_RING && pb->layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
-  std::unique_ptr<pd_instance> I(new pd_instance);
-  int rc = build_mesh(mesh, I->M);
+  std::unique_ptr<pd_instance> I;
+  std::unique_ptr<HostImage> img;
+  int rc = prepare_instance(mesh, pb, precision, I, img);
   if (rc) return rc;
-  const int m = I->M.m, n = I->M.n, N = m * n + 1;
-  I->T = make_tiling(m, n);
-  I->precision = precision;
-  I->pde = pb->pde;
-  I->flux = pb->flux;
-  I->bc = pb->bc;
-  I->nsrc = pb->nsrc;
   HIPCHK(hipGetDevice(&I->device));
   if (hip_stream) {
     I->stream = (hipStream_t)hip_stream;
@@ -984,137 +1152,12 @@ int pd_mesh_create(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_t 
     I->stream = it->second;
     I->own_stream = false;
   }
-  const MeshH &M = I->M;
-  const int np = I->T.npad;
-  // ---- host-side preparation of every device array
-  std::vector<double> Dr, Er, Dt, Et, bn, g, nb, u0;
-  const int dp = pb->device_ptrs;
-  if (pb->D_rface) { if ((rc = fetch(pb->D_rface, (size_t)(m + 1) * n, dp, Dr))) return rc; }
-  else Dr.assign((size_t)(m + 1) * n, 1.0);
-  if (pb->Er_rface) { if ((rc = fetch(pb->Er_rface, (size_t)(m + 1) * n, dp, Er))) return rc; }
-  else Er.assign((size_t)(m + 1) * n, 0.0);
-  if (pb->D_tface) { if ((rc = fetch(pb->D_tface, (size_t)m * n, dp, Dt))) return rc; }
-  else Dt.assign((size_t)m * n, 1.0);
-  if (pb->Et_tface) { if ((rc = fetch(pb->Et_tface, (size_t)m * n, dp, Et))) return rc; }
-  else Et.assign((size_t)m * n, 0.0);
-  if ((rc = fetch(pb->u0, N, dp, u0))) return rc;
-  if (pb->nsrc > 0) {
-    if (!pb->lambda) return fail(PD_EINVAL, "lambda is NULL");
-    if ((rc = fetch(pb->g, (size_t)pb->nsrc * N, dp, g))) return rc;
-    if (pb->nb) { if ((rc = fetch(pb->nb, (size_t)pb->nsrc * n, dp, nb))) return rc; }
-    else nb.assign((size_t)pb->nsrc * n, 0.0);
+  if ((rc = upload_instance(I.get(), *img))) {
+    if (I->dmem) (void)hipFree(I->dmem);
+    if (I->t_table) (void)hipFree(I->t_table);
+    if (I->stats) (void)hipFree(I->stats);
+    return rc;
   }
-  const bool has_b = pb->b_node != nullptr;
-  if (has_b && (rc = fetch(pb->b_node, N, dp, bn))) return rc;
-  for (double v : Dr) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "D_rface must be finite and >= 0");
-  for (double v : Dt) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "D_tface must be finite and >= 0");
-  for (double v : u0) if (!std::isfinite(v)) return fail(PD_EINVAL, "u0 has a non-finite value");
-  // faces
-  std::vector<double> gpr((size_t)(m + 1) * n), gmr((size_t)(m + 1) * n), gpt((size_t)m * n), gmt((size_t)m * n);
-  for (int i = 0; i <= m; ++i)
-    for (int j = 0; j < n; ++j) {
-      const size_t k = (size_t)i * n + j;
-      const double area = M.rh[i] * M.dth[j];
-      double G = Dr[k] * area / M.h[i + 1], K = Er[k] * area;
-      if (i == m && I->bc == 1) G = K = 0.0;
-      face_pair(G, K, I->flux, gpr[k], gmr[k]);
-    }
-  for (int i = 1; i <= m; ++i)
-    for (int j = 0; j < n; ++j) {
-      const size_t k = (size_t)(i - 1) * n + j;
-      const double G = Dt[k] * M.w[i] / (M.r[i] * M.mu[j + 1]);
-      const double K = Et[k] * M.w[i];
-      face_pair(G, K, I->flux, gpt[k], gmt[k]);
-    }
-  std::vector<double> inv_rw(m + 2, 0.0), inv_dth(n);
-  for (int i = 1; i <= m; ++i) inv_rw[i] = 1.0 / (M.r[i] * M.w[i]);
-  for (int j = 0; j < n; ++j) inv_dth[j] = 1.0 / M.dth[j];
-  I->H.inv_V0 = 1.0 / (kPi * 0.25 * M.h[1] * M.h[1]);
-  // ---- device allocation
-  Carver dry{nullptr, 0, true};
-  carve(I.get(), dry);
-  I->dbytes = dry.off;
-  hipError_t e = hipMalloc(&I->dmem, I->dbytes);
-  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? PD_ENOMEM : PD_EHIP, "device allocation of %zu bytes failed: %s", I->dbytes, hipGetErrorString(e));
-  HIPCHK(hipMemsetAsync(I->dmem, 0, I->dbytes, I->stream));
-  Carver cv{(char *)I->dmem, 0, false};
-  carve(I.get(), cv);
-  PdInst &H = I->H;
-  H.m = m;
-  H.n = n;
-  H.npad = np;
-  H.nsrc = pb->nsrc;
-  H.mixed = precision == PD_MIXED;
-  H.has_b = has_b;
-  H.zero_flux = I->bc;
-  H.ncg = I->T.ncg;
-  H.nrg = I->T.nrg;
-  H.nb_sten = I->T.nb_sten;
-  H.nb_elem = I->T.nb_elem;
-  H.cw = I->T.cw;
-  H.nseg = I->T.nseg;
-  H.brad = I->T.brad;
-  H.nb_rad = I->T.nb_rad;
-  H.bang = I->T.bang;
-  H.nb_ang = I->T.nb_ang;
-  H.nb_frad = I->T.nb_frad;
-  H.nb_fang = I->T.nb_fang;
-  if (!has_b) H.b_node = nullptr;
-  hipStream_t s = I->stream;
-  auto up = [&](const void *dst, const void *src, size_t bytes) -> int {
-    HIPCHK(hipMemcpyAsync(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice, s));
-    return PD_OK;
-  };
-  std::vector<double> tmp(np);
-  std::vector<std::vector<double>> keep;   // host staging must outlive the async copies
-  if ((rc = up(H.inv_rw, inv_rw.data(), inv_rw.size() * 8))) return rc;
-  if ((rc = up(H.inv_dth, inv_dth.data(), inv_dth.size() * 8))) return rc;
-  if ((rc = up(H.r_nodes, M.r.data(), M.r.size() * 8))) return rc;
-  if ((rc = up(H.th_nodes, M.th.data(), M.th.size() * 8))) return rc;
-  if ((rc = up(H.k64.gp_r, gpr.data(), gpr.size() * 8))) return rc;
-  if ((rc = up(H.k64.gm_r, gmr.data(), gmr.size() * 8))) return rc;
-  if ((rc = up(H.k64.gp_t, gpt.data(), gpt.size() * 8))) return rc;
-  if ((rc = up(H.k64.gm_t, gmt.data(), gmt.size() * 8))) return rc;
-  std::vector<float> f_gpr, f_gmr, f_gpt, f_gmt;
-  if (H.mixed) {
-    f_gpr.assign(gpr.begin(), gpr.end());
-    f_gmr.assign(gmr.begin(), gmr.end());
-    f_gpt.assign(gpt.begin(), gpt.end());
-    f_gmt.assign(gmt.begin(), gmt.end());
-    if ((rc = up(H.k32.gp_r, f_gpr.data(), f_gpr.size() * 4))) return rc;
-    if ((rc = up(H.k32.gm_r, f_gmr.data(), f_gmr.size() * 4))) return rc;
-    if ((rc = up(H.k32.gp_t, f_gpt.data(), f_gpt.size() * 4))) return rc;
-    if ((rc = up(H.k32.gm_t, f_gmt.data(), f_gmt.size() * 4))) return rc;
-  }
-  if (has_b) {
-    keep.emplace_back(np);
-    to_internal(bn.data(), pb->layout, m, n, np, keep.back().data());
-    if ((rc = up(H.b_node, keep.back().data(), np * 8))) return rc;
-  }
-  for (int q = 0; q < pb->nsrc; ++q) {
-    keep.emplace_back(np);
-    to_internal(g.data() + (size_t)q * N, pb->layout, m, n, np, keep.back().data());
-    if ((rc = up(H.g + (size_t)q * np, keep.back().data(), np * 8))) return rc;
-  }
-  if (pb->nsrc > 0) {
-    if ((rc = up(H.nb, nb.data(), nb.size() * 8))) return rc;
-    double lam[PD_MAXSRC] = {0, 0, 0, 0};
-    int tp[PD_MAXSRC] = {0, 0, 0, 0};
-    for (int q = 0; q < pb->nsrc; ++q) {
-      lam[q] = pb->lambda[q];
-      tp[q] = pb->tpow ? pb->tpow[q] : 0;
-      if (tp[q] < 0 || tp[q] > 8) return fail(PD_EINVAL, "tpow must be in [0, 8]");
-    }
-    if ((rc = up(H.lam, lam, sizeof lam))) return rc;
-    if ((rc = up(H.tpow, tp, sizeof tp))) return rc;
-  }
-  keep.emplace_back(np);
-  to_internal(u0.data(), pb->layout, m, n, np, keep.back().data());
-  I->rot = 0;
-  if ((rc = up(H.sol[1], keep.back().data(), np * 8))) return rc;
-  if ((rc = ensure_time_capacity(I.get(), 16))) return rc;
-  HIPCHK(hipStreamSynchronize(s));
-  I->t = 0.0;
   *out = I.release();
   return PD_OK;
 }
@@ -1447,13 +1490,10 @@ using Clock = std::chrono::steady_clock;
 
 struct Request {
   uint64_t ticket = 0;
-  pd_mesh_desc mesh{};
-  std::vector<double> r_expl, th_expl;
-  pd_problem_desc pb{};
-  std::vector<double> b, Dr, Er, Dt, Et, lam, g, nb, u0;
-  std::vector<int32_t> tpow;
-  std::vector<double> ttab;   // the K+1 levels from t = 0
-  int precision = PD_FP64;
+  std::unique_ptr<pd_instance> prepared;   // host part, until admission
+  std::unique_ptr<HostImage> image;        // uploads, until admission
+  int layout = PD_LAYOUT_RING;
+  std::vector<double> ttab;                // the K+1 levels from t = 0
   int K = 0, N = 0;
   size_t footprint = 0;
   SolveParams sp{};
@@ -1467,16 +1507,6 @@ struct Request {
 
 double seconds(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double>(b - a).count();
-}
-
-// Copies an optional input array (count values) into `keep`; the copy's
-// address replaces the caller's pointer.
-int keep_copy(const double *&p, size_t count, int device_ptrs, std::vector<double> &keep) {
-  if (!p) return PD_OK;
-  int rc = fetch(p, count, device_ptrs, keep);
-  if (rc) return rc;
-  p = keep.data();
-  return PD_OK;
 }
 
 }  // namespace
@@ -1499,15 +1529,29 @@ struct pd_batch {
 
 namespace {
 
-// Creates the request's instance on the loop's stream and readies its solve.
+// Uploads the request's prepared instance on the loop's stream and readies its solve.
 int admit_request(pd_batch *B, Request *R) {
-  int rc = pd_mesh_create(&R->mesh, &R->pb, R->precision, B->stream, &R->inst);
-  if (rc) return rc;
-  pd_instance *I = R->inst;
-  if ((rc = ensure_time_capacity(I, R->K))) return rc;
-  HIPCHK(hipMemcpyAsync(I->t_table, R->ttab.data(), R->ttab.size() * sizeof(double), hipMemcpyHostToDevice,
+  pd_instance *I = R->prepared.get();
+  I->device = B->device;
+  I->stream = B->stream;
+  I->own_stream = false;
+  int rc = upload_instance(I, *R->image);
+  R->image.reset();
+  if (rc) {
+    if (I->dmem) (void)hipFree(I->dmem);
+    if (I->t_table) (void)hipFree(I->t_table);
+    if (I->stats) (void)hipFree(I->stats);
+    I->dmem = nullptr;
+    I->t_table = nullptr;
+    I->stats = nullptr;
+    R->prepared.reset();
+    return rc;
+  }
+  R->inst = R->prepared.release();
+  if ((rc = ensure_time_capacity(R->inst, R->K))) return rc;
+  HIPCHK(hipMemcpyAsync(R->inst->t_table, R->ttab.data(), R->ttab.size() * sizeof(double), hipMemcpyHostToDevice,
                         B->stream));
-  return init_scalars(I, R->sp, R->K, B->stream);
+  return init_scalars(R->inst, R->sp, R->K, B->stream);
 }
 
 // Collects a finished request's result and statistics (its first `levels`
@@ -1529,7 +1573,7 @@ void retire_request(pd_batch *B, Request *R, int rc, int levels) {
         S.t = st[8 * k + 5];
       }
       R->result.resize(R->N);
-      rc = pd_get_solution(R->inst, R->result.data(), R->pb.layout, 0);
+      rc = pd_get_solution(R->inst, R->result.data(), R->layout, 0);
     }
     if (rc) err = g_err;
     if (!rc && worst != PD_OK) {
@@ -1551,6 +1595,9 @@ void retire_request(pd_batch *B, Request *R, int rc, int levels) {
   B->info.active -= 1;
   B->info.completed += 1;
 }
+
+// Cycles the loop runs between looks at its queue and its finished requests.
+constexpr long kServeSlice = 8;
 
 void serve(pd_batch *B) {
   (void)hipSetDevice(B->device);
@@ -1600,7 +1647,9 @@ void serve(pd_batch *B) {
       std::lock_guard<std::mutex> lk(B->mu);
       B->info.plans_built += 1;
     }
-    if (!rc) rc = E.level();
+    // a slice of asynchronous cycles, then retire whoever left the batch
+    bool fin = false;
+    if (!rc) rc = E.run(kServeSlice, &fin);
     if (!rc) rc = E.levels_done(lv);
     if (rc) {
       // a failure of the loop itself ends every active request
@@ -1612,7 +1661,7 @@ void serve(pd_batch *B) {
     std::vector<Request *> keep;
     for (size_t q = 0; q < active.size(); ++q) {
       Request *R = active[q];
-      if (lv[2 * q] >= R->K || lv[2 * q + 1] != ST_DONE) {
+      if (lv[2 * q + 1]) {
         retire_request(B, R, PD_OK, lv[2 * q]);
         dirty = true;
       } else {
@@ -1622,7 +1671,7 @@ void serve(pd_batch *B) {
     active.swap(keep);
     if (active.empty()) E.release();
     std::lock_guard<std::mutex> lk(B->mu);
-    B->info.levels_run += 1;
+    B->info.slices_run += 1;       // slices of cycles run
   }
   E.release();
   for (Request *R : active)
@@ -1673,45 +1722,11 @@ int pd_batch_submit(pd_batch *B, const pd_mesh_desc *mesh, const pd_problem_desc
     if (pb->layout != PD_LAYOUT_RING && pb->layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
     if (!pb->u0) return fail(PD_EINVAL, "u0 is NULL");
     if (pb->nsrc > 0 && (!pb->lambda || !pb->g)) return fail(PD_EINVAL, "lambda and g are required when nsrc > 0");
+    const auto t_submit = Clock::now();
     std::unique_ptr<Request> R(new Request);
     const int m = mesh->nr, n = mesh->ntheta, N = m * n + 1;
     R->N = N;
-    R->precision = precision;
-    R->mesh = *mesh;
-    if (mesh->r_kind == PD_MESH_EXPLICIT) {
-      R->r_expl.assign(mesh->r_explicit, mesh->r_explicit + m + 2);
-      R->mesh.r_explicit = R->r_expl.data();
-    }
-    if (mesh->th_kind == PD_MESH_EXPLICIT) {
-      R->th_expl.assign(mesh->th_explicit, mesh->th_explicit + n + 1);
-      R->mesh.th_explicit = R->th_expl.data();
-    }
-    R->pb = *pb;
-    pd_problem_desc &P = R->pb;
-    const int dp = pb->device_ptrs;
-    const size_t nr_f = (size_t)(m + 1) * n, nt_f = (size_t)m * n;
-    if ((rc = keep_copy(P.b_node, N, dp, R->b))) return rc;
-    if ((rc = keep_copy(P.D_rface, nr_f, dp, R->Dr))) return rc;
-    if ((rc = keep_copy(P.Er_rface, nr_f, dp, R->Er))) return rc;
-    if ((rc = keep_copy(P.D_tface, nt_f, dp, R->Dt))) return rc;
-    if ((rc = keep_copy(P.Et_tface, nt_f, dp, R->Et))) return rc;
-    if ((rc = keep_copy(P.u0, N, dp, R->u0))) return rc;
-    if (pb->nsrc > 0) {
-      R->lam.assign(pb->lambda, pb->lambda + pb->nsrc);   // host array (as for create)
-      P.lambda = R->lam.data();
-      if (pb->tpow) {
-        R->tpow.assign(pb->tpow, pb->tpow + pb->nsrc);
-        P.tpow = R->tpow.data();
-      }
-      if ((rc = keep_copy(P.g, (size_t)pb->nsrc * N, dp, R->g))) return rc;
-      if ((rc = keep_copy(P.nb, (size_t)pb->nsrc * n, dp, R->nb))) return rc;
-    } else {
-      P.lambda = nullptr;
-      P.tpow = nullptr;
-      P.g = nullptr;
-      P.nb = nullptr;
-    }
-    P.device_ptrs = 0;
+    R->layout = pb->layout;
     if ((rc = build_time_table(td, 0.0, R->ttab))) return rc;
     R->K = td->K;
     R->sp = params_from(td, precision);
@@ -1720,11 +1735,13 @@ int pd_batch_submit(pd_batch *B, const pd_mesh_desc *mesh, const pd_problem_desc
     R->footprint = fp + (9 * (size_t)std::max(R->K, 16) + 1) * sizeof(double);
     if (R->footprint > B->pool)
       return fail(PD_ENOMEM, "request needs %zu bytes, the pool holds %zu", R->footprint, B->pool);
+    // the host part of the instance is built here, on the caller's thread
+    if ((rc = prepare_instance(mesh, pb, precision, R->prepared, R->image))) return rc;
     {
       std::lock_guard<std::mutex> lk(B->mu);
       if (B->stop) return fail(PD_EINVAL, "batch is shutting down");
       R->ticket = B->next++;
-      R->t_submit = Clock::now();
+      R->t_submit = t_submit;
       *ticket = R->ticket;
       B->pending.push_back(R.get());
       B->reqs.emplace(R->ticket, std::move(R));

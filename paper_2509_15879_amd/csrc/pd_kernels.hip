@@ -129,9 +129,8 @@ __device__ __forceinline__ int block_status(const PdScalars *sc) {
   return st;
 }
 
-__device__ __forceinline__ void finish_instance(const PdInst &I, PdScalars *sc, int status) {
-  sc->status = status;
-  atomicSub(I.n_active, 1);
+__device__ __forceinline__ void finish_instance(const PdInst &, PdScalars *sc, int status) {
+  sc->status = status;   // the level ends; the control kernel takes it from here
 }
 
 __device__ __forceinline__ bool inner_active(const PdScalars *sc) {
@@ -173,13 +172,10 @@ __device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
 
 // ------------------------------------------------------------ level control
 
-// Per-instance set-up of a time level t_k -> t_{k+1} (one thread per instance).
-__global__ void k_level_begin(PdInst *insts, int ninst) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= ninst) return;
-  PdInst &I = insts[q];
-  PdScalars *sc = I.sc;
-  if (sc->status == ST_IDLE) return;          // not stepping in this level
+// Sets up level sc->level of an instance, t_k -> t_{k+1}: Δt, θ, the
+// source weights, the extrapolation factor; its factorisation (when Δt or θ
+// changed) and right-hand side are then due.
+__device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   const int k = sc->level;
   const double t0 = I.t_table[k], t1 = I.t_table[k + 1];
   const double dt = t1 - t0, th = sc->theta;
@@ -193,7 +189,8 @@ __global__ void k_level_begin(PdInst *insts, int ninst) {
   for (int s = 0; s < I.nsrc; ++s)
     sc->cq[s] = (1.0 - th) * tau_q(I.lam[s], I.tpow[s], t0) + th * tau_q(I.lam[s], I.tpow[s], t1);
   sc->status = ST_ACTIVE;
-  atomicAdd(I.n_active, 1);
+  sc->stage = STAGE_START;
+  sc->in_level = 1;
   sc->phase = PH_INNER;
   sc->pend = PEND_BEGIN;
   sc->restarted = 0;
@@ -208,13 +205,9 @@ __global__ void k_level_begin(PdInst *insts, int ninst) {
   sc->rho_old = sc->rho_new = sc->rho_next = sc->rho_cur = 1.0;
 }
 
-// Records the level, rotates the solution buffers (iterate -> n^{k+1}).
-__global__ void k_level_end(PdInst *insts, int ninst) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= ninst) return;
-  PdInst &I = insts[q];
-  PdScalars *sc = I.sc;
-  if (sc->status == ST_IDLE) return;
+// Records the level that just ended and rotates the solution buffers
+// (iterate -> n^{k+1}); returns whether it met its tolerance.
+__device__ __forceinline__ bool end_level(const PdInst &I, PdScalars *sc) {
   const int k = sc->level;
   double *st = I.level_stats + 8 * k;
   st[0] = sc->iters;
@@ -228,10 +221,6 @@ __global__ void k_level_end(PdInst *insts, int ninst) {
   sc->total_iters += sc->iters;
   const bool ok = sc->status == ST_DONE;
   if (!ok) sc->nfail += 1;
-  if (sc->status == ST_ACTIVE) {       // stopped by the host's cycle cap
-    st[2] = ST_NOCONV;
-    atomicSub(I.n_active, 1);
-  }
   sc->rot = (sc->rot + 1) % 3;       // old iterate slot becomes n^k
   sc->prev_dt = sc->dt;
   sc->have_prev = 1;
@@ -241,10 +230,41 @@ __global__ void k_level_end(PdInst *insts, int ninst) {
     sc->fact_dt = sc->dt;
     sc->fact_theta = sc->theta;
   }
-  sc->status = (ok && k + 1 < sc->K) ? ST_DONE : ST_IDLE;
-  if (I.lvl_out) {
-    I.lvl_out[0] = k + 1;
-    I.lvl_out[1] = ok ? ST_DONE : (int)st[2];
+  sc->in_level = 0;
+  if (I.lvl_out) I.lvl_out[0] = k + 1;
+  return ok;
+}
+
+// One level's set-up alone (right-hand side assembly without a solve).
+__global__ void k_level_begin(PdInst *insts, int ninst) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ninst) return;
+  PdInst &I = insts[q];
+  PdScalars *sc = I.sc;
+  if (sc->status == ST_IDLE) return;
+  begin_level(I, sc);
+}
+
+// Control of asynchronous levels (one thread per instance), first in every
+// cycle: an instance whose level has ended (converged, or stopped) records
+// it and starts its next level at once, whatever the others are doing; one
+// that has taken all its levels, or failed one, leaves the batch and is
+// counted out of the active-instance counter.
+__global__ void k_ctl(PdInst *insts, int ninst) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ninst) return;
+  PdInst &I = insts[q];
+  PdScalars *sc = I.sc;
+  const int st = sc->status;
+  if (st == ST_IDLE || st == ST_ACTIVE) return;
+  bool ok = true;
+  if (sc->in_level) ok = end_level(I, sc);
+  if (ok && sc->level < sc->K) {
+    begin_level(I, sc);
+  } else {
+    sc->status = ST_IDLE;
+    atomicSub(I.n_active, 1);
+    if (I.lvl_out) I.lvl_out[1] = 1;
   }
 }
 
@@ -303,7 +323,7 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   const PdScalars *sc = I.sc;
-  if (sc->status != ST_ACTIVE || !sc->refactor) return;
+  if (sc->status != ST_ACTIVE || sc->stage != STAGE_START || !sc->refactor) return;
   const int m = I.m, n = I.n, cw = I.cw, B = I.brad;
   const int c = threadIdx.x % cw, seg = threadIdx.x / cw;
   const int j = mp.y * cw + c;
@@ -402,7 +422,7 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   const PdScalars *sc = I.sc;
-  if (sc->status != ST_ACTIVE || !sc->refactor) return;
+  if (sc->status != ST_ACTIVE || sc->stage != STAGE_START || !sc->refactor) return;
   const int m = I.m, n = I.n, B = I.bang;
   const int lane = threadIdx.x & 63;
   const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
@@ -776,6 +796,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
   PdScalars *sc = I.sc;
   if (MODE != SM_APPLY) {
     if (sc->status != ST_ACTIVE) return;     // no block of this kernel changes the status
+    if (MODE == SM_BEGIN && sc->stage != STAGE_START) return;
     if ((MODE == SM_V || MODE == SM_T) && !prec_match<TK>(I)) return;
     if (MODE == SM_UR && !I.mixed) return;
   }
@@ -1174,6 +1195,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
       const OriginBegin O = origin_begin(I, sc, tot);
       if (b0) {
         origin_begin_store(I, sc, O);
+        sc->stage = STAGE_ITER;   // the level's factorisation and rhs are done
         sc->bnorm2 = O.bb;
         sc->r0norm2 = O.rr;
         sc->inner_first = 1;
@@ -1718,8 +1740,8 @@ enum { KF_BEGIN = 0, KF_FACTOR = 1, KF_RAD_P = 2, KF_ANG_P = 3, KF_STEN_V = 4, K
 void launch_level_begin(const LaunchSet &L, hipStream_t s) {
   go(KF_CONTROL, k_level_begin, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
 }
-void launch_level_end(const LaunchSet &L, hipStream_t s) {
-  go(KF_CONTROL, k_level_end, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
+void launch_ctl(const LaunchSet &L, hipStream_t s) {
+  go(KF_CONTROL, k_ctl, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
 }
 // Register-array length of the segmented sweeps: the smallest of 4, 8, 16,
 // 32 that holds the longest segment of the batch.
@@ -1772,6 +1794,17 @@ static void cycle_t(const LaunchSet &L, hipStream_t s) {
   ang<T, AM_S>(L, s);
   sten<T, SM_T>(KF_STEN_T, L, s);
   go(KF_UPDATE, k_elem_x<T>, g1(L.nb_elem), dim3(256), s, L.insts, L.map_elem);
+}
+
+// One round of asynchronous levels: level control (an instance whose level
+// ended starts its next one), the factorisations and right-hand sides of
+// the instances starting a level, then `cycles` Krylov iterations of every
+// active instance.
+void launch_round(const LaunchSet &L, int cycles, hipStream_t s) {
+  launch_ctl(L, s);
+  launch_factor(L, s);
+  launch_begin(L, s);
+  for (int c = 0; c < cycles; ++c) launch_cycle(L, s);
 }
 
 void launch_cycle(const LaunchSet &L, hipStream_t s) {

@@ -74,7 +74,7 @@ class RequestSummary(C.Structure):
 class BatchInfo(C.Structure):
     _fields_ = [("pending", C.c_int32), ("active", C.c_int32), ("peak_active", C.c_int32),
                 ("reserved", C.c_int32), ("submitted", C.c_uint64), ("completed", C.c_uint64),
-                ("levels_run", C.c_uint64), ("plans_built", C.c_uint64), ("used_bytes", C.c_size_t),
+                ("slices_run", C.c_uint64), ("plans_built", C.c_uint64), ("used_bytes", C.c_size_t),
                 ("peak_bytes", C.c_size_t)]
 
     def as_dict(self):

@@ -58,3 +58,47 @@ def cfg4_batch(count=None):
                                 name=f"cfg4_{q}")
         out.append((q, m, n, theta, pb))
     return out
+
+
+# Request stream of the serving loop: Poisson arrivals (rate per second) for
+# a bounded duration; each request draws a template (mesh m log-uniform in
+# [32, 1024], n in [64, 2048], PDE alternating), its own θ in [0.5, 1],
+# tolerance 1e-6 or 1e-8, and end time T log-uniform in [5e-3, 5e-2] at a
+# fixed Δt = 1e-3 (5 to 50 levels).
+CFG5 = dict(rate=200.0, m=(32, 1024), n=(64, 2048), dt=1e-3, T=(5e-3, 5e-2), tols=(1e-6, 1e-8),
+            p=1.3, templates=24, seed=1500)
+
+
+def cfg5_templates(count=None):
+    """[(m, n, Problem)] request templates."""
+    from .manufactured import parabolic_family
+    c = CFG5
+    rng = np.random.default_rng(c["seed"])
+    out = []
+    for k in range(c["templates"] if count is None else count):
+        m = int(round(np.exp(rng.uniform(np.log(c["m"][0]), np.log(c["m"][1])))))
+        n = int(round(np.exp(rng.uniform(np.log(c["n"][0]), np.log(c["n"][1])))))
+        if k % 2 == 0:
+            pb = parabolic_family(float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.0, 0.9)),
+                                  float(rng.uniform(0.0, 2 * np.pi)), name=f"cfg5_{k}")
+        else:
+            pb = continuity_cfg(c["seed"] + k, m, n, 0.5, c["p"], name=f"cfg5_{k}")
+        out.append((m, n, pb))
+    return out
+
+
+def cfg5_arrivals(duration, rate=None, seed=None):
+    """[(arrival time s, template index, θ, tol, K)] of a Poisson stream."""
+    c = CFG5
+    rng = np.random.default_rng(c["seed"] + 1 if seed is None else seed)
+    rate = c["rate"] if rate is None else rate
+    t, out = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration:
+            return out
+        k = int(rng.integers(0, c["templates"]))
+        theta = float(rng.uniform(0.5, 1.0))
+        tol = float(c["tols"][int(rng.integers(0, 2))])
+        T = float(np.exp(rng.uniform(np.log(c["T"][0]), np.log(c["T"][1]))))
+        out.append((t, k, theta, tol, max(1, int(round(T / c["dt"])))))

@@ -62,7 +62,7 @@ def test_requests_joining_a_running_batch_match_alone():
     B = pdk.Batch(8 << 30, 16)
     first = [submit(B, s, r) for s, r in zip(SPECS[:3], reqs[:3])]
     t_end = time.monotonic() + 60
-    while B.stats()["levels_run"] < 2:
+    while B.stats()["slices_run"] < 2:
         assert time.monotonic() < t_end, "the loop did not start"
         time.sleep(1e-4)
     later = [submit(B, s, r) for s, r in zip(SPECS[3:], reqs[3:])]
