@@ -42,17 +42,22 @@ KERNEL_NAMES = {
 
 # HBM bytes per active unknown that each kernel moved (FETCH_SIZE and
 # WRITE_SIZE counters, calibrated on a copy of known size), valid for the
-# kernel source with this SHA-1 only; any other source reports traffic null.
-TRAFFIC_SOURCE_SHA1 = "507088c5efcf47b92caaf58e6b94d77b2654ad2e"
-TRAFFIC_B_PER_CELL = {"rad_p": 63.67, "ang_p": 61.70, "sten_v": 71.69, "rad_s": 56.27,
-                      "ang_s": 61.09, "sten_t": 71.54, "update": 64.36}
+# sources with this SHA-1 only (kernel_source_sha1); any other source
+# reports traffic null.
+TRAFFIC_SOURCE_SHA1 = "328e2a7ae00b946690e512fbbb2ce99c39ce85c7"
+TRAFFIC_B_PER_CELL = {"rad_p": 65.97, "ang_p": 48.44, "sten_v": 72.99, "rad_s": 56.39,
+                      "ang_s": 48.44, "sten_t": 73.53, "update": 64.53}
 
 
 def kernel_source_sha1():
+    """SHA-1 of the kernels' source and of the host runtime that lays out
+    their launches (the block maps decide which tiles share an L2)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2509_15879_amd", "csrc", "pd_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+    h = hashlib.sha1()
+    for name in ("pd_kernels.hip", "pd_host.cpp"):
+        with open(os.path.join(ROOT, "paper_2509_15879_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def bytes_per_cell(family, w):

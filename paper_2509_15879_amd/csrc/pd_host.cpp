@@ -473,6 +473,21 @@ int build_map(std::vector<pd_instance *> const &insts, F per_inst, std::vector<i
   return (int)map.size();
 }
 
+// Workgroups of a launch are dealt to the 8 XCDs (each with its own L2) in
+// turn: workgroup b runs on XCD b % 8.  This reorders a block map so that
+// XCD x receives a contiguous run of logical blocks (its b = x, x+8, x+16,
+// ... take the next logical blocks in order), so that neighbouring tiles,
+// which read each other's edge rings and columns, share an L2.
+constexpr int kXcds = 8;
+void xcd_contiguous(std::vector<int2> &map) {
+  const size_t nb = map.size();
+  std::vector<int2> out(nb);
+  size_t next = 0;
+  for (int x = 0; x < kXcds; ++x)
+    for (size_t b = x; b < nb; b += kXcds) out[b] = map[next++];
+  map.swap(out);
+}
+
 int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
   const int ninst = (int)insts.size();
   HIPCHK(hipMalloc(&P.n_active, sizeof(int)));
@@ -499,9 +514,10 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
   HIPCHK(hipMemcpyAsync(P.L.insts, hv.data(), ninst * sizeof(PdInst), hipMemcpyHostToDevice, s));
   P.L.ninst = ninst;
   std::vector<int2> mp;
-  auto upload = [&](int2 **dst, int *cnt, auto fn) -> int {
+  auto upload = [&](int2 **dst, int *cnt, auto fn, bool by_xcd = false) -> int {
     *cnt = build_map(insts, fn, mp);
     if (*cnt == 0) return PD_OK;
+    if (by_xcd) xcd_contiguous(mp);
     HIPCHK(hipMalloc(dst, mp.size() * sizeof(int2)));
     P.bufs.push_back(*dst);
     HIPCHK(hipMemcpyAsync(*dst, mp.data(), mp.size() * sizeof(int2), hipMemcpyHostToDevice, s));
@@ -509,7 +525,7 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
     return PD_OK;
   };
   int rc;
-  if ((rc = upload(&P.L.map_sten, &P.L.nb_sten, [](pd_instance *I) { return I->T.nb_sten; }))) return rc;
+  if ((rc = upload(&P.L.map_sten, &P.L.nb_sten, [](pd_instance *I) { return I->T.nb_sten; }, true))) return rc;
   if ((rc = upload(&P.L.map_elem, &P.L.nb_elem, [](pd_instance *I) { return I->T.nb_elem; }))) return rc;
   if ((rc = upload(&P.L.map_rad, &P.L.nb_rad, [](pd_instance *I) { return I->T.nb_rad; }))) return rc;
   for (int c = 0; c < 2; ++c)
