@@ -32,7 +32,8 @@ M, N_TH, P_STRETCH, T_END, K_LEVELS, L_TIME = (CFG2[k] for k in ("m", "n", "p", 
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per unknown of one launch (w: storage bytes of the
-# Krylov data, pivots are FP64): what the kernel must read and write once.
+# Krylov data; the sweeps' factors are FP32): what the kernel must read and
+# write once.
 KERNEL_NAMES = {
     "sten_v": "k_sten<T, SM_V>", "sten_t": "k_sten<T, SM_T>", "rad_p": "k_rad<T, RM_P, BM>",
     "rad_s": "k_rad<T, RM_S, BM>", "ang_p": "k_ang<T, AM_P, BM>", "ang_s": "k_ang<T, AM_S, BM>",
@@ -64,10 +65,10 @@ def bytes_per_cell(family, w):
     return {
         "sten_v": 8 * w,            # p̂, 4 face coefficients, 1/diag, r̂ in; v out
         "sten_t": 8 * w,            # ŝ, 4 faces, 1/diag, s in; t out
-        "rad_p": 7 * w + 8,         # r, p, v, f, g, pivot in; p, w out
-        "rad_s": 6 * w + 8,         # r, v, f, g, pivot in; s, w out
-        "ang_p": 5 * w + 8,         # w, f, g, z, pivot in; p̂ out
-        "ang_s": 5 * w + 8,         # w, f, g, z, pivot in; ŝ out
+        "rad_p": 5 * w + 12,        # r, p, v in; p, w out; f, g, pivot (FP32) in
+        "rad_s": 4 * w + 12,        # r, v in; s, w out; f, g, pivot (FP32) in
+        "ang_p": 2 * w + 16,        # w in; p̂ out; f, g, z, pivot (FP32) in
+        "ang_s": 2 * w + 16,        # w in; ŝ out; f, g, z, pivot (FP32) in
         "update": 8 * w,            # p̂, ŝ, x, s, t, r̂ in; x, r out
     }[family]
 

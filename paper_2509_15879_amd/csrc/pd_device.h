@@ -64,8 +64,6 @@ struct KSet {
   T *d;                              // inner iterate (mixed precision only)
   const T *gp_r, *gm_r, *gp_t, *gm_t;  // faces
   const T *inv_d;                    // 1/diag(A): the Krylov iteration runs on D^{-1}A
-  T *rf_f, *rf_g;                    // radial factors (multipliers)
-  T *af_f, *af_g, *af_z;             // angular factors (multipliers, SM vector)
 };
 
 struct PdInst {
@@ -91,8 +89,12 @@ struct PdInst {
   double *diag;             // [npad] diagonal of I/dt + θL
   double *inv_diag;         // [npad] its reciprocal (k64.inv_d)
   float *inv_diag32;        // [npad] FP32 copy (k32.inv_d, mixed precision)
-  double *rf_uinv;          // [m*n] radial pivots 1/u (FP64 in both precisions)
-  double *af_uinv;          // [m*n] angular pivots
+  // Factors of the two sweeps of the preconditioner, computed in FP64 and
+  // stored in FP32 in both precisions (the sweeps themselves run in FP64 in
+  // the FP64 solve: the rounded factors define a fixed, slightly different
+  // preconditioner, which moves the iterates but not the converged solution).
+  float *rf_uinv, *rf_f, *rf_g;           // [m*n] radial pivots 1/u and multipliers
+  float *af_uinv, *af_f, *af_g, *af_z;    // [m*64*bang] angular (sweep order), SM vector
   double *af_kappa, *af_alpha0;   // [m] Sherman-Morrison scalars per ring
   KSet<double> k64;
   KSet<float> k32;

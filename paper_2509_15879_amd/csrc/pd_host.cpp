@@ -236,19 +236,19 @@ void carve(pd_instance *I, Carver &c) {
   H.k64.inv_d = H.inv_diag;
   H.inv_diag32 = mixed ? c.take<float>(np) : nullptr;
   H.k32.inv_d = H.inv_diag32;
-  H.rf_uinv = c.take<double>(mn);
-  H.af_uinv = c.take<double>(ma);
+  H.rf_uinv = c.take<float>(mn);
+  H.rf_f = c.take<float>(mn);
+  H.rf_g = c.take<float>(mn);
+  H.af_uinv = c.take<float>(ma);
+  H.af_f = c.take<float>(ma);
+  H.af_g = c.take<float>(ma);
+  H.af_z = c.take<float>(ma);
   H.af_kappa = c.take<double>(m);
   H.af_alpha0 = c.take<double>(m);
   H.k64.gp_r = c.take<double>((size_t)(m + 1) * n);
   H.k64.gm_r = c.take<double>((size_t)(m + 1) * n);
   H.k64.gp_t = c.take<double>(mn);
   H.k64.gm_t = c.take<double>(mn);
-  H.k64.rf_f = c.take<double>(mn);
-  H.k64.rf_g = c.take<double>(mn);
-  H.k64.af_f = c.take<double>(ma);
-  H.k64.af_g = c.take<double>(ma);
-  H.k64.af_z = c.take<double>(ma);
   if (!mixed) {
     H.k64.r = c.take<double>(np);
     H.k64.rh = c.take<double>(np);
@@ -276,11 +276,6 @@ void carve(pd_instance *I, Carver &c) {
     H.k32.gm_r = c.take<float>((size_t)(m + 1) * n);
     H.k32.gp_t = c.take<float>(mn);
     H.k32.gm_t = c.take<float>(mn);
-    H.k32.rf_f = c.take<float>(mn);
-    H.k32.rf_g = c.take<float>(mn);
-    H.k32.af_f = c.take<float>(ma);
-    H.k32.af_g = c.take<float>(ma);
-    H.k32.af_z = c.take<float>(ma);
   }
   const int nbs = I->T.nb_sten;
   H.part_b = c.take<double>(4 * (size_t)nbs);

@@ -362,8 +362,8 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts
   }
   double u_prev = (q0 != 0.0) ? q1 / q0 : 1.0;
   cp = c_prev;
-  GAS double *dg = G(I.diag), *idg = G(I.inv_diag), *uinv = G(I.rf_uinv);
-  GAS double *ff = G(I.k64.rf_f), *gg = G(I.k64.rf_g);
+  GAS double *dg = G(I.diag), *idg = G(I.inv_diag);
+  GAS float *uinv = G(I.rf_uinv), *ff = G(I.rf_f), *gg = G(I.rf_g);
   for (int k = 0; k < cnt; ++k) {
     const int i = k0 + k + 1;
     const RadRow R = rad_row(I, i, j, inv_dt, th);
@@ -372,14 +372,10 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts
     const int idx = (i - 1) * n + j;
     dg[idx] = R.d;
     idg[idx] = 1.0 / R.d;
-    uinv[idx] = ui;
-    ff[idx] = R.a * ui;
-    gg[idx] = R.c * ui;
-    if (I.mixed) {
-      G(I.inv_diag32)[idx] = (float)(1.0 / R.d);
-      G(I.k32.rf_f)[idx] = (float)(R.a * ui);
-      G(I.k32.rf_g)[idx] = (float)(R.c * ui);
-    }
+    uinv[idx] = (float)ui;
+    ff[idx] = (float)(R.a * ui);
+    gg[idx] = (float)(R.c * ui);
+    if (I.mixed) G(I.inv_diag32)[idx] = (float)(1.0 / R.d);
     u_prev = u;
     cp = R.c;
   }
@@ -479,7 +475,7 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
   double u_prev = (q0 != 0.0) ? q1 / q0 : 1.0;
   cp = gprev;
   double fl[BM] = {}, gf[BM] = {}, ul[BM] = {};
-  GAS double *uinv = G(I.af_uinv), *ff = G(I.k64.af_f), *gg = G(I.k64.af_g), *zz = G(I.k64.af_z);
+  GAS float *uinv = G(I.af_uinv), *ff = G(I.af_f), *gg = G(I.af_g), *zz = G(I.af_z);
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     if (k < cnt) {
@@ -488,9 +484,9 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
       ul[k] = ui;
       fl[k] = al[k] * ui;
       gf[k] = ga[k] * ui;
-      uinv[frow + 64 * k + lane] = ui;
-      ff[frow + 64 * k + lane] = fl[k];
-      gg[frow + 64 * k + lane] = gf[k];
+      uinv[frow + 64 * k + lane] = (float)ui;
+      ff[frow + 64 * k + lane] = (float)fl[k];
+      gg[frow + 64 * k + lane] = (float)gf[k];
       u_prev = u;
       cp = ga[k];
     }
@@ -545,13 +541,8 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
     if (k < cnt) {
       Q *= -gf[k];
       wl[k] += Q * Xin;
-      zz[frow + 64 * k + lane] = wl[k];
+      zz[frow + 64 * k + lane] = (float)wl[k];
       if (j0 + k == n - 1) zlast = wl[k];
-      if (I.mixed) {
-        G(I.k32.af_f)[frow + 64 * k + lane] = (float)fl[k];
-        G(I.k32.af_g)[frow + 64 * k + lane] = (float)gf[k];
-        G(I.k32.af_z)[frow + 64 * k + lane] = (float)wl[k];
-      }
     }
   }
   const double z0 = __shfl(wl[0], 0, 64);
@@ -1000,9 +991,8 @@ template <typename T, int MODE, int BM>
 __device__ __forceinline__ void rad_load(int n, int j, int rb, int klast, double omega,
                                          const GAS T *__restrict__ a, const GAS T *__restrict__ b,
                                          const GAS T *__restrict__ c,
-                                         const GAS double *__restrict__ uinv,
-                                         const GAS T *__restrict__ f, const GAS T *__restrict__ g,
-                                         RadRegs<BM> &R) {
+                                         const GAS float *__restrict__ uinv,
+                                         const GAS float *__restrict__ f, RadRegs<BM> &R) {
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     // rows past the segment's end repeat its last row (clamped, always issued)
@@ -1010,7 +1000,7 @@ __device__ __forceinline__ void rad_load(int n, int j, int rb, int klast, double
     R.a[k] = (double)a[idx];
     if (MODE == RM_P) R.b[k] = (double)b[idx] - omega * (double)c[idx];
     if (MODE == RM_S) R.b[k] = (double)b[idx];
-    R.u[k] = uinv[idx];
+    R.u[k] = (double)uinv[idx];
     R.f[k] = (double)f[idx];
   }
 }
@@ -1018,9 +1008,9 @@ __device__ __forceinline__ void rad_load(int n, int j, int rb, int klast, double
 // The backward multipliers, loaded once the launch's partial sums are read
 // (they are first needed after the forward join, and holding them through
 // the closure of the p-sweep would cost registers).
-template <typename T, int BM>
+template <int BM>
 __device__ __forceinline__ void rad_load_g(int n, int j, int rb, int klast,
-                                           const GAS T *__restrict__ g, RadRegs<BM> &R) {
+                                           const GAS float *__restrict__ g, RadRegs<BM> &R) {
 #pragma unroll
   for (int k = 0; k < BM; ++k) R.g[k] = (double)g[(rb + min(k, klast)) * n + j];
 }
@@ -1175,7 +1165,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
     const T *a = (MODE == RM_PLAIN) ? plain_in : KS.r;
     const T *bb = (MODE == RM_P) ? KS.p : KS.v;
     rad_load<T, MODE, BM>(n, jj, rb, klast, sc->omega, G(a), G((const T *)bb), G((const T *)KS.v),
-                          G(I.rf_uinv), G((const T *)KS.rf_f), G((const T *)KS.rf_g), R);
+                          G((const float *)I.rf_uinv), G((const float *)I.rf_f), R);
   };
   // the loads are issued before the partial sums are read, except on the
   // rare closures of a level begin or a refinement, whose origin arithmetic
@@ -1285,7 +1275,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
     if (st != ST_ACTIVE) return;
   }
   if (pend != PEND_UPDATE) load();
-  rad_load_g<T, BM>(n, jj, rb, klast, G((const T *)KS.rf_g), R);
+  rad_load_g<BM>(n, jj, rb, klast, G((const float *)I.rf_g), R);
   T *out = (MODE == RM_PLAIN) ? plain_out : KS.w;
   rad_solve<T, MODE, BM, NT>(m, n, jj, c, seg * B, cnt, b0, beta, omega, alpha, first, reset, R,
                          G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s),
@@ -1317,9 +1307,10 @@ template <typename T, int BM>
 __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, double kappa,
                                          double alpha0, const GAS T *__restrict__ in,
                                          GAS T *__restrict__ out,
-                                         const GAS double *__restrict__ uinv,
-                                         const GAS T *__restrict__ f, const GAS T *__restrict__ g,
-                                         const GAS T *__restrict__ z, double *tb) {
+                                         const GAS float *__restrict__ uinv,
+                                         const GAS float *__restrict__ f,
+                                         const GAS float *__restrict__ g,
+                                         const GAS float *__restrict__ z, double *tb) {
   const int row = (i - 1) * n, frow = (i - 1) * 64 * B;
   const int j0 = lane * B;
   const int cnt = max(0, min(B, n - j0));
@@ -1334,7 +1325,7 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
       const int jn = min(lane + 64 * k, n - 1);
       const int fi = frow + 64 * k + lane;
       xin[k] = (double)in[row + jn];
-      ul[k] = uinv[fi];
+      ul[k] = (double)uinv[fi];
       fl[k] = (double)f[fi];
       gl[k] = (double)g[fi];
       zl[k] = (double)z[fi];
@@ -1448,7 +1439,8 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
   const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
   T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
   ang_body<T, BM>(m, n, I.bang, i, lane, I.af_kappa[i - 1], I.af_alpha0[i - 1], G(in), G(out),
-                  G(I.af_uinv), G((const T *)KS.af_f), G((const T *)KS.af_g), G((const T *)KS.af_z),
+                  G((const float *)I.af_uinv), G((const float *)I.af_f), G((const float *)I.af_g),
+                  G((const float *)I.af_z),
                   tbuf[threadIdx.x >> 6]);
 }
 
