@@ -24,6 +24,11 @@
 #define PD_RAD_BMAX 32    // max rows per radial segment held in registers
 #define PD_ANG_BMAX 32    // max angular nodes per lane held in registers
 #define PD_NSLOT 4
+#define PD_NSOL 4         // rotating solution slots: n^{k-2}, n^{k-1}, n^k, iterate
+
+// Slot holding n^{k-back} (back = 0, 1, 2) or, for back = -1, the iterate of
+// the level under way, under rotation `rot`.
+__host__ __device__ inline int sol_slot(int rot, int back) { return (rot + 2 - back) % PD_NSOL; }
 
 enum { ST_IDLE = 0, ST_ACTIVE = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOCONV = 4 };
 enum { PH_INNER = 0, PH_OUTER = 1 };
@@ -38,10 +43,12 @@ enum { CNT_BEGIN = 0, CNT_V = 1, CNT_T = 2, CNT_X = 3, CNT_UR = 4, CNT_APPLY = 5
 
 struct PdScalars {
   // time level
-  double t0, t1, dt, inv_dt, theta, extrap;
+  double t0, t1, dt, inv_dt, theta;
+  double ex_a, ex_b;        // initial guess n^k + ex_a (n^k - n^{k-1}) + ex_b (n^{k-1} - n^{k-2})
+  int ex_n, pad3;           // earlier levels the guess uses (0, 1 or 2)
   double cq[PD_MAXSRC];
   double tol, tol_inner;
-  double fact_dt, fact_theta, prev_dt;
+  double fact_dt, fact_theta, prev_dt, prev_dt2;   // Δt of the last two levels
   int maxit, level, K, refactor;
   int status, phase, iters, outer;
   int inner_iters, restarts, first, reset_rh;
@@ -51,7 +58,7 @@ struct PdScalars {
   int stage, in_level;      // STAGE_* of the level under way; a level has been started
   // Krylov scalars
   double rho_next, rho_cur; // ρ of this iteration (set by the p-sweep), of the last (by the s-sweep)
-  double rho_old, rho_new, alpha, omega;
+  double alpha, omega;
   double bnorm2, rnorm2, r0norm2;
   double rel_resid;
   double t_now;
@@ -83,7 +90,7 @@ struct PdInst {
   const double *lam;        // [nsrc]
   const int *tpow;          // [nsrc]
   const double *t_table;    // [K+1]
-  double *sol[3];           // rotating: n^{k-1}, n^k, iterate
+  double *sol[PD_NSOL];     // rotating (sol_slot): n^{k-2}, n^{k-1}, n^k, iterate
   double *bvec;             // right-hand side (FP64)
   double *rout;             // FP64 outer residual (mixed)
   double *diag;             // [npad] diagonal of I/dt + θL

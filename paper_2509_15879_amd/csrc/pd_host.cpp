@@ -229,7 +229,7 @@ void carve(pd_instance *I, Carver &c) {
   H.nb = c.take<double>((size_t)ns * n);
   H.lam = c.take<double>(PD_MAXSRC);
   H.tpow = c.take<int>(PD_MAXSRC);
-  for (int k = 0; k < 3; ++k) H.sol[k] = c.take<double>(np);
+  for (int k = 0; k < PD_NSOL; ++k) H.sol[k] = c.take<double>(np);
   H.bvec = c.take<double>(np);
   H.diag = c.take<double>(np);
   H.inv_diag = c.take<double>(np);
@@ -278,7 +278,7 @@ void carve(pd_instance *I, Carver &c) {
     H.k32.gm_t = c.take<float>(mn);
   }
   const int nbs = I->T.nb_sten;
-  H.part_b = c.take<double>(4 * (size_t)nbs);
+  H.part_b = c.take<double>(5 * (size_t)nbs);
   H.part_v = c.take<double>(2 * (size_t)nbs);
   H.part_t = c.take<double>(3 * (size_t)nbs);
   H.part_ur = c.take<double>(2 * (size_t)nbs);
@@ -555,6 +555,7 @@ int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   h.fact_dt = -1.0;
   h.fact_theta = -1.0;
   h.prev_dt = 0.0;
+  h.prev_dt2 = 0.0;
   h.t_now = I->t;
   HIPCHK(hipMemcpyAsync(I->sc, &h, sizeof h, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));
@@ -1061,7 +1062,7 @@ int upload_instance(pd_instance *I, const HostImage &X) {
     if ((rc = up(H.tpow, X.tp, sizeof X.tp))) return rc;
   }
   I->rot = 0;
-  if ((rc = up(H.sol[1], X.u0_int.data(), (size_t)np * 8))) return rc;
+  if ((rc = up(H.sol[sol_slot(0, 0)], X.u0_int.data(), (size_t)np * 8))) return rc;
   if ((rc = ensure_time_capacity(I, 16))) return rc;
   HIPCHK(hipStreamSynchronize(s));
   I->t = 0.0;
@@ -1249,7 +1250,7 @@ int pd_get_solution(const pd_instance *I, double *out, int32_t layout, int32_t d
   const int m = I->M.m, n = I->M.n, N = m * n + 1;
   std::vector<double> h(I->T.npad), o(N);
   HIPCHK(hipStreamSynchronize(I->stream));
-  HIPCHK(hipMemcpy(h.data(), I->H.sol[(I->rot + 1) % 3], I->T.npad * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(h.data(), I->H.sol[sol_slot(I->rot, 0)], I->T.npad * sizeof(double), hipMemcpyDeviceToHost));
   from_internal(h.data(), layout, m, n, o.data());
   if (device_ptr) {
     HIPCHK(hipMemcpy(out, o.data(), N * sizeof(double), hipMemcpyHostToDevice));
@@ -1275,7 +1276,7 @@ int pd_set_solution(pd_instance *I, const double *in, int32_t layout, int32_t de
   if (rc) return rc;
   std::vector<double> h(I->T.npad);
   to_internal(src.data(), layout, m, n, I->T.npad, h.data());
-  HIPCHK(hipMemcpy(I->H.sol[(I->rot + 1) % 3], h.data(), I->T.npad * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I->H.sol[sol_slot(I->rot, 0)], h.data(), I->T.npad * sizeof(double), hipMemcpyHostToDevice));
   I->t = t;
   I->have_prev = false;
   return PD_OK;
@@ -1426,7 +1427,7 @@ int pd_error_indicator(pd_instance *I, double p_current, const double *p_candida
     ~Free() { (void)hipFree(p); }
   } fr{dbuf};
   const PdInst &H = I->H;
-  pd::launch_indicator(H.sol[(I->rot + 1) % 3], m, n, H.r_nodes, H.th_nodes, H.nb, H.lam, H.tpow, H.nsrc,
+  pd::launch_indicator(H.sol[sol_slot(I->rot, 0)], m, n, H.r_nodes, H.th_nodes, H.nb, H.lam, H.tpow, H.nsrc,
                        I->t, I->bc == 0 ? 1 : 0, dbuf, eta ? dbuf + ring_vals : nullptr, s);
   HIPCHK(hipGetLastError());
   std::vector<double> ring(ring_vals);
@@ -1475,9 +1476,9 @@ int pd_remesh_transfer(pd_instance *from, pd_instance *to) {
   HIPCHK(hipStreamSynchronize(from->stream));
   const PdInst &A = from->H;
   const PdInst &B = to->H;
-  pd::launch_transfer(A.sol[(from->rot + 1) % 3], from->M.m, from->M.n, A.r_nodes, A.th_nodes, A.nb, A.lam,
+  pd::launch_transfer(A.sol[sol_slot(from->rot, 0)], from->M.m, from->M.n, A.r_nodes, A.th_nodes, A.nb, A.lam,
                       A.tpow, A.nsrc, from->t, from->bc == 0 ? 1 : 0, B.r_nodes, B.th_nodes, to->M.m, to->M.n,
-                      B.sol[(to->rot + 1) % 3], to->stream);
+                      B.sol[sol_slot(to->rot, 0)], to->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(to->stream));
   to->t = from->t;

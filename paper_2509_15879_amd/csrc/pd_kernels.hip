@@ -148,7 +148,7 @@ template <typename T>
 __device__ __forceinline__ T *iterate_ptr(const PdInst &I, const PdScalars *sc);
 template <>
 __device__ __forceinline__ double *iterate_ptr<double>(const PdInst &I, const PdScalars *sc) {
-  return I.sol[(sc->rot + 2) % 3];
+  return I.sol[sol_slot(sc->rot, -1)];
 }
 template <>
 __device__ __forceinline__ float *iterate_ptr<float>(const PdInst &I, const PdScalars *sc) {
@@ -173,8 +173,17 @@ __device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
 // ------------------------------------------------------------ level control
 
 // Sets up level sc->level of an instance, t_k -> t_{k+1}: Δt, θ, the
-// source weights, the extrapolation factor; its factorisation (when Δt or θ
-// changed) and right-hand side are then due.
+// source weights, the initial guess's extrapolation weights; its
+// factorisation (when Δt or θ changed) and right-hand side are then due.
+//
+// The guess extrapolates the last levels to t_{k+1} by the Lagrange
+// polynomial through (t_{k-2}, t_{k-1}, t_k) (quadratic; linear or constant
+// while fewer levels are known), written in differences:
+//   g = n^k + a (n^k - n^{k-1}) + b (n^{k-1} - n^{k-2}),
+// with Δ0 = t_{k+1} - t_k, Δ1 = t_k - t_{k-1}, Δ2 = t_{k-1} - t_{k-2}:
+//   quadratic  a = Δ0 (Δ0+Δ1+Δ2)/(Δ1 Δ2) - b',  b = -b',  b' = Δ0 (Δ0+Δ1)/((Δ1+Δ2) Δ2)
+//   linear     a = Δ0/Δ1, b = 0.
+// Only the iteration's starting point depends on it, not the solution.
 __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   const int k = sc->level;
   const double t0 = I.t_table[k], t1 = I.t_table[k + 1];
@@ -184,7 +193,17 @@ __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   sc->dt = dt;
   sc->inv_dt = 1.0 / dt;
   sc->refactor = (dt != sc->fact_dt || th != sc->fact_theta) ? 1 : 0;
-  sc->extrap = sc->have_prev ? dt / sc->prev_dt : 0.0;
+  const int nprev = sc->have_prev;
+  if (nprev >= 2) {
+    const double d1 = sc->prev_dt, d2 = sc->prev_dt2;
+    const double bq = dt * (dt + d1) / ((d1 + d2) * d2);
+    sc->ex_a = dt * (dt + d1 + d2) / (d1 * d2) - bq;
+    sc->ex_b = -bq;
+  } else {
+    sc->ex_a = nprev == 1 ? dt / sc->prev_dt : 0.0;
+    sc->ex_b = 0.0;
+  }
+  sc->ex_n = nprev < 2 ? nprev : 2;
   for (int s = 0; s < PD_MAXSRC; ++s) sc->cq[s] = 0.0;
   for (int s = 0; s < I.nsrc; ++s)
     sc->cq[s] = (1.0 - th) * tau_q(I.lam[s], I.tpow[s], t0) + th * tau_q(I.lam[s], I.tpow[s], t1);
@@ -202,7 +221,7 @@ __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   sc->reset_rh = 0;
   sc->inner_first = 1;
   sc->alpha = sc->omega = 1.0;
-  sc->rho_old = sc->rho_new = sc->rho_next = sc->rho_cur = 1.0;
+  sc->rho_next = sc->rho_cur = 1.0;
 }
 
 // Records the level that just ended and rotates the solution buffers
@@ -221,9 +240,10 @@ __device__ __forceinline__ bool end_level(const PdInst &I, PdScalars *sc) {
   sc->total_iters += sc->iters;
   const bool ok = sc->status == ST_DONE;
   if (!ok) sc->nfail += 1;
-  sc->rot = (sc->rot + 1) % 3;       // old iterate slot becomes n^k
+  sc->rot = (sc->rot + 1) % PD_NSOL;   // the iterate's slot becomes n^k
+  sc->prev_dt2 = sc->prev_dt;
   sc->prev_dt = sc->dt;
-  sc->have_prev = 1;
+  sc->have_prev = sc->have_prev < 2 ? sc->have_prev + 1 : 2;
   sc->t_now = sc->t1;
   sc->level = k + 1;
   if (sc->refactor) {
@@ -607,6 +627,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
                                           const GAS TF *__restrict__ gm_t,
                                           const GAS TX *__restrict__ X0,
                                           const GAS TX *__restrict__ X1,
+                                          const GAS TX *__restrict__ X2,
                                           const GAS double *__restrict__ inv_rw,
                                           const GAS double *__restrict__ inv_dth,
                                           const GAS double *__restrict__ bnode, double (&S0)[NV],
@@ -614,7 +635,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
   const int m = g.m, n = g.n, jc = g.jc;
   const int i0 = g.i0, i1 = g.i1, nr = i1 - i0 + 1;
   const int orig = m * n;
-  const GAS TX *X[2] = {X0, X1};
+  const GAS TX *X[3] = {X0, X1, X2};
   const double idth = inv_dth[jc];
   // wave-edge columns for every row of the tile
   const int hr = (g.lane < nr) ? (i0 - 1 + g.lane) * n : (i0 - 1) * n;
@@ -704,21 +725,24 @@ struct OriginBegin {
   double b, xg, r, rs, bb, rr;
 };
 __device__ __forceinline__ OriginBegin origin_begin(const PdInst &I, const PdScalars *sc,
-                                                    const double (&tot)[4]) {
+                                                    const double (&tot)[5]) {
   const int orig = I.m * I.n;
-  const double inv_dt = sc->inv_dt, th = sc->theta, rho = sc->extrap;
-  const bool ex = rho != 0.0;
-  const double *xk = I.sol[(sc->rot + 1) % 3], *xkm = I.sol[sc->rot % 3];
+  const double inv_dt = sc->inv_dt, th = sc->theta, ea = sc->ex_a, eb = sc->ex_b;
+  const int ne = sc->ex_n;
+  const double *xk = I.sol[sol_slot(sc->rot, 0)];
+  const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
+  const double *xk2 = I.sol[sol_slot(sc->rot, ne >= 2 ? 2 : 0)];
   const double bo = I.has_b ? I.b_node[orig] : 0.0;
-  const double xk0 = xk[orig], xkm0 = ex ? xkm[orig] : xk0;
-  const double L0 = I.inv_V0 * tot[2] + bo * xk0;
-  const double L1 = I.inv_V0 * tot[3] + bo * xkm0;
-  double b = inv_dt * xk0 - (1.0 - th) * L0;
+  const double x0 = xk[orig], x1 = xk1[orig], x2 = xk2[orig];
+  const double L0 = I.inv_V0 * tot[2] + bo * x0;
+  const double L1 = I.inv_V0 * tot[3] + bo * x1;
+  const double L2 = I.inv_V0 * tot[4] + bo * x2;
+  double b = inv_dt * x0 - (1.0 - th) * L0;
   for (int q = 0; q < I.nsrc; ++q) b += sc->cq[q] * I.g[q * I.npad + orig];
   OriginBegin O;
   O.b = b;
-  O.xg = ex ? xk0 + rho * (xk0 - xkm0) : xk0;
-  const double Lg = ex ? L0 + rho * (L0 - L1) : L0;
+  O.xg = x0 + ea * (x0 - x1) + eb * (x1 - x2);
+  const double Lg = L0 + ea * (L0 - L1) + eb * (L1 - L2);
   O.r = b - (inv_dt * O.xg + th * Lg);
   const double id = I.inv_diag[orig];
   O.rs = O.r * id;
@@ -731,7 +755,7 @@ __device__ __forceinline__ void origin_begin_store(const PdInst &I, const PdScal
                                                    const OriginBegin &O) {
   const int orig = I.m * I.n;
   I.bvec[orig] = O.b;
-  I.sol[(sc->rot + 2) % 3][orig] = O.xg;
+  I.sol[sol_slot(sc->rot, -1)][orig] = O.xg;
   if (I.mixed) {
     I.k32.r[orig] = (float)O.rs;
     I.k32.rh[orig] = (float)O.rs;
@@ -820,24 +844,27 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     double S0[1] = {0.0};
     GAS TK *y = G(ay);
     if (wave_on)
-      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(ax), G(ax), inv_rw,
+      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(ax), G(ax), G(ax), inv_rw,
                            inv_dth, bnode, S0, no_pre,
                            [&](int, int, int idx, const double *xc, const double *Lx, Nil) {
                              y[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
                            });
     produce<1>(S0, I.part_a, I.nb_sten, mp.y);
   } else if (MODE == SM_BEGIN) {
-    // FP64 operator on x^k and x^{k-1}
-    const double inv_dt = sc->inv_dt, th = sc->theta, rho = sc->extrap;
-    const double *xk = I.sol[(sc->rot + 1) % 3];
-    const double *xkm = I.sol[sc->rot % 3];
-    double *x0 = I.sol[(sc->rot + 2) % 3];
-    const bool ex = rho != 0.0;
+    // FP64 operator on n^k, n^{k-1}, n^{k-2} (those the guess uses; the
+    // others alias n^k and carry zero weight)
+    const double inv_dt = sc->inv_dt, th = sc->theta, ea = sc->ex_a, eb = sc->ex_b;
+    const int ne = sc->ex_n;
+    const double *xk = I.sol[sol_slot(sc->rot, 0)];
+    const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
+    const double *xk2 = I.sol[sol_slot(sc->rot, ne >= 2 ? 2 : 0)];
+    double *x0 = I.sol[sol_slot(sc->rot, -1)];
     double cq[PD_MAXSRC];
     for (int q = 0; q < PD_MAXSRC; ++q) cq[q] = sc->cq[q];
     const int nsrc = I.nsrc, npad = I.npad;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // ||D^-1 b||^2, ||D^-1 r||^2, S0(x^k), S0(x^{k-1})
-    double S0[2] = {0.0, 0.0};
+    // ||D^-1 b||^2, ||D^-1 r||^2, S0(n^k), S0(n^{k-1}), S0(n^{k-2})
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double S0[3] = {0.0, 0.0, 0.0};
     const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb), *idg = G(I.inv_diag);
     GAS double *bv = G(I.bvec), *xo = G(x0);
     GAS double *rout = G(I.rout);
@@ -845,8 +872,8 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh);
     const bool mixed = I.mixed;
     if (wave_on)
-      sten_tile<double, double, 2>(
-          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk), G(ex ? xkm : xk),
+      sten_tile<double, double, 3>(
+          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk), G(xk1), G(xk2),
           inv_rw, inv_dth, bnode, S0, no_pre,
           [&](int i, int j, int idx, const double *xc, const double *Lx, Nil) {
             double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
@@ -856,8 +883,8 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
               for (int q = 0; q < nsrc; ++q) Nm += cq[q] * nbv[q * n + j];
               b += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
             }
-            const double xg = ex ? xc[0] + rho * (xc[0] - xc[1]) : xc[0];
-            const double Lg = ex ? Lx[0] + rho * (Lx[0] - Lx[1]) : Lx[0];
+            const double xg = xc[0] + ea * (xc[0] - xc[1]) + eb * (xc[1] - xc[2]);
+            const double Lg = Lx[0] + ea * (Lx[0] - Lx[1]) + eb * (Lx[1] - Lx[2]);
             const double r = b - (inv_dt * xg + th * Lg);
             const double id = idg[idx];
             const double rs = r * id, bs = b * id;
@@ -876,7 +903,8 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
           });
     acc[2] = S0[0];
     acc[3] = S0[1];
-    produce<4>(acc, I.part_b, I.nb_sten, mp.y);
+    acc[4] = S0[2];
+    produce<5>(acc, I.part_b, I.nb_sten, mp.y);
   } else if (MODE == SM_V || MODE == SM_T) {
     const double inv_dt = sc->inv_dt, th = sc->theta;
     const TK *xin = (MODE == SM_V) ? KS.ph : KS.sh;
@@ -888,7 +916,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     double acc[3] = {0.0, 0.0, 0.0};
     double S0[1] = {0.0};
     if (wave_on)
-      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(xin), G(xin),
+      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(xin), G(xin), G(xin),
                            inv_rw, inv_dth, bnode, S0,
                            [&](int idx) { return Pre2{(double)idg[idx], (double)ot[idx]}; },
                            [&](int, int, int idx, const double *xc, const double *Lx, Pre2 q) {
@@ -909,7 +937,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
   } else if (MODE == SM_UR) {
     // FP64 operator applied to the FP32 correction d
     const double inv_dt = sc->inv_dt, th = sc->theta;
-    double *x = I.sol[(sc->rot + 2) % 3];
+    double *x = I.sol[sol_slot(sc->rot, -1)];
     GAS double *xg = G(x), *rout = G(I.rout);
     const GAS double *idg = G(I.inv_diag);
     GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh);
@@ -917,7 +945,8 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     double S0[1] = {0.0};
     if (wave_on)
       sten_tile<double, float, 1>(geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t),
-                                  G((const float *)I.k32.d), G((const float *)I.k32.d), inv_rw,
+                                  G((const float *)I.k32.d), G((const float *)I.k32.d),
+                                  G((const float *)I.k32.d), inv_rw,
                                   inv_dth, bnode, S0,
                                   [&](int idx) { return Pre3{rout[idx], idg[idx], xg[idx]}; },
                                   [&](int, int, int idx, const double *xc, const double *Lx, Pre3 q) {
@@ -952,8 +981,8 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ninst) return;
   const PdInst &I = insts[q];
-  double tot[4];
-  for (int k = 0; k < 4; ++k) {
+  double tot[5];
+  for (int k = 0; k < 5; ++k) {
     double sum = 0.0;
     for (int b = 0; b < I.nb_sten; ++b) sum += I.part_b[k * I.nb_sten + b];
     tot[k] = sum;
@@ -1180,8 +1209,8 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
     int st = ST_ACTIVE;
     double rho = 0.0, rel = -1.0;
     if (pend == PEND_BEGIN) {
-      double tot[4];
-      consume<4>(I.part_b, I.nb_sten, tot);
+      double tot[5];
+      consume<5>(I.part_b, I.nb_sten, tot);
       const OriginBegin O = origin_begin(I, sc, tot);
       if (b0) {
         origin_begin_store(I, sc, O);
@@ -1203,7 +1232,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
       const OriginRefine O = origin_refine(I, sc, tot);
       if (b0) {
         sc->rout0[sc->outer & 1] = O.r;
-        I.sol[(sc->rot + 2) % 3][orig] += O.d0;
+        I.sol[sol_slot(sc->rot, -1)][orig] += O.d0;
         I.k32.r[orig] = (float)O.rs;
         I.k32.rh[orig] = (float)O.rs;
         sc->r0norm2 = O.rr;
