@@ -24,11 +24,12 @@
 #define PD_RAD_BMAX 32    // max rows per radial segment held in registers
 #define PD_ANG_BMAX 32    // max angular nodes per lane held in registers
 #define PD_NSLOT 4
-#define PD_NSOL 4         // rotating solution slots: n^{k-2}, n^{k-1}, n^k, iterate
+#define PD_NHIST 4        // earlier levels kept for the initial guess: n^k .. n^{k-3}
+#define PD_NSOL 5         // rotating solution slots: the PD_NHIST levels and the iterate
 
-// Slot holding n^{k-back} (back = 0, 1, 2) or, for back = -1, the iterate of
+// Slot holding n^{k-back} (back = 0..3) or, for back = -1, the iterate of
 // the level under way, under rotation `rot`.
-__host__ __device__ inline int sol_slot(int rot, int back) { return (rot + 2 - back) % PD_NSOL; }
+__host__ __device__ inline int sol_slot(int rot, int back) { return (rot + 3 - back) % PD_NSOL; }
 
 enum { ST_IDLE = 0, ST_ACTIVE = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOCONV = 4 };
 enum { PH_INNER = 0, PH_OUTER = 1 };
@@ -44,11 +45,14 @@ enum { CNT_BEGIN = 0, CNT_V = 1, CNT_T = 2, CNT_X = 3, CNT_UR = 4, CNT_APPLY = 5
 struct PdScalars {
   // time level
   double t0, t1, dt, inv_dt, theta;
-  double ex_a, ex_b;        // initial guess n^k + ex_a (n^k - n^{k-1}) + ex_b (n^{k-1} - n^{k-2})
-  int ex_n, pad3;           // earlier levels the guess uses (0, 1 or 2)
+  double ex_w[2][PD_NHIST]; // two candidate initial guesses: Σ_a w[c][a] n^{k-a}
+  int ex_n;                 // earlier levels beyond n^k the guesses use (0..3)
+  int ex_sel;               // candidate taken at this level
+  int ex_next;              // candidate with the smaller residual at this level's begin
+  int pad3;
   double cq[PD_MAXSRC];
   double tol, tol_inner;
-  double fact_dt, fact_theta, prev_dt, prev_dt2;   // Δt of the last two levels
+  double fact_dt, fact_theta;
   int maxit, level, K, refactor;
   int status, phase, iters, outer;
   int inner_iters, restarts, first, reset_rh;

@@ -554,8 +554,6 @@ int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   h.have_prev = 0;             // extrapolation restarts with each solve call
   h.fact_dt = -1.0;
   h.fact_theta = -1.0;
-  h.prev_dt = 0.0;
-  h.prev_dt2 = 0.0;
   h.t_now = I->t;
   HIPCHK(hipMemcpyAsync(I->sc, &h, sizeof h, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));

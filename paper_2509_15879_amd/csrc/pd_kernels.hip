@@ -172,18 +172,79 @@ __device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
 
 // ------------------------------------------------------------ level control
 
+// Weights of the initial guesses of level k -> k+1 (t = t_{k+1}) from the
+// levels t_{k-a}, a = 0..ne, of this solve (ne = 0..3).
+//  candidate 0: the Lagrange polynomial through all of them (cubic at ne = 3);
+//  candidate 1: at ne = 3, a quadratic plus a component multiplied by
+//    ρ = -(1-θ)/θ per level, the amplification of the θ-scheme on its
+//    stiffest modes (ρ = -1 for Crank-Nicolson, whose stiff error components
+//    alternate in sign instead of decaying); the quadratic through the last
+//    three levels when ρ is near 0 (θ near 1); below ne = 3, candidate 0.
+// Only where the iteration starts depends on them, not the solution.
+__device__ void guess_weights(const double *tt, int k, int ne, double theta, double (&w)[2][PD_NHIST]) {
+  const double t = tt[k + 1], h = t - tt[k];
+  double s[PD_NHIST];   // (t_{k-a} - t)/Δt
+  for (int a = 0; a < PD_NHIST; ++a) {
+    s[a] = a <= ne ? (tt[k - a] - t) / h : 0.0;
+    w[0][a] = w[1][a] = 0.0;
+  }
+  for (int a = 0; a <= ne; ++a) {
+    double l = 1.0;
+    for (int c = 0; c <= ne; ++c)
+      if (c != a) l *= (0.0 - s[c]) / (s[a] - s[c]);
+    w[0][a] = l;
+  }
+  if (ne < 3) {
+    for (int a = 0; a < PD_NHIST; ++a) w[1][a] = w[0][a];
+    return;
+  }
+  const double rho = -(1.0 - theta) / theta;
+  if (rho > -0.05) {
+    for (int a = 0; a <= 2; ++a) {
+      double l = 1.0;
+      for (int c = 0; c <= 2; ++c)
+        if (c != a) l *= (0.0 - s[c]) / (s[a] - s[c]);
+      w[1][a] = l;
+    }
+    return;
+  }
+  // Σ_a w_a = 1, Σ_a w_a s_a = 0, Σ_a w_a s_a² = 0, Σ_a w_a ρ^{-a} = ρ
+  double A[4][5];
+  for (int a = 0; a < 4; ++a) {
+    A[0][a] = 1.0;
+    A[1][a] = s[a];
+    A[2][a] = s[a] * s[a];
+    A[3][a] = pow(rho, -(double)a);
+  }
+  A[0][4] = 1.0;
+  A[1][4] = 0.0;
+  A[2][4] = 0.0;
+  A[3][4] = rho;
+  for (int c = 0; c < 4; ++c) {             // Gaussian elimination, partial pivoting
+    int pr = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (fabs(A[r][c]) > fabs(A[pr][c])) pr = r;
+    for (int q = 0; q < 5; ++q) {
+      const double tmp = A[c][q];
+      A[c][q] = A[pr][q];
+      A[pr][q] = tmp;
+    }
+    for (int r = c + 1; r < 4; ++r) {
+      const double f = A[r][c] / A[c][c];
+      for (int q = c; q < 5; ++q) A[r][q] -= f * A[c][q];
+    }
+  }
+  for (int c = 3; c >= 0; --c) {
+    double v = A[c][4];
+    for (int q = c + 1; q < 4; ++q) v -= A[c][q] * w[1][q];
+    w[1][c] = v / A[c][c];
+  }
+}
+
 // Sets up level sc->level of an instance, t_k -> t_{k+1}: Δt, θ, the
-// source weights, the initial guess's extrapolation weights; its
+// source weights, the initial guesses' weights (the candidate with the
+// smaller residual at the previous level's begin is taken); its
 // factorisation (when Δt or θ changed) and right-hand side are then due.
-//
-// The guess extrapolates the last levels to t_{k+1} by the Lagrange
-// polynomial through (t_{k-2}, t_{k-1}, t_k) (quadratic; linear or constant
-// while fewer levels are known), written in differences:
-//   g = n^k + a (n^k - n^{k-1}) + b (n^{k-1} - n^{k-2}),
-// with Δ0 = t_{k+1} - t_k, Δ1 = t_k - t_{k-1}, Δ2 = t_{k-1} - t_{k-2}:
-//   quadratic  a = Δ0 (Δ0+Δ1+Δ2)/(Δ1 Δ2) - b',  b = -b',  b' = Δ0 (Δ0+Δ1)/((Δ1+Δ2) Δ2)
-//   linear     a = Δ0/Δ1, b = 0.
-// Only the iteration's starting point depends on it, not the solution.
 __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   const int k = sc->level;
   const double t0 = I.t_table[k], t1 = I.t_table[k + 1];
@@ -193,17 +254,13 @@ __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   sc->dt = dt;
   sc->inv_dt = 1.0 / dt;
   sc->refactor = (dt != sc->fact_dt || th != sc->fact_theta) ? 1 : 0;
-  const int nprev = sc->have_prev;
-  if (nprev >= 2) {
-    const double d1 = sc->prev_dt, d2 = sc->prev_dt2;
-    const double bq = dt * (dt + d1) / ((d1 + d2) * d2);
-    sc->ex_a = dt * (dt + d1 + d2) / (d1 * d2) - bq;
-    sc->ex_b = -bq;
-  } else {
-    sc->ex_a = nprev == 1 ? dt / sc->prev_dt : 0.0;
-    sc->ex_b = 0.0;
-  }
-  sc->ex_n = nprev < 2 ? nprev : 2;
+  const int ne = min(sc->have_prev, PD_NHIST - 1);
+  double w[2][PD_NHIST];
+  guess_weights(I.t_table, k, ne, th, w);
+  for (int c = 0; c < 2; ++c)
+    for (int a = 0; a < PD_NHIST; ++a) sc->ex_w[c][a] = w[c][a];
+  sc->ex_n = ne;
+  sc->ex_sel = sc->ex_next;
   for (int s = 0; s < PD_MAXSRC; ++s) sc->cq[s] = 0.0;
   for (int s = 0; s < I.nsrc; ++s)
     sc->cq[s] = (1.0 - th) * tau_q(I.lam[s], I.tpow[s], t0) + th * tau_q(I.lam[s], I.tpow[s], t1);
@@ -241,9 +298,7 @@ __device__ __forceinline__ bool end_level(const PdInst &I, PdScalars *sc) {
   const bool ok = sc->status == ST_DONE;
   if (!ok) sc->nfail += 1;
   sc->rot = (sc->rot + 1) % PD_NSOL;   // the iterate's slot becomes n^k
-  sc->prev_dt2 = sc->prev_dt;
-  sc->prev_dt = sc->dt;
-  sc->have_prev = sc->have_prev < 2 ? sc->have_prev + 1 : 2;
+  sc->have_prev = min(sc->have_prev + 1, PD_NHIST - 1);
   sc->t_now = sc->t1;
   sc->level = k + 1;
   if (sc->refactor) {
@@ -628,6 +683,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
                                           const GAS TX *__restrict__ X0,
                                           const GAS TX *__restrict__ X1,
                                           const GAS TX *__restrict__ X2,
+                                          const GAS TX *__restrict__ X3,
                                           const GAS double *__restrict__ inv_rw,
                                           const GAS double *__restrict__ inv_dth,
                                           const GAS double *__restrict__ bnode, double (&S0)[NV],
@@ -635,7 +691,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
   const int m = g.m, n = g.n, jc = g.jc;
   const int i0 = g.i0, i1 = g.i1, nr = i1 - i0 + 1;
   const int orig = m * n;
-  const GAS TX *X[3] = {X0, X1, X2};
+  const GAS TX *X[4] = {X0, X1, X2, X3};
   const double idth = inv_dth[jc];
   // wave-edge columns for every row of the tile
   const int hr = (g.lane < nr) ? (i0 - 1 + g.lane) * n : (i0 - 1) * n;
@@ -720,35 +776,49 @@ enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4 };
 // Origin rows, closed by a later kernel from the producers' partial sums
 // (the ring-1 face sums S0 and the ring parts of the norms).
 
-// Level begin at the origin: rhs b_0, extrapolated guess, scaled residual.
+// Level begin at the origin: rhs b_0, both guesses and their scaled
+// residuals; the selected guess's values are stored.
 struct OriginBegin {
-  double b, xg, r, rs, bb, rr;
+  double b, xg, r, rs, bb, rr, rr_other;
 };
+// Partial sums of the level-begin stencil: ||D^-1 b||², the two candidates'
+// ||D^-1 r||², S0 of n^k .. n^{k-3}.
+#define PD_NBEGIN (3 + PD_NHIST)
 __device__ __forceinline__ OriginBegin origin_begin(const PdInst &I, const PdScalars *sc,
-                                                    const double (&tot)[5]) {
+                                                    const double (&tot)[PD_NBEGIN]) {
   const int orig = I.m * I.n;
-  const double inv_dt = sc->inv_dt, th = sc->theta, ea = sc->ex_a, eb = sc->ex_b;
-  const int ne = sc->ex_n;
-  const double *xk = I.sol[sol_slot(sc->rot, 0)];
-  const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
-  const double *xk2 = I.sol[sol_slot(sc->rot, ne >= 2 ? 2 : 0)];
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  const int ne = sc->ex_n, sel = sc->ex_sel;
   const double bo = I.has_b ? I.b_node[orig] : 0.0;
-  const double x0 = xk[orig], x1 = xk1[orig], x2 = xk2[orig];
-  const double L0 = I.inv_V0 * tot[2] + bo * x0;
-  const double L1 = I.inv_V0 * tot[3] + bo * x1;
-  const double L2 = I.inv_V0 * tot[4] + bo * x2;
-  double b = inv_dt * x0 - (1.0 - th) * L0;
+  double xa[PD_NHIST], La[PD_NHIST];
+  for (int a = 0; a < PD_NHIST; ++a) {
+    xa[a] = I.sol[sol_slot(sc->rot, a <= ne ? a : 0)][orig];
+    La[a] = I.inv_V0 * tot[3 + a] + bo * xa[a];
+  }
+  double b = inv_dt * xa[0] - (1.0 - th) * La[0];
   for (int q = 0; q < I.nsrc; ++q) b += sc->cq[q] * I.g[q * I.npad + orig];
+  const double id = I.inv_diag[orig];
   OriginBegin O;
   O.b = b;
-  O.xg = x0 + ea * (x0 - x1) + eb * (x1 - x2);
-  const double Lg = L0 + ea * (L0 - L1) + eb * (L1 - L2);
-  O.r = b - (inv_dt * O.xg + th * Lg);
-  const double id = I.inv_diag[orig];
-  O.rs = O.r * id;
+  double rs[2], xg[2], r[2];
+  for (int c = 0; c < 2; ++c) {   // c = 0: the selected candidate, 1: the other
+    const double *w = sc->ex_w[c == 0 ? sel : 1 - sel];
+    double g = 0.0, Lg = 0.0;
+    for (int a = 0; a < PD_NHIST; ++a) {
+      g += w[a] * xa[a];
+      Lg += w[a] * La[a];
+    }
+    r[c] = b - (inv_dt * g + th * Lg);
+    xg[c] = g;
+    rs[c] = r[c] * id;
+  }
+  O.r = r[0];
+  O.xg = xg[0];
+  O.rs = rs[0];
+  O.rr = tot[1] + rs[0] * rs[0];
+  O.rr_other = tot[2] + rs[1] * rs[1];
   const double bs = b * id;
   O.bb = tot[0] + bs * bs;
-  O.rr = tot[1] + O.rs * O.rs;
   return O;
 }
 __device__ __forceinline__ void origin_begin_store(const PdInst &I, const PdScalars *sc,
@@ -844,27 +914,33 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     double S0[1] = {0.0};
     GAS TK *y = G(ay);
     if (wave_on)
-      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(ax), G(ax), G(ax), inv_rw,
+      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(ax), G(ax), G(ax), G(ax), inv_rw,
                            inv_dth, bnode, S0, no_pre,
                            [&](int, int, int idx, const double *xc, const double *Lx, Nil) {
                              y[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
                            });
     produce<1>(S0, I.part_a, I.nb_sten, mp.y);
   } else if (MODE == SM_BEGIN) {
-    // FP64 operator on n^k, n^{k-1}, n^{k-2} (those the guess uses; the
-    // others alias n^k and carry zero weight)
-    const double inv_dt = sc->inv_dt, th = sc->theta, ea = sc->ex_a, eb = sc->ex_b;
-    const int ne = sc->ex_n;
-    const double *xk = I.sol[sol_slot(sc->rot, 0)];
+    // FP64 operator on n^k .. n^{k-3} (levels the guesses do not use alias
+    // n^k and carry zero weight); both candidates' residuals are summed, the
+    // selected one is stored
+    const double inv_dt = sc->inv_dt, th = sc->theta;
+    const int ne = sc->ex_n, sel = sc->ex_sel;
+    double w0[PD_NHIST], w1[PD_NHIST];
+    for (int a = 0; a < PD_NHIST; ++a) {
+      w0[a] = sc->ex_w[sel][a];
+      w1[a] = sc->ex_w[1 - sel][a];
+    }
+    const double *xk0 = I.sol[sol_slot(sc->rot, 0)];
     const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
     const double *xk2 = I.sol[sol_slot(sc->rot, ne >= 2 ? 2 : 0)];
+    const double *xk3 = I.sol[sol_slot(sc->rot, ne >= 3 ? 3 : 0)];
     double *x0 = I.sol[sol_slot(sc->rot, -1)];
     double cq[PD_MAXSRC];
     for (int q = 0; q < PD_MAXSRC; ++q) cq[q] = sc->cq[q];
     const int nsrc = I.nsrc, npad = I.npad;
-    // ||D^-1 b||^2, ||D^-1 r||^2, S0(n^k), S0(n^{k-1}), S0(n^{k-2})
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    double S0[3] = {0.0, 0.0, 0.0};
+    double acc[PD_NBEGIN] = {};   // ||D^-1 b||², selected and other ||D^-1 r||², S0 per level
+    double S0[PD_NHIST] = {};
     const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb), *idg = G(I.inv_diag);
     GAS double *bv = G(I.bvec), *xo = G(x0);
     GAS double *rout = G(I.rout);
@@ -872,9 +948,9 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh);
     const bool mixed = I.mixed;
     if (wave_on)
-      sten_tile<double, double, 3>(
-          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk), G(xk1), G(xk2),
-          inv_rw, inv_dth, bnode, S0, no_pre,
+      sten_tile<double, double, PD_NHIST>(
+          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk0), G(xk1), G(xk2),
+          G(xk3), inv_rw, inv_dth, bnode, S0, no_pre,
           [&](int i, int j, int idx, const double *xc, const double *Lx, Nil) {
             double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
             for (int q = 0; q < nsrc; ++q) b += cq[q] * gsrc[q * npad + idx];
@@ -883,11 +959,18 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
               for (int q = 0; q < nsrc; ++q) Nm += cq[q] * nbv[q * n + j];
               b += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
             }
-            const double xg = xc[0] + ea * (xc[0] - xc[1]) + eb * (xc[1] - xc[2]);
-            const double Lg = Lx[0] + ea * (Lx[0] - Lx[1]) + eb * (Lx[1] - Lx[2]);
+            double xg = 0.0, Lg = 0.0, xo2 = 0.0, Lo = 0.0;
+#pragma unroll
+            for (int a = 0; a < PD_NHIST; ++a) {
+              xg += w0[a] * xc[a];
+              Lg += w0[a] * Lx[a];
+              xo2 += w1[a] * xc[a];
+              Lo += w1[a] * Lx[a];
+            }
             const double r = b - (inv_dt * xg + th * Lg);
             const double id = idg[idx];
             const double rs = r * id, bs = b * id;
+            const double ro = (b - (inv_dt * xo2 + th * Lo)) * id;
             bv[idx] = b;
             xo[idx] = xg;
             if (mixed) {
@@ -900,11 +983,11 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
             }
             acc[0] += bs * bs;
             acc[1] += rs * rs;
+            acc[2] += ro * ro;
           });
-    acc[2] = S0[0];
-    acc[3] = S0[1];
-    acc[4] = S0[2];
-    produce<5>(acc, I.part_b, I.nb_sten, mp.y);
+#pragma unroll
+    for (int a = 0; a < PD_NHIST; ++a) acc[3 + a] = S0[a];
+    produce<PD_NBEGIN>(acc, I.part_b, I.nb_sten, mp.y);
   } else if (MODE == SM_V || MODE == SM_T) {
     const double inv_dt = sc->inv_dt, th = sc->theta;
     const TK *xin = (MODE == SM_V) ? KS.ph : KS.sh;
@@ -916,7 +999,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     double acc[3] = {0.0, 0.0, 0.0};
     double S0[1] = {0.0};
     if (wave_on)
-      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(xin), G(xin), G(xin),
+      sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(xin), G(xin), G(xin), G(xin),
                            inv_rw, inv_dth, bnode, S0,
                            [&](int idx) { return Pre2{(double)idg[idx], (double)ot[idx]}; },
                            [&](int, int, int idx, const double *xc, const double *Lx, Pre2 q) {
@@ -946,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (wave_on)
       sten_tile<double, float, 1>(geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t),
                                   G((const float *)I.k32.d), G((const float *)I.k32.d),
-                                  G((const float *)I.k32.d), inv_rw,
+                                  G((const float *)I.k32.d), G((const float *)I.k32.d), inv_rw,
                                   inv_dth, bnode, S0,
                                   [&](int idx) { return Pre3{rout[idx], idg[idx], xg[idx]}; },
                                   [&](int, int, int idx, const double *xc, const double *Lx, Pre3 q) {
@@ -981,8 +1064,8 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ninst) return;
   const PdInst &I = insts[q];
-  double tot[5];
-  for (int k = 0; k < 5; ++k) {
+  double tot[PD_NBEGIN];
+  for (int k = 0; k < PD_NBEGIN; ++k) {
     double sum = 0.0;
     for (int b = 0; b < I.nb_sten; ++b) sum += I.part_b[k * I.nb_sten + b];
     tot[k] = sum;
@@ -1209,8 +1292,8 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
     int st = ST_ACTIVE;
     double rho = 0.0, rel = -1.0;
     if (pend == PEND_BEGIN) {
-      double tot[5];
-      consume<5>(I.part_b, I.nb_sten, tot);
+      double tot[PD_NBEGIN];
+      consume<PD_NBEGIN>(I.part_b, I.nb_sten, tot);
       const OriginBegin O = origin_begin(I, sc, tot);
       if (b0) {
         origin_begin_store(I, sc, O);
@@ -1220,6 +1303,8 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
         sc->inner_first = 1;
         sc->inner_iters = 0;
         sc->rout0[0] = O.r;
+        // the candidate for the next level: the one with the smaller residual here
+        if (sc->ex_n == PD_NHIST - 1 && O.rr_other < O.rr) sc->ex_next = 1 - sc->ex_sel;
       }
       rho = O.rr;
       first = true;
