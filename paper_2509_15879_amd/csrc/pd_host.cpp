@@ -499,6 +499,7 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
     P.L.mixed_any |= insts[q]->precision == PD_MIXED;
     P.L.fp64_any |= insts[q]->precision != PD_MIXED;
     P.L.max_bang = std::max(P.L.max_bang, insts[q]->T.bang);
+    P.L.max_bfrad = std::max(P.L.max_bfrad, insts[q]->T.brad);
   }
   for (auto *I : insts) {
     const int c = pd::rad_class(I->M.m);

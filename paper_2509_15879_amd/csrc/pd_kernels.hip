@@ -184,61 +184,49 @@ __device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
 __device__ void guess_weights(const double *tt, int k, int ne, double theta, double (&w)[2][PD_NHIST]) {
   const double t = tt[k + 1], h = t - tt[k];
   double s[PD_NHIST];   // (t_{k-a} - t)/Δt
+#pragma unroll
+  for (int a = 0; a < PD_NHIST; ++a) s[a] = a <= ne ? (tt[k - a] - t) / h : 0.0;
+  // Lagrange weights through the ne + 1 known levels, at s = 0
+#pragma unroll
   for (int a = 0; a < PD_NHIST; ++a) {
-    s[a] = a <= ne ? (tt[k - a] - t) / h : 0.0;
-    w[0][a] = w[1][a] = 0.0;
+    double l = a <= ne ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < PD_NHIST; ++c)
+      if (c != a && c <= ne && a <= ne) l *= (0.0 - s[c]) / (s[a] - s[c]);
+    w[0][a] = w[1][a] = l;
   }
-  for (int a = 0; a <= ne; ++a) {
-    double l = 1.0;
-    for (int c = 0; c <= ne; ++c)
-      if (c != a) l *= (0.0 - s[c]) / (s[a] - s[c]);
-    w[0][a] = l;
-  }
-  if (ne < 3) {
-    for (int a = 0; a < PD_NHIST; ++a) w[1][a] = w[0][a];
-    return;
-  }
+  if (ne < PD_NHIST - 1) return;
   const double rho = -(1.0 - theta) / theta;
   if (rho > -0.05) {
-    for (int a = 0; a <= 2; ++a) {
-      double l = 1.0;
-      for (int c = 0; c <= 2; ++c)
-        if (c != a) l *= (0.0 - s[c]) / (s[a] - s[c]);
+    // the quadratic through the last three levels
+#pragma unroll
+    for (int a = 0; a < PD_NHIST; ++a) {
+      double l = a < 3 ? 1.0 : 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c != a && a < 3) l *= (0.0 - s[c]) / (s[a] - s[c]);
       w[1][a] = l;
     }
     return;
   }
-  // Σ_a w_a = 1, Σ_a w_a s_a = 0, Σ_a w_a s_a² = 0, Σ_a w_a ρ^{-a} = ρ
-  double A[4][5];
-  for (int a = 0; a < 4; ++a) {
-    A[0][a] = 1.0;
-    A[1][a] = s[a];
-    A[2][a] = s[a] * s[a];
-    A[3][a] = pow(rho, -(double)a);
+  // The cubic's weights reproduce quadratics; so do they plus any multiple
+  // of v_a = 1/Π_{c≠a}(s_a - s_c), which annihilates quadratics.  The
+  // multiple is fixed by Σ_a w_a ρ^{-a} = ρ (exactness on the stiff mode).
+  double v[PD_NHIST], sw = 0.0, sv = 0.0, pa = 1.0;
+#pragma unroll
+  for (int a = 0; a < PD_NHIST; ++a) {
+    double q = 1.0;
+#pragma unroll
+    for (int c = 0; c < PD_NHIST; ++c)
+      if (c != a) q *= s[a] - s[c];
+    v[a] = 1.0 / q;
+    sw += w[0][a] * pa;
+    sv += v[a] * pa;
+    pa /= rho;
   }
-  A[0][4] = 1.0;
-  A[1][4] = 0.0;
-  A[2][4] = 0.0;
-  A[3][4] = rho;
-  for (int c = 0; c < 4; ++c) {             // Gaussian elimination, partial pivoting
-    int pr = c;
-    for (int r = c + 1; r < 4; ++r)
-      if (fabs(A[r][c]) > fabs(A[pr][c])) pr = r;
-    for (int q = 0; q < 5; ++q) {
-      const double tmp = A[c][q];
-      A[c][q] = A[pr][q];
-      A[pr][q] = tmp;
-    }
-    for (int r = c + 1; r < 4; ++r) {
-      const double f = A[r][c] / A[c][c];
-      for (int q = c; q < 5; ++q) A[r][q] -= f * A[c][q];
-    }
-  }
-  for (int c = 3; c >= 0; --c) {
-    double v = A[c][4];
-    for (int q = c + 1; q < 4; ++q) v -= A[c][q] * w[1][q];
-    w[1][c] = v / A[c][c];
-  }
+  const double g = (rho - sw) / sv;
+#pragma unroll
+  for (int a = 0; a < PD_NHIST; ++a) w[1][a] = w[0][a] + g * v[a];
 }
 
 // Sets up level sc->level of an instance, t_k -> t_{k+1}: Δt, θ, the
@@ -363,106 +351,161 @@ struct RadRow {
   double d, a, c;   // diagonal of A, scaled sub and super entries
 };
 
-__device__ __forceinline__ RadRow rad_row(const PdInst &I, int i, int j, double inv_dt, double th) {
-  const int m = I.m, n = I.n;
-  const int jl = (j == 0) ? n - 1 : j - 1;
-  const GAS double *gpr = G(I.k64.gp_r), *gmr = G(I.k64.gm_r);
-  const GAS double *gpt = G(I.k64.gp_t), *gmt = G(I.k64.gm_t);
-  const int row = (i - 1) * n;
-  const double gpo = gpr[i * n + j], gmo = gmr[i * n + j];
-  const double gpi = gpr[(i - 1) * n + j], gmi = gmr[(i - 1) * n + j];
-  const double ivV = G(I.inv_rw)[i] * G(I.inv_dth)[j];
-  double v = ivV * (gpo + gmi + gpt[row + j] + gmt[row + jl]);
-  if (I.has_b) v += G(I.b_node)[row + j];
-  RadRow R;
-  R.d = inv_dt + th * v;
-  const double s = th * ivV / R.d;
-  R.a = (i >= 2) ? -s * gpi : 0.0;
-  R.c = (i < m) ? -s * gmo : 0.0;
-  return R;
-}
-
 struct Mat2 {
   double a, b, c, d;   // [[a, b], [c, d]]
 };
 __device__ __forceinline__ Mat2 mul2(Mat2 x, Mat2 y) {
   return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
 }
+// Rescales by a power of two (exact) to keep the products in range.
 __device__ __forceinline__ Mat2 norm2(Mat2 x) {
   const double s = fmax(fmax(fabs(x.a), fabs(x.b)), fmax(fabs(x.c), fabs(x.d)));
-  const double k = (s > 0.0) ? 1.0 / s : 1.0;
-  return {x.a * k, x.b * k, x.c * k, x.d * k};
+  if (!(s > 0.0) || !(s < INFINITY)) return x;
+  const int e = -ilogb(s);
+  return {ldexp(x.a, e), ldexp(x.b, e), ldexp(x.c, e), ldexp(x.d, e)};
 }
 
+// Row i of the radial system from its loaded face values: diagonal of A and
+// the scaled sub/super entries (ring 1 has no sub entry, ring m no super).
+__device__ __forceinline__ RadRow rad_row_of(int i, int m, double gpo, double gmo, double gpi,
+                                             double gmi, double gpt, double gmtl, double ivV,
+                                             double bP, double inv_dt, double th) {
+  RadRow R;
+  R.d = inv_dt + th * (ivV * (gpo + gmi + gpt + gmtl) + bP);
+  const double s = th * ivV / R.d;
+  R.a = (i >= 2) ? -s * gpi : 0.0;
+  R.c = (i < m) ? -s * gmo : 0.0;
+  return R;
+}
+
+// A block: 16 columns x 64 segments of B <= BM rows.  Every thread loads the
+// faces of its rows (up to 4 rows at once; longer segments load and form
+// their rows again for the pivots) and of the row before its segment, forms
+// its segment's continuant product, and the products are chained by a
+// shuffle scan over the 4 segments of a wave and a fold over the earlier
+// waves' totals (LDS).  Block 0 of an instance also sums the origin's faces.
+template <int BM>
 __global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   const PdScalars *sc = I.sc;
   if (sc->status != ST_ACTIVE || sc->stage != STAGE_START || !sc->refactor) return;
+  constexpr int NW = PD_RAD_THREADS / 64;
   const int m = I.m, n = I.n, cw = I.cw, B = I.brad;
   const int c = threadIdx.x % cw, seg = threadIdx.x / cw;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sub = lane >> 4;
   const int j = mp.y * cw + c;
   const bool act = j < n;
+  const int jj = act ? j : 0, jl = (jj == 0) ? n - 1 : jj - 1;
   const int k0 = seg * B;                          // first 0-based row of the segment
   const int cnt = act ? max(0, min(B, m - k0)) : 0;
   const double th = sc->theta, inv_dt = sc->inv_dt;
+  const GAS double *gpr = G(I.k64.gp_r), *gmr = G(I.k64.gm_r);
+  const GAS double *gpt = G(I.k64.gp_t), *gmt = G(I.k64.gm_t);
+  const GAS double *irw = G(I.inv_rw), *bnode = I.has_b ? G(I.b_node) : nullptr;
+  const double idth = G(I.inv_dth)[jj];
 
-  __shared__ double lm[4][PD_RAD_THREADS];
-  // super entry of the row before the segment
+  // the row of ring i (clamped to [1, m]); loads of CH rows are issued together
+  auto load_row = [&](int i) -> RadRow {
+    i = min(max(i, 1), m);
+    return rad_row_of(i, m, gpr[i * n + jj], gmr[i * n + jj], gpr[(i - 1) * n + jj],
+                      gmr[(i - 1) * n + jj], gpt[(i - 1) * n + jj], gmt[(i - 1) * n + jl],
+                      irw[i] * idth, bnode ? bnode[(i - 1) * n + jj] : 0.0, inv_dt, th);
+  };
+  constexpr int CH = BM < 4 ? BM : 4;     // rows per chunk
+  constexpr int NCH = BM / CH;            // chunks; with one, rows stay in registers
   double c_prev = 0.0;
-  if (cnt > 0 && k0 >= 1) c_prev = rad_row(I, k0, j, inv_dt, th).c;
-  // segment product of continuant matrices
+  {
+    const RadRow R0 = load_row(k0);       // the row before the segment
+    if (cnt > 0 && k0 >= 1) c_prev = R0.c;
+  }
+  // segment product of continuant matrices (later rows on the left)
   Mat2 Mp{1.0, 0.0, 0.0, 1.0};
   double cp = c_prev;
-  for (int k = 0; k < cnt; ++k) {
-    const RadRow R = rad_row(I, k0 + k + 1, j, inv_dt, th);
-    const Mat2 Mi{1.0, -R.a * cp, 1.0, 0.0};
-    Mp = norm2(mul2(Mi, Mp));
-    cp = R.c;
+  RadRow rw[CH];
+#pragma unroll 1
+  for (int h = 0; h < NCH; ++h) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) rw[q] = load_row(k0 + min(h * CH + q, max(cnt - 1, 0)) + 1);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      if (h * CH + q < cnt) {
+        const Mat2 Mi{1.0, -rw[q].a * cp, 1.0, 0.0};
+        Mp = norm2(mul2(Mi, Mp));
+        cp = rw[q].c;
+      }
+    }
   }
-  lm[0][threadIdx.x] = Mp.a;
-  lm[1][threadIdx.x] = Mp.b;
-  lm[2][threadIdx.x] = Mp.c;
-  lm[3][threadIdx.x] = Mp.d;
+  // inclusive scan over the wave's 4 segments, then the earlier waves' totals
+  Mat2 S = Mp;
+#pragma unroll
+  for (int d = 1; d < 4; d <<= 1) {
+    const Mat2 o{__shfl_up(S.a, 16 * d, 64), __shfl_up(S.b, 16 * d, 64), __shfl_up(S.c, 16 * d, 64),
+                 __shfl_up(S.d, 16 * d, 64)};
+    if (sub >= d) S = norm2(mul2(S, o));
+  }
+  Mat2 ex{__shfl_up(S.a, 16, 64), __shfl_up(S.b, 16, 64), __shfl_up(S.c, 16, 64), __shfl_up(S.d, 16, 64)};
+  if (sub == 0) ex = Mat2{1.0, 0.0, 0.0, 1.0};
+  __shared__ double tw[NW][4][16];
+  if (sub == 3) {
+    tw[wave][0][c] = S.a;
+    tw[wave][1][c] = S.b;
+    tw[wave][2][c] = S.c;
+    tw[wave][3][c] = S.d;
+  }
   __syncthreads();
-  // incoming (q_{k0}, q_{k0-1}) from the products of the earlier segments
-  double q1 = 1.0, q0 = 0.0;
-  for (int s2 = 0; s2 < seg; ++s2) {
-    const int t = s2 * cw + c;
-    const double n1 = lm[0][t] * q1 + lm[1][t] * q0;
-    const double n0 = lm[2][t] * q1 + lm[3][t] * q0;
-    const double sc2 = fmax(fabs(n1), fabs(n0));
-    q1 = n1 / sc2;
-    q0 = n0 / sc2;
-  }
+  Mat2 Pw{1.0, 0.0, 0.0, 1.0};
+  for (int w = 0; w < wave; ++w) Pw = norm2(mul2(Mat2{tw[w][0][c], tw[w][1][c], tw[w][2][c], tw[w][3][c]}, Pw));
+  const Mat2 E = mul2(ex, Pw);
+  // incoming (q_{k0}, q_{k0-1}) = E (1, 0); then the pivots of the own rows
+  const double q1 = E.a, q0 = E.c;
   double u_prev = (q0 != 0.0) ? q1 / q0 : 1.0;
   cp = c_prev;
   GAS double *dg = G(I.diag), *idg = G(I.inv_diag);
   GAS float *uinv = G(I.rf_uinv), *ff = G(I.rf_f), *gg = G(I.rf_g);
-  for (int k = 0; k < cnt; ++k) {
-    const int i = k0 + k + 1;
-    const RadRow R = rad_row(I, i, j, inv_dt, th);
-    const double u = 1.0 - R.a * cp / u_prev;
-    const double ui = 1.0 / u;
-    const int idx = (i - 1) * n + j;
-    dg[idx] = R.d;
-    idg[idx] = 1.0 / R.d;
-    uinv[idx] = (float)ui;
-    ff[idx] = (float)(R.a * ui);
-    gg[idx] = (float)(R.c * ui);
-    if (I.mixed) G(I.inv_diag32)[idx] = (float)(1.0 / R.d);
-    u_prev = u;
-    cp = R.c;
+#pragma unroll 1
+  for (int h = 0; h < NCH; ++h) {
+    if (NCH > 1) {
+#pragma unroll
+      for (int q = 0; q < CH; ++q) rw[q] = load_row(k0 + min(h * CH + q, max(cnt - 1, 0)) + 1);
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int k = h * CH + q;
+      if (k < cnt) {
+        const int idx = (k0 + k) * n + jj;
+        const double u = 1.0 - rw[q].a * cp / u_prev;
+        const double ui = 1.0 / u;
+        const double id = 1.0 / rw[q].d;
+        dg[idx] = rw[q].d;
+        idg[idx] = id;
+        uinv[idx] = (float)ui;
+        ff[idx] = (float)(rw[q].a * ui);
+        gg[idx] = (float)(rw[q].c * ui);
+        if (I.mixed) G(I.inv_diag32)[idx] = (float)id;
+        u_prev = u;
+        cp = rw[q].c;
+      }
+    }
   }
-  if (mp.y == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int jj = 0; jj < n; ++jj) s += G(I.k64.gp_r)[jj];
-    double v = I.inv_V0 * s;
-    if (I.has_b) v += G(I.b_node)[m * n];
-    const double d0 = inv_dt + th * v;
-    dg[m * n] = d0;
-    idg[m * n] = 1.0 / d0;
-    if (I.mixed) G(I.inv_diag32)[m * n] = (float)(1.0 / d0);
+  if (mp.y == 0) {
+    // origin: Σ_j gp_r(1/2, j), summed in a fixed order
+    double s0 = 0.0;
+    for (int q = threadIdx.x; q < n; q += PD_RAD_THREADS) s0 += gpr[q];
+    s0 = wave_sum(s0);
+    __shared__ double ws[NW];
+    if (lane == 0) ws[wave] = s0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += ws[w];
+      double v = I.inv_V0 * s;
+      if (I.has_b) v += G(I.b_node)[m * n];
+      const double d0 = inv_dt + th * v;
+      dg[m * n] = d0;
+      idg[m * n] = 1.0 / d0;
+      if (I.mixed) G(I.inv_diag32)[m * n] = (float)(1.0 / d0);
+    }
   }
 }
 
@@ -1862,7 +1905,8 @@ static inline int seg_len(int b) { return b <= 4 ? 4 : (b <= 8 ? 8 : (b <= 16 ? 
   }
 
 void launch_factor(const LaunchSet &L, hipStream_t s) {
-  if (L.nb_rad) go(KF_FACTOR, k_fact_rad, g1(L.nb_rad), dim3(PD_RAD_THREADS), s, L.insts, L.map_rad);
+  if (L.nb_rad)
+    PD_DISPATCH_BM(L.max_bfrad, (go(KF_FACTOR, k_fact_rad<BM>, g1(L.nb_rad), dim3(PD_RAD_THREADS), s, L.insts, L.map_rad)));
   if (L.nb_ang)
     PD_DISPATCH_BM(L.max_bang, (go(KF_FACTOR, k_fact_ang<BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang)));
 }

@@ -15,6 +15,7 @@ struct LaunchSet {
   int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0, nb_frad = 0, nb_fang = 0;
   int mixed_any = 0, fp64_any = 0;
   int max_bang = 1;                 // longest angular lane span of the batch
+  int max_bfrad = 1;                // longest radial segment of the factorisation
   // Radial sweeps, two classes by ring count: 512-thread blocks (32 segments
   // per column) for m <= 256, 1024-thread blocks (64 segments) above.  The
   // class depends on the instance alone, so its arithmetic does not depend
