@@ -929,11 +929,16 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (MODE == SM_UR && !I.mixed) return;
   }
   if (MODE == SM_UR) {
-    // refine once the inner solve has iterated and met its tolerance
+    // refine once the inner solve has iterated and met its tolerance: a
+    // reduction by tol_inner, or a residual of half the outer tolerance,
+    // whichever is reached first (no inner solve goes beyond what the
+    // outer test needs)
     if (sc->inner_iters == 0) return;
     double tot[2];
     consume<2>(I.part_x, I.nb_elem, tot);
-    const bool due = tot[1] <= sc->tol_inner * sc->tol_inner * sc->r0norm2 ||
+    const double goal = fmax(sc->tol_inner * sc->tol_inner * sc->r0norm2,
+                             0.25 * sc->tol * sc->tol * sc->bnorm2);
+    const bool due = tot[1] <= goal ||
                      sc->inner_iters >= sc->maxit_inner || sc->iters >= sc->maxit || !(tot[1] == tot[1]);
     if (!due) return;
     if (mp.y == 0 && threadIdx.x == 0) {
