@@ -329,11 +329,18 @@ int pd_batch_destroy(pd_batch *batch);
  * (the instances' stream and library-owned streams of default priority), so
  * that the parts' launches overlap; results do not depend on it.
  * cycles_per_graph: Krylov cycles per captured HIP graph (a part's
- * active-instance count is read back after each graph).  NULL restores
- * groups = 1, cycles_per_graph = 2.  PD_EINVAL outside [1, 8] / [1, 16].  */
+ * active-instance count is read back after each graph).
+ * fp32_stencil_rings: rings per wave of the stencil tiles of FP32 (mixed)
+ * instances, 4 or 8 (0 = 4); deeper tiles halve the waves and suit large
+ * batches.  FP64 instances always take 4.  It changes the summation order
+ * of an FP32 instance's partial sums, so results are the same alone and
+ * batched under one schedule, not across schedules.
+ * NULL restores groups = 1, cycles_per_graph = 2, fp32_stencil_rings = 4.
+ * PD_EINVAL outside [1, 8] / [1, 16] / {0, 4, 8}.                          */
 typedef struct {
   int32_t groups;
   int32_t cycles_per_graph;
+  int32_t fp32_stencil_rings;
 } pd_schedule;
 int pd_set_schedule(const pd_schedule *schedule);
 int pd_get_schedule(pd_schedule *schedule);

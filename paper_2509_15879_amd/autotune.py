@@ -1,8 +1,9 @@
 """Autotuner of the launch schedule of a batch.
 
 A batch's best schedule (how many stream groups it is split into, how many
-Krylov cycles one captured graph holds) depends on its instance sizes,
-precisions and convergence behaviour.  `tune` times the first levels of the
+Krylov cycles one captured graph holds) and stencil tile (rings per wave of
+its FP32 instances) depend on its instance sizes, precisions and
+convergence behaviour.  `tune` times the first levels of the
 batch's own solve under every candidate schedule, starting each time from
 the batch's current state (saved and restored, so tuning leaves no trace),
 then sets the fastest as the library's default and returns the table.
@@ -17,6 +18,7 @@ from typing import Dict, List, Sequence, Tuple
 from . import polardisk as pdk
 
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 2), (2, 2), (3, 2), (2, 4), (3, 4), (1, 4))
+FP32_RINGS: Tuple[int, ...] = (4, 8)
 
 _cache: Dict[tuple, dict] = {}
 
@@ -34,7 +36,9 @@ def tune(insts: Sequence["pdk.Instance"], tds: Sequence["pdk.TimeDesc"], levels:
          candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 2,
          sync=None, use_cache: bool = True) -> dict:
     """Chooses and sets the fastest schedule for advancing `insts` through
-    `tds`; returns {"best": (groups, cycles_per_graph), "ms": {...}}.
+    `tds`; returns {"best": (groups, cycles_per_graph, fp32_stencil_rings),
+    "ms": {...}}.  The stencil depth is only varied when the batch holds
+    FP32 (mixed) instances.
 
     sync: callable that waits for the device (e.g. torch.cuda.synchronize);
     the library's own calls already return after the work is done."""
@@ -45,9 +49,11 @@ def tune(insts: Sequence["pdk.Instance"], tds: Sequence["pdk.TimeDesc"], levels:
         return _cache[key]
     saved = [(i.solution(), i.time) for i in insts]
     short = [_first_levels(td, t, levels) for td, (_, t) in zip(tds, saved)]
-    ms: Dict[Tuple[int, int], float] = {}
+    any_fp32 = any(int(i.precision) == pdk.PD_MIXED for i in insts)
+    full = [(g, c, r) for g, c in candidates for r in (FP32_RINGS if any_fp32 else (4,))]
+    ms: Dict[Tuple[int, int, int], float] = {}
     try:
-        for cand in candidates:
+        for cand in full:
             pdk.set_schedule(*cand)
             best_t = float("inf")
             for rep in range(repeats + 1):                # first run warms the plan up
@@ -67,7 +73,8 @@ def tune(insts: Sequence["pdk.Instance"], tds: Sequence["pdk.TimeDesc"], levels:
             inst.set_solution(x, t)
     best = min(ms, key=ms.get)
     pdk.set_schedule(*best)
-    out = {"best": best, "ms": {f"{g}x{c}": round(v, 3) for (g, c), v in ms.items()}, "levels": levels}
+    out = {"best": best, "ms": {f"{g}x{c}x{r}": round(v, 3) for (g, c, r), v in ms.items()},
+           "levels": levels}
     _cache[key] = out
     return out
 

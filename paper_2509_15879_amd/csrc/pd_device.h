@@ -17,7 +17,7 @@
 #include <stdint.h>
 
 #define PD_MAXSRC 4
-#define PD_RB 4           // rings per stencil wave (one wave = 64 columns x PD_RB rings)
+#define PD_RB 4           // rings per stencil wave (one wave = 64 columns x rb rings; FP32 instances may take 2 PD_RB)
 #define PD_STEN_WAVES 4   // waves per stencil block, stacked over consecutive rings
 #define PD_ELEM_PER_BLOCK 2048
 #define PD_RAD_THREADS 1024
@@ -80,6 +80,7 @@ struct KSet {
 struct PdInst {
   int m, n, npad, nsrc;
   int K, mixed, has_b, zero_flux;
+  int rb, pad_rb;                    // rings per stencil wave (set by the launch plan)
   int ncg, nrg, nb_sten, nb_elem;    // stencil tiling and block counts
   int cw, nseg, brad, nb_rad;        // radial sweep: columns per block, segments, rows/segment
   int bang, nb_ang, nb_frad, nb_fang;

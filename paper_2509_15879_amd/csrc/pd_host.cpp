@@ -147,14 +147,23 @@ int build_mesh(const pd_mesh_desc *d, MeshH &M) {
 // ------------------------------------------------------------------ tiling
 
 struct Tiling {
-  int ncg, nrg, nb_sten, nb_elem, cw, nseg, brad, nb_rad, bang, nb_ang, nb_frad, nb_fang, npad;
+  int rb, ncg, nrg, nb_sten, nb_elem, cw, nseg, brad, nb_rad, bang, nb_ang, nb_frad, nb_fang, npad;
 };
 
+// Stencil blocks of an instance whose waves take `rb` rings each.
+int sten_blocks(int m, int n, int rb) {
+  const int nrg = (m + rb - 1) / rb;
+  return ((n + 63) / 64) * ((nrg + PD_STEN_WAVES - 1) / PD_STEN_WAVES);
+}
+
+// Launch geometry of an instance (the stencil's for PD_RB rings per wave,
+// the most blocks a schedule can ask for; see make_plan).
 Tiling make_tiling(int m, int n) {
   Tiling t;
+  t.rb = PD_RB;
   t.ncg = (n + 63) / 64;
-  t.nrg = (m + PD_RB - 1) / PD_RB;
-  t.nb_sten = t.ncg * ((t.nrg + PD_STEN_WAVES - 1) / PD_STEN_WAVES);
+  t.nrg = (m + t.rb - 1) / t.rb;
+  t.nb_sten = sten_blocks(m, n, t.rb);
   const int N = m * n + 1;
   t.nb_elem = (N + PD_ELEM_PER_BLOCK - 1) / PD_ELEM_PER_BLOCK;
   // radial sweep and factorisation: 16 columns (one 128-byte line of FP64)
@@ -483,8 +492,11 @@ void xcd_contiguous(std::vector<int2> &map) {
   map.swap(out);
 }
 
-int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
+// fp32_rings: stencil rings per wave of the plan's FP32 (mixed) instances
+// (PD_RB or 2 PD_RB); FP64 instances always take PD_RB.
+int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, int fp32_rings = PD_RB) {
   const int ninst = (int)insts.size();
+  auto rings = [&](const pd_instance *I) { return I->precision == PD_MIXED ? fp32_rings : PD_RB; };
   HIPCHK(hipMalloc(&P.n_active, sizeof(int)));
   P.bufs.push_back(P.n_active);
   HIPCHK(hipMemsetAsync(P.n_active, 0, sizeof(int), s));
@@ -494,6 +506,9 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
   std::vector<PdInst> hv(ninst);
   for (int q = 0; q < ninst; ++q) {
     hv[q] = insts[q]->H;
+    hv[q].rb = rings(insts[q]);
+    hv[q].nrg = (insts[q]->M.m + hv[q].rb - 1) / hv[q].rb;
+    hv[q].nb_sten = sten_blocks(insts[q]->M.m, insts[q]->M.n, hv[q].rb);
     hv[q].n_active = P.n_active;
     hv[q].lvl_out = P.lvl + 2 * q;
     P.L.mixed_any |= insts[q]->precision == PD_MIXED;
@@ -521,7 +536,9 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P) {
     return PD_OK;
   };
   int rc;
-  if ((rc = upload(&P.L.map_sten, &P.L.nb_sten, [](pd_instance *I) { return I->T.nb_sten; }, true))) return rc;
+  if ((rc = upload(&P.L.map_sten, &P.L.nb_sten,
+                   [&](pd_instance *I) { return sten_blocks(I->M.m, I->M.n, rings(I)); }, true)))
+    return rc;
   if ((rc = upload(&P.L.map_elem, &P.L.nb_elem, [](pd_instance *I) { return I->T.nb_elem; }))) return rc;
   if ((rc = upload(&P.L.map_rad, &P.L.nb_rad, [](pd_instance *I) { return I->T.nb_rad; }))) return rc;
   for (int c = 0; c < 2; ++c)
@@ -583,14 +600,16 @@ hipStream_t helper_stream(int device, int k) {
 struct Schedule {
   int groups = 1;
   int cycles_per_graph = 2;
+  int fp32_rings = PD_RB;     // stencil rings per wave of FP32 instances
 };
 
-std::atomic<int> g_sched_groups{1}, g_sched_cpg{2};
+std::atomic<int> g_sched_groups{1}, g_sched_cpg{2}, g_sched_rings{PD_RB};
 
 Schedule default_schedule() {
   Schedule sc;
   sc.groups = g_sched_groups.load();
   sc.cycles_per_graph = g_sched_cpg.load();
+  sc.fp32_rings = g_sched_rings.load();
   return sc;
 }
 
@@ -624,6 +643,7 @@ struct Engine {
   int max_cycles = 0;
   int ninst = 0;
   int cpg = 2;
+  int rings = PD_RB;
 
   void release() {
     for (auto &g : G) {
@@ -646,6 +666,7 @@ struct Engine {
     ninst = (int)insts.size();
     max_cycles = cycles_cap;
     cpg = std::max(1, sch.cycles_per_graph);
+    rings = sch.fp32_rings;
     const int ng = std::max(1, std::min(sch.groups, ninst));
     int device = 0;
     HIPCHK(hipGetDevice(&device));
@@ -676,7 +697,7 @@ struct Engine {
       std::vector<pd_instance *> part;
       for (int q : g.members) part.push_back(insts[q]);
       g.P.reset(new Plan);
-      int rc = make_plan(part, g.s, *g.P);
+      int rc = make_plan(part, g.s, *g.P, rings);
       if (rc) return rc;
       // every member still has levels to take
       HIPCHK(hipMemsetD32Async((hipDeviceptr_t)g.P->n_active, (int)part.size(), 1, g.s));
@@ -1020,6 +1041,7 @@ int upload_instance(pd_instance *I, const HostImage &X) {
   H.mixed = I->precision == PD_MIXED;
   H.has_b = X.has_b;
   H.zero_flux = I->bc;
+  H.rb = I->T.rb;
   H.ncg = I->T.ncg;
   H.nrg = I->T.nrg;
   H.nb_sten = I->T.nb_sten;
@@ -1078,13 +1100,17 @@ int pd_set_schedule(const pd_schedule *sc) {
   if (!sc) {
     g_sched_groups = 1;
     g_sched_cpg = 2;
+    g_sched_rings = PD_RB;
     return PD_OK;
   }
   if (sc->groups < 1 || sc->groups > 8) return fail(PD_EINVAL, "groups must be in [1, 8]");
   if (sc->cycles_per_graph < 1 || sc->cycles_per_graph > 16)
     return fail(PD_EINVAL, "cycles_per_graph must be in [1, 16]");
+  if (sc->fp32_stencil_rings != 0 && sc->fp32_stencil_rings != PD_RB && sc->fp32_stencil_rings != 2 * PD_RB)
+    return fail(PD_EINVAL, "fp32_stencil_rings must be 0, %d or %d", PD_RB, 2 * PD_RB);
   g_sched_groups = sc->groups;
   g_sched_cpg = sc->cycles_per_graph;
+  g_sched_rings = sc->fp32_stencil_rings ? sc->fp32_stencil_rings : PD_RB;
   return PD_OK;
 }
 
@@ -1092,6 +1118,7 @@ int pd_get_schedule(pd_schedule *sc) {
   if (!sc) return fail(PD_EINVAL, "NULL argument");
   sc->groups = g_sched_groups.load();
   sc->cycles_per_graph = g_sched_cpg.load();
+  sc->fp32_stencil_rings = g_sched_rings.load();
   return PD_OK;
 }
 

@@ -673,7 +673,8 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
 
 // ------------------------------------------------------------ stencil march
 //
-// One wave owns 64 consecutive θ-columns and PD_RB consecutive rings and
+// One wave owns 64 consecutive θ-columns and rb consecutive rings (PD_RB, or
+// twice that for FP32 instances when the launch schedule asks for it) and
 // marches outward in r, keeping the radial neighbours and the shared radial
 // faces in registers and fetching the next ring (stencil operands and the
 // epilogue's own operands) while it computes the current one.  A block
@@ -698,7 +699,7 @@ struct TileGeo {
   bool act, need_l, need_r;
 };
 
-__device__ __forceinline__ TileGeo tile_geo(int m, int n, int cg, int rg) {
+__device__ __forceinline__ TileGeo tile_geo(int m, int n, int cg, int rg, int rb) {
   TileGeo g;
   g.m = m;
   g.n = n;
@@ -711,8 +712,8 @@ __device__ __forceinline__ TileGeo tile_geo(int m, int n, int cg, int rg) {
   g.jr0 = (jlast == n - 1) ? 0 : jlast + 1;
   g.need_l = g.lane == 0;
   g.need_r = g.j == jlast;
-  g.i0 = rg * PD_RB + 1;
-  g.i1 = min(g.i0 + PD_RB - 1, m);
+  g.i0 = rg * rb + 1;
+  g.i1 = min(g.i0 + rb - 1, m);
   return g;
 }
 
@@ -953,7 +954,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
   const int cg = mp.y % I.ncg, rg = wave_on ? rg0 : 0;
   const int m = I.m, n = I.n;
   const KSet<TK> &KS = kset<TK>(I);
-  const TileGeo geo = tile_geo(m, n, cg, rg);
+  const TileGeo geo = tile_geo(m, n, cg, rg, I.rb);
   const GAS double *inv_rw = G(I.inv_rw), *inv_dth = G(I.inv_dth);
   const GAS double *bnode = I.has_b ? G(I.b_node) : nullptr;
 
@@ -1671,7 +1672,7 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   const int orig = I.m * I.n;
   const bool b0 = mp.y == 0 && threadIdx.x == 0;
   T *x = iterate_ptr<T>(I, sc);
-  const int base = mp.y * PD_ELEM_PER_BLOCK;
+  const int base = mp.y * 256 * E;
   // the vectors first, then the partial sums of the t-stencil
   ElemRegs<E> R;
   elem_load<T, E>(orig + 1, base, G((const T *)KS.ph), G((const T *)KS.sh), G((const T *)KS.s),
