@@ -45,9 +45,9 @@ KERNEL_NAMES = {
 # WRITE_SIZE counters, calibrated on a copy of known size), valid for the
 # sources with this SHA-1 only (kernel_source_sha1); any other source
 # reports traffic null.
-TRAFFIC_SOURCE_SHA1 = "328e2a7ae00b946690e512fbbb2ce99c39ce85c7"
-TRAFFIC_B_PER_CELL = {"rad_p": 65.97, "ang_p": 48.44, "sten_v": 72.99, "rad_s": 56.39,
-                      "ang_s": 48.44, "sten_t": 73.53, "update": 64.53}
+TRAFFIC_SOURCE_SHA1 = "b4b38d071fef35460963e0f2521897aa632467eb"
+TRAFFIC_B_PER_CELL = {"rad_p": 53.54, "ang_p": 32.44, "sten_v": 64.94, "rad_s": 44.21,
+                      "ang_s": 32.43, "sten_t": 64.41, "update": 64.54}
 
 
 def kernel_source_sha1():

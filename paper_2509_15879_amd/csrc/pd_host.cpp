@@ -540,10 +540,15 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
                    [&](pd_instance *I) { return sten_blocks(I->M.m, I->M.n, rings(I)); }, true)))
     return rc;
   if ((rc = upload(&P.L.map_elem, &P.L.nb_elem, [](pd_instance *I) { return I->T.nb_elem; }))) return rc;
+  // radial sweep blocks: neighbouring column blocks share the 128-byte
+  // lines of FP32 rows (16 columns x 4 bytes), so they go to the same XCD
+  // (L2).  The factorisation keeps the plain order: only the instances
+  // starting a level take part in it, and a contiguous run per XCD would
+  // crowd them onto a few XCDs.
   if ((rc = upload(&P.L.map_rad, &P.L.nb_rad, [](pd_instance *I) { return I->T.nb_rad; }))) return rc;
   for (int c = 0; c < 2; ++c)
     if ((rc = upload(&P.L.map_rs[c], &P.L.nb_rs[c],
-                     [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? I->T.nb_rad : 0; })))
+                     [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? I->T.nb_rad : 0; }, true)))
       return rc;
   if ((rc = upload(&P.L.map_ang, &P.L.nb_ang, [](pd_instance *I) { return I->T.nb_ang; }))) return rc;
   HIPCHK(hipHostMalloc((void **)&P.h_active, 2 * sizeof(int)));

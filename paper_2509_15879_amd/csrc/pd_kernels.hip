@@ -351,6 +351,20 @@ struct RadRow {
   double d, a, c;   // diagonal of A, scaled sub and super entries
 };
 
+// Diagonal of L at a ring node from the coefficients of its four faces
+// that multiply it (outer radial gp, inner radial gm, upper angular gp,
+// lower angular gm), and the diagonal of A = I/dt + θL.  Written with
+// explicit fused multiply-adds, so that the factorisation (which stores
+// 1/diag) and the stencils (which form it again from the faces they hold)
+// get the same bits.
+__device__ __forceinline__ double l_diag(double ivV, double gpo, double gmi, double gpt, double gmtl,
+                                         double bP) {
+  return __builtin_fma(ivV, ((gpo + gmi) + gpt) + gmtl, bP);
+}
+__device__ __forceinline__ double diag_of(double inv_dt, double th, double ld) {
+  return __builtin_fma(th, ld, inv_dt);
+}
+
 struct Mat2 {
   double a, b, c, d;   // [[a, b], [c, d]]
 };
@@ -371,7 +385,7 @@ __device__ __forceinline__ RadRow rad_row_of(int i, int m, double gpo, double gm
                                              double gmi, double gpt, double gmtl, double ivV,
                                              double bP, double inv_dt, double th) {
   RadRow R;
-  R.d = inv_dt + th * (ivV * (gpo + gmi + gpt + gmtl) + bP);
+  R.d = diag_of(inv_dt, th, l_diag(ivV, gpo, gmi, gpt, gmtl, bP));
   const double s = th * ivV / R.d;
   R.a = (i >= 2) ? -s * gpi : 0.0;
   R.c = (i < m) ? -s * gmo : 0.0;
@@ -718,7 +732,8 @@ __device__ __forceinline__ TileGeo tile_geo(int m, int n, int cg, int rg, int rb
 }
 
 // pre(idx) loads what the epilogue needs at node idx (one ring ahead);
-// epi(i, j, idx, x, Lx, pre) finishes node idx.
+// epi(i, j, idx, x, Lx, ld, pre) finishes node idx (ld: the diagonal of L
+// there, l_diag).
 template <typename TF, typename TX, int NV, class Pre, class Epi>
 __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__restrict__ gp_r,
                                           const GAS TF *__restrict__ gm_r,
@@ -796,7 +811,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
       Lx[v] = ivV * fs + bP * xc[v];
       if (i == 1 && g.act) S0[v] += gpi * xb[v] - gmi * xc[v];
     }
-    if (g.act) epi(i, jc, row + jc, xc, Lx, pc);
+    if (g.act) epi(i, jc, row + jc, xc, Lx, l_diag(ivV, gpo, gmi, gpt, gmtl, bP), pc);
     pc = pn;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -965,7 +980,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (wave_on)
       sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(ax), G(ax), G(ax), G(ax), inv_rw,
                            inv_dth, bnode, S0, no_pre,
-                           [&](int, int, int idx, const double *xc, const double *Lx, Nil) {
+                           [&](int, int, int idx, const double *xc, const double *Lx, double, Nil) {
                              y[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
                            });
     produce<1>(S0, I.part_a, I.nb_sten, mp.y);
@@ -990,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     const int nsrc = I.nsrc, npad = I.npad;
     double acc[PD_NBEGIN] = {};   // ||D^-1 b||², selected and other ||D^-1 r||², S0 per level
     double S0[PD_NHIST] = {};
-    const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb), *idg = G(I.inv_diag);
+    const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb);
     GAS double *bv = G(I.bvec), *xo = G(x0);
     GAS double *rout = G(I.rout);
     GAS double *r64 = G(I.k64.r), *rh64 = G(I.k64.rh);
@@ -1000,7 +1015,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       sten_tile<double, double, PD_NHIST>(
           geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk0), G(xk1), G(xk2),
           G(xk3), inv_rw, inv_dth, bnode, S0, no_pre,
-          [&](int i, int j, int idx, const double *xc, const double *Lx, Nil) {
+          [&](int i, int j, int idx, const double *xc, const double *Lx, double ld, Nil) {
             double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
             for (int q = 0; q < nsrc; ++q) b += cq[q] * gsrc[q * npad + idx];
             if (i == m) {
@@ -1017,7 +1032,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
               Lo += w1[a] * Lx[a];
             }
             const double r = b - (inv_dt * xg + th * Lg);
-            const double id = idg[idx];
+            const double id = 1.0 / diag_of(inv_dt, th, ld);
             const double rs = r * id, bs = b * id;
             const double ro = (b - (inv_dt * xo2 + th * Lo)) * id;
             bv[idx] = b;
@@ -1050,9 +1065,13 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (wave_on)
       sten_tile<TK, TK, 1>(geo, G(KS.gp_r), G(KS.gm_r), G(KS.gp_t), G(KS.gm_t), G(xin), G(xin), G(xin), G(xin),
                            inv_rw, inv_dth, bnode, S0,
-                           [&](int idx) { return Pre2{(double)idg[idx], (double)ot[idx]}; },
-                           [&](int, int, int idx, const double *xc, const double *Lx, Pre2 q) {
-                             const double y = (inv_dt * xc[0] + th * Lx[0]) * q.a;
+                           [&](int idx) {
+                             // FP64 forms 1/diag from its faces; FP32 loads its rounded copy
+                             return Pre2{sizeof(TK) == 8 ? 0.0 : (double)idg[idx], (double)ot[idx]};
+                           },
+                           [&](int, int, int idx, const double *xc, const double *Lx, double ld, Pre2 q) {
+                             const double ia = sizeof(TK) == 8 ? 1.0 / diag_of(inv_dt, th, ld) : q.a;
+                             const double y = (inv_dt * xc[0] + th * Lx[0]) * ia;
                              const TK ys = (TK)y;
                              yo[idx] = ys;
                              const double yd = (double)ys;
@@ -1071,7 +1090,6 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     const double inv_dt = sc->inv_dt, th = sc->theta;
     double *x = I.sol[sol_slot(sc->rot, -1)];
     GAS double *xg = G(x), *rout = G(I.rout);
-    const GAS double *idg = G(I.inv_diag);
     GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh);
     double acc[2] = {0.0, 0.0};
     double S0[1] = {0.0};
@@ -1080,12 +1098,12 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                                   G((const float *)I.k32.d), G((const float *)I.k32.d),
                                   G((const float *)I.k32.d), G((const float *)I.k32.d), inv_rw,
                                   inv_dth, bnode, S0,
-                                  [&](int idx) { return Pre3{rout[idx], idg[idx], xg[idx]}; },
-                                  [&](int, int, int idx, const double *xc, const double *Lx, Pre3 q) {
+                                  [&](int idx) { return Pre2{rout[idx], xg[idx]}; },
+                                  [&](int, int, int idx, const double *xc, const double *Lx, double ld, Pre2 q) {
                                     const double r = q.a - (inv_dt * xc[0] + th * Lx[0]);
-                                    const double rs = r * q.b;
+                                    const double rs = r * (1.0 / diag_of(inv_dt, th, ld));
                                     rout[idx] = r;
-                                    xg[idx] = q.c + xc[0];
+                                    xg[idx] = q.b + xc[0];
                                     r32[idx] = (float)rs;
                                     rh32[idx] = (float)rs;
                                     acc[0] += rs * rs;
