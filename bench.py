@@ -63,8 +63,10 @@ def kernel_source_sha1():
 
 def bytes_per_cell(family, w):
     return {
-        "sten_v": 8 * w,            # p̂, 4 face coefficients, 1/diag, r̂ in; v out
-        "sten_t": 8 * w,            # ŝ, 4 faces, 1/diag, s in; t out
+        # p̂ or ŝ, 4 face coefficients, r̂ or s in; v or t out; FP32 also reads
+        # its 1/diag copy (FP64 forms 1/diag from the faces)
+        "sten_v": 7 * w + (4 if w == 4 else 0),
+        "sten_t": 7 * w + (4 if w == 4 else 0),
         "rad_p": 5 * w + 12,        # r, p, v in; p, w out; f, g, pivot (FP32) in
         "rad_s": 4 * w + 12,        # r, v in; s, w out; f, g, pivot (FP32) in
         "ang_p": 2 * w + 16,        # w in; p̂ out; f, g, z, pivot (FP32) in
