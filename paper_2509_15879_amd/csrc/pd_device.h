@@ -24,6 +24,7 @@
 #define PD_RAD_BMAX 32    // max rows per radial segment held in registers
 #define PD_ANG_BMAX 32    // max angular nodes per lane held in registers
 #define PD_NSLOT 4
+#define PD_REFACTOR_DT 0.25   // relative change of Δt that triggers a new factorisation
 #define PD_NHIST 4        // earlier levels kept for the initial guess: n^k .. n^{k-3}
 #define PD_NSOL 5         // rotating solution slots: the PD_NHIST levels and the iterate
 
@@ -85,6 +86,7 @@ struct PdInst {
   int cw, nseg, brad, nb_rad;        // radial sweep: columns per block, segments, rows/segment
   int bang, nb_ang, nb_frad, nb_fang;
   double inv_V0;
+  double l0;                // diagonal of L at the origin: inv_V0 Σ_j gp_r(1/2, j) + b_0 (fixed order)
   const double *inv_rw;     // [m+2] 1/(r_i (h_i+h_{i+1})/2), index i
   const double *inv_dth;    // [n]   1/Δθ_j
   const double *r_nodes;    // [m+2] r_0..r_{m+1}
@@ -98,9 +100,9 @@ struct PdInst {
   double *sol[PD_NSOL];     // rotating (sol_slot): n^{k-2}, n^{k-1}, n^k, iterate
   double *bvec;             // right-hand side (FP64)
   double *rout;             // FP64 outer residual (mixed)
-  double *diag;             // [npad] diagonal of I/dt + θL
-  double *inv_diag;         // [npad] its reciprocal (k64.inv_d)
-  float *inv_diag32;        // [npad] FP32 copy (k32.inv_d, mixed precision)
+  double *diag;             // [npad] diagonal of I/dt + θL at the last factorisation
+  double *inv_diag;         // [npad] its reciprocal (k64.inv_d; the FP64 kernels form 1/diag themselves)
+  float *inv_diag32;        // [npad] FP32 1/diag of the level under way (k32.inv_d, mixed precision)
   // Factors of the two sweeps of the preconditioner, computed in FP64 and
   // stored in FP32 in both precisions (the sweeps themselves run in FP64 in
   // the FP64 solve: the rounded factors define a fixed, slightly different

@@ -1015,6 +1015,13 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
     to_internal(g.data() + (size_t)q * N, pb->layout, m, n, np, X.g_int.data() + (size_t)q * np);
   X.u0_int.resize(np);
   to_internal(u0.data(), pb->layout, m, n, np, X.u0_int.data());
+  {
+    // diagonal of L at the origin, with the ring-1 faces summed in order
+    double s0 = 0.0;
+    for (int j = 0; j < n; ++j) s0 += X.gpr[j];
+    const double b0 = X.has_b ? X.b_int[m * n] : 0.0;
+    I->H.l0 = std::fma(I->H.inv_V0, s0, b0);
+  }
   out = std::move(I);
   img_out = std::move(img);
   return PD_OK;

@@ -241,7 +241,11 @@ __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   sc->t1 = t1;
   sc->dt = dt;
   sc->inv_dt = 1.0 / dt;
-  sc->refactor = (dt != sc->fact_dt || th != sc->fact_theta) ? 1 : 0;
+  // the preconditioner is refactored when θ changed or Δt moved by more than
+  // PD_REFACTOR_DT (relative) since its factorisation: it only has to stay
+  // close to the system, not equal it (the operator, the diagonal scaling
+  // and the right-hand side always follow the current Δt)
+  sc->refactor = (th != sc->fact_theta || !(fabs(dt - sc->fact_dt) <= PD_REFACTOR_DT * sc->fact_dt)) ? 1 : 0;
   const int ne = min(sc->have_prev, PD_NHIST - 1);
   double w[2][PD_NHIST];
   guess_weights(I.t_table, k, ne, th, w);
@@ -363,6 +367,10 @@ __device__ __forceinline__ double l_diag(double ivV, double gpo, double gmi, dou
 }
 __device__ __forceinline__ double diag_of(double inv_dt, double th, double ld) {
   return __builtin_fma(th, ld, inv_dt);
+}
+// 1/diag of the origin row for the level under way.
+__device__ __forceinline__ double origin_invd(const PdInst &I, double inv_dt, double th) {
+  return 1.0 / diag_of(inv_dt, th, I.l0);
 }
 
 struct Mat2 {
@@ -496,30 +504,15 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts
         uinv[idx] = (float)ui;
         ff[idx] = (float)(rw[q].a * ui);
         gg[idx] = (float)(rw[q].c * ui);
-        if (I.mixed) G(I.inv_diag32)[idx] = (float)id;
         u_prev = u;
         cp = rw[q].c;
       }
     }
   }
-  if (mp.y == 0) {
-    // origin: Σ_j gp_r(1/2, j), summed in a fixed order
-    double s0 = 0.0;
-    for (int q = threadIdx.x; q < n; q += PD_RAD_THREADS) s0 += gpr[q];
-    s0 = wave_sum(s0);
-    __shared__ double ws[NW];
-    if (lane == 0) ws[wave] = s0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int w = 0; w < NW; ++w) s += ws[w];
-      double v = I.inv_V0 * s;
-      if (I.has_b) v += G(I.b_node)[m * n];
-      const double d0 = inv_dt + th * v;
-      dg[m * n] = d0;
-      idg[m * n] = 1.0 / d0;
-      if (I.mixed) G(I.inv_diag32)[m * n] = (float)(1.0 / d0);
-    }
+  if (mp.y == 0 && threadIdx.x == 0) {
+    const double d0 = diag_of(inv_dt, th, I.l0);
+    dg[m * n] = d0;
+    idg[m * n] = 1.0 / d0;
   }
 }
 
@@ -856,7 +849,7 @@ __device__ __forceinline__ OriginBegin origin_begin(const PdInst &I, const PdSca
   }
   double b = inv_dt * xa[0] - (1.0 - th) * La[0];
   for (int q = 0; q < I.nsrc; ++q) b += sc->cq[q] * I.g[q * I.npad + orig];
-  const double id = I.inv_diag[orig];
+  const double id = origin_invd(I, inv_dt, th);
   OriginBegin O;
   O.b = b;
   double rs[2], xg[2], r[2];
@@ -888,6 +881,7 @@ __device__ __forceinline__ void origin_begin_store(const PdInst &I, const PdScal
   if (I.mixed) {
     I.k32.r[orig] = (float)O.rs;
     I.k32.rh[orig] = (float)O.rs;
+    I.inv_diag32[orig] = (float)origin_invd(I, sc->inv_dt, sc->theta);
   } else {
     I.k64.r[orig] = O.rs;
     I.k64.rh[orig] = O.rs;
@@ -909,7 +903,7 @@ __device__ __forceinline__ OriginRefine origin_refine(const PdInst &I, const PdS
   O.d0 = (double)I.k32.d[orig];
   const double rprev = sc->rout0[(sc->outer + 1) & 1];
   O.r = rprev - (inv_dt * O.d0 + th * (I.inv_V0 * tot[1] + bo * O.d0));
-  O.rs = O.r * I.inv_diag[orig];
+  O.rs = O.r * origin_invd(I, inv_dt, th);
   O.rr = tot[0] + O.rs * O.rs;
   return O;
 }
@@ -1009,7 +1003,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     GAS double *bv = G(I.bvec), *xo = G(x0);
     GAS double *rout = G(I.rout);
     GAS double *r64 = G(I.k64.r), *rh64 = G(I.k64.rh);
-    GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh);
+    GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh), *id32 = G(I.inv_diag32);
     const bool mixed = I.mixed;
     if (wave_on)
       sten_tile<double, double, PD_NHIST>(
@@ -1041,6 +1035,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
               rout[idx] = r;
               r32[idx] = (float)rs;
               rh32[idx] = (float)rs;
+              id32[idx] = (float)id;
             } else {
               r64[idx] = rs;
               rh64[idx] = rs;
@@ -1433,7 +1428,8 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
     double tot[2];
     consume<2>(I.part_v, I.nb_sten, tot);
     const double ph0 = (double)KS.ph[orig];
-    const T v0 = (T)origin_apply<T>(I, sc->inv_dt, sc->theta, ph0, tot[1], (double)KS.inv_d[orig]);
+    const double invd0 = sizeof(T) == 8 ? origin_invd(I, sc->inv_dt, sc->theta) : (double)KS.inv_d[orig];
+    const T v0 = (T)origin_apply<T>(I, sc->inv_dt, sc->theta, ph0, tot[1], invd0);
     const double dot = tot[0] + (double)KS.rh[orig] * (double)v0;
     const double rho = sc->rho_next;
     int st = ST_ACTIVE;
@@ -1698,8 +1694,8 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   // ω = (t·s)/(t·t), closing the t-stencil with its origin row
   double tot[3];
   consume<3>(I.part_t, I.nb_sten, tot);
-  const T t0 = (T)origin_apply<T>(I, sc->inv_dt, sc->theta, (double)KS.sh[orig], tot[2],
-                                  (double)KS.inv_d[orig]);
+  const double invd0 = sizeof(T) == 8 ? origin_invd(I, sc->inv_dt, sc->theta) : (double)KS.inv_d[orig];
+  const T t0 = (T)origin_apply<T>(I, sc->inv_dt, sc->theta, (double)KS.sh[orig], tot[2], invd0);
   const double s0 = (double)KS.s[orig];
   const double ts = tot[0] + s0 * (double)t0, tt = tot[1] + (double)t0 * (double)t0;
   double om = 0.0;
