@@ -82,7 +82,7 @@ typedef enum { PD_FP64 = 0, PD_MIXED = 1 } pd_precision;
 
 enum { PD_MESH_UNIFORM = 0, PD_MESH_SINE = 1, PD_MESH_EXPLICIT = 2, PD_MESH_POLY = 3 };
 enum { PD_LAYOUT_RING = 0, PD_LAYOUT_PAPER = 1 };
-enum { PD_TIME_UNIFORM = 0, PD_TIME_SINE = 1, PD_TIME_TABLE = 2 };
+enum { PD_TIME_UNIFORM = 0, PD_TIME_SINE = 1, PD_TIME_TABLE = 2, PD_TIME_ADAPTIVE = 3 };
 
 /* Mesh (§2.1 "region divided", §3.1 stretching equations).
  *   r_kind: PD_MESH_UNIFORM r_i = i h; PD_MESH_SINE r_i = sin((i h)^p π/2)
@@ -144,7 +144,20 @@ typedef struct {
  *   tol:   per-step stopping tolerance on the diagonally scaled residual
  *          ||D^{-1}(b - A x)||_2 / ||D^{-1} b||_2 (FP64), D = diag(A); every
  *          row weighs alike, whatever the local mesh spacing.
- *   max_iters: cap on BiCGSTAB iterations per step (0: library default).  */
+ *   max_iters: cap on BiCGSTAB iterations per step (0: library default).
+ * PD_TIME_ADAPTIVE (the paper fixes its levels in advance; this is an
+ * a-posteriori step control of the same scheme): advances from the current
+ * time t_s to t_s + T choosing each Δt on the GPU from a local error
+ * estimate of the step just taken, with f(t, x) = -L x + S(t) + c N(t) the
+ * semi-discrete right-hand side: (θ - 1/2) Δt (f_{k+1} - f_k) for θ ≠ 1/2,
+ * the trapezoidal rule against the variable-step Adams-Bashforth-2
+ * predictor for θ = 1/2.  e = ||d||_2 / ||x_{k+1}||_2 (relative); a step with
+ * e > 2 tol_time (and Δt > dt_min) is retaken smaller, an accepted one sets
+ * the next Δt = Δt clamp(0.9 (tol_time/e)^{1/(q+1)}, 1/2, 2) within
+ * [dt_min, dt_max] (q = 1, or 2 for θ = 1/2); the first step is dt0 and the
+ * second tries dt0 again; steps land exactly on t_s + T.  K caps the number
+ * of accepted steps (PD_ENOCONV if T is not reached); per-step statistics
+ * past the steps taken are zero.  Not accepted by pd_batch_submit.      */
 typedef struct {
   int32_t t_kind;
   int32_t K;
@@ -153,15 +166,20 @@ typedef struct {
   double theta;
   double tol;
   int32_t max_iters;
+  double dt0, dt_min, dt_max;   /* PD_TIME_ADAPTIVE only                  */
+  double tol_time;              /* PD_TIME_ADAPTIVE: local error tolerance */
 } pd_time_desc;
 
 typedef struct {
   int32_t iters;        /* Krylov iterations (inner, for PD_MIXED)         */
   int32_t refinements;  /* FP64 outer refinements (PD_MIXED), else 0       */
   int32_t status;       /* PD_OK, PD_EBREAKDOWN or PD_ENOCONV              */
-  int32_t reserved;
+  int32_t reserved;     /* Krylov restarts                                 */
   double rel_resid;     /* final scaled relative residual (see tol)        */
-  double dt, t;         /* step size and the time reached                  */
+  double dt, t;         /* step size and the time reached (0: no step)     */
+  double err_time;      /* adaptive stepping: the step's local error estimate e */
+  int32_t rejected;     /* adaptive stepping: attempts rejected before it  */
+  int32_t pad;
 } pd_step_stats;
 
 /* Mesh nodes and face sample points of a mesh description: r_nodes r_0..r_{m+1}

@@ -25,6 +25,7 @@
 #define PD_ANG_BMAX 32    // max angular nodes per lane held in registers
 #define PD_NSLOT 4
 #define PD_REFACTOR_DT 0.25   // relative change of Δt that triggers a new factorisation
+#define PD_LSTAT 10           // statistics per level (see end_level)
 #define PD_NHIST 4        // earlier levels kept for the initial guess: n^k .. n^{k-3}
 #define PD_NSOL 5         // rotating solution slots: the PD_NHIST levels and the iterate
 
@@ -68,6 +69,12 @@ struct PdScalars {
   double rel_resid;
   double t_now;
   double rout0[2];          // FP64 outer residual at the origin (mixed), by refinement parity
+  // adaptive time stepping: the next level's Δt is chosen from the local
+  // error estimate of the step just taken (time levels written on the fly)
+  int adaptive, need_f0;    // adaptive mode; f(t_0, x_0) not formed yet
+  int nrej, pad5;           // rejected attempts of the level under way
+  double t_end, dt_min, dt_max, tol_time;
+  double err_last;          // relative local error estimate of the last step
 };
 
 template <typename T>
@@ -96,7 +103,7 @@ struct PdInst {
   const double *nb;         // [nsrc*n]
   const double *lam;        // [nsrc]
   const int *tpow;          // [nsrc]
-  const double *t_table;    // [K+1]
+  double *t_table;          // [K+1] (adaptive stepping writes its levels as it goes)
   double *sol[PD_NSOL];     // rotating (sol_slot): n^{k-2}, n^{k-1}, n^k, iterate
   double *bvec;             // right-hand side (FP64)
   double *rout;             // FP64 outer residual (mixed)
@@ -119,5 +126,8 @@ struct PdInst {
   PdScalars *sc;
   int *n_active;            // shared counter of the batch (device)
   int *lvl_out;             // (levels done, status) written at each level end
-  double *level_stats;      // [K * 8]: iters, outer, status, rel_resid, dt, t1, restarts, 0
+  double *level_stats;      // [K * PD_LSTAT]: iters, outer, status, rel_resid, dt, t1, restarts,
+                            // error estimate, rejected attempts, 0
+  double *fdot[3];          // adaptive stepping: f(t_k, x_k) by level modulo 3 (FP64)
+  double *part_e;           // [3 * nb_sten]: the level-end pass's ||d||², ||x||², S0
 };

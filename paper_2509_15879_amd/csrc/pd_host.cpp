@@ -197,7 +197,7 @@ struct pd_instance {
   PdInst H{};            // host image of the device descriptor
   PdScalars *sc = nullptr;   // device scalars
   double *t_table = nullptr; // device time table (capacity kcap+1)
-  double *stats = nullptr;   // device level stats (8 * kcap)
+  double *stats = nullptr;   // device level stats (PD_LSTAT * kcap)
   int kcap = 0;
   int rot = 0;               // host mirror of the buffer rotation
   double t = 0.0;            // current time
@@ -239,6 +239,7 @@ void carve(pd_instance *I, Carver &c) {
   H.lam = c.take<double>(PD_MAXSRC);
   H.tpow = c.take<int>(PD_MAXSRC);
   for (int k = 0; k < PD_NSOL; ++k) H.sol[k] = c.take<double>(np);
+  for (int k = 0; k < 3; ++k) H.fdot[k] = c.take<double>(np);
   H.bvec = c.take<double>(np);
   H.diag = c.take<double>(np);
   H.inv_diag = c.take<double>(np);
@@ -292,6 +293,7 @@ void carve(pd_instance *I, Carver &c) {
   H.part_t = c.take<double>(3 * (size_t)nbs);
   H.part_ur = c.take<double>(2 * (size_t)nbs);
   H.part_a = c.take<double>(1 * (size_t)nbs);
+  H.part_e = c.take<double>(3 * (size_t)nbs);
   H.part_x = c.take<double>(2 * (size_t)I->T.nb_elem);
   H.partials = H.part_b;
   H.counters = c.take<unsigned>(CNT_N);
@@ -354,17 +356,37 @@ int ensure_time_capacity(pd_instance *I, int K) {
   I->stats = nullptr;
   const int cap = std::max(K, 16);
   HIPCHK(hipMalloc(&I->t_table, (cap + 1) * sizeof(double)));
-  HIPCHK(hipMalloc(&I->stats, 8 * (size_t)cap * sizeof(double)));
+  HIPCHK(hipMalloc(&I->stats, PD_LSTAT * (size_t)cap * sizeof(double)));
   I->kcap = cap;
   I->H.t_table = I->t_table;
   I->H.level_stats = I->stats;
   return PD_OK;
 }
 
+// Adaptive stepping: the first step from t_start (clamped to [dt_min,
+// dt_max], landing on T as every later step does); the device writes the
+// later levels as it decides them.
+double first_adaptive_level(const pd_time_desc *td, double t_start) {
+  double dt = std::min(std::max(td->dt0, td->dt_min), td->dt_max);
+  const double rem = td->T;
+  if (dt >= rem) return t_start + td->T;
+  if (dt > 0.5 * rem) dt = 0.5 * rem;
+  return t_start + dt;
+}
+
 int build_time_table(const pd_time_desc *td, double t_start, std::vector<double> &t) {
   if (!td) return fail(PD_EINVAL, "time descriptor is NULL");
   if (td->K < 1) return fail(PD_EINVAL, "K must be >= 1");
   const int K = td->K;
+  if (td->t_kind == PD_TIME_ADAPTIVE) {
+    if (!(td->T > 0.0)) return fail(PD_EINVAL, "T must be > 0");
+    if (!(td->dt0 > 0.0) || !(td->dt_min > 0.0) || !(td->dt_max >= td->dt_min))
+      return fail(PD_EINVAL, "adaptive stepping needs dt0 > 0 and 0 < dt_min <= dt_max");
+    if (!(td->tol_time > 0.0)) return fail(PD_EINVAL, "adaptive stepping needs tol_time > 0");
+    if (K < 2) return fail(PD_EINVAL, "K (the cap on adaptive steps) must be >= 2");
+    t = {t_start, first_adaptive_level(td, t_start)};
+    return PD_OK;
+  }
   t.assign(K + 1, 0.0);
   if (td->t_kind == PD_TIME_TABLE) {
     if (!td->t_table) return fail(PD_EINVAL, "t_table is NULL");
@@ -560,6 +582,8 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
 struct SolveParams {
   double theta, tol, tol_inner;
   int maxit, maxit_inner, max_outer;
+  int adaptive = 0;
+  double T = 0.0, dt_min = 0.0, dt_max = 0.0, tol_time = 0.0;
 };
 
 int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
@@ -578,10 +602,16 @@ int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   h.fact_dt = -1.0;
   h.fact_theta = -1.0;
   h.t_now = I->t;
+  h.adaptive = sp.adaptive;
+  h.need_f0 = sp.adaptive;
+  h.t_end = I->t + sp.T;
+  h.dt_min = sp.dt_min;
+  h.dt_max = sp.dt_max;
+  h.tol_time = sp.tol_time;
   HIPCHK(hipMemcpyAsync(I->sc, &h, sizeof h, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));
   // levels never taken read as not done
-  if (I->stats) HIPCHK(hipMemsetAsync(I->stats, 0, 8 * (size_t)K * sizeof(double), s));
+  if (I->stats) HIPCHK(hipMemsetAsync(I->stats, 0, PD_LSTAT * (size_t)K * sizeof(double), s));
   return PD_OK;
 }
 
@@ -665,7 +695,8 @@ struct Engine {
   }
   ~Engine() { release(); }
 
-  int build(std::vector<pd_instance *> const &insts, int cycles_cap, hipStream_t st, Schedule sch = {}) {
+  int build(std::vector<pd_instance *> const &insts, int cycles_cap, hipStream_t st, Schedule sch = {},
+            bool adaptive = false) {
     release();
     s = st;
     ninst = (int)insts.size();
@@ -704,6 +735,7 @@ struct Engine {
       g.P.reset(new Plan);
       int rc = make_plan(part, g.s, *g.P, rings);
       if (rc) return rc;
+      g.P->L.adaptive_any = adaptive ? 1 : 0;
       // every member still has levels to take
       HIPCHK(hipMemsetD32Async((hipDeviceptr_t)g.P->n_active, (int)part.size(), 1, g.s));
       if (use_graph) {
@@ -787,17 +819,21 @@ struct Engine {
 
 int cycles_cap(SolveParams const &sp) { return sp.maxit + sp.max_outer + 8; }
 
-// Per-level statistics of an instance after a solve: 8 doubles per level.
+// Per-level statistics of an instance after a solve: PD_LSTAT doubles per
+// level; an adaptive solve takes fewer levels than its cap K (the rest stay
+// zero), and fails when the cap came before T.
 int read_level_stats(pd_instance *I, int K, std::vector<double> &st, int &worst) {
   PdScalars h{};
   HIPCHK(hipMemcpy(&h, I->sc, sizeof h, hipMemcpyDeviceToHost));
   I->rot = h.rot;
   I->t = h.t_now;
   I->have_prev = true;
-  st.assign(8 * (size_t)K, 0.0);
+  st.assign(PD_LSTAT * (size_t)K, 0.0);
   HIPCHK(hipMemcpy(st.data(), I->stats, st.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int k = 0; k < K; ++k) {
-    const int status = (int)st[8 * k + 2];
+  const int taken = h.adaptive ? std::min(h.level, K) : K;
+  if (h.adaptive && h.t_now < h.t_end && worst == PD_OK) worst = PD_ENOCONV;
+  for (int k = 0; k < taken; ++k) {
+    const int status = (int)st[PD_LSTAT * k + 2];
     if (status == ST_BREAKDOWN) worst = PD_EBREAKDOWN;
     else if (status != ST_DONE && worst == PD_OK) worst = PD_ENOCONV;
   }
@@ -814,7 +850,9 @@ int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &
     cap = std::max(cap, cycles_cap(sps[q]));
   }
   Engine E;
-  if ((rc = E.build(insts, cap, s, default_schedule()))) return rc;
+  bool adaptive = false;
+  for (auto const &sp : sps) adaptive |= sp.adaptive != 0;
+  if ((rc = E.build(insts, cap, s, default_schedule(), adaptive))) return rc;
   bool finished = false;
   if ((rc = E.run((long)maxK * cap + 2 * maxK, &finished))) return rc;
   HIPCHK(hipGetLastError());
@@ -833,14 +871,26 @@ int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &
 }
 
 void fill_stats(const std::vector<double> &st, int k, pd_step_stats *o) {
-  o->iters = (int)st[8 * k + 0];
-  o->refinements = (int)st[8 * k + 1];
-  const int status = (int)st[8 * k + 2];
+  const double *e = st.data() + PD_LSTAT * (size_t)k;
+  o->iters = (int)e[0];
+  o->refinements = (int)e[1];
+  o->err_time = e[7];
+  o->rejected = (int)e[8];
+  o->pad = 0;
+  if (e[4] == 0.0) {                      // a level an adaptive solve did not need
+    o->status = PD_OK;
+    o->reserved = 0;
+    o->rel_resid = 0.0;
+    o->dt = 0.0;
+    o->t = 0.0;
+    return;
+  }
+  const int status = (int)e[2];
   o->status = status == ST_DONE ? PD_OK : (status == ST_BREAKDOWN ? PD_EBREAKDOWN : PD_ENOCONV);
-  o->reserved = (int)st[8 * k + 6];
-  o->rel_resid = st[8 * k + 3];
-  o->dt = st[8 * k + 4];
-  o->t = st[8 * k + 5];
+  o->reserved = (int)e[6];
+  o->rel_resid = e[3];
+  o->dt = e[4];
+  o->t = e[5];
 }
 
 SolveParams params_from(const pd_time_desc *td, int precision) {
@@ -851,6 +901,13 @@ SolveParams params_from(const pd_time_desc *td, int precision) {
   sp.tol_inner = 1e-3;
   sp.maxit_inner = 400;
   sp.max_outer = precision == PD_MIXED ? 40 : 0;
+  if (td->t_kind == PD_TIME_ADAPTIVE) {
+    sp.adaptive = 1;
+    sp.T = td->T;
+    sp.dt_min = td->dt_min;
+    sp.dt_max = td->dt_max;
+    sp.tol_time = td->tol_time;
+  }
   return sp;
 }
 
@@ -1617,10 +1674,10 @@ void retire_request(pd_batch *B, Request *R, int rc, int levels) {
       pd_request_summary &S = R->sum;
       for (int k = 0; k < levels; ++k) {
         S.levels = k + 1;
-        S.iters += (int)st[8 * k + 0];
-        S.refinements += (int)st[8 * k + 1];
-        S.max_rel_resid = std::max(S.max_rel_resid, st[8 * k + 3]);
-        S.t = st[8 * k + 5];
+        S.iters += (int)st[PD_LSTAT * k + 0];
+        S.refinements += (int)st[PD_LSTAT * k + 1];
+        S.max_rel_resid = std::max(S.max_rel_resid, st[PD_LSTAT * k + 3]);
+        S.t = st[PD_LSTAT * k + 5];
       }
       R->result.resize(R->N);
       rc = pd_get_solution(R->inst, R->result.data(), R->layout, 0);
@@ -1777,12 +1834,14 @@ int pd_batch_submit(pd_batch *B, const pd_mesh_desc *mesh, const pd_problem_desc
     const int m = mesh->nr, n = mesh->ntheta, N = m * n + 1;
     R->N = N;
     R->layout = pb->layout;
+    if (td->t_kind == PD_TIME_ADAPTIVE)
+      return fail(PD_EINVAL, "adaptive time stepping is not served; use pd_solve_to_T or pd_solve_batch");
     if ((rc = build_time_table(td, 0.0, R->ttab))) return rc;
     R->K = td->K;
     R->sp = params_from(td, precision);
     size_t fp = 0;
     if ((rc = pd_footprint(mesh, pb->nsrc, precision, &fp))) return rc;
-    R->footprint = fp + (9 * (size_t)std::max(R->K, 16) + 1) * sizeof(double);
+    R->footprint = fp + ((PD_LSTAT + 1) * (size_t)std::max(R->K, 16) + 1) * sizeof(double);
     if (R->footprint > B->pool)
       return fail(PD_ENOMEM, "request needs %zu bytes, the pool holds %zu", R->footprint, B->pool);
     // the host part of the instance is built here, on the caller's thread

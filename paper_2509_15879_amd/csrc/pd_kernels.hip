@@ -246,6 +246,10 @@ __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   // close to the system, not equal it (the operator, the diagonal scaling
   // and the right-hand side always follow the current Δt)
   sc->refactor = (th != sc->fact_theta || !(fabs(dt - sc->fact_dt) <= PD_REFACTOR_DT * sc->fact_dt)) ? 1 : 0;
+  if (sc->refactor) {
+    sc->fact_dt = dt;
+    sc->fact_theta = th;
+  }
   const int ne = min(sc->have_prev, PD_NHIST - 1);
   double w[2][PD_NHIST];
   guess_weights(I.t_table, k, ne, th, w);
@@ -277,7 +281,7 @@ __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
 // (iterate -> n^{k+1}); returns whether it met its tolerance.
 __device__ __forceinline__ bool end_level(const PdInst &I, PdScalars *sc) {
   const int k = sc->level;
-  double *st = I.level_stats + 8 * k;
+  double *st = I.level_stats + PD_LSTAT * k;
   st[0] = sc->iters;
   st[1] = sc->outer;
   st[2] = sc->status;
@@ -285,7 +289,9 @@ __device__ __forceinline__ bool end_level(const PdInst &I, PdScalars *sc) {
   st[4] = sc->dt;
   st[5] = sc->t1;
   st[6] = sc->restarts;
-  st[7] = 0.0;
+  st[7] = sc->adaptive ? sc->err_last : 0.0;
+  st[8] = sc->nrej;
+  st[9] = 0.0;
   sc->total_iters += sc->iters;
   const bool ok = sc->status == ST_DONE;
   if (!ok) sc->nfail += 1;
@@ -293,10 +299,7 @@ __device__ __forceinline__ bool end_level(const PdInst &I, PdScalars *sc) {
   sc->have_prev = min(sc->have_prev + 1, PD_NHIST - 1);
   sc->t_now = sc->t1;
   sc->level = k + 1;
-  if (sc->refactor) {
-    sc->fact_dt = sc->dt;
-    sc->fact_theta = sc->theta;
-  }
+  sc->nrej = 0;
   sc->in_level = 0;
   if (I.lvl_out) I.lvl_out[0] = k + 1;
   return ok;
@@ -312,6 +315,53 @@ __global__ void k_level_begin(PdInst *insts, int ninst) {
   begin_level(I, sc);
 }
 
+// ------------------------------------------------------------ adaptive steps
+//
+// A-posteriori control of Δt (the paper fixes its levels in advance; this is
+// the library's adaptive mode).  With f(t, x) = -L x + S(t) + c N(t) the
+// θ-scheme is (x_{k+1} - x_k)/Δt = (1-θ) f_k + θ f_{k+1}.  Local error
+// estimate of the step t_k -> t_{k+1}, from Taylor expansion:
+//   θ ≠ 1/2: d = (θ - 1/2) Δt (f_{k+1} - f_k)                      (order q = 1)
+//   θ = 1/2: d = (x_{k+1} - x^P) / (3 (1 + Δt_prev/Δt)),            (order q = 2)
+//            x^P = x_k + Δt ((1 + r/2) f_k - (r/2) f_{k-1}), r = Δt/Δt_prev
+//            (trapezoidal rule against the variable-step Adams-Bashforth 2)
+// e = ||d||/||x_{k+1}||.  The first step is accepted with Δt_0 and the second
+// tried with Δt_0; later a step with e > 2 tol (and Δt > dt_min) is retaken
+// with Δt max(1/4, 0.9 (tol/e)^{1/(q+1)}), and an accepted one sets the
+// next Δt to Δt clamp(0.9 (tol/e)^{1/(q+1)}, 1/2, 2) within [dt_min, dt_max];
+// a step that would pass T ends on it, one that would leave less than a
+// step ends half-way.  f and the ring part of the norms come from a stencil
+// pass at the end of every level; k_ctl closes the origin and decides.
+
+__device__ __forceinline__ double est_d(double x1, double x0, double f1, double f0, double fm1,
+                                        double dt, double dtp, double th) {
+  if (th != 0.5) return (th - 0.5) * dt * (f1 - f0);
+  const double r = dt / dtp;
+  const double xp = x0 + dt * ((1.0 + 0.5 * r) * f0 - 0.5 * r * fm1);
+  return (x1 - xp) / (3.0 * (1.0 + dtp / dt));
+}
+
+__device__ __forceinline__ double land_step(double t, double dt, double t_end) {
+  const double rem = t_end - t;
+  if (dt >= rem) return rem;
+  if (dt > 0.5 * rem) return 0.5 * rem;
+  return dt;
+}
+
+// The time level reached by a step dt from t (exactly t_end when it lands).
+__device__ __forceinline__ double next_level(double t, double dt, double t_end) {
+  return dt >= t_end - t ? t_end : t + dt;
+}
+
+// f at the origin: -(L x)_0 + S_0(t), from the ring-1 face sum S0.
+__device__ __forceinline__ double origin_f(const PdInst &I, double x0, double S0, double t) {
+  const int orig = I.m * I.n;
+  const double bo = I.has_b ? I.b_node[orig] : 0.0;
+  double f = -(I.inv_V0 * S0 + bo * x0);
+  for (int q = 0; q < I.nsrc; ++q) f += tau_q(I.lam[q], I.tpow[q], t) * I.g[q * I.npad + orig];
+  return f;
+}
+
 // Control of asynchronous levels (one thread per instance), first in every
 // cycle: an instance whose level has ended (converged, or stopped) records
 // it and starts its next level at once, whatever the others are doing; one
@@ -322,10 +372,70 @@ __global__ void k_ctl(PdInst *insts, int ninst) {
   if (q >= ninst) return;
   PdInst &I = insts[q];
   PdScalars *sc = I.sc;
+  const int orig = I.m * I.n;
+  auto level_end_sums = [&](double (&tot)[3]) {
+    for (int c = 0; c < 3; ++c) {
+      double sum = 0.0;
+      for (int b = 0; b < I.nb_sten; ++b) sum += I.part_e[c * I.nb_sten + b];
+      tot[c] = sum;
+    }
+  };
+  if (sc->adaptive && sc->need_f0) {
+    // f(t_0, x_0): the ring part was formed by the level-end pass
+    double tot[3];
+    level_end_sums(tot);
+    const double x0 = I.sol[sol_slot(sc->rot, 0)][orig];
+    I.fdot[sc->level % 3][orig] = origin_f(I, x0, tot[2], sc->t_now);
+    sc->need_f0 = 0;
+  }
   const int st = sc->status;
   if (st == ST_IDLE || st == ST_ACTIVE) return;
   bool ok = true;
+  double e = 0.0;
+  const int qord = sc->theta == 0.5 ? 2 : 1;
+  if (sc->in_level && sc->adaptive && st == ST_DONE) {
+    // the step just taken: f at its end, its error estimate, accept or retake
+    double tot[3];
+    level_end_sums(tot);
+    const int k = sc->level;
+    const double x1 = I.sol[sol_slot(sc->rot, -1)][orig];
+    const double f1 = origin_f(I, x1, tot[2], sc->t1);
+    I.fdot[(k + 1) % 3][orig] = f1;
+    if (k >= 1) {
+      const double dtp = I.t_table[k] - I.t_table[k - 1];
+      const double d0 = est_d(x1, I.sol[sol_slot(sc->rot, 0)][orig], f1, I.fdot[k % 3][orig],
+                              I.fdot[(k + 2) % 3][orig], sc->dt, dtp, sc->theta);
+      const double xx = tot[1] + x1 * x1;
+      e = sqrt(tot[0] + d0 * d0) / fmax(sqrt(xx), 1e-300);
+    }
+    sc->err_last = e;
+    if (k >= 1 && e > 2.0 * sc->tol_time && sc->dt > sc->dt_min) {
+      const double fr = fmax(0.25, 0.9 * pow(sc->tol_time / e, 1.0 / (qord + 1)));
+      const double dtr = land_step(sc->t0, fmax(sc->dt_min, sc->dt * fr), sc->t_end);
+      I.t_table[k + 1] = next_level(sc->t0, dtr, sc->t_end);
+      sc->nrej += 1;
+      begin_level(I, sc);                 // the same level again from n^k
+      return;
+    }
+  }
   if (sc->in_level) ok = end_level(I, sc);
+  if (ok && sc->adaptive) {
+    // the next level's time: grown or shrunk after the second step
+    const int k1 = sc->level;
+    const double t = sc->t_now;
+    if (t >= sc->t_end) {
+      sc->K = k1;                         // reached T: no more levels
+    } else if (k1 >= 1) {
+      double nxt = sc->dt;
+      if (k1 >= 2) {
+        const double g = e > 0.0 ? fmin(2.0, fmax(0.5, 0.9 * pow(sc->tol_time / e, 1.0 / (qord + 1)))) : 2.0;
+        nxt = sc->dt * g;
+      }
+      nxt = fmin(fmax(nxt, sc->dt_min), sc->dt_max);
+      if (k1 < sc->K) I.t_table[k1 + 1] = next_level(t, land_step(t, nxt, sc->t_end), sc->t_end);
+      else ok = false;                    // the level cap came before T
+    }
+  }
   if (ok && sc->level < sc->K) {
     begin_level(I, sc);
   } else {
@@ -823,7 +933,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
   }
 }
 
-enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4 };
+enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4, SM_EST = 5 };
 
 // Origin rows, closed by a later kernel from the producers' partial sums
 // (the ring-1 face sums S0 and the ring parts of the norms).
@@ -932,7 +1042,12 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
-  if (MODE != SM_APPLY) {
+  if (MODE == SM_EST) {
+    // adaptive stepping: f(t_0, x_0) once, then f at the end of every level
+    if (!sc->adaptive) return;
+    const bool ended = sc->in_level && sc->status == ST_DONE;
+    if (!sc->need_f0 && !ended) return;
+  } else if (MODE != SM_APPLY) {
     if (sc->status != ST_ACTIVE) return;     // no block of this kernel changes the status
     if (MODE == SM_BEGIN && sc->stage != STAGE_START) return;
     if ((MODE == SM_V || MODE == SM_T) && !prec_match<TK>(I)) return;
@@ -1080,6 +1195,44 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
       acc[2] = S0[0];
       produce<3>(acc, I.part_t, I.nb_sten, mp.y);
     }
+  } else if (MODE == SM_EST) {
+    // f = -L x + S(t) + c N(t) at the start (x_0) or at the end of a level
+    // (x_{k+1}), and the ring part of ||d||², ||x_{k+1}||² and S0
+    const bool f0 = sc->need_f0 != 0;
+    const int k = sc->level;
+    const double t = f0 ? sc->t_now : sc->t1, th = sc->theta, dt = sc->dt;
+    const bool est = !f0 && k >= 1;
+    const double dtp = est ? I.t_table[k] - I.t_table[k - 1] : 1.0;
+    const GAS double *xv = G((const double *)I.sol[sol_slot(sc->rot, f0 ? 0 : -1)]);
+    const GAS double *x0 = G((const double *)I.sol[sol_slot(sc->rot, 0)]);
+    const GAS double *fk = G((const double *)I.fdot[k % 3]), *fkm = G((const double *)I.fdot[(k + 2) % 3]);
+    GAS double *fo = G(I.fdot[(k + (f0 ? 0 : 1)) % 3]);
+    const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb);
+    double tq[PD_MAXSRC];
+    for (int q = 0; q < PD_MAXSRC; ++q) tq[q] = q < I.nsrc ? tau_q(I.lam[q], I.tpow[q], t) : 0.0;
+    const int nsrc = I.nsrc, npad = I.npad;
+    double acc[3] = {0.0, 0.0, 0.0};
+    double S0[1] = {0.0};
+    if (wave_on)
+      sten_tile<double, double, 1>(geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), xv, xv,
+                                   xv, xv, inv_rw, inv_dth, bnode, S0, no_pre,
+                                   [&](int i, int j, int idx, const double *xc, const double *Lx, double, Nil) {
+                                     double f = -Lx[0];
+                                     for (int q = 0; q < nsrc; ++q) f += tq[q] * gsrc[q * npad + idx];
+                                     if (i == m) {
+                                       double Nm = 0.0;
+                                       for (int q = 0; q < nsrc; ++q) Nm += tq[q] * nbv[q * n + j];
+                                       f += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
+                                     }
+                                     fo[idx] = f;
+                                     if (est) {
+                                       const double d = est_d(xc[0], x0[idx], f, fk[idx], fkm[idx], dt, dtp, th);
+                                       acc[0] += d * d;
+                                     }
+                                     acc[1] += xc[0] * xc[0];
+                                   });
+    acc[2] = S0[0];
+    produce<3>(acc, I.part_e, I.nb_sten, mp.y);
   } else if (MODE == SM_UR) {
     // FP64 operator applied to the FP32 correction d
     const double inv_dt = sc->inv_dt, th = sc->theta;
@@ -1971,6 +2124,9 @@ static void cycle_t(const LaunchSet &L, hipStream_t s) {
 // the instances starting a level, then `cycles` Krylov iterations of every
 // active instance.
 void launch_round(const LaunchSet &L, int cycles, hipStream_t s) {
+  if (L.adaptive_any)
+    go(KF_CONTROL, k_sten<double, SM_EST>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
+       (const double *)nullptr, (double *)nullptr);
   launch_ctl(L, s);
   launch_factor(L, s);
   launch_begin(L, s);

@@ -14,6 +14,7 @@ struct LaunchSet {
   int2 *map_frad = nullptr, *map_fang = nullptr;
   int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0, nb_frad = 0, nb_fang = 0;
   int mixed_any = 0, fp64_any = 0;
+  int adaptive_any = 0;             // some instance steps adaptively (level-end pass in the round head)
   int max_bang = 1;                 // longest angular lane span of the batch
   int max_bfrad = 1;                // longest radial segment of the factorisation
   // Radial sweeps, two classes by ring count: 512-thread blocks (32 segments

@@ -23,7 +23,7 @@ ERRORS = {-1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EBREAKDOWN", -4: "PD_ENOCONV
 PD_FP64, PD_MIXED = 0, 1
 MESH_UNIFORM, MESH_SINE, MESH_EXPLICIT, MESH_POLY = 0, 1, 2, 3
 LAYOUT_RING, LAYOUT_PAPER = 0, 1
-TIME_UNIFORM, TIME_SINE, TIME_TABLE = 0, 1, 2
+TIME_UNIFORM, TIME_SINE, TIME_TABLE, TIME_ADAPTIVE = 0, 1, 2, 3
 
 
 class PolarDiskError(RuntimeError):
@@ -49,17 +49,20 @@ class ProblemDesc(C.Structure):
 class TimeDesc(C.Structure):
     _fields_ = [("t_kind", C.c_int32), ("K", C.c_int32), ("T", C.c_double), ("l", C.c_double),
                 ("t_table", C.c_void_p), ("theta", C.c_double), ("tol", C.c_double),
-                ("max_iters", C.c_int32)]
+                ("max_iters", C.c_int32), ("dt0", C.c_double), ("dt_min", C.c_double),
+                ("dt_max", C.c_double), ("tol_time", C.c_double)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("status", C.c_int32),
                 ("reserved", C.c_int32), ("rel_resid", C.c_double), ("dt", C.c_double),
-                ("t", C.c_double)]
+                ("t", C.c_double), ("err_time", C.c_double), ("rejected", C.c_int32),
+                ("pad", C.c_int32)]
 
     def as_dict(self):
         return {"iters": self.iters, "refinements": self.refinements, "status": self.status,
-                "restarts": self.reserved, "rel_resid": self.rel_resid, "dt": self.dt, "t": self.t}
+                "restarts": self.reserved, "rel_resid": self.rel_resid, "dt": self.dt, "t": self.t,
+                "err_time": self.err_time, "rejected": self.rejected}
 
 
 class RequestSummary(C.Structure):
@@ -193,13 +196,26 @@ def ring_vector(origin, grid):
 
 def time_desc(theta, K, T=None, t_kind=TIME_UNIFORM, l=1.0, table=None, tol=1e-12, max_iters=0):
     td = TimeDesc(int(t_kind), int(K), float(T or 0.0), float(l), None, float(theta), float(tol),
-                  int(max_iters))
+                  int(max_iters), 0.0, 0.0, 0.0, 0.0)
     if table is not None:
         a = _f64(table)
         td.t_table = _ptr(a)
         td.t_kind = TIME_TABLE
         td._keep = a
     return td
+
+
+def adaptive_time_desc(theta, T, dt0, tol_time, dt_min, dt_max, K_max=20000, tol=1e-12, max_iters=0):
+    """A-posteriori step control from the current time to T later: the GPU
+    picks every Δt from its local error estimate (statistics past the steps
+    taken have dt = 0)."""
+    return TimeDesc(TIME_ADAPTIVE, int(K_max), float(T), 1.0, None, float(theta), float(tol),
+                    int(max_iters), float(dt0), float(dt_min), float(dt_max), float(tol_time))
+
+
+def taken(stats):
+    """The steps an (adaptive) solve took: statistics with dt > 0."""
+    return [s for s in stats if s["dt"] > 0.0]
 
 
 def time_levels(td: TimeDesc, t_start=0.0):
