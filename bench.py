@@ -208,6 +208,44 @@ def uneven_variant(pdk, stream, tol, sample_alone=32):
     }
 
 
+def adaptive_variant(pdk, stream, tol, tol_time=1e-6):
+    """The benchmark batch advanced to T with a-posteriori step control
+    (dt in [1e-5, 1e-3], first step 1e-5, local error tolerance tol_time),
+    FP64: steps taken, wall time, and the error against a converged FP64
+    solve of the same (logged) time levels."""
+    import torch
+    insts, tds, u0s = build_instances(pdk, pdk.PD_FP64, stream)
+    cells = [i.N for i in insts]
+    descs = [pdk.adaptive_time_desc(th, T_END, 1e-5, tol_time, 1e-5, 1e-3, tol=tol) for th, _ in tds]
+    reset(insts, u0s)
+    pdk.solve_batch(insts, descs)                       # warm-up (plans, graphs)
+    reset(insts, u0s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = pdk.solve_batch(insts, descs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    steps = [pdk.taken(st) for st in sts]
+    xs = [i.solution() for i in insts]
+    # converged FP64 replay of each instance's own levels
+    errs = []
+    for inst, u0, (th, _), st, x in zip(insts, u0s, tds, steps, xs):
+        inst.set_solution(u0, 0.0)
+        inst.solve(pdk.time_desc(th, len(st), table=[0.0] + [s["t"] for s in st], tol=1e-13))
+        r = inst.solution()
+        errs.append(float(np.linalg.norm(x - r) / np.linalg.norm(r)))
+    for i in insts:
+        i.close()
+    upd = sum(c * len(st) for c, st in zip(cells, steps))
+    return {"workload": "benchmark batch, adaptive dt in [1e-5, 1e-3] from 1e-5, local error tol "
+                        f"{tol_time:g}, FP64, T=0.05",
+            "steps_per_instance": [len(st) for st in steps],
+            "rejected": sum(s["rejected"] for st in steps for s in st),
+            "ms": round(1e3 * el, 1), "value": round(upd / el, 1),
+            "iters_per_step_mean": round(float(np.mean([s["iters"] for st in steps for s in st])), 2),
+            "l2_rel_vs_fp64_converged_same_levels_max": max(errs)}
+
+
 def paper_table_variant(pdk, stream):
     """Ch. 2 numerical experiment 1 as one batch of the fifteen runs of its
     error table (m = 19..99, n = floor(2 pi m); the stretch (2.4) with
@@ -522,6 +560,8 @@ def main():
                                         [sum(s["refinements"] for s in st) for st in mst])) / K_LEVELS, 2)}
             for i in mix:
                 i.close()
+        log("adaptive time steps ...")
+        var["adaptive_dt"] = adaptive_variant(pdk, stream, args.tol)
         log("Table 2.1 runs batched ...")
         var["paper_table_2_1"] = paper_table_variant(pdk, stream)
         log("serving stream ...")
