@@ -354,6 +354,7 @@ def serving_variant(pdk, duration=8.0, check=6):
         "utilisation": round((work / duration) / (work / wall), 3),
         "wall_s": round(wall, 2),
         "peak_active": info["peak_active"], "plans_built": info["plans_built"],
+        "worker_s": {k: round(info[k], 3) for k in ("build_s", "admit_s", "retire_s", "run_s")},
         "l2_rel_vs_fp64_alone_sample": {k: max(v) for k, v in errs.items()},
     }
 

@@ -332,6 +332,10 @@ typedef struct {
   int32_t reserved;
   uint64_t submitted, completed, slices_run, plans_built;
   size_t used_bytes, peak_bytes;   /* admitted footprint, now and at most   */
+  double build_s;        /* worker time building launch plans and graphs    */
+  double admit_s;        /* worker time uploading admitted requests         */
+  double retire_s;       /* worker time reading back and freeing results    */
+  double run_s;          /* worker time launching slices and waiting on them */
 } pd_batch_info;
 
 int pd_batch_create(size_t hbm_pool_bytes, int32_t max_slots, void *hip_stream, pd_batch **out);

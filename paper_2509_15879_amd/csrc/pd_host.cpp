@@ -199,6 +199,7 @@ struct pd_instance {
   double *t_table = nullptr; // device time table (capacity kcap+1)
   double *stats = nullptr;   // device level stats (PD_LSTAT * kcap)
   int kcap = 0;
+  bool arena = false;         // dmem, t_table and stats are one chunk of a serving arena
   int rot = 0;               // host mirror of the buffer rotation
   double t = 0.0;            // current time
   bool have_prev = false;
@@ -1086,17 +1087,23 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
 
 // Device allocation and uploads of a prepared instance on I->stream
 // (returns once the uploads are done; the image may then be dropped).
-int upload_instance(pd_instance *I, const HostImage &X) {
+// mem: device memory of at least instance_bytes(I) to carve into, or NULL
+// to allocate it.
+int upload_instance(pd_instance *I, const HostImage &X, void *mem = nullptr) {
   const int m = I->M.m, n = I->M.n;
   const int np = I->T.npad;
   Carver dry{nullptr, 0, true};
   carve(I, dry);
   I->dbytes = dry.off;
-  hipError_t e = hipMalloc(&I->dmem, I->dbytes);
-  if (e != hipSuccess) {
-    I->dmem = nullptr;
-    return fail(e == hipErrorOutOfMemory ? PD_ENOMEM : PD_EHIP, "device allocation of %zu bytes failed: %s",
-                I->dbytes, hipGetErrorString(e));
+  if (mem) {
+    I->dmem = mem;
+  } else {
+    hipError_t e = hipMalloc(&I->dmem, I->dbytes);
+    if (e != hipSuccess) {
+      I->dmem = nullptr;
+      return fail(e == hipErrorOutOfMemory ? PD_ENOMEM : PD_EHIP, "device allocation of %zu bytes failed: %s",
+                  I->dbytes, hipGetErrorString(e));
+    }
   }
   hipStream_t s = I->stream;
   HIPCHK(hipMemsetAsync(I->dmem, 0, I->dbytes, s));
@@ -1273,9 +1280,11 @@ int pd_destroy(pd_instance *I) {
   if (!I) return PD_OK;
   if (I->busy) return fail(PD_EBUSY, "instance is in use");
   if (I->stream) (void)hipStreamSynchronize(I->stream);
-  if (I->dmem) (void)hipFree(I->dmem);
-  if (I->t_table) (void)hipFree(I->t_table);
-  if (I->stats) (void)hipFree(I->stats);
+  if (!I->arena) {          // a serving arena takes its chunk back itself
+    if (I->dmem) (void)hipFree(I->dmem);
+    if (I->t_table) (void)hipFree(I->t_table);
+    if (I->stats) (void)hipFree(I->stats);
+  }
   if (I->own_stream) (void)hipStreamDestroy(I->stream);
   delete I;
   return PD_OK;
@@ -1605,6 +1614,8 @@ struct Request {
   size_t footprint = 0;
   SolveParams sp{};
   pd_instance *inst = nullptr;
+  void *chunk = nullptr;                   // its device memory, from the loop's arena
+  size_t chunk_bytes = 0;
   int status = PD_PENDING;
   std::string err;
   std::vector<double> result;
@@ -1618,8 +1629,68 @@ double seconds(Clock::time_point a, Clock::time_point b) {
 
 }  // namespace
 
+// Device memory of a serving loop: segments allocated on demand (at least
+// seg_bytes) and kept until the loop ends, carved first-fit with free
+// lists that coalesce, so that requests are admitted and retired without
+// hipMalloc or hipFree (hipFree waits for the whole device).  Used by the
+// loop's worker thread only.
+struct Arena {
+  struct Seg {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free;   // offset -> bytes
+  };
+  std::vector<Seg> segs;
+  size_t seg_bytes = size_t(1) << 30;
+  static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+  void *alloc(size_t bytes) {
+    bytes = round(bytes);
+    for (auto &g : segs)
+      for (auto it = g.free.begin(); it != g.free.end(); ++it)
+        if (it->second >= bytes) {
+          const size_t off = it->first, rest = it->second - bytes;
+          g.free.erase(it);
+          if (rest) g.free.emplace(off + bytes, rest);
+          return g.base + off;
+        }
+    Seg g;
+    g.size = std::max(seg_bytes, bytes);
+    if (hipMalloc((void **)&g.base, g.size) != hipSuccess) return nullptr;
+    if (g.size > bytes) g.free.emplace(bytes, g.size - bytes);
+    segs.push_back(std::move(g));
+    return segs.back().base;
+  }
+  void release(void *p, size_t bytes) {
+    bytes = round(bytes);
+    for (auto &g : segs) {
+      if ((char *)p < g.base || (char *)p >= g.base + g.size) continue;
+      size_t off = (char *)p - g.base;
+      auto nx = g.free.lower_bound(off);
+      if (nx != g.free.end() && nx->first == off + bytes) {   // merge with the next free run
+        bytes += nx->second;
+        nx = g.free.erase(nx);
+      }
+      if (nx != g.free.begin()) {                              // and with the previous one
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == off) {
+          off = pv->first;
+          bytes += pv->second;
+          g.free.erase(pv);
+        }
+      }
+      g.free.emplace(off, bytes);
+      return;
+    }
+  }
+  void destroy() {
+    for (auto &g : segs) (void)hipFree(g.base);
+    segs.clear();
+  }
+};
+
 struct pd_batch {
   size_t pool = 0;
+  Arena arena;
   int max_slots = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -1642,20 +1713,32 @@ int admit_request(pd_batch *B, Request *R) {
   I->device = B->device;
   I->stream = B->stream;
   I->own_stream = false;
-  int rc = upload_instance(I, *R->image);
-  R->image.reset();
-  if (rc) {
-    if (I->dmem) (void)hipFree(I->dmem);
-    if (I->t_table) (void)hipFree(I->t_table);
-    if (I->stats) (void)hipFree(I->stats);
-    I->dmem = nullptr;
-    I->t_table = nullptr;
-    I->stats = nullptr;
+  // one arena chunk: the instance's arrays, then its time table and statistics
+  Carver dry{nullptr, 0, true};
+  carve(I, dry);
+  const size_t kcap = (size_t)std::max(R->K, 16);
+  const size_t db = Arena::round(dry.off), tb = Arena::round((kcap + 1) * sizeof(double));
+  R->chunk_bytes = db + tb + PD_LSTAT * kcap * sizeof(double);
+  R->chunk = B->arena.alloc(R->chunk_bytes);
+  if (!R->chunk) {
     R->prepared.reset();
+    return fail(PD_ENOMEM, "device allocation of %zu bytes for a request failed", R->chunk_bytes);
+  }
+  int rc = upload_instance(I, *R->image, R->chunk);
+  R->image.reset();
+  I->arena = true;
+  I->t_table = (double *)((char *)R->chunk + db);
+  I->stats = (double *)((char *)R->chunk + db + tb);
+  I->kcap = (int)kcap;
+  I->H.t_table = I->t_table;
+  I->H.level_stats = I->stats;
+  if (rc) {
+    R->prepared.reset();
+    B->arena.release(R->chunk, R->chunk_bytes);
+    R->chunk = nullptr;
     return rc;
   }
   R->inst = R->prepared.release();
-  if ((rc = ensure_time_capacity(R->inst, R->K))) return rc;
   HIPCHK(hipMemcpyAsync(R->inst->t_table, R->ttab.data(), R->ttab.size() * sizeof(double), hipMemcpyHostToDevice,
                         B->stream));
   return init_scalars(R->inst, R->sp, R->K, B->stream);
@@ -1691,6 +1774,8 @@ void retire_request(pd_batch *B, Request *R, int rc, int levels) {
   }
   if (R->inst) (void)pd_destroy(R->inst);
   R->inst = nullptr;
+  if (R->chunk) B->arena.release(R->chunk, R->chunk_bytes);
+  R->chunk = nullptr;
   const auto now = Clock::now();
   std::lock_guard<std::mutex> lk(B->mu);
   R->sum.status = rc;
@@ -1730,6 +1815,7 @@ void serve(pd_batch *B) {
       }
       B->info.peak_active = std::max(B->info.peak_active, B->info.active);
     }
+    const auto t_a = Clock::now();
     for (Request *R : admit) {
       R->t_admit = Clock::now();
       const int rc = admit_request(B, R);
@@ -1739,6 +1825,11 @@ void serve(pd_batch *B) {
         active.push_back(R);
         dirty = true;
       }
+    }
+    const auto t_b = Clock::now();
+    if (!admit.empty()) {
+      std::lock_guard<std::mutex> lk(B->mu);
+      B->info.admit_s += std::chrono::duration<double>(t_b - t_a).count();
     }
     if (active.empty()) continue;
     int rc = PD_OK;
@@ -1753,11 +1844,14 @@ void serve(pd_batch *B) {
       dirty = false;
       std::lock_guard<std::mutex> lk(B->mu);
       B->info.plans_built += 1;
+      B->info.build_s += std::chrono::duration<double>(Clock::now() - t_b).count();
     }
     // a slice of asynchronous cycles, then retire whoever left the batch
+    const auto t_r = Clock::now();
     bool fin = false;
     if (!rc) rc = E.run(kServeSlice, &fin);
     if (!rc) rc = E.levels_done(lv);
+    const auto t_d = Clock::now();
     if (rc) {
       // a failure of the loop itself ends every active request
       E.release();
@@ -1779,6 +1873,8 @@ void serve(pd_batch *B) {
     if (active.empty()) E.release();
     std::lock_guard<std::mutex> lk(B->mu);
     B->info.slices_run += 1;       // slices of cycles run
+    B->info.run_s += std::chrono::duration<double>(t_d - t_r).count();
+    B->info.retire_s += std::chrono::duration<double>(Clock::now() - t_d).count();
   }
   E.release();
   for (Request *R : active)
@@ -1897,6 +1993,7 @@ int pd_batch_destroy(pd_batch *B) {
   B->cv.notify_all();
   if (B->worker.joinable()) B->worker.join();
   if (B->stream) (void)hipStreamSynchronize(B->stream);
+  B->arena.destroy();
   if (B->own_stream) (void)hipStreamDestroy(B->stream);
   delete B;
   return PD_OK;

@@ -78,7 +78,8 @@ class BatchInfo(C.Structure):
     _fields_ = [("pending", C.c_int32), ("active", C.c_int32), ("peak_active", C.c_int32),
                 ("reserved", C.c_int32), ("submitted", C.c_uint64), ("completed", C.c_uint64),
                 ("slices_run", C.c_uint64), ("plans_built", C.c_uint64), ("used_bytes", C.c_size_t),
-                ("peak_bytes", C.c_size_t)]
+                ("peak_bytes", C.c_size_t), ("build_s", C.c_double), ("admit_s", C.c_double),
+                ("retire_s", C.c_double), ("run_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
