@@ -163,10 +163,13 @@ template <>
 __device__ __forceinline__ const KSet<float> &kset<float>(const PdInst &I) { return I.k32; }
 
 // Composition of affine maps u -> P u + e:  (P2, e2) ∘ (P1, e1).
-struct Aff {
-  double P, e;
+template <typename C>
+struct AffT {
+  C P, e;
 };
-__device__ __forceinline__ Aff compose(Aff later, Aff earlier) {
+using Aff = AffT<double>;
+template <typename C>
+__device__ __forceinline__ AffT<C> compose(AffT<C> later, AffT<C> earlier) {
   return {later.P * earlier.P, later.P * earlier.e + later.e};
 }
 
@@ -1308,10 +1311,12 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
 
 enum { RM_P = 0, RM_S = 1, RM_PLAIN = 2 };
 
-template <int BM>
+// C: the sweep's arithmetic type, its storage type T (FP64, or FP32 for the
+// inner solve of mixed precision).
+template <typename C, int BM>
 struct RadRegs {
-  double a[BM], b[BM];          // P: r, p - ω v   S: r, v   PLAIN: x
-  double u[BM], f[BM], g[BM];   // pivot inverse and multipliers
+  C a[BM], b[BM];               // P: r, p - ω v   S: r, v
+  C u[BM], f[BM], g[BM];        // pivot inverse and multipliers
 };
 
 template <typename T, int MODE, int BM>
@@ -1319,54 +1324,55 @@ __device__ __forceinline__ void rad_load(int n, int j, int rb, int klast, double
                                          const GAS T *__restrict__ a, const GAS T *__restrict__ b,
                                          const GAS T *__restrict__ c,
                                          const GAS float *__restrict__ uinv,
-                                         const GAS float *__restrict__ f, RadRegs<BM> &R) {
+                                         const GAS float *__restrict__ f, RadRegs<T, BM> &R) {
+  const T om = (T)omega;
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     // rows past the segment's end repeat its last row (clamped, always issued)
     const int idx = (rb + min(k, klast)) * n + j;
-    R.a[k] = (double)a[idx];
-    if (MODE == RM_P) R.b[k] = (double)b[idx] - omega * (double)c[idx];
-    if (MODE == RM_S) R.b[k] = (double)b[idx];
-    R.u[k] = (double)uinv[idx];
-    R.f[k] = (double)f[idx];
+    R.a[k] = a[idx];
+    if (MODE == RM_P) R.b[k] = b[idx] - om * c[idx];
+    if (MODE == RM_S) R.b[k] = b[idx];
+    R.u[k] = (T)uinv[idx];
+    R.f[k] = (T)f[idx];
   }
 }
 
 // The backward multipliers, loaded once the launch's partial sums are read
 // (they are first needed after the forward join, and holding them through
 // the closure of the p-sweep would cost registers).
-template <int BM>
+template <typename C, int BM>
 __device__ __forceinline__ void rad_load_g(int n, int j, int rb, int klast,
-                                           const GAS float *__restrict__ g, RadRegs<BM> &R) {
+                                           const GAS float *__restrict__ g, RadRegs<C, BM> &R) {
 #pragma unroll
-  for (int k = 0; k < BM; ++k) R.g[k] = (double)g[(rb + min(k, klast)) * n + j];
+  for (int k = 0; k < BM; ++k) R.g[k] = (C)g[(rb + min(k, klast)) * n + j];
 }
 
 // Joins of the segments of a block's columns (NW waves, 4 segments of the
 // 16 columns per wave).  Forward: the value entering segment s from above is
 // the composition of the maps of segments 0..s-1 applied to 0; backward: of
 // the segments below s.  lane/16 is the segment within the wave.
-template <int NW>
-__device__ __forceinline__ double rad_join(Aff A, bool fwd, int c, int lane, int wave,
-                                           double (&lp)[NW][16], double (&le)[NW][16]) {
+template <typename C, int NW>
+__device__ __forceinline__ C rad_join(AffT<C> A, bool fwd, int c, int lane, int wave,
+                                      C (&lp)[NW][16], C (&le)[NW][16]) {
   const int sub = lane >> 4;
   // inclusive scan over the wave's 4 segments
 #pragma unroll
   for (int d = 1; d < 4; d <<= 1) {
-    const Aff o = fwd ? Aff{__shfl_up(A.P, 16 * d, 64), __shfl_up(A.e, 16 * d, 64)}
-                      : Aff{__shfl_down(A.P, 16 * d, 64), __shfl_down(A.e, 16 * d, 64)};
+    const AffT<C> o = fwd ? AffT<C>{__shfl_up(A.P, 16 * d, 64), __shfl_up(A.e, 16 * d, 64)}
+                          : AffT<C>{__shfl_down(A.P, 16 * d, 64), __shfl_down(A.e, 16 * d, 64)};
     if (fwd ? sub >= d : sub + d < 4) A = compose(A, o);
   }
   // the part of the wave before (forward) or after (backward) the segment
-  const Aff ex = fwd ? Aff{__shfl_up(A.P, 16, 64), __shfl_up(A.e, 16, 64)}
-                     : Aff{__shfl_down(A.P, 16, 64), __shfl_down(A.e, 16, 64)};
+  const AffT<C> ex = fwd ? AffT<C>{__shfl_up(A.P, 16, 64), __shfl_up(A.e, 16, 64)}
+                         : AffT<C>{__shfl_down(A.P, 16, 64), __shfl_down(A.e, 16, 64)};
   const bool edge = fwd ? sub == 0 : sub == 3;
   if (sub == (fwd ? 3 : 0)) {
     lp[wave][c] = A.P;
     le[wave][c] = A.e;
   }
   __syncthreads();
-  double W = 0.0;
+  C W = (C)0;
   if (fwd) {
     for (int w = 0; w < wave; ++w) W = lp[w][c] * W + le[w][c];
   } else {
@@ -1379,30 +1385,31 @@ __device__ __forceinline__ double rad_join(Aff A, bool fwd, int c, int lane, int
 template <typename T, int MODE, int BM, int NT>
 __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begin, int cnt,
                                           bool origin_thread, double beta, double omega,
-                                          double alpha, bool first, bool reset, RadRegs<BM> &R,
+                                          double alpha, bool first, bool reset, RadRegs<T, BM> &R,
                                           const GAS T *__restrict__ r, GAS T *__restrict__ p,
                                           const GAS T *__restrict__ v, GAS T *__restrict__ rh,
                                           GAS T *__restrict__ s, const GAS T *__restrict__ pin,
                                           GAS T *__restrict__ out) {
   constexpr int NW = NT / 64;
-  __shared__ double lp[NW][16], le[NW][16];
+  __shared__ T lp[NW][16], le[NW][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  // RM_P: b = p - ω v, so that p = r + β b
-  auto input = [&](double a, double b) -> T {
-    if (MODE == RM_P) return (T)(first ? a : a + beta * b);
-    if (MODE == RM_S) return (T)(a - alpha * b);
-    return (T)a;
+  // RM_P: b = p - ω v, so that p = r + β b (in T: FP32 for the inner solve)
+  const T be = (T)beta, al = (T)alpha;
+  auto input = [&](T a, T b) -> T {
+    if (MODE == RM_P) return first ? a : a + be * b;
+    if (MODE == RM_S) return a - al * b;
+    return a;
   };
   if (origin_thread) {
     const int o = m * n;
     if (MODE == RM_P) {
-      const T ps = input((double)r[o], (double)p[o] - omega * (double)v[o]);
+      const T ps = input(r[o], (T)((double)p[o] - omega * (double)v[o]));
       p[o] = ps;
       if (reset) rh[o] = r[o];
       out[o] = ps;
     } else if (MODE == RM_S) {
-      const T ss = input((double)r[o], (double)v[o]);
+      const T ss = input(r[o], v[o]);
       s[o] = ss;
       out[o] = ss;
     } else {
@@ -1412,7 +1419,7 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
 
   // right-hand side of the sweep (stored in the Krylov vector it defines),
   // then the local forward pass
-  double wl[BM];
+  T wl[BM];
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     const T ys = input(R.a[k], R.b[k]);
@@ -1420,15 +1427,15 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
       const int idx = (i_begin + k) * n + j;
       if (MODE == RM_P) {
         p[idx] = ys;
-        if (reset) rh[idx] = (T)R.a[k];
+        if (reset) rh[idx] = R.a[k];
       } else if (MODE == RM_S) {
         s[idx] = ys;
       }
     }
-    wl[k] = k < cnt ? R.u[k] * (double)ys : 0.0;
-    if (k >= cnt) R.f[k] = 0.0;   // the forward fix-up then leaves such rows alone
+    wl[k] = k < cnt ? R.u[k] * ys : (T)0;
+    if (k >= cnt) R.f[k] = (T)0;  // the forward fix-up then leaves such rows alone
   }
-  Aff A{1.0, 0.0};
+  AffT<T> A{(T)1, (T)0};
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     if (k < cnt) {
@@ -1437,14 +1444,14 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
       wl[k] = A.e;
     }
   }
-  const double Win = rad_join<NW>(A, true, c, lane, wave, lp, le);
-  double P = 1.0;
+  const T Win = rad_join<T, NW>(A, true, c, lane, wave, lp, le);
+  T P = (T)1;
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     P *= -R.f[k];
     wl[k] += P * Win;
   }
-  Aff Bk{1.0, 0.0};
+  AffT<T> Bk{(T)1, (T)0};
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
@@ -1453,13 +1460,13 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
       wl[k] = Bk.e;
     }
   }
-  const double Xin = rad_join<NW>(Bk, false, c, lane, wave, lp, le);
-  double Q = 1.0;
+  const T Xin = rad_join<T, NW>(Bk, false, c, lane, wave, lp, le);
+  T Q = (T)1;
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
       Q *= -R.g[k];
-      out[(i_begin + k) * n + j] = (T)(wl[k] + Q * Xin);
+      out[(i_begin + k) * n + j] = wl[k] + Q * Xin;
     }
   }
 }
@@ -1487,7 +1494,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   const int cnt = act ? max(0, min(B, m - seg * B)) : 0;
   const int jj = act ? j : 0;
   const int rb = cnt > 0 ? seg * B : 0, klast = cnt > 0 ? cnt - 1 : 0;
-  RadRegs<BM> R;
+  RadRegs<T, BM> R;
   auto load = [&]() {
     const T *a = (MODE == RM_PLAIN) ? plain_in : KS.r;
     const T *bb = (MODE == RM_P) ? KS.p : KS.v;
@@ -1605,7 +1612,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
     if (st != ST_ACTIVE) return;
   }
   if (pend != PEND_UPDATE) load();
-  rad_load_g<BM>(n, jj, rb, klast, G((const float *)I.rf_g), R);
+  rad_load_g<T, BM>(n, jj, rb, klast, G((const float *)I.rf_g), R);
   T *out = (MODE == RM_PLAIN) ? plain_out : KS.w;
   rad_solve<T, MODE, BM, NT>(m, n, jj, c, seg * B, cnt, b0, beta, omega, alpha, first, reset, R,
                          G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s),
@@ -1633,14 +1640,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The sweep computes in its storage type T (FP64, or FP32 for the inner
+// solve of mixed precision).
 template <typename T, int BM>
-__device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, double kappa,
-                                         double alpha0, const GAS T *__restrict__ in,
+__device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, double kappa_d,
+                                         double alpha0_d, const GAS T *__restrict__ in,
                                          GAS T *__restrict__ out,
                                          const GAS float *__restrict__ uinv,
                                          const GAS float *__restrict__ f,
                                          const GAS float *__restrict__ g,
-                                         const GAS float *__restrict__ z, double *tb) {
+                                         const GAS float *__restrict__ z, T *tb) {
+  using C = T;
+  const C kappa = (C)kappa_d, alpha0 = (C)alpha0_d;
   const int row = (i - 1) * n, frow = (i - 1) * 64 * B;
   const int j0 = lane * B;
   const int cnt = max(0, min(B, n - j0));
@@ -1648,19 +1659,19 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
 
   // every load first: the ring's input (coalesced, node lane + 64k) and this
   // lane's factors (node j0 + k, stored at 64k + lane)
-  double xin[BM], ul[BM], fl[BM], gl[BM], zl[BM];
+  C xin[BM], ul[BM], fl[BM], gl[BM], zl[BM];
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     if (k < B) {
       const int jn = min(lane + 64 * k, n - 1);
       const int fi = frow + 64 * k + lane;
-      xin[k] = (double)in[row + jn];
-      ul[k] = (double)uinv[fi];
-      fl[k] = (double)f[fi];
-      gl[k] = (double)g[fi];
-      zl[k] = (double)z[fi];
+      xin[k] = (C)in[row + jn];
+      ul[k] = (C)uinv[fi];
+      fl[k] = (C)f[fi];
+      gl[k] = (C)g[fi];
+      zl[k] = (C)z[fi];
     } else {
-      xin[k] = ul[k] = fl[k] = gl[k] = zl[k] = 0.0;
+      xin[k] = ul[k] = fl[k] = gl[k] = zl[k] = (C)0;
     }
   }
   // node j sits at j + j/B in LDS: lane L's nodes are contiguous, one gap after each lane
@@ -1670,18 +1681,18 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
     if (k < B && j < n) tb[j + j / B] = xin[k];
   }
   wave_sync();
-  double wl[BM];
+  C wl[BM];
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     const bool own = k < cnt;
-    wl[k] = own ? ul[k] * tb[lane * (B + 1) + k] : 0.0;
-    fl[k] = own ? fl[k] : 0.0;
-    gl[k] = own ? gl[k] : 0.0;
-    zl[k] = own ? zl[k] : 0.0;
+    wl[k] = own ? ul[k] * tb[lane * (B + 1) + k] : (C)0;
+    fl[k] = own ? fl[k] : (C)0;
+    gl[k] = own ? gl[k] : (C)0;
+    zl[k] = own ? zl[k] : (C)0;
   }
   wave_sync();
 
-  Aff A{1.0, 0.0};
+  AffT<C> A{(C)1, (C)0};
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     if (k < cnt) {
@@ -1692,18 +1703,18 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
   }
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const Aff o{__shfl_up(A.P, d, 64), __shfl_up(A.e, d, 64)};
+    const AffT<C> o{__shfl_up(A.P, d, 64), __shfl_up(A.e, d, 64)};
     if (lane >= d) A = compose(A, o);
   }
-  double Win = __shfl_up(A.e, 1, 64);
-  if (lane == 0) Win = 0.0;
-  double P = 1.0;
+  C Win = __shfl_up(A.e, 1, 64);
+  if (lane == 0) Win = (C)0;
+  C P = (C)1;
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     P *= -fl[k];
     wl[k] += P * Win;
   }
-  Aff Bk{1.0, 0.0};
+  AffT<C> Bk{(C)1, (C)0};
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
@@ -1714,12 +1725,12 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
   }
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const Aff o{__shfl_down(Bk.P, d, 64), __shfl_down(Bk.e, d, 64)};
+    const AffT<C> o{__shfl_down(Bk.P, d, 64), __shfl_down(Bk.e, d, 64)};
     if (lane + d < 64) Bk = compose(Bk, o);
   }
-  double Xin = __shfl_down(Bk.e, 1, 64);
-  if (lane == 63) Xin = 0.0;
-  double Q = 1.0, ylast = 0.0;
+  C Xin = __shfl_down(Bk.e, 1, 64);
+  if (lane == 63) Xin = (C)0;
+  C Q = (C)1, ylast = (C)0;
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
@@ -1728,9 +1739,9 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
       if (j0 + k == n - 1) ylast = wl[k];
     }
   }
-  const double y0 = __shfl(wl[0], 0, 64);
-  const double yl = __shfl(ylast, (n - 1) / B, 64);
-  const double sfac = kappa * (y0 - alpha0 * yl);
+  const C y0 = __shfl(wl[0], 0, 64);
+  const C yl = __shfl(ylast, (n - 1) / B, 64);
+  const C sfac = kappa * (y0 - alpha0 * yl);
   // back to node order through LDS, then coalesced stores
 #pragma unroll
   for (int k = 0; k < BM; ++k)
@@ -1765,7 +1776,7 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
     sc->pend = PEND_UPDATE;
   }
   if (i > m) return;                                 // whole wave exits together
-  __shared__ double tbuf[4][64 * (BM + 1)];          // one exchange buffer per wave
+  __shared__ T tbuf[4][64 * (BM + 1)];               // one exchange buffer per wave
   const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
   T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
   ang_body<T, BM>(m, n, I.bang, i, lane, I.af_kappa[i - 1], I.af_alpha0[i - 1], G(in), G(out),
