@@ -351,6 +351,7 @@ inline void face_pair(double G, double K, int flux, double &gp, double &gm) {
 
 int ensure_time_capacity(pd_instance *I, int K) {
   if (K <= I->kcap) return PD_OK;
+  if (I->arena) return fail(PD_EINVAL, "a served request's level capacity is fixed at admission");
   if (I->t_table) (void)hipFree(I->t_table);
   if (I->stats) (void)hipFree(I->stats);
   I->t_table = nullptr;
@@ -475,15 +476,36 @@ EventTimer *g_event_timer = nullptr;
 
 // ------------------------------------------------------------------ engine
 
+// Launch plan of a set of instances.  Its device data (active counter,
+// level words, instance descriptors, block maps) lives in one buffer staged
+// through one pinned host buffer; both grow only and are kept when the plan
+// is rebuilt for another set, so that a serving loop re-plans without
+// allocating or freeing device memory (hipFree waits for the whole device).
 struct Plan {
   pd::LaunchSet L;
-  std::vector<void *> bufs;
+  char *dbuf = nullptr, *hbuf = nullptr;   // device data and its pinned staging
+  size_t cap = 0;
   int *n_active = nullptr;
   int *h_active = nullptr;   // pinned, 2 slots
   int *lvl = nullptr;        // device: (levels done, status) per instance
   hipEvent_t ev[2] = {nullptr, nullptr};
+  int reserve(size_t bytes, hipStream_t s) {
+    if (bytes <= cap) return PD_OK;
+    if (dbuf) {
+      HIPCHK(hipStreamSynchronize(s));
+      (void)hipFree(dbuf);
+      (void)hipHostFree(hbuf);
+      dbuf = hbuf = nullptr;
+    }
+    const size_t c = std::max(bytes, cap + cap / 2);
+    HIPCHK(hipMalloc(&dbuf, c));
+    HIPCHK(hipHostMalloc((void **)&hbuf, c));
+    cap = c;
+    return PD_OK;
+  }
   ~Plan() {
-    for (void *b : bufs) (void)hipFree(b);
+    if (dbuf) (void)hipFree(dbuf);
+    if (hbuf) (void)hipHostFree(hbuf);
     if (h_active) (void)hipHostFree(h_active);
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -520,13 +542,47 @@ void xcd_contiguous(std::vector<int2> &map) {
 int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, int fp32_rings = PD_RB) {
   const int ninst = (int)insts.size();
   auto rings = [&](const pd_instance *I) { return I->precision == PD_MIXED ? fp32_rings : PD_RB; };
-  HIPCHK(hipMalloc(&P.n_active, sizeof(int)));
-  P.bufs.push_back(P.n_active);
-  HIPCHK(hipMemsetAsync(P.n_active, 0, sizeof(int), s));
-  HIPCHK(hipMalloc(&P.lvl, 2 * (size_t)ninst * sizeof(int)));
-  P.bufs.push_back(P.lvl);
-  HIPCHK(hipMemsetAsync(P.lvl, 0, 2 * (size_t)ninst * sizeof(int), s));
-  std::vector<PdInst> hv(ninst);
+  P.L = pd::LaunchSet{};
+  // host side first: the block maps, then one layout for everything
+  std::vector<int2> maps[7];
+  int *counts[7] = {&P.L.nb_sten, &P.L.nb_elem, &P.L.nb_rad, &P.L.nb_rs[0], &P.L.nb_rs[1], &P.L.nb_ang, nullptr};
+  int2 **dsts[7] = {&P.L.map_sten, &P.L.map_elem, &P.L.map_rad, &P.L.map_rs[0], &P.L.map_rs[1], &P.L.map_ang,
+                    nullptr};
+  *counts[0] = build_map(insts, [&](pd_instance *I) { return sten_blocks(I->M.m, I->M.n, rings(I)); }, maps[0]);
+  *counts[1] = build_map(insts, [](pd_instance *I) { return I->T.nb_elem; }, maps[1]);
+  // radial sweep blocks: neighbouring column blocks share the 128-byte
+  // lines of FP32 rows (16 columns x 4 bytes), so they go to the same XCD
+  // (L2).  The factorisation keeps the plain order: only the instances
+  // starting a level take part in it, and a contiguous run per XCD would
+  // crowd them onto a few XCDs.
+  *counts[2] = build_map(insts, [](pd_instance *I) { return I->T.nb_rad; }, maps[2]);
+  for (int c = 0; c < 2; ++c)
+    *counts[3 + c] =
+        build_map(insts, [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? I->T.nb_rad : 0; }, maps[3 + c]);
+  *counts[5] = build_map(insts, [](pd_instance *I) { return I->T.nb_ang; }, maps[5]);
+  xcd_contiguous(maps[0]);
+  xcd_contiguous(maps[3]);
+  xcd_contiguous(maps[4]);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t off = 0;
+  const size_t o_act = off;
+  off += al(sizeof(int));
+  const size_t o_lvl = off;
+  off += al(2 * (size_t)ninst * sizeof(int));
+  const size_t o_inst = off;
+  off += al((size_t)ninst * sizeof(PdInst));
+  size_t o_map[6];
+  for (int k = 0; k < 6; ++k) {
+    o_map[k] = off;
+    off += al(maps[k].size() * sizeof(int2));
+  }
+  int rc;
+  if ((rc = P.reserve(off, s))) return rc;
+  P.n_active = (int *)(P.dbuf + o_act);
+  P.lvl = (int *)(P.dbuf + o_lvl);
+  P.L.insts = (PdInst *)(P.dbuf + o_inst);
+  std::memset(P.hbuf, 0, off);
+  PdInst *hv = (PdInst *)(P.hbuf + o_inst);
   for (int q = 0; q < ninst; ++q) {
     hv[q] = insts[q]->H;
     hv[q].rb = rings(insts[q]);
@@ -543,40 +599,22 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
     const int c = pd::rad_class(I->M.m);
     P.L.max_brs[c] = std::max(P.L.max_brs[c], pd::rad_rows(I->M.m));
   }
-  HIPCHK(hipMalloc(&P.L.insts, ninst * sizeof(PdInst)));
-  P.bufs.push_back(P.L.insts);
-  HIPCHK(hipMemcpyAsync(P.L.insts, hv.data(), ninst * sizeof(PdInst), hipMemcpyHostToDevice, s));
+  for (int k = 0; k < 6; ++k) {
+    *dsts[k] = maps[k].empty() ? nullptr : (int2 *)(P.dbuf + o_map[k]);
+    if (!maps[k].empty()) std::memcpy(P.hbuf + o_map[k], maps[k].data(), maps[k].size() * sizeof(int2));
+  }
   P.L.ninst = ninst;
-  std::vector<int2> mp;
-  auto upload = [&](int2 **dst, int *cnt, auto fn, bool by_xcd = false) -> int {
-    *cnt = build_map(insts, fn, mp);
-    if (*cnt == 0) return PD_OK;
-    if (by_xcd) xcd_contiguous(mp);
-    HIPCHK(hipMalloc(dst, mp.size() * sizeof(int2)));
-    P.bufs.push_back(*dst);
-    HIPCHK(hipMemcpyAsync(*dst, mp.data(), mp.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return PD_OK;
-  };
-  int rc;
-  if ((rc = upload(&P.L.map_sten, &P.L.nb_sten,
-                   [&](pd_instance *I) { return sten_blocks(I->M.m, I->M.n, rings(I)); }, true)))
-    return rc;
-  if ((rc = upload(&P.L.map_elem, &P.L.nb_elem, [](pd_instance *I) { return I->T.nb_elem; }))) return rc;
-  // radial sweep blocks: neighbouring column blocks share the 128-byte
-  // lines of FP32 rows (16 columns x 4 bytes), so they go to the same XCD
-  // (L2).  The factorisation keeps the plain order: only the instances
-  // starting a level take part in it, and a contiguous run per XCD would
-  // crowd them onto a few XCDs.
-  if ((rc = upload(&P.L.map_rad, &P.L.nb_rad, [](pd_instance *I) { return I->T.nb_rad; }))) return rc;
-  for (int c = 0; c < 2; ++c)
-    if ((rc = upload(&P.L.map_rs[c], &P.L.nb_rs[c],
-                     [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? I->T.nb_rad : 0; }, true)))
-      return rc;
-  if ((rc = upload(&P.L.map_ang, &P.L.nb_ang, [](pd_instance *I) { return I->T.nb_ang; }))) return rc;
-  HIPCHK(hipHostMalloc((void **)&P.h_active, 2 * sizeof(int)));
+  // one copy (the pinned staging is rewritten only after the next plan's
+  // copy has been ordered behind this one on the same stream, and the
+  // stream is synchronised before the host writes it again)
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpyAsync(P.dbuf, P.hbuf, off, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!P.h_active) {
+    HIPCHK(hipHostMalloc((void **)&P.h_active, 2 * sizeof(int)));
+    for (auto &e : P.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   P.h_active[0] = P.h_active[1] = 1;
-  for (auto &e : P.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return PD_OK;
 }
 
@@ -681,12 +719,15 @@ struct Engine {
   int cpg = 2;
   int rings = PD_RB;
 
+  std::vector<std::unique_ptr<Plan>> spare;   // plans kept for the next build
+
   void release() {
     for (auto &g : G) {
       if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
       if (g.graph) (void)hipGraphDestroy(g.graph);
-      if (g.s && g.s != s) (void)hipStreamSynchronize(g.s);
-      g.P.reset();
+      // a kept plan may next serve another stream: nothing may still read it
+      if (g.s) (void)hipStreamSynchronize(g.s);
+      if (g.P) spare.push_back(std::move(g.P));
     }
     G.clear();
     if (fork_ev) (void)hipEventDestroy(fork_ev);
@@ -733,7 +774,12 @@ struct Engine {
       if (!g.s) return fail(PD_EHIP, "could not create a helper stream");
       std::vector<pd_instance *> part;
       for (int q : g.members) part.push_back(insts[q]);
-      g.P.reset(new Plan);
+      if (!spare.empty()) {
+        g.P = std::move(spare.back());
+        spare.pop_back();
+      } else {
+        g.P.reset(new Plan);
+      }
       int rc = make_plan(part, g.s, *g.P, rings);
       if (rc) return rc;
       g.P->L.adaptive_any = adaptive ? 1 : 0;
@@ -1724,12 +1770,14 @@ int admit_request(pd_batch *B, Request *R) {
     R->prepared.reset();
     return fail(PD_ENOMEM, "device allocation of %zu bytes for a request failed", R->chunk_bytes);
   }
-  int rc = upload_instance(I, *R->image, R->chunk);
-  R->image.reset();
+  // the time table and statistics live in the chunk too (set before the
+  // upload, which would otherwise allocate them)
   I->arena = true;
   I->t_table = (double *)((char *)R->chunk + db);
   I->stats = (double *)((char *)R->chunk + db + tb);
   I->kcap = (int)kcap;
+  int rc = upload_instance(I, *R->image, R->chunk);
+  R->image.reset();
   I->H.t_table = I->t_table;
   I->H.level_stats = I->stats;
   if (rc) {
