@@ -117,6 +117,14 @@ struct PdInst {
   float *rf_uinv, *rf_f, *rf_g;           // [m*n] radial pivots 1/u and multipliers
   float *af_uinv, *af_f, *af_g, *af_z;    // [m*64*bang] angular (sweep order), SM vector
   double *af_kappa, *af_alpha0;   // [m] Sherman-Morrison scalars per ring
+  // The origin row and ring 1's couplings to the origin belong to the
+  // angular factor (ring 1 and the origin form an arrow system): with
+  // T1 = ring 1's block of (I + D^{-1}Θ), ã_j = ring 1's scaled coupling to
+  // the origin, c̃_j = the origin row's scaled coupling to ring 1,
+  // q = T1^{-1} ã and σ = 1 - c̃·q, the sweep takes u = T1^{-1} w_1,
+  // z_0 = (w_0 - c̃·u)/σ, z_1 = u - q z_0.
+  float *af_q, *af_c;       // [64*bang] q and c̃, sweep order
+  double *af_sigma;         // [1] σ (1, with q = c̃ = 0, when the arrow is not used)
   KSet<double> k64;
   KSet<float> k32;
   double *partials;         // per-block partial sums, one region per producer:

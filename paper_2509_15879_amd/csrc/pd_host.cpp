@@ -256,6 +256,9 @@ void carve(pd_instance *I, Carver &c) {
   H.af_z = c.take<float>(ma);
   H.af_kappa = c.take<double>(m);
   H.af_alpha0 = c.take<double>(m);
+  H.af_q = c.take<float>(64 * I->T.bang);
+  H.af_c = c.take<float>(64 * I->T.bang);
+  H.af_sigma = c.take<double>(1);
   H.k64.gp_r = c.take<double>((size_t)(m + 1) * n);
   H.k64.gm_r = c.take<double>((size_t)(m + 1) * n);
   H.k64.gp_t = c.take<double>(mn);

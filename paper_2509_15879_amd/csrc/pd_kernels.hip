@@ -785,10 +785,101 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
   }
   const double z0 = __shfl(wl[0], 0, 64);
   const double zl = __shfl(zlast, (n - 1) / B, 64);
+  const double kap = 1.0 / (1.0 + z0 - a0 * zl);
   if (lane == 0) {
-    G(I.af_kappa)[i - 1] = 1.0 / (1.0 + z0 - a0 * zl);
+    G(I.af_kappa)[i - 1] = kap;
     G(I.af_alpha0)[i - 1] = a0;
   }
+  if (i != 1) return;
+
+  // Ring 1 and the origin: ã_j = -θ gp_r(1/2, j)/(V_1j d_1j) couples ring 1
+  // to the origin, c̃_j = -θ gm_r(1/2, j)/(V_0 d_0) the origin to ring 1.
+  // q = T1^{-1} ã by the same substitutions and Sherman-Morrison closure,
+  // then σ = 1 - c̃·q (a fixed-order wave sum: every lane gets the same bits).
+  const GAS double *dg = G(I.diag), *gpr = G(I.k64.gp_r), *gmr = G(I.k64.gm_r);
+  const double d0 = dg[m * n], iv1 = G(I.inv_rw)[1];
+  double qv[BM] = {};
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      const int j = j0 + k;
+      qv[k] = -th * iv1 * G(I.inv_dth)[j] * gpr[j] / dg[j];
+    }
+  }
+  Aff F{1.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      F.e = ul[k] * qv[k] - fl[k] * F.e;
+      F.P *= -fl[k];
+      qv[k] = F.e;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const Aff o{__shfl_up(F.P, d, 64), __shfl_up(F.e, d, 64)};
+    if (lane >= d) F = compose(F, o);
+  }
+  double Fin = __shfl_up(F.e, 1, 64);
+  if (lane == 0) Fin = 0.0;
+  double PF = 1.0;
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      PF *= -fl[k];
+      qv[k] += PF * Fin;
+    }
+  }
+  Aff Bq{1.0, 0.0};
+#pragma unroll
+  for (int k = BM - 1; k >= 0; --k) {
+    if (k < cnt) {
+      Bq.e = qv[k] - gf[k] * Bq.e;
+      Bq.P *= -gf[k];
+      qv[k] = Bq.e;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const Aff o{__shfl_down(Bq.P, d, 64), __shfl_down(Bq.e, d, 64)};
+    if (lane + d < 64) Bq = compose(Bq, o);
+  }
+  double Qin = __shfl_down(Bq.e, 1, 64);
+  if (lane == 63) Qin = 0.0;
+  double QB = 1.0, qlast = 0.0;
+#pragma unroll
+  for (int k = BM - 1; k >= 0; --k) {
+    if (k < cnt) {
+      QB *= -gf[k];
+      qv[k] += QB * Qin;
+      if (j0 + k == n - 1) qlast = qv[k];
+    }
+  }
+  const double sf = kap * (__shfl(qv[0], 0, 64) - a0 * __shfl(qlast, (n - 1) / B, 64));
+  double dot = 0.0, cv[BM] = {};
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      qv[k] -= sf * wl[k];
+      cv[k] = -th * I.inv_V0 * gmr[j0 + k] / d0;
+      dot += cv[k] * qv[k];
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) dot += __shfl_xor(dot, d, 64);
+  const double sigma = 1.0 - dot;
+  // an arrow whose Schur complement is not safely positive is not used:
+  // the origin then passes through as in the radial sweep
+  const bool use = sigma > 1e-6 && sigma < INFINITY;
+  GAS float *qq = G(I.af_q), *cc = G(I.af_c);
+#pragma unroll
+  for (int k = 0; k < BM; ++k) {
+    if (k < cnt) {
+      qq[64 * k + lane] = use ? (float)qv[k] : 0.0f;
+      cc[64 * k + lane] = use ? (float)cv[k] : 0.0f;
+    }
+  }
+  if (lane == 0) G(I.af_sigma)[0] = use ? sigma : 1.0;
 }
 
 // ------------------------------------------------------------ stencil march
@@ -1649,19 +1740,34 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
                                          const GAS float *__restrict__ uinv,
                                          const GAS float *__restrict__ f,
                                          const GAS float *__restrict__ g,
-                                         const GAS float *__restrict__ z, T *tb) {
+                                         const GAS float *__restrict__ z,
+                                         const GAS float *__restrict__ qa,
+                                         const GAS float *__restrict__ ca,
+                                         const GAS double *__restrict__ sigma, T *tb,
+                                         float *abuf) {
   using C = T;
   const C kappa = (C)kappa_d, alpha0 = (C)alpha0_d;
   const int row = (i - 1) * n, frow = (i - 1) * 64 * B;
   const int j0 = lane * B;
   const int cnt = max(0, min(B, n - j0));
-  if (i == 1 && lane == 0) out[m * n] = in[m * n];
+  const bool arrow = i == 1;   // ring 1 closes the origin row (wave-uniform)
 
   // every load first: the ring's input (coalesced, node lane + 64k) and this
   // lane's factors (node j0 + k, stored at 64k + lane)
   C xin[BM], ul[BM], fl[BM], gl[BM], zl[BM];
+  C w0 = (C)0, sg = (C)1;
+  float aq[BM], ac[BM];   // ring 1: its arrow vectors, parked in LDS (abuf) with the input
+  if (arrow) {
+    w0 = (C)in[m * n];
+    sg = (C)sigma[0];
+  }
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
+    aq[k] = ac[k] = 0.0f;
+    if (arrow && k < cnt) {
+      aq[k] = qa[64 * k + lane];
+      ac[k] = ca[64 * k + lane];
+    }
     if (k < B) {
       const int jn = min(lane + 64 * k, n - 1);
       const int fi = frow + 64 * k + lane;
@@ -1679,6 +1785,10 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
   for (int k = 0; k < BM; ++k) {
     const int j = lane + 64 * k;
     if (k < B && j < n) tb[j + j / B] = xin[k];
+    if (arrow) {
+      abuf[64 * k + lane] = aq[k];            // read back by this lane only
+      abuf[64 * (BM + k) + lane] = ac[k];
+    }
   }
   wave_sync();
   C wl[BM];
@@ -1742,10 +1852,26 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
   const C y0 = __shfl(wl[0], 0, 64);
   const C yl = __shfl(ylast, (n - 1) / B, 64);
   const C sfac = kappa * (y0 - alpha0 * yl);
+#pragma unroll
+  for (int k = 0; k < BM; ++k) wl[k] -= sfac * zl[k];
+  if (arrow) {
+    // z_0 = (w_0 - c̃·u)/σ, z_1 = u - q z_0 (fixed-order wave sum)
+    C dot = (C)0;
+#pragma unroll
+    for (int k = 0; k < BM; ++k)
+      if (k < cnt) dot += (C)abuf[64 * (BM + k) + lane] * wl[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) dot += __shfl_xor(dot, d, 64);
+    const C z0 = (w0 - dot) / sg;
+#pragma unroll
+    for (int k = 0; k < BM; ++k)
+      if (k < cnt) wl[k] -= (C)abuf[64 * k + lane] * z0;
+    if (lane == 0) out[m * n] = (T)z0;
+  }
   // back to node order through LDS, then coalesced stores
 #pragma unroll
   for (int k = 0; k < BM; ++k)
-    if (k < cnt) tb[lane * (B + 1) + k] = wl[k] - sfac * zl[k];
+    if (k < cnt) tb[lane * (B + 1) + k] = wl[k];
   wave_sync();
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
@@ -1777,12 +1903,13 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
   }
   if (i > m) return;                                 // whole wave exits together
   __shared__ T tbuf[4][64 * (BM + 1)];               // one exchange buffer per wave
+  __shared__ float abuf[2 * 64 * BM];                // ring 1's arrow vectors (its wave only)
   const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
   T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
   ang_body<T, BM>(m, n, I.bang, i, lane, I.af_kappa[i - 1], I.af_alpha0[i - 1], G(in), G(out),
                   G((const float *)I.af_uinv), G((const float *)I.af_f), G((const float *)I.af_g),
-                  G((const float *)I.af_z),
-                  tbuf[threadIdx.x >> 6]);
+                  G((const float *)I.af_z), G((const float *)I.af_q), G((const float *)I.af_c),
+                  G((const double *)I.af_sigma), tbuf[threadIdx.x >> 6], abuf);
 }
 
 // ------------------------------------------------------------ update kernel
