@@ -45,9 +45,8 @@ KERNEL_NAMES = {
 # WRITE_SIZE counters, calibrated on a copy of known size), valid for the
 # sources with this SHA-1 only (kernel_source_sha1); any other source
 # reports traffic null.
-TRAFFIC_SOURCE_SHA1 = "b4b38d071fef35460963e0f2521897aa632467eb"
-TRAFFIC_B_PER_CELL = {"rad_p": 53.54, "ang_p": 32.44, "sten_v": 64.94, "rad_s": 44.21,
-                      "ang_s": 32.43, "sten_t": 64.41, "update": 64.54}
+TRAFFIC_SOURCE_SHA1 = "69646537a4b9777d296faa7a93e258c3db06c8c0"
+TRAFFIC_B_PER_CELL = {"rad_p": 53.87, "ang_p": 32.47, "sten_v": 64.68, "rad_s": 44.20, "ang_s": 32.46, "sten_t": 64.64, "update": 64.51}
 
 
 def kernel_source_sha1():
