@@ -28,6 +28,10 @@
 #define PD_LSTAT 10           // statistics per level (see end_level)
 #define PD_NHIST 4        // earlier levels kept for the initial guess: n^k .. n^{k-3}
 #define PD_NSOL 5         // rotating solution slots: the PD_NHIST levels and the iterate
+#define PD_NBEGIN (2 + PD_NHIST)   // partials of the level-begin stencil: ||D^-1 b||², ||D^-1 r||², S0 per level
+// partials of the Gram pass: Z Z^T (upper triangle), Z r_c for both
+// candidates, ||r_c||² for both, S0 per level
+#define PD_NGRAM (10 + 2 * PD_NHIST + 2 + PD_NHIST)
 
 // Slot holding n^{k-back} (back = 0..3) or, for back = -1, the iterate of
 // the level under way, under rotation `rot`.
@@ -47,11 +51,10 @@ enum { CNT_BEGIN = 0, CNT_V = 1, CNT_T = 2, CNT_X = 3, CNT_UR = 4, CNT_APPLY = 5
 struct PdScalars {
   // time level
   double t0, t1, dt, inv_dt, theta;
-  double ex_w[2][PD_NHIST]; // two candidate initial guesses: Σ_a w[c][a] n^{k-a}
+  double ex_w[2][PD_NHIST]; // two polynomial candidate guesses: Σ_a w[c][a] n^{k-a}
   int ex_n;                 // earlier levels beyond n^k the guesses use (0..3)
-  int ex_sel;               // candidate taken at this level
-  int ex_next;              // candidate with the smaller residual at this level's begin
-  int pad3;
+  int guess_kind;           // the guess taken: candidate 0 or 1, plus 2 with the least-squares correction
+  double guess_w[PD_NHIST]; // its weights (set by the level-begin stencil)
   double cq[PD_MAXSRC];
   double tol, tol_inner;
   double fact_dt, fact_theta;
@@ -130,6 +133,7 @@ struct PdInst {
   double *partials;         // per-block partial sums, one region per producer:
   double *part_b, *part_v, *part_t, *part_ur, *part_a;   // [slots * nb_sten]
   double *part_x;                                        // [2 * nb_elem]
+  double *part_g;                                        // [PD_NGRAM * nb_sten]
   unsigned *counters;       // [CNT_N]
   PdScalars *sc;
   int *n_active;            // shared counter of the batch (device)

@@ -292,7 +292,8 @@ void carve(pd_instance *I, Carver &c) {
     H.k32.gm_t = c.take<float>(mn);
   }
   const int nbs = I->T.nb_sten;
-  H.part_b = c.take<double>(5 * (size_t)nbs);
+  H.part_b = c.take<double>(PD_NBEGIN * (size_t)nbs);
+  H.part_g = c.take<double>(PD_NGRAM * (size_t)nbs);
   H.part_v = c.take<double>(2 * (size_t)nbs);
   H.part_t = c.take<double>(3 * (size_t)nbs);
   H.part_ur = c.take<double>(2 * (size_t)nbs);

@@ -259,7 +259,7 @@ __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   for (int c = 0; c < 2; ++c)
     for (int a = 0; a < PD_NHIST; ++a) sc->ex_w[c][a] = w[c][a];
   sc->ex_n = ne;
-  sc->ex_sel = sc->ex_next;
+  sc->guess_kind = 0;
   for (int s = 0; s < PD_MAXSRC; ++s) sc->cq[s] = 0.0;
   for (int s = 0; s < I.nsrc; ++s)
     sc->cq[s] = (1.0 - th) * tau_q(I.lam[s], I.tpow[s], t0) + th * tau_q(I.lam[s], I.tpow[s], t1);
@@ -1027,52 +1027,40 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
   }
 }
 
-enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4, SM_EST = 5 };
+enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4, SM_EST = 5, SM_GRAM = 6 };
 
 // Origin rows, closed by a later kernel from the producers' partial sums
 // (the ring-1 face sums S0 and the ring parts of the norms).
 
-// Level begin at the origin: rhs b_0, both guesses and their scaled
-// residuals; the selected guess's values are stored.
+// Level begin at the origin: rhs b_0, the guess and its scaled residual.
 struct OriginBegin {
-  double b, xg, r, rs, bb, rr, rr_other;
+  double b, xg, r, rs, bb, rr;
 };
-// Partial sums of the level-begin stencil: ||D^-1 b||², the two candidates'
-// ||D^-1 r||², S0 of n^k .. n^{k-3}.
-#define PD_NBEGIN (3 + PD_NHIST)
 __device__ __forceinline__ OriginBegin origin_begin(const PdInst &I, const PdScalars *sc,
                                                     const double (&tot)[PD_NBEGIN]) {
   const int orig = I.m * I.n;
   const double inv_dt = sc->inv_dt, th = sc->theta;
-  const int ne = sc->ex_n, sel = sc->ex_sel;
+  const int ne = sc->ex_n;
   const double bo = I.has_b ? I.b_node[orig] : 0.0;
   double xa[PD_NHIST], La[PD_NHIST];
   for (int a = 0; a < PD_NHIST; ++a) {
     xa[a] = I.sol[sol_slot(sc->rot, a <= ne ? a : 0)][orig];
-    La[a] = I.inv_V0 * tot[3 + a] + bo * xa[a];
+    La[a] = I.inv_V0 * tot[2 + a] + bo * xa[a];
   }
   double b = inv_dt * xa[0] - (1.0 - th) * La[0];
   for (int q = 0; q < I.nsrc; ++q) b += sc->cq[q] * I.g[q * I.npad + orig];
   const double id = origin_invd(I, inv_dt, th);
+  double g = 0.0, Lg = 0.0;
+  for (int a = 0; a < PD_NHIST; ++a) {
+    g += sc->guess_w[a] * xa[a];
+    Lg += sc->guess_w[a] * La[a];
+  }
   OriginBegin O;
   O.b = b;
-  double rs[2], xg[2], r[2];
-  for (int c = 0; c < 2; ++c) {   // c = 0: the selected candidate, 1: the other
-    const double *w = sc->ex_w[c == 0 ? sel : 1 - sel];
-    double g = 0.0, Lg = 0.0;
-    for (int a = 0; a < PD_NHIST; ++a) {
-      g += w[a] * xa[a];
-      Lg += w[a] * La[a];
-    }
-    r[c] = b - (inv_dt * g + th * Lg);
-    xg[c] = g;
-    rs[c] = r[c] * id;
-  }
-  O.r = r[0];
-  O.xg = xg[0];
-  O.rs = rs[0];
-  O.rr = tot[1] + rs[0] * rs[0];
-  O.rr_other = tot[2] + rs[1] * rs[1];
+  O.xg = g;
+  O.r = b - (inv_dt * g + th * Lg);
+  O.rs = O.r * id;
+  O.rr = tot[1] + O.rs * O.rs;
   const double bs = b * id;
   O.bb = tot[0] + bs * bs;
   return O;
@@ -1090,6 +1078,151 @@ __device__ __forceinline__ void origin_begin_store(const PdInst &I, const PdScal
     I.k64.r[orig] = O.rs;
     I.k64.rh[orig] = O.rs;
   }
+}
+
+// The initial guess of a level.  With y_a = D^{-1} A n^{k-a} (a = 0..ne),
+// the Gram pass sums over the ring nodes both polynomial candidates' scaled
+// residuals r_c = D^{-1}b - Σ_a w_{c,a} y_a, so that the better candidate
+// is known at this very level.  It is then corrected by least squares over
+// the span of n^k and its first ne differences, whose images are z_0 = y_0,
+// z_1 = y_0 - y_1, z_2 = y_0 - 2y_1 + y_2, z_3 = y_0 - 3y_1 + 3y_2 - y_3:
+// minimise ||r_c - Σ_i d_i z_i|| by the normal equations, scaled to a unit
+// diagonal and factored by Cholesky while the pivots stay above rounding
+// level.  Solving for the correction, whose right-hand side is the already
+// small r_c, keeps the rounding of these badly conditioned equations at the
+// scale of r_c rather than of b.  The correction is taken only when it
+// predicts at most half the candidate's residual norm.  The origin row is
+// added to the partial sums here.  Returns the candidate, plus 2 when
+// corrected.
+__device__ __forceinline__ void gram_dirs(const double (&y)[PD_NHIST], double (&z)[PD_NHIST]) {
+  const double d1a = y[0] - y[1], d1b = y[1] - y[2], d1c = y[2] - y[3];
+  const double d2a = d1a - d1b, d2b = d1b - d1c;
+  z[0] = y[0];
+  z[1] = d1a;
+  z[2] = d2a;
+  z[3] = d2a - d2b;
+}
+__device__ __forceinline__ int begin_guess(const PdInst &I, const PdScalars *sc,
+                                           const double (&tot)[PD_NGRAM], double (&w)[PD_NHIST]) {
+  const int orig = I.m * I.n;
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  const int ne = sc->ex_n;
+  const double bo = I.has_b ? I.b_node[orig] : 0.0;
+  const double id = origin_invd(I, inv_dt, th);
+  double y[PD_NHIST], xa0 = 0.0, La0 = 0.0;
+#pragma unroll
+  for (int a = 0; a < PD_NHIST; ++a) {
+    const double xa = I.sol[sol_slot(sc->rot, a <= ne ? a : 0)][orig];
+    const double La = I.inv_V0 * tot[20 + a] + bo * xa;
+    y[a] = (inv_dt * xa + th * La) * id;
+    if (a == 0) {
+      xa0 = xa;
+      La0 = La;
+    }
+  }
+  double b = inv_dt * xa0 - (1.0 - th) * La0;
+  for (int q = 0; q < I.nsrc; ++q) b += sc->cq[q] * I.g[q * I.npad + orig];
+  const double bs = b * id;
+  double z[PD_NHIST], rc[2];
+  gram_dirs(y, z);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    rc[c] = bs;
+#pragma unroll
+    for (int a = 0; a < PD_NHIST; ++a) rc[c] -= sc->ex_w[c][a] * y[a];
+  }
+  const double rr0 = tot[18] + rc[0] * rc[0], rr1 = tot[19] + rc[1] * rc[1];
+  // below three earlier levels both candidates are the same polynomial
+  const int base = (ne == PD_NHIST - 1 && rr1 < rr0) ? 1 : 0;
+  const double rrb = base ? rr1 : rr0, rb = rc[base];
+  double G[PD_NHIST][PD_NHIST], h[PD_NHIST];
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < PD_NHIST; ++i) {
+#pragma unroll
+    for (int j = i; j < PD_NHIST; ++j) {
+      G[i][j] = G[j][i] = tot[t] + z[i] * z[j];
+      ++t;
+    }
+    h[i] = tot[10 + PD_NHIST * base + i] + z[i] * rb;
+  }
+  // fixed loop bounds and masks throughout, so that everything stays in registers
+  double sca[PD_NHIST], L[PD_NHIST][PD_NHIST], u[PD_NHIST];
+  bool live = true;
+  int used = 0;
+#pragma unroll
+  for (int j = 0; j < PD_NHIST; ++j) {
+    sca[j] = 0.0;
+    u[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < PD_NHIST; ++k) L[j][k] = 0.0;
+    if (live && j <= ne && G[j][j] > 0.0 && G[j][j] < INFINITY) {
+      sca[j] = 1.0 / sqrt(G[j][j]);
+    } else {
+      live = false;
+    }
+  }
+  live = true;
+#pragma unroll
+  for (int j = 0; j < PD_NHIST; ++j) {
+    if (live && sca[j] > 0.0) {
+      double d = G[j][j] * sca[j] * sca[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+      if (d > 1e-13) {
+        L[j][j] = sqrt(d);
+#pragma unroll
+        for (int i = j + 1; i < PD_NHIST; ++i) {
+          double v = G[i][j] * sca[i] * sca[j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+          L[i][j] = sca[i] > 0.0 ? v / L[j][j] : 0.0;
+        }
+        used = j + 1;
+      } else {
+        live = false;
+      }
+    } else {
+      live = false;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PD_NHIST; ++j) {
+    if (j < used) {
+      double v = h[j] * sca[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[j][k] * u[k];
+      u[j] = v / L[j][j];
+    }
+  }
+#pragma unroll
+  for (int j = PD_NHIST - 1; j >= 0; --j) {
+    if (j < used) {
+      double v = u[j];
+#pragma unroll
+      for (int k = j + 1; k < PD_NHIST; ++k)
+        if (k < used) v -= L[k][j] * u[k];
+      u[j] = v / L[j][j];
+    }
+  }
+  // the correction's coefficients, its predicted residual ||r_c||² - h·d,
+  // and the weights of the levels (z_i = Σ_a C[i][a] y_a)
+  const double C[PD_NHIST][PD_NHIST] = {{1, 0, 0, 0}, {1, -1, 0, 0}, {1, -2, 1, 0}, {1, -3, 3, -1}};
+  double dw[PD_NHIST] = {0.0, 0.0, 0.0, 0.0}, hd = 0.0;
+  bool fin = true;
+#pragma unroll
+  for (int j = 0; j < PD_NHIST; ++j) {
+    const double d = j < used ? u[j] * sca[j] : 0.0;
+    hd += h[j] * d;
+#pragma unroll
+    for (int a = 0; a < PD_NHIST; ++a) dw[a] += d * C[j][a];
+  }
+#pragma unroll
+  for (int a = 0; a < PD_NHIST; ++a) fin = fin && fabs(dw[a]) < INFINITY;
+  const bool corr = used > 0 && fin && (rrb - hd) < 0.25 * rrb;
+#pragma unroll
+  for (int a = 0; a < PD_NHIST; ++a) w[a] = sc->ex_w[base][a] + (corr ? dw[a] : 0.0);
+  return base + (corr ? 2 : 0);
 }
 
 // Refinement at the origin: r_0 <- r_0 - (A d)_0, with the previous r_0 kept
@@ -1123,6 +1256,9 @@ __device__ __forceinline__ double origin_apply(const PdInst &I, double inv_dt, d
 // Stencil kernels.  TK: storage type of the Krylov set the mode works on.
 // Ring rows only; the origin row is closed by the consumer of the partials.
 //  SM_APPLY: y = x/dt + θ L x (diagnostic; partial S0)
+//  SM_GRAM:  (level begin, first pass) b as below and y_a = D^{-1}A n^{k-a};
+//            partials: the Gram matrix of the difference directions of the
+//            y_a, their products with D^{-1}b, S0 of n^k .. n^{k-3}
 //  SM_BEGIN: b = x^k/dt - (1-θ) L x^k + Σ_q c_q g_q + boundary;
 //            x0 = x^k + ρ (x^k - x^{k-1});  r = D^{-1}(b - A x0);  r̂ = r
 //            partials ||D^{-1}b||², ||r||², S0(x^k), S0(x^{k-1})
@@ -1143,7 +1279,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (!sc->need_f0 && !ended) return;
   } else if (MODE != SM_APPLY) {
     if (sc->status != ST_ACTIVE) return;     // no block of this kernel changes the status
-    if (MODE == SM_BEGIN && sc->stage != STAGE_START) return;
+    if ((MODE == SM_BEGIN || MODE == SM_GRAM) && sc->stage != STAGE_START) return;
     if ((MODE == SM_V || MODE == SM_T) && !prec_match<TK>(I)) return;
     if (MODE == SM_UR && !I.mixed) return;
   }
@@ -1187,16 +1323,78 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                              y[idx] = (TK)(inv_dt * xc[0] + th * Lx[0]);
                            });
     produce<1>(S0, I.part_a, I.nb_sten, mp.y);
-  } else if (MODE == SM_BEGIN) {
-    // FP64 operator on n^k .. n^{k-3} (levels the guesses do not use alias
-    // n^k and carry zero weight); both candidates' residuals are summed, the
-    // selected one is stored
+  } else if (MODE == SM_GRAM) {
+    // the rows of the least-squares problem of the guess, summed per block
     const double inv_dt = sc->inv_dt, th = sc->theta;
-    const int ne = sc->ex_n, sel = sc->ex_sel;
-    double w0[PD_NHIST], w1[PD_NHIST];
+    const int ne = sc->ex_n;
+    const double *xk0 = I.sol[sol_slot(sc->rot, 0)];
+    const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
+    const double *xk2 = I.sol[sol_slot(sc->rot, ne >= 2 ? 2 : 0)];
+    const double *xk3 = I.sol[sol_slot(sc->rot, ne >= 3 ? 3 : 0)];
+    double cq[PD_MAXSRC], w0[PD_NHIST], w1[PD_NHIST];
+    for (int q = 0; q < PD_MAXSRC; ++q) cq[q] = sc->cq[q];
     for (int a = 0; a < PD_NHIST; ++a) {
-      w0[a] = sc->ex_w[sel][a];
-      w1[a] = sc->ex_w[1 - sel][a];
+      w0[a] = sc->ex_w[0][a];
+      w1[a] = sc->ex_w[1][a];
+    }
+    const int nsrc = I.nsrc, npad = I.npad;
+    double acc[PD_NGRAM] = {};
+    double S0[PD_NHIST] = {};
+    const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb);
+    if (wave_on)
+      sten_tile<double, double, PD_NHIST>(
+          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk0), G(xk1), G(xk2),
+          G(xk3), inv_rw, inv_dth, bnode, S0, no_pre,
+          [&](int i, int j, int idx, const double *xc, const double *Lx, double ld, Nil) {
+            double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
+            for (int q = 0; q < nsrc; ++q) b += cq[q] * gsrc[q * npad + idx];
+            if (i == m) {
+              double Nm = 0.0;
+              for (int q = 0; q < nsrc; ++q) Nm += cq[q] * nbv[q * n + j];
+              b += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
+            }
+            const double id = 1.0 / diag_of(inv_dt, th, ld);
+            double y[PD_NHIST], z[PD_NHIST];
+#pragma unroll
+            for (int a = 0; a < PD_NHIST; ++a) y[a] = (inv_dt * xc[a] + th * Lx[a]) * id;
+            gram_dirs(y, z);
+            double r0 = b * id, r1 = r0;
+#pragma unroll
+            for (int a = 0; a < PD_NHIST; ++a) {
+              r0 -= w0[a] * y[a];
+              r1 -= w1[a] * y[a];
+            }
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < PD_NHIST; ++a) {
+#pragma unroll
+              for (int c = a; c < PD_NHIST; ++c) acc[t++] += z[a] * z[c];
+              acc[10 + a] += z[a] * r0;
+              acc[10 + PD_NHIST + a] += z[a] * r1;
+            }
+            acc[18] += r0 * r0;
+            acc[19] += r1 * r1;
+          });
+#pragma unroll
+    for (int a = 0; a < PD_NHIST; ++a) acc[20 + a] = S0[a];
+    produce<PD_NGRAM>(acc, I.part_g, I.nb_sten, mp.y);
+  } else if (MODE == SM_BEGIN) {
+    // FP64 operator on n^k .. n^{k-3} (levels the guess does not use alias
+    // n^k and carry zero weight).  Every block solves the same small
+    // problem of the guess from the Gram pass's partials; block 0 records
+    // the weights for the origin row.
+    const double inv_dt = sc->inv_dt, th = sc->theta;
+    const int ne = sc->ex_n;
+    double w0[PD_NHIST];
+    int kind;
+    {
+      double tg[PD_NGRAM];
+      consume<PD_NGRAM>(I.part_g, I.nb_sten, tg);
+      kind = begin_guess(I, sc, tg, w0);
+    }
+    if (mp.y == 0 && threadIdx.x == 0) {
+      sc->guess_kind = kind;
+      for (int a = 0; a < PD_NHIST; ++a) sc->guess_w[a] = w0[a];
     }
     const double *xk0 = I.sol[sol_slot(sc->rot, 0)];
     const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
@@ -1206,7 +1404,7 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     double cq[PD_MAXSRC];
     for (int q = 0; q < PD_MAXSRC; ++q) cq[q] = sc->cq[q];
     const int nsrc = I.nsrc, npad = I.npad;
-    double acc[PD_NBEGIN] = {};   // ||D^-1 b||², selected and other ||D^-1 r||², S0 per level
+    double acc[PD_NBEGIN] = {};   // ||D^-1 b||², ||D^-1 r||², S0 per level
     double S0[PD_NHIST] = {};
     const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb);
     GAS double *bv = G(I.bvec), *xo = G(x0);
@@ -1226,18 +1424,15 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
               for (int q = 0; q < nsrc; ++q) Nm += cq[q] * nbv[q * n + j];
               b += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
             }
-            double xg = 0.0, Lg = 0.0, xo2 = 0.0, Lo = 0.0;
+            double xg = 0.0, Lg = 0.0;
 #pragma unroll
             for (int a = 0; a < PD_NHIST; ++a) {
               xg += w0[a] * xc[a];
               Lg += w0[a] * Lx[a];
-              xo2 += w1[a] * xc[a];
-              Lo += w1[a] * Lx[a];
             }
             const double r = b - (inv_dt * xg + th * Lg);
             const double id = 1.0 / diag_of(inv_dt, th, ld);
             const double rs = r * id, bs = b * id;
-            const double ro = (b - (inv_dt * xo2 + th * Lo)) * id;
             bv[idx] = b;
             xo[idx] = xg;
             if (mixed) {
@@ -1251,10 +1446,9 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
             }
             acc[0] += bs * bs;
             acc[1] += rs * rs;
-            acc[2] += ro * ro;
           });
 #pragma unroll
-    for (int a = 0; a < PD_NHIST; ++a) acc[3 + a] = S0[a];
+    for (int a = 0; a < PD_NHIST; ++a) acc[2 + a] = S0[a];
     produce<PD_NBEGIN>(acc, I.part_b, I.nb_sten, mp.y);
   } else if (MODE == SM_V || MODE == SM_T) {
     const double inv_dt = sc->inv_dt, th = sc->theta;
@@ -1616,8 +1810,6 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
         sc->inner_first = 1;
         sc->inner_iters = 0;
         sc->rout0[0] = O.r;
-        // the candidate for the next level: the one with the smaller residual here
-        if (sc->ex_n == PD_NHIST - 1 && O.rr_other < O.rr) sc->ex_next = 1 - sc->ex_sel;
       }
       rho = O.rr;
       first = true;
@@ -2222,6 +2414,8 @@ void launch_factor(const LaunchSet &L, hipStream_t s) {
     PD_DISPATCH_BM(L.max_bang, (go(KF_FACTOR, k_fact_ang<BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang)));
 }
 void launch_begin(const LaunchSet &L, hipStream_t s) {
+  go(KF_BEGIN, k_sten<double, SM_GRAM>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
+     (const double *)nullptr, (double *)nullptr);
   go(KF_BEGIN, k_sten<double, SM_BEGIN>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
      (const double *)nullptr, (double *)nullptr);
 }
