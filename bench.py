@@ -30,6 +30,9 @@ from problems.workloads import CFG2, CFG2_SEEDS as SEEDS, CFG2_THETAS as THETAS,
 
 M, N_TH, P_STRETCH, T_END, K_LEVELS, L_TIME = (CFG2[k] for k in ("m", "n", "p", "T", "K", "l"))
 HBM_PEAK_GBS = 8000.0
+TUNE_LEVELS = 10         # levels the schedule autotuner times each candidate on (the
+                         # benchmark batch itself is tuned on whole solves)
+ADAPTIVE_CPG = (2, 4, 6)  # cycles per graph tried for the adaptive-step variant
 
 # Algorithmic bytes per unknown of one launch (w: storage bytes of the
 # Krylov data; the sweeps' factors are FP32): what the kernel must read and
@@ -117,7 +120,7 @@ def precision_variant(pdk, stream, tol):
         td = pdk.time_desc(c["theta"], c["K"], c["dt"] * c["K"], pdk.TIME_UNIFORM, tol=t)
         if tune:
             from paper_2509_15879_amd import autotune
-            sched.append(autotune.tune([inst], [td], levels=3, sync=torch.cuda.synchronize)["best"])
+            sched.append(autotune.tune([inst], [td], levels=TUNE_LEVELS, sync=torch.cuda.synchronize)["best"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = inst.solve(td)
@@ -182,7 +185,7 @@ def uneven_variant(pdk, stream, tol, sample_alone=32):
         i.close()
     insts = make(pdk.PD_MIXED)
     u0s = [pdk.ring_vector(d["u0_origin"], d["u0_grid"]) for d in datas]
-    tuned = autotune.tune(insts, tds, levels=3, sync=torch.cuda.synchronize)
+    tuned = autotune.tune(insts, tds, levels=TUNE_LEVELS, sync=torch.cuda.synchronize)
     for inst, u0 in zip(insts, u0s):
         inst.set_solution(u0, 0.0)
     torch.cuda.synchronize()
@@ -198,7 +201,7 @@ def uneven_variant(pdk, stream, tol, sample_alone=32):
                      "half drift-diffusion, theta U[0.5,1], dt=5e-4 fixed, 100 levels"),
         "cells": cells,
         "mixed_batched": {"value": round(cells * c["K"] / el, 1), "ms": round(1e3 * el, 1),
-                          "schedule": list(tuned["best"]), "autotune_ms_first_3_levels": tuned["ms"],
+                          "schedule": list(tuned["best"]), "autotune_ms_first_levels": tuned["ms"],
                           "l2_rel_vs_fp64_converged_max": max(errs),
                           "inner_iters_per_level_mean": round(float(np.mean(
                               [np.mean([s["iters"] for s in x]) for x in st])), 2)},
@@ -216,8 +219,22 @@ def adaptive_variant(pdk, stream, tol, tol_time=1e-6):
     insts, tds, u0s = build_instances(pdk, pdk.PD_FP64, stream)
     cells = [i.N for i in insts]
     descs = [pdk.adaptive_time_desc(th, T_END, 1e-5, tol_time, 1e-5, 1e-3, tol=tol) for th, _ in tds]
-    reset(insts, u0s)
-    pdk.solve_batch(insts, descs)                       # warm-up (plans, graphs)
+    # schedule: adaptive steps take few iterations, and a level can only
+    # start at a round head, so the round length is chosen on whole solves
+    # (the first of each pair warms the plans and graphs up)
+    groups = pdk.get_schedule()["groups"]
+    tried = {}
+    for cpg in ADAPTIVE_CPG:
+        pdk.set_schedule(groups, cpg)
+        for rep in range(2):
+            reset(insts, u0s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pdk.solve_batch(insts, descs)
+            torch.cuda.synchronize()
+        tried[cpg] = time.perf_counter() - t0
+    best = min(tried, key=tried.get)
+    pdk.set_schedule(groups, best)
     reset(insts, u0s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -238,6 +255,7 @@ def adaptive_variant(pdk, stream, tol, tol_time=1e-6):
     upd = sum(c * len(st) for c, st in zip(cells, steps))
     return {"workload": "benchmark batch, adaptive dt in [1e-5, 1e-3] from 1e-5, local error tol "
                         f"{tol_time:g}, FP64, T=0.05",
+            "schedule": [groups, best], "round_length_ms": {str(k): round(1e3 * v, 1) for k, v in tried.items()},
             "steps_per_instance": [len(st) for st in steps],
             "rejected": sum(s["rejected"] for st in steps for s in st),
             "ms": round(1e3 * el, 1), "value": round(upd / el, 1),
@@ -431,7 +449,7 @@ def main():
     # autotuner on the first levels of this batch, outside the timed region
     from paper_2509_15879_amd import autotune
     reset(insts, u0s)
-    tuned = autotune.tune(insts, descs, levels=3, sync=torch.cuda.synchronize)
+    tuned = autotune.tune(insts, descs, levels=K_LEVELS, repeats=1, sync=torch.cuda.synchronize)
     log(f"schedule {tuned['best']} from {tuned['ms']}")
     for w in range(args.warmup):
         reset(insts, u0s)
@@ -513,7 +531,7 @@ def main():
             "parallelism": "single GPU, batched instances",
             "schedule": {"groups": tuned["best"][0], "cycles_per_graph": tuned["best"][1],
                          "fp32_stencil_rings": tuned["best"][2],
-                         "autotune_ms_first_3_levels": tuned["ms"]},
+                         "autotune_ms_first_levels": tuned["ms"]},
         },
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
@@ -541,7 +559,7 @@ def main():
             mix, _, _ = build_instances(pdk, pdk.PD_MIXED, stream)
             mdesc = time_descs(pdk, tds, args.tol)
             reset(mix, u0s)
-            mtuned = autotune.tune(mix, mdesc, levels=3, sync=torch.cuda.synchronize)
+            mtuned = autotune.tune(mix, mdesc, levels=K_LEVELS, repeats=1, sync=torch.cuda.synchronize)
             reset(mix, u0s)
             pdk.solve_batch(mix, mdesc)
             reset(mix, u0s)

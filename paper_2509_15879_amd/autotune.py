@@ -17,7 +17,10 @@ from typing import Dict, List, Sequence, Tuple
 
 from . import polardisk as pdk
 
-DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 2), (2, 2), (3, 2), (2, 4), (3, 4), (1, 4))
+# (stream groups, cycles per graph).  Longer rounds pay for their idle
+# cycles (an instance that converges waits for the next round head) by
+# running the round head, which costs about one cycle, less often.
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((g, c) for g in (1, 2, 3) for c in (4, 8, 12))
 FP32_RINGS: Tuple[int, ...] = (4, 8)
 
 _cache: Dict[tuple, dict] = {}

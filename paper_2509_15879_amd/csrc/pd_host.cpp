@@ -1842,6 +1842,7 @@ void retire_request(pd_batch *B, Request *R, int rc, int levels) {
 
 // Cycles the loop runs between looks at its queue and its finished requests.
 constexpr long kServeSlice = 8;
+constexpr int kServeRound = 4;   // most Krylov cycles per round in the serving loop
 
 void serve(pd_batch *B) {
   (void)hipSetDevice(B->device);
@@ -1892,7 +1893,11 @@ void serve(pd_batch *B) {
         insts.push_back(R->inst);
         cap = std::max(cap, cycles_cap(R->sp));
       }
-      rc = E.build(insts, cap, B->stream, default_schedule());
+      // short rounds: a request's level can only start at a round head, and
+      // a slice of the loop is at least one round
+      Schedule sch = default_schedule();
+      sch.cycles_per_graph = std::min(sch.cycles_per_graph, kServeRound);
+      rc = E.build(insts, cap, B->stream, sch);
       dirty = false;
       std::lock_guard<std::mutex> lk(B->mu);
       B->info.plans_built += 1;
