@@ -48,8 +48,8 @@ KERNEL_NAMES = {
 # WRITE_SIZE counters, calibrated on a copy of known size), valid for the
 # sources with this SHA-1 only (kernel_source_sha1); any other source
 # reports traffic null.
-TRAFFIC_SOURCE_SHA1 = "69646537a4b9777d296faa7a93e258c3db06c8c0"
-TRAFFIC_B_PER_CELL = {"rad_p": 53.87, "ang_p": 32.47, "sten_v": 64.68, "rad_s": 44.20, "ang_s": 32.46, "sten_t": 64.64, "update": 64.51}
+TRAFFIC_SOURCE_SHA1 = "88f33aac31882ab2565aea56d64dafcb381cd153"
+TRAFFIC_B_PER_CELL = {"rad_p": 54.71, "ang_p": 32.48, "sten_v": 65.01, "rad_s": 44.21, "ang_s": 32.47, "sten_t": 64.78, "update": 64.53}
 
 
 def kernel_source_sha1():

@@ -1601,7 +1601,7 @@ enum { RM_P = 0, RM_S = 1, RM_PLAIN = 2 };
 template <typename C, int BM>
 struct RadRegs {
   C a[BM], b[BM];               // P: r, p - ω v   S: r, v
-  C u[BM], f[BM], g[BM];        // pivot inverse and multipliers
+  float u[BM], f[BM], g[BM];    // pivot inverse and multipliers, as stored (converted at use)
 };
 
 template <typename T, int MODE, int BM>
@@ -1618,8 +1618,8 @@ __device__ __forceinline__ void rad_load(int n, int j, int rb, int klast, double
     R.a[k] = a[idx];
     if (MODE == RM_P) R.b[k] = b[idx] - om * c[idx];
     if (MODE == RM_S) R.b[k] = b[idx];
-    R.u[k] = (T)uinv[idx];
-    R.f[k] = (T)f[idx];
+    R.u[k] = uinv[idx];
+    R.f[k] = f[idx];
   }
 }
 
@@ -1630,7 +1630,7 @@ template <typename C, int BM>
 __device__ __forceinline__ void rad_load_g(int n, int j, int rb, int klast,
                                            const GAS float *__restrict__ g, RadRegs<C, BM> &R) {
 #pragma unroll
-  for (int k = 0; k < BM; ++k) R.g[k] = (C)g[(rb + min(k, klast)) * n + j];
+  for (int k = 0; k < BM; ++k) R.g[k] = g[(rb + min(k, klast)) * n + j];
 }
 
 // Joins of the segments of a block's columns (NW waves, 4 segments of the
@@ -1717,15 +1717,15 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
         s[idx] = ys;
       }
     }
-    wl[k] = k < cnt ? R.u[k] * ys : (T)0;
-    if (k >= cnt) R.f[k] = (T)0;  // the forward fix-up then leaves such rows alone
+    wl[k] = k < cnt ? (T)R.u[k] * ys : (T)0;
+    if (k >= cnt) R.f[k] = 0.0f;  // the forward fix-up then leaves such rows alone
   }
   AffT<T> A{(T)1, (T)0};
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     if (k < cnt) {
-      A.e = wl[k] - R.f[k] * A.e;
-      A.P *= -R.f[k];
+      A.e = wl[k] - (T)R.f[k] * A.e;
+      A.P *= -(T)R.f[k];
       wl[k] = A.e;
     }
   }
@@ -1733,15 +1733,15 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
   T P = (T)1;
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
-    P *= -R.f[k];
+    P *= -(T)R.f[k];
     wl[k] += P * Win;
   }
   AffT<T> Bk{(T)1, (T)0};
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      Bk.e = wl[k] - R.g[k] * Bk.e;
-      Bk.P *= -R.g[k];
+      Bk.e = wl[k] - (T)R.g[k] * Bk.e;
+      Bk.P *= -(T)R.g[k];
       wl[k] = Bk.e;
     }
   }
@@ -1750,7 +1750,7 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
     if (k < cnt) {
-      Q *= -R.g[k];
+      Q *= -(T)R.g[k];
       out[(i_begin + k) * n + j] = wl[k] + Q * Xin;
     }
   }
