@@ -16,7 +16,8 @@
 //   k_level_begin   per-instance set-up: Δt, θ, source weights, extrapolation
 //   k_fact_rad      radial-line LU of (I + D^{-1}R) per θ-column (when Δt/θ change)
 //   k_fact_ang      ring-periodic LU of (I + D^{-1}Θ) per ring, Sherman-Morrison
-//   k_sten<BEGIN>   rhs, extrapolated initial guess and its residual
+//   k_sten<GRAM>    the least-squares problem of the initial guess (partial sums)
+//   k_sten<BEGIN>   rhs, initial guess (extrapolation, corrected by least squares) and its residual
 //   BiCGSTAB cycles k_rad -> k_ang -> k_sten<V> -> k_rad -> k_ang -> k_sten<T> -> k_elem_x
 //   (mixed precision: k_sten<UR> refines in FP64 between FP32 inner solves)
 //   k_level_end
@@ -28,8 +29,10 @@
 // product
 //   M = (I + D^{-1}R)(I + D^{-1}Θ),  M^{-1} y = (I + D^{-1}Θ)^{-1} (I + D^{-1}R)^{-1} y,
 // with R the radial (same-column) couplings and Θ the angular (same-ring,
-// periodic) couplings of A; the origin row is left as is (unit diagonal).
-// The radial blocks are the tridiagonal A_j of (2.12).
+// periodic) couplings of A.  Θ also holds the origin row and ring 1's
+// couplings to the origin, so that ring 1 and the origin are solved as one
+// arrow system (the radial sweep passes the origin through).  The radial
+// blocks are the tridiagonal A_j of (2.12).
 //
 // Both tridiagonal families are solved by segmented scans: a thread owns a
 // contiguous segment of a line, substitutes locally in registers, and the
@@ -233,9 +236,10 @@ __device__ void guess_weights(const double *tt, int k, int ne, double theta, dou
 }
 
 // Sets up level sc->level of an instance, t_k -> t_{k+1}: Δt, θ, the
-// source weights, the initial guesses' weights (the candidate with the
-// smaller residual at the previous level's begin is taken); its
-// factorisation (when Δt or θ changed) and right-hand side are then due.
+// source weights, the weights of both polynomial candidate guesses (the
+// level-begin passes choose between them and correct the choice); its
+// factorisation (when θ changed or Δt moved enough) and right-hand side
+// are then due.
 __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   const int k = sc->level;
   const double t0 = I.t_table[k], t1 = I.t_table[k + 1];
