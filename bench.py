@@ -48,8 +48,8 @@ KERNEL_NAMES = {
 # WRITE_SIZE counters, calibrated on a copy of known size), valid for the
 # sources with this SHA-1 only (kernel_source_sha1); any other source
 # reports traffic null.
-TRAFFIC_SOURCE_SHA1 = "fa4f553054bf6ab6cdf1a563e06e250683484df7"
-TRAFFIC_B_PER_CELL = {"rad_p": 54.71, "ang_p": 32.48, "sten_v": 65.01, "rad_s": 44.21, "ang_s": 32.47, "sten_t": 64.78, "update": 64.53}
+TRAFFIC_SOURCE_SHA1 = "418ca1ac8737f19c30c2a12998e641d8b4ffa273"
+TRAFFIC_B_PER_CELL = {"rad_p": 54.72, "ang_p": 32.48, "sten_v": 64.84, "rad_s": 44.21, "ang_s": 32.47, "sten_t": 64.73, "update": 64.53}
 
 
 def kernel_source_sha1():

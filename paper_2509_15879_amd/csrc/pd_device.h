@@ -45,8 +45,6 @@ enum { PEND_UPDATE = 0, PEND_BEGIN = 1, PEND_REFINE = 2 };
 // due (START), or it is iterating (ITER).
 enum { STAGE_ITER = 0, STAGE_START = 1 };
 
-// Counter slots (per instance; kept for the layout of older tools).
-enum { CNT_BEGIN = 0, CNT_V = 1, CNT_T = 2, CNT_X = 3, CNT_UR = 4, CNT_APPLY = 5, CNT_N = 8 };
 
 struct PdScalars {
   // time level
@@ -130,11 +128,10 @@ struct PdInst {
   double *af_sigma;         // [1] σ (1, with q = c̃ = 0, when the arrow is not used)
   KSet<double> k64;
   KSet<float> k32;
-  double *partials;         // per-block partial sums, one region per producer:
+  // per-block partial sums, one region per producer
   double *part_b, *part_v, *part_t, *part_ur, *part_a;   // [slots * nb_sten]
   double *part_x;                                        // [2 * nb_elem]
   double *part_g;                                        // [PD_NGRAM * nb_sten]
-  unsigned *counters;       // [CNT_N]
   PdScalars *sc;
   int *n_active;            // shared counter of the batch (device)
   int *lvl_out;             // (levels done, status) written at each level end

@@ -300,8 +300,6 @@ void carve(pd_instance *I, Carver &c) {
   H.part_a = c.take<double>(1 * (size_t)nbs);
   H.part_e = c.take<double>(3 * (size_t)nbs);
   H.part_x = c.take<double>(2 * (size_t)I->T.nb_elem);
-  H.partials = H.part_b;
-  H.counters = c.take<unsigned>(CNT_N);
   I->sc = c.take<PdScalars>(1);
   H.sc = I->sc;
 }
@@ -652,7 +650,6 @@ int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   h.dt_max = sp.dt_max;
   h.tol_time = sp.tol_time;
   HIPCHK(hipMemcpyAsync(I->sc, &h, sizeof h, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));
   // levels never taken read as not done
   if (I->stats) HIPCHK(hipMemsetAsync(I->stats, 0, PD_LSTAT * (size_t)K * sizeof(double), s));
   return PD_OK;
@@ -1463,7 +1460,6 @@ int pd_apply_operator(pd_instance *I, double dt, double theta, const double *x, 
   }
   Plan P;
   if ((rc = make_plan({I}, s, P))) return rc;
-  HIPCHK(hipMemsetAsync(I->H.counters, 0, CNT_N * sizeof(unsigned), s));
   pd::launch_apply(P.L, dt, theta, dx, dy, precision == 1, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

@@ -1596,9 +1596,8 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
 //
 // RM_P:  y = p = r + β (p - ω v)   (p = r on a (re)start; r̂ = r on a restart)
 // RM_S:  y = s = r - α v
-// RM_PLAIN: y = x (diagnostic)
 
-enum { RM_P = 0, RM_S = 1, RM_PLAIN = 2 };
+enum { RM_P = 0, RM_S = 1 };
 
 // C: the sweep's arithmetic type, its storage type T (FP64, or FP32 for the
 // inner solve of mixed precision).
@@ -1677,8 +1676,7 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
                                           double alpha, bool first, bool reset, RadRegs<T, BM> &R,
                                           const GAS T *__restrict__ r, GAS T *__restrict__ p,
                                           const GAS T *__restrict__ v, GAS T *__restrict__ rh,
-                                          GAS T *__restrict__ s, const GAS T *__restrict__ pin,
-                                          GAS T *__restrict__ out) {
+                                          GAS T *__restrict__ s, GAS T *__restrict__ out) {
   constexpr int NW = NT / 64;
   __shared__ T lp[NW][16], le[NW][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1697,12 +1695,10 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
       p[o] = ps;
       if (reset) rh[o] = r[o];
       out[o] = ps;
-    } else if (MODE == RM_S) {
+    } else {
       const T ss = input(r[o], v[o]);
       s[o] = ss;
       out[o] = ss;
-    } else {
-      out[o] = pin[o];
     }
   }
 
@@ -1763,15 +1759,12 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
 // NT threads per block (512 or 1024): 16 columns x NT/16 segments; at most
 // 128 VGPRs, so that two 512-thread blocks share a CU.
 template <typename T, int MODE, int BM, int NT>
-__global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *map,
-                                                      const T *plain_in, T *plain_out) {
+__global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
-  if (MODE != RM_PLAIN) {
-    if (!prec_match<T>(I)) return;
-    if (block_status(sc) != ST_ACTIVE) return;   // the p- and s-sweeps change the status
-  }
+  if (!prec_match<T>(I)) return;
+  if (block_status(sc) != ST_ACTIVE) return;   // the p- and s-sweeps change the status
   const KSet<T> &KS = kset<T>(I);
   constexpr int cw = 16, NSEG = NT / 16;
   const int m = I.m, n = I.n, orig = m * n, B = (m + NSEG - 1) / NSEG;
@@ -1785,7 +1778,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   const int rb = cnt > 0 ? seg * B : 0, klast = cnt > 0 ? cnt - 1 : 0;
   RadRegs<T, BM> R;
   auto load = [&]() {
-    const T *a = (MODE == RM_PLAIN) ? plain_in : KS.r;
+    const T *a = KS.r;
     const T *bb = (MODE == RM_P) ? KS.p : KS.v;
     rad_load<T, MODE, BM>(n, jj, rb, klast, sc->omega, G(a), G((const T *)bb), G((const T *)KS.v),
                           G((const float *)I.rf_uinv), G((const float *)I.rf_f), R);
@@ -1900,10 +1893,8 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   }
   if (pend != PEND_UPDATE) load();
   rad_load_g<T, BM>(n, jj, rb, klast, G((const float *)I.rf_g), R);
-  T *out = (MODE == RM_PLAIN) ? plain_out : KS.w;
   rad_solve<T, MODE, BM, NT>(m, n, jj, c, seg * B, cnt, b0, beta, omega, alpha, first, reset, R,
-                         G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s),
-                         G(plain_in), G(out));
+                         G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s), G(KS.w));
 }
 
 // ------------------------------------------------------------ angular sweep
@@ -1915,10 +1906,12 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
 // and read directly.  Local substitution in registers, then the lanes' affine
 // maps are composed by a Kogge-Stone scan across the wave (prefix for the
 // forward, suffix for the backward substitution), then the Sherman-Morrison
-// correction closes the period.
+// correction closes the period.  Ring 1's wave then closes the origin row
+// of the arrow system (ring 1 with the origin): z_0 = (w_0 - c̃·u)/σ and
+// z_1 = u - q z_0, from the vectors and scalar its factorisation stored.
 //
-// AM_P: input w, output p̂ (origin copied);  AM_S: output ŝ;  AM_PLAIN: diagnostic.
-enum { AM_P = 0, AM_S = 1, AM_PLAIN = 2 };
+// AM_P: input w, output p̂;  AM_S: output ŝ (ring 1's wave also closes the origin).
+enum { AM_P = 0, AM_S = 1 };
 
 // Orders the LDS accesses of one wave (its lanes exchange values through LDS).
 __device__ __forceinline__ void wave_sync() {
@@ -2077,12 +2070,11 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
 }
 
 template <typename T, int MODE, int BM>
-__global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *map,
-                                             const T *plain_in, T *plain_out) {
+__global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
-  if (MODE != AM_PLAIN && (!inner_active(sc) || !prec_match<T>(I))) return;
+  if (!inner_active(sc) || !prec_match<T>(I)) return;
   const KSet<T> &KS = kset<T>(I);
   const int m = I.m, n = I.n;
   const int lane = threadIdx.x & 63;
@@ -2100,8 +2092,8 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
   if (i > m) return;                                 // whole wave exits together
   __shared__ T tbuf[4][64 * (BM + 1)];               // one exchange buffer per wave
   __shared__ float abuf[2 * 64 * BM];                // ring 1's arrow vectors (its wave only)
-  const T *in = (MODE == AM_PLAIN) ? plain_in : KS.w;
-  T *out = (MODE == AM_PLAIN) ? plain_out : ((MODE == AM_P) ? KS.ph : KS.sh);
+  const T *in = KS.w;
+  T *out = (MODE == AM_P) ? KS.ph : KS.sh;
   ang_body<T, BM>(m, n, I.bang, i, lane, I.af_kappa[i - 1], I.af_alpha0[i - 1], G(in), G(out),
                   G((const float *)I.af_uinv), G((const float *)I.af_f), G((const float *)I.af_g),
                   G((const float *)I.af_z), G((const float *)I.af_q), G((const float *)I.af_c),
@@ -2425,18 +2417,18 @@ void launch_begin(const LaunchSet &L, hipStream_t s) {
 }
 
 template <typename T, int MODE>
-static void rad(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
+static void rad(const LaunchSet &L, hipStream_t s) {
   const int fam = MODE == RM_S ? KF_RAD_S : KF_RAD_P;
   if (L.nb_rs[0]) {
-    PD_DISPATCH_BM(L.max_brs[0], (go(fam, k_rad<T, MODE, BM, 512>, g1(L.nb_rs[0]), dim3(512), s, L.insts, L.map_rs[0], in, out)));
+    PD_DISPATCH_BM(L.max_brs[0], (go(fam, k_rad<T, MODE, BM, 512>, g1(L.nb_rs[0]), dim3(512), s, L.insts, L.map_rs[0])));
   }
   if (L.nb_rs[1]) {
-    PD_DISPATCH_BM(L.max_brs[1], (go(fam, k_rad<T, MODE, BM, 1024>, g1(L.nb_rs[1]), dim3(1024), s, L.insts, L.map_rs[1], in, out)));
+    PD_DISPATCH_BM(L.max_brs[1], (go(fam, k_rad<T, MODE, BM, 1024>, g1(L.nb_rs[1]), dim3(1024), s, L.insts, L.map_rs[1])));
   }
 }
 template <typename T, int MODE>
-static void ang(const LaunchSet &L, hipStream_t s, const T *in = nullptr, T *out = nullptr) {
-  PD_DISPATCH_BM(L.max_bang, (go(MODE == AM_S ? KF_ANG_S : KF_ANG_P, k_ang<T, MODE, BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang, in, out)));
+static void ang(const LaunchSet &L, hipStream_t s) {
+  PD_DISPATCH_BM(L.max_bang, (go(MODE == AM_S ? KF_ANG_S : KF_ANG_P, k_ang<T, MODE, BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang)));
 }
 template <typename T, int MODE>
 static void sten(int fam, const LaunchSet &L, hipStream_t s) {
@@ -2516,12 +2508,6 @@ void launch_transfer(const double *x, int m, int n, const double *r, const doubl
   const int cnt = m2 * n2;
   go(KF_CONTROL, k_transfer, dim3((cnt + 255) / 256), dim3(256), s, x, m, n, r, th, nb, lam, tpow, nsrc, t,
      dirichlet, r2, th2, m2, n2, y);
-}
-
-void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,
-                          hipStream_t s) {
-  rad<double, RM_PLAIN>(L, s, x, tmp);
-  ang<double, AM_PLAIN>(L, s, tmp, y);
 }
 
 }  // namespace pd

@@ -55,7 +55,5 @@ void launch_indicator(const double *x, int m, int n, const double *r, const doub
 void launch_transfer(const double *x, int m, int n, const double *r, const double *th, const double *nb,
                      const double *lam, const int *tpow, int nsrc, double t, int dirichlet,
                      const double *r2, const double *th2, int m2, int n2, double *y, hipStream_t s);
-void launch_precond_plain(const LaunchSet &L, const double *x, double *tmp, double *y,
-                          hipStream_t s);
 
 }  // namespace pd
