@@ -350,8 +350,10 @@ int pd_batch_destroy(pd_batch *batch);
  * first, each to the part with the fewest), each stepping on its own stream
  * (the instances' stream and library-owned streams of default priority), so
  * that the parts' launches overlap; results do not depend on it.
- * cycles_per_graph: Krylov cycles per captured HIP graph (a part's
- * active-instance count is read back after each graph).
+ * cycles_per_graph: Krylov cycles per captured HIP graph, a round (a part's
+ * active-instance count is read back after each round).  An instance can
+ * only start a level at a round head, so rounds about as long as a level's
+ * iterations suit batch solves; the serving loop caps them at 4 cycles.
  * fp32_stencil_rings: rings per wave of the stencil tiles of FP32 (mixed)
  * instances, 4 or 8 (0 = 4); deeper tiles halve the waves and suit large
  * batches.  FP64 instances always take 4.  It changes the summation order
