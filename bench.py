@@ -52,22 +52,29 @@ TRAFFIC_SOURCE_SHA1 = "418ca1ac8737f19c30c2a12998e641d8b4ffa273"
 TRAFFIC_B_PER_CELL = {"rad_p": 54.72, "ang_p": 32.48, "sten_v": 64.84, "rad_s": 44.21, "ang_s": 32.47, "sten_t": 64.73, "update": 64.53}
 
 
-def kernel_source_sha1():
-    """SHA-1 of the kernels' source and of the host runtime that lays out
-    their launches (the block maps decide which tiles share an L2), with
-    comments and blank lines removed: an edit of the comments leaves the
-    measured traffic valid, any change of the code voids it."""
+def code_digest(texts):
+    """SHA-1 of C++/HIP sources with comments and blank lines removed."""
     import hashlib
     import re
     h = hashlib.sha1()
-    for name in ("pd_kernels.hip", "pd_host.cpp"):
-        with open(os.path.join(ROOT, "paper_2509_15879_amd", "csrc", name), encoding="utf-8") as f:
-            src = f.read()
+    for src in texts:
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"//[^\n]*", "", src)
         code = "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
         h.update(code.encode("utf-8"))
     return h.hexdigest()
+
+
+def kernel_source_sha1():
+    """Digest of the kernels' source and of the host runtime that lays out
+    their launches (the block maps decide which tiles share an L2), without
+    comments and blank lines: an edit of the comments leaves the measured
+    traffic valid, any change of the code voids it."""
+    texts = []
+    for name in ("pd_kernels.hip", "pd_host.cpp"):
+        with open(os.path.join(ROOT, "paper_2509_15879_amd", "csrc", name), encoding="utf-8") as f:
+            texts.append(f.read())
+    return code_digest(texts)
 
 
 def bytes_per_cell(family, w):
