@@ -44,6 +44,6 @@ def test_traffic_table_covers_every_cycle_kernel():
 def test_algorithmic_bytes_of_one_iteration():
     # FP64: two radial sweeps, two ring sweeps, two stencils and the update
     fams = ["rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t", "update"]
-    assert sum(bench.bytes_per_cell(f, 8) for f in fams) == 344
+    assert sum(bench.bytes_per_cell(f, 8) for f in fams) == 336
     # FP32 inner iteration (the stencils also read their FP32 1/diag copy)
     assert sum(bench.bytes_per_cell(f, 4) for f in fams) == 204
