@@ -104,17 +104,26 @@ __device__ __forceinline__ void produce(double (&v)[NS], double *part, int nblk,
 
 // Total of a producer's partials: wave 0 sums them in a fixed order (lane
 // strided, then a butterfly) and the block shares the result.  Every thread
-// of the block must call it.
+// of the block must call it.  All slots advance together and the strided
+// loop is unrolled, so that many loads are in flight at once (a large
+// instance leaves thousands of partials per slot); each slot is still summed
+// in ascending block order.
 template <int NS>
 __device__ __forceinline__ void consume(const double *part, int nblk, double (&tot)[NS]) {
   __shared__ double sh[NS];
   if (threadIdx.x < 64) {
+    double sum[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) sum[k] = 0.0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nblk; b += 64) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) sum[k] += part[k * nblk + b];
+    }
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      double sum = 0.0;
-      for (int b = threadIdx.x; b < nblk; b += 64) sum += part[k * nblk + b];
-      sum = wave_sum(sum);
-      if (threadIdx.x == 0) sh[k] = sum;
+      const double v = wave_sum(sum[k]);
+      if (threadIdx.x == 0) sh[k] = v;
     }
   }
   __syncthreads();
@@ -380,12 +389,16 @@ __global__ void k_ctl(PdInst *insts, int ninst) {
   PdInst &I = insts[q];
   PdScalars *sc = I.sc;
   const int orig = I.m * I.n;
+  // each slot in ascending block order; the slots advance together and the
+  // loop is unrolled, so that many loads are in flight
   auto level_end_sums = [&](double (&tot)[3]) {
-    for (int c = 0; c < 3; ++c) {
-      double sum = 0.0;
-      for (int b = 0; b < I.nb_sten; ++b) sum += I.part_e[c * I.nb_sten + b];
-      tot[c] = sum;
+    double sum[3] = {0.0, 0.0, 0.0};
+#pragma unroll 8
+    for (int b = 0; b < I.nb_sten; ++b) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sum[c] += I.part_e[c * I.nb_sten + b];
     }
+    for (int c = 0; c < 3; ++c) tot[c] = sum[c];
   };
   if (sc->adaptive && sc->need_f0) {
     // f(t_0, x_0): the ring part was formed by the level-end pass
@@ -1572,10 +1585,12 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
   if (q >= ninst) return;
   const PdInst &I = insts[q];
   double tot[PD_NBEGIN];
-  for (int k = 0; k < PD_NBEGIN; ++k) {
-    double sum = 0.0;
-    for (int b = 0; b < I.nb_sten; ++b) sum += I.part_b[k * I.nb_sten + b];
-    tot[k] = sum;
+#pragma unroll
+  for (int k = 0; k < PD_NBEGIN; ++k) tot[k] = 0.0;
+#pragma unroll 4
+  for (int b = 0; b < I.nb_sten; ++b) {
+#pragma unroll
+    for (int k = 0; k < PD_NBEGIN; ++k) tot[k] += I.part_b[k * I.nb_sten + b];
   }
   const OriginBegin O = origin_begin(I, I.sc, tot);
   origin_begin_store(I, I.sc, O);
