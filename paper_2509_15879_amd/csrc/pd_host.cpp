@@ -546,10 +546,12 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
   auto rings = [&](const pd_instance *I) { return I->precision == PD_MIXED ? fp32_rings : PD_RB; };
   P.L = pd::LaunchSet{};
   // host side first: the block maps, then one layout for everything
-  std::vector<int2> maps[7];
-  int *counts[7] = {&P.L.nb_sten, &P.L.nb_elem, &P.L.nb_rad, &P.L.nb_rs[0], &P.L.nb_rs[1], &P.L.nb_ang, nullptr};
-  int2 **dsts[7] = {&P.L.map_sten, &P.L.map_elem, &P.L.map_rad, &P.L.map_rs[0], &P.L.map_rs[1], &P.L.map_ang,
-                    nullptr};
+  constexpr int NMAP = 7;
+  std::vector<int2> maps[NMAP];
+  int *counts[NMAP] = {&P.L.nb_sten, &P.L.nb_elem, &P.L.nb_rad, &P.L.nb_rs[0], &P.L.nb_rs[1], &P.L.nb_rs[2],
+                       &P.L.nb_ang};
+  int2 **dsts[NMAP] = {&P.L.map_sten, &P.L.map_elem, &P.L.map_rad, &P.L.map_rs[0], &P.L.map_rs[1], &P.L.map_rs[2],
+                       &P.L.map_ang};
   *counts[0] = build_map(insts, [&](pd_instance *I) { return sten_blocks(I->M.m, I->M.n, rings(I)); }, maps[0]);
   *counts[1] = build_map(insts, [](pd_instance *I) { return I->T.nb_elem; }, maps[1]);
   // radial sweep blocks: neighbouring column blocks share the 128-byte
@@ -558,13 +560,15 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
   // starting a level take part in it, and a contiguous run per XCD would
   // crowd them onto a few XCDs.
   *counts[2] = build_map(insts, [](pd_instance *I) { return I->T.nb_rad; }, maps[2]);
-  for (int c = 0; c < 2; ++c)
+  for (int c = 0; c < 3; ++c)
     *counts[3 + c] =
-        build_map(insts, [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? I->T.nb_rad : 0; }, maps[3 + c]);
-  *counts[5] = build_map(insts, [](pd_instance *I) { return I->T.nb_ang; }, maps[5]);
+        build_map(insts, [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? pd::rad_blocks(I->M.m, I->M.n) : 0; },
+                  maps[3 + c]);
+  *counts[6] = build_map(insts, [](pd_instance *I) { return I->T.nb_ang; }, maps[6]);
   xcd_contiguous(maps[0]);
   xcd_contiguous(maps[3]);
   xcd_contiguous(maps[4]);
+  xcd_contiguous(maps[5]);
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t off = 0;
   const size_t o_act = off;
@@ -573,8 +577,8 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
   off += al(2 * (size_t)ninst * sizeof(int));
   const size_t o_inst = off;
   off += al((size_t)ninst * sizeof(PdInst));
-  size_t o_map[6];
-  for (int k = 0; k < 6; ++k) {
+  size_t o_map[NMAP];
+  for (int k = 0; k < NMAP; ++k) {
     o_map[k] = off;
     off += al(maps[k].size() * sizeof(int2));
   }
@@ -601,7 +605,7 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
     const int c = pd::rad_class(I->M.m);
     P.L.max_brs[c] = std::max(P.L.max_brs[c], pd::rad_rows(I->M.m));
   }
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < NMAP; ++k) {
     *dsts[k] = maps[k].empty() ? nullptr : (int2 *)(P.dbuf + o_map[k]);
     if (!maps[k].empty()) std::memcpy(P.hbuf + o_map[k], maps[k].data(), maps[k].size() * sizeof(int2));
   }

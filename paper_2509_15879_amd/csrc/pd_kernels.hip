@@ -1598,16 +1598,17 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
 
 // ------------------------------------------------------------ radial sweep
 //
-// w = (I + D^{-1}R)^{-1} y for every θ-column of an instance.  A block owns cw
-// (= 16) consecutive columns; its 1024 threads split every column into 64
-// segments of brad rows: thread t takes column t % 16 and segment t / 16, so
-// a wave holds 4 consecutive segments of 16 columns (four 128-byte row
-// pieces per load).  Every operand of a thread's rows is loaded at the start,
-// before the launch's partial sums are read.  Each thread runs the forward
-// and backward substitution of its segment in registers; the segments' affine
-// maps are joined by a scan over the 4 segments of a wave (lane shuffles),
-// then over the 16 waves of the block (wave totals through LDS), and each
-// thread corrects its rows.  The origin row passes through (unit diagonal).
+// w = (I + D^{-1}R)^{-1} y for every θ-column of an instance.  A block owns
+// CW consecutive columns (16, or 8 in the 1024-thread class) and splits every
+// column into NT/CW segments: thread t takes column t % CW and segment
+// t / CW, so a wave holds 64/CW consecutive segments of the block's columns
+// (row pieces of CW values per load).  Every operand of a thread's rows is
+// loaded at the start, before the launch's partial sums are read.  Each
+// thread runs the forward and backward substitution of its segment in
+// registers; the segments' affine maps are joined by a scan over the
+// segments of a wave (lane shuffles), then over the waves of the block
+// (wave totals through LDS), and each thread corrects its rows.  The origin
+// row passes through (unit diagonal).
 //
 // RM_P:  y = p = r + β (p - ω v)   (p = r on a (re)start; r̂ = r on a restart)
 // RM_S:  y = s = r - α v
@@ -1651,26 +1652,28 @@ __device__ __forceinline__ void rad_load_g(int n, int j, int rb, int klast,
   for (int k = 0; k < BM; ++k) R.g[k] = g[(rb + min(k, klast)) * n + j];
 }
 
-// Joins of the segments of a block's columns (NW waves, 4 segments of the
-// 16 columns per wave).  Forward: the value entering segment s from above is
-// the composition of the maps of segments 0..s-1 applied to 0; backward: of
-// the segments below s.  lane/16 is the segment within the wave.
-template <typename C, int NW>
+// Joins of the segments of a block's columns (NW waves; a wave holds
+// 64/CW consecutive segments of the block's CW columns).  Forward: the value
+// entering segment s from above is the composition of the maps of segments
+// 0..s-1 applied to 0; backward: of the segments below s.  lane/CW is the
+// segment within the wave.
+template <typename C, int NW, int CW>
 __device__ __forceinline__ C rad_join(AffT<C> A, bool fwd, int c, int lane, int wave,
-                                      C (&lp)[NW][16], C (&le)[NW][16]) {
-  const int sub = lane >> 4;
-  // inclusive scan over the wave's 4 segments
+                                      C (&lp)[NW][CW], C (&le)[NW][CW]) {
+  constexpr int SPW = 64 / CW;
+  const int sub = lane / CW;
+  // inclusive scan over the wave's segments
 #pragma unroll
-  for (int d = 1; d < 4; d <<= 1) {
-    const AffT<C> o = fwd ? AffT<C>{__shfl_up(A.P, 16 * d, 64), __shfl_up(A.e, 16 * d, 64)}
-                          : AffT<C>{__shfl_down(A.P, 16 * d, 64), __shfl_down(A.e, 16 * d, 64)};
-    if (fwd ? sub >= d : sub + d < 4) A = compose(A, o);
+  for (int d = 1; d < SPW; d <<= 1) {
+    const AffT<C> o = fwd ? AffT<C>{__shfl_up(A.P, CW * d, 64), __shfl_up(A.e, CW * d, 64)}
+                          : AffT<C>{__shfl_down(A.P, CW * d, 64), __shfl_down(A.e, CW * d, 64)};
+    if (fwd ? sub >= d : sub + d < SPW) A = compose(A, o);
   }
   // the part of the wave before (forward) or after (backward) the segment
-  const AffT<C> ex = fwd ? AffT<C>{__shfl_up(A.P, 16, 64), __shfl_up(A.e, 16, 64)}
-                         : AffT<C>{__shfl_down(A.P, 16, 64), __shfl_down(A.e, 16, 64)};
-  const bool edge = fwd ? sub == 0 : sub == 3;
-  if (sub == (fwd ? 3 : 0)) {
+  const AffT<C> ex = fwd ? AffT<C>{__shfl_up(A.P, CW, 64), __shfl_up(A.e, CW, 64)}
+                         : AffT<C>{__shfl_down(A.P, CW, 64), __shfl_down(A.e, CW, 64)};
+  const bool edge = fwd ? sub == 0 : sub == SPW - 1;
+  if (sub == (fwd ? SPW - 1 : 0)) {
     lp[wave][c] = A.P;
     le[wave][c] = A.e;
   }
@@ -1685,7 +1688,7 @@ __device__ __forceinline__ C rad_join(AffT<C> A, bool fwd, int c, int lane, int 
   return edge ? W : ex.P * W + ex.e;
 }
 
-template <typename T, int MODE, int BM, int NT>
+template <typename T, int MODE, int BM, int NT, int CW>
 __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begin, int cnt,
                                           bool origin_thread, double beta, double omega,
                                           double alpha, bool first, bool reset, RadRegs<T, BM> &R,
@@ -1693,7 +1696,7 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
                                           const GAS T *__restrict__ v, GAS T *__restrict__ rh,
                                           GAS T *__restrict__ s, GAS T *__restrict__ out) {
   constexpr int NW = NT / 64;
-  __shared__ T lp[NW][16], le[NW][16];
+  __shared__ T lp[NW][CW], le[NW][CW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   // RM_P: b = p - ω v, so that p = r + β b (in T: FP32 for the inner solve)
@@ -1744,7 +1747,7 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
       wl[k] = A.e;
     }
   }
-  const T Win = rad_join<T, NW>(A, true, c, lane, wave, lp, le);
+  const T Win = rad_join<T, NW, CW>(A, true, c, lane, wave, lp, le);
   T P = (T)1;
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
@@ -1760,7 +1763,7 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
       wl[k] = Bk.e;
     }
   }
-  const T Xin = rad_join<T, NW>(Bk, false, c, lane, wave, lp, le);
+  const T Xin = rad_join<T, NW, CW>(Bk, false, c, lane, wave, lp, le);
   T Q = (T)1;
 #pragma unroll
   for (int k = BM - 1; k >= 0; --k) {
@@ -1771,9 +1774,9 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
   }
 }
 
-// NT threads per block (512 or 1024): 16 columns x NT/16 segments; at most
-// 128 VGPRs, so that two 512-thread blocks share a CU.
-template <typename T, int MODE, int BM, int NT>
+// NT threads per block of CW columns x NT/CW segments (the three classes of
+// rad_class); at most 128 VGPRs, so that two 512-thread blocks share a CU.
+template <typename T, int MODE, int BM, int NT, int CW>
 __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *map) {
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
@@ -1781,7 +1784,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   if (!prec_match<T>(I)) return;
   if (block_status(sc) != ST_ACTIVE) return;   // the p- and s-sweeps change the status
   const KSet<T> &KS = kset<T>(I);
-  constexpr int cw = 16, NSEG = NT / 16;
+  constexpr int cw = CW, NSEG = NT / CW;
   const int m = I.m, n = I.n, orig = m * n, B = (m + NSEG - 1) / NSEG;
   const bool b0 = mp.y == 0 && threadIdx.x == 0;
   // this thread's rows: column j, segment seg (threads without rows read row 0)
@@ -1908,7 +1911,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   }
   if (pend != PEND_UPDATE) load();
   rad_load_g<T, BM>(n, jj, rb, klast, G((const float *)I.rf_g), R);
-  rad_solve<T, MODE, BM, NT>(m, n, jj, c, seg * B, cnt, b0, beta, omega, alpha, first, reset, R,
+  rad_solve<T, MODE, BM, NT, CW>(m, n, jj, c, seg * B, cnt, b0, beta, omega, alpha, first, reset, R,
                          G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s), G(KS.w));
 }
 
@@ -2435,10 +2438,13 @@ template <typename T, int MODE>
 static void rad(const LaunchSet &L, hipStream_t s) {
   const int fam = MODE == RM_S ? KF_RAD_S : KF_RAD_P;
   if (L.nb_rs[0]) {
-    PD_DISPATCH_BM(L.max_brs[0], (go(fam, k_rad<T, MODE, BM, 512>, g1(L.nb_rs[0]), dim3(512), s, L.insts, L.map_rs[0])));
+    PD_DISPATCH_BM(L.max_brs[0], (go(fam, k_rad<T, MODE, BM, 512, 16>, g1(L.nb_rs[0]), dim3(512), s, L.insts, L.map_rs[0])));
   }
   if (L.nb_rs[1]) {
-    PD_DISPATCH_BM(L.max_brs[1], (go(fam, k_rad<T, MODE, BM, 1024>, g1(L.nb_rs[1]), dim3(1024), s, L.insts, L.map_rs[1])));
+    PD_DISPATCH_BM(L.max_brs[1], (go(fam, k_rad<T, MODE, BM, 1024, 16>, g1(L.nb_rs[1]), dim3(1024), s, L.insts, L.map_rs[1])));
+  }
+  if (L.nb_rs[2]) {
+    PD_DISPATCH_BM(L.max_brs[2], (go(fam, k_rad<T, MODE, BM, 1024, 8>, g1(L.nb_rs[2]), dim3(1024), s, L.insts, L.map_rs[2])));
   }
 }
 template <typename T, int MODE>

@@ -17,18 +17,26 @@ struct LaunchSet {
   int adaptive_any = 0;             // some instance steps adaptively (level-end pass in the round head)
   int max_bang = 1;                 // longest angular lane span of the batch
   int max_bfrad = 1;                // longest radial segment of the factorisation
-  // Radial sweeps, two classes by ring count: 512-thread blocks (32 segments
-  // per column) for m <= 256, 1024-thread blocks (64 segments) above.  The
-  // class depends on the instance alone, so its arithmetic does not depend
-  // on the rest of the batch.
-  int2 *map_rs[2] = {nullptr, nullptr};
-  int nb_rs[2] = {0, 0};
-  int max_brs[2] = {1, 1};          // longest radial segment per class
+  // Radial sweeps, three classes by ring count (rad_class).  The class
+  // depends on the instance alone, so its arithmetic does not depend on the
+  // rest of the batch.
+  int2 *map_rs[3] = {nullptr, nullptr, nullptr};
+  int nb_rs[3] = {0, 0, 0};
+  int max_brs[3] = {1, 1, 1};       // longest radial segment per class
 };
 
-// Radial-sweep class of an instance with m rings and the rows per segment.
-inline int rad_class(int m) { return (m + 31) / 32 <= 8 ? 0 : 1; }
-inline int rad_rows(int m) { return rad_class(m) == 0 ? (m + 31) / 32 : (m + 63) / 64; }
+// Radial-sweep classes: 512-thread blocks of 16 columns x 32 segments for
+// m <= 256; 1024-thread blocks of 16 columns x 64 segments for m <= 512;
+// above, 1024-thread blocks of 8 columns x 128 segments, whose segments stay
+// short enough for registers and which give twice the blocks.
+inline int rad_class(int m) { return m <= 256 ? 0 : (m <= 512 ? 1 : 2); }
+inline int rad_threads_of(int c) { return c == 0 ? 512 : 1024; }
+inline int rad_cols_of(int c) { return c == 2 ? 8 : 16; }
+inline int rad_rows(int m) {
+  const int c = rad_class(m), seg = rad_threads_of(c) / rad_cols_of(c);
+  return (m + seg - 1) / seg;
+}
+inline int rad_blocks(int m, int n) { return (n + rad_cols_of(rad_class(m)) - 1) / rad_cols_of(rad_class(m)); }
 
 // Optional per-family event timing of launches (diagnostics).
 struct KTimer {
