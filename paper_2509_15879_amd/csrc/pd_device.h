@@ -93,6 +93,7 @@ struct PdInst {
   int ncg, nrg, nb_sten, nb_elem;    // stencil tiling and block counts
   int cw, nseg, brad, nb_rad;        // radial sweep: columns per block, segments, rows/segment
   int bang, nb_ang, nb_frad, nb_fang;
+  int aw, pad_aw;                    // waves per ring of the ring sweep (1, 2 or 4)
   double inv_V0;
   double l0;                // diagonal of L at the origin: inv_V0 Σ_j gp_r(1/2, j) + b_0 (fixed order)
   const double *inv_rw;     // [m+2] 1/(r_i (h_i+h_{i+1})/2), index i

@@ -147,7 +147,7 @@ int build_mesh(const pd_mesh_desc *d, MeshH &M) {
 // ------------------------------------------------------------------ tiling
 
 struct Tiling {
-  int rb, ncg, nrg, nb_sten, nb_elem, cw, nseg, brad, nb_rad, bang, nb_ang, nb_frad, nb_fang, npad;
+  int rb, ncg, nrg, nb_sten, nb_elem, cw, nseg, brad, nb_rad, bang, aw, nb_ang, nb_frad, nb_fang, npad;
 };
 
 // Stencil blocks of an instance whose waves take `rb` rings each.
@@ -172,7 +172,11 @@ Tiling make_tiling(int m, int n) {
   t.nseg = PD_RAD_THREADS / t.cw;
   t.brad = (m + t.nseg - 1) / t.nseg;
   t.nb_rad = (n + t.cw - 1) / t.cw;
-  t.bang = (n + 63) / 64;
+  // ring sweeps: one wave per ring up to 512 nodes; beyond, 2 or 4 waves of
+  // 8 nodes per lane (the lane span rounded up to 16 or 32)
+  const int b0 = (n + 63) / 64;
+  t.aw = b0 <= 8 ? 1 : (b0 <= 16 ? 2 : 4);
+  t.bang = t.aw == 1 ? b0 : 8 * t.aw;
   t.nb_ang = (m + 3) / 4;
   t.nb_frad = t.nb_rad;
   t.nb_fang = t.nb_ang;
@@ -546,12 +550,12 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
   auto rings = [&](const pd_instance *I) { return I->precision == PD_MIXED ? fp32_rings : PD_RB; };
   P.L = pd::LaunchSet{};
   // host side first: the block maps, then one layout for everything
-  constexpr int NMAP = 7;
+  constexpr int NMAP = 9;
   std::vector<int2> maps[NMAP];
   int *counts[NMAP] = {&P.L.nb_sten, &P.L.nb_elem, &P.L.nb_rad, &P.L.nb_rs[0], &P.L.nb_rs[1], &P.L.nb_rs[2],
-                       &P.L.nb_ang};
+                       &P.L.nb_ang, &P.L.nb_angs[0], &P.L.nb_angs[1]};
   int2 **dsts[NMAP] = {&P.L.map_sten, &P.L.map_elem, &P.L.map_rad, &P.L.map_rs[0], &P.L.map_rs[1], &P.L.map_rs[2],
-                       &P.L.map_ang};
+                       &P.L.map_ang, &P.L.map_angs[0], &P.L.map_angs[1]};
   *counts[0] = build_map(insts, [&](pd_instance *I) { return sten_blocks(I->M.m, I->M.n, rings(I)); }, maps[0]);
   *counts[1] = build_map(insts, [](pd_instance *I) { return I->T.nb_elem; }, maps[1]);
   // radial sweep blocks: neighbouring column blocks share the 128-byte
@@ -564,7 +568,14 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
     *counts[3 + c] =
         build_map(insts, [c](pd_instance *I) { return pd::rad_class(I->M.m) == c ? pd::rad_blocks(I->M.m, I->M.n) : 0; },
                   maps[3 + c]);
+  // factorisation of the rings: 4 rings (waves) per block for every
+  // instance; sweeps: the same for one-wave rings, 4/aw rings per block for
+  // the wider ones
   *counts[6] = build_map(insts, [](pd_instance *I) { return I->T.nb_ang; }, maps[6]);
+  *counts[7] = build_map(insts, [](pd_instance *I) { return I->T.aw == 1 ? I->T.nb_ang : 0; }, maps[7]);
+  *counts[8] = build_map(insts, [](pd_instance *I) {
+    return I->T.aw == 1 ? 0 : (I->M.m * I->T.aw + 3) / 4;
+  }, maps[8]);
   xcd_contiguous(maps[0]);
   xcd_contiguous(maps[3]);
   xcd_contiguous(maps[4]);
@@ -599,6 +610,7 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
     P.L.mixed_any |= insts[q]->precision == PD_MIXED;
     P.L.fp64_any |= insts[q]->precision != PD_MIXED;
     P.L.max_bang = std::max(P.L.max_bang, insts[q]->T.bang);
+    if (insts[q]->T.aw == 1) P.L.max_bang1 = std::max(P.L.max_bang1, insts[q]->T.bang);
     P.L.max_bfrad = std::max(P.L.max_bfrad, insts[q]->T.brad);
   }
   for (auto *I : insts) {
@@ -1178,6 +1190,7 @@ int upload_instance(pd_instance *I, const HostImage &X, void *mem = nullptr) {
   H.brad = I->T.brad;
   H.nb_rad = I->T.nb_rad;
   H.bang = I->T.bang;
+  H.aw = I->T.aw;
   H.nb_ang = I->T.nb_ang;
   H.nb_frad = I->T.nb_frad;
   H.nb_fang = I->T.nb_fang;

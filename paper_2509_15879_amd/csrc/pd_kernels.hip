@@ -646,6 +646,15 @@ __global__ __launch_bounds__(PD_RAD_THREADS) void k_fact_rad(const PdInst *insts
   }
 }
 
+// Where the ring sweeps keep the factor of node j of a ring (ring offset
+// frow, lane span bang): with one wave per ring (aw = 1), lane L owns nodes
+// [L*bang, (L+1)*bang) and node L*bang + k sits at 64k + L; with aw waves
+// per ring each of the 64*aw threads owns 8 nodes, node 8t + k at k*64*aw + t.
+// Either way the threads of a sweep read their factors with coalesced loads.
+__device__ __forceinline__ int afac_index(int frow, int j, int bang, int aw) {
+  return aw == 1 ? frow + 64 * (j % bang) + j / bang : frow + (j & 7) * 64 * aw + (j >> 3);
+}
+
 // Ring-periodic LU of (I + D^{-1}Θ) for ring i: row j has diagonal 1,
 // sub α_j = -θ gp_t(j-1/2)/(V d_j), super γ_j = -θ gm_t(j+1/2)/(V d_j),
 // periodic corners α_0 (row 0, column n-1) and γ_{n-1} (row n-1, column 0).
@@ -674,7 +683,7 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
   const PdInst &I = insts[mp.x];
   const PdScalars *sc = I.sc;
   if (sc->status != ST_ACTIVE || sc->stage != STAGE_START || !sc->refactor) return;
-  const int m = I.m, n = I.n, B = I.bang;
+  const int m = I.m, n = I.n, B = I.bang, aw = I.aw;
   const int lane = threadIdx.x & 63;
   const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
   if (i > m) return;                                  // whole wave exits together
@@ -739,9 +748,10 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
       ul[k] = ui;
       fl[k] = al[k] * ui;
       gf[k] = ga[k] * ui;
-      uinv[frow + 64 * k + lane] = (float)ui;
-      ff[frow + 64 * k + lane] = (float)fl[k];
-      gg[frow + 64 * k + lane] = (float)gf[k];
+      const int fi = afac_index(frow, j0 + k, B, aw);
+      uinv[fi] = (float)ui;
+      ff[fi] = (float)fl[k];
+      gg[fi] = (float)gf[k];
       u_prev = u;
       cp = ga[k];
     }
@@ -796,7 +806,7 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
     if (k < cnt) {
       Q *= -gf[k];
       wl[k] += Q * Xin;
-      zz[frow + 64 * k + lane] = (float)wl[k];
+      zz[afac_index(frow, j0 + k, B, aw)] = (float)wl[k];
       if (j0 + k == n - 1) zlast = wl[k];
     }
   }
@@ -892,8 +902,8 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
     if (k < cnt) {
-      qq[64 * k + lane] = use ? (float)qv[k] : 0.0f;
-      cc[64 * k + lane] = use ? (float)cv[k] : 0.0f;
+      qq[afac_index(0, j0 + k, B, aw)] = use ? (float)qv[k] : 0.0f;
+      cc[afac_index(0, j0 + k, B, aw)] = use ? (float)cv[k] : 0.0f;
     }
   }
   if (lane == 0) G(I.af_sigma)[0] = use ? sigma : 1.0;
@@ -2118,6 +2128,192 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
                   G((const double *)I.af_sigma), tbuf[threadIdx.x >> 6], abuf);
 }
 
+// Ring sweep of rings with more than 512 nodes: aw = 2 or 4 waves per ring.
+// Each of the ring's 64*aw threads owns the 8 consecutive nodes 8t..8t+7
+// (factors stored thread-major, afac_index).  The segments' affine maps are
+// scanned over the lanes of each wave, then joined across the ring's waves
+// through LDS (forward: the waves before, backward: the waves after); the
+// Sherman-Morrison closure reads the ring's first and last values from LDS,
+// and ring 1's arrow closure sums its dot product over the waves in a fixed
+// order.  A block of 256 threads holds 4/aw rings; every thread reaches
+// every barrier (rings past m only skip their memory accesses).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *map) {
+  using C = T;
+  constexpr int BW = 8;                          // nodes per thread
+  const int2 mp = map[blockIdx.x];
+  const PdInst &I = insts[mp.x];
+  PdScalars *sc = I.sc;
+  if (!inner_active(sc) || !prec_match<T>(I)) return;   // the same for the whole block
+  const KSet<T> &KS = kset<T>(I);
+  const int m = I.m, n = I.n, aw = I.aw, B = I.bang;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rpb = 4 / aw;
+  const int slot = wv / aw, wr = wv % aw;        // ring of the block, wave of the ring
+  const int nt = 64 * aw, t = wr * 64 + lane;    // threads of a ring, this thread
+  const int i = mp.y * rpb + slot + 1;
+  const bool on = i <= m;
+  // the p-sweep before this launch consumed the restart flag and the
+  // pending closure; only this block's thread 0 touches these fields here
+  if (MODE == AM_P && mp.y == 0 && threadIdx.x == 0) {
+    if (sc->restarted) {
+      sc->restarts += 1;
+      sc->restarted = 0;
+    }
+    sc->reset_rh = 0;
+    sc->pend = PEND_UPDATE;
+  }
+  __shared__ C tb[2304];                         // node order, one gap after every 8 nodes
+  __shared__ C fP[4], fE[4], bP[4], bE[4];       // wave totals of the forward and backward maps
+  __shared__ C ends[4][2];                       // per ring: first and last value
+  __shared__ C dsum[4];                          // per wave: ring 1's arrow dot product
+  C *rbuf = tb + slot * 576 * aw;
+  const int row = (i - 1) * n, frow = (i - 1) * 64 * B;
+  const int j0 = BW * t;
+  const int cnt = on ? max(0, min(BW, n - j0)) : 0;
+  const bool arrow = on && i == 1;
+  const GAS T *in = G((const T *)KS.w);
+  GAS T *out = G(MODE == AM_P ? KS.ph : KS.sh);
+  const GAS float *uinv = G((const float *)I.af_uinv), *f = G((const float *)I.af_f);
+  const GAS float *g = G((const float *)I.af_g), *z = G((const float *)I.af_z);
+
+  // every load first: the ring's input (coalesced, node t + nt k) and this
+  // thread's factors (node 8t + k at k nt + t)
+  C xin[BW];
+  float ul[BW], fl[BW], gl[BW], zl[BW], aq[BW], ac[BW];   // factors as stored, converted at use
+  C w0 = (C)0, sg = (C)1;
+  if (arrow) {
+    w0 = (C)in[m * n];
+    sg = (C)I.af_sigma[0];
+  }
+#pragma unroll
+  for (int k = 0; k < BW; ++k) {
+    const int jn = t + nt * k;
+    const bool own = k < cnt;                   // implies on
+    const int fi = own ? frow + k * nt + t : 0; // indexes stay in range for rings past m
+    xin[k] = (on && jn < n) ? (C)in[(on && jn < n) ? row + jn : 0] : (C)0;
+    ul[k] = own ? uinv[fi] : 0.0f;
+    fl[k] = own ? f[fi] : 0.0f;
+    gl[k] = own ? g[fi] : 0.0f;
+    zl[k] = own ? z[fi] : 0.0f;
+    aq[k] = (arrow && own) ? G((const float *)I.af_q)[fi] : 0.0f;   // ring 1: frow = 0
+    ac[k] = (arrow && own) ? G((const float *)I.af_c)[fi] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < BW; ++k) {
+    const int jn = t + nt * k;
+    if (on && jn < n) rbuf[jn + jn / BW] = xin[k];
+  }
+  __syncthreads();
+  C wl[BW];
+#pragma unroll
+  for (int k = 0; k < BW; ++k) wl[k] = k < cnt ? (C)ul[k] * rbuf[j0 + k + t] : (C)0;
+  __syncthreads();   // the buffer is rewritten with the result
+
+  // forward substitution: local, over the wave, over the ring's earlier waves
+  AffT<C> A{(C)1, (C)0};
+#pragma unroll
+  for (int k = 0; k < BW; ++k) {
+    if (k < cnt) {
+      A.e = wl[k] - (C)fl[k] * A.e;
+      A.P *= -(C)fl[k];
+      wl[k] = A.e;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const AffT<C> o{__shfl_up(A.P, d, 64), __shfl_up(A.e, d, 64)};
+    if (lane >= d) A = compose(A, o);
+  }
+  AffT<C> X{__shfl_up(A.P, 1, 64), __shfl_up(A.e, 1, 64)};
+  if (lane == 0) X = AffT<C>{(C)1, (C)0};
+  if (lane == 63) {
+    fP[wv] = A.P;
+    fE[wv] = A.e;
+  }
+  __syncthreads();
+  C E = (C)0;
+  for (int w = 0; w < wr; ++w) E = fP[slot * aw + w] * E + fE[slot * aw + w];
+  const C Win = X.P * E + X.e;
+  C P = (C)1;
+#pragma unroll
+  for (int k = 0; k < BW; ++k) {
+    P *= -(C)fl[k];
+    wl[k] += P * Win;
+  }
+  // backward substitution: local, over the wave, over the ring's later waves
+  AffT<C> Bk{(C)1, (C)0};
+#pragma unroll
+  for (int k = BW - 1; k >= 0; --k) {
+    if (k < cnt) {
+      Bk.e = wl[k] - (C)gl[k] * Bk.e;
+      Bk.P *= -(C)gl[k];
+      wl[k] = Bk.e;
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const AffT<C> o{__shfl_down(Bk.P, d, 64), __shfl_down(Bk.e, d, 64)};
+    if (lane + d < 64) Bk = compose(Bk, o);
+  }
+  AffT<C> Y{__shfl_down(Bk.P, 1, 64), __shfl_down(Bk.e, 1, 64)};
+  if (lane == 63) Y = AffT<C>{(C)1, (C)0};
+  if (lane == 0) {
+    bP[wv] = Bk.P;
+    bE[wv] = Bk.e;
+  }
+  __syncthreads();
+  C F = (C)0;
+  for (int w = aw - 1; w > wr; --w) F = bP[slot * aw + w] * F + bE[slot * aw + w];
+  const C Xin = Y.P * F + Y.e;
+  C Q = (C)1, ylast = (C)0;
+#pragma unroll
+  for (int k = BW - 1; k >= 0; --k) {
+    if (k < cnt) {
+      Q *= -(C)gl[k];
+      wl[k] += Q * Xin;
+      if (j0 + k == n - 1) ylast = wl[k];
+    }
+  }
+  // Sherman-Morrison closure of the period
+  if (on && t == 0) ends[slot][0] = wl[0];
+  if (on && t == (n - 1) / BW) ends[slot][1] = ylast;
+  __syncthreads();
+  if (on) {
+    const C kappa = (C)I.af_kappa[i - 1], alpha0 = (C)I.af_alpha0[i - 1];
+    const C sfac = kappa * (ends[slot][0] - alpha0 * ends[slot][1]);
+#pragma unroll
+    for (int k = 0; k < BW; ++k) wl[k] -= sfac * (C)zl[k];
+  }
+  // ring 1 closes the origin row: z_0 = (w_0 - c.u)/σ, z_1 = u - q z_0
+  C dot = (C)0;
+#pragma unroll
+  for (int k = 0; k < BW; ++k)
+    if (k < cnt) dot += (C)ac[k] * wl[k];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) dot += __shfl_xor(dot, d, 64);
+  if (lane == 0) dsum[wv] = dot;
+  __syncthreads();
+  if (arrow) {
+    C tot = (C)0;
+    for (int w = 0; w < aw; ++w) tot += dsum[slot * aw + w];
+    const C z0 = (w0 - tot) / sg;
+#pragma unroll
+    for (int k = 0; k < BW; ++k) wl[k] -= (C)aq[k] * z0;
+    if (t == 0) out[m * n] = (T)z0;
+  }
+  // back to node order through LDS, then coalesced stores
+#pragma unroll
+  for (int k = 0; k < BW; ++k)
+    if (k < cnt) rbuf[j0 + k + t] = wl[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < BW; ++k) {
+    const int jn = t + nt * k;
+    if (on && jn < n) out[row + jn] = (T)rbuf[jn + jn / BW];
+  }
+}
+
 // ------------------------------------------------------------ update kernel
 //
 // x += α p̂ + ω ŝ (x = ... on the first inner iteration of a refinement),
@@ -2449,7 +2645,10 @@ static void rad(const LaunchSet &L, hipStream_t s) {
 }
 template <typename T, int MODE>
 static void ang(const LaunchSet &L, hipStream_t s) {
-  PD_DISPATCH_BM(L.max_bang, (go(MODE == AM_S ? KF_ANG_S : KF_ANG_P, k_ang<T, MODE, BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang)));
+  const int fam = MODE == AM_S ? KF_ANG_S : KF_ANG_P;
+  if (L.nb_angs[0])
+    PD_DISPATCH_BM(L.max_bang1, (go(fam, k_ang<T, MODE, BM>, g1(L.nb_angs[0]), dim3(256), s, L.insts, L.map_angs[0])));
+  if (L.nb_angs[1]) go(fam, k_angw<T, MODE>, g1(L.nb_angs[1]), dim3(256), s, L.insts, L.map_angs[1]);
 }
 template <typename T, int MODE>
 static void sten(int fam, const LaunchSet &L, hipStream_t s) {

@@ -15,7 +15,12 @@ struct LaunchSet {
   int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0, nb_frad = 0, nb_fang = 0;
   int mixed_any = 0, fp64_any = 0;
   int adaptive_any = 0;             // some instance steps adaptively (level-end pass in the round head)
-  int max_bang = 1;                 // longest angular lane span of the batch
+  int max_bang = 1;                 // longest angular lane span of the batch (factorisation)
+  int max_bang1 = 1;                // longest lane span of the one-wave ring sweeps
+  // ring sweeps: [0] one wave per ring (4 rings per block), [1] rings of 2 or
+  // 4 waves (4/aw rings per block)
+  int2 *map_angs[2] = {nullptr, nullptr};
+  int nb_angs[2] = {0, 0};
   int max_bfrad = 1;                // longest radial segment of the factorisation
   // Radial sweeps, three classes by ring count (rad_class).  The class
   // depends on the instance alone, so its arithmetic does not depend on the
