@@ -172,10 +172,11 @@ Tiling make_tiling(int m, int n) {
   t.nseg = PD_RAD_THREADS / t.cw;
   t.brad = (m + t.nseg - 1) / t.nseg;
   t.nb_rad = (n + t.cw - 1) / t.cw;
-  // ring sweeps: one wave per ring up to 512 nodes; beyond, 2 or 4 waves of
-  // 8 nodes per lane (the lane span rounded up to 16 or 32)
+  // ring sweeps: one wave per ring up to 1024 nodes; beyond, 4 waves of 8
+  // nodes per lane (the lane span rounded up to 32).  Two waves for 513-1024
+  // nodes cost a small batch more in barriers than they gained.
   const int b0 = (n + 63) / 64;
-  t.aw = b0 <= 8 ? 1 : (b0 <= 16 ? 2 : 4);
+  t.aw = b0 <= 16 ? 1 : 4;
   t.bang = t.aw == 1 ? b0 : 8 * t.aw;
   t.nb_ang = (m + 3) / 4;
   t.nb_frad = t.nb_rad;

@@ -2128,7 +2128,8 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
                   G((const double *)I.af_sigma), tbuf[threadIdx.x >> 6], abuf);
 }
 
-// Ring sweep of rings with more than 512 nodes: aw = 2 or 4 waves per ring.
+// Ring sweep of rings with more than 1024 nodes: aw = 4 waves per ring (the
+// kernel also takes aw = 2).
 // Each of the ring's 64*aw threads owns the 8 consecutive nodes 8t..8t+7
 // (factors stored thread-major, afac_index).  The segments' affine maps are
 // scanned over the lanes of each wave, then joined across the ring's waves
