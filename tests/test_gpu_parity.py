@@ -218,3 +218,27 @@ def test_zero_flux_conserves_mass_on_gpu():
     M0, M1 = S.V @ x0, S.V @ x1
     assert abs(M1 - M0) / abs(M0) <= 1e-12
     inst.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wide_rings_solve(precision):
+    """Rings of more than 1024 nodes run on four waves per ring (k_angw).
+    n = 1100 is not a multiple of 8: the last threads own part of a segment
+    and part of the fourth wave has no nodes.  Ring 1's arrow closure runs
+    in the wide sweep too."""
+    m, n, theta = 10, 1100, 0.5
+    say(f"[solve] continuity {m}x{n} graded (four waves per ring), precision={precision}")
+    from paper_2509_15879_amd import polardisk as pdk
+    pb = continuity_cfg(1106, m, n)
+    S, me = oracle_system(pb, m, n, 1, 1.3)
+    ref = solve(S, time_levels(0.02, 6, 1, 1.5), theta)
+    inst = gpu_instance(pb, m, n, 1, 1.3, precision=precision)
+    stats = inst.solve(pdk.time_desc(theta, 6, 0.02, pdk.TIME_SINE, 1.5, tol=1e-13))
+    got = inst.solution(layout=1)
+    say(f"  iters/step {np.mean([s['iters'] for s in stats]):.1f}, "
+        f"max-rel {max_rel(got, ref):.2e}, l2-rel {l2_rel(got, ref):.2e}")
+    if precision == 0:
+        assert max_rel(got, ref) <= FP64_BAR
+    else:
+        assert l2_rel(got, ref) <= MIXED_BAR
+    inst.close()
