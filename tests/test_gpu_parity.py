@@ -242,3 +242,28 @@ def test_wide_rings_solve(precision):
     else:
         assert l2_rel(got, ref) <= MIXED_BAR
     inst.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("m,n", [(2048, 64), (8, 2048)])
+def test_maximum_ring_and_node_counts(m, n, precision):
+    """The largest meshes the library accepts along each axis.  2048 rings
+    give the radial sweep its longest segments (16 rows per thread, 128
+    segments per column); 2048 nodes fill the four-wave ring sweep exactly
+    (256 threads of 8 nodes)."""
+    theta = 0.5
+    say(f"[solve] continuity {m}x{n} graded (maximum counts), precision={precision}")
+    from paper_2509_15879_amd import polardisk as pdk
+    pb = continuity_cfg(1107, m, n)
+    S, me = oracle_system(pb, m, n, 1, 1.3)
+    ref = solve(S, time_levels(0.01, 3, 1, 1.5), theta)
+    inst = gpu_instance(pb, m, n, 1, 1.3, precision=precision)
+    stats = inst.solve(pdk.time_desc(theta, 3, 0.01, pdk.TIME_SINE, 1.5, tol=1e-13))
+    got = inst.solution(layout=1)
+    say(f"  iters/step {np.mean([s['iters'] for s in stats]):.1f}, "
+        f"max-rel {max_rel(got, ref):.2e}, l2-rel {l2_rel(got, ref):.2e}")
+    if precision == 0:
+        assert max_rel(got, ref) <= FP64_BAR
+    else:
+        assert l2_rel(got, ref) <= MIXED_BAR
+    inst.close()
