@@ -267,3 +267,39 @@ def test_maximum_ring_and_node_counts(m, n, precision):
     else:
         assert l2_rel(got, ref) <= MIXED_BAR
     inst.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", ["zero", "constant"])
+def test_degenerate_levels_finish_at_the_guess(case, precision):
+    """Two problems whose every level is solved by its initial guess.
+    "zero": no sources, zero boundary values and initial state; b = 0 at
+    every level, the solution is exactly 0.  "constant": pure diffusion with
+    zero-flux boundary and a constant initial state; every face flux of a
+    constant vanishes exactly, so the state stays exactly at the constant.
+    Each level must stop at its begin test with no iteration, and the
+    least-squares guess, whose Gram matrix is all zeros or carries only
+    rounding, must stay finite."""
+    from paper_2509_15879_amd import polardisk as pdk
+    from problems import TimeMode
+    m, n = 24, 80
+    zero = lambda r, th: np.zeros(np.broadcast(r, th).shape)  # noqa: E731
+    pb = continuity_cfg(1108, m, n)
+    pb.modes = [TimeMode(0.0, 0, zero, lambda th: np.zeros(np.shape(th)))]
+    if case == "zero":
+        pb.u0, bc, expect = zero, 0, 0.0
+    else:
+        pb.Er = pb.Et = None
+        pb.u0, bc, expect = (lambda r, th: np.ones(np.broadcast(r, th).shape)), 1, 1.0
+    say(f"[solve] degenerate '{case}' {m}x{n}, precision={precision}")
+    inst = gpu_instance(pb, m, n, 1, 1.3, 1, 1.5, precision=precision, bc=bc)
+    stats = inst.solve(pdk.time_desc(0.5, 8, 0.02, pdk.TIME_SINE, 1.5, tol=1e-13))
+    got = inst.solution(layout=1)
+    say(f"  iters {[s['iters'] for s in stats]}, max |x - {expect}| {np.max(np.abs(got - expect)):.2e}")
+    assert np.all(np.isfinite(got))
+    assert all(s["status"] == 0 and s["iters"] == 0 for s in stats)
+    if case == "zero":
+        assert np.all(got == 0.0)
+    else:
+        assert np.max(np.abs(got - 1.0)) <= 1e-14
+    inst.close()
