@@ -1,6 +1,7 @@
 """CPU-side checks of the C ABI: the library loads, exports every entry
-point that include/polardisk.h declares, and its host-only mesh routine
-agrees with the paper's mesh formulas (no GPU call is made)."""
+point that include/polardisk.h declares, its host-only mesh routine agrees
+with the paper's mesh formulas, and bad mesh and problem descriptors are
+refused on the host (no GPU call is made)."""
 
 import os
 import re
@@ -82,3 +83,66 @@ def test_time_levels_errors():
         pdk.time_levels(pdk.time_desc(0.5, 10, 0.0, pdk.TIME_SINE, 1.5))
     with pytest.raises(pdk.PolarDiskError, match="increase"):
         pdk.time_levels(pdk.time_desc(0.5, 2, table=[0.0, 0.2, 0.1]))
+
+
+def test_explicit_meshes_are_taken_as_given():
+    """Explicit nodes are used as passed, with the end points set to 0, 1
+    (radial) and 0, 2π (angular) exactly."""
+    from paper_2509_15879_amd import polardisk as pdk
+    m, n = 6, 9
+    r = np.array([0.0, 0.05, 0.15, 0.3, 0.5, 0.7, 0.9, 1.0])
+    th = np.sort(np.random.default_rng(5).uniform(0.1, 6.2, n - 1))
+    th = np.concatenate([[0.0], th, [2 * np.pi]])
+    md = pdk.mesh_desc(m, n, pdk.MESH_EXPLICIT, 1.0, pdk.MESH_EXPLICIT, 1.0, r_explicit=r, th_explicit=th)
+    rr, rf, tt, tf = pdk.mesh_coords(md)
+    assert np.array_equal(rr, r) and np.array_equal(tt, th)
+    assert np.all((rf > rr[:-1]) & (rf < rr[1:]))
+    assert np.all((tf > tt[:-1]) & (tf < tt[1:]))
+
+
+@pytest.mark.parametrize("case,msg", [("r_order", "radial nodes not strictly increasing"),
+                                      ("th_order", "angular nodes not strictly increasing"),
+                                      ("r_null", "r_explicit is NULL"),
+                                      ("r_kind", "unknown r_kind"),
+                                      ("th_kind", "unknown th_kind")])
+def test_explicit_mesh_errors(case, msg):
+    from paper_2509_15879_amd import polardisk as pdk
+    m, n = 4, 6
+    r = np.linspace(0.0, 1.0, m + 2)
+    th = np.linspace(0.0, 2 * np.pi, n + 1)
+    rk = tk = pdk.MESH_EXPLICIT
+    if case == "r_order":
+        r[2], r[3] = r[3], r[2]
+    elif case == "th_order":
+        th[3] = th[1]
+    elif case == "r_null":
+        r = None
+    elif case == "r_kind":
+        rk = 7
+    else:
+        tk = 9
+    md = pdk.mesh_desc(m, n, rk, 1.0, tk, 1.0, r_explicit=r, th_explicit=th)
+    with pytest.raises(pdk.PolarDiskError) as e:
+        pdk.mesh_coords(md)
+    assert e.value.code == -1 and msg in str(e.value)
+
+
+@pytest.mark.parametrize("kw,msg", [(dict(precision=5), "unknown precision"),
+                                    (dict(flux=2), "flux must be 0 or 1"),
+                                    (dict(bc=3), "bc must be 0 or 1"),
+                                    (dict(nsrc=5), "nsrc must be in")])
+def test_problem_errors_are_reported_before_any_device_call(kw, msg):
+    """pd_mesh_create checks its descriptors on the host first: a bad one is
+    refused with PD_EINVAL and its message, with or without a GPU."""
+    from paper_2509_15879_amd import polardisk as pdk
+    from problems import continuity_cfg, sample
+    m, n = 4, 8
+    md = pdk.mesh_desc(m, n)
+    data = sample(continuity_cfg(1110, m, n), *pdk.mesh_coords(md))
+    if "nsrc" in kw:                     # the problem's first mode, repeated
+        k = kw["nsrc"]
+        for key in ("lam", "tpow", "g_origin", "g_grid", "nb"):
+            data[key] = np.stack([np.asarray(data[key])[0]] * k)
+    with pytest.raises(pdk.PolarDiskError) as e:
+        pdk.Instance(md, data, kw.get("precision", pdk.PD_FP64), flux=kw.get("flux", 0), bc=kw.get("bc", 0))
+    assert e.value.code == -1 and msg in str(e.value)
