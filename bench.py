@@ -48,8 +48,8 @@ KERNEL_NAMES = {
 # WRITE_SIZE counters, calibrated on a copy of known size), valid for the
 # sources with this SHA-1 only (kernel_source_sha1); any other source
 # reports traffic null.
-TRAFFIC_SOURCE_SHA1 = "72c33e87204945999b1148df9ddf06070bb6265c"
-TRAFFIC_B_PER_CELL = {"rad_p": 54.72, "ang_p": 32.47, "sten_v": 64.80, "rad_s": 44.21, "ang_s": 32.47, "sten_t": 64.63, "update": 64.53}
+TRAFFIC_SOURCE_SHA1 = "bbd27df650443088c565f76e1e047c6beb0124fc"
+TRAFFIC_B_PER_CELL = {"rad_p": 54.72, "ang_p": 32.47, "sten_v": 64.90, "rad_s": 44.21, "ang_s": 32.47, "sten_t": 65.03, "update": 64.53}
 
 
 def code_digest(texts):

@@ -118,7 +118,8 @@ typedef struct {
  *   N(t, θ_j) = Σ_q τ_q(t) nb_q[j] with nb: nsrc*n values (NULL means 0).
  *   tpow may be NULL (all 0).
  *   u0: N initial values in `layout` (eq. (2.10) / (3.3)).
- *   device_ptrs: 1 if every array above is a device pointer.             */
+ *   device_ptrs: 1 if every array above (lambda and tpow included) is a
+ *   device pointer; they are copied to the host at creation.              */
 typedef struct {
   int32_t pde;
   int32_t flux;

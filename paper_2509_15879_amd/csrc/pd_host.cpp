@@ -1084,9 +1084,19 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
     if ((rc = fetch(pb->g, (size_t)pb->nsrc * N, dp, g))) return rc;
     if (pb->nb) { if ((rc = fetch(pb->nb, (size_t)pb->nsrc * n, dp, X.nb))) return rc; }
     else X.nb.assign((size_t)pb->nsrc * n, 0.0);
+    std::vector<double> lam;
+    if ((rc = fetch(pb->lambda, (size_t)pb->nsrc, dp, lam))) return rc;
+    int32_t tp[PD_MAXSRC] = {0, 0, 0, 0};
+    if (pb->tpow) {
+      if (dp) {
+        HIPCHK(hipMemcpy(tp, pb->tpow, pb->nsrc * sizeof(int32_t), hipMemcpyDeviceToHost));
+      } else {
+        std::memcpy(tp, pb->tpow, pb->nsrc * sizeof(int32_t));
+      }
+    }
     for (int q = 0; q < pb->nsrc; ++q) {
-      X.lam[q] = pb->lambda[q];
-      X.tp[q] = pb->tpow ? pb->tpow[q] : 0;
+      X.lam[q] = lam[q];
+      X.tp[q] = tp[q];
       if (X.tp[q] < 0 || X.tp[q] > 8) return fail(PD_EINVAL, "tpow must be in [0, 8]");
     }
   }
