@@ -375,8 +375,9 @@ def _hip_runtime():
 def test_device_pointer_inputs_and_outputs():
     """Every array of the problem descriptor, λ and tpow included, may be a
     device pointer: an instance created from device copies solves bit for bit
-    as the one created from host arrays.  Solutions read and written, and an
-    operator applied, through device pointers equal the host-pointer calls."""
+    as the one created from host arrays.  Solutions read and written, an
+    operator applied and a right-hand side assembled through device pointers
+    equal the host-pointer calls."""
     import ctypes as C
 
     from paper_2509_15879_amd import polardisk as pdk
@@ -416,7 +417,10 @@ def test_device_pointer_inputs_and_outputs():
     y = _DeviceBuffer(hip, np.zeros(N))
     pdk._check(pdk.lib.pd_apply_operator(devinst.h, C.c_double(1e-3), C.c_double(theta), x.p, y.p, 1, 1, 0))
     assert np.array_equal(y.read(), host.apply(0.5 * ref + 0.25, 1e-3, theta, layout=1))
-    say("  device-pointer create, get, set and apply match the host-pointer calls bit for bit")
+    host.set_solution(0.5 * ref + 0.25, 0.02, layout=1)
+    pdk._check(pdk.lib.pd_assemble_rhs(devinst.h, C.c_double(0.02), C.c_double(1e-3), C.c_double(theta), y.p, 1, 1))
+    assert np.array_equal(y.read(), host.rhs(0.02, 1e-3, theta, layout=1))
+    say("  device-pointer create, get, set, apply and rhs match the host-pointer calls bit for bit")
     devinst.close()
     host.close()
     for b in bufs + [out, x, y]:
