@@ -20,9 +20,9 @@ from . import polardisk as pdk
 # (stream groups, cycles per graph).  Longer rounds pay for their idle
 # cycles (an instance that converges waits for the next round head) by
 # running the round head, which costs about one cycle, less often.  4 and
-# 5 groups ran the ten-instance 256 x 512 batch 45-53% slower than 3 (with
-# HIP's default of 4 hardware queues per process; the cause was not
-# pinned down).
+# 5 groups ran the ten-instance 256 x 512 batch 45-53% slower than 3, and
+# more hardware queues per process made them slower still: from the fourth
+# stream on the groups stop overlapping (same iterations, same results).
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((g, c) for g in (1, 2, 3) for c in (4, 8, 12))
 FP32_RINGS: Tuple[int, ...] = (4, 8)
 
