@@ -271,11 +271,22 @@ class Instance:
     """One disk problem resident on the GPU."""
 
     def __init__(self, md: MeshDesc, data: dict, precision=PD_FP64, flux=0, bc=0, stream=None):
+        self._create(md, problem_desc(data, flux, bc), precision, stream)
+
+    @classmethod
+    def from_desc(cls, md: MeshDesc, pdesc: ProblemDesc, precision=PD_FP64, stream=None):
+        """An instance from a problem descriptor built by the caller (for
+        instance one whose arrays are device pointers, device_ptrs = 1)."""
+        inst = cls.__new__(cls)
+        inst._create(md, pdesc, precision, stream)
+        return inst
+
+    def _create(self, md, pdesc, precision, stream):
+        self.h = None
         self.md = md
         self.m, self.n = md.nr, md.ntheta
         self.N = self.m * self.n + 1
         self.precision = precision
-        pdesc = problem_desc(data, flux, bc)
         h = C.c_void_p()
         _check(lib.pd_mesh_create(C.byref(md), C.byref(pdesc), int(precision),
                                   C.c_void_p(stream) if stream else None, C.byref(h)))

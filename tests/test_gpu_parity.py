@@ -399,10 +399,7 @@ def test_device_pointer_inputs_and_outputs():
             setattr(pdd, field, bufs[-1].p.value)
     assert len(bufs) >= 9
     pdd.device_ptrs = 1
-    h = C.c_void_p()
-    pdk._check(pdk.lib.pd_mesh_create(C.byref(md), C.byref(pdd), pdk.PD_FP64, None, C.byref(h)))
-    devinst = pdk.Instance.__new__(pdk.Instance)
-    devinst.md, devinst.m, devinst.n, devinst.N, devinst.precision, devinst.h = md, m, n, N, 0, h
+    devinst = pdk.Instance.from_desc(md, pdd, pdk.PD_FP64)
     td = pdk.time_desc(theta, 5, 0.02, pdk.TIME_SINE, 1.5, tol=1e-13)
     host.solve(td)
     devinst.solve(td)
