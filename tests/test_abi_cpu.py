@@ -146,3 +146,16 @@ def test_problem_errors_are_reported_before_any_device_call(kw, msg):
     with pytest.raises(pdk.PolarDiskError) as e:
         pdk.Instance(md, data, kw.get("precision", pdk.PD_FP64), flux=kw.get("flux", 0), bc=kw.get("bc", 0))
     assert e.value.code == -1 and msg in str(e.value)
+
+
+def test_from_desc_refuses_a_bad_descriptor_cleanly():
+    """Instance.from_desc passes a caller-built descriptor through unchanged:
+    a refused one raises the library's error, and nothing is left to destroy."""
+    from paper_2509_15879_amd import polardisk as pdk
+    from problems import continuity_cfg, sample
+    m, n = 4, 8
+    md = pdk.mesh_desc(m, n)
+    pdesc = pdk.problem_desc(sample(continuity_cfg(1113, m, n), *pdk.mesh_coords(md)))
+    pdesc.layout = 7
+    with pytest.raises(pdk.PolarDiskError, match="bad layout"):
+        pdk.Instance.from_desc(md, pdesc)
