@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import make_mesh
-from oracle.adapt import choose_stretch, indicator, second_differences, transfer
+from oracle.adapt import choose_stretch, indicator, predicted_max, second_differences, transfer
 from oracle.operator import to_vec
 
 
@@ -36,17 +36,101 @@ def test_angular_second_difference_closed_form():
     assert np.allclose(d2t, expect[None, :], rtol=1e-12, atol=1e-12)
 
 
-def test_indicator_combines_directions():
-    me = make_mesh(9, 16, 1, 1.2)
-    rng = np.random.default_rng(3)
-    x = rng.standard_normal(9 * 16 + 1)
-    nb = rng.standard_normal(16)
-    eta, kappa = indicator(me, x, nb)
-    d2r, d2t = second_differences(me, x, nb)
-    h = me.h
-    hl = 0.5 * (h[1:10] + h[2:11])
-    assert np.allclose(eta, np.maximum(hl[:, None] ** 2 * abs(d2r), me.dtheta[None, :] ** 2 * abs(d2t)))
-    assert np.allclose(kappa, abs(d2r).max(axis=1))
+def hand_nodes(m, p):
+    """Nodes of the stretch (2.4) written out with math.sin, node by node."""
+    import math
+    h = 1.0 / (m + 1)
+    r = [0.0] + [math.sin((k * h) ** p * math.pi / 2.0) for k in range(1, m + 1)] + [1.0]
+    return r
+
+
+@pytest.mark.parametrize("rk,p", [(0, 1.0), (1, 1.3), (1, 0.8)])
+def test_indicator_of_a_radial_quadratic(rk, p):
+    """n = a r² + c: δ_r² n = 2a exactly and δ_θ² n = 0, so the indicator is
+    η_ij = ((r_{i+1} - r_{i-1})/2)² · 2|a| (on a uniform mesh 2|a| h²), and
+    κ_i = 2|a|.  A wrong local spacing (h_i or h_{i+1} in place of their
+    mean) fails on the graded meshes."""
+    m, n, a, c = 13, 10, -1.3, 0.7
+    me = make_mesh(m, n, rk, p)
+    x = to_vec(c, grid_values(me, lambda R, T: a * R ** 2 + c))
+    eta, kappa = indicator(me, x, nb=np.full(n, a + c))
+    r = me.r
+    for i in range(1, m + 1):
+        want = ((r[i + 1] - r[i - 1]) / 2.0) ** 2 * 2.0 * abs(a)
+        assert np.allclose(eta[i - 1], want, rtol=1e-9, atol=0), (i, eta[i - 1, 0], want)
+    if rk == 0:
+        assert np.allclose(eta, 2 * abs(a) / (m + 1) ** 2, rtol=1e-9)
+    assert np.allclose(kappa, 2 * abs(a), rtol=1e-9)
+
+
+def test_indicator_of_r2_cos_k_theta():
+    """n = r² cos kθ on a uniform mesh: δ_r² n = 2 cos kθ_j and
+    δ_θ² n = r_i² (2 cos kμ - 2)/μ² cos kθ_j exactly, so
+    η_ij = |cos kθ_j| max(2 ĥ², r_i² |2 cos kμ - 2|) (ĥ = h, Δθ = μ) and
+    κ_i = 2 max_j |cos kθ_j|.  The angular part decides near r = 1, the
+    radial part near the origin."""
+    m, n, k = 9, 12, 2
+    me = make_mesh(m, n, 0, 1.0)
+    h, mu = 1.0 / (m + 1), 2 * np.pi / n
+    x = to_vec(0.0, grid_values(me, lambda R, T: R ** 2 * np.cos(k * T)))
+    thj = 2 * np.pi * np.arange(n) / n
+    eta, kappa = indicator(me, x, nb=np.cos(k * thj))
+    for i in range(1, m + 1):
+        ri = i * h
+        want = np.abs(np.cos(k * thj)) * max(2 * h * h, ri * ri * abs(2 * np.cos(k * mu) - 2))
+        assert np.allclose(eta[i - 1], want, rtol=1e-9, atol=1e-15), i
+    assert np.allclose(kappa, 2 * np.max(np.abs(np.cos(k * thj))), rtol=1e-9)
+
+
+def test_predicted_max_for_constant_curvature():
+    """κ ≡ K0: P(p) = K0 · max_k ((r'_{k+1} - r'_{k-1})/2)² over the nodes
+    of the stretch (2.4), computed here node by node.  Using h_{k+1} in
+    place of the mean spacing fails."""
+    old = make_mesh(20, 8, 0, 1.0)
+    K0 = 3.5
+    for p, m_new in ((1.0, 20), (1.3, 31), (2.0, 17)):
+        r = hand_nodes(m_new, p)
+        want = K0 * max(((r[k + 1] - r[k - 1]) / 2.0) ** 2 for k in range(1, m_new + 1))
+        got = predicted_max(old.r, np.full(20, K0), m_new, p)
+        assert got == pytest.approx(want, rel=1e-12), (p, got, want)
+
+
+def test_predicted_max_for_linear_curvature():
+    """κ linear in r between the outermost old nodes (and constant beyond
+    them): P(p) = max_k ĥ'_k² κ(r'_k) with κ evaluated at the new node
+    itself.  Sampling κ at a neighbouring node fails."""
+    m_old = 25
+    old = make_mesh(m_old, 8, 1, 1.1)
+    al, be = 0.4, 5.0
+    rin = old.r[1:m_old + 1]
+    kappa = al + be * rin
+    for p, m_new in ((1.3, 25), (0.9, 40)):
+        r = hand_nodes(m_new, p)
+        vals = []
+        for k in range(1, m_new + 1):
+            rk = min(max(r[k], rin[0]), rin[-1])
+            vals.append(((r[k + 1] - r[k - 1]) / 2.0) ** 2 * (al + be * rk))
+        got = predicted_max(old.r, kappa, m_new, p)
+        assert got == pytest.approx(max(vals), rel=1e-12), p
+
+
+def test_choose_stretch_picks_the_smallest_prediction():
+    """κ ≡ 1 and candidates 1 and 5: the stretch (2.4) with p = 1 has its
+    largest spacing at the origin, about (π/2) h, while p = 5 reaches about
+    3 h near s = 0.9, so p = 1 is chosen, and from p = 5 a remesh is
+    recommended.  Among equal predictions the first candidate wins, and the
+    recommendation needs P(best) <= 0.8 P(current)."""
+    me = make_mesh(30, 8, 1, 5.0)
+    kap = np.ones(30)
+    best, pb, pc, rec = choose_stretch(me, kap, 5.0, [5.0, 1.0])
+    h = 1.0 / 31
+    assert best == 1.0 and rec
+    assert pb == pytest.approx(max(((a - b) / 2) ** 2 for a, b in
+                                   zip(hand_nodes(30, 1.0)[2:], hand_nodes(30, 1.0)[:-2])), rel=1e-12)
+    assert 1.4 * h < np.sqrt(pb) < 1.6 * h and np.sqrt(pc) > 2.5 * h
+    # the first of equal candidates; no recommendation when nothing improves
+    best, pb, pc, rec = choose_stretch(me, kap, 1.0, [1.0, 1.0, 5.0])
+    assert best == 1.0 and pb == pc and not rec
 
 
 def test_transfer_onto_the_same_mesh_is_the_identity():

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import assemble, make_mesh, solve, time_levels
 from oracle.stepper import rhs, system_matrix
-from oracle.timectl import f_eval, land, local_error, solve_adaptive, solve_levels
+from oracle.timectl import f_eval, land, local_error, retry_factor, solve_adaptive, solve_levels, step_factor
 from problems import continuity_cfg, sample
 
 
@@ -92,3 +92,29 @@ def test_controller_invariants_and_error_follows_tolerance(theta):
         assert np.max(np.abs(solve_levels(S, lv, theta) - x)) <= 1e-12 * np.max(np.abs(x))
         errs.append(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     assert errs[1] < errs[0]
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_step_factor_at_hand_computed_errors(q):
+    """0.9 (tol/e)^{1/(q+1)} equals a chosen g at e = tol (0.9/g)^{q+1}:
+    inside [1/2, 2] the factor is g itself, and it sits on each clamp at the
+    error that reaches it.  An exponent 1/q instead of 1/(q+1) fails."""
+    tol = 3e-7
+    for g in (1.5, 1.0, 0.7):
+        e = tol * (0.9 / g) ** (q + 1)
+        assert step_factor(e, tol, q) == pytest.approx(g, rel=1e-12)
+    assert step_factor(tol * (0.9 / 2.0) ** (q + 1), tol, q) == pytest.approx(2.0, rel=1e-12)
+    assert step_factor(0.5 * tol * (0.9 / 2.0) ** (q + 1), tol, q) == 2.0     # clamped above
+    assert step_factor(tol * 1.8 ** (q + 1), tol, q) == pytest.approx(0.5, rel=1e-12)
+    assert step_factor(2.0 * tol * 1.8 ** (q + 1), tol, q) == 0.5              # clamped below
+    assert step_factor(0.0, tol, q) == 2.0
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_retry_factor_at_hand_computed_errors(q):
+    """A rejected step shrinks by 0.9 (tol/e)^{1/(q+1)}, at least to 1/4."""
+    tol = 1e-6
+    for g in (0.8, 0.4):
+        assert retry_factor(tol * (0.9 / g) ** (q + 1), tol, q) == pytest.approx(g, rel=1e-12)
+    assert retry_factor(tol * 3.6 ** (q + 1), tol, q) == pytest.approx(0.25, rel=1e-12)
+    assert retry_factor(10.0 * tol * 3.6 ** (q + 1), tol, q) == 0.25
