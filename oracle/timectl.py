@@ -38,9 +38,8 @@ Controller (relative L2 error e = ||d|| / ||x_{k+1}||, tolerance tol):
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse.linalg as spla
 
-from .stepper import _lu, rhs, system_matrix
+from .stepper import rhs, solve_system, step
 
 
 def f_eval(sys, x, t):
@@ -94,8 +93,7 @@ def solve_adaptive(sys, theta, T, dt0, tol, dt_min, dt_max, t0=0.0, x0=None, max
     levels, steps, rejected = [t], [], 0
     while t < t_end and len(steps) < max_steps:
         t1 = t + dt if t + dt < t_end else t_end
-        A = _lu(sys, t1 - t, theta)
-        x1 = A.solve(rhs(sys, x, t, t1, theta))
+        x1 = solve_system(sys, t1 - t, theta, rhs(sys, x, t, t1, theta))
         f1 = f_eval(sys, x1, t1)
         if f_prev is None:
             e, q, accept = 0.0, (2 if theta == 0.5 else 1), True   # first step: accepted as is
@@ -124,5 +122,7 @@ def solve_levels(sys, levels, theta, x0=None):
     x = sys.initial() if x0 is None else np.array(x0, float)
     for k in range(len(levels) - 1):
         t0, t1 = float(levels[k]), float(levels[k + 1])
-        x = spla.spsolve(system_matrix(sys, t1 - t0, theta), rhs(sys, x, t0, t1, theta))
+        x = step(sys, x, t0, t1, theta)
+        if len(sys.lu_cache) > 4:
+            sys.lu_cache.clear()
     return x
