@@ -279,6 +279,26 @@ typedef struct {
 int pd_error_indicator(pd_instance *inst, double p_current, const double *p_candidates,
                        int32_t n_candidates, double *kappa, double *eta, pd_indicator *out);
 
+/* pd_error_indicator_noalloc: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Computes what pd_error_indicator computes, with the
+ * same kernel and the same host arithmetic (identical results), and calls
+ * no hipMalloc, hipFree or other allocating routine.  The per-ring values
+ * go through a fixed device array of 4*2048 doubles (64 KiB) that each GPU
+ * the library runs on holds until the process ends.
+ *   eta_device: NULL, or a DEVICE pointer to m*n doubles (ring-major
+ *   (i-1)*n + j) owned by the caller, which receives the indicator field;
+ *   kappa and out are host buffers as for pd_error_indicator.
+ * Limits and errors: PD_EINVAL for m > 2048 (larger than any instance the
+ * library creates) and for the arguments pd_error_indicator refuses.  The
+ * call waits for its kernel on the instance's stream.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (from several
+ * host threads, or on several streams) race and may return each other's
+ * values; serialise them.                                                  */
+int pd_error_indicator_noalloc(pd_instance *inst, double p_current, const double *p_candidates,
+                               int32_t n_candidates, double *kappa, double *eta_device,
+                               pd_indicator *out);
+
 /* pd_remesh_transfer: sets the state of `to` (another mesh of the same
  * problem and boundary condition) from the current state of `from` by
  * tensor cubic Lagrange interpolation: radially along each θ-line of

@@ -1549,37 +1549,116 @@ int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double 
 
 // ================================================================== adaptivity
 
+// Scratch of the allocation-free indicator: the per-ring values of
+// k_indicator (4 doubles per ring), up to kMaxM rings.  Each device holds
+// its own copy for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress returns for that device.
+constexpr size_t kIndScratch = 4 * (size_t)kMaxM;
+static __device__ __align__(256) double scratch[kIndScratch];
+
 namespace {
 
-// Nodes of the radial stretch (2.4) with exponent p: r_i = sin((i h)^p π/2).
-std::vector<double> sine_nodes(int m, double p) {
-  std::vector<double> r(m + 2);
-  const double h = 1.0 / (m + 1);
-  for (int i = 0; i <= m + 1; ++i) r[i] = std::sin(std::pow(i * h, p) * kPi / 2.0);
-  r[0] = 0.0;
-  r[m + 1] = 1.0;
-  return r;
+// Node k of the radial stretch (2.4) with exponent p: r_k = sin((k h)^p π/2),
+// the end points exact.
+double sine_node(int m, double p, int k) {
+  if (k <= 0) return 0.0;
+  if (k >= m + 1) return 1.0;
+  return std::sin(std::pow(k * (1.0 / (m + 1)), p) * kPi / 2.0);
 }
 
-// κ at v by linear interpolation between (xs[k], ys[k]), constant beyond the ends.
-double interp_linear(const std::vector<double> &xs, const std::vector<double> &ys, double v) {
-  if (v <= xs.front()) return ys.front();
-  if (v >= xs.back()) return ys.back();
-  const size_t k = std::upper_bound(xs.begin(), xs.end(), v) - xs.begin();   // xs[k-1] <= v < xs[k]
+// κ at v by linear interpolation between (xs[k], ys[k]), k = 0..cnt-1 (xs
+// increasing), constant beyond the ends.
+double interp_linear(const double *xs, const double *ys, int cnt, double v) {
+  if (v <= xs[0]) return ys[0];
+  if (v >= xs[cnt - 1]) return ys[cnt - 1];
+  const int k = (int)(std::upper_bound(xs, xs + cnt, v) - xs);   // xs[k-1] <= v < xs[k]
   const double w = (v - xs[k - 1]) / (xs[k] - xs[k - 1]);
   return ys[k - 1] + w * (ys[k] - ys[k - 1]);
 }
 
-// Predicted largest radial indicator max_k ĥ'_k² κ(r'_k) of the stretch with exponent p.
-double predicted_max(const std::vector<double> &r_old, const std::vector<double> &kappa, int m, double p) {
-  const std::vector<double> r = sine_nodes(m, p);
-  std::vector<double> xs(r_old.begin() + 1, r_old.end() - 1);   // r_1..r_m
+// Predicted largest radial indicator max_k ĥ'_k² κ(r'_k) of the stretch with
+// exponent p; r_old holds r_0..r_{m+1} of the current mesh, kappa κ_1..κ_m.
+// Allocates nothing.
+double predicted_max(const double *r_old, const double *kappa, int m, double p) {
   double best = 0.0;
+  double rl = sine_node(m, p, 0), rc = sine_node(m, p, 1);
   for (int k = 1; k <= m; ++k) {
-    const double hl = 0.5 * ((r[k] - r[k - 1]) + (r[k + 1] - r[k]));
-    best = std::max(best, hl * hl * interp_linear(xs, kappa, r[k]));
+    const double rr = sine_node(m, p, k + 1);
+    const double hl = 0.5 * ((rc - rl) + (rr - rc));
+    best = std::max(best, hl * hl * interp_linear(r_old + 1, kappa, m, rc));
+    rl = rc;
+    rc = rr;
   }
   return best;
+}
+
+// The indicator summary from the per-ring values of k_indicator (4 per
+// ring: κ_i, max_j η, its first j, Σ_j η) and the candidate exponents.
+// Allocates nothing; kappa (m values) may be NULL.
+void indicator_summary(const pd_instance *I, const double *ring, double p_current, const double *p_candidates,
+                       int n_candidates, double *kappa, double *kap_work, pd_indicator *out) {
+  const int m = I->M.m;
+  pd_indicator R{};
+  R.eta_max = -1.0;
+  for (int i = 1; i <= m; ++i) {
+    const double *q = ring + 4 * (size_t)(i - 1);
+    kap_work[i - 1] = q[0];
+    if (q[1] > R.eta_max) {
+      R.eta_max = q[1];
+      R.i_max = i;
+      R.j_max = (int)q[2];
+    }
+    R.eta_sum += q[3];
+  }
+  if (kappa) std::copy(kap_work, kap_work + m, kappa);
+  R.p_best = p_current;
+  R.pred_current = predicted_max(I->M.r.data(), kap_work, m, p_current);
+  R.pred_best = R.pred_current;
+  bool found = false;
+  for (int c = 0; c < n_candidates; ++c) {
+    const double v = predicted_max(I->M.r.data(), kap_work, m, p_candidates[c]);
+    if (!found || v < R.pred_best) {
+      R.pred_best = v;
+      R.p_best = p_candidates[c];
+      found = true;
+    }
+  }
+  R.recommend = (found && R.pred_best <= 0.8 * R.pred_current) ? 1 : 0;
+  *out = R;
+}
+
+int check_indicator_args(pd_instance *I, double p_current, const double *p_candidates, int32_t n_candidates,
+                         pd_indicator *out) {
+  if (!I || !out) return fail(PD_EINVAL, "NULL argument");
+  if (n_candidates < 0 || (n_candidates > 0 && !p_candidates)) return fail(PD_EINVAL, "bad candidate list");
+  for (int c = 0; c < n_candidates; ++c)
+    if (!(p_candidates[c] > 0.0)) return fail(PD_EINVAL, "stretch exponents must be > 0");
+  if (!(p_current > 0.0)) return fail(PD_EINVAL, "p_current must be > 0");
+  return PD_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device
+// with that device current (the caller's current device is restored).
+int scratch_on(int device, double **ptr) {
+  if (device < 0 || device >= kMaxDevices) return fail(PD_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) HIPCHK(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      return fail(PD_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = (double *)p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return PD_OK;
 }
 
 }  // namespace
@@ -1588,11 +1667,8 @@ extern "C" {
 
 int pd_error_indicator(pd_instance *I, double p_current, const double *p_candidates, int32_t n_candidates,
                        double *kappa, double *eta, pd_indicator *out) {
-  if (!I || !out) return fail(PD_EINVAL, "NULL argument");
-  if (n_candidates < 0 || (n_candidates > 0 && !p_candidates)) return fail(PD_EINVAL, "bad candidate list");
-  for (int c = 0; c < n_candidates; ++c)
-    if (!(p_candidates[c] > 0.0)) return fail(PD_EINVAL, "stretch exponents must be > 0");
-  if (!(p_current > 0.0)) return fail(PD_EINVAL, "p_current must be > 0");
+  int rc = check_indicator_args(I, p_current, p_candidates, n_candidates, out);
+  if (rc) return rc;
   BusyGuard g({I});
   if (!g.ok) return fail(PD_EBUSY, "instance is in use");
   const int m = I->M.m, n = I->M.n;
@@ -1608,38 +1684,36 @@ int pd_error_indicator(pd_instance *I, double p_current, const double *p_candida
   pd::launch_indicator(H.sol[sol_slot(I->rot, 0)], m, n, H.r_nodes, H.th_nodes, H.nb, H.lam, H.tpow, H.nsrc,
                        I->t, I->bc == 0 ? 1 : 0, dbuf, eta ? dbuf + ring_vals : nullptr, s);
   HIPCHK(hipGetLastError());
-  std::vector<double> ring(ring_vals);
+  std::vector<double> ring(ring_vals), kap(m);
   HIPCHK(hipMemcpyAsync(ring.data(), dbuf, ring_vals * sizeof(double), hipMemcpyDeviceToHost, s));
   if (eta) HIPCHK(hipMemcpyAsync(eta, dbuf + ring_vals, eta_vals * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  pd_indicator R{};
-  R.eta_max = -1.0;
-  std::vector<double> kap(m);
-  for (int i = 1; i <= m; ++i) {
-    const double *q = &ring[4 * (size_t)(i - 1)];
-    kap[i - 1] = q[0];
-    if (q[1] > R.eta_max) {
-      R.eta_max = q[1];
-      R.i_max = i;
-      R.j_max = (int)q[2];
-    }
-    R.eta_sum += q[3];
-  }
-  if (kappa) std::copy(kap.begin(), kap.end(), kappa);
-  R.p_best = p_current;
-  R.pred_current = predicted_max(I->M.r, kap, m, p_current);
-  R.pred_best = R.pred_current;
-  bool found = false;
-  for (int c = 0; c < n_candidates; ++c) {
-    const double v = predicted_max(I->M.r, kap, m, p_candidates[c]);
-    if (!found || v < R.pred_best) {
-      R.pred_best = v;
-      R.p_best = p_candidates[c];
-      found = true;
-    }
-  }
-  R.recommend = (found && R.pred_best <= 0.8 * R.pred_current) ? 1 : 0;
-  *out = R;
+  indicator_summary(I, ring.data(), p_current, p_candidates, n_candidates, kappa, kap.data(), out);
+  return PD_OK;
+}
+
+int pd_error_indicator_noalloc(pd_instance *I, double p_current, const double *p_candidates,
+                               int32_t n_candidates, double *kappa, double *eta_device, pd_indicator *out) {
+  int rc = check_indicator_args(I, p_current, p_candidates, n_candidates, out);
+  if (rc) return rc;
+  const int m = I->M.m, n = I->M.n;
+  if (4 * (size_t)m > kIndScratch)
+    return fail(PD_EINVAL, "m = %d exceeds the scratch of the allocation-free indicator (%d rings)", m, kMaxM);
+  double *ring_dev = nullptr;
+  if ((rc = scratch_on(I->device, &ring_dev))) return rc;
+  BusyGuard g({I});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  hipStream_t s = I->stream;
+  const PdInst &H = I->H;
+  // k_indicator writes every ring's four values: nothing needs clearing
+  pd::launch_indicator(H.sol[sol_slot(I->rot, 0)], m, n, H.r_nodes, H.th_nodes, H.nb, H.lam, H.tpow, H.nsrc,
+                       I->t, I->bc == 0 ? 1 : 0, ring_dev, eta_device, s);
+  HIPCHK(hipGetLastError());
+  double ring[kIndScratch];
+  double kap[kMaxM];
+  HIPCHK(hipMemcpyAsync(ring, ring_dev, 4 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  indicator_summary(I, ring, p_current, p_candidates, n_candidates, kappa, kap, out);
   return PD_OK;
 }
 

@@ -98,7 +98,7 @@ class Indicator(C.Structure):
 EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
-           "pd_batch_stats", "pd_error_indicator", "pd_remesh_transfer", "pd_set_schedule",
+           "pd_batch_stats", "pd_error_indicator", "pd_error_indicator_noalloc", "pd_remesh_transfer", "pd_set_schedule",
            "pd_get_schedule", "pd_get_time",
            "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
 
@@ -131,6 +131,7 @@ def _load():
         "pd_batch_poll": [P, U64, P, C.POINTER(RequestSummary)],
         "pd_batch_stats": [P, C.POINTER(BatchInfo)],
         "pd_error_indicator": [P, D, P, I32, P, P, C.POINTER(Indicator)],
+        "pd_error_indicator_noalloc": [P, D, P, I32, P, P, C.POINTER(Indicator)],
         "pd_remesh_transfer": [P, P],
         "pd_set_schedule": [P],
         "pd_get_time": [P, P],
@@ -370,6 +371,22 @@ def error_indicator(inst: "Instance", p_current: float, candidates=(), want_eta=
     out = res.as_dict()
     out["kappa"] = kappa
     out["eta"] = eta.reshape(inst.m, inst.n) if eta is not None else None
+    return out
+
+
+def error_indicator_noalloc(inst: "Instance", p_current: float, candidates=(), eta_device_ptr=None):
+    """The same indicator through the allocation-free entry point; the field
+    (if wanted) goes to caller-owned device memory at eta_device_ptr (m*n
+    doubles, ring-major)."""
+    cand = _f64(list(candidates)) if len(candidates) else None
+    kappa = np.empty(inst.m)
+    res = Indicator()
+    _check(lib.pd_error_indicator_noalloc(inst.h, float(p_current), _ptr(cand) if cand is not None else None,
+                                          len(candidates), _ptr(kappa),
+                                          C.c_void_p(eta_device_ptr) if eta_device_ptr else None,
+                                          C.byref(res)))
+    out = res.as_dict()
+    out["kappa"] = kappa
     return out
 
 

@@ -26,3 +26,38 @@ def max_rel(a, b):
 
 def l2_rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+class DeviceBuffer:
+    """Device memory from the HIP runtime the library itself is linked
+    against (already loaded in this process), filled from a host array."""
+
+    def __init__(self, hip, arr):
+        import ctypes as C
+        self.hip = hip
+        self.a = np.ascontiguousarray(arr)
+        self.p = C.c_void_p()
+        assert hip.hipMalloc(C.byref(self.p), max(self.a.nbytes, 8)) == 0
+        assert hip.hipMemcpy(self.p, self.a.ctypes.data, self.a.nbytes, 1) == 0   # host to device
+
+    def read(self):
+        out = np.empty_like(self.a)
+        assert self.hip.hipMemcpy(out.ctypes.data, self.p, out.nbytes, 2) == 0   # device to host
+        return out
+
+    def free(self):
+        if self.p:
+            assert self.hip.hipFree(self.p) == 0
+            self.p = None
+
+
+def hip_runtime():
+    """The HIP runtime the loaded library resolved (by its soname, so the copy
+    already in the process is the one returned)."""
+    import ctypes as C
+    from paper_2509_15879_amd import polardisk  # noqa: F401  (loads the library first)
+    hip = C.CDLL("libamdhip64.so.7")
+    hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    hip.hipFree.argtypes = [C.c_void_p]
+    return hip

@@ -8,7 +8,7 @@ operator and the right-hand side) hold to a few ulps of the row sums.
 import numpy as np
 import pytest
 
-from helpers import gpu_instance, l2_rel, max_rel, oracle_system
+from helpers import DeviceBuffer, gpu_instance, hip_runtime, l2_rel, max_rel, oracle_system
 from oracle import solve, time_levels
 from oracle.stepper import rhs as oracle_rhs
 from oracle.stepper import step as oracle_step
@@ -338,40 +338,6 @@ def test_explicit_irregular_mesh_solve(precision):
     inst.close()
 
 
-class _DeviceBuffer:
-    """Device memory from the HIP runtime the library itself is linked
-    against (already loaded in this process), filled from a host array."""
-
-    def __init__(self, hip, arr):
-        import ctypes as C
-        self.hip = hip
-        self.a = np.ascontiguousarray(arr)
-        self.p = C.c_void_p()
-        assert hip.hipMalloc(C.byref(self.p), max(self.a.nbytes, 8)) == 0
-        assert hip.hipMemcpy(self.p, self.a.ctypes.data, self.a.nbytes, 1) == 0   # host to device
-
-    def read(self):
-        out = np.empty_like(self.a)
-        assert self.hip.hipMemcpy(out.ctypes.data, self.p, out.nbytes, 2) == 0   # device to host
-        return out
-
-    def free(self):
-        if self.p:
-            assert self.hip.hipFree(self.p) == 0
-            self.p = None
-
-
-def _hip_runtime():
-    import ctypes as C
-    paths = sorted({ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln and "torch" not in ln})
-    assert paths, "the library's HIP runtime is not loaded"
-    hip = C.CDLL(paths[0])
-    hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
-    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
-    hip.hipFree.argtypes = [C.c_void_p]
-    return hip
-
-
 def test_device_pointer_inputs_and_outputs():
     """Every array of the problem descriptor, λ and tpow included, may be a
     device pointer: an instance created from device copies solves bit for bit
@@ -385,7 +351,7 @@ def test_device_pointer_inputs_and_outputs():
     m, n, theta = 20, 48, 0.5
     N = m * n + 1
     say(f"[device pointers] continuity {m}x{n}")
-    hip = _hip_runtime()
+    hip = hip_runtime()
     md = pdk.mesh_desc(m, n, 1, 1.3)
     data = sample(continuity_cfg(1112, m, n), *pdk.mesh_coords(md))
     host = pdk.Instance(md, data, pdk.PD_FP64)
@@ -395,7 +361,7 @@ def test_device_pointer_inputs_and_outputs():
                        ("Et_tface", "Et"), ("lam", "lam"), ("tpow", "tpow"), ("g", "g"), ("nb", "nb"),
                        ("u0", "u0")):
         if key in pdd._keep:
-            bufs.append(_DeviceBuffer(hip, pdd._keep[key]))
+            bufs.append(DeviceBuffer(hip, pdd._keep[key]))
             setattr(pdd, field, bufs[-1].p.value)
     assert len(bufs) >= 9
     pdd.device_ptrs = 1
@@ -405,13 +371,13 @@ def test_device_pointer_inputs_and_outputs():
     devinst.solve(td)
     ref = host.solution(layout=1)
     assert np.array_equal(devinst.solution(layout=1), ref)
-    out = _DeviceBuffer(hip, np.zeros(N))
+    out = DeviceBuffer(hip, np.zeros(N))
     pdk._check(pdk.lib.pd_get_solution(devinst.h, out.p, 1, 1))
     assert np.array_equal(out.read(), ref)
-    x = _DeviceBuffer(hip, 0.5 * ref + 0.25)
+    x = DeviceBuffer(hip, 0.5 * ref + 0.25)
     pdk._check(pdk.lib.pd_set_solution(devinst.h, x.p, 1, 1, C.c_double(0.02)))
     assert np.array_equal(devinst.solution(layout=1), 0.5 * ref + 0.25)
-    y = _DeviceBuffer(hip, np.zeros(N))
+    y = DeviceBuffer(hip, np.zeros(N))
     pdk._check(pdk.lib.pd_apply_operator(devinst.h, C.c_double(1e-3), C.c_double(theta), x.p, y.p, 1, 1, 0))
     assert np.array_equal(y.read(), host.apply(0.5 * ref + 0.25, 1e-3, theta, layout=1))
     host.set_solution(0.5 * ref + 0.25, 0.02, layout=1)
