@@ -158,7 +158,16 @@ typedef struct {
  * [dt_min, dt_max] (q = 1, or 2 for θ = 1/2); the first step is dt0 and the
  * second tries dt0 again; steps land exactly on t_s + T.  K caps the number
  * of accepted steps (PD_ENOCONV if T is not reached); per-step statistics
- * past the steps taken are zero.  Not accepted by pd_batch_submit.      */
+ * past the steps taken are zero.  Not accepted by pd_batch_submit.
+ * Bounds of a solve call: the library stops launching work and returns
+ * PD_ENOCONV ("wall-clock limit") once max_seconds have passed on the host
+ * (the smallest limit of a batch applies), and once the batch has used the
+ * Krylov cycles its levels can need: levels x attempts per level x
+ * (max_iters + refinements + 8), where an adaptive solve can take at most
+ * ceil(T/dt_min) + 2 accepted steps and ceil(ln(dt_max/dt_min)/ln 1.4) + 1
+ * rejected attempts per step (each rejection shrinks Δt by at least 1/1.4).
+ * After either stop the instances keep the last completed level (their
+ * time says which) and may be solved again.                              */
 typedef struct {
   int32_t t_kind;
   int32_t K;
@@ -169,6 +178,8 @@ typedef struct {
   int32_t max_iters;
   double dt0, dt_min, dt_max;   /* PD_TIME_ADAPTIVE only                  */
   double tol_time;              /* PD_TIME_ADAPTIVE: local error tolerance */
+  double max_seconds;           /* host wall-clock limit of the solve call
+                                   (0: 600 s); see below                   */
 } pd_time_desc;
 
 typedef struct {

@@ -51,6 +51,8 @@ constexpr int kMaxM = 2048;
 constexpr int kMaxN = 2048;
 constexpr double kPi = 3.14159265358979323846;
 
+using Clock = std::chrono::steady_clock;
+
 // ------------------------------------------------------------------ mesh
 
 // §2.1 / §3.1: h = 1/(m+1), r_i = υ(i h) with υ from (2.4) or (2.13); the
@@ -642,7 +644,10 @@ struct SolveParams {
   int maxit, maxit_inner, max_outer;
   int adaptive = 0;
   double T = 0.0, dt_min = 0.0, dt_max = 0.0, tol_time = 0.0;
+  double max_seconds = 0.0;   // host wall-clock limit of the call (0: kDefaultMaxSeconds)
 };
+
+constexpr double kDefaultMaxSeconds = 600.0;
 
 int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   PdScalars h{};
@@ -820,14 +825,22 @@ struct Engine {
   // instances have taken all their levels) or max_cycles cycles have been
   // launched; returns whether everything finished.  Work stays queued on
   // the parts' streams; the caller's stream is joined to them.
-  int run(long max_cycles_run, bool *finished) {
+  // Replays stop early, with *timed_out set, once the host clock passes
+  // `deadline` (the work already queued still completes).
+  int run(long max_cycles_run, bool *finished, Clock::time_point deadline = Clock::time_point::max(),
+          bool *timed_out = nullptr) {
     const int ng = (int)G.size();
+    if (timed_out) *timed_out = false;
     HIPCHK(hipEventRecord(fork_ev, s));
     for (int k = 1; k < ng; ++k) HIPCHK(hipStreamWaitEvent(G[k].s, fork_ev, 0));
     std::vector<char> live(ng, 1);
     int left = ng;
     const long max_launch = (max_cycles_run + cpg - 1) / cpg;   // rounds of cpg cycles
     for (long c = 0; c < max_launch && left > 0; ++c) {
+      if (Clock::now() > deadline) {
+        if (timed_out) *timed_out = true;
+        break;
+      }
       for (int k = 0; k < ng; ++k) {
         if (!live[k]) continue;
         Plan &Q = *G[k].P;
@@ -884,6 +897,32 @@ struct Engine {
 
 int cycles_cap(SolveParams const &sp) { return sp.maxit + sp.max_outer + 8; }
 
+// Krylov cycles a solve of K levels can need: levels x attempts per level x
+// cycles per attempt.  An adaptive solve takes at most ceil(T/dt_min) + 2
+// accepted steps (every step but the last two is at least dt_min long) and,
+// per step, at most ceil(ln(dt_max/dt_min)/ln 1.4) + 1 rejected attempts: a
+// rejection has e > 2 tol_time, so it shrinks Δt by 0.9 (1/2)^{1/(q+1)} <=
+// 1/1.4 or more, and stops once Δt reaches dt_min.
+long solve_cycle_bound(SolveParams const &sp, int K) {
+  long levels = K, attempts = 1;
+  if (sp.adaptive && sp.dt_min > 0.0) {
+    levels = std::min<long>(K, (long)std::ceil(sp.T / sp.dt_min) + 2);
+    attempts = 2 + (long)std::ceil(std::log(std::max(1.0, sp.dt_max / sp.dt_min)) / std::log(1.4));
+  }
+  return levels * attempts * (long)cycles_cap(sp) + 2 * levels;
+}
+
+// After a solve that stopped early: the host mirror of the instance follows
+// its last completed level (the level under way, if any, is dropped).
+int sync_host_state(pd_instance *I) {
+  PdScalars h{};
+  HIPCHK(hipMemcpy(&h, I->sc, sizeof h, hipMemcpyDeviceToHost));
+  I->rot = h.rot;
+  I->t = h.t_now;
+  I->have_prev = false;
+  return PD_OK;
+}
+
 // Per-level statistics of an instance after a solve: PD_LSTAT doubles per
 // level; an adaptive solve takes fewer levels than its cap K (the rest stay
 // zero), and fails when the cap came before T.
@@ -908,22 +947,32 @@ int read_level_stats(pd_instance *I, int K, std::vector<double> &st, int &worst)
 // Runs all levels of every instance (instance q has Ks[q] levels).
 int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &Ks,
                std::vector<SolveParams> const &sps, hipStream_t s, std::vector<std::vector<double>> *stats_out) {
-  int rc, maxK = 0, cap = 0;
+  const Clock::time_point t_start = Clock::now();
+  int rc, cap = 0;
+  long bound = 0;
+  double max_s = 0.0;
   for (size_t q = 0; q < insts.size(); ++q) {
     if ((rc = init_scalars(insts[q], sps[q], Ks[q], s))) return rc;
-    maxK = std::max(maxK, Ks[q]);
     cap = std::max(cap, cycles_cap(sps[q]));
+    bound = std::max(bound, solve_cycle_bound(sps[q], Ks[q]));
+    const double lim = sps[q].max_seconds > 0.0 ? sps[q].max_seconds : kDefaultMaxSeconds;
+    max_s = q == 0 ? lim : std::min(max_s, lim);
   }
   Engine E;
   bool adaptive = false;
   for (auto const &sp : sps) adaptive |= sp.adaptive != 0;
   if ((rc = E.build(insts, cap, s, default_schedule(), adaptive))) return rc;
-  bool finished = false;
-  if ((rc = E.run((long)maxK * cap + 2 * maxK, &finished))) return rc;
+  bool finished = false, timed_out = false;
+  const auto deadline = t_start + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(max_s));
+  if ((rc = E.run(bound, &finished, deadline, &timed_out))) return rc;
   HIPCHK(hipGetLastError());
   for (auto &g : E.G) HIPCHK(hipStreamSynchronize(g.s));
   HIPCHK(hipStreamSynchronize(s));
-  if (!finished) return fail(PD_ENOCONV, "the batch did not finish within its cycle cap");
+  if (!finished) {
+    for (auto *I : insts) (void)sync_host_state(I);
+    if (timed_out) return fail(PD_ENOCONV, "the solve passed its wall-clock limit of %g s", max_s);
+    return fail(PD_ENOCONV, "the batch did not finish within its cycle bound (%ld cycles)", bound);
+  }
   int worst = PD_OK;
   for (size_t q = 0; q < insts.size(); ++q) {
     std::vector<double> st;
@@ -966,6 +1015,7 @@ SolveParams params_from(const pd_time_desc *td, int precision) {
   sp.tol_inner = 1e-3;
   sp.maxit_inner = 400;
   sp.max_outer = precision == PD_MIXED ? 40 : 0;
+  sp.max_seconds = td->max_seconds;
   if (td->t_kind == PD_TIME_ADAPTIVE) {
     sp.adaptive = 1;
     sp.T = td->T;
@@ -1750,7 +1800,6 @@ int pd_remesh_transfer(pd_instance *from, pd_instance *to) {
 
 namespace {
 
-using Clock = std::chrono::steady_clock;
 
 struct Request {
   uint64_t ticket = 0;

@@ -50,7 +50,7 @@ class TimeDesc(C.Structure):
     _fields_ = [("t_kind", C.c_int32), ("K", C.c_int32), ("T", C.c_double), ("l", C.c_double),
                 ("t_table", C.c_void_p), ("theta", C.c_double), ("tol", C.c_double),
                 ("max_iters", C.c_int32), ("dt0", C.c_double), ("dt_min", C.c_double),
-                ("dt_max", C.c_double), ("tol_time", C.c_double)]
+                ("dt_max", C.c_double), ("tol_time", C.c_double), ("max_seconds", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -196,9 +196,10 @@ def ring_vector(origin, grid):
     return np.concatenate([[float(origin)], np.asarray(grid, np.float64).reshape(-1)])
 
 
-def time_desc(theta, K, T=None, t_kind=TIME_UNIFORM, l=1.0, table=None, tol=1e-12, max_iters=0):
+def time_desc(theta, K, T=None, t_kind=TIME_UNIFORM, l=1.0, table=None, tol=1e-12, max_iters=0,
+              max_seconds=0.0):
     td = TimeDesc(int(t_kind), int(K), float(T or 0.0), float(l), None, float(theta), float(tol),
-                  int(max_iters), 0.0, 0.0, 0.0, 0.0)
+                  int(max_iters), 0.0, 0.0, 0.0, 0.0, float(max_seconds))
     if table is not None:
         a = _f64(table)
         td.t_table = _ptr(a)
@@ -207,12 +208,14 @@ def time_desc(theta, K, T=None, t_kind=TIME_UNIFORM, l=1.0, table=None, tol=1e-1
     return td
 
 
-def adaptive_time_desc(theta, T, dt0, tol_time, dt_min, dt_max, K_max=20000, tol=1e-12, max_iters=0):
+def adaptive_time_desc(theta, T, dt0, tol_time, dt_min, dt_max, K_max=20000, tol=1e-12, max_iters=0,
+                       max_seconds=0.0):
     """A-posteriori step control from the current time to T later: the GPU
     picks every Δt from its local error estimate (statistics past the steps
     taken have dt = 0)."""
     return TimeDesc(TIME_ADAPTIVE, int(K_max), float(T), 1.0, None, float(theta), float(tol),
-                    int(max_iters), float(dt0), float(dt_min), float(dt_max), float(tol_time))
+                    int(max_iters), float(dt0), float(dt_min), float(dt_max), float(tol_time),
+                    float(max_seconds))
 
 
 def taken(stats):
