@@ -1,17 +1,20 @@
 #!/usr/bin/env python
 """Throughput benchmark of the polar-disk θ-scheme solver on one MI355X.
 
-Workload (one "step" = one pass of the whole hot path over one batch): the
-drift-diffusion continuity problem on a 256 x 512 polar mesh graded towards
-r = 0 and r = 1 (radial stretch (2.4), p = 1.3), seeded diffusivity
-D = 1 + ½ sin(kθ) r² and Fourier-Bessel drift E = -∇ψ, manufactured exact
-solution, time levels t_k = T sin((k/K)^l π/2) with T = 0.05, K = 100,
-l = 1.5 (Δt from 1.4e-5 to 7.1e-4), five seeds x θ ∈ {0.5, 1}: ten instances
-of 131,073 unknowns, all advanced from t = 0 to T in the same batched
-launches.  Metric: cell-updates/s = Σ unknowns x levels / wall time, with
-every instance's result within 1e-8 (L2-relative) of a fully converged FP64
-solution.  The oracle (FP64 sparse LU on the host) is timed beside it on a
-bounded sample of the same workload.
+Headline workload (one "step" = one pass of the whole hot path): the
+drift-diffusion continuity problem on a 1024 x 2048 polar mesh graded
+towards r = 0 and r = 1 (radial stretch (2.4), p = 1.3; 2,097,153
+unknowns), seeded diffusivity D = 1 + ½ sin(kθ) r² and Fourier-Bessel drift
+E = -∇ψ, manufactured exact solution, Crank-Nicolson (θ = 0.5), fixed
+Δt = 2.5e-4, 200 levels to T = 0.05, all in FP64.  Metric: cell-updates/s =
+unknowns x levels / wall time, valid when the result is within 1e-8
+(L2-relative) of the FP64 oracle's solution of the same 200 levels, whose
+samples are stored by tests/golden/make_cfg3_reference.py.  The oracle
+(FP64 sparse LU on the host) is timed on a bounded sample of the same
+workload in a child process beside the GPU legs.  Variants (not the
+headline): the same workload in mixed precision, the ten-instance 256 x 512
+batch, adaptive time steps, the runs of Table 2.1, the 512-instance uneven
+sweep and the serving loop under a Poisson request stream.
 """
 
 import argparse
@@ -44,12 +47,17 @@ KERNEL_NAMES = {
 }
 
 
-# HBM bytes per active unknown that each kernel moved (FETCH_SIZE and
-# WRITE_SIZE counters, calibrated on a copy of known size), valid for the
-# sources with this SHA-1 only (kernel_source_sha1); any other source
-# reports traffic null.
-TRAFFIC_SOURCE_SHA1 = "bbd27df650443088c565f76e1e047c6beb0124fc"
-TRAFFIC_B_PER_CELL = {"rad_p": 54.72, "ang_p": 32.47, "sten_v": 64.90, "rad_s": 44.21, "ang_s": 32.47, "sten_t": 65.03, "update": 64.53}
+# HBM bytes per active unknown that each kernel moved on the headline
+# workload (FETCH_SIZE and WRITE_SIZE counters, calibrated on a copy of known
+# size), valid for the sources with this SHA-1 only (kernel_source_sha1);
+# any other source reports traffic null.
+TRAFFIC = {
+    "cfg3_fp64": {
+        "sha1": "34e5c07bdc2e47d26d75948929a745bdfb62d96f",
+        "b_per_cell": {"rad_p": 52.76, "ang_p": 32.23, "sten_v": 62.89, "rad_s": 44.23, "ang_s": 32.23,
+                       "sten_t": 62.41, "update": 64.53},
+    },
+}
 
 
 def code_digest(texts):
@@ -117,46 +125,33 @@ def reset(insts, u0s):
         inst.set_solution(u0, 0.0)
 
 
-def precision_variant(pdk, stream, tol):
-    """The 1024 x 2048 graded continuity problem (2,097,153 unknowns), fixed
-    Δt = 2.5e-4, 200 levels: FP64 and mixed precision each timed alone,
-    both measured against a converged FP64 solve (tolerance 1e-13)."""
+def mixed_cfg3_variant(pdk, stream, tol, ref):
+    """The headline workload in mixed precision (FP32 inner iterations, FP64
+    refinement), under its own tuned schedule, against the oracle's stored
+    samples."""
     import torch
-    from problems import sample
-    from problems.workloads import CFG3, cfg3_problem
+    from paper_2509_15879_amd import autotune
+    from problems.workloads import CFG3
     c = CFG3
-    md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
-    data = sample(cfg3_problem(), *pdk.mesh_coords(md))
     cells = c["m"] * c["n"] + 1
-
-    def run(prec, t, tune=False):
-        inst = pdk.Instance(md, data, prec, stream=stream)
-        td = pdk.time_desc(c["theta"], c["K"], c["dt"] * c["K"], pdk.TIME_UNIFORM, tol=t)
-        if tune:
-            from paper_2509_15879_amd import autotune
-            sched.append(autotune.tune([inst], [td], levels=TUNE_LEVELS, sync=torch.cuda.synchronize)["best"])
+    inst, u0 = cfg3_instance(pdk, pdk.PD_MIXED, stream)
+    desc = cfg3_desc(pdk, tol)
+    inst.set_solution(u0, 0.0)
+    tuned = autotune.tune([inst], [desc], levels=TUNE_LEVELS, sync=torch.cuda.synchronize)
+    best, st = float("inf"), None
+    for rep in range(2):
+        inst.set_solution(u0, 0.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = inst.solve(td)
+        st = inst.solve(desc)
         torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        x = inst.solution()
-        inst.close()
-        return x, el, st
-
-    sched = []
-    ref, _, _ = run(pdk.PD_FP64, 1e-13)
-    out = {"workload": "continuity 1024x2048 graded (p=1.3), dt=2.5e-4 fixed, 200 levels, theta=0.5",
-           "tol_per_step": tol}
-    for name, prec in (("fp64", pdk.PD_FP64), ("mixed", pdk.PD_MIXED)):
-        x, el, st = run(prec, tol, tune=True)
-        out[name] = {"value": round(cells * c["K"] / el, 1), "ms": round(1e3 * el, 1),
-                     "l2_rel_vs_fp64_converged": float(np.linalg.norm(x - ref) / np.linalg.norm(ref)),
-                     "iters_per_level": round(float(np.mean([s["iters"] for s in st])), 2),
-                     "schedule": list(sched[-1])}
-        if prec == pdk.PD_MIXED:
-            out[name]["refinements_per_level"] = round(float(np.mean([s["refinements"] for s in st])), 2)
-    return out
+        best = min(best, time.perf_counter() - t0)
+    x = inst.solution(pdk.LAYOUT_PAPER)
+    inst.close()
+    return {"value": round(cells * c["K"] / best, 1), "ms": round(1e3 * best, 1), "tol_per_step": tol,
+            "schedule": list(tuned["best"]), "vs_oracle": vs_oracle_samples(x, ref, c["K"]),
+            "inner_iters_per_level": round(float(np.mean([s["iters"] for s in st])), 2),
+            "refinements_per_level": round(float(np.mean([s["refinements"] for s in st])), 2)}
 
 
 def uneven_variant(pdk, stream, tol, sample_alone=32):
@@ -390,142 +385,139 @@ def serving_variant(pdk, duration=8.0, check=6):
     }
 
 
-def cpu_baseline(levels, gpu_states):
-    """The oracle on a bounded sample: one instance (seed 1200, θ = 0.5), the
-    first `levels` time levels, one thread."""
+def cpu_info():
+    """CPU model (from /proc/cpuinfo) and os.cpu_count() of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline_worker(levels, out_path):
+    """The oracle on a bounded sample of the headline workload, one thread:
+    mesh, sampling, assembly, one SuperLU factorisation (fixed Δt) and the
+    first `levels` levels.  Writes its timings and state to out_path (npz).
+    Runs in a child process started before anything touches the GPU."""
     from threadpoolctl import threadpool_limits
-    from oracle import assemble, make_mesh, solve, time_levels
-    from problems import continuity_cfg, sample
-    pb = continuity_cfg(SEEDS[0], M, N_TH, THETAS[0], P_STRETCH, T_END, K_LEVELS, L_TIME)
-    t_all = time_levels(T_END, K_LEVELS, 1, L_TIME)
+    from oracle import assemble, make_mesh
+    from oracle.stepper import step
+    from problems import sample
+    from problems.workloads import CFG3, cfg3_problem
+    c = CFG3
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        me = make_mesh(M, N_TH, 1, P_STRETCH)
-        S = assemble(me, sample(pb, *me.sample_points()))
-        x = solve(S, t_all[:levels + 1], THETAS[0])
-        el = time.perf_counter() - t0
-    cells = M * N_TH + 1
-    ref = gpu_states
-    err = float(np.max(np.abs(ref - x)) / np.max(np.abs(x))) if ref is not None else None
-    return {
-        "value": cells * levels / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-        "sample": (f"seed {SEEDS[0]}, theta {THETAS[0]}, first {levels} of {K_LEVELS} levels "
-                   f"({cells} unknowns; mesh, sampling, assembly, one SuperLU factorisation and "
-                   f"solve per level; {el:.1f} s)"),
-        "gpu_vs_oracle_max_rel": err,
+        me = make_mesh(c["m"], c["n"], 1, c["p"])
+        S = assemble(me, sample(cfg3_problem(), *me.sample_points()))
+        x = S.initial()
+        t_setup = time.perf_counter() - t0
+        marks = []
+        for k in range(levels):
+            x = step(S, x, k * c["dt"], (k + 1) * c["dt"], c["theta"])
+            marks.append(time.perf_counter() - t0)
+    np.savez(out_path, x=x, t_setup=t_setup, marks=np.array(marks))
+
+
+def start_cpu_baseline(levels):
+    import subprocess
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".npz", prefix="pd_oracle_")
+    os.close(fd)
+    proc = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
+                             str(levels), path], stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+    return proc, path, time.perf_counter()
+
+
+def finish_cpu_baseline(job, levels, gpu_state):
+    """Waits for the oracle sample; its rate and its difference from the GPU
+    state after the same levels (full vectors, paper order)."""
+    proc, path, t_launch = job
+    _, err = proc.communicate()
+    if proc.returncode != 0:
+        return {"error": err.decode(errors="replace")[-2000:]}
+    from problems.workloads import CFG3
+    c = CFG3
+    d = np.load(path)
+    os.unlink(path)
+    x, t_setup, marks = d["x"], float(d["t_setup"]), d["marks"]
+    N = c["m"] * c["n"] + 1
+    el = float(marks[-1])
+    t_fact = float(marks[0]) - t_setup                 # first level: factorisation + solve
+    t_level = (el - float(marks[0])) / max(1, levels - 1)
+    full = t_setup + t_fact + (c["K"] - 1) * t_level
+    out = {
+        "value": N * levels / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+        "sample": (f"the headline workload's first {levels} of {c['K']} levels on one thread: mesh, "
+                   f"sampling, assembly ({t_setup:.1f} s), one SuperLU factorisation with the first "
+                   f"level ({t_fact:.1f} s), then {t_level:.1f} s per level (LU solve + one refinement "
+                   f"step); {el:.1f} s in all, run beside the GPU legs in a child process"),
+        "full_run_estimate_cell_updates_per_s": N * c["K"] / full,
+        "full_run_estimate_s": round(full, 1),
+        **cpu_info(),
     }
+    if gpu_state is not None:
+        out["gpu_vs_oracle_same_levels"] = {
+            "max_rel": float(np.max(np.abs(gpu_state - x)) / np.max(np.abs(x))),
+            "l2_rel": float(np.linalg.norm(gpu_state - x) / np.linalg.norm(x)),
+            "levels": levels}
+    return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--tol", type=float, default=4e-12)
-    ap.add_argument("--oracle-levels", type=int, default=16)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--schedule", default=None,
-                    help="groups,cycles_per_graph,fp32_stencil_rings: use this schedule instead of tuning "
-                         "the batch (e.g. to profile the schedule an un-profiled run chose)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(instances are independent; a multi-GPU run would shard them by footprint)",
-              file=sys.stderr)
-        sys.exit(2)
+def oracle_samples():
+    """The oracle's stored trajectory of the headline workload (levels 20
+    and 200, sampled; written by tests/golden/make_cfg3_reference.py)."""
+    path = os.path.join(ROOT, "tests", "golden", "cfg3_oracle_samples.npz")
+    return np.load(path)
 
-    import torch
-    from paper_2509_15879_amd import polardisk as pdk
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream().cuda_stream
-    prec = pdk.PD_MIXED if args.precision == "mixed" else pdk.PD_FP64
 
-    log("building instances ...")
-    insts, tds, u0s = build_instances(pdk, prec, stream)
-    cells = sum(i.N for i in insts)
+def vs_oracle_samples(x_paper, ref, level):
+    """Max-rel (normwise, by the full state's max norm) and L2-rel over the
+    stored samples of the oracle's state at `level`."""
+    idx = ref["indices"]
+    xr = ref[f"x_{level}"]
+    d = x_paper[idx] - xr
+    return {"max_rel": float(np.max(np.abs(d)) / float(ref[f"maxabs_{level}"])),
+            "l2_rel_samples": float(np.linalg.norm(d) / np.linalg.norm(xr)),
+            "samples": int(len(idx))}
 
-    # fully converged FP64 reference of every instance
-    log("reference solve (FP64, tol 1e-13) ...")
-    refs_insts = insts if prec == pdk.PD_FP64 else build_instances(pdk, pdk.PD_FP64, stream)[0]
-    reset(refs_insts, u0s)
-    pdk.solve_batch(refs_insts, time_descs(pdk, tds, 1e-13))
-    refs = [i.solution() for i in refs_insts]
-    # GPU state after the oracle's sample levels (instance 0), for the sampled parity
-    t_all = pdk.time_levels(pdk.time_desc(THETAS[0], K_LEVELS, T_END, pdk.TIME_SINE, L_TIME))
-    inst0 = refs_insts[0]
-    inst0.set_solution(u0s[0], 0.0)
-    inst0.solve(pdk.time_desc(THETAS[0], args.oracle_levels, table=t_all[:args.oracle_levels + 1],
-                              tol=1e-13))
-    sample_state = inst0.solution(pdk.LAYOUT_PAPER)
 
-    descs = time_descs(pdk, tds, args.tol)
-    # launch schedule (stream groups, cycles per graph) chosen by the
-    # autotuner on whole solves of this batch, outside the timed region
-    from paper_2509_15879_amd import autotune
-    reset(insts, u0s)
-    if args.schedule:
-        fixed = tuple(int(v) for v in args.schedule.split(","))
-        pdk.set_schedule(*fixed)
-        tuned = {"best": fixed, "ms": {}}
-    else:
-        tuned = autotune.tune(insts, descs, levels=K_LEVELS, repeats=1, sync=torch.cuda.synchronize)
-    log(f"schedule {tuned['best']} from {tuned['ms']}")
-    for w in range(args.warmup):
-        reset(insts, u0s)
-        pdk.solve_batch(insts, descs)
-    torch.cuda.synchronize()
+def cfg3_instance(pdk, prec, stream):
+    from problems import sample
+    from problems.workloads import CFG3, cfg3_problem
+    c = CFG3
+    md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
+    data = sample(cfg3_problem(), *pdk.mesh_coords(md))
+    inst = pdk.Instance(md, data, prec, stream=stream)
+    return inst, pdk.ring_vector(data["u0_origin"], data["u0_grid"])
 
-    lat, stats = [], None
-    for s in range(args.steps):
-        reset(insts, u0s)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stats = pdk.solve_batch(insts, descs)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-        log(f"step {s}: {lat[-1] * 1e3:.1f} ms")
-    ms_per_step = 1e3 * float(np.mean(lat))
-    value = cells * K_LEVELS / (ms_per_step / 1e3)
 
-    # accuracy of the timed result against the converged FP64 solution
-    errs_l2, errs_max = [], []
-    for inst, ref in zip(insts, refs):
-        x = inst.solution()
-        errs_l2.append(float(np.linalg.norm(x - ref) / np.linalg.norm(ref)))
-        errs_max.append(float(np.max(np.abs(x - ref)) / np.max(np.abs(ref))))
-    valid = max(errs_l2) <= 1e-8
+def cfg3_desc(pdk, tol, K=None):
+    from problems.workloads import CFG3
+    c = CFG3
+    K = c["K"] if K is None else K
+    return pdk.time_desc(c["theta"], K, c["dt"] * K, pdk.TIME_UNIFORM, tol=tol, max_seconds=120.0)
 
-    # roofline of the dominant kernel: one more step of the same workload
-    # with every launch stamped by a start and a stop event of its own
-    # dispatch (the timed steps replay captured graphs, which carry none)
-    # (one stream group, so that no other launch shares the GPU with the one
-    # being stamped)
-    reset(insts, u0s)
-    torch.cuda.synchronize()
-    timed_schedule = pdk.get_schedule()
-    pdk.set_schedule(1, timed_schedule["cycles_per_graph"], timed_schedule["fp32_stencil_rings"])
+
+def roofline_of(pdk, run_step, w, cells_iters, traffic_table):
+    """Event-stamped extra step: per-family launch times; the dominant
+    kernel's algorithmic bytes per launch over its average launch time."""
     pdk.kernel_timing(True, reset=True)
     t0 = time.perf_counter()
-    pstats = pdk.solve_batch(insts, descs)
-    torch.cuda.synchronize()
+    run_step()
     prof_ms = 1e3 * (time.perf_counter() - t0)
     kms, kcnt = pdk.kernel_timing(False, reset=True)
-    pdk.set_schedule(timed_schedule["groups"], timed_schedule["cycles_per_graph"],
-                     timed_schedule["fp32_stencil_rings"])
-    w = 4 if prec == pdk.PD_MIXED else 8
-    iters = [sum(s["iters"] for s in st) for st in pstats]      # per instance
-    inst_cells = [i.N for i in insts]
-    cell_iters = sum(c * it for c, it in zip(inst_cells, iters))
-    fam_bytes = {f: cell_iters * bytes_per_cell(f, w) for f in KERNEL_NAMES}
+    fam_bytes = {f: cells_iters * bytes_per_cell(f, w) for f in KERNEL_NAMES}
     dom = max(fam_bytes, key=lambda f: kms[f])
     achieved = fam_bytes[dom] / (kms[dom] / 1e3) / 1e9
     traffic = None
-    if w == 8 and kernel_source_sha1() == TRAFFIC_SOURCE_SHA1:
-        traffic = round(TRAFFIC_B_PER_CELL[dom] * cell_iters / max(1, kcnt[dom]))
-    roofline = {
+    if traffic_table is not None and kernel_source_sha1() == traffic_table["sha1"]:
+        traffic = round(traffic_table["b_per_cell"][dom] * cells_iters / max(1, kcnt[dom]))
+    return {
         "bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
@@ -533,92 +525,209 @@ def main():
         "bytes_per_launch": round(fam_bytes[dom] / max(1, kcnt[dom])),
         "kernel_gbs": {f: round(fam_bytes[f] / (kms[f] / 1e3) / 1e9, 1) for f in fam_bytes if kms[f] > 0},
         "kernel_avg_us": {f: round(1e3 * kms[f] / kcnt[f], 2) for f in kms if kcnt[f] > 0},
+        "kernel_launches": {f: int(kcnt[f]) for f in kms if kcnt[f] > 0},
         "kernel_ms": {k: round(v, 2) for k, v in kms.items()},
         "profiled_step_ms": round(prof_ms, 1),
         "measured_on": "an extra step, each launch stamped by its own start/stop events",
     }
 
+
+def batch_variant(pdk, stream, tol):
+    """The ten-instance 256 x 512 batch (five seeds x θ in {0.5, 1}, 100
+    sine-stretched levels): FP64 batched, FP64 one instance at a time and
+    mixed batched, each against a converged FP64 solve."""
+    import torch
+    from paper_2509_15879_amd import autotune
+    insts, tds, u0s = build_instances(pdk, pdk.PD_FP64, stream)
+    cells = sum(i.N for i in insts)
+    reset(insts, u0s)
+    pdk.solve_batch(insts, time_descs(pdk, tds, 1e-13))
+    refs = [i.solution() for i in insts]
+    descs = time_descs(pdk, tds, tol)
+    out = {"workload": ("continuity drift-diffusion, 256x512 graded (p=1.3), 100 sine-stretched levels to "
+                        "T=0.05, 5 seeds x theta {0.5,1} = 10 instances"), "tol_per_step": tol}
+
+    def timed(instances, ds):
+        reset(instances, u0s)
+        pdk.solve_batch(instances, ds)
+        reset(instances, u0s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = pdk.solve_batch(instances, ds)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
+    reset(insts, u0s)
+    tuned = autotune.tune(insts, descs, levels=K_LEVELS, repeats=1, sync=torch.cuda.synchronize)
+    el, st = timed(insts, descs)
+    errs = [float(np.linalg.norm(i.solution() - r) / np.linalg.norm(r)) for i, r in zip(insts, refs)]
+    out["fp64_batched"] = {"value": round(cells * K_LEVELS / el, 1), "ms": round(1e3 * el, 1),
+                           "schedule": list(tuned["best"]), "l2_rel_vs_fp64_converged_max": max(errs),
+                           "iters_per_level": round(float(np.mean([sum(s["iters"] for s in x) for x in st]))
+                                                    / K_LEVELS, 2)}
+    t_alone = 0.0
+    for inst, u0, d in zip(insts, u0s, descs):
+        inst.set_solution(u0, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inst.solve(d)
+        torch.cuda.synchronize()
+        t_alone += time.perf_counter() - t0
+    out["fp64_one_instance_at_a_time"] = {"value": round(cells * K_LEVELS / t_alone, 1),
+                                          "ms": round(1e3 * t_alone, 1)}
+    mix, _, _ = build_instances(pdk, pdk.PD_MIXED, stream)
+    reset(mix, u0s)
+    mtuned = autotune.tune(mix, descs, levels=K_LEVELS, repeats=1, sync=torch.cuda.synchronize)
+    el, mst = timed(mix, descs)
+    me = max(float(np.linalg.norm(i.solution() - r) / np.linalg.norm(r)) for i, r in zip(mix, refs))
+    out["mixed_batched"] = {"value": round(cells * K_LEVELS / el, 1), "ms": round(1e3 * el, 1),
+                            "schedule": list(mtuned["best"]), "l2_rel_vs_fp64_converged_max": me,
+                            "inner_iters_per_level": round(float(np.mean(
+                                [sum(s["iters"] for s in x) for x in mst])) / K_LEVELS, 2),
+                            "refinements_per_level": round(float(np.mean(
+                                [sum(s["refinements"] for s in x) for x in mst])) / K_LEVELS, 2)}
+    for i in insts + mix:
+        i.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-12,
+                    help="per-step scaled-residual tolerance of the headline solve")
+    ap.add_argument("--oracle-levels", type=int, default=2)
+    ap.add_argument("--serving-seconds", type=float, default=60.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--schedule", default=None,
+                    help="groups,cycles_per_graph,fp32_stencil_rings: use this schedule instead of tuning "
+                         "(e.g. to profile the schedule an un-profiled run chose)")
+    ap.add_argument("--cpu-baseline-worker", nargs=2, default=None, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(int(args.cpu_baseline_worker[0]), args.cpu_baseline_worker[1])
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(instances are independent; a multi-GPU run would shard them by footprint)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    # the oracle's sample runs in a child process beside the GPU legs; it is
+    # started before anything touches the GPU
+    job = None if args.no_cpu_baseline else start_cpu_baseline(args.oracle_levels)
+
+    import torch
+    from paper_2509_15879_amd import autotune
+    from paper_2509_15879_amd import polardisk as pdk
+    from problems.workloads import CFG3
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    c = CFG3
+    cells = c["m"] * c["n"] + 1
+
+    log("headline: 1024x2048 instance ...")
+    inst, u0 = cfg3_instance(pdk, pdk.PD_FP64, stream)
+    desc = cfg3_desc(pdk, args.tol)
+
+    def run_step():
+        inst.set_solution(u0, 0.0)
+        return inst.solve(desc)
+
+    inst.set_solution(u0, 0.0)
+    if args.schedule:
+        fixed = tuple(int(v) for v in args.schedule.split(","))
+        pdk.set_schedule(*fixed)
+        tuned = {"best": fixed, "ms": {}}
+    else:
+        tuned = autotune.tune([inst], [desc], levels=TUNE_LEVELS, sync=torch.cuda.synchronize)
+    log(f"schedule {tuned['best']} from {tuned['ms']}")
+    for w in range(args.warmup):
+        run_step()
+    torch.cuda.synchronize()
+    lat, stats = [], None
+    for s in range(args.steps):
+        inst.set_solution(u0, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = inst.solve(desc)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        log(f"step {s}: {lat[-1] * 1e3:.1f} ms")
+    ms_per_step = 1e3 * float(np.mean(lat))
+    value = cells * c["K"] / (ms_per_step / 1e3)
+    x = inst.solution(pdk.LAYOUT_PAPER)
+    iters = sum(s["iters"] for s in stats)
+
+    # accuracy: the oracle's stored trajectory (sampled) and a converged GPU FP64 solve
+    ref = oracle_samples()
+    acc = vs_oracle_samples(x, ref, c["K"])
+    conv = pdk.Instance.__new__(pdk.Instance)
+    conv_inst, _ = cfg3_instance(pdk, pdk.PD_FP64, stream)
+    conv_inst.solve(cfg3_desc(pdk, 1e-13))
+    xc = conv_inst.solution(pdk.LAYOUT_PAPER)
+    conv_inst.close()
+    del conv
+    acc["l2_rel_vs_gpu_fp64_tol_1e-13"] = float(np.linalg.norm(x - xc) / np.linalg.norm(xc))
+    acc["valid"] = acc["l2_rel_samples"] <= 1e-8
+    acc["bar"] = "L2-relative <= 1e-8 against the FP64 oracle (levels 200, stored samples)"
+
+    # roofline of the dominant kernel on one more, event-stamped step
+    roof = roofline_of(pdk, run_step, 8, cells * iters, TRAFFIC.get("cfg3_fp64"))
+    # the GPU state after the oracle sample's levels, for the live comparison
+    early = None
+    if job is not None:
+        inst.set_solution(u0, 0.0)
+        inst.solve(cfg3_desc(pdk, args.tol, K=args.oracle_levels))
+        early = inst.solution(pdk.LAYOUT_PAPER)
+    inst.close()
+
     out = {
         "metric": "cell-updates/s (cells×steps/s) at 1e-8 rel err vs FP64; p50/p99 solve latency",
         "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w == 8 else "f32+f64",
-        "data": "synthetic (seeded manufactured continuity problems)",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded manufactured continuity problem)",
         "config": {
-            "workload": ("continuity drift-diffusion, 256x512 polar mesh graded (p=1.3), "
-                         "100 sine-stretched levels to T=0.05, 5 seeds x theta {0.5,1} = 10 "
-                         "instances batched"),
-            "instances": len(insts), "m": M, "n": N_TH, "unknowns_per_instance": M * N_TH + 1,
-            "levels": K_LEVELS, "tol_per_step": args.tol, "precision": args.precision,
-            "parallelism": "single GPU, batched instances",
+            "workload": ("continuity drift-diffusion on a 1024x2048 polar mesh graded towards r=0 and r=1 "
+                         "(radial stretch (2.4), p=1.3; 2,097,153 unknowns), seed 1300, theta=0.5 "
+                         "(Crank-Nicolson), fixed dt=2.5e-4, 200 levels to T=0.05"),
+            "m": c["m"], "n": c["n"], "unknowns": cells, "levels": c["K"], "tol_per_step": args.tol,
+            "precision": "fp64", "parallelism": "single GPU, one instance",
             "schedule": {"groups": tuned["best"][0], "cycles_per_graph": tuned["best"][1],
-                         "fp32_stencil_rings": tuned["best"][2],
-                         "autotune_ms_first_levels": tuned["ms"]},
+                         "fp32_stencil_rings": tuned["best"][2], "autotune_ms_first_levels": tuned["ms"]},
         },
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
-        "accuracy": {"l2_rel_vs_fp64_converged_max": max(errs_l2),
-                     "max_rel_vs_fp64_converged_max": max(errs_max), "valid": valid},
-        "iters_per_level_mean": round(float(np.mean([sum(s["iters"] for s in st) for st in stats]))
-                                      / K_LEVELS, 2),
-        "roofline": roofline,
+        "accuracy": acc,
+        "iters_per_level_mean": round(iters / c["K"], 2),
+        "roofline": roof,
     }
 
     if not args.no_variants:
-        # same workload, one instance at a time (FP64) and batched mixed precision
         var = {}
-        t0 = time.perf_counter()
-        for inst, u0, d in zip(insts if prec == pdk.PD_FP64 else refs_insts, u0s,
-                               time_descs(pdk, tds, args.tol)):
-            inst.set_solution(u0, 0.0)
-            torch.cuda.synchronize()
-            inst.solve(d)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        var["fp64_one_instance_at_a_time"] = {"value": round(cells * K_LEVELS / el, 1),
-                                              "ms": round(1e3 * el, 1)}
-        if prec == pdk.PD_FP64:
-            mix, _, _ = build_instances(pdk, pdk.PD_MIXED, stream)
-            mdesc = time_descs(pdk, tds, args.tol)
-            reset(mix, u0s)
-            mtuned = autotune.tune(mix, mdesc, levels=K_LEVELS, repeats=1, sync=torch.cuda.synchronize)
-            reset(mix, u0s)
-            pdk.solve_batch(mix, mdesc)
-            reset(mix, u0s)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            mst = pdk.solve_batch(mix, mdesc)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            me = max(float(np.linalg.norm(i.solution() - r) / np.linalg.norm(r)) for i, r in zip(mix, refs))
-            var["mixed_batched"] = {"value": round(cells * K_LEVELS / el, 1), "ms": round(1e3 * el, 1),
-                                    "schedule": list(mtuned["best"]),
-                                    "l2_rel_vs_fp64_converged_max": me,
-                                    "inner_iters_per_level": round(float(np.mean(
-                                        [sum(s["iters"] for s in st) for st in mst])) / K_LEVELS, 2),
-                                    "refinements_per_level": round(float(np.mean(
-                                        [sum(s["refinements"] for s in st) for st in mst])) / K_LEVELS, 2)}
-            for i in mix:
-                i.close()
+        log("mixed precision, same workload ...")
+        var["mixed_1024x2048"] = mixed_cfg3_variant(pdk, stream, args.tol, ref)
+        log("ten-instance 256x512 batch ...")
+        var["batch_10x256x512"] = batch_variant(pdk, stream, 4e-12)
         log("adaptive time steps ...")
-        var["adaptive_dt"] = adaptive_variant(pdk, stream, args.tol)
+        var["adaptive_dt"] = adaptive_variant(pdk, stream, 4e-12)
         log("Table 2.1 runs batched ...")
         var["paper_table_2_1"] = paper_table_variant(pdk, stream)
-        log("serving stream ...")
-        var["serving"] = serving_variant(pdk)
         log("uneven batch of 512 ...")
-        var["uneven_512"] = uneven_variant(pdk, stream, args.tol)
-        log("precision configuration 1024x2048 ...")
-        # the finer mesh amplifies the residual more: 1e-12 meets the 1e-8 bar there
-        var["precision_1024x2048"] = precision_variant(pdk, stream, 1e-12)
+        var["uneven_512"] = uneven_variant(pdk, stream, 4e-12)
+        log(f"serving stream ({args.serving_seconds:g} s) ...")
+        var["serving"] = serving_variant(pdk, duration=args.serving_seconds)
         out["variants"] = var
 
-    if not args.no_cpu_baseline:
+    if job is not None:
         log("oracle sample ...")
-        out["cpu_baseline"] = cpu_baseline(args.oracle_levels, sample_state)
+        out["cpu_baseline"] = finish_cpu_baseline(job, args.oracle_levels, early)
 
-    for i in insts:
-        i.close()
     print(json.dumps(out), flush=True)
 
 

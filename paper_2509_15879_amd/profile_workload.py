@@ -1,14 +1,14 @@
-"""A short run of the benchmark workload for hardware-counter profiling.
+"""A short run of a benchmark workload for hardware-counter profiling.
 
-    python -m paper_2509_15879_amd.profile_workload [--levels L] [--copy-mib M]
+    python -m paper_2509_15879_amd.profile_workload [--workload W] [--levels L] [--copy-mib M]
 
-Advances the ten 256 x 512 continuity instances of the benchmark through the
-first L time levels with plain kernel launches (no captured graphs, so every
+Advances the workload (cfg3: the 1024 x 2048 continuity instance of the
+headline; cfg2: the ten 256 x 512 continuity instances) through its first L
+time levels with plain kernel launches (no captured graphs, so every
 dispatch is counted on its own), then copies an M MiB device buffer, filled
 and then pushed out of the caches, once with torch: a kernel that reads and
 writes exactly M MiB, against which the profiler's byte counters are
-calibrated.  Under rocprofv3 --pmc each pass
-takes seconds.
+calibrated.  Under rocprofv3 --pmc each pass takes seconds.
 """
 
 import argparse
@@ -25,27 +25,36 @@ def main():
     ap.add_argument("--levels", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--workload", choices=["cfg3", "cfg2"], default="cfg3")
+    ap.add_argument("--tol", type=float, default=None)
     args = ap.parse_args()
     os.environ["PD_NO_GRAPH"] = "1"
 
     import torch
     from problems import sample
-    from problems.workloads import CFG2, cfg2_batch
+    from problems.workloads import CFG2, CFG3, cfg2_batch, cfg3_problem
     from paper_2509_15879_amd import polardisk as pdk
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     prec = pdk.PD_MIXED if args.precision == "mixed" else pdk.PD_FP64
-    c = CFG2
     insts, descs = [], []
-    for seed, th, pb in cfg2_batch():
+    if args.workload == "cfg2":
+        c = CFG2
+        tol = args.tol or 4e-12
+        for seed, th, pb in cfg2_batch():
+            md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
+            insts.append(pdk.Instance(md, sample(pb, *pdk.mesh_coords(md)), prec, stream=stream))
+            descs.append(pdk.time_desc(th, c["K"], c["T"], pdk.TIME_SINE, c["l"], tol=tol))
+    else:
+        c = CFG3
+        tol = args.tol or 1e-12
         md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
-        insts.append(pdk.Instance(md, sample(pb, *pdk.mesh_coords(md)), prec, stream=stream))
-        full = pdk.time_desc(th, c["K"], c["T"], pdk.TIME_SINE, c["l"], tol=4e-12)
-        descs.append(full)
-    print(f"[profile] {len(insts)} instances, {args.levels} levels", flush=True)
+        insts.append(pdk.Instance(md, sample(cfg3_problem(), *pdk.mesh_coords(md)), prec, stream=stream))
+        descs.append(pdk.time_desc(c["theta"], c["K"], c["dt"] * c["K"], pdk.TIME_UNIFORM, tol=tol))
+    print(f"[profile] {args.workload}: {len(insts)} instances, {args.levels} levels", flush=True)
     t = pdk.time_levels(descs[0])[:args.levels + 1]
-    descs = [pdk.time_desc(d.theta, args.levels, table=t, tol=4e-12) for d in descs]
+    descs = [pdk.time_desc(d.theta, args.levels, table=t, tol=tol) for d in descs]
     stats = pdk.solve_batch(insts, descs)
     torch.cuda.synchronize()
     print("[profile] iterations per level:", [[s["iters"] for s in st] for st in stats], flush=True)

@@ -7,6 +7,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import numpy as np  # noqa: E402
+
 import bench  # noqa: E402
 
 SRC = """// header comment
@@ -34,11 +36,52 @@ def test_digest_sees_every_code_change():
 
 
 def test_traffic_table_covers_every_cycle_kernel():
-    assert set(bench.TRAFFIC_B_PER_CELL) == set(bench.KERNEL_NAMES)
-    for fam, b in bench.TRAFFIC_B_PER_CELL.items():
-        # measured bytes are at least the algorithmic ones, and not wildly above
-        alg = bench.bytes_per_cell(fam, 8)
-        assert alg <= b <= 1.25 * alg, (fam, b, alg)
+    for name, tab in bench.TRAFFIC.items():
+        if tab is None:
+            continue
+        assert set(tab["b_per_cell"]) == set(bench.KERNEL_NAMES), name
+        assert len(tab["sha1"]) == 40
+        for fam, b in tab["b_per_cell"].items():
+            # measured bytes are at least the algorithmic ones, and not wildly above
+            alg = bench.bytes_per_cell(fam, 8)
+            assert alg <= b <= 1.25 * alg, (name, fam, b, alg)
+
+
+def test_oracle_samples_fixture_covers_the_headline():
+    ref = bench.oracle_samples()
+    idx = ref["indices"]
+    m, n = 1024, 2048
+    assert idx[0] == 0 and idx[-1] <= m * n and len(set(idx.tolist())) == len(idx)
+    assert list(ref["levels"]) == [20, 200]
+    for lv in (20, 200):
+        x = ref[f"x_{lv}"]
+        assert x.shape == idx.shape and np.all(np.isfinite(x))
+        assert float(ref[f"maxabs_{lv}"]) >= np.max(np.abs(x))
+    # the stored samples are the discrete solution, so they lie within the
+    # discretisation error of the manufactured exact solution (measured
+    # 1.5e-6 at level 20, 6.4e-6 at level 200); a level or index mix-up
+    # would not (level 20 against the exact solution at level 200: 4.6e-2)
+    from oracle import make_mesh
+    from problems.manufactured import exact_at
+    from problems.workloads import CFG3, cfg3_problem
+    me = make_mesh(m, n, 1, CFG3["p"])
+    i, j = (idx[1:] - 1) % m, (idx[1:] - 1) // m
+    for lv, other in ((20, 200), (200, 20)):
+        e0, eg = exact_at(cfg3_problem(), lv * CFG3["dt"], me.r, me.th)
+        ex = np.concatenate([[e0], eg[i, j]])
+        scale = np.max(np.abs(ex))
+        assert np.max(np.abs(ref[f"x_{lv}"] - ex)) <= 1e-4 * scale
+        assert np.max(np.abs(ref[f"x_{other}"] - ex)) >= 1e-2 * scale
+    # a state equal to the samples scores zero
+    full = np.zeros(m * n + 1)
+    full[idx] = ref["x_200"]
+    d = bench.vs_oracle_samples(full, ref, 200)
+    assert d["max_rel"] == 0.0 and d["l2_rel_samples"] == 0.0
+
+
+def test_cpu_info_names_the_host():
+    info = bench.cpu_info()
+    assert info["cpu_count"] == os.cpu_count()
 
 
 def test_algorithmic_bytes_of_one_iteration():
