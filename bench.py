@@ -596,7 +596,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tol", type=float, default=1e-12,
+    ap.add_argument("--tol", type=float, default=3e-12,
                     help="per-step scaled-residual tolerance of the headline solve")
     ap.add_argument("--oracle-levels", type=int, default=2)
     ap.add_argument("--serving-seconds", type=float, default=60.0)

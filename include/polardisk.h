@@ -411,7 +411,7 @@ int pd_get_schedule(pd_schedule *schedule);
  * last reset.                                                             */
 enum { PD_KF_BEGIN = 0, PD_KF_FACTOR = 1, PD_KF_RAD_P = 2, PD_KF_ANG_P = 3, PD_KF_STEN_V = 4,
        PD_KF_RAD_S = 5, PD_KF_ANG_S = 6, PD_KF_STEN_T = 7, PD_KF_UPDATE = 8, PD_KF_REFINE = 9,
-       PD_KF_CONTROL = 10, PD_KF_N = 11 };
+       PD_KF_CONTROL = 10, PD_KF_LEVEL_END = 11, PD_KF_N = 12 };
 int pd_kernel_timing(int32_t enable, int32_t reset, double *total_ms, int64_t *launches);
 
 const char *pd_last_error(void);

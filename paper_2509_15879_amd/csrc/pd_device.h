@@ -140,4 +140,15 @@ struct PdInst {
                             // error estimate, rejected attempts, 0
   double *fdot[3];          // adaptive stepping: f(t_k, x_k) by level modulo 3 (FP64)
   double *part_e;           // [3 * nb_sten]: the level-end pass's ||d||², ||x||², S0
+  // Ring-mean correction at the end of every level: the Galerkin projection
+  // of the system onto ring-constant vectors (one unknown per ring plus the
+  // origin) is a tridiagonal system of m+1 unknowns whose coefficients are
+  // ring sums of the faces and volumes, fixed per instance:
+  //   crs[k*(m+1) + i], k = 0..5: Σ_j V_ij, Σ_j V_ij b_ij, Σ_j gp_r(i+1/2, j),
+  //   Σ_j gm_r(i-1/2, j), Σ_j gm_r(i+1/2, j), Σ_j gp_r(i-1/2, j)
+  // (ring 0 is the origin, with V_0 and b_0; terms outside the mesh are 0).
+  const double *crs;
+  double *cr_c;             // [m+1] the correction of the level that just ended
+  double *part_c;           // [m * ncg] per ring and column group: Σ_j V_ij (b - A x)_ij
+  double *part_c0;          // [nb_sten] S0 partials of the same pass
 };

@@ -307,6 +307,10 @@ void carve(pd_instance *I, Carver &c) {
   H.part_a = c.take<double>(1 * (size_t)nbs);
   H.part_e = c.take<double>(3 * (size_t)nbs);
   H.part_x = c.take<double>(2 * (size_t)I->T.nb_elem);
+  H.crs = c.take<double>(6 * (size_t)(m + 1));
+  H.cr_c = c.take<double>(m + 1);
+  H.part_c = c.take<double>((size_t)m * I->T.ncg);
+  H.part_c0 = c.take<double>(nbs);
   I->sc = c.take<PdScalars>(1);
   H.sc = I->sc;
 }
@@ -1091,6 +1095,7 @@ struct HostImage {
   std::vector<double> gpr, gmr, gpt, gmt;
   std::vector<float> f_gpr, f_gmr, f_gpt, f_gmt;
   std::vector<double> b_int, g_int, nb, u0_int;
+  std::vector<double> crs;   // ring sums of the ring-mean correction (PdInst::crs)
   double lam[PD_MAXSRC] = {0, 0, 0, 0};
   int tp[PD_MAXSRC] = {0, 0, 0, 0};
   bool has_b = false;
@@ -1204,6 +1209,36 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
     const double b0 = X.has_b ? X.b_int[m * n] : 0.0;
     I->H.l0 = std::fma(I->H.inv_V0, s0, b0);
   }
+  {
+    // ring sums of the ring-mean (Galerkin) correction: with P the
+    // prolongation of ring values to their nodes and V the cell volumes
+    // (those the stencil divides by), P^T V (I/dt + θ L) P is tridiagonal:
+    //   row i: (Σ V)/dt + θ (Σ V b + Σ gp_r(i+1/2) + Σ gm_r(i-1/2)) on the
+    //   diagonal, -θ Σ gm_r(i+1/2) above and -θ Σ gp_r(i-1/2) below (the
+    //   angular fluxes of a ring-constant vector cancel around the ring)
+    const int M1 = m + 1;
+    X.crs.assign(6 * (size_t)M1, 0.0);
+    double *cV = &X.crs[0], *cB = &X.crs[M1], *cO = &X.crs[2 * M1], *cI = &X.crs[3 * M1];
+    double *cU = &X.crs[4 * M1], *cL = &X.crs[5 * M1];
+    const double V0 = 1.0 / I->H.inv_V0;
+    cV[0] = V0;
+    cB[0] = V0 * (X.has_b ? X.b_int[m * n] : 0.0);
+    for (int i = 1; i <= m; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double V = 1.0 / (X.inv_rw[i] * X.inv_dth[j]);
+        cV[i] += V;
+        if (X.has_b) cB[i] += V * X.b_int[(size_t)(i - 1) * n + j];
+      }
+    for (int i = 0; i <= m; ++i)
+      for (int j = 0; j < n; ++j) {
+        cO[i] += X.gpr[(size_t)i * n + j];
+        if (i < m) cU[i] += X.gmr[(size_t)i * n + j];
+        if (i >= 1) {
+          cI[i] += X.gmr[(size_t)(i - 1) * n + j];
+          cL[i] += X.gpr[(size_t)(i - 1) * n + j];
+        }
+      }
+  }
   out = std::move(I);
   img_out = std::move(img);
   return PD_OK;
@@ -1270,6 +1305,7 @@ int upload_instance(pd_instance *I, const HostImage &X, void *mem = nullptr) {
   if ((rc = up(H.k64.gm_r, X.gmr.data(), X.gmr.size() * 8))) return rc;
   if ((rc = up(H.k64.gp_t, X.gpt.data(), X.gpt.size() * 8))) return rc;
   if ((rc = up(H.k64.gm_t, X.gmt.data(), X.gmt.size() * 8))) return rc;
+  if ((rc = up(H.crs, X.crs.data(), X.crs.size() * 8))) return rc;
   if (H.mixed) {
     if ((rc = up(H.k32.gp_r, X.f_gpr.data(), X.f_gpr.size() * 4))) return rc;
     if ((rc = up(H.k32.gm_r, X.f_gmr.data(), X.f_gmr.size() * 4))) return rc;

@@ -141,6 +141,12 @@ __device__ __forceinline__ int block_status(const PdScalars *sc) {
   return st;
 }
 
+// A level of the instance has just met its tolerance and is not yet
+// recorded: the round head closes it (ring-mean correction, then control).
+__device__ __forceinline__ bool level_converged(const PdScalars *sc) {
+  return sc->in_level && sc->status == ST_DONE;
+}
+
 __device__ __forceinline__ void finish_instance(const PdInst &, PdScalars *sc, int status) {
   sc->status = status;   // the level ends; the control kernel takes it from here
 }
@@ -1054,7 +1060,7 @@ __device__ __forceinline__ void sten_tile(const TileGeo &g, const GAS TF *__rest
   }
 }
 
-enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4, SM_EST = 5, SM_GRAM = 6 };
+enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4, SM_EST = 5, SM_GRAM = 6, SM_RES = 7 };
 
 // Origin rows, closed by a later kernel from the producers' partial sums
 // (the ring-1 face sums S0 and the ring parts of the norms).
@@ -1293,6 +1299,9 @@ __device__ __forceinline__ double origin_apply(const PdInst &I, double inv_dt, d
 //  SM_T:     t = D^{-1} A ŝ,  partials t·s, t·t, S0(ŝ)
 //  SM_UR:    (mixed, when the inner solve has converged) r <- r - A d in
 //            FP64, x <- x + d, r32 = r̂32 = D^{-1} r; partials ||r32||², S0(d)
+//  SM_RES:   (a level has just converged) the FP64 residual b - A x of its
+//            system, summed per ring with the cell volumes as weights
+//            (Σ_j V_ij (b - A x)_ij per ring and column group), and S0(x)
 template <typename TK, int MODE>
 __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *map, double a_dt,
                                               double a_th, const TK *ax, TK *ay) {
@@ -1304,6 +1313,8 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     if (!sc->adaptive) return;
     const bool ended = sc->in_level && sc->status == ST_DONE;
     if (!sc->need_f0 && !ended) return;
+  } else if (MODE == SM_RES) {
+    if (!level_converged(sc)) return;
   } else if (MODE != SM_APPLY) {
     if (sc->status != ST_ACTIVE) return;     // no block of this kernel changes the status
     if ((MODE == SM_BEGIN || MODE == SM_GRAM) && sc->stage != STAGE_START) return;
@@ -1548,6 +1559,34 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                                    });
     acc[2] = S0[0];
     produce<3>(acc, I.part_e, I.nb_sten, mp.y);
+  } else if (MODE == SM_RES) {
+    const double inv_dt = sc->inv_dt, th = sc->theta;
+    const GAS double *xv = G((const double *)I.sol[sol_slot(sc->rot, -1)]);
+    const GAS double *bv = G((const double *)I.bvec);
+    double rs[2 * PD_RB];   // per ring of the wave's tile (at most 2 PD_RB rings)
+#pragma unroll
+    for (int u = 0; u < 2 * PD_RB; ++u) rs[u] = 0.0;
+    double S0[1] = {0.0};
+    if (wave_on)
+      sten_tile<double, double, 1>(geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), xv, xv,
+                                   xv, xv, inv_rw, inv_dth, bnode, S0,
+                                   [&](int idx) { return Pre2{bv[idx], 0.0}; },
+                                   [&](int i, int j, int, const double *xc, const double *Lx, double, Pre2 q) {
+                                     const double r = q.a - (inv_dt * xc[0] + th * Lx[0]);
+                                     const double v = r * (1.0 / (inv_rw[i] * inv_dth[j]));
+                                     const int k = i - geo.i0;
+#pragma unroll
+                                     for (int u = 0; u < 2 * PD_RB; ++u)
+                                       if (u == k) rs[u] += v;
+                                   });
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < 2 * PD_RB; ++u) {
+      const double tsum = wave_sum(rs[u]);   // every lane takes part; idle columns hold 0
+      if (wave_on && lane == 0 && u < I.rb && geo.i0 + u <= geo.i1)
+        I.part_c[(size_t)(geo.i0 + u - 1) * I.ncg + cg] = tsum;
+    }
+    produce<1>(S0, I.part_c0, I.nb_sten, mp.y);
   } else if (MODE == SM_UR) {
     // FP64 operator applied to the FP32 correction d
     const double inv_dt = sc->inv_dt, th = sc->theta;
@@ -1573,6 +1612,165 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                                   });
     acc[1] = S0[0];
     produce<2>(acc, I.part_ur, I.nb_sten, mp.y);
+  }
+}
+
+// ------------------------------------------------------------ ring-mean correction
+//
+// When a level has converged, its iterate x is corrected once within the
+// ring-constant vectors: x <- x + P c with P^T V A P c = P^T V (b - A x),
+// the Galerkin projection of the level's system onto one value per ring
+// (and the origin), V the cell volumes.  That tridiagonal system of m+1
+// unknowns has the ring sums of PdInst::crs as coefficients.  It removes
+// what the Krylov iteration converges slowest on these meshes: the θ-mean
+// of the error on the rings next to the origin, where a handful of rows of
+// the diagonally scaled residual carry coefficients near 1/(r_1 Δθ)².  The
+// scheme's solution is unchanged (the correction only moves the iterate
+// towards it).
+//
+// k_coarse (one block per instance) sums SM_RES's per-ring partials in a
+// fixed order, closes the origin row and solves the tridiagonal system by
+// segments: every thread owns a contiguous run of rows; the pivots follow
+// from the continuants q_i = d_i q_{i-1} - a_i c_{i-1} q_{i-2} (2x2 matrix
+// products, rescaled by powers of two), and the forward and back
+// substitutions are affine recurrences; each is joined across the threads
+// by a scan in LDS.  k_cadd adds c to the iterate.
+
+constexpr int PD_CC_THREADS = 256;
+constexpr int PD_CC_ROWS = 9;   // rows per thread: 256 x 9 >= 2049 = the most rings plus the origin
+
+// Exclusive scan over the block's threads at positions pos (a permutation of
+// 0..blockDim-1): returns op-composition of the values at all smaller
+// positions (later position on the left), ident at position 0.
+template <typename V, class Op>
+__device__ __forceinline__ V block_exclusive_scan(V v, int pos, V ident, Op op, V *sh) {
+  const int T = blockDim.x;
+  sh[pos] = v;
+  __syncthreads();
+  for (int o = 1; o < T; o <<= 1) {
+    const V other = pos >= o ? sh[pos - o] : ident;
+    __syncthreads();
+    if (pos >= o) v = op(v, other);
+    sh[pos] = v;
+    __syncthreads();
+  }
+  const V ex = pos > 0 ? sh[pos - 1] : ident;
+  __syncthreads();
+  return ex;
+}
+
+__global__ __launch_bounds__(PD_CC_THREADS) void k_coarse(const PdInst *insts) {
+  const PdInst &I = insts[blockIdx.x];
+  const PdScalars *sc = I.sc;
+  if (!level_converged(sc)) return;   // the same for every thread of the block
+  __shared__ Mat2 shm[PD_CC_THREADS];
+  __shared__ Aff sha[PD_CC_THREADS];
+  const int m = I.m, n = I.n, M1 = m + 1, orig = m * n, ncg = I.ncg;
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  double s0[1];
+  consume<1>(I.part_c0, I.nb_sten, s0);
+  const double *cV = I.crs, *cB = I.crs + M1, *cO = I.crs + 2 * M1, *cI = I.crs + 3 * M1;
+  const double *cU = I.crs + 4 * M1, *cL = I.crs + 5 * M1;
+  const int t = threadIdx.x;
+  const int S = (M1 + blockDim.x - 1) / blockDim.x;   // <= PD_CC_ROWS
+  const int r0 = t * S;
+  const int cnt = max(0, min(S, M1 - r0));
+  double d[PD_CC_ROWS], a[PD_CC_ROWS], c[PD_CC_ROWS], f[PD_CC_ROWS];
+#pragma unroll
+  for (int k = 0; k < PD_CC_ROWS; ++k) {
+    d[k] = 1.0;
+    a[k] = c[k] = f[k] = 0.0;
+    if (k < cnt) {
+      const int i = r0 + k;
+      d[k] = cV[i] * inv_dt + th * (cB[i] + cO[i] + cI[i]);
+      c[k] = -th * cU[i];
+      a[k] = -th * cL[i];
+      if (i == 0) {
+        const double x0 = I.sol[sol_slot(sc->rot, -1)][orig];
+        const double bo = I.has_b ? I.b_node[orig] : 0.0;
+        const double r = I.bvec[orig] - (inv_dt * x0 + th * (I.inv_V0 * s0[0] + bo * x0));
+        f[k] = cV[0] * r;
+      } else {
+        double sum = 0.0;
+        for (int g = 0; g < ncg; ++g) sum += I.part_c[(size_t)(i - 1) * ncg + g];
+        f[k] = sum;
+      }
+    }
+  }
+  const double cprev = (cnt > 0 && r0 > 0) ? -th * cU[r0 - 1] : 0.0;   // c_{r0-1}
+  // pivots: the segment's continuant product, joined over the threads
+  Mat2 P = {1.0, 0.0, 0.0, 1.0};
+#pragma unroll
+  for (int k = 0; k < PD_CC_ROWS; ++k) {
+    if (k < cnt) {
+      const double cm = k == 0 ? cprev : c[k - 1];
+      P = norm2(mul2(Mat2{d[k], -a[k] * cm, 1.0, 0.0}, P));
+    }
+  }
+  const Mat2 Pin = block_exclusive_scan(P, t, Mat2{1.0, 0.0, 0.0, 1.0},
+                                        [](Mat2 later, Mat2 earlier) { return norm2(mul2(later, earlier)); }, shm);
+  // 1/u of the row before the segment: q_{r0-2}/q_{r0-1} (0 before row 0)
+  const double rho = Pin.a != 0.0 ? Pin.c / Pin.a : 0.0;
+  double uinv[PD_CC_ROWS], l[PD_CC_ROWS];
+  double up = rho;   // 1/u of the previous row
+#pragma unroll
+  for (int k = 0; k < PD_CC_ROWS; ++k) {
+    uinv[k] = 1.0;
+    l[k] = 0.0;
+    if (k < cnt) {
+      const double cm = k == 0 ? cprev : c[k - 1];
+      const double u = d[k] - a[k] * cm * up;
+      l[k] = a[k] * up;
+      uinv[k] = 1.0 / u;
+      up = uinv[k];
+    }
+  }
+  // forward substitution y_i = f_i - l_i y_{i-1}
+  Aff F = {1.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < PD_CC_ROWS; ++k)
+    if (k < cnt) F = compose(Aff{-l[k], f[k]}, F);
+  const Aff Fin = block_exclusive_scan(F, t, Aff{1.0, 0.0}, [](Aff later, Aff earlier) { return compose(later, earlier); },
+                                       sha);
+  double y = Fin.e;   // y_{r0-1} (0 before row 0)
+#pragma unroll
+  for (int k = 0; k < PD_CC_ROWS; ++k) {
+    if (k < cnt) {
+      y = f[k] - l[k] * y;
+      f[k] = y;
+    }
+  }
+  // back substitution x_i = (y_i - c_i x_{i+1}) / u_i, joined from the last thread down
+  Aff B = {1.0, 0.0};
+#pragma unroll
+  for (int k = PD_CC_ROWS - 1; k >= 0; --k)
+    if (k < cnt) B = compose(Aff{-c[k] * uinv[k], f[k] * uinv[k]}, B);
+  const int rpos = blockDim.x - 1 - t;
+  const Aff Bin = block_exclusive_scan(B, rpos, Aff{1.0, 0.0}, [](Aff later, Aff earlier) { return compose(later, earlier); },
+                                       sha);
+  double xn = Bin.e;   // x_{r0+cnt} (0 past the last row)
+#pragma unroll
+  for (int k = PD_CC_ROWS - 1; k >= 0; --k) {
+    if (k < cnt) {
+      xn = (f[k] - c[k] * xn) * uinv[k];
+      I.cr_c[r0 + k] = xn;
+    }
+  }
+}
+
+// x <- x + P c for the instances whose level has converged (elementwise).
+__global__ __launch_bounds__(256) void k_cadd(const PdInst *insts, const int2 *map) {
+  const int2 mp = map[blockIdx.x];
+  const PdInst &I = insts[mp.x];
+  if (!level_converged(I.sc)) return;
+  double *x = I.sol[sol_slot(I.sc->rot, -1)];
+  const int n = I.n, orig = I.m * I.n;
+  const double *c = I.cr_c;
+  const int base = mp.y * PD_ELEM_PER_BLOCK;
+  for (int k = threadIdx.x; k < PD_ELEM_PER_BLOCK; k += blockDim.x) {
+    const int idx = base + k;
+    if (idx < orig) x[idx] += c[idx / n + 1];
+    else if (idx == orig) x[idx] += c[0];
   }
 }
 
@@ -2598,7 +2796,7 @@ static inline void go(int fam, void (*k)(KArgs...), dim3 grid, dim3 block, hipSt
     k<<<grid, block, 0, s>>>(args...);
 }
 enum { KF_BEGIN = 0, KF_FACTOR = 1, KF_RAD_P = 2, KF_ANG_P = 3, KF_STEN_V = 4, KF_RAD_S = 5,
-       KF_ANG_S = 6, KF_STEN_T = 7, KF_UPDATE = 8, KF_REFINE = 9, KF_CONTROL = 10 };
+       KF_ANG_S = 6, KF_STEN_T = 7, KF_UPDATE = 8, KF_REFINE = 9, KF_CONTROL = 10, KF_LEVEL_END = 11 };
 
 void launch_level_begin(const LaunchSet &L, hipStream_t s) {
   go(KF_CONTROL, k_level_begin, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
@@ -2668,11 +2866,20 @@ static void cycle_t(const LaunchSet &L, hipStream_t s) {
   go(KF_UPDATE, k_elem_x<T>, g1(L.nb_elem), dim3(256), s, L.insts, L.map_elem);
 }
 
-// One round of asynchronous levels: level control (an instance whose level
-// ended starts its next one), the factorisations and right-hand sides of
-// the instances starting a level, then `cycles` Krylov iterations of every
+// One round of asynchronous levels: the ring-mean correction of the levels
+// that have just converged, level control (an instance whose level ended
+// starts its next one), the factorisations and right-hand sides of the
+// instances starting a level, then `cycles` Krylov iterations of every
 // active instance.
+void launch_level_end(const LaunchSet &L, hipStream_t s) {
+  go(KF_LEVEL_END, k_sten<double, SM_RES>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
+     (const double *)nullptr, (double *)nullptr);
+  go(KF_LEVEL_END, k_coarse, g1(L.ninst), dim3(PD_CC_THREADS), s, (const PdInst *)L.insts);
+  go(KF_LEVEL_END, k_cadd, g1(L.nb_elem), dim3(256), s, (const PdInst *)L.insts, (const int2 *)L.map_elem);
+}
+
 void launch_round(const LaunchSet &L, int cycles, hipStream_t s) {
+  launch_level_end(L, s);
   if (L.adaptive_any)
     go(KF_CONTROL, k_sten<double, SM_EST>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
        (const double *)nullptr, (double *)nullptr);

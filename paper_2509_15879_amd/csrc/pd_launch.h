@@ -55,6 +55,7 @@ extern KTimer *g_timer;
 
 void launch_level_begin(const LaunchSet &L, hipStream_t s);
 void launch_ctl(const LaunchSet &L, hipStream_t s);
+void launch_level_end(const LaunchSet &L, hipStream_t s);
 void launch_round(const LaunchSet &L, int cycles, hipStream_t s);
 void launch_factor(const LaunchSet &L, hipStream_t s);
 void launch_begin(const LaunchSet &L, hipStream_t s);

@@ -103,7 +103,7 @@ EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step
            "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
 
 KERNEL_FAMILIES = ("begin", "factor", "rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t",
-                   "update", "refine", "control")
+                   "update", "refine", "control", "level_end")
 
 
 def _load():
