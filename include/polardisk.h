@@ -75,9 +75,13 @@ enum {
 typedef enum { PD_PARABOLIC = 0, PD_CONTINUITY = 1 } pd_pde;
 
 /* PD_FP64: every vector, coefficient and Krylov scalar in FP64.
- * PD_MIXED: FP64 right-hand side, outer residual, origin-row sum and
- * tridiagonal pivots; the inner BiCGSTAB (stencil, sweeps, vectors) runs in
- * FP32 and is refined until the FP64 residual meets the tolerance.        */
+ * PD_MIXED: FP64 right-hand side, outer residual and origin-row sum; the
+ * inner BiCGSTAB (stencil, sweeps, vectors) runs in FP32 and is refined
+ * until the FP64 residual meets the tolerance.
+ * In both precisions the preconditioner's tridiagonal factors (pivots,
+ * multipliers, the Sherman-Morrison vector) are computed in FP64 and stored
+ * in FP32: they define a fixed preconditioner, which moves the iterates but
+ * not the converged solution.                                             */
 typedef enum { PD_FP64 = 0, PD_MIXED = 1 } pd_precision;
 
 enum { PD_MESH_UNIFORM = 0, PD_MESH_SINE = 1, PD_MESH_EXPLICIT = 2, PD_MESH_POLY = 3 };
@@ -254,6 +258,22 @@ int pd_apply_operator(pd_instance *inst, double dt, double theta, const double *
                       int32_t layout, int32_t device_ptrs, int32_t precision);
 int pd_assemble_rhs(pd_instance *inst, double t_k, double dt, double theta, double *rhs,
                     int32_t layout, int32_t device_ptr);
+
+/* pd_apply_preconditioner (diagnostic): z = M^{-1} y for the preconditioner
+ * the solver builds for the step system A = I/dt + θ L_h of (2.11)/(2.12)
+ * (the paper solves that system directly; the preconditioner is the
+ * library's).  The Krylov iteration works on the diagonally scaled system
+ * D^{-1} A (D = diag A), and M = (I + D^{-1} R)(I + D^{-1} Θ): R holds the
+ * radial (same θ-line) couplings of the ring nodes -- the tridiagonal blocks
+ * A_j of (2.12) -- and Θ the angular (same-ring, periodic) couplings plus
+ * the couplings between the origin and ring 1 (an arrow system).
+ * z = (I + D^{-1}Θ)^{-1} (I + D^{-1}R)^{-1} y.  The factors are computed in
+ * FP64 and stored in FP32, and a mixed-precision instance applies M in FP32,
+ * so z agrees with the exact M^{-1} y to about FP32 rounding.  y, z: N
+ * values in `layout`, host or device (device_ptrs).  The instance's state
+ * and time are not changed.                                               */
+int pd_apply_preconditioner(pd_instance *inst, double dt, double theta, const double *y, double *z,
+                            int32_t layout, int32_t device_ptrs);
 
 /* Device bytes an instance of this mesh and precision occupies. */
 int pd_footprint(const pd_mesh_desc *mesh, int32_t nsrc, int32_t precision, size_t *bytes);

@@ -28,6 +28,8 @@
 #define PD_LSTAT 10           // statistics per level (see end_level)
 #define PD_NHIST 4        // earlier levels kept for the initial guess: n^k .. n^{k-3}
 #define PD_NSOL 5         // rotating solution slots: the PD_NHIST levels and the iterate
+#define PD_RANNACHER 2    // backward-Euler steps that start an adaptive Crank-Nicolson solve
+#define PD_STALL 20       // steps at dt_min above the error tolerance that end an adaptive solve
 #define PD_NBEGIN (2 + PD_NHIST)   // partials of the level-begin stencil: ||D^-1 b||², ||D^-1 r||², S0 per level
 // partials of the Gram pass: Z Z^T (upper triangle), Z r_c for both
 // candidates, ||r_c||² for both, S0 per level
@@ -76,6 +78,10 @@ struct PdScalars {
   int nrej, pad5;           // rejected attempts of the level under way
   double t_end, dt_min, dt_max, tol_time;
   double err_last;          // relative local error estimate of the last step
+  double theta_run;         // θ of the solve (theta is the level's: an adaptive
+                            // Crank-Nicolson solve starts with PD_RANNACHER
+                            // backward-Euler steps)
+  int stall, pad6;          // consecutive steps forced through at dt_min with e > 2 tol_time
 };
 
 template <typename T>

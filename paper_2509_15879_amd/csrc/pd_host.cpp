@@ -656,6 +656,7 @@ constexpr double kDefaultMaxSeconds = 600.0;
 int init_scalars(pd_instance *I, const SolveParams &sp, int K, hipStream_t s) {
   PdScalars h{};
   h.theta = sp.theta;
+  h.theta_run = sp.theta;
   h.tol = sp.tol;
   h.tol_inner = sp.tol_inner;
   h.maxit = sp.maxit;
@@ -984,7 +985,10 @@ int run_levels(std::vector<pd_instance *> const &insts, std::vector<int> const &
     if (stats_out) (*stats_out)[q] = std::move(st);
   }
   if (worst == PD_EBREAKDOWN) return fail(worst, "Krylov breakdown in at least one step");
-  if (worst == PD_ENOCONV) return fail(worst, "a step did not reach the tolerance within the iteration cap");
+  if (worst == PD_ENOCONV)
+    return fail(worst, adaptive ? "an adaptive solve stopped before T (a step hit its iteration cap, the level cap "
+                                  "came first, or the local error stayed above 2 tol_time at dt_min)"
+                                : "a step did not reach the tolerance within the iteration cap");
   return PD_OK;
 }
 
@@ -1627,6 +1631,57 @@ int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double 
     HIPCHK(hipMemcpy(rhs, o.data(), N * 8, hipMemcpyHostToDevice));
   } else {
     std::memcpy(rhs, o.data(), N * 8);
+  }
+  return PD_OK;
+}
+
+int pd_apply_preconditioner(pd_instance *I, double dt, double theta, const double *y, double *z, int32_t layout,
+                            int32_t device_ptrs) {
+  if (!I || !y || !z) return fail(PD_EINVAL, "NULL argument");
+  if (!(dt > 0.0)) return fail(PD_EINVAL, "dt must be > 0");
+  int rc = validate_theta(theta);
+  if (rc) return rc;
+  if (layout != PD_LAYOUT_RING && layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
+  BusyGuard g({I});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  const int m = I->M.m, n = I->M.n, N = m * n + 1, np = I->T.npad;
+  std::vector<double> src;
+  if ((rc = fetch(y, N, device_ptrs, src))) return rc;
+  std::vector<double> hin(np), hout(np), o(N);
+  to_internal(src.data(), layout, m, n, np, hin.data());
+  hipStream_t s = I->stream;
+  // one level t -> t + dt set up and factored (its Krylov phase is not run);
+  // the state of the instance is not touched
+  double tab[2] = {I->t, I->t + dt};
+  if ((rc = ensure_time_capacity(I, 1))) return rc;
+  HIPCHK(hipMemcpyAsync(I->t_table, tab, sizeof tab, hipMemcpyHostToDevice, s));
+  Plan P;
+  if ((rc = make_plan({I}, s, P))) return rc;
+  SolveParams sp{theta, 1e-300, 1e-3, 1, 1, 1};
+  if ((rc = init_scalars(I, sp, 1, s))) return rc;
+  pd::launch_level_begin(P.L, s);
+  pd::launch_factor(P.L, s);
+  const bool fp32 = I->precision == PD_MIXED;
+  if (fp32) {
+    std::vector<float> f(hin.begin(), hin.end());
+    HIPCHK(hipMemcpyAsync(I->H.k32.r, f.data(), np * 4, hipMemcpyHostToDevice, s));
+    pd::launch_precond_apply(P.L, 1, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(f.data(), I->H.k32.ph, np * 4, hipMemcpyDeviceToHost));
+    for (int k = 0; k < np; ++k) hout[k] = f[k];
+  } else {
+    HIPCHK(hipMemcpyAsync(I->H.k64.r, hin.data(), np * 8, hipMemcpyHostToDevice, s));
+    pd::launch_precond_apply(P.L, 0, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(hout.data(), I->H.k64.ph, np * 8, hipMemcpyDeviceToHost));
+  }
+  from_internal(hout.data(), layout, m, n, o.data());
+  if (device_ptrs) {
+    HIPCHK(hipMemcpy(z, o.data(), N * 8, hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(z, o.data(), N * 8);
   }
   return PD_OK;
 }

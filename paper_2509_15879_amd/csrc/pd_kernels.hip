@@ -41,9 +41,11 @@
 // recurrence of the factorisation).  Radial lines join through LDS across
 // the waves of a block; rings join across the lanes of one wave.
 //
-// Arithmetic is FP64 throughout; the FP32 inner solve of the mixed-precision
-// mode only stores its vectors, faces and multipliers in FP32 (pivots stay
-// FP64).  Pointers taken from the instance descriptor are handed to the
+// Arithmetic is FP64, except that the inner solve of the mixed-precision
+// mode keeps its vectors and faces in FP32 and its sweeps compute in FP32,
+// and that the preconditioner's factors (pivots, multipliers, the
+// Sherman-Morrison vector) are computed in FP64 but stored in FP32 in both
+// precisions.  Pointers taken from the instance descriptor are handed to the
 // bodies as restrict-qualified global-address-space pointers, so that loads
 // of different arrays can be in flight together.
 
@@ -258,7 +260,12 @@ __device__ void guess_weights(const double *tt, int k, int ne, double theta, dou
 __device__ __forceinline__ void begin_level(const PdInst &I, PdScalars *sc) {
   const int k = sc->level;
   const double t0 = I.t_table[k], t1 = I.t_table[k + 1];
-  const double dt = t1 - t0, th = sc->theta;
+  // an adaptive Crank-Nicolson solve takes its first steps with backward
+  // Euler, which damps the stiff components of the initial state that
+  // Crank-Nicolson would carry undamped (and the step control would chase)
+  const double th = (sc->adaptive && sc->theta_run == 0.5 && k < PD_RANNACHER) ? 1.0 : sc->theta_run;
+  sc->theta = th;
+  const double dt = t1 - t0;
   sc->t0 = t0;
   sc->t1 = t1;
   sc->dt = dt;
@@ -435,7 +442,10 @@ __global__ void k_ctl(PdInst *insts, int ninst) {
       e = sqrt(tot[0] + d0 * d0) / fmax(sqrt(xx), 1e-300);
     }
     sc->err_last = e;
-    if (k >= 1 && e > 2.0 * sc->tol_time && sc->dt > sc->dt_min) {
+    // "longer than dt_min" compares levels: the step's level against the one a
+    // dt_min step reaches (t1 - t0 itself may round above dt_min, which would
+    // reject a step at dt_min again and again)
+    if (k >= 1 && e > 2.0 * sc->tol_time && sc->t1 > next_level(sc->t0, sc->dt_min, sc->t_end)) {
       const double fr = fmax(0.25, 0.9 * pow(sc->tol_time / e, 1.0 / (qord + 1)));
       const double dtr = land_step(sc->t0, fmax(sc->dt_min, sc->dt * fr), sc->t_end);
       I.t_table[k + 1] = next_level(sc->t0, dtr, sc->t_end);
@@ -443,8 +453,13 @@ __global__ void k_ctl(PdInst *insts, int ninst) {
       begin_level(I, sc);                 // the same level again from n^k
       return;
     }
+    // a step forced through at dt_min although its error is above 2 tol_time
+    sc->stall = (k >= 1 && e > 2.0 * sc->tol_time) ? sc->stall + 1 : 0;
   }
   if (sc->in_level) ok = end_level(I, sc);
+  // PD_STALL such steps in a row: tol_time is out of reach at dt_min, the
+  // solve stops (PD_ENOCONV: T not reached)
+  if (ok && sc->adaptive && sc->stall >= PD_STALL) ok = false;
   if (ok && sc->adaptive) {
     // the next level's time: grown or shrunk after the second step
     const int k1 = sc->level;
@@ -1820,8 +1835,9 @@ __global__ void k_begin_origin(const PdInst *insts, int ninst) {
 //
 // RM_P:  y = p = r + β (p - ω v)   (p = r on a (re)start; r̂ = r on a restart)
 // RM_S:  y = s = r - α v
+// RM_Y:  y = r (diagnostic application of the preconditioner; no scalars)
 
-enum { RM_P = 0, RM_S = 1 };
+enum { RM_P = 0, RM_S = 1, RM_Y = 2 };
 
 // C: the sweep's arithmetic type, its storage type T (FP64, or FP32 for the
 // inner solve of mixed precision).
@@ -1845,6 +1861,7 @@ __device__ __forceinline__ void rad_load(int n, int j, int rb, int klast, double
     R.a[k] = a[idx];
     if (MODE == RM_P) R.b[k] = b[idx] - om * c[idx];
     if (MODE == RM_S) R.b[k] = b[idx];
+    if (MODE == RM_Y) R.b[k] = (T)0;
     R.u[k] = uinv[idx];
     R.f[k] = f[idx];
   }
@@ -1923,7 +1940,7 @@ __device__ __forceinline__ void rad_solve(int m, int n, int j, int c, int i_begi
       out[o] = ps;
     } else {
       const T ss = input(r[o], v[o]);
-      s[o] = ss;
+      if (MODE == RM_S) s[o] = ss;
       out[o] = ss;
     }
   }
@@ -2831,7 +2848,7 @@ void launch_begin(const LaunchSet &L, hipStream_t s) {
 
 template <typename T, int MODE>
 static void rad(const LaunchSet &L, hipStream_t s) {
-  const int fam = MODE == RM_S ? KF_RAD_S : KF_RAD_P;
+  const int fam = MODE == RM_S ? KF_RAD_S : (MODE == RM_P ? KF_RAD_P : KF_CONTROL);
   if (L.nb_rs[0]) {
     PD_DISPATCH_BM(L.max_brs[0], (go(fam, k_rad<T, MODE, BM, 512, 16>, g1(L.nb_rs[0]), dim3(512), s, L.insts, L.map_rs[0])));
   }
@@ -2887,6 +2904,19 @@ void launch_round(const LaunchSet &L, int cycles, hipStream_t s) {
   launch_factor(L, s);
   launch_begin(L, s);
   for (int c = 0; c < cycles; ++c) launch_cycle(L, s);
+}
+
+// z = M^{-1} y of the preconditioner (diagnostic): y in the Krylov set's r,
+// the radial sweep into w, the ring sweep (with the origin's arrow closure)
+// into p̂.
+void launch_precond_apply(const LaunchSet &L, int fp32, hipStream_t s) {
+  if (fp32) {
+    rad<float, RM_Y>(L, s);
+    ang<float, AM_P>(L, s);
+  } else {
+    rad<double, RM_Y>(L, s);
+    ang<double, AM_P>(L, s);
+  }
 }
 
 void launch_cycle(const LaunchSet &L, hipStream_t s) {

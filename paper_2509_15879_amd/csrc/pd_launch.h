@@ -61,6 +61,7 @@ void launch_factor(const LaunchSet &L, hipStream_t s);
 void launch_begin(const LaunchSet &L, hipStream_t s);
 void launch_begin_origin(const LaunchSet &L, hipStream_t s);
 void launch_cycle(const LaunchSet &L, hipStream_t s);
+void launch_precond_apply(const LaunchSet &L, int fp32, hipStream_t s);
 void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void *y, int fp32,
                   hipStream_t s);
 void launch_indicator(const double *x, int m, int n, const double *r, const double *th,

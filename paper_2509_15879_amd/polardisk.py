@@ -97,6 +97,7 @@ class Indicator(C.Structure):
 # every entry point declared in include/polardisk.h
 EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
+           "pd_apply_preconditioner",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
            "pd_batch_stats", "pd_error_indicator", "pd_error_indicator_noalloc", "pd_remesh_transfer", "pd_set_schedule",
            "pd_get_schedule", "pd_get_time",
@@ -123,6 +124,7 @@ def _load():
         "pd_set_solution": [P, P, I32, I32, D],
         "pd_apply_operator": [P, D, D, P, P, I32, I32, I32],
         "pd_assemble_rhs": [P, D, D, D, P, I32, I32],
+        "pd_apply_preconditioner": [P, D, D, P, P, I32, I32],
         "pd_footprint": [C.POINTER(MeshDesc), I32, I32, C.POINTER(SZ)],
         "pd_destroy": [P],
         "pd_batch_create": [SZ, I32, P, C.POINTER(P)],
@@ -344,6 +346,13 @@ class Instance:
         _check(lib.pd_apply_operator(self.h, float(dt), float(theta), _ptr(a), _ptr(y), int(layout),
                                      0, int(precision)))
         return y
+
+    def precondition(self, y, dt, theta, layout=LAYOUT_RING):
+        """z = M^{-1} y of the preconditioner of the step system at (dt, θ)."""
+        a = _f64(y)
+        z = np.empty(self.N)
+        _check(lib.pd_apply_preconditioner(self.h, float(dt), float(theta), _ptr(a), _ptr(z), int(layout), 0))
+        return z
 
     def rhs(self, t, dt, theta, layout=LAYOUT_RING):
         y = np.empty(self.N)

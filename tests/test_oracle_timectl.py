@@ -8,7 +8,9 @@ import pytest
 
 from oracle import assemble, make_mesh, solve, time_levels
 from oracle.stepper import rhs, system_matrix
-from oracle.timectl import f_eval, land, local_error, retry_factor, solve_adaptive, solve_levels, step_factor
+from oracle.timectl import (RANNACHER, STALL, f_eval, land, local_error, retry_factor, solve_adaptive,
+                            solve_levels, step_factor, step_theta)
+from oracle.stepper import step
 from problems import continuity_cfg, sample
 
 
@@ -89,7 +91,7 @@ def test_controller_invariants_and_error_follows_tolerance(theta):
         assert np.all(dts[1:-2] / dts[:-3] <= 2.0 * (1 + 1e-12))    # growth (the last steps may land)
         assert all(e <= 2 * tol for dt, e in steps[1:] if dt > dt_min)
         # replaying the accepted levels gives the same state
-        assert np.max(np.abs(solve_levels(S, lv, theta) - x)) <= 1e-12 * np.max(np.abs(x))
+        assert np.max(np.abs(solve_levels(S, lv, theta, adaptive_start=True) - x)) <= 1e-12 * np.max(np.abs(x))
         errs.append(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     assert errs[1] < errs[0]
 
@@ -118,3 +120,33 @@ def test_retry_factor_at_hand_computed_errors(q):
         assert retry_factor(tol * (0.9 / g) ** (q + 1), tol, q) == pytest.approx(g, rel=1e-12)
     assert retry_factor(tol * 3.6 ** (q + 1), tol, q) == pytest.approx(0.25, rel=1e-12)
     assert retry_factor(10.0 * tol * 3.6 ** (q + 1), tol, q) == 0.25
+
+
+def test_crank_nicolson_starts_with_backward_euler_steps():
+    """An adaptive Crank-Nicolson solve takes its first RANNACHER steps with
+    θ = 1: its first levels equal plain backward-Euler steps over the same
+    levels, and other θ are left alone."""
+    assert RANNACHER == 2
+    assert [step_theta(0.5, k) for k in range(4)] == [1.0, 1.0, 0.5, 0.5]
+    assert [step_theta(0.7, k) for k in range(3)] == [0.7, 0.7, 0.7]
+    S = small_system(theta=0.5)
+    x, lv, steps, rej = solve_adaptive(S, 0.5, 0.01, 1e-4, 1e-5, 1e-6, 1e-2)
+    y = S.initial()
+    for k in range(RANNACHER):
+        y = step(S, y, lv[k], lv[k + 1], 1.0)
+    x2 = solve_levels(S, lv[:RANNACHER + 1], 0.5, adaptive_start=True)
+    assert np.max(np.abs(x2 - y)) <= 1e-13 * np.max(np.abs(y))
+    # with Crank-Nicolson throughout the second level differs
+    x2cn = solve_levels(S, lv[:RANNACHER + 1], 0.5)
+    assert np.max(np.abs(x2cn - y)) > 1e-9 * np.max(np.abs(y))
+
+
+def test_solve_stops_when_tolerance_is_out_of_reach_at_dt_min():
+    """A tolerance that even dt_min cannot meet: after STALL steps forced
+    through at dt_min the solve stops before T."""
+    S = small_system(theta=1.0)
+    dt_min = 1e-3
+    x, lv, steps, rej = solve_adaptive(S, 1.0, 1.0, dt_min, 1e-14, dt_min, 1e-2)
+    assert lv[-1] < 1.0
+    assert len(steps) == STALL + 1      # the first step (accepted as is) and STALL stalled ones
+    assert all(e > 2e-14 for _, e in steps[1:])
