@@ -86,6 +86,7 @@ typedef enum { PD_FP64 = 0, PD_MIXED = 1 } pd_precision;
 
 enum { PD_MESH_UNIFORM = 0, PD_MESH_SINE = 1, PD_MESH_EXPLICIT = 2, PD_MESH_POLY = 3 };
 enum { PD_LAYOUT_RING = 0, PD_LAYOUT_PAPER = 1 };
+enum { PD_FLUX_CENTRAL = 0, PD_FLUX_UPWIND = 1, PD_FLUX_LITERAL = 2 };
 enum { PD_TIME_UNIFORM = 0, PD_TIME_SINE = 1, PD_TIME_TABLE = 2, PD_TIME_ADAPTIVE = 3 };
 
 /* Mesh (§2.1 "region divided", §3.1 stretching equations).
@@ -111,7 +112,11 @@ typedef struct {
  * L n = -∇·(D∇n) + ∇·(nE) + b n and Dirichlet data N(t, θ) on r = 1.
  *   pde:  PD_PARABOLIC or PD_CONTINUITY (informational; both use the arrays).
  *   flux: 0 central drift average (n_P + n_Q)/2 (the origin choice of
- *         §3.2.2), 1 upwind drift.
+ *         §3.2.2), 1 upwind drift, 2 PD_FLUX_LITERAL: the operator ϖ_h of
+ *         §3.2.1 and the origin row of §3.2.2 as printed (scalar E at the
+ *         nodes, one-sided drift differences; not conservative).  It needs
+ *         E_node and D_origin and Dirichlet data; Er/Et faces are ignored.
+ *         Kept to reproduce the paper's Ch. 3 tables.
  *   bc:   0 Dirichlet on r = 1, 1 zero flux through r = 1.
  *   D_rface, Er_rface: (m+1)*n radial-face samples, NULL means D = 1 / E_r = 0.
  *   D_tface, Et_tface: m*n angular-face samples, NULL means D = 1 / E_θ = 0.
@@ -123,7 +128,9 @@ typedef struct {
  *   tpow may be NULL (all 0).
  *   u0: N initial values in `layout` (eq. (2.10) / (3.3)).
  *   device_ptrs: 1 if every array above (lambda and tpow included) is a
- *   device pointer; they are copied to the host at creation.              */
+ *   device pointer; they are copied to the host at creation.
+ *   E_node, D_origin (PD_FLUX_LITERAL only): the scalar field E at the N
+ *   nodes in `layout` (E_node follows device_ptrs), and D at the origin.   */
 typedef struct {
   int32_t pde;
   int32_t flux;
@@ -139,6 +146,8 @@ typedef struct {
   const double *g;
   const double *nb;
   const double *u0;
+  const double *E_node;          /* PD_FLUX_LITERAL only */
+  double D_origin;               /* PD_FLUX_LITERAL only */
 } pd_problem_desc;
 
 /* Time levels (§2.1 Δt = T/K; §3.1 t_k = V(k T/K), V(t) = T sin((t/T)^l π/2);

@@ -1105,12 +1105,80 @@ struct HostImage {
   bool has_b = false;
 };
 
+// The operator ϖ_h of §3.2.1 and the origin row of §3.2.2 as printed (scalar
+// E at the nodes, one-sided drift differences), written into the face-pair
+// form the kernels apply.  Row (i, j) of the printed stencil, with
+// s = h_i + h_{i+1} and the face diffusivities D_{i±1/2,j}, D_{i,j±1/2}:
+//   diagonal  2/(r_i s) (r_{i+1/2} D_{i+1/2,j}/h_{i+1} + r_{i-1/2} D_{i-1/2,j}/h_i)
+//             + 2/(r_i² (μ_j+μ_{j+1})) (D_{i,j+1/2}/μ_{j+1} + D_{i,j-1/2}/μ_j)
+//             + E_ij (1/(r_i μ_{j+1}) + 1/h_{i+1})
+//   (i-1, j)  -2 r_{i-1/2} D_{i-1/2,j} / (r_i h_i s)            (the origin for i = 1)
+//   (i+1, j)  -(2 r_{i+1/2} D_{i+1/2,j} / (r_i h_{i+1} s) + E_ij/h_{i+1})   (N_j for i = m)
+//   (i, j-1)  -2 D_{i,j-1/2} / (r_i² μ_j (μ_j+μ_{j+1}))
+//   (i, j+1)  -(2 D_{i,j+1/2} / (r_i² μ_{j+1} (μ_j+μ_{j+1})) + E_ij/(r_i μ_{j+1}))
+// and the origin row  (4 D_00/h_1² + E_00/h_1) n_0 - (4 D_00/(n h_1²) - E_00/(n h_1)) Σ_j n_{1,j}.
+// A kernel row is ivV_P (Σ_faces gp x_P - gm x_Q) + b_P x_P: every
+// off-diagonal coefficient of a row fixes one face coefficient (the one that
+// multiplies the neighbour in that row), and what the faces leave of the
+// printed diagonal goes into b_P (added to the reaction already in b).
+int literal_stencil(const MeshH &M, const std::vector<double> &Dr, const std::vector<double> &Dt,
+                    const std::vector<double> &E, double D00, double inv_V0, const std::vector<double> &inv_rw,
+                    const std::vector<double> &inv_dth, HostImage &X, std::vector<double> &b) {
+  const int m = M.m, n = M.n;
+  const std::vector<double> &r = M.r, &h = M.h, &rh = M.rh, &mu = M.mu;
+  auto ivV = [&](int i, int j) { return inv_rw[i] * inv_dth[j]; };
+  std::fill(X.gpr.begin(), X.gpr.end(), 0.0);
+  std::fill(X.gmr.begin(), X.gmr.end(), 0.0);
+  std::fill(X.gpt.begin(), X.gpt.end(), 0.0);
+  std::fill(X.gmt.begin(), X.gmt.end(), 0.0);
+  std::vector<double> diag((size_t)m * n);
+  for (int i = 1; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const int jm = (j + n - 1) % n;
+      const double Dp = Dr[(size_t)i * n + j], Dm = Dr[(size_t)(i - 1) * n + j];
+      const double Dtp = Dt[(size_t)(i - 1) * n + j], Dtm = Dt[(size_t)(i - 1) * n + jm];
+      const double mj = mu[j], mj1 = mu[j + 1], e = E[(size_t)(i - 1) * n + j];
+      const double s = h[i] + h[i + 1], w = ivV(i, j);
+      diag[(size_t)(i - 1) * n + j] = 2.0 / (r[i] * s) * (rh[i] * Dp / h[i + 1] + rh[i - 1] * Dm / h[i]) +
+                                      2.0 / (r[i] * r[i] * (mj + mj1)) * (Dtp / mj1 + Dtm / mj) +
+                                      e * (1.0 / (r[i] * mj1) + 1.0 / h[i + 1]);
+      const double c_in = -2.0 * rh[i - 1] * Dm / (r[i] * h[i] * s);
+      const double c_out = -(2.0 * rh[i] * Dp / (r[i] * h[i + 1] * s) + e / h[i + 1]);
+      const double c_lo = -2.0 * Dtm / (r[i] * r[i] * mj * (mj + mj1));
+      const double c_hi = -(2.0 * Dtp / (r[i] * r[i] * mj1 * (mj + mj1)) + e / (r[i] * mj1));
+      X.gpr[(size_t)(i - 1) * n + j] = -c_in / w;    // face i-1/2 times the inner neighbour
+      X.gmr[(size_t)i * n + j] = -c_out / w;         // face i+1/2 times the outer neighbour (or N_j)
+      X.gmt[(size_t)(i - 1) * n + j] = -c_hi / w;    // face j+1/2 times (i, j+1)
+      X.gpt[(size_t)(i - 1) * n + jm] = -c_lo / w;   // face j-1/2 times (i, j-1)
+    }
+  const double E00 = E[(size_t)m * n], h1 = h[1];
+  const double d0 = 4.0 * D00 / (h1 * h1) + E00 / h1;
+  const double off = -(4.0 * D00 / (n * h1 * h1) - E00 / (n * h1));
+  for (int j = 0; j < n; ++j) X.gmr[j] = -off / inv_V0;   // the origin row times ring 1
+  for (int i = 1; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const int jm = (j + n - 1) % n;
+      const size_t k = (size_t)(i - 1) * n + j;
+      const double faces = X.gpr[(size_t)i * n + j] + X.gmr[(size_t)(i - 1) * n + j] + X.gpt[k] +
+                           X.gmt[(size_t)(i - 1) * n + jm];
+      b[k] += diag[k] - ivV(i, j) * faces;
+    }
+  double s0 = 0.0;
+  for (int j = 0; j < n; ++j) s0 += X.gpr[j];
+  b[(size_t)m * n] += d0 - inv_V0 * s0;
+  for (double v : b)
+    if (!std::isfinite(v)) return fail(PD_EINVAL, "the printed stencil gave a non-finite coefficient");
+  return PD_OK;
+}
+
 int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_t precision,
                      std::unique_ptr<pd_instance> &out, std::unique_ptr<HostImage> &img_out) {
   if (!pb) return fail(PD_EINVAL, "problem descriptor is NULL");
   if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision %d", precision);
   if (pb->nsrc < 0 || pb->nsrc > PD_MAXSRC) return fail(PD_EINVAL, "nsrc must be in [0, %d]", PD_MAXSRC);
-  if (pb->flux != 0 && pb->flux != 1) return fail(PD_EINVAL, "flux must be 0 or 1");
+  if (pb->flux < 0 || pb->flux > 2) return fail(PD_EINVAL, "flux must be 0, 1 or 2");
+  if (pb->flux == 2 && pb->bc != 0) return fail(PD_EINVAL, "the printed stencil (flux 2) takes Dirichlet data only");
+  if (pb->flux == 2 && !pb->E_node) return fail(PD_EINVAL, "the printed stencil (flux 2) needs E_node");
   if (pb->bc != 0 && pb->bc != 1) return fail(PD_EINVAL, "bc must be 0 or 1");
   if (pb->layout != PD_LAYOUT_RING && pb->layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
   std::unique_ptr<pd_instance> I(new pd_instance);
@@ -1188,9 +1256,27 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
   X.inv_dth.resize(n);
   for (int i = 1; i <= m; ++i) X.inv_rw[i] = 1.0 / (M.r[i] * M.w[i]);
   for (int j = 0; j < n; ++j) X.inv_dth[j] = 1.0 / M.dth[j];
+  I->H.inv_V0 = 1.0 / (kPi * 0.25 * M.h[1] * M.h[1]);
+  if (pb->flux == 2) {
+    std::vector<double> En;
+    if ((rc = fetch(pb->E_node, N, dp, En))) return rc;
+    std::vector<double> E_int(np, 0.0), b_lit;
+    to_internal(En.data(), pb->layout, m, n, np, E_int.data());
+    if (X.has_b) {
+      b_lit.resize(np);
+      to_internal(bn.data(), pb->layout, m, n, np, b_lit.data());
+    } else {
+      b_lit.assign(np, 0.0);
+    }
+    if ((rc = literal_stencil(M, Dr, Dt, E_int, pb->D_origin, I->H.inv_V0, X.inv_rw, X.inv_dth, X, b_lit)))
+      return rc;
+    // the literal rows' diagonals live in the node reaction term
+    X.has_b = true;
+    bn.assign(N, 0.0);
+    from_internal(b_lit.data(), pb->layout, m, n, bn.data());
+  }
   X.r = M.r;
   X.th = M.th;
-  I->H.inv_V0 = 1.0 / (kPi * 0.25 * M.h[1] * M.h[1]);
   if (precision == PD_MIXED) {
     X.f_gpr.assign(X.gpr.begin(), X.gpr.end());
     X.f_gmr.assign(X.gmr.begin(), X.gmr.end());
@@ -2215,7 +2301,9 @@ int pd_batch_submit(pd_batch *B, const pd_mesh_desc *mesh, const pd_problem_desc
     if (rc) return rc;
     if ((rc = validate_theta(td->theta))) return rc;
     if (pb->nsrc < 0 || pb->nsrc > PD_MAXSRC) return fail(PD_EINVAL, "nsrc must be in [0, %d]", PD_MAXSRC);
-    if (pb->flux != 0 && pb->flux != 1) return fail(PD_EINVAL, "flux must be 0 or 1");
+    if (pb->flux < 0 || pb->flux > 2) return fail(PD_EINVAL, "flux must be 0, 1 or 2");
+  if (pb->flux == 2 && pb->bc != 0) return fail(PD_EINVAL, "the printed stencil (flux 2) takes Dirichlet data only");
+  if (pb->flux == 2 && !pb->E_node) return fail(PD_EINVAL, "the printed stencil (flux 2) needs E_node");
     if (pb->bc != 0 && pb->bc != 1) return fail(PD_EINVAL, "bc must be 0 or 1");
     if (pb->layout != PD_LAYOUT_RING && pb->layout != PD_LAYOUT_PAPER) return fail(PD_EINVAL, "bad layout");
     if (!pb->u0) return fail(PD_EINVAL, "u0 is NULL");

@@ -23,6 +23,7 @@ ERRORS = {-1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EBREAKDOWN", -4: "PD_ENOCONV
 PD_FP64, PD_MIXED = 0, 1
 MESH_UNIFORM, MESH_SINE, MESH_EXPLICIT, MESH_POLY = 0, 1, 2, 3
 LAYOUT_RING, LAYOUT_PAPER = 0, 1
+FLUX_CENTRAL, FLUX_UPWIND, FLUX_LITERAL = 0, 1, 2
 TIME_UNIFORM, TIME_SINE, TIME_TABLE, TIME_ADAPTIVE = 0, 1, 2, 3
 
 
@@ -43,7 +44,7 @@ class ProblemDesc(C.Structure):
                 ("device_ptrs", C.c_int32), ("b_node", C.c_void_p), ("D_rface", C.c_void_p),
                 ("Er_rface", C.c_void_p), ("D_tface", C.c_void_p), ("Et_tface", C.c_void_p),
                 ("nsrc", C.c_int32), ("lam", C.c_void_p), ("tpow", C.c_void_p), ("g", C.c_void_p),
-                ("nb", C.c_void_p), ("u0", C.c_void_p)]
+                ("nb", C.c_void_p), ("u0", C.c_void_p), ("E_node", C.c_void_p), ("D_origin", C.c_double)]
 
 
 class TimeDesc(C.Structure):
@@ -263,6 +264,9 @@ def problem_desc(data: dict, flux=0, bc=0):
     pd_.g = put("g", np.stack([ring_vector(data["g_origin"][q], data["g_grid"][q]) for q in range(ns)]))
     pd_.nb = put("nb", np.asarray(data["nb"]).reshape(ns, n))
     pd_.u0 = put("u0", ring_vector(data["u0_origin"], data["u0_grid"]))
+    if flux == FLUX_LITERAL and "E_grid" in data:
+        pd_.E_node = put("E", ring_vector(data["E_origin"], data["E_grid"]))
+        pd_.D_origin = float(data["D_origin"])
     pd_._keep = keep
     return pd_
 

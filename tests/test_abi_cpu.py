@@ -128,8 +128,10 @@ def test_explicit_mesh_errors(case, msg):
 
 
 @pytest.mark.parametrize("kw,msg", [(dict(precision=5), "unknown precision"),
-                                    (dict(flux=2), "flux must be 0 or 1"),
+                                    (dict(flux=3), "flux must be 0, 1 or 2"),
                                     (dict(bc=3), "bc must be 0 or 1"),
+                                    (dict(flux=2, bc=1), "Dirichlet data only"),
+                                    (dict(flux=2), "needs E_node"),
                                     (dict(nsrc=5), "nsrc must be in")])
 def test_problem_errors_are_reported_before_any_device_call(kw, msg):
     """pd_mesh_create checks its descriptors on the host first: a bad one is
