@@ -19,7 +19,9 @@
 #define PD_MAXSRC 4
 #define PD_RB 4           // rings per stencil wave (one wave = 64 columns x rb rings; FP32 instances may take 2 PD_RB)
 #define PD_STEN_WAVES 4   // waves per stencil block, stacked over consecutive rings
+#ifndef PD_ELEM_PER_BLOCK
 #define PD_ELEM_PER_BLOCK 2048
+#endif
 #define PD_RAD_THREADS 1024
 #define PD_RAD_BMAX 32    // max rows per radial segment held in registers
 #define PD_ANG_BMAX 32    // max angular nodes per lane held in registers

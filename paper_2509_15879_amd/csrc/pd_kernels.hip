@@ -2396,7 +2396,7 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
   // every load first: the ring's input (coalesced, node t + nt k) and this
   // thread's factors (node 8t + k at k nt + t)
   C xin[BW];
-  float ul[BW], fl[BW], gl[BW], zl[BW], aq[BW], ac[BW];   // factors as stored, converted at use
+  float ul[BW], fl[BW], gl[BW], zl[BW];   // factors as stored, converted at use
   C w0 = (C)0, sg = (C)1;
   if (arrow) {
     w0 = (C)in[m * n];
@@ -2412,8 +2412,6 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
     fl[k] = own ? f[fi] : 0.0f;
     gl[k] = own ? g[fi] : 0.0f;
     zl[k] = own ? z[fi] : 0.0f;
-    aq[k] = (arrow && own) ? G((const float *)I.af_q)[fi] : 0.0f;   // ring 1: frow = 0
-    ac[k] = (arrow && own) ? G((const float *)I.af_c)[fi] : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < BW; ++k) {
@@ -2501,22 +2499,27 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
 #pragma unroll
     for (int k = 0; k < BW; ++k) wl[k] -= sfac * (C)zl[k];
   }
-  // ring 1 closes the origin row: z_0 = (w_0 - c.u)/σ, z_1 = u - q z_0
-  C dot = (C)0;
+  // ring 1 closes the origin row: z_0 = (w_0 - c.u)/σ, z_1 = u - q z_0 (only
+  // the block holding ring 1 takes this branch and its barrier; the arrow
+  // vectors are loaded here, for ring 1 alone, frow = 0)
+  if (mp.y == 0) {
+    C dot = (C)0;
 #pragma unroll
-  for (int k = 0; k < BW; ++k)
-    if (k < cnt) dot += (C)ac[k] * wl[k];
+    for (int k = 0; k < BW; ++k)
+      if (arrow && k < cnt) dot += (C)G((const float *)I.af_c)[k * nt + t] * wl[k];
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) dot += __shfl_xor(dot, d, 64);
-  if (lane == 0) dsum[wv] = dot;
-  __syncthreads();
-  if (arrow) {
-    C tot = (C)0;
-    for (int w = 0; w < aw; ++w) tot += dsum[slot * aw + w];
-    const C z0 = (w0 - tot) / sg;
+    for (int d = 32; d >= 1; d >>= 1) dot += __shfl_xor(dot, d, 64);
+    if (lane == 0) dsum[wv] = dot;
+    __syncthreads();
+    if (arrow) {
+      C tot = (C)0;
+      for (int w = 0; w < aw; ++w) tot += dsum[slot * aw + w];
+      const C z0 = (w0 - tot) / sg;
 #pragma unroll
-    for (int k = 0; k < BW; ++k) wl[k] -= (C)aq[k] * z0;
-    if (t == 0) out[m * n] = (T)z0;
+      for (int k = 0; k < BW; ++k)
+        if (k < cnt) wl[k] -= (C)G((const float *)I.af_q)[k * nt + t] * z0;
+      if (t == 0) out[m * n] = (T)z0;
+    }
   }
   // back to node order through LDS, then coalesced stores
 #pragma unroll
