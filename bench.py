@@ -408,13 +408,16 @@ def cpu_baseline_worker(levels, out_path):
     """The oracle on a bounded sample of the headline workload, one thread:
     mesh, sampling, assembly, one SuperLU factorisation (fixed Δt) and the
     first `levels` levels.  Writes its timings and state to out_path (npz).
-    Runs in a child process started before anything touches the GPU."""
+    Runs in a child process started before anything touches the GPU; it
+    waits for a line on stdin (sent once the timed GPU steps are over, so
+    that its host work does not overlap them)."""
     from threadpoolctl import threadpool_limits
     from oracle import assemble, make_mesh
     from oracle.stepper import step
     from problems import sample
     from problems.workloads import CFG3, cfg3_problem
     c = CFG3
+    sys.stdin.readline()
     with threadpool_limits(1):
         t0 = time.perf_counter()
         me = make_mesh(c["m"], c["n"], 1, c["p"])
@@ -434,8 +437,16 @@ def start_cpu_baseline(levels):
     fd, path = tempfile.mkstemp(suffix=".npz", prefix="pd_oracle_")
     os.close(fd)
     proc = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
-                             str(levels), path], stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+                             str(levels), path], stdin=subprocess.PIPE, stdout=subprocess.DEVNULL,
+                            stderr=subprocess.PIPE)
     return proc, path, time.perf_counter()
+
+
+def release_cpu_baseline(job):
+    """Lets the oracle sample start (the worker waits for this line)."""
+    if job is not None:
+        job[0].stdin.write(b"go\n")
+        job[0].stdin.flush()
 
 
 def finish_cpu_baseline(job, levels, gpu_state):
@@ -460,7 +471,8 @@ def finish_cpu_baseline(job, levels, gpu_state):
         "sample": (f"the headline workload's first {levels} of {c['K']} levels on one thread: mesh, "
                    f"sampling, assembly ({t_setup:.1f} s), one SuperLU factorisation with the first "
                    f"level ({t_fact:.1f} s), then {t_level:.1f} s per level (LU solve + one refinement "
-                   f"step); {el:.1f} s in all, run beside the GPU legs in a child process"),
+                   f"step); {el:.1f} s in all, run in a child process beside the GPU legs that "
+                   f"follow the timed headline steps"),
         "full_run_estimate_cell_updates_per_s": N * c["K"] / full,
         "full_run_estimate_s": round(full, 1),
         **cpu_info(),
@@ -621,8 +633,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    # the oracle's sample runs in a child process beside the GPU legs; it is
-    # started before anything touches the GPU
+    # the oracle's sample runs in a child process beside the GPU legs after
+    # the timed steps; it is started before anything touches the GPU
     job = None if args.no_cpu_baseline else start_cpu_baseline(args.oracle_levels)
 
     import torch
@@ -663,6 +675,7 @@ def main():
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
         log(f"step {s}: {lat[-1] * 1e3:.1f} ms")
+    release_cpu_baseline(job)
     ms_per_step = 1e3 * float(np.mean(lat))
     value = cells * c["K"] / (ms_per_step / 1e3)
     x = inst.solution(pdk.LAYOUT_PAPER)

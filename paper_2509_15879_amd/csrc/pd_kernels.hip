@@ -2008,7 +2008,17 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   PdScalars *sc = I.sc;
   if (!prec_match<T>(I)) return;
   if (block_status(sc) != ST_ACTIVE) return;   // the p- and s-sweeps change the status
-  const KSet<T> &KS = kset<T>(I);
+  // the descriptor's fields are read before the first store (they then stay
+  // scalar; read after a store that may alias them they would be vector
+  // loads, and every later store would wait for the wave's memory traffic)
+  const KSet<T> KS = kset<T>(I);
+  const float *rfu = I.rf_uinv, *rff = I.rf_f, *rfg = I.rf_g;
+  const double *part_x = I.part_x, *part_v = I.part_v;
+  const int nb_elem = I.nb_elem, nb_sten = I.nb_sten, mixed = I.mixed;
+  // the scalars the update closure reads (this launch writes none of them)
+  const double sc_omega = sc->omega, sc_alpha = sc->alpha, sc_rho_cur = sc->rho_cur;
+  const double sc_tol = sc->tol, sc_bnorm2 = sc->bnorm2;
+  const int sc_iters = sc->iters, sc_maxit = sc->maxit, sc_reset = sc->reset_rh;
   constexpr int cw = CW, NSEG = NT / CW;
   const int m = I.m, n = I.n, orig = m * n, B = (m + NSEG - 1) / NSEG;
   const bool b0 = mp.y == 0 && threadIdx.x == 0;
@@ -2023,8 +2033,8 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   auto load = [&]() {
     const T *a = KS.r;
     const T *bb = (MODE == RM_P) ? KS.p : KS.v;
-    rad_load<T, MODE, BM>(n, jj, rb, klast, sc->omega, G(a), G((const T *)bb), G((const T *)KS.v),
-                          G((const float *)I.rf_uinv), G((const float *)I.rf_f), R);
+    rad_load<T, MODE, BM>(n, jj, rb, klast, sc_omega, G(a), G((const T *)bb), G((const T *)KS.v),
+                          G(rfu), G(rff), R);
   };
   // the loads are issued before the partial sums are read, except on the
   // rare closures of a level begin or a refinement, whose origin arithmetic
@@ -2077,29 +2087,29 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
       else if (sc->outer >= sc->max_outer || sc->iters >= sc->maxit) st = ST_NOCONV;
     } else {
       double tot[2];
-      consume<2>(I.part_x, I.nb_elem, tot);
+      consume<2>(part_x, nb_elem, tot);
       const double rr = tot[1];
       rho = tot[0];
       if (!(rr == rr) || !(rho == rho)) {
         st = ST_BREAKDOWN;
-      } else if (!I.mixed) {
-        rel = sqrt(rr / sc->bnorm2);
-        if (rr <= sc->tol * sc->tol * sc->bnorm2) st = ST_DONE;
-        else if (sc->iters >= sc->maxit) st = ST_NOCONV;
+      } else if (!mixed) {
+        rel = sqrt(rr / sc_bnorm2);
+        if (rr <= sc_tol * sc_tol * sc_bnorm2) st = ST_DONE;
+        else if (sc_iters >= sc_maxit) st = ST_NOCONV;
       }
       if (st == ST_ACTIVE) {
-        if (sc->reset_rh || fabs(rho) <= 1e-30 * rr) {
+        if (sc_reset || fabs(rho) <= 1e-30 * rr) {
           first = true;                  // restart from the iterate: r̂ = r, p = r
           reset = true;
           rho = rr;
           if (b0) sc->restarted = 1;
         } else {
-          beta = (rho / sc->rho_cur) * (sc->alpha / sc->omega);
+          beta = (rho / sc_rho_cur) * (sc_alpha / sc_omega);
         }
       }
       if (b0) sc->inner_first = 0;
     }
-    omega = sc->omega;
+    omega = sc_omega;
     if (b0) {
       sc->rho_next = rho;
       if (rel >= 0.0) sc->rel_resid = rel;
@@ -2109,7 +2119,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
   } else if (MODE == RM_S) {
     // α = ρ / (r̂·v), closing the v-stencil with its origin row
     double tot[2];
-    consume<2>(I.part_v, I.nb_sten, tot);
+    consume<2>(part_v, nb_sten, tot);
     const double ph0 = (double)KS.ph[orig];
     const double invd0 = sizeof(T) == 8 ? origin_invd(I, sc->inv_dt, sc->theta) : (double)KS.inv_d[orig];
     const T v0 = (T)origin_apply<T>(I, sc->inv_dt, sc->theta, ph0, tot[1], invd0);
@@ -2135,7 +2145,7 @@ __global__ __launch_bounds__(NT, 4) void k_rad(const PdInst *insts, const int2 *
     if (st != ST_ACTIVE) return;
   }
   if (pend != PEND_UPDATE) load();
-  rad_load_g<T, BM>(n, jj, rb, klast, G((const float *)I.rf_g), R);
+  rad_load_g<T, BM>(n, jj, rb, klast, G(rfg), R);
   rad_solve<T, MODE, BM, NT, CW>(m, n, jj, c, seg * B, cnt, b0, beta, omega, alpha, first, reset, R,
                          G((const T *)KS.r), G(KS.p), G((const T *)KS.v), G(KS.rh), G(KS.s), G(KS.w));
 }
@@ -2184,33 +2194,36 @@ __device__ __forceinline__ void ang_body(int m, int n, int B, int i, int lane, d
   const int cnt = max(0, min(B, n - j0));
   const bool arrow = i == 1;   // ring 1 closes the origin row (wave-uniform)
 
-  // every load first: the ring's input (coalesced, node lane + 64k) and this
-  // lane's factors (node j0 + k, stored at 64k + lane)
+  // every load first, issued together (a load under a per-lane condition
+  // becomes a branch that waits for it): the ring's input (coalesced, node
+  // lane + 64k) and this lane's factors (node j0 + k, stored at 64k + lane)
   C xin[BM], ul[BM], fl[BM], gl[BM], zl[BM];
-  C w0 = (C)0, sg = (C)1;
+  const C w0 = (C)in[m * n], sg = (C)sigma[0];
   float aq[BM], ac[BM];   // ring 1: its arrow vectors, parked in LDS (abuf) with the input
+#pragma unroll
+  for (int k = 0; k < BM; ++k) aq[k] = ac[k] = 0.0f;
   if (arrow) {
-    w0 = (C)in[m * n];
-    sg = (C)sigma[0];
+#pragma unroll
+    for (int k = 0; k < BM; ++k) {
+      if (k < B) {
+        aq[k] = qa[64 * k + lane];   // in the arrays; entries past the ring end go unused
+        ac[k] = ca[64 * k + lane];
+      }
+    }
   }
 #pragma unroll
   for (int k = 0; k < BM; ++k) {
-    aq[k] = ac[k] = 0.0f;
-    if (arrow && k < cnt) {
-      aq[k] = qa[64 * k + lane];
-      ac[k] = ca[64 * k + lane];
-    }
-    if (k < B) {
-      const int jn = min(lane + 64 * k, n - 1);
-      const int fi = frow + 64 * k + lane;
-      xin[k] = (C)in[row + jn];
-      ul[k] = (C)uinv[fi];
-      fl[k] = (C)f[fi];
-      gl[k] = (C)g[fi];
-      zl[k] = (C)z[fi];
-    } else {
-      xin[k] = ul[k] = fl[k] = gl[k] = zl[k] = (C)0;
-    }
+    // k >= B (the kernel's span beyond the instance's) rereads the last slots
+    const int kk = min(k, B - 1);
+    const int jn = min(lane + 64 * kk, n - 1);
+    const int fi = frow + 64 * kk + lane;
+    const C xv = (C)in[row + jn], uv = (C)uinv[fi], fv = (C)f[fi], gv = (C)g[fi], zv = (C)z[fi];
+    const bool in_span = k < B;
+    xin[k] = in_span ? xv : (C)0;
+    ul[k] = in_span ? uv : (C)0;
+    fl[k] = in_span ? fv : (C)0;
+    gl[k] = in_span ? gv : (C)0;
+    zl[k] = in_span ? zv : (C)0;
   }
   // node j sits at j + j/B in LDS: lane L's nodes are contiguous, one gap after each lane
 #pragma unroll
@@ -2318,10 +2331,16 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
   if (!inner_active(sc) || !prec_match<T>(I)) return;
-  const KSet<T> &KS = kset<T>(I);
-  const int m = I.m, n = I.n;
+  // the descriptor is read before the first store (read after a store that
+  // may alias it, its fields would be vector loads that later stores wait on)
+  const KSet<T> KS = kset<T>(I);
+  const int m = I.m, n = I.n, B = I.bang;
   const int lane = threadIdx.x & 63;
   const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
+  const int ic = i <= m ? i : 1;
+  const double kappa = I.af_kappa[ic - 1], alpha0 = I.af_alpha0[ic - 1];
+  const float *fu = I.af_uinv, *ff = I.af_f, *fg = I.af_g, *fz = I.af_z, *fq = I.af_q, *fc = I.af_c;
+  const double *sig = I.af_sigma;
   // the p-sweep before this launch consumed the restart flag and the
   // pending closure; only this block's thread 0 touches these fields here
   if (MODE == AM_P && mp.y == 0 && threadIdx.x == 0) {
@@ -2337,10 +2356,8 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
   __shared__ float abuf[2 * 64 * BM];                // ring 1's arrow vectors (its wave only)
   const T *in = KS.w;
   T *out = (MODE == AM_P) ? KS.ph : KS.sh;
-  ang_body<T, BM>(m, n, I.bang, i, lane, I.af_kappa[i - 1], I.af_alpha0[i - 1], G(in), G(out),
-                  G((const float *)I.af_uinv), G((const float *)I.af_f), G((const float *)I.af_g),
-                  G((const float *)I.af_z), G((const float *)I.af_q), G((const float *)I.af_c),
-                  G((const double *)I.af_sigma), tbuf[threadIdx.x >> 6], abuf);
+  ang_body<T, BM>(m, n, B, i, lane, kappa, alpha0, G(in), G(out), G(fu), G(ff), G(fg), G(fz), G(fq),
+                  G(fc), G(sig), tbuf[threadIdx.x >> 6], abuf);
 }
 
 // Ring sweep of rings with more than 1024 nodes: aw = 4 waves per ring (the
@@ -2354,14 +2371,18 @@ __global__ __launch_bounds__(256) void k_ang(const PdInst *insts, const int2 *ma
 // order.  A block of 256 threads holds 4/aw rings; every thread reaches
 // every barrier (rings past m only skip their memory accesses).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *map) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_angw(const PdInst *insts, const int2 *map) {
   using C = T;
   constexpr int BW = 8;                          // nodes per thread
   const int2 mp = map[blockIdx.x];
   const PdInst &I = insts[mp.x];
   PdScalars *sc = I.sc;
   if (!inner_active(sc) || !prec_match<T>(I)) return;   // the same for the whole block
-  const KSet<T> &KS = kset<T>(I);
+  // every field of the descriptor is read before the first store, so that
+  // the reads stay scalar: a read after a store that may alias it becomes a
+  // vector load, and each later store would then wait for all memory
+  // traffic of the wave
+  const KSet<T> KS = kset<T>(I);
   const int m = I.m, n = I.n, aw = I.aw, B = I.bang;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rpb = 4 / aw;
@@ -2369,6 +2390,14 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
   const int nt = 64 * aw, t = wr * 64 + lane;    // threads of a ring, this thread
   const int i = mp.y * rpb + slot + 1;
   const bool on = i <= m;
+  const int ic = on ? i : 1;                     // rings past m read ring 1's data (unused)
+  const double kappa_d = I.af_kappa[ic - 1], alpha0_d = I.af_alpha0[ic - 1];
+  const double sigma_d = I.af_sigma[0];
+  const GAS T *in = G((const T *)KS.w);
+  GAS T *out = G(MODE == AM_P ? KS.ph : KS.sh);
+  const GAS float *uinv = G((const float *)I.af_uinv), *f = G((const float *)I.af_f);
+  const GAS float *g = G((const float *)I.af_g), *z = G((const float *)I.af_z);
+  const GAS float *aq = G((const float *)I.af_q), *ac = G((const float *)I.af_c);
   // the p-sweep before this launch consumed the restart flag and the
   // pending closure; only this block's thread 0 touches these fields here
   if (MODE == AM_P && mp.y == 0 && threadIdx.x == 0) {
@@ -2384,34 +2413,30 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
   __shared__ C ends[4][2];                       // per ring: first and last value
   __shared__ C dsum[4];                          // per wave: ring 1's arrow dot product
   C *rbuf = tb + slot * 576 * aw;
-  const int row = (i - 1) * n, frow = (i - 1) * 64 * B;
+  const int row = (ic - 1) * n, frow = (ic - 1) * 64 * B;
   const int j0 = BW * t;
   const int cnt = on ? max(0, min(BW, n - j0)) : 0;
   const bool arrow = on && i == 1;
-  const GAS T *in = G((const T *)KS.w);
-  GAS T *out = G(MODE == AM_P ? KS.ph : KS.sh);
-  const GAS float *uinv = G((const float *)I.af_uinv), *f = G((const float *)I.af_f);
-  const GAS float *g = G((const float *)I.af_g), *z = G((const float *)I.af_z);
 
-  // every load first: the ring's input (coalesced, node t + nt k) and this
-  // thread's factors (node 8t + k at k nt + t)
+  // every load first, all of them issued (indexes clamped into the ring,
+  // values masked afterwards: a load under a per-lane condition becomes a
+  // branch that waits for it): the ring's input (coalesced, node t + nt k)
+  // and this thread's factors (node 8t + k at k nt + t)
   C xin[BW];
   float ul[BW], fl[BW], gl[BW], zl[BW];   // factors as stored, converted at use
-  C w0 = (C)0, sg = (C)1;
-  if (arrow) {
-    w0 = (C)in[m * n];
-    sg = (C)I.af_sigma[0];
-  }
+  const C w0 = (C)in[m * n], sg = (C)sigma_d;
 #pragma unroll
   for (int k = 0; k < BW; ++k) {
     const int jn = t + nt * k;
     const bool own = k < cnt;                   // implies on
-    const int fi = own ? frow + k * nt + t : 0; // indexes stay in range for rings past m
-    xin[k] = (on && jn < n) ? (C)in[(on && jn < n) ? row + jn : 0] : (C)0;
-    ul[k] = own ? uinv[fi] : 0.0f;
-    fl[k] = own ? f[fi] : 0.0f;
-    gl[k] = own ? g[fi] : 0.0f;
-    zl[k] = own ? z[fi] : 0.0f;
+    const int fi = frow + min(k * nt + t, 64 * B - 1);
+    const C xv = (C)in[row + min(jn, n - 1)];
+    const float uv = uinv[fi], fv = f[fi], gv = g[fi], zv = z[fi];
+    xin[k] = jn < n ? xv : (C)0;   // rings past m hold ring 1's values, never stored
+    ul[k] = own ? uv : 0.0f;
+    fl[k] = own ? fv : 0.0f;
+    gl[k] = own ? gv : 0.0f;
+    zl[k] = own ? zv : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < BW; ++k) {
@@ -2421,7 +2446,10 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
   __syncthreads();
   C wl[BW];
 #pragma unroll
-  for (int k = 0; k < BW; ++k) wl[k] = k < cnt ? (C)ul[k] * rbuf[j0 + k + t] : (C)0;
+  for (int k = 0; k < BW; ++k) {
+    const C v = rbuf[j0 + k + t];   // in the buffer for every thread; unset past the ring's end
+    wl[k] = k < cnt ? (C)ul[k] * v : (C)0;
+  }
   __syncthreads();   // the buffer is rewritten with the result
 
   // forward substitution: local, over the wave, over the ring's earlier waves
@@ -2489,24 +2517,34 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
       if (j0 + k == n - 1) ylast = wl[k];
     }
   }
+  // ring 1 closes the origin row: z_0 = (w_0 - c.u)/σ, z_1 = u - q z_0 (only
+  // the block holding ring 1 takes this branch and its barrier; its arrow
+  // vectors are loaded here, before the Sherman-Morrison barrier, all
+  // issued: frow = 0 for ring 1)
+  float cq[BW], qq[BW];
+  if (mp.y == 0) {
+#pragma unroll
+    for (int k = 0; k < BW; ++k) {
+      const int ai = min(k * nt + t, 64 * B - 1);
+      cq[k] = ac[ai];
+      qq[k] = aq[ai];
+    }
+  }
   // Sherman-Morrison closure of the period
   if (on && t == 0) ends[slot][0] = wl[0];
   if (on && t == (n - 1) / BW) ends[slot][1] = ylast;
   __syncthreads();
   if (on) {
-    const C kappa = (C)I.af_kappa[i - 1], alpha0 = (C)I.af_alpha0[i - 1];
+    const C kappa = (C)kappa_d, alpha0 = (C)alpha0_d;
     const C sfac = kappa * (ends[slot][0] - alpha0 * ends[slot][1]);
 #pragma unroll
     for (int k = 0; k < BW; ++k) wl[k] -= sfac * (C)zl[k];
   }
-  // ring 1 closes the origin row: z_0 = (w_0 - c.u)/σ, z_1 = u - q z_0 (only
-  // the block holding ring 1 takes this branch and its barrier; the arrow
-  // vectors are loaded here, for ring 1 alone, frow = 0)
   if (mp.y == 0) {
     C dot = (C)0;
 #pragma unroll
     for (int k = 0; k < BW; ++k)
-      if (arrow && k < cnt) dot += (C)G((const float *)I.af_c)[k * nt + t] * wl[k];
+      if (arrow && k < cnt) dot += (C)cq[k] * wl[k];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) dot += __shfl_xor(dot, d, 64);
     if (lane == 0) dsum[wv] = dot;
@@ -2517,7 +2555,7 @@ __global__ __launch_bounds__(256) void k_angw(const PdInst *insts, const int2 *m
       const C z0 = (w0 - tot) / sg;
 #pragma unroll
       for (int k = 0; k < BW; ++k)
-        if (k < cnt) wl[k] -= (C)G((const float *)I.af_q)[k * nt + t] * z0;
+        if (k < cnt) wl[k] -= (C)qq[k] * z0;
       if (t == 0) out[m * n] = (T)z0;
     }
   }
@@ -2594,10 +2632,16 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   PdScalars *sc = I.sc;
   if (!prec_match<T>(I)) return;
   if (block_status(sc) != ST_ACTIVE) return;   // this kernel changes the status
-  const KSet<T> &KS = kset<T>(I);
+  // the descriptor's fields and the scalars are read before the first store
+  // (read after it they would be vector loads that every later store waits on)
+  const KSet<T> KS = kset<T>(I);
   const int orig = I.m * I.n;
   const bool b0 = mp.y == 0 && threadIdx.x == 0;
   T *x = iterate_ptr<T>(I, sc);
+  double *part_x = I.part_x;
+  const int nb_elem = I.nb_elem;
+  const double sc_alpha = sc->alpha;
+  const bool setx = I.mixed && sc->inner_first != 0;
   const int base = mp.y * 256 * E;
   // the vectors first, then the partial sums of the t-stencil
   ElemRegs<E> R;
@@ -2629,9 +2673,8 @@ __global__ __launch_bounds__(256) void k_elem_x(const PdInst *insts, const int2 
   }
   if (st != ST_ACTIVE) return;
   double acc[2] = {0.0, 0.0};
-  elem_update<T, E>(orig + 1, base, sc->alpha, om, I.mixed && sc->inner_first != 0, orig, (double)t0,
-                    R, G(x), G(KS.r), acc);
-  produce<2>(acc, I.part_x, I.nb_elem, mp.y);
+  elem_update<T, E>(orig + 1, base, sc_alpha, om, setx, orig, (double)t0, R, G(x), G(KS.r), acc);
+  produce<2>(acc, part_x, nb_elem, mp.y);
 }
 
 // ------------------------------------------------------------ adaptivity
