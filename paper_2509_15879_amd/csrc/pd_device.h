@@ -32,10 +32,12 @@
 #define PD_NSOL 5         // rotating solution slots: the PD_NHIST levels and the iterate
 #define PD_RANNACHER 2    // backward-Euler steps that start an adaptive Crank-Nicolson solve
 #define PD_STALL 20       // steps at dt_min above the error tolerance that end an adaptive solve
-#define PD_NBEGIN (2 + PD_NHIST)   // partials of the level-begin stencil: ||D^-1 b||², ||D^-1 r||², S0 per level
+#define PD_NBEGIN 2        // partials of the level-begin pass: ||D^-1 b||², ||D^-1 r||²
 // partials of the Gram pass: Z Z^T (upper triangle), Z r_c for both
-// candidates, ||r_c||² for both, S0 per level
-#define PD_NGRAM (10 + 2 * PD_NHIST + 2 + PD_NHIST)
+// candidates, ||r_c||² for both, S0 of n^k (the earlier levels' S0 are kept
+// in PdScalars::s0h from their own Gram passes)
+#define PD_GRAM_S0 (10 + 2 * PD_NHIST + 2)
+#define PD_NGRAM (PD_GRAM_S0 + 1)
 
 // Slot holding n^{k-back} (back = 0..3) or, for back = -1, the iterate of
 // the level under way, under rotation `rot`.
@@ -84,6 +86,11 @@ struct PdScalars {
                             // Crank-Nicolson solve starts with PD_RANNACHER
                             // backward-Euler steps)
   int stall, pad6;          // consecutive steps forced through at dt_min with e > 2 tol_time
+  // the level-begin passes reuse L n^{k-a} and S0(n^{k-a}) of the earlier
+  // levels (PdInst::lsol): S0 per solution slot, set by each level's Gram
+  // totals; the diagonal of L is stored once per solve call
+  double s0h[PD_NSOL];
+  int ld_ready, pad7;
 };
 
 template <typename T>
@@ -114,7 +121,10 @@ struct PdInst {
   const double *lam;        // [nsrc]
   const int *tpow;          // [nsrc]
   double *t_table;          // [K+1] (adaptive stepping writes its levels as it goes)
-  double *sol[PD_NSOL];     // rotating (sol_slot): n^{k-2}, n^{k-1}, n^k, iterate
+  double *sol[PD_NSOL];     // rotating (sol_slot): n^{k-3} .. n^k, iterate
+  double *lsol[PD_NSOL];    // L of the slot's state, written by the Gram pass of the level
+                            // where it is n^k (L: the operator without 1/dt, θ)
+  double *ldiag;            // [npad] diagonal of L (faces only; l_diag)
   double *bvec;             // right-hand side (FP64)
   double *rout;             // FP64 outer residual (mixed)
   double *diag;             // [npad] diagonal of I/dt + θL at the last factorisation
@@ -141,6 +151,7 @@ struct PdInst {
   double *part_b, *part_v, *part_t, *part_ur, *part_a;   // [slots * nb_sten]
   double *part_x;                                        // [2 * nb_elem]
   double *part_g;                                        // [PD_NGRAM * nb_sten]
+  double *gram_tot;                                      // [PD_NGRAM] totals of part_g
   PdScalars *sc;
   int *n_active;            // shared counter of the batch (device)
   int *lvl_out;             // (levels done, status) written at each level end
@@ -158,5 +169,6 @@ struct PdInst {
   const double *crs;
   double *cr_c;             // [m+1] the correction of the level that just ended
   double *part_c;           // [m * ncg] per ring and column group: Σ_j V_ij (b - A x)_ij
+  double *cr_f;             // [m+1] the ring totals of part_c (index i = ring, 0 unused)
   double *part_c0;          // [nb_sten] S0 partials of the same pass
 };

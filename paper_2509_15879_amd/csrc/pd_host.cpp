@@ -247,6 +247,8 @@ void carve(pd_instance *I, Carver &c) {
   H.lam = c.take<double>(PD_MAXSRC);
   H.tpow = c.take<int>(PD_MAXSRC);
   for (int k = 0; k < PD_NSOL; ++k) H.sol[k] = c.take<double>(np);
+  for (int k = 0; k < PD_NSOL; ++k) H.lsol[k] = c.take<double>(np);
+  H.ldiag = c.take<double>(np);
   for (int k = 0; k < 3; ++k) H.fdot[k] = c.take<double>(np);
   H.bvec = c.take<double>(np);
   H.diag = c.take<double>(np);
@@ -301,6 +303,7 @@ void carve(pd_instance *I, Carver &c) {
   const int nbs = I->T.nb_sten;
   H.part_b = c.take<double>(PD_NBEGIN * (size_t)nbs);
   H.part_g = c.take<double>(PD_NGRAM * (size_t)nbs);
+  H.gram_tot = c.take<double>(PD_NGRAM);
   H.part_v = c.take<double>(2 * (size_t)nbs);
   H.part_t = c.take<double>(3 * (size_t)nbs);
   H.part_ur = c.take<double>(2 * (size_t)nbs);
@@ -310,6 +313,7 @@ void carve(pd_instance *I, Carver &c) {
   H.crs = c.take<double>(6 * (size_t)(m + 1));
   H.cr_c = c.take<double>(m + 1);
   H.part_c = c.take<double>((size_t)m * I->T.ncg);
+  H.cr_f = c.take<double>((size_t)m + 1);
   H.part_c0 = c.take<double>(nbs);
   I->sc = c.take<PdScalars>(1);
   H.sc = I->sc;

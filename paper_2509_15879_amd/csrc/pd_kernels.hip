@@ -17,6 +17,7 @@
 //   k_fact_rad      radial-line LU of (I + D^{-1}R) per θ-column (when Δt/θ change)
 //   k_fact_ang      ring-periodic LU of (I + D^{-1}Θ) per ring, Sherman-Morrison
 //   k_sten<GRAM>    the least-squares problem of the initial guess (partial sums)
+//   k_gram_total    their totals, one block per instance and sum
 //   k_sten<BEGIN>   rhs, initial guess (extrapolation, corrected by least squares) and its residual
 //   BiCGSTAB cycles k_rad -> k_ang -> k_sten<V> -> k_rad -> k_ang -> k_sten<T> -> k_elem_x
 //   (mixed precision: k_sten<UR> refines in FP64 between FP32 inner solves)
@@ -951,6 +952,9 @@ struct Pre2 {
 struct Pre3 {
   double a, b, c;
 };
+struct Hist3 {   // n^{k-1..k-3} and their L at a node
+  double x1, x2, x3, l1, l2, l3;
+};
 __device__ __forceinline__ Nil no_pre(int) { return Nil{}; }
 
 struct TileGeo {
@@ -1080,6 +1084,13 @@ enum { SM_APPLY = 0, SM_BEGIN = 1, SM_V = 2, SM_T = 3, SM_UR = 4, SM_EST = 5, SM
 // Origin rows, closed by a later kernel from the producers' partial sums
 // (the ring-1 face sums S0 and the ring parts of the norms).
 
+// S0 (the origin row's ring-1 face sum) of n^{k-a}: the Gram pass's total
+// s0k for n^k (and for the levels the guess does not use, which alias n^k),
+// the value its own Gram pass kept for an earlier level.
+__device__ __forceinline__ double s0_of(const PdScalars *sc, int a, double s0k) {
+  return (a == 0 || a > sc->ex_n) ? s0k : sc->s0h[sol_slot(sc->rot, a)];
+}
+
 // Level begin at the origin: rhs b_0, the guess and its scaled residual.
 struct OriginBegin {
   double b, xg, r, rs, bb, rr;
@@ -1090,10 +1101,11 @@ __device__ __forceinline__ OriginBegin origin_begin(const PdInst &I, const PdSca
   const double inv_dt = sc->inv_dt, th = sc->theta;
   const int ne = sc->ex_n;
   const double bo = I.has_b ? I.b_node[orig] : 0.0;
+  const double s0k = I.gram_tot[PD_GRAM_S0];
   double xa[PD_NHIST], La[PD_NHIST];
   for (int a = 0; a < PD_NHIST; ++a) {
     xa[a] = I.sol[sol_slot(sc->rot, a <= ne ? a : 0)][orig];
-    La[a] = I.inv_V0 * tot[2 + a] + bo * xa[a];
+    La[a] = I.inv_V0 * s0_of(sc, a, s0k) + bo * xa[a];
   }
   double b = inv_dt * xa[0] - (1.0 - th) * La[0];
   for (int q = 0; q < I.nsrc; ++q) b += sc->cq[q] * I.g[q * I.npad + orig];
@@ -1161,7 +1173,7 @@ __device__ __forceinline__ int begin_guess(const PdInst &I, const PdScalars *sc,
 #pragma unroll
   for (int a = 0; a < PD_NHIST; ++a) {
     const double xa = I.sol[sol_slot(sc->rot, a <= ne ? a : 0)][orig];
-    const double La = I.inv_V0 * tot[20 + a] + bo * xa;
+    const double La = I.inv_V0 * s0_of(sc, a, tot[PD_GRAM_S0]) + bo * xa;
     y[a] = (inv_dt * xa + th * La) * id;
     if (a == 0) {
       xa0 = xa;
@@ -1301,15 +1313,45 @@ __device__ __forceinline__ double origin_apply(const PdInst &I, double inv_dt, d
   return (inv_dt * x0 + th * (I.inv_V0 * S0 + bo * x0)) * invd0;
 }
 
+// Totals of the Gram pass's partial sums, one block per instance and slot,
+// read by every block of the level-begin stencil (which would otherwise
+// each sum PD_NGRAM x nb_sten partials).  Thread t sums blocks t, t + 256,
+// ... in ascending order, then the block adds its threads in a fixed tree,
+// so the order depends on the instance's own tiling alone.
+__global__ __launch_bounds__(256) void k_gram_total(const PdInst *insts, int ninst) {
+  const int q = blockIdx.x / PD_NGRAM, k = blockIdx.x % PD_NGRAM;
+  if (q >= ninst) return;
+  const PdInst &I = insts[q];
+  PdScalars *sc = I.sc;
+  if (sc->status != ST_ACTIVE || sc->stage != STAGE_START) return;
+  const int nb = I.nb_sten;
+  const double *part = I.part_g + (size_t)k * nb;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) v += part[b];
+  __shared__ double red[4];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tot = ((red[0] + red[1]) + red[2]) + red[3];
+    I.gram_tot[k] = tot;
+    if (k == PD_GRAM_S0) {
+      sc->s0h[sol_slot(sc->rot, 0)] = tot;   // S0 of n^k, for the levels to come
+      sc->ld_ready = 1;                      // the Gram pass has stored L's diagonal
+    }
+  }
+}
+
 // Stencil kernels.  TK: storage type of the Krylov set the mode works on.
 // Ring rows only; the origin row is closed by the consumer of the partials.
 //  SM_APPLY: y = x/dt + θ L x (diagnostic; partial S0)
-//  SM_GRAM:  (level begin, first pass) b as below and y_a = D^{-1}A n^{k-a};
-//            partials: the Gram matrix of the difference directions of the
-//            y_a, their products with D^{-1}b, S0 of n^k .. n^{k-3}
-//  SM_BEGIN: b = x^k/dt - (1-θ) L x^k + Σ_q c_q g_q + boundary;
-//            x0 = x^k + ρ (x^k - x^{k-1});  r = D^{-1}(b - A x0);  r̂ = r
-//            partials ||D^{-1}b||², ||r||², S0(x^k), S0(x^{k-1})
+//  SM_GRAM:  (level begin, first pass) L n^k (stored), b as below and
+//            y_a = D^{-1}A n^{k-a} from the stored L n^{k-a}; partials: the
+//            Gram matrix of the difference directions of the y_a, their
+//            products with D^{-1}b, S0 of n^k
+//  SM_BEGIN: (no stencil) b = x^k/dt - (1-θ) L x^k + Σ_q c_q g_q + boundary;
+//            x0 = Σ_a w_a n^{k-a};  r = D^{-1}(b - A x0);  r̂ = r
+//            partials ||D^{-1}b||², ||r||²
 //  SM_V:     v = D^{-1} A p̂,  partials r̂·v, S0(p̂)
 //  SM_T:     t = D^{-1} A ŝ,  partials t·s, t·t, S0(ŝ)
 //  SM_UR:    (mixed, when the inner solve has converged) r <- r - A d in
@@ -1377,13 +1419,24 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
                            });
     produce<1>(S0, I.part_a, I.nb_sten, mp.y);
   } else if (MODE == SM_GRAM) {
-    // the rows of the least-squares problem of the guess, summed per block
+    // the rows of the least-squares problem of the guess, summed per block.
+    // The stencil runs on n^k alone: L n^k is stored (lsol) for this level's
+    // begin pass and the next levels, whose L n^{k-a} are read back (the same
+    // values a stencil on those states would give).  The first Gram pass of
+    // a solve call also stores L's diagonal.
     const double inv_dt = sc->inv_dt, th = sc->theta;
-    const int ne = sc->ex_n;
-    const double *xk0 = I.sol[sol_slot(sc->rot, 0)];
-    const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
-    const double *xk2 = I.sol[sol_slot(sc->rot, ne >= 2 ? 2 : 0)];
-    const double *xk3 = I.sol[sol_slot(sc->rot, ne >= 3 ? 3 : 0)];
+    const int ne = sc->ex_n, rot = sc->rot;
+    const bool put_ld = sc->ld_ready == 0;
+    const int s0 = sol_slot(rot, 0);
+    const double *xk0 = I.sol[s0];
+    // levels the guess does not use read n^k (their values are not used)
+    const GAS double *xh1 = G((const double *)(ne >= 1 ? I.sol[sol_slot(rot, 1)] : xk0));
+    const GAS double *xh2 = G((const double *)(ne >= 2 ? I.sol[sol_slot(rot, 2)] : xk0));
+    const GAS double *xh3 = G((const double *)(ne >= 3 ? I.sol[sol_slot(rot, 3)] : xk0));
+    const GAS double *lh1 = G((const double *)(ne >= 1 ? I.lsol[sol_slot(rot, 1)] : xk0));
+    const GAS double *lh2 = G((const double *)(ne >= 2 ? I.lsol[sol_slot(rot, 2)] : xk0));
+    const GAS double *lh3 = G((const double *)(ne >= 3 ? I.lsol[sol_slot(rot, 3)] : xk0));
+    GAS double *lo = G(I.lsol[s0]), *ldo = G(I.ldiag);
     double cq[PD_MAXSRC], w0[PD_NHIST], w1[PD_NHIST];
     for (int q = 0; q < PD_MAXSRC; ++q) cq[q] = sc->cq[q];
     for (int a = 0; a < PD_NHIST; ++a) {
@@ -1392,13 +1445,20 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
     }
     const int nsrc = I.nsrc, npad = I.npad;
     double acc[PD_NGRAM] = {};
-    double S0[PD_NHIST] = {};
+    double S0[1] = {0.0};
     const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb);
     if (wave_on)
-      sten_tile<double, double, PD_NHIST>(
-          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk0), G(xk1), G(xk2),
-          G(xk3), inv_rw, inv_dth, bnode, S0, no_pre,
-          [&](int i, int j, int idx, const double *xc, const double *Lx, double ld, Nil) {
+      sten_tile<double, double, 1>(
+          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk0), G(xk0), G(xk0),
+          G(xk0), inv_rw, inv_dth, bnode, S0,
+          [&](int idx) { return Hist3{xh1[idx], xh2[idx], xh3[idx], lh1[idx], lh2[idx], lh3[idx]}; },
+          [&](int i, int j, int idx, const double *xk, const double *Lk, double ld, Hist3 hq) {
+            lo[idx] = Lk[0];
+            if (put_ld) ldo[idx] = ld;
+            const double xc[PD_NHIST] = {xk[0], ne >= 1 ? hq.x1 : xk[0], ne >= 2 ? hq.x2 : xk[0],
+                                         ne >= 3 ? hq.x3 : xk[0]};
+            const double Lx[PD_NHIST] = {Lk[0], ne >= 1 ? hq.l1 : Lk[0], ne >= 2 ? hq.l2 : Lk[0],
+                                         ne >= 3 ? hq.l3 : Lk[0]};
             double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
             for (int q = 0; q < nsrc; ++q) b += cq[q] * gsrc[q * npad + idx];
             if (i == m) {
@@ -1428,80 +1488,102 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
             acc[18] += r0 * r0;
             acc[19] += r1 * r1;
           });
-#pragma unroll
-    for (int a = 0; a < PD_NHIST; ++a) acc[20 + a] = S0[a];
+    acc[PD_GRAM_S0] = S0[0];
     produce<PD_NGRAM>(acc, I.part_g, I.nb_sten, mp.y);
   } else if (MODE == SM_BEGIN) {
-    // FP64 operator on n^k .. n^{k-3} (levels the guess does not use alias
-    // n^k and carry zero weight).  Every block solves the same small
-    // problem of the guess from the Gram pass's partials; block 0 records
-    // the weights for the origin row.
+    // b, the guess x0 = Σ_a w_a n^{k-a} and its residual D^{-1}(b - A x0),
+    // node by node from the states, their L (lsol: A x0 = Σ_a w_a
+    // (n^{k-a}/dt + θ L n^{k-a})) and L's diagonal; no stencil.  Every
+    // block solves the same small problem of the guess from the Gram
+    // totals; block 0 records the weights for the origin row.  The nodes
+    // and the order of the partial sums are the stencil tile's.
     const double inv_dt = sc->inv_dt, th = sc->theta;
-    const int ne = sc->ex_n;
+    const int ne = sc->ex_n, rot = sc->rot;
     double w0[PD_NHIST];
     int kind;
     {
       double tg[PD_NGRAM];
-      consume<PD_NGRAM>(I.part_g, I.nb_sten, tg);
+#pragma unroll
+      for (int k = 0; k < PD_NGRAM; ++k) tg[k] = I.gram_tot[k];
       kind = begin_guess(I, sc, tg, w0);
     }
-    if (mp.y == 0 && threadIdx.x == 0) {
-      sc->guess_kind = kind;
-      for (int a = 0; a < PD_NHIST; ++a) sc->guess_w[a] = w0[a];
+    const GAS double *xs[PD_NHIST], *ls[PD_NHIST];
+#pragma unroll
+    for (int a = 0; a < PD_NHIST; ++a) {
+      const int sl = sol_slot(rot, a <= ne ? a : 0);
+      xs[a] = G((const double *)I.sol[sl]);
+      ls[a] = G((const double *)I.lsol[sl]);
     }
-    const double *xk0 = I.sol[sol_slot(sc->rot, 0)];
-    const double *xk1 = I.sol[sol_slot(sc->rot, ne >= 1 ? 1 : 0)];
-    const double *xk2 = I.sol[sol_slot(sc->rot, ne >= 2 ? 2 : 0)];
-    const double *xk3 = I.sol[sol_slot(sc->rot, ne >= 3 ? 3 : 0)];
-    double *x0 = I.sol[sol_slot(sc->rot, -1)];
+    double *x0 = I.sol[sol_slot(rot, -1)];
     double cq[PD_MAXSRC];
     for (int q = 0; q < PD_MAXSRC; ++q) cq[q] = sc->cq[q];
     const int nsrc = I.nsrc, npad = I.npad;
-    double acc[PD_NBEGIN] = {};   // ||D^-1 b||², ||D^-1 r||², S0 per level
-    double S0[PD_NHIST] = {};
-    const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb);
+    const GAS double *gmr = G(I.k64.gm_r), *gsrc = G(I.g), *nbv = G(I.nb), *ldv = G(I.ldiag);
     GAS double *bv = G(I.bvec), *xo = G(x0);
     GAS double *rout = G(I.rout);
     GAS double *r64 = G(I.k64.r), *rh64 = G(I.k64.rh);
     GAS float *r32 = G(I.k32.r), *rh32 = G(I.k32.rh), *id32 = G(I.inv_diag32);
     const bool mixed = I.mixed;
-    if (wave_on)
-      sten_tile<double, double, PD_NHIST>(
-          geo, G(I.k64.gp_r), G(I.k64.gm_r), G(I.k64.gp_t), G(I.k64.gm_t), G(xk0), G(xk1), G(xk2),
-          G(xk3), inv_rw, inv_dth, bnode, S0, no_pre,
-          [&](int i, int j, int idx, const double *xc, const double *Lx, double ld, Nil) {
-            double b = inv_dt * xc[0] - (1.0 - th) * Lx[0];
-            for (int q = 0; q < nsrc; ++q) b += cq[q] * gsrc[q * npad + idx];
-            if (i == m) {
-              double Nm = 0.0;
-              for (int q = 0; q < nsrc; ++q) Nm += cq[q] * nbv[q * n + j];
-              b += inv_rw[i] * inv_dth[j] * gmr[m * n + j] * Nm;
-            }
-            double xg = 0.0, Lg = 0.0;
+    if (mp.y == 0 && threadIdx.x == 0) {
+      sc->guess_kind = kind;
+      for (int a = 0; a < PD_NHIST; ++a) sc->guess_w[a] = w0[a];
+    }
+    double acc[PD_NBEGIN] = {};   // ||D^-1 b||², ||D^-1 r||²
+    if (wave_on && geo.act) {
+      const int jc = geo.jc, nr = geo.i1 - geo.i0 + 1;
+      // rings of the tile in groups of four, every load of a group issued
+      // first (rows past the tile reread its last row and are not stored)
+      for (int h0 = 0; h0 < nr; h0 += 4) {
+        double xv[4][PD_NHIST], lv[4][PD_NHIST], ldn[4], gq[4][PD_MAXSRC];
 #pragma unroll
-            for (int a = 0; a < PD_NHIST; ++a) {
-              xg += w0[a] * xc[a];
-              Lg += w0[a] * Lx[a];
-            }
-            const double r = b - (inv_dt * xg + th * Lg);
-            const double id = 1.0 / diag_of(inv_dt, th, ld);
-            const double rs = r * id, bs = b * id;
-            bv[idx] = b;
-            xo[idx] = xg;
-            if (mixed) {
-              rout[idx] = r;
-              r32[idx] = (float)rs;
-              rh32[idx] = (float)rs;
-              id32[idx] = (float)id;
-            } else {
-              r64[idx] = rs;
-              rh64[idx] = rs;
-            }
-            acc[0] += bs * bs;
-            acc[1] += rs * rs;
-          });
+        for (int u = 0; u < 4; ++u) {
+          const int idx = (min(geo.i0 + h0 + u, geo.i1) - 1) * n + jc;
 #pragma unroll
-    for (int a = 0; a < PD_NHIST; ++a) acc[2 + a] = S0[a];
+          for (int a = 0; a < PD_NHIST; ++a) {
+            xv[u][a] = xs[a][idx];
+            lv[u][a] = ls[a][idx];
+          }
+          ldn[u] = ldv[idx];
+#pragma unroll
+          for (int q = 0; q < PD_MAXSRC; ++q) gq[u][q] = gsrc[max(0, min(q, nsrc - 1)) * npad + idx];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = geo.i0 + h0 + u;
+          if (i > geo.i1) break;
+          const int idx = (i - 1) * n + jc;
+          double b = inv_dt * xv[u][0] - (1.0 - th) * lv[u][0];
+          for (int q = 0; q < nsrc; ++q) b += cq[q] * gq[u][q];
+          if (i == m) {
+            double Nm = 0.0;
+            for (int q = 0; q < nsrc; ++q) Nm += cq[q] * nbv[q * n + jc];
+            b += inv_rw[i] * inv_dth[jc] * gmr[m * n + jc] * Nm;
+          }
+          double xg = 0.0, Lg = 0.0;
+#pragma unroll
+          for (int a = 0; a < PD_NHIST; ++a) {
+            xg += w0[a] * xv[u][a];
+            Lg += w0[a] * lv[u][a];
+          }
+          const double r = b - (inv_dt * xg + th * Lg);
+          const double id = 1.0 / diag_of(inv_dt, th, ldn[u]);
+          const double rs = r * id, bs = b * id;
+          bv[idx] = b;
+          xo[idx] = xg;
+          if (mixed) {
+            rout[idx] = r;
+            r32[idx] = (float)rs;
+            rh32[idx] = (float)rs;
+            id32[idx] = (float)id;
+          } else {
+            r64[idx] = rs;
+            rh64[idx] = rs;
+          }
+          acc[0] += bs * bs;
+          acc[1] += rs * rs;
+        }
+      }
+    }
     produce<PD_NBEGIN>(acc, I.part_b, I.nb_sten, mp.y);
   } else if (MODE == SM_V || MODE == SM_T) {
     const double inv_dt = sc->inv_dt, th = sc->theta;
@@ -1643,13 +1725,26 @@ __global__ __launch_bounds__(256) void k_sten(const PdInst *insts, const int2 *m
 // scheme's solution is unchanged (the correction only moves the iterate
 // towards it).
 //
-// k_coarse (one block per instance) sums SM_RES's per-ring partials in a
-// fixed order, closes the origin row and solves the tridiagonal system by
+// k_ring_total sums SM_RES's partials of every ring (one wave per ring, its
+// column groups over the lanes, a fixed butterfly).  k_coarse (one block
+// per instance) closes the origin row and solves the tridiagonal system by
 // segments: every thread owns a contiguous run of rows; the pivots follow
 // from the continuants q_i = d_i q_{i-1} - a_i c_{i-1} q_{i-2} (2x2 matrix
 // products, rescaled by powers of two), and the forward and back
 // substitutions are affine recurrences; each is joined across the threads
 // by a scan in LDS.  k_cadd adds c to the iterate.
+
+__global__ __launch_bounds__(256) void k_ring_total(const PdInst *insts, const int2 *map) {
+  const int2 mp = map[blockIdx.x];
+  const PdInst &I = insts[mp.x];
+  if (!level_converged(I.sc)) return;
+  const int i = mp.y * 4 + (threadIdx.x >> 6) + 1;
+  if (i > I.m) return;                         // the whole wave
+  const int lane = threadIdx.x & 63, ncg = I.ncg;   // ncg <= 32 (n <= 2048)
+  double v = lane < ncg ? I.part_c[(size_t)(i - 1) * ncg + lane] : 0.0;
+  v = wave_sum(v);
+  if (lane == 0) I.cr_f[i] = v;
+}
 
 constexpr int PD_CC_THREADS = 256;
 constexpr int PD_CC_ROWS = 9;   // rows per thread: 256 x 9 >= 2049 = the most rings plus the origin
@@ -1680,36 +1775,42 @@ __global__ __launch_bounds__(PD_CC_THREADS) void k_coarse(const PdInst *insts) {
   if (!level_converged(sc)) return;   // the same for every thread of the block
   __shared__ Mat2 shm[PD_CC_THREADS];
   __shared__ Aff sha[PD_CC_THREADS];
-  const int m = I.m, n = I.n, M1 = m + 1, orig = m * n, ncg = I.ncg;
+  const int m = I.m, n = I.n, M1 = m + 1, orig = m * n;
   const double inv_dt = sc->inv_dt, th = sc->theta;
   double s0[1];
   consume<1>(I.part_c0, I.nb_sten, s0);
-  const double *cV = I.crs, *cB = I.crs + M1, *cO = I.crs + 2 * M1, *cI = I.crs + 3 * M1;
-  const double *cU = I.crs + 4 * M1, *cL = I.crs + 5 * M1;
+  const double *cV = I.crs, *cU = I.crs + 4 * M1;
   const int t = threadIdx.x;
   const int S = (M1 + blockDim.x - 1) / blockDim.x;   // <= PD_CC_ROWS
   const int r0 = t * S;
   const int cnt = max(0, min(S, M1 - r0));
   double d[PD_CC_ROWS], a[PD_CC_ROWS], c[PD_CC_ROWS], f[PD_CC_ROWS];
+  // the origin's residual (thread 0 only), then every row's coefficients,
+  // all loads issued (rows past the end reread the last row, masked below)
+  double f0 = 0.0;
+  if (t == 0) {
+    const double x0 = I.sol[sol_slot(sc->rot, -1)][orig];
+    const double bo = I.has_b ? I.b_node[orig] : 0.0;
+    const double r = I.bvec[orig] - (inv_dt * x0 + th * (I.inv_V0 * s0[0] + bo * x0));
+    f0 = cV[0] * r;
+  }
+  {
+    const GAS double *gc = G(I.crs), *gf = G((const double *)I.cr_f);
+    double v[7][PD_CC_ROWS];
 #pragma unroll
-  for (int k = 0; k < PD_CC_ROWS; ++k) {
-    d[k] = 1.0;
-    a[k] = c[k] = f[k] = 0.0;
-    if (k < cnt) {
-      const int i = r0 + k;
-      d[k] = cV[i] * inv_dt + th * (cB[i] + cO[i] + cI[i]);
-      c[k] = -th * cU[i];
-      a[k] = -th * cL[i];
-      if (i == 0) {
-        const double x0 = I.sol[sol_slot(sc->rot, -1)][orig];
-        const double bo = I.has_b ? I.b_node[orig] : 0.0;
-        const double r = I.bvec[orig] - (inv_dt * x0 + th * (I.inv_V0 * s0[0] + bo * x0));
-        f[k] = cV[0] * r;
-      } else {
-        double sum = 0.0;
-        for (int g = 0; g < ncg; ++g) sum += I.part_c[(size_t)(i - 1) * ncg + g];
-        f[k] = sum;
-      }
+    for (int k = 0; k < PD_CC_ROWS; ++k) {
+      const int i = min(r0 + k, M1 - 1);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) v[q][k] = gc[q * M1 + i];
+      v[6][k] = gf[i];
+    }
+#pragma unroll
+    for (int k = 0; k < PD_CC_ROWS; ++k) {
+      const bool own = k < cnt;
+      d[k] = own ? v[0][k] * inv_dt + th * (v[1][k] + v[2][k] + v[3][k]) : 1.0;
+      c[k] = own ? -th * v[4][k] : 0.0;
+      a[k] = own ? -th * v[5][k] : 0.0;
+      f[k] = own ? (r0 + k == 0 ? f0 : v[6][k]) : 0.0;
     }
   }
   const double cprev = (cnt > 0 && r0 > 0) ? -th * cU[r0 - 1] : 0.0;   // c_{r0-1}
@@ -2888,6 +2989,7 @@ void launch_factor(const LaunchSet &L, hipStream_t s) {
 void launch_begin(const LaunchSet &L, hipStream_t s) {
   go(KF_BEGIN, k_sten<double, SM_GRAM>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
      (const double *)nullptr, (double *)nullptr);
+  go(KF_BEGIN, k_gram_total, dim3(L.ninst * PD_NGRAM), dim3(256), s, L.insts, L.ninst);
   go(KF_BEGIN, k_sten<double, SM_BEGIN>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
      (const double *)nullptr, (double *)nullptr);
 }
@@ -2937,6 +3039,8 @@ static void cycle_t(const LaunchSet &L, hipStream_t s) {
 void launch_level_end(const LaunchSet &L, hipStream_t s) {
   go(KF_LEVEL_END, k_sten<double, SM_RES>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
      (const double *)nullptr, (double *)nullptr);
+  go(KF_LEVEL_END, k_ring_total, g1(L.nb_ang), dim3(256), s, (const PdInst *)L.insts,
+     (const int2 *)L.map_ang);
   go(KF_LEVEL_END, k_coarse, g1(L.ninst), dim3(PD_CC_THREADS), s, (const PdInst *)L.insts);
   go(KF_LEVEL_END, k_cadd, g1(L.nb_elem), dim3(256), s, (const PdInst *)L.insts, (const int2 *)L.map_elem);
 }

@@ -11,8 +11,7 @@ struct LaunchSet {
   PdInst *insts = nullptr;
   int ninst = 0;
   int2 *map_sten = nullptr, *map_elem = nullptr, *map_rad = nullptr, *map_ang = nullptr;
-  int2 *map_frad = nullptr, *map_fang = nullptr;
-  int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0, nb_frad = 0, nb_fang = 0;
+  int nb_sten = 0, nb_elem = 0, nb_rad = 0, nb_ang = 0;
   int mixed_any = 0, fp64_any = 0;
   int adaptive_any = 0;             // some instance steps adaptively (level-end pass in the round head)
   int max_bang = 1;                 // longest angular lane span of the batch (factorisation)
