@@ -520,9 +520,11 @@ def cfg3_desc(pdk, tol, K=None):
     return pdk.time_desc(c["theta"], K, c["dt"] * K, pdk.TIME_UNIFORM, tol=tol, max_seconds=120.0)
 
 
-def roofline_of(pdk, run_step, w, cells_iters, traffic_table):
+def roofline_of(pdk, run_step, w, cells_iters, traffic_table, instance_iters=None):
     """Event-stamped extra step: per-family launch times; the dominant
-    kernel's algorithmic bytes per launch over its average launch time."""
+    kernel's algorithmic bytes per launch over its average launch time.
+    instance_iters (one instance): the share of the p-sweep launches that
+    found the instance iterating (the rest wait for the next round head)."""
     pdk.kernel_timing(True, reset=True)
     t0 = time.perf_counter()
     run_step()
@@ -546,6 +548,8 @@ def roofline_of(pdk, run_step, w, cells_iters, traffic_table):
         "kernel_ms": {k: round(v, 2) for k, v in kms.items()},
         "profiled_step_ms": round(prof_ms, 1),
         "measured_on": "an extra step, each launch stamped by its own start/stop events",
+        **({"active_launch_fraction": round(instance_iters / max(1, kcnt["rad_p"]), 4)}
+           if instance_iters is not None else {}),
     }
 
 
@@ -620,7 +624,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--schedule", default=None,
-                    help="groups,cycles_per_graph,fp32_stencil_rings: use this schedule instead of tuning "
+                    help="groups,cycles_per_graph,stencil_rings: use this schedule instead of tuning "
                          "(e.g. to profile the schedule an un-profiled run chose)")
     ap.add_argument("--cpu-baseline-worker", nargs=2, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
@@ -695,7 +699,7 @@ def main():
     acc["bar"] = "L2-relative <= 1e-8 against the FP64 oracle (levels 200, stored samples)"
 
     # roofline of the dominant kernel on one more, event-stamped step
-    roof = roofline_of(pdk, run_step, 8, cells * iters, TRAFFIC.get("cfg3_fp64"))
+    roof = roofline_of(pdk, run_step, 8, cells * iters, TRAFFIC.get("cfg3_fp64"), instance_iters=iters)
     # the GPU state after the oracle sample's levels, for the live comparison
     early = None
     if job is not None:
@@ -717,7 +721,7 @@ def main():
             "m": c["m"], "n": c["n"], "unknowns": cells, "levels": c["K"], "tol_per_step": args.tol,
             "precision": "fp64", "parallelism": "single GPU, one instance",
             "schedule": {"groups": tuned["best"][0], "cycles_per_graph": tuned["best"][1],
-                         "fp32_stencil_rings": tuned["best"][2], "autotune_ms_first_levels": tuned["ms"]},
+                         "stencil_rings": tuned["best"][2], "autotune_ms_first_levels": tuned["ms"]},
         },
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),

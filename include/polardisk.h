@@ -415,17 +415,17 @@ int pd_batch_destroy(pd_batch *batch);
  * active-instance count is read back after each round).  An instance can
  * only start a level at a round head, so rounds about as long as a level's
  * iterations suit batch solves; the serving loop caps them at 4 cycles.
- * fp32_stencil_rings: rings per wave of the stencil tiles of FP32 (mixed)
- * instances, 4 or 8 (0 = 4); deeper tiles halve the waves and suit large
- * batches.  FP64 instances always take 4.  It changes the summation order
- * of an FP32 instance's partial sums, so results are the same alone and
+ * stencil_rings: rings per wave of the stencil tiles, 4 or 8 (0 = 4), for
+ * every instance; deeper tiles halve the stencil blocks, their edge reads
+ * and the partial sums that later kernels read.  It changes the summation
+ * order of an instance's partial sums, so results are the same alone and
  * batched under one schedule, not across schedules.
- * NULL restores groups = 1, cycles_per_graph = 2, fp32_stencil_rings = 4.
+ * NULL restores groups = 1, cycles_per_graph = 2, stencil_rings = 4.
  * PD_EINVAL outside [1, 8] / [1, 16] / {0, 4, 8}.                          */
 typedef struct {
   int32_t groups;
   int32_t cycles_per_graph;
-  int32_t fp32_stencil_rings;
+  int32_t stencil_rings;
 } pd_schedule;
 int pd_set_schedule(const pd_schedule *schedule);
 int pd_get_schedule(pd_schedule *schedule);

@@ -1,9 +1,8 @@
 """Autotuner of the launch schedule of a batch.
 
 A batch's best schedule (how many stream groups it is split into, how many
-Krylov cycles one captured graph holds) and stencil tile (rings per wave of
-its FP32 instances) depend on its instance sizes, precisions and
-convergence behaviour.  `tune` times the first levels of the
+Krylov cycles one captured graph holds) and stencil tile (rings per wave)
+depend on its instance sizes, precisions and convergence behaviour.  `tune` times the first levels of the
 batch's own solve under every candidate schedule, starting each time from
 the batch's current state (saved and restored, so tuning leaves no trace),
 then sets the fastest as the library's default and returns the table.
@@ -19,12 +18,13 @@ from . import polardisk as pdk
 
 # (stream groups, cycles per graph).  Longer rounds pay for their idle
 # cycles (an instance that converges waits for the next round head) by
-# running the round head, which costs about one cycle, less often.  4 and
-# 5 groups ran the ten-instance 256 x 512 batch 45-53% slower than 3, and
-# more hardware queues per process made them slower still: from the fourth
-# stream on the groups stop overlapping (same iterations, same results).
-DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((g, c) for g in (1, 2, 3) for c in (4, 8, 12))
-FP32_RINGS: Tuple[int, ...] = (4, 8)
+# running the round head, which costs about one cycle, less often; 6 and 7
+# fit warm levels of about six iterations.  4 and 5 groups ran the
+# ten-instance 256 x 512 batch 45-53% slower than 3, and more hardware
+# queues per process made them slower still: from the fourth stream on the
+# groups stop overlapping (same iterations, same results).
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((g, c) for g in (1, 2, 3) for c in (4, 6, 7, 8, 12))
+STENCIL_RINGS: Tuple[int, ...] = (4, 8)
 
 _cache: Dict[tuple, dict] = {}
 
@@ -42,9 +42,8 @@ def tune(insts: Sequence["pdk.Instance"], tds: Sequence["pdk.TimeDesc"], levels:
          candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 2,
          sync=None, use_cache: bool = True) -> dict:
     """Chooses and sets the fastest schedule for advancing `insts` through
-    `tds`; returns {"best": (groups, cycles_per_graph, fp32_stencil_rings),
-    "ms": {...}}.  The stencil depth is only varied when the batch holds
-    FP32 (mixed) instances.
+    `tds`; returns {"best": (groups, cycles_per_graph, stencil_rings),
+    "ms": {...}}.  Every candidate is timed under both stencil depths.
 
     sync: callable that waits for the device (e.g. torch.cuda.synchronize);
     the library's own calls already return after the work is done."""
@@ -55,8 +54,7 @@ def tune(insts: Sequence["pdk.Instance"], tds: Sequence["pdk.TimeDesc"], levels:
         return _cache[key]
     saved = [(i.solution(), i.time) for i in insts]
     short = [_first_levels(td, t, levels) for td, (_, t) in zip(tds, saved)]
-    any_fp32 = any(int(i.precision) == pdk.PD_MIXED for i in insts)
-    full = [(g, c, r) for g, c in candidates for r in (FP32_RINGS if any_fp32 else (4,))]
+    full = [(g, c, r) for g, c in candidates for r in STENCIL_RINGS]
     ms: Dict[Tuple[int, int, int], float] = {}
     try:
         for cand in full:

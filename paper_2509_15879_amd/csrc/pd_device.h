@@ -17,7 +17,7 @@
 #include <stdint.h>
 
 #define PD_MAXSRC 4
-#define PD_RB 4           // rings per stencil wave (one wave = 64 columns x rb rings; FP32 instances may take 2 PD_RB)
+#define PD_RB 4           // rings per stencil wave (one wave = 64 columns x rb rings; a schedule may ask for 2 PD_RB)
 #define PD_STEN_WAVES 4   // waves per stencil block, stacked over consecutive rings
 #ifndef PD_ELEM_PER_BLOCK
 #define PD_ELEM_PER_BLOCK 2048

@@ -554,11 +554,11 @@ void xcd_contiguous(std::vector<int2> &map) {
   map.swap(out);
 }
 
-// fp32_rings: stencil rings per wave of the plan's FP32 (mixed) instances
-// (PD_RB or 2 PD_RB); FP64 instances always take PD_RB.
-int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, int fp32_rings = PD_RB) {
+// stencil_rings: stencil rings per wave of the plan's instances (PD_RB or
+// 2 PD_RB, either precision).
+int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, int stencil_rings = PD_RB) {
   const int ninst = (int)insts.size();
-  auto rings = [&](const pd_instance *I) { return I->precision == PD_MIXED ? fp32_rings : PD_RB; };
+  auto rings = [&](const pd_instance *) { return stencil_rings; };
   P.L = pd::LaunchSet{};
   // host side first: the block maps, then one layout for everything
   constexpr int NMAP = 9;
@@ -706,7 +706,7 @@ hipStream_t helper_stream(int device, int k) {
 struct Schedule {
   int groups = 1;
   int cycles_per_graph = 2;
-  int fp32_rings = PD_RB;     // stencil rings per wave of FP32 instances
+  int stencil_rings = PD_RB;  // stencil rings per wave
 };
 
 std::atomic<int> g_sched_groups{1}, g_sched_cpg{2}, g_sched_rings{PD_RB};
@@ -715,7 +715,7 @@ Schedule default_schedule() {
   Schedule sc;
   sc.groups = g_sched_groups.load();
   sc.cycles_per_graph = g_sched_cpg.load();
-  sc.fp32_rings = g_sched_rings.load();
+  sc.stencil_rings = g_sched_rings.load();
   return sc;
 }
 
@@ -776,7 +776,7 @@ struct Engine {
     ninst = (int)insts.size();
     max_cycles = cycles_cap;
     cpg = std::max(1, sch.cycles_per_graph);
-    rings = sch.fp32_rings;
+    rings = sch.stencil_rings;
     const int ng = std::max(1, std::min(sch.groups, ninst));
     int device = 0;
     HIPCHK(hipGetDevice(&device));
@@ -1437,11 +1437,11 @@ int pd_set_schedule(const pd_schedule *sc) {
   if (sc->groups < 1 || sc->groups > 8) return fail(PD_EINVAL, "groups must be in [1, 8]");
   if (sc->cycles_per_graph < 1 || sc->cycles_per_graph > 16)
     return fail(PD_EINVAL, "cycles_per_graph must be in [1, 16]");
-  if (sc->fp32_stencil_rings != 0 && sc->fp32_stencil_rings != PD_RB && sc->fp32_stencil_rings != 2 * PD_RB)
-    return fail(PD_EINVAL, "fp32_stencil_rings must be 0, %d or %d", PD_RB, 2 * PD_RB);
+  if (sc->stencil_rings != 0 && sc->stencil_rings != PD_RB && sc->stencil_rings != 2 * PD_RB)
+    return fail(PD_EINVAL, "stencil_rings must be 0, %d or %d", PD_RB, 2 * PD_RB);
   g_sched_groups = sc->groups;
   g_sched_cpg = sc->cycles_per_graph;
-  g_sched_rings = sc->fp32_stencil_rings ? sc->fp32_stencil_rings : PD_RB;
+  g_sched_rings = sc->stencil_rings ? sc->stencil_rings : PD_RB;
   return PD_OK;
 }
 
@@ -1449,7 +1449,7 @@ int pd_get_schedule(pd_schedule *sc) {
   if (!sc) return fail(PD_EINVAL, "NULL argument");
   sc->groups = g_sched_groups.load();
   sc->cycles_per_graph = g_sched_cpg.load();
-  sc->fp32_stencil_rings = g_sched_rings.load();
+  sc->stencil_rings = g_sched_rings.load();
   return PD_OK;
 }
 

@@ -934,7 +934,7 @@ __global__ __launch_bounds__(256) void k_fact_ang(const PdInst *insts, const int
 // ------------------------------------------------------------ stencil march
 //
 // One wave owns 64 consecutive θ-columns and rb consecutive rings (PD_RB, or
-// twice that for FP32 instances when the launch schedule asks for it) and
+// twice that when the launch schedule asks for it) and
 // marches outward in r, keeping the radial neighbours and the shared radial
 // faces in registers and fetching the next ring (stencil operands and the
 // epilogue's own operands) while it computes the current one.  A block

@@ -471,13 +471,13 @@ class Batch:
 
 class Schedule(C.Structure):
     _fields_ = [("groups", C.c_int32), ("cycles_per_graph", C.c_int32),
-                ("fp32_stencil_rings", C.c_int32)]
+                ("stencil_rings", C.c_int32)]
 
 
-def set_schedule(groups=1, cycles_per_graph=2, fp32_stencil_rings=4):
+def set_schedule(groups=1, cycles_per_graph=2, stencil_rings=4):
     """Default launch schedule of later solves: stream groups, cycles per
-    graph, and the stencil tile depth (rings per wave) of FP32 instances."""
-    sc = Schedule(int(groups), int(cycles_per_graph), int(fp32_stencil_rings))
+    graph, and the stencil tile depth (rings per wave)."""
+    sc = Schedule(int(groups), int(cycles_per_graph), int(stencil_rings))
     _check(lib.pd_set_schedule(C.byref(sc)))
 
 
@@ -485,7 +485,7 @@ def get_schedule():
     sc = Schedule()
     _check(lib.pd_get_schedule(C.byref(sc)))
     return {"groups": sc.groups, "cycles_per_graph": sc.cycles_per_graph,
-            "fp32_stencil_rings": sc.fp32_stencil_rings}
+            "stencil_rings": sc.stencil_rings}
 
 
 def kernel_timing(enable: bool, reset: bool = False):

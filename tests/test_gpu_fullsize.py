@@ -43,7 +43,7 @@ def solve(precision, tol, K, schedule=(1, 8, 4)):
     try:
         st = inst.solve(pdk.time_desc(c["theta"], K, c["dt"] * K, pdk.TIME_UNIFORM, tol=tol, max_seconds=60.0))
     finally:
-        pdk.set_schedule(old["groups"], old["cycles_per_graph"], old["fp32_stencil_rings"])
+        pdk.set_schedule(old["groups"], old["cycles_per_graph"], old["stencil_rings"])
     x = inst.solution(pdk.LAYOUT_PAPER)
     inst.close()
     return x, float(np.mean([s["iters"] for s in st]))
