@@ -325,6 +325,69 @@ def paper_table_variant(pdk, stream):
                                                "stretch_2_13": round(dev[2], 4)}}
 
 
+def fig_sweeps_variant(pdk, stream):
+    """The seven parameter sweeps of Figs 2.9-2.11 (Ch. 2 example 1) and
+    Figs 3.5-3.8 (Ch. 3 example 1, printed stencil) at m = 19..99: all 250
+    runs as one uneven FP64 batch.  Wall time of the batched solve, the
+    swept value of the smallest error per figure and m, and the largest
+    relative deviation of the runs' errors from the oracle's stored sweep
+    table (m = 19, 39, 59)."""
+    import torch
+    from problems import paper_continuity_ex1, paper_parabolic_ex1, sample
+    from problems.manufactured import exact_at
+    from problems.workloads import FIG_EXAMPLES, FIG_SWEEPS, fig_sweep_runs
+    with open(os.path.join(ROOT, "tests", "golden", "fig_sweeps.json")) as f:
+        golden = json.load(f)["figures"]
+    pbs = {"ch2_ex1": paper_parabolic_ex1(), "ch3_ex1": paper_continuity_ex1()}
+    runs = fig_sweep_runs()
+    insts, tds, coords = [], [], []
+    for fig, m, n, prm in runs:
+        ex = FIG_EXAMPLES[FIG_SWEEPS[fig]["example"]]
+        md = pdk.mesh_desc(m, n, ex["r_kind"], prm["p"], ex["th_kind"], prm["q"])
+        c = pdk.mesh_coords(md)
+        flux = pdk.FLUX_LITERAL if ex["literal"] else pdk.FLUX_CENTRAL
+        insts.append(pdk.Instance(md, sample(pbs[FIG_SWEEPS[fig]["example"]], *c), pdk.PD_FP64, stream=stream,
+                                  flux=flux))
+        tds.append(pdk.time_desc(1.0 - prm["a"], ex["K"], ex["T"],
+                                 pdk.TIME_SINE if ex["t_kind"] else pdk.TIME_UNIFORM, prm["l"], tol=1e-13))
+        coords.append(c)
+    u0 = [i.solution() for i in insts]
+    pdk.solve_batch(insts, tds)                       # warm-up (plans, graphs)
+    for i, x in zip(insts, u0):
+        i.set_solution(x, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pdk.solve_batch(insts, tds)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    best, errs, dev = {}, {}, 0.0
+    for inst, (fig, m, n, prm), c in zip(insts, runs, coords):
+        ex = FIG_EXAMPLES[FIG_SWEEPS[fig]["example"]]
+        e0, eg = exact_at(pbs[FIG_SWEEPS[fig]["example"]], ex["T"], c[0], c[2])
+        d = np.abs(inst.solution() - pdk.ring_vector(e0, eg))
+        err = float(np.max(d)) if ex["error"] == "max" else float(np.mean(d[1:]))   # origin first
+        errs.setdefault((fig, m), []).append(err)
+        if str(m) in golden[fig]["m"]:
+            k = list(FIG_SWEEPS[fig]["values"]).index(prm[FIG_SWEEPS[fig]["vary"]])
+            dev = max(dev, abs(err / golden[fig]["m"][str(m)][ex["error"]][k] - 1))
+    for (fig, m), e in errs.items():
+        best.setdefault(fig, {})[str(m)] = FIG_SWEEPS[fig]["values"][int(np.argmin(e))]
+    cell_updates = sum(i.N * FIG_EXAMPLES[FIG_SWEEPS[r[0]]["example"]]["K"] for i, r in zip(insts, runs))
+    cells = sum(i.N for i in insts)
+    for i in insts:
+        i.close()
+    return {"workload": ("Figs 2.9-2.11 and 3.5-3.8 parameter sweeps: 250 runs, m 19..99, n floor(2 pi m), "
+                         "Ch. 2 example 1 (5 levels) and Ch. 3 example 1 with the printed stencil (10 levels), "
+                         "theta 0.5..1"),
+            "instances": len(runs), "cells": cells, "ms": round(1e3 * el, 2),
+            "value": round(cell_updates / el, 1),
+            "best_value_per_figure": {f: {"vary": FIG_SWEEPS[f]["vary"], "by_m": b} for f, b in best.items()},
+            "paper_states": {"fig_2_9": "p ~ 1.1", "fig_2_10": "p ~ 1.1", "fig_2_11": "a ~ 0.4 (dt 0.02)",
+                             "fig_3_5": "p ~ 0.1", "fig_3_6": "q ~ 1.9", "fig_3_7": "l ~ 1.5",
+                             "fig_3_8": "a ~ 0.5"},
+            "max_rel_error_deviation_vs_oracle_table": dev}
+
+
 def serving_variant(pdk, duration=8.0, check=6):
     """The serving loop under a Poisson request stream (200 requests/s for
     `duration` seconds, mixed precision): latency percentiles, aggregate
@@ -740,6 +803,8 @@ def main():
         var["adaptive_dt"] = adaptive_variant(pdk, stream, 4e-12)
         log("Table 2.1 runs batched ...")
         var["paper_table_2_1"] = paper_table_variant(pdk, stream)
+        log("figure sweeps (250 runs) ...")
+        var["fig_sweeps"] = fig_sweeps_variant(pdk, stream)
         log("uneven batch of 512 ...")
         var["uneven_512"] = uneven_variant(pdk, stream, 4e-12)
         log(f"serving stream ({args.serving_seconds:g} s) ...")

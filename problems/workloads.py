@@ -102,3 +102,51 @@ def cfg5_arrivals(duration, rate=None, seed=None):
         tol = float(c["tols"][int(rng.integers(0, 2))])
         T = float(np.exp(rng.uniform(np.log(c["T"][0]), np.log(c["T"][1]))))
         out.append((t, k, theta, tol, max(1, int(round(T / c["dt"])))))
+
+
+# Parameter sweeps of the paper's figures, each run of a sweep one instance
+# of an uneven batch; m = 19..99 rings with n = floor(2 pi m) (h = 1/(m+1)).
+#  Ch. 2 example 1 (Figs 2.9-2.11): stretch (2.4) in r, uniform θ, the
+#  θ-scheme with a = 1 - θ, Δt = 0.02 to T = 0.1 (five uniform levels);
+#  the maximum error over all unknowns at T.
+#  Ch. 3 example 1 (Figs 3.5-3.8): the printed stencil, stretch (2.4) in r
+#  with p and the angular stretch with q, ten levels of the time stretch
+#  with l to T = 0.1; the mean error over the ring unknowns at T.
+# `vary` names the swept parameter, `fixed` the others (p, q, l, a).
+FIG_SWEEP_M = (19, 39, 59, 79, 99)
+_P2 = (0.6, 0.8, 0.9, 1.0, 1.1, 1.2, 1.3, 1.5, 1.8)
+FIG_SWEEPS = {
+    "fig_2_9": dict(example="ch2_ex1", vary="p", values=_P2, fixed=dict(q=1.0, l=1.0, a=0.4)),
+    "fig_2_10": dict(example="ch2_ex1", vary="p", values=_P2, fixed=dict(q=1.0, l=1.0, a=0.5)),
+    "fig_2_11": dict(example="ch2_ex1", vary="a", values=(0.0, 0.1, 0.2, 0.3, 0.4, 0.45, 0.5),
+                     fixed=dict(p=1.1, q=1.0, l=1.0)),
+    "fig_3_5": dict(example="ch3_ex1", vary="p", values=(0.05, 0.1, 0.2, 0.4, 0.7, 1.0, 1.3),
+                    fixed=dict(q=1.0, l=1.0, a=0.5)),
+    "fig_3_6": dict(example="ch3_ex1", vary="q", values=(1.0, 1.3, 1.6, 1.9, 2.2, 2.5),
+                    fixed=dict(p=0.1, l=1.0, a=0.5)),
+    "fig_3_7": dict(example="ch3_ex1", vary="l", values=(1.0, 1.25, 1.5, 1.75, 2.0, 2.5),
+                    fixed=dict(p=0.1, q=1.9, a=0.5)),
+    "fig_3_8": dict(example="ch3_ex1", vary="a", values=(0.0, 0.1, 0.2, 0.3, 0.4, 0.5),
+                    fixed=dict(p=0.1, q=1.9, l=1.5)),
+}
+FIG_EXAMPLES = {
+    # radial kind, angular kind (1: stretched with q), time kind (1: stretched with l), levels, T
+    "ch2_ex1": dict(r_kind=1, th_kind=0, t_kind=0, K=5, T=0.1, error="max", literal=False),
+    "ch3_ex1": dict(r_kind=1, th_kind=1, t_kind=1, K=10, T=0.1, error="mean", literal=True),
+}
+
+
+def fig_sweep_runs(ms=FIG_SWEEP_M, figs=None):
+    """[(figure, m, n, params)] of the sweeps: every (figure, m, swept value),
+    params = dict(p, q, l, a) with the swept one set."""
+    runs = []
+    for fig, s in FIG_SWEEPS.items():
+        if figs is not None and fig not in figs:
+            continue
+        for m in ms:
+            n = int(np.floor(2 * np.pi * m))
+            for v in s["values"]:
+                prm = dict(s["fixed"])
+                prm[s["vary"]] = v
+                runs.append((fig, m, n, prm))
+    return runs

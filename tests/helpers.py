@@ -61,3 +61,31 @@ def hip_runtime():
     hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
     hip.hipFree.argtypes = [C.c_void_p]
     return hip
+
+
+def fig_problem(example):
+    from problems import paper_continuity_ex1, paper_parabolic_ex1
+    return paper_parabolic_ex1() if example == "ch2_ex1" else paper_continuity_ex1()
+
+
+def fig_errors(x, pb, T, r_nodes, th_nodes):
+    """(mean over the ring unknowns, max over all unknowns) of |x - exact| at
+    T; x in the paper's unknown order (2.12)."""
+    from oracle.operator import to_vec
+    from problems.manufactured import exact_at
+    e0, eg = exact_at(pb, T, r_nodes, th_nodes)
+    d = np.abs(x - to_vec(e0, eg))
+    return float(np.mean(d[1:])), float(np.max(d))
+
+
+def oracle_fig_run(fig, m, n, prm):
+    """One run of a figure's sweep with the oracle: its state at T (paper
+    order) and its errors (mean, max)."""
+    from problems.workloads import FIG_EXAMPLES, FIG_SWEEPS
+    ex = FIG_EXAMPLES[FIG_SWEEPS[fig]["example"]]
+    pb = fig_problem(FIG_SWEEPS[fig]["example"])
+    me = make_mesh(m, n, ex["r_kind"], prm["p"], ex["th_kind"], prm["q"])
+    data = sample(pb, *me.sample_points())
+    S = assemble_literal(me, data) if ex["literal"] else assemble(me, data)
+    x = solve(S, time_levels(ex["T"], ex["K"], ex["t_kind"], prm["l"]), 1.0 - prm["a"])
+    return x, fig_errors(x, pb, ex["T"], me.r, me.th)
