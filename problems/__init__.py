@@ -19,4 +19,5 @@ from .manufactured import (  # noqa: F401
     paper_continuity_ex1,
     random_positive,
     zero_flux_random,
+    two_carrier,
 )

@@ -404,3 +404,40 @@ def zero_flux_random(seed: int):
     pb.name = f"zero_flux{seed}"
     pb.modes = [TimeMode(0.0, 0, _const(0.0), _bc_const(0.0))]
     return pb
+
+
+def two_carrier(seed: int, eps: float = 0.5, doping: float = 1.0, zero_flux: bool = False):
+    """Electrons n, holes p and the electrostatic potential ψ on the unit
+    disk (the two continuity equations of §3.1 with the field of a Poisson
+    problem, in scaled units): (ψ problem, n problem, p problem).
+
+    * ψ: D = eps, no drift; mode 0 is the charge slot (g = 0, filled with
+      p - n by the coupling; Dirichlet ψ_b(θ) = 0.2 cos(θ + c)), mode 1 the
+      doping C(r, θ) = doping (1 - r²)(1 + ½ r cos(2θ + c')); λ = 0.
+    * n, p: seeded diffusivities D = d0 (1 + ¼ r² sin(kθ + c)), no drift of
+      their own (the coupling sets it from ψ); a steady generation
+      g(r, θ) = 0.3 (1 - r²) (λ = 0); Dirichlet data 1 (n) and 0.5 + 0.1 sin θ
+      (p), or zero flux with no generation; positive smooth initial data.
+    Draw order: c[0..5] ~ U[0, 2π), k ~ U{1..3}."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.0, 2 * np.pi, size=6)
+    k = int(rng.integers(1, 4))
+    zero = _const(0.0)
+    psi = Problem(
+        name=f"two_carrier_psi{seed}", pde=1,
+        modes=[TimeMode(0.0, 0, zero, lambda th: 0.2 * np.cos(th + c[0])),
+               TimeMode(0.0, 0, lambda r, th: doping * (1 - r * r) * (1 + 0.5 * r * np.cos(2 * th + c[1])),
+                        _bc_const(0.0))],
+        u0=zero, D=_const(eps))
+
+    def carrier(name, d0, nb, u0_amp, phase):
+        g = zero if zero_flux else (lambda r, th: 0.3 * (1 - r * r) + 0.0 * th)
+        return Problem(
+            name=f"two_carrier_{name}{seed}", pde=1,
+            modes=[TimeMode(0.0, 0, g, _bc_const(0.0) if zero_flux else nb)],
+            u0=lambda r, th: 1.0 + u0_amp * (1 - r * r) * (1 + 0.5 * r * np.cos(th + phase)),
+            D=lambda r, th: d0 * (1.0 + 0.25 * r * r * np.sin(k * th + phase)))
+
+    n_pb = carrier("n", 1.0, _bc_const(1.0), 0.5, c[2])
+    p_pb = carrier("p", 0.5, lambda th: 0.5 + 0.1 * np.sin(th), 0.3, c[3])
+    return psi, n_pb, p_pb
