@@ -388,6 +388,50 @@ def fig_sweeps_variant(pdk, stream):
             "max_rel_error_deviation_vs_oracle_table": dev}
 
 
+def gummel_variant(pdk, stream, m=256, n=512, K=20, dt=1e-3, theta=0.5):
+    """The coupled two-carrier system (electrons and holes through a polar
+    Poisson problem, Gummel's iteration to a relative potential change of
+    1e-10 per level) on a 256 x 512 graded mesh (p = 1.3), K levels of
+    Crank-Nicolson: wall time, Gummel and Krylov iterations per level, and
+    the zero-flux variant's conservation of each carrier."""
+    import torch
+    from problems import sample, two_carrier
+    out = {"workload": (f"two carriers + polar Poisson (Gummel), {m}x{n} graded p=1.3, {K} levels of "
+                        f"theta {theta}, dt {dt}, FP64")}
+    psi_pb, n_pb, p_pb = two_carrier(3200)
+    md = pdk.mesh_desc(m, n, pdk.MESH_SINE, 1.3)
+    coords = pdk.mesh_coords(md)
+    gd = [sample(pb, *coords) for pb in (psi_pb, n_pb, p_pb)]
+    psi = pdk.Instance(md, gd[0], pdk.PD_FP64, stream=stream)
+    car = [pdk.Instance(md, gd[k], pdk.PD_FP64, stream=stream) for k in (1, 2)]
+    for inst, d, sign in zip(car, gd[1:], (-1.0, 1.0)):
+        pdk.set_mobility(inst, d["D_r"], d["D_t"], sign)
+    pdk.gummel_step(psi, car[0], car[1], 0.0, dt, theta, tol=1e-12)     # warm-up (plans)
+    u = [ring_u0(d) for d in gd]
+    for i, x in zip([psi] + car, u):
+        i.set_solution(x, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [pdk.gummel_step(psi, car[0], car[1], k * dt, dt, theta, tol=1e-12, gummel_tol=1e-10, max_gummel=40)
+           for k in range(K)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = 3 * (m * n + 1)
+    out.update({"ms": round(1e3 * el, 1), "value": round(cells * K / el, 1),
+                "unit_note": "cell-updates/s counts the three fields per level",
+                "gummel_iters_per_level": round(float(np.mean([s["gummel_iters"] for s in sts])), 2),
+                "krylov_iters_per_level": round(float(np.mean([s["krylov_iters"] for s in sts])), 1),
+                "last_change": max(s["change"] for s in sts)})
+    for i in [psi] + car:
+        i.close()
+    return out
+
+
+def ring_u0(d):
+    from paper_2509_15879_amd import polardisk as pdk
+    return pdk.ring_vector(d["u0_origin"], d["u0_grid"])
+
+
 def serving_variant(pdk, duration=8.0, check=6):
     """The serving loop under a Poisson request stream (200 requests/s for
     `duration` seconds, mixed precision): latency percentiles, aggregate
@@ -805,6 +849,8 @@ def main():
         var["paper_table_2_1"] = paper_table_variant(pdk, stream)
         log("figure sweeps (250 runs) ...")
         var["fig_sweeps"] = fig_sweeps_variant(pdk, stream)
+        log("two carriers with Gummel coupling ...")
+        var["gummel_2carrier"] = gummel_variant(pdk, stream)
         log("uneven batch of 512 ...")
         var["uneven_512"] = uneven_variant(pdk, stream, 4e-12)
         log(f"serving stream ({args.serving_seconds:g} s) ...")

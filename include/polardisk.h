@@ -284,6 +284,53 @@ int pd_assemble_rhs(pd_instance *inst, double t_k, double dt, double theta, doub
 int pd_apply_preconditioner(pd_instance *inst, double dt, double theta, const double *y, double *z,
                             int32_t layout, int32_t device_ptrs);
 
+/* Two carriers coupled through their field.  §3.1 states the continuity
+ * equations of electrons n and holes p, each with the drift of a field,
+ * and then solves one of them, (3.1), with the field given.  These calls
+ * couple two carrier instances through a polar Poisson problem
+ * -∇·(ε∇ψ) = p - n + C, 𝓔 = -∇ψ, in scaled units, by Gummel's iteration.
+ * Each carrier is (3.1) with the drift velocity E = s μ 𝓔 (3.4), s = -1 for
+ * electrons and +1 for holes, on the conservative face-flux operator; the
+ * drift of a face comes from the potential's difference across it:
+ *   radial face (i+1/2, j):  E_r = s μ (ψ_{i,j} - ψ_{i+1,j}) / h_{i+1},
+ *   angular face (i, j+1/2): E_θ = s μ (ψ_{i,j} - ψ_{i,j+1}) / (r_i μ_{j+1}),
+ * ψ_{0,j} the origin value and ψ_{m+1,j} the potential's Dirichlet value.
+ *
+ * pd_set_mobility: makes `carrier` a carrier of charge sign `sign` (+1 or
+ * -1) with face mobilities mu_rface ((m+1) n values at (r_{i+1/2}, θ_j)) and
+ * mu_tface (m n values at (r_i, θ_{j+1/2})), the layout of D_rface and
+ * D_tface, host or device (device_ptrs).  The carrier must be an FP64
+ * instance with the central or upwind flux created without drift
+ * (Er_rface = Et_tface = 0 or NULL); its faces then hold the conductances,
+ * which it keeps.  Allocates a small device array (2 words per face), freed
+ * by pd_destroy.  PD_EINVAL otherwise.
+ *
+ * pd_gummel_step: one time level t_k -> t_k + dt of the coupled system.
+ * `psi` is the potential: an FP64 continuity instance on the same mesh with
+ * D = ε, no drift, Dirichlet data ψ_b, source mode 0 its charge slot (its g
+ * is overwritten with p - n) and any further modes the doping C; every mode
+ * steady (lambda = tpow = 0).  From the carriers' states (n^k, p^k), repeat:
+ * ψ <- the steady solve of the potential (a θ = 1 level of length 1e30
+ * from its last state) with the charge p - n; the carriers' faces from ψ;
+ * (n, p) <- one θ-level t_k -> t_k + dt from (n^k, p^k); until the relative
+ * max-norm change of ψ between iterations is at most gummel_tol (checked
+ * from the second iteration on) or max_gummel iterations.  tol is the
+ * per-solve scaled-residual tolerance.  On return the carriers hold
+ * n^{k+1}, p^{k+1} at t_k + dt and psi the last potential; stats (or NULL)
+ * gets the Gummel and Krylov iteration counts and the last change.  The
+ * carriers must share one stream; no other call may use the three
+ * instances during the call.  PD_EINVAL for mismatched meshes or settings,
+ * the solve's codes otherwise.                                            */
+typedef struct {
+  int32_t gummel_iters;   /* Gummel iterations taken */
+  int32_t krylov_iters;   /* Krylov iterations over all solves of the step */
+  double change;          /* last relative max-norm change of ψ */
+} pd_gummel_stats;
+int pd_set_mobility(pd_instance *carrier, const double *mu_rface, const double *mu_tface, double sign,
+                    int32_t device_ptrs);
+int pd_gummel_step(pd_instance *psi, pd_instance *n_carrier, pd_instance *p_carrier, double t_k, double dt,
+                   double theta, double tol, double gummel_tol, int32_t max_gummel, pd_gummel_stats *stats);
+
 /* Device bytes an instance of this mesh and precision occupies. */
 int pd_footprint(const pd_mesh_desc *mesh, int32_t nsrc, int32_t precision, size_t *bytes);
 

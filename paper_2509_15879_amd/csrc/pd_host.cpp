@@ -211,6 +211,13 @@ struct pd_instance {
   double t = 0.0;            // current time
   bool have_prev = false;
   std::atomic<int> busy{0};
+  // carrier of a coupled system (pd_set_mobility): created without drift,
+  // its faces then take the drift of a potential
+  bool zero_drift = false;    // no drift at creation: gp = gm = G on every face
+  std::vector<double> lam_h;  // host copies of the source exponents and powers
+  std::vector<int> tp_h;
+  double b0 = 0.0;            // reaction at the origin (the origin diagonal l0)
+  double *drift = nullptr;    // device: G_r, c_r ((m+1) n each), G_t, c_t (m n each)
 };
 
 namespace {
@@ -1056,8 +1063,10 @@ struct BusyGuard {
       v.push_back(I);
     }
   }
-  ~BusyGuard() {
+  ~BusyGuard() { release(); }
+  void release() {
     for (auto *I : v) I->busy = 0;
+    v.clear();
   }
 };
 
@@ -1209,6 +1218,8 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
   else Dt.assign((size_t)m * n, 1.0);
   if (pb->Et_tface) { if ((rc = fetch(pb->Et_tface, (size_t)m * n, dp, Et))) return rc; }
   else Et.assign((size_t)m * n, 0.0);
+  I->zero_drift = std::all_of(Er.begin(), Er.end(), [](double v) { return v == 0.0; }) &&
+                  std::all_of(Et.begin(), Et.end(), [](double v) { return v == 0.0; });
   if ((rc = fetch(pb->u0, N, dp, u0))) return rc;
   if (pb->nsrc > 0) {
     if (!pb->lambda) return fail(PD_EINVAL, "lambda is NULL");
@@ -1230,6 +1241,8 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
       X.tp[q] = tp[q];
       if (X.tp[q] < 0 || X.tp[q] > 8) return fail(PD_EINVAL, "tpow must be in [0, 8]");
     }
+    I->lam_h.assign(X.lam, X.lam + pb->nsrc);
+    I->tp_h.assign(X.tp, X.tp + pb->nsrc);
   }
   X.has_b = pb->b_node != nullptr;
   if (X.has_b && (rc = fetch(pb->b_node, N, dp, bn))) return rc;
@@ -1302,6 +1315,7 @@ int prepare_instance(const pd_mesh_desc *mesh, const pd_problem_desc *pb, int32_
     for (int j = 0; j < n; ++j) s0 += X.gpr[j];
     const double b0 = X.has_b ? X.b_int[m * n] : 0.0;
     I->H.l0 = std::fma(I->H.inv_V0, s0, b0);
+    I->b0 = b0;
   }
   {
     // ring sums of the ring-mean (Galerkin) correction: with P the
@@ -1535,6 +1549,7 @@ int pd_destroy(pd_instance *I) {
   if (!I) return PD_OK;
   if (I->busy) return fail(PD_EBUSY, "instance is in use");
   if (I->stream) (void)hipStreamSynchronize(I->stream);
+  if (I->drift) (void)hipFree(I->drift);
   if (!I->arena) {          // a serving arena takes its chunk back itself
     if (I->dmem) (void)hipFree(I->dmem);
     if (I->t_table) (void)hipFree(I->t_table);
@@ -1721,6 +1736,160 @@ int pd_assemble_rhs(pd_instance *I, double t_k, double dt, double theta, double 
     HIPCHK(hipMemcpy(rhs, o.data(), N * 8, hipMemcpyHostToDevice));
   } else {
     std::memcpy(rhs, o.data(), N * 8);
+  }
+  return PD_OK;
+}
+
+// ------------------------------------------------------------ two carriers
+
+int pd_set_mobility(pd_instance *I, const double *mu_rface, const double *mu_tface, double sign,
+                    int32_t device_ptrs) {
+  if (!I || !mu_rface || !mu_tface) return fail(PD_EINVAL, "NULL argument");
+  if (I->precision != PD_FP64) return fail(PD_EINVAL, "a carrier of the coupled system must be an FP64 instance");
+  if (I->flux != 0 && I->flux != 1) return fail(PD_EINVAL, "a carrier takes the central or upwind flux (0 or 1)");
+  if (!I->zero_drift) return fail(PD_EINVAL, "a carrier must be created without drift (Er_rface = Et_tface = 0)");
+  if (sign != 1.0 && sign != -1.0) return fail(PD_EINVAL, "sign must be +1 (holes) or -1 (electrons)");
+  BusyGuard g({I});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  const MeshH &M = I->M;
+  const int m = M.m, n = M.n;
+  const size_t nr = (size_t)(m + 1) * n, nt = (size_t)m * n;
+  std::vector<double> mr, mt;
+  int rc = fetch(mu_rface, nr, device_ptrs, mr);
+  if (rc || (rc = fetch(mu_tface, nt, device_ptrs, mt))) return rc;
+  for (double v : mr) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "mu_rface must be finite and >= 0");
+  for (double v : mt) if (!std::isfinite(v) || v < 0) return fail(PD_EINVAL, "mu_tface must be finite and >= 0");
+  // c = s μ (face length) / (node distance), so that the face's drift
+  // coefficient is K = c (ψ_P - ψ_Q); the outer faces of a zero-flux
+  // carrier carry nothing
+  std::vector<double> c(nr + nt);
+  for (int i = 0; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t k = (size_t)i * n + j;
+      c[k] = (i == m && I->bc == 1) ? 0.0 : sign * mr[k] * (M.rh[i] * M.dth[j]) / M.h[i + 1];
+    }
+  for (int i = 1; i <= m; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t k = (size_t)(i - 1) * n + j;
+      c[nr + k] = sign * mt[k] * M.w[i] / (M.r[i] * M.mu[j + 1]);
+    }
+  if (!I->drift) HIPCHK(hipMalloc(&I->drift, 2 * (nr + nt) * sizeof(double)));
+  double *G_r = I->drift, *c_r = G_r + nr, *G_t = c_r + nr, *c_t = G_t + nt;
+  // created without drift, the faces hold the conductances: gp = gm = G
+  HIPCHK(hipMemcpy(G_r, I->H.k64.gp_r, nr * sizeof(double), hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(G_t, I->H.k64.gp_t, nt * sizeof(double), hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(c_r, c.data(), nr * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c_t, c.data() + nr, nt * sizeof(double), hipMemcpyHostToDevice));
+  return PD_OK;
+}
+
+namespace {
+constexpr double kSteadyDt = 1e30;   // a level this long is the steady problem (θ = 1)
+
+bool same_mesh(const pd_instance *a, const pd_instance *b) {
+  return a->M.m == b->M.m && a->M.n == b->M.n && a->M.r == b->M.r && a->M.th == b->M.th;
+}
+
+// The carrier's faces from the potential's state, then its ring sums and
+// origin diagonal (read back into the descriptor the next plans copy).
+int drift_from(pd_instance *C, pd_instance *P, double *l0_dev) {
+  const int m = C->M.m, n = C->M.n;
+  const size_t nr = (size_t)(m + 1) * n, nt = (size_t)m * n;
+  const double *G_r = C->drift, *c_r = G_r + nr, *G_t = c_r + nr, *c_t = G_t + nt;
+  PdInst &H = C->H;
+  pd::launch_drift(m, n, C->flux, G_r, c_r, G_t, c_t, P->H.sol[sol_slot(P->rot, 0)], P->H.nb, P->H.lam, P->H.tpow,
+                   P->nsrc, const_cast<double *>(H.k64.gp_r), const_cast<double *>(H.k64.gm_r),
+                   const_cast<double *>(H.k64.gp_t), const_cast<double *>(H.k64.gm_t), const_cast<double *>(H.crs),
+                   H.inv_V0, C->b0, l0_dev, C->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(&H.l0, l0_dev, sizeof(double), hipMemcpyDeviceToHost, C->stream));
+  HIPCHK(hipStreamSynchronize(C->stream));
+  return PD_OK;
+}
+}  // namespace
+
+int pd_gummel_step(pd_instance *psi, pd_instance *ne, pd_instance *pe, double t_k, double dt, double theta,
+                   double tol, double gummel_tol, int32_t max_gummel, pd_gummel_stats *stats) {
+  if (!psi || !ne || !pe) return fail(PD_EINVAL, "instance is NULL");
+  if (psi == ne || psi == pe || ne == pe) return fail(PD_EINVAL, "the potential and the carriers must be three instances");
+  if (!(dt > 0.0)) return fail(PD_EINVAL, "dt must be > 0");
+  int rc = validate_theta(theta);
+  if (rc) return rc;
+  if (max_gummel < 1 || !(gummel_tol >= 0.0)) return fail(PD_EINVAL, "max_gummel must be >= 1 and gummel_tol >= 0");
+  if (psi->precision != PD_FP64) return fail(PD_EINVAL, "the potential must be an FP64 instance");
+  if (!ne->drift || !pe->drift) return fail(PD_EINVAL, "pd_set_mobility has not been called for both carriers");
+  if (!same_mesh(psi, ne) || !same_mesh(psi, pe)) return fail(PD_EINVAL, "the three instances must share one mesh");
+  if (psi->bc != 0) return fail(PD_EINVAL, "the potential takes Dirichlet data");
+  if (psi->nsrc < 1) return fail(PD_EINVAL, "the potential needs its charge slot (source mode 0)");
+  for (int q = 0; q < psi->nsrc; ++q)
+    if (psi->lam_h[q] != 0.0 || psi->tp_h[q] != 0)
+      return fail(PD_EINVAL, "the potential's sources and boundary data must be steady (lambda = 0, tpow = 0)");
+  if (ne->stream != pe->stream) return fail(PD_EINVAL, "the two carriers must share one stream");
+  for (const pd_instance *C : {ne, pe})
+    if (std::fabs(C->t - t_k) > 1e-12 * std::max(1.0, std::fabs(t_k)))
+      return fail(PD_EINVAL, "the step starts at %g but a carrier is at t = %g", t_k, C->t);
+  BusyGuard g({psi, ne, pe});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  const int np = psi->T.npad;
+  const int nblk = std::max(1, std::min(1024, (np + 2047) / 2048));
+  double *tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, (3 * (size_t)np + 2 * nblk + 4) * sizeof(double)));
+  struct Free { double *p; ~Free() { if (p) (void)hipFree(p); } } fr{tmp};
+  double *n0 = tmp, *p0 = n0 + np, *prev = p0 + np, *part = prev + np, *out = part + 2 * nblk, *l0 = out + 2;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(n0, ne->H.sol[sol_slot(ne->rot, 0)], np * sizeof(double), hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(p0, pe->H.sol[sol_slot(pe->rot, 0)], np * sizeof(double), hipMemcpyDeviceToDevice));
+  double tab_c[2] = {t_k, t_k + dt}, tab_p[2] = {0.0, kSteadyDt};
+  pd_time_desc tdc{}, tdp{};
+  tdc.t_kind = tdp.t_kind = PD_TIME_TABLE;
+  tdc.K = tdp.K = 1;
+  tdc.t_table = tab_c;
+  tdp.t_table = tab_p;
+  tdc.theta = theta;
+  tdp.theta = 1.0;
+  tdc.tol = tdp.tol = tol;
+  int it = 0, krylov = 0;
+  double change = 0.0;
+  g.release();   // each solve below takes the instances itself
+  for (; it < max_gummel; ++it) {
+    // ψ from the charge p - n (the potential's source mode 0)
+    double *charge = const_cast<double *>(psi->H.g);
+    pd::launch_sub(pe->H.sol[sol_slot(pe->rot, 0)], ne->H.sol[sol_slot(ne->rot, 0)], charge, np, psi->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(prev, psi->H.sol[sol_slot(psi->rot, 0)], np * sizeof(double), hipMemcpyDeviceToDevice,
+                          psi->stream));
+    HIPCHK(hipStreamSynchronize(psi->stream));
+    psi->t = 0.0;     // every steady solve is the level [0, kSteadyDt] from the last potential
+    std::vector<std::vector<double>> st(1);
+    if ((rc = solve_many({psi}, {&tdp}, &st))) return rc;
+    krylov += (int)st[0][0];
+    pd::launch_maxdiff(psi->H.sol[sol_slot(psi->rot, 0)], prev, np, part, nblk, out, psi->stream);
+    HIPCHK(hipGetLastError());
+    double hd[2];
+    HIPCHK(hipMemcpyAsync(hd, out, sizeof hd, hipMemcpyDeviceToHost, psi->stream));
+    HIPCHK(hipStreamSynchronize(psi->stream));
+    change = hd[1] > 0.0 ? hd[0] / hd[1] : hd[0];
+    // the carriers' drift from ψ, then their level from the level's start
+    for (pd_instance *C : {ne, pe}) {
+      if ((rc = drift_from(C, psi, l0))) return rc;
+      HIPCHK(hipMemcpy(C->H.sol[sol_slot(C->rot, 0)], C == ne ? n0 : p0, np * sizeof(double),
+                       hipMemcpyDeviceToDevice));
+      C->t = t_k;
+      C->have_prev = false;
+    }
+    std::vector<std::vector<double>> sc(2);
+    if ((rc = solve_many({ne, pe}, {&tdc, &tdc}, &sc))) return rc;
+    krylov += (int)sc[0][0] + (int)sc[1][0];
+    if (it >= 1 && change <= gummel_tol) {
+      ++it;
+      break;
+    }
+  }
+  psi->t = 0.0;
+  if (stats) {
+    stats->gummel_iters = it;
+    stats->krylov_iters = krylov;
+    stats->change = change;
   }
   return PD_OK;
 }

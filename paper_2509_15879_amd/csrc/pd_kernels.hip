@@ -3103,6 +3103,164 @@ void launch_begin_origin(const LaunchSet &L, hipStream_t s) {
   go(KF_BEGIN, k_begin_origin, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
 }
 
+// ------------------------------------------------------------ two carriers
+//
+// A carrier of the coupled system (electrons or holes, (3.1) with the drift
+// velocity s μ 𝓔 of §3.1's continuity equations, 𝓔 = -∇ψ) takes the drift
+// of a potential ψ computed on the same mesh.  Per face, from the inner (or
+// lower-θ) node P to the outer (or higher-θ) node Q,
+//   K = c (ψ_P - ψ_Q),  c = s μ (face length) / (distance of P and Q),
+// c and the conductance G kept from the set-up, and the face pair formed
+// as at creation: central gp = G + K/2, gm = G - K/2, or upwind.  ψ_Q of the
+// outer faces is the potential's Dirichlet value; P of the faces i = 1/2 is
+// the origin.  One thread per face, radial faces first.
+__global__ __launch_bounds__(256) void k_drift(int m, int n, int flux, const double *__restrict__ G_r,
+                                               const double *__restrict__ c_r, const double *__restrict__ G_t,
+                                               const double *__restrict__ c_t, const double *__restrict__ psi,
+                                               const double *__restrict__ nb, const double *__restrict__ lam,
+                                               const int *__restrict__ tpow, int nsrc,
+                                               double *__restrict__ gp_r, double *__restrict__ gm_r,
+                                               double *__restrict__ gp_t, double *__restrict__ gm_t) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int nr = (m + 1) * n, nt = m * n;
+  double G, K;
+  double *gp, *gm;
+  if (k < nr) {
+    const int i = k / n, j = k - i * n;
+    const double pp = i == 0 ? psi[m * n] : psi[(i - 1) * n + j];
+    const double pq = i == m ? boundary_value(nb, lam, tpow, nsrc, n, j, 0.0) : psi[i * n + j];
+    G = G_r[k];
+    K = c_r[k] * (pp - pq);
+    gp = gp_r + k;
+    gm = gm_r + k;
+  } else if (k < nr + nt) {
+    const int f = k - nr, i1 = f / n, j = f - i1 * n;   // ring i1 + 1
+    const int jq = j + 1 == n ? 0 : j + 1;
+    G = G_t[f];
+    K = c_t[f] * (psi[i1 * n + j] - psi[i1 * n + jq]);
+    gp = gp_t + f;
+    gm = gm_t + f;
+  } else {
+    return;
+  }
+  if (flux == 0) {
+    *gp = G + 0.5 * K;
+    *gm = G - 0.5 * K;
+  } else {
+    *gp = G + fmax(K, 0.0);
+    *gm = G - fmin(K, 0.0);
+  }
+}
+
+// The face sums of the ring-mean correction that depend on the radial faces
+// (PdInst::crs rows 2-5) after a drift update, one wave per ring i = 0..m
+// (a fixed lane-strided order and butterfly), and the origin's diagonal of
+// L, inv_V0 Σ_j gp_r(1/2, j) + b_0, into *l0.
+__global__ __launch_bounds__(256) void k_drift_rings(int m, int n, const double *__restrict__ gp_r,
+                                                     const double *__restrict__ gm_r, double *__restrict__ crs,
+                                                     double inv_V0, double b0, double *__restrict__ l0) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i > m) return;                                   // the whole wave
+  const int lane = threadIdx.x & 63, M1 = m + 1;
+  double sO = 0.0, sU = 0.0, sI = 0.0, sL = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    sO += gp_r[(size_t)i * n + j];
+    if (i < m) sU += gm_r[(size_t)i * n + j];
+    if (i >= 1) {
+      sI += gm_r[(size_t)(i - 1) * n + j];
+      sL += gp_r[(size_t)(i - 1) * n + j];
+    }
+  }
+  sO = wave_sum(sO);
+  sU = wave_sum(sU);
+  sI = wave_sum(sI);
+  sL = wave_sum(sL);
+  if (lane == 0) {
+    crs[2 * M1 + i] = sO;
+    crs[3 * M1 + i] = sI;
+    crs[4 * M1 + i] = sU;
+    crs[5 * M1 + i] = sL;
+    if (i == 0) *l0 = fma(inv_V0, sO, b0);
+  }
+}
+
+// out = a - b over N values (the coupled system's charge p - n).
+__global__ __launch_bounds__(256) void k_sub(const double *__restrict__ a, const double *__restrict__ b,
+                                             double *__restrict__ out, int N) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < N) out[k] = a[k] - b[k];
+}
+
+// max |a - b| and max |a| over N values: per-block maxima, then one block
+// takes the maxima of those (out[0], out[1]).
+__global__ __launch_bounds__(256) void k_maxdiff(const double *__restrict__ a, const double *__restrict__ b,
+                                                 int N, double *__restrict__ part) {
+  __shared__ double sd[4], sa[4];
+  double d = 0.0, x = 0.0;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < N; k += gridDim.x * 256) {
+    d = fmax(d, fabs(a[k] - b[k]));
+    x = fmax(x, fabs(a[k]));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d = fmax(d, __shfl_xor(d, o, 64));
+    x = fmax(x, __shfl_xor(x, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sd[threadIdx.x >> 6] = d;
+    sa[threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+    part[2 * blockIdx.x + 1] = fmax(fmax(sa[0], sa[1]), fmax(sa[2], sa[3]));
+  }
+}
+__global__ __launch_bounds__(256) void k_maxdiff_final(const double *__restrict__ part, int nblk,
+                                                       double *__restrict__ out) {
+  __shared__ double sd[4], sa[4];
+  double d = 0.0, x = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += 256) {
+    d = fmax(d, part[2 * k]);
+    x = fmax(x, part[2 * k + 1]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d = fmax(d, __shfl_xor(d, o, 64));
+    x = fmax(x, __shfl_xor(x, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sd[threadIdx.x >> 6] = d;
+    sa[threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+    out[1] = fmax(fmax(sa[0], sa[1]), fmax(sa[2], sa[3]));
+  }
+}
+
+void launch_drift(int m, int n, int flux, const double *G_r, const double *c_r, const double *G_t,
+                  const double *c_t, const double *psi, const double *nb, const double *lam, const int *tpow,
+                  int nsrc, double *gp_r, double *gm_r, double *gp_t, double *gm_t, double *crs, double inv_V0,
+                  double b0, double *l0, hipStream_t s) {
+  const int faces = (2 * m + 1) * n;
+  go(KF_CONTROL, k_drift, dim3((faces + 255) / 256), dim3(256), s, m, n, flux, G_r, c_r, G_t, c_t, psi, nb,
+     lam, tpow, nsrc, gp_r, gm_r, gp_t, gm_t);
+  go(KF_CONTROL, k_drift_rings, dim3((m + 1 + 3) / 4), dim3(256), s, m, n, (const double *)gp_r,
+     (const double *)gm_r, crs, inv_V0, b0, l0);
+}
+
+void launch_sub(const double *a, const double *b, double *out, int N, hipStream_t s) {
+  go(KF_CONTROL, k_sub, dim3((N + 255) / 256), dim3(256), s, a, b, out, N);
+}
+
+void launch_maxdiff(const double *a, const double *b, int N, double *part, int nblk, double *out,
+                    hipStream_t s) {
+  go(KF_CONTROL, k_maxdiff, dim3(nblk), dim3(256), s, a, b, N, part);
+  go(KF_CONTROL, k_maxdiff_final, dim3(1), dim3(256), s, (const double *)part, nblk, out);
+}
+
 void launch_indicator(const double *x, int m, int n, const double *r, const double *th,
                       const double *nb, const double *lam, const int *tpow, int nsrc, double t,
                       int dirichlet, double *ring_out, double *eta_out, hipStream_t s) {

@@ -63,6 +63,16 @@ void launch_cycle(const LaunchSet &L, hipStream_t s);
 void launch_precond_apply(const LaunchSet &L, int fp32, hipStream_t s);
 void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void *y, int fp32,
                   hipStream_t s);
+// Coupled carriers: drift faces from a potential (and the ring sums and
+// origin diagonal that depend on them), a difference of two vectors, and
+// max |a - b|, max |a| (out[0], out[1]; part: 2 nblk doubles).
+void launch_drift(int m, int n, int flux, const double *G_r, const double *c_r, const double *G_t,
+                  const double *c_t, const double *psi, const double *nb, const double *lam, const int *tpow,
+                  int nsrc, double *gp_r, double *gm_r, double *gp_t, double *gm_t, double *crs, double inv_V0,
+                  double b0, double *l0, hipStream_t s);
+void launch_sub(const double *a, const double *b, double *out, int N, hipStream_t s);
+void launch_maxdiff(const double *a, const double *b, int N, double *part, int nblk, double *out,
+                    hipStream_t s);
 void launch_indicator(const double *x, int m, int n, const double *r, const double *th,
                       const double *nb, const double *lam, const int *tpow, int nsrc, double t,
                       int dirichlet, double *ring_out, double *eta_out, hipStream_t s);

@@ -86,6 +86,10 @@ class BatchInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class GummelStats(C.Structure):
+    _fields_ = [("gummel_iters", C.c_int32), ("krylov_iters", C.c_int32), ("change", C.c_double)]
+
+
 class Indicator(C.Structure):
     _fields_ = [("eta_max", C.c_double), ("eta_sum", C.c_double), ("i_max", C.c_int32),
                 ("j_max", C.c_int32), ("p_best", C.c_double), ("pred_best", C.c_double),
@@ -98,7 +102,7 @@ class Indicator(C.Structure):
 # every entry point declared in include/polardisk.h
 EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
-           "pd_apply_preconditioner",
+           "pd_apply_preconditioner", "pd_set_mobility", "pd_gummel_step",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
            "pd_batch_stats", "pd_error_indicator", "pd_error_indicator_noalloc", "pd_remesh_transfer", "pd_set_schedule",
            "pd_get_schedule", "pd_get_time",
@@ -126,6 +130,8 @@ def _load():
         "pd_apply_operator": [P, D, D, P, P, I32, I32, I32],
         "pd_assemble_rhs": [P, D, D, D, P, I32, I32],
         "pd_apply_preconditioner": [P, D, D, P, P, I32, I32],
+        "pd_set_mobility": [P, P, P, D, I32],
+        "pd_gummel_step": [P, P, P, D, D, D, D, D, I32, C.POINTER(GummelStats)],
         "pd_footprint": [C.POINTER(MeshDesc), I32, I32, C.POINTER(SZ)],
         "pd_destroy": [P],
         "pd_batch_create": [SZ, I32, P, C.POINTER(P)],
@@ -467,6 +473,25 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def set_mobility(carrier: "Instance", mu_rface, mu_tface, sign: float):
+    """Makes `carrier` (FP64, created without drift) a carrier of the coupled
+    system with charge sign +1 (holes) or -1 (electrons) and face
+    mobilities mu_rface ((m+1, n)) and mu_tface ((m, n))."""
+    mr = _f64(np.asarray(mu_rface).reshape(carrier.m + 1, carrier.n))
+    mt = _f64(np.asarray(mu_tface).reshape(carrier.m, carrier.n))
+    _check(lib.pd_set_mobility(carrier.h, _ptr(mr), _ptr(mt), float(sign), 0))
+
+
+def gummel_step(psi: "Instance", n_carrier: "Instance", p_carrier: "Instance", t, dt, theta, tol=1e-12,
+                gummel_tol=1e-10, max_gummel=30):
+    """One time level of the coupled system (potential, electrons, holes) by
+    Gummel's iteration; returns its statistics."""
+    st = GummelStats()
+    _check(lib.pd_gummel_step(psi.h, n_carrier.h, p_carrier.h, float(t), float(dt), float(theta), float(tol),
+                              float(gummel_tol), int(max_gummel), C.byref(st)))
+    return {"gummel_iters": st.gummel_iters, "krylov_iters": st.krylov_iters, "change": st.change}
 
 
 class Schedule(C.Structure):
