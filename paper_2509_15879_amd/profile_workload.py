@@ -27,6 +27,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--workload", choices=["cfg3", "cfg2"], default="cfg3")
     ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--schedule", default=None,
+                    help="groups,cycles_per_graph,stencil_rings of the run (e.g. the one bench.py tuned)")
     args = ap.parse_args()
     os.environ["PD_NO_GRAPH"] = "1"
 
@@ -37,6 +39,8 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
+    if args.schedule:
+        pdk.set_schedule(*(int(v) for v in args.schedule.split(",")))
     prec = pdk.PD_MIXED if args.precision == "mixed" else pdk.PD_FP64
     insts, descs = [], []
     if args.workload == "cfg2":
@@ -48,7 +52,7 @@ def main():
             descs.append(pdk.time_desc(th, c["K"], c["T"], pdk.TIME_SINE, c["l"], tol=tol))
     else:
         c = CFG3
-        tol = args.tol or 1e-12
+        tol = args.tol or 3e-12
         md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
         insts.append(pdk.Instance(md, sample(cfg3_problem(), *pdk.mesh_coords(md)), prec, stream=stream))
         descs.append(pdk.time_desc(c["theta"], c["K"], c["dt"] * c["K"], pdk.TIME_UNIFORM, tol=tol))
