@@ -16,6 +16,13 @@ What it computes (Ch. 2 §2.1 and Ch. 3 §3.1-§3.2 of the paper):
   (I/Δt + θ L_h) n^{k+1} = (I/Δt - (1-θ) L_h) n^k + sources + boundary terms
   with a sparse direct LU (SciPy SuperLU), θ = 1 - a.
 
+The GPU library's own solver parts are stated plainly beside them: the
+alternating-line preconditioner (precond.py), the θ-semi-coarsening multigrid
+built on it (multigrid.py; the paper's §4.2 names multigrid-type
+preconditioners for large grids), the a-posteriori step control
+(timectl.py), the error indicator (adapt.py) and the coupled two-carrier
+system (gummel.py).
+
 Unknowns are kept in the paper's ordering (2.12): the origin first, then
 radial line j = 0..n-1, each listing rings i = 1..m.
 

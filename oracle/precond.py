@@ -49,11 +49,21 @@ class LinePreconditioner:
     """z = M^{-1} y for the step system of `sys` at (dt, theta)."""
 
     def __init__(self, sys: OracleSystem, dt: float, theta: float):
-        A = system_matrix(sys, dt, theta)
+        self._build(system_matrix(sys, dt, theta), sys.mesh.m)
+
+    @classmethod
+    def of_matrix(cls, A, m: int):
+        """The same preconditioner for any matrix A of m rings in the paper's
+        ordering (the origin, then θ-line after θ-line)."""
+        P = cls.__new__(cls)
+        P._build(A, m)
+        return P
+
+    def _build(self, A, m: int):
         self.A = A
         self.d = A.diagonal()
         Dinv = sp.diags(1.0 / self.d)
-        R, T = coupling_split(A, sys.mesh.m)
+        R, T = coupling_split(A, m)
         N = A.shape[0]
         I = sp.identity(N, format="csc")
         self._radial = spla.splu((I + Dinv @ R).tocsc())
