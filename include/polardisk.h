@@ -280,7 +280,9 @@ int pd_assemble_rhs(pd_instance *inst, double t_k, double dt, double theta, doub
  * FP64 and stored in FP32, and a mixed-precision instance applies M in FP32,
  * so z agrees with the exact M^{-1} y to about FP32 rounding.  y, z: N
  * values in `layout`, host or device (device_ptrs).  The instance's state
- * and time are not changed.                                               */
+ * and time are not changed.  With the multigrid preconditioner
+ * (pd_set_preconditioner) z is its V-cycle instead, whose first step is
+ * this M^{-1} y.                                                          */
 int pd_apply_preconditioner(pd_instance *inst, double dt, double theta, const double *y, double *z,
                             int32_t layout, int32_t device_ptrs);
 
@@ -453,6 +455,32 @@ int pd_batch_poll(pd_batch *batch, uint64_t ticket, double *out, pd_request_summ
 int pd_batch_stats(pd_batch *batch, pd_batch_info *info);
 int pd_batch_destroy(pd_batch *batch);
 
+/* Preconditioner of an instance's later solves.  The paper solves every
+ * level's system (2.11)/(2.12) directly and names multigrid-type
+ * preconditioners as the way to large grids (§4.2, outlook); the library's
+ * Krylov solver offers two:
+ *   PD_PRECOND_LINE (default): M above, the alternating line sweeps;
+ *   PD_PRECOND_MG: a θ-semi-coarsening multigrid V-cycle built on them.
+ *     Level l+1 merges the θ-lines of level l in pairs (the last three when
+ *     n_l is odd) while n_l >= 16, by the Galerkin product of the
+ *     volume-weighted system (radial faces add, the angular face inside a
+ *     merged cell drops out, volumes add); the ring means (one value per
+ *     ring and the origin) lie below the last level and are solved directly.
+ *     Every level smooths with one step of its own line sweeps before and
+ *     after its coarse correction.  It costs about three line-preconditioned
+ *     iterations per iteration and pays where iterations are many: cold
+ *     starts, large steps, steady problems (the potential of
+ *     pd_gummel_step is solved with it when its instance has it).
+ * The multigrid preconditioner takes FP64 instances, solved on their own
+ * (a batch holding one fails with PD_EINVAL); its levels (about 150 bytes
+ * per unknown) are allocated by the instance's next solve that needs them
+ * and kept until PD_PRECOND_LINE is set again or the instance is destroyed.
+ * Solutions agree with either preconditioner to the solve's tolerance.
+ * PD_EINVAL: unknown kind, or PD_PRECOND_MG on a mixed-precision instance;
+ * PD_EBUSY while the instance is in use.                                  */
+enum { PD_PRECOND_LINE = 0, PD_PRECOND_MG = 1 };
+int pd_set_preconditioner(pd_instance *inst, int32_t kind);
+
 /* Launch schedule (process-wide default for later solves and serving
  * plans).  groups: a batch is split into this many parts (by cells, largest
  * first, each to the part with the fewest), each stepping on its own stream
@@ -481,13 +509,14 @@ int pd_get_schedule(pd_schedule *schedule);
  * solver goes through hipExtLaunchKernel with a start and a stop event that
  * the dispatch itself stamps, so each launch's execution time (no launch
  * gaps) is added to its family's total (families PD_KF_*: one per kernel of
- * the Krylov cycle; a level is synchronised after it ends so the events can
+ * the Krylov cycle, PD_KF_MG for every launch of a multigrid V-cycle beyond
+ * the instance's own sweeps; a level is synchronised after it ends so the events can
  * be read, and captured graphs are not used meanwhile).  total_ms /
  * launches (PD_KF_N entries each, may be NULL) receive the totals since the
  * last reset.                                                             */
 enum { PD_KF_BEGIN = 0, PD_KF_FACTOR = 1, PD_KF_RAD_P = 2, PD_KF_ANG_P = 3, PD_KF_STEN_V = 4,
        PD_KF_RAD_S = 5, PD_KF_ANG_S = 6, PD_KF_STEN_T = 7, PD_KF_UPDATE = 8, PD_KF_REFINE = 9,
-       PD_KF_CONTROL = 10, PD_KF_LEVEL_END = 11, PD_KF_N = 12 };
+       PD_KF_CONTROL = 10, PD_KF_LEVEL_END = 11, PD_KF_MG = 12, PD_KF_N = 13 };
 int pd_kernel_timing(int32_t enable, int32_t reset, double *total_ms, int64_t *launches);
 
 const char *pd_last_error(void);

@@ -101,6 +101,28 @@ struct KSet {
   const T *inv_d;                    // 1/diag(A): the Krylov iteration runs on D^{-1}A
 };
 
+// One level of the θ-semi-coarsening multigrid preconditioner (device
+// descriptor).  Level 0 is the instance's own system; level l+1 merges the
+// θ-lines of level l in pairs (J <- 2J, 2J+1; the last coarse line takes
+// three when n_l is odd).  A level's operator is I/dt + θ L_l in the face
+// form of PdInst, with its own faces and angular cell widths: radial faces
+// of merged lines add up, the angular face between them drops out, the
+// volumes add (the Galerkin product of the volume-weighted system).  The
+// level below the last holds the ring means and is solved directly.
+struct PdMgLevel {
+  int m, n, npad;                     // rings, θ-lines, padded length (origin at m*n)
+  int has_b;
+  const double *gp_r, *gm_r, *gp_t, *gm_t;   // faces (PdInst layout)
+  const double *inv_rw;               // [m+2] the instance's (shared by every level)
+  const double *inv_dth;              // [n] 1/(angular cell width)
+  const double *b_node;               // [npad] volume-weighted reaction, or null
+  const double *diag, *inv_diag;      // [npad] diagonal of I/dt + θL_l (its factorisation)
+  double inv_V0;                      // 1/(origin volume), the same on every level
+  double *g;                          // right-hand side per volume (levels >= 1)
+  double *x;                          // iterate after the coarse correction (levels >= 1)
+  double *r, *w, *sh;                 // sweep input, radial intermediate, output
+};
+
 struct PdInst {
   int m, n, npad, nsrc;
   int K, mixed, has_b, zero_flux;

@@ -191,6 +191,10 @@ Tiling make_tiling(int m, int n) {
 
 // ------------------------------------------------------------------ instance
 
+namespace {
+struct MgHier;   // multigrid levels of an instance (below)
+}
+
 struct pd_instance {
   MeshH M;
   Tiling T;
@@ -218,6 +222,8 @@ struct pd_instance {
   std::vector<int> tp_h;
   double b0 = 0.0;            // reaction at the origin (the origin diagonal l0)
   double *drift = nullptr;    // device: G_r, c_r ((m+1) n each), G_t, c_t (m n each)
+  int precond = PD_PRECOND_LINE;   // pd_set_preconditioner
+  MgHier *mg = nullptr;            // its multigrid levels, built at the first solve that needs them
 };
 
 namespace {
@@ -654,6 +660,243 @@ int make_plan(std::vector<pd_instance *> const &insts, hipStream_t s, Plan &P, i
   return PD_OK;
 }
 
+// ------------------------------------------------------------------ multigrid
+//
+// The θ-semi-coarsening levels of an instance (PdMgLevel): level l+1 merges
+// the θ-lines of level l in pairs while n_l >= kMgMin, and the ring means
+// lie below the last level.  Each coarse level is laid out like an instance
+// of its own (faces, widths, reaction, factors, vectors) so that the
+// instance's factorisation and line-sweep kernels serve it unchanged; a
+// "shadow" descriptor of level 0 gives the instance's own factors the
+// V-cycle's vectors.  All of them point at the instance's scalars, so that
+// they run exactly when the instance's own kernels do.
+
+constexpr int kMgMin = 16;   // lines are merged while a level has at least this many
+
+struct MgHier {
+  int m = 0, n0 = 0, nlev = 0;
+  std::vector<int> ns;                                // θ-lines per level
+  void *dmem = nullptr;
+  std::vector<std::unique_ptr<pd_instance>> shadow;   // [0..nlev]
+  std::vector<std::unique_ptr<Plan>> plans;           // [0..nlev]
+  std::vector<PdMgLevel> hl;                          // host copies of the level descriptors
+  PdMgLevel *dlev = nullptr;
+  pd::MgSet set;
+  ~MgHier() {
+    plans.clear();
+    if (dmem) (void)hipFree(dmem);
+  }
+};
+
+void mg_free(pd_instance *I) {
+  delete I->mg;
+  I->mg = nullptr;
+}
+
+// Lays out the levels' arrays (a dry run only measures).
+void mg_carve(MgHier &H, const pd_instance *I, Carver &c) {
+  const int m = H.m;
+  const bool hb = I->H.has_b != 0;
+  H.hl.assign(H.nlev + 1, PdMgLevel{});
+  for (int l = 0; l <= H.nlev; ++l) {
+    const int n = H.ns[l];
+    const Tiling T = make_tiling(m, n);
+    const int np = T.npad, mn = m * n, ma = m * 64 * T.bang;
+    PdMgLevel &L = H.hl[l];
+    pd_instance &S = *H.shadow[l];
+    PdInst &D = S.H;
+    L.m = m;
+    L.n = n;
+    L.npad = np;
+    L.has_b = hb ? 1 : 0;
+    L.inv_rw = I->H.inv_rw;
+    L.inv_V0 = I->H.inv_V0;
+    L.r = c.take<double>(np);
+    L.w = c.take<double>(np);
+    L.sh = c.take<double>(np);
+    if (l == 0) {
+      L.gp_r = I->H.k64.gp_r;
+      L.gm_r = I->H.k64.gm_r;
+      L.gp_t = I->H.k64.gp_t;
+      L.gm_t = I->H.k64.gm_t;
+      L.inv_dth = I->H.inv_dth;
+      L.b_node = I->H.b_node;
+      L.diag = I->H.diag;
+      L.inv_diag = I->H.inv_diag;
+      continue;
+    }
+    L.gp_r = c.take<double>((size_t)(m + 1) * n);
+    L.gm_r = c.take<double>((size_t)(m + 1) * n);
+    L.gp_t = c.take<double>(mn);
+    L.gm_t = c.take<double>(mn);
+    L.inv_dth = c.take<double>(n);
+    L.b_node = hb ? c.take<double>(np) : nullptr;
+    double *dg = c.take<double>(np), *idg = c.take<double>(np);
+    L.diag = dg;
+    L.inv_diag = idg;
+    L.g = c.take<double>(np);
+    L.x = c.take<double>(np);
+    D.diag = dg;
+    D.inv_diag = idg;
+    D.rf_uinv = c.take<float>(mn);
+    D.rf_f = c.take<float>(mn);
+    D.rf_g = c.take<float>(mn);
+    D.af_uinv = c.take<float>(ma);
+    D.af_f = c.take<float>(ma);
+    D.af_g = c.take<float>(ma);
+    D.af_z = c.take<float>(ma);
+    D.af_kappa = c.take<double>(m);
+    D.af_alpha0 = c.take<double>(m);
+    D.af_q = c.take<float>(64 * T.bang);
+    D.af_c = c.take<float>(64 * T.bang);
+    D.af_sigma = c.take<double>(1);
+  }
+  H.dlev = c.take<PdMgLevel>(H.nlev + 1);
+  H.set.btot = c.take<double>(m + 1);
+  H.set.cring = c.take<double>(m + 1);
+}
+
+// The shadow descriptor of level l: the instance's descriptor with the
+// level's geometry, faces, factors and vectors (fields no sweep or
+// factorisation reads are cleared, so that a stray use fails loudly).
+void mg_shadow(MgHier &H, const pd_instance *I, int l) {
+  pd_instance &S = *H.shadow[l];
+  const PdMgLevel &L = H.hl[l];
+  const int m = H.m, n = H.ns[l];
+  S.M.m = m;
+  S.M.n = n;
+  S.T = l == 0 ? I->T : make_tiling(m, n);
+  S.precision = PD_FP64;
+  S.stream = I->stream;
+  PdInst D = I->H;
+  if (l > 0) {
+    const PdInst &K = S.H;   // factor arrays set by mg_carve
+    D.diag = K.diag;
+    D.inv_diag = K.inv_diag;
+    D.rf_uinv = K.rf_uinv;
+    D.rf_f = K.rf_f;
+    D.rf_g = K.rf_g;
+    D.af_uinv = K.af_uinv;
+    D.af_f = K.af_f;
+    D.af_g = K.af_g;
+    D.af_z = K.af_z;
+    D.af_kappa = K.af_kappa;
+    D.af_alpha0 = K.af_alpha0;
+    D.af_q = K.af_q;
+    D.af_c = K.af_c;
+    D.af_sigma = K.af_sigma;
+    D.inv_dth = L.inv_dth;
+    D.b_node = L.b_node;
+  }
+  D.m = m;
+  D.n = n;
+  D.npad = S.T.npad;
+  D.mixed = 0;
+  D.rb = S.T.rb;
+  D.ncg = S.T.ncg;
+  D.nrg = S.T.nrg;
+  D.nb_sten = S.T.nb_sten;
+  D.nb_elem = S.T.nb_elem;
+  D.cw = S.T.cw;
+  D.nseg = S.T.nseg;
+  D.brad = S.T.brad;
+  D.nb_rad = S.T.nb_rad;
+  D.bang = S.T.bang;
+  D.aw = S.T.aw;
+  D.nb_ang = S.T.nb_ang;
+  D.nb_frad = S.T.nb_frad;
+  D.nb_fang = S.T.nb_fang;
+  D.k64 = KSet<double>{};
+  D.k64.r = D.k64.rh = D.k64.p = D.k64.v = D.k64.ph = D.k64.s = D.k64.t = D.k64.d = L.r;
+  D.k64.w = L.w;
+  D.k64.sh = L.sh;
+  D.k64.gp_r = L.gp_r;
+  D.k64.gm_r = L.gm_r;
+  D.k64.gp_t = L.gp_t;
+  D.k64.gm_t = L.gm_t;
+  D.k64.inv_d = D.inv_diag;
+  D.k32 = KSet<float>{};
+  D.inv_diag32 = nullptr;
+  for (int k = 0; k < PD_NSOL; ++k) D.sol[k] = D.lsol[k] = nullptr;
+  for (int k = 0; k < 3; ++k) D.fdot[k] = nullptr;
+  D.ldiag = D.bvec = D.rout = nullptr;
+  D.part_b = D.part_v = D.part_t = D.part_ur = D.part_a = D.part_x = D.part_g = D.gram_tot = nullptr;
+  D.part_e = D.cr_c = D.part_c = D.cr_f = D.part_c0 = nullptr;
+  D.level_stats = nullptr;
+  D.sc = I->H.sc;
+  S.H = D;
+}
+
+// Builds (or reuses) the instance's levels for a solve on stream s: the
+// coarse faces from the instance's current faces, the level descriptors,
+// and one launch set per level.
+int mg_prepare(pd_instance *I, hipStream_t s, const pd::MgSet **out) {
+  if (I->precision != PD_FP64) return fail(PD_EINVAL, "the multigrid preconditioner takes FP64 instances");
+  const int m = I->M.m, n = I->M.n;
+  MgHier *H = I->mg;
+  if (!H || H->m != m || H->n0 != n) {
+    mg_free(I);
+    std::unique_ptr<MgHier> N(new MgHier);
+    N->m = m;
+    N->n0 = n;
+    N->ns = {n};
+    while (N->ns.back() >= kMgMin) N->ns.push_back(N->ns.back() / 2);
+    N->nlev = (int)N->ns.size() - 1;
+    if (N->nlev > PD_MG_MAXLEV) return fail(PD_EINVAL, "too many multigrid levels for %d lines", n);
+    for (int l = 0; l <= N->nlev; ++l) {
+      N->shadow.emplace_back(new pd_instance);
+      N->plans.emplace_back(new Plan);
+    }
+    Carver dry{nullptr, 0, true};
+    mg_carve(*N, I, dry);
+    const size_t bytes = dry.off;
+    hipError_t e = hipMalloc(&N->dmem, bytes);
+    if (e != hipSuccess) {
+      N->dmem = nullptr;
+      return fail(e == hipErrorOutOfMemory ? PD_ENOMEM : PD_EHIP, "multigrid allocation of %zu bytes failed: %s",
+                  bytes, hipGetErrorString(e));
+    }
+    HIPCHK(hipMemsetAsync(N->dmem, 0, bytes, s));
+    Carver cv{(char *)N->dmem, 0, false};
+    mg_carve(*N, I, cv);
+    I->mg = H = N.release();
+  }
+  // level 0 follows the instance (its faces may have changed since the last
+  // call: a carrier's drift); the coarse faces are formed again from them
+  {
+    Carver cv{(char *)H->dmem, 0, false};
+    mg_carve(*H, I, cv);   // the same layout again, with level 0's pointers into the instance
+  }
+  HIPCHK(hipMemcpyAsync(H->dlev, H->hl.data(), H->hl.size() * sizeof(PdMgLevel), hipMemcpyHostToDevice, s));
+  for (int l = 1; l <= H->nlev; ++l) {
+    PdMgLevel &L = H->hl[l];
+    pd::launch_mg_faces(H->dlev, l - 1, m, H->ns[l], const_cast<double *>(L.gp_r), const_cast<double *>(L.gm_r),
+                        const_cast<double *>(L.gp_t), const_cast<double *>(L.gm_t),
+                        const_cast<double *>(L.inv_dth), const_cast<double *>(L.b_node), s);
+    HIPCHK(hipGetLastError());
+  }
+  pd::MgSet &M = H->set;
+  M.nlev = H->nlev;
+  M.m = m;
+  for (int l = 0; l <= H->nlev; ++l) {
+    M.n[l] = H->ns[l];
+    mg_shadow(*H, I, l);
+    int rc = make_plan({H->shadow[l].get()}, s, *H->plans[l]);
+    if (rc) return rc;
+    M.lev[l] = H->plans[l]->L;
+  }
+  M.dlev = H->dlev;
+  M.sc = I->sc;
+  M.crs = I->H.crs;
+  M.p = I->H.k64.p;
+  M.s = I->H.k64.s;
+  M.r = I->H.k64.r;
+  M.ph = I->H.k64.ph;
+  M.sh = I->H.k64.sh;
+  *out = &M;
+  return PD_OK;
+}
+
 struct SolveParams {
   double theta, tol, tol_inner;
   int maxit, maxit_inner, max_outer;
@@ -821,6 +1064,16 @@ struct Engine {
       }
       int rc = make_plan(part, g.s, *g.P, rings);
       if (rc) return rc;
+      // a multigrid instance is solved on its own (its V-cycle launches are
+      // the plan's only instance's)
+      for (auto *I : part) {
+        if (I->precond != PD_PRECOND_MG) continue;
+        if (part.size() != 1)
+          return fail(PD_EINVAL, "an instance with the multigrid preconditioner is solved on its own");
+        const pd::MgSet *ms = nullptr;
+        if ((rc = mg_prepare(I, g.s, &ms))) return rc;
+        g.P->L.mg = ms;
+      }
       g.P->L.adaptive_any = adaptive ? 1 : 0;
       // every member still has levels to take
       HIPCHK(hipMemsetD32Async((hipDeviceptr_t)g.P->n_active, (int)part.size(), 1, g.s));
@@ -1459,6 +1712,21 @@ int pd_set_schedule(const pd_schedule *sc) {
   return PD_OK;
 }
 
+int pd_set_preconditioner(pd_instance *I, int32_t kind) {
+  if (!I) return fail(PD_EINVAL, "instance is NULL");
+  if (kind != PD_PRECOND_LINE && kind != PD_PRECOND_MG) return fail(PD_EINVAL, "unknown preconditioner %d", kind);
+  if (kind == PD_PRECOND_MG && I->precision != PD_FP64)
+    return fail(PD_EINVAL, "the multigrid preconditioner takes FP64 instances");
+  BusyGuard g({I});
+  if (!g.ok) return fail(PD_EBUSY, "instance is in use");
+  I->precond = kind;
+  if (kind == PD_PRECOND_LINE) {
+    if (I->stream) HIPCHK(hipStreamSynchronize(I->stream));
+    mg_free(I);
+  }
+  return PD_OK;
+}
+
 int pd_get_schedule(pd_schedule *sc) {
   if (!sc) return fail(PD_EINVAL, "NULL argument");
   sc->groups = g_sched_groups.load();
@@ -1550,6 +1818,7 @@ int pd_destroy(pd_instance *I) {
   if (I->busy) return fail(PD_EBUSY, "instance is in use");
   if (I->stream) (void)hipStreamSynchronize(I->stream);
   if (I->drift) (void)hipFree(I->drift);
+  mg_free(I);
   if (!I->arena) {          // a serving arena takes its chunk back itself
     if (I->dmem) (void)hipFree(I->dmem);
     if (I->t_table) (void)hipFree(I->t_table);
@@ -1878,7 +2147,16 @@ int pd_gummel_step(pd_instance *psi, pd_instance *ne, pd_instance *pe, double t_
       C->have_prev = false;
     }
     std::vector<std::vector<double>> sc(2);
-    if ((rc = solve_many({ne, pe}, {&tdc, &tdc}, &sc))) return rc;
+    if (ne->precond == PD_PRECOND_MG || pe->precond == PD_PRECOND_MG) {
+      // a multigrid instance is solved on its own
+      std::vector<std::vector<double>> one(1);
+      if ((rc = solve_many({ne}, {&tdc}, &one))) return rc;
+      sc[0] = one[0];
+      if ((rc = solve_many({pe}, {&tdc}, &one))) return rc;
+      sc[1] = one[0];
+    } else if ((rc = solve_many({ne, pe}, {&tdc, &tdc}, &sc))) {
+      return rc;
+    }
     krylov += (int)sc[0][0] + (int)sc[1][0];
     if (it >= 1 && change <= gummel_tol) {
       ++it;
@@ -1916,6 +2194,11 @@ int pd_apply_preconditioner(pd_instance *I, double dt, double theta, const doubl
   HIPCHK(hipMemcpyAsync(I->t_table, tab, sizeof tab, hipMemcpyHostToDevice, s));
   Plan P;
   if ((rc = make_plan({I}, s, P))) return rc;
+  if (I->precond == PD_PRECOND_MG) {
+    const pd::MgSet *ms = nullptr;
+    if ((rc = mg_prepare(I, s, &ms))) return rc;
+    P.L.mg = ms;
+  }
   SolveParams sp{theta, 1e-300, 1e-3, 1, 1, 1};
   if ((rc = init_scalars(I, sp, 1, s))) return rc;
   pd::launch_level_begin(P.L, s);

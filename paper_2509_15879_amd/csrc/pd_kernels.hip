@@ -1769,33 +1769,24 @@ __device__ __forceinline__ V block_exclusive_scan(V v, int pos, V ident, Op op, 
   return ex;
 }
 
-__global__ __launch_bounds__(PD_CC_THREADS) void k_coarse(const PdInst *insts) {
-  const PdInst &I = insts[blockIdx.x];
-  const PdScalars *sc = I.sc;
-  if (!level_converged(sc)) return;   // the same for every thread of the block
+// The ring-mean system for the right-hand side (f0 at the origin, known to
+// thread 0; fr[i] for ring i), solved into out[0..m].  One block of
+// PD_CC_THREADS threads; every thread calls it.
+__device__ void ring_solve(const double *crs, int m, double inv_dt, double th, double f0, const double *fr,
+                           double *out) {
   __shared__ Mat2 shm[PD_CC_THREADS];
   __shared__ Aff sha[PD_CC_THREADS];
-  const int m = I.m, n = I.n, M1 = m + 1, orig = m * n;
-  const double inv_dt = sc->inv_dt, th = sc->theta;
-  double s0[1];
-  consume<1>(I.part_c0, I.nb_sten, s0);
-  const double *cV = I.crs, *cU = I.crs + 4 * M1;
+  const int M1 = m + 1;
+  const double *cU = crs + 4 * M1;
   const int t = threadIdx.x;
   const int S = (M1 + blockDim.x - 1) / blockDim.x;   // <= PD_CC_ROWS
   const int r0 = t * S;
   const int cnt = max(0, min(S, M1 - r0));
   double d[PD_CC_ROWS], a[PD_CC_ROWS], c[PD_CC_ROWS], f[PD_CC_ROWS];
-  // the origin's residual (thread 0 only), then every row's coefficients,
-  // all loads issued (rows past the end reread the last row, masked below)
-  double f0 = 0.0;
-  if (t == 0) {
-    const double x0 = I.sol[sol_slot(sc->rot, -1)][orig];
-    const double bo = I.has_b ? I.b_node[orig] : 0.0;
-    const double r = I.bvec[orig] - (inv_dt * x0 + th * (I.inv_V0 * s0[0] + bo * x0));
-    f0 = cV[0] * r;
-  }
+  // every row's coefficients, all loads issued (rows past the end reread the
+  // last row, masked below)
   {
-    const GAS double *gc = G(I.crs), *gf = G((const double *)I.cr_f);
+    const GAS double *gc = G(crs), *gf = G(fr);
     double v[7][PD_CC_ROWS];
 #pragma unroll
     for (int k = 0; k < PD_CC_ROWS; ++k) {
@@ -1869,9 +1860,28 @@ __global__ __launch_bounds__(PD_CC_THREADS) void k_coarse(const PdInst *insts) {
   for (int k = PD_CC_ROWS - 1; k >= 0; --k) {
     if (k < cnt) {
       xn = (f[k] - c[k] * xn) * uinv[k];
-      I.cr_c[r0 + k] = xn;
+      out[r0 + k] = xn;
     }
   }
+}
+
+__global__ __launch_bounds__(PD_CC_THREADS) void k_coarse(const PdInst *insts) {
+  const PdInst &I = insts[blockIdx.x];
+  const PdScalars *sc = I.sc;
+  if (!level_converged(sc)) return;   // the same for every thread of the block
+  const int n = I.n, orig = I.m * n;
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  double s0[1];
+  consume<1>(I.part_c0, I.nb_sten, s0);
+  // the origin's residual (thread 0 only)
+  double f0 = 0.0;
+  if (threadIdx.x == 0) {
+    const double x0 = I.sol[sol_slot(sc->rot, -1)][orig];
+    const double bo = I.has_b ? I.b_node[orig] : 0.0;
+    const double r = I.bvec[orig] - (inv_dt * x0 + th * (I.inv_V0 * s0[0] + bo * x0));
+    f0 = I.crs[0] * r;
+  }
+  ring_solve(I.crs, I.m, inv_dt, th, f0, I.cr_f, I.cr_c);
 }
 
 // x <- x + P c for the instances whose level has converged (elementwise).
@@ -1888,6 +1898,248 @@ __global__ __launch_bounds__(256) void k_cadd(const PdInst *insts, const int2 *m
     if (idx < orig) x[idx] += c[idx / n + 1];
     else if (idx == orig) x[idx] += c[0];
   }
+}
+
+// ------------------------------------------------------------ multigrid
+//
+// The θ-semi-coarsening V-cycle (PdMgLevel) as the preconditioner of one
+// FP64 instance's Krylov system D^{-1}A: z ≈ (D^{-1}A)^{-1} y.  Every level
+// smooths with one step of its own alternating-line sweeps,
+//   x <- x + M_l^{-1} D_l^{-1} (g_l - A_l x),
+// from x = 0 on the way down and again after the coarse correction on the
+// way up; the ring means at the bottom are solved directly (ring_solve with
+// the instance's ring sums: merging lines does not change them).  Level 0's
+// right-hand side is diag(A) y and its pre-smoothed iterate is the Krylov
+// vector z = M^{-1} y that the instance's own sweeps have just written.
+//
+// Vectors of a level l >= 1: g_l (right-hand side per volume); sh_l holds
+// the pre-smoothed iterate, then x_l = sh_l + P e_{l+1} after the coarse
+// correction, and sh_l the post-smoothing correction, so that the level
+// returns e_l = x_l + sh_l.  The kernels run only while the instance
+// iterates (the same gate as its own sweeps).
+
+// Coarse line of line j of a level with nc coarse lines.
+__device__ __forceinline__ int mg_coarse(int j, int nc) { return min(j >> 1, nc - 1); }
+
+// (A_l x) at ring node (i, j) of a level, x(ii, jj) its values, x0 the origin's.
+template <class X>
+__device__ __forceinline__ double mg_apply(const PdMgLevel &L, int i, int j, double inv_dt, double th, X x,
+                                           double x0) {
+  const int n = L.n, m = L.m, row = (i - 1) * n;
+  const int jl = j == 0 ? n - 1 : j - 1, jr = j == n - 1 ? 0 : j + 1;
+  const double xc = x(i, j);
+  const double xi = i == 1 ? x0 : x(i - 1, j);
+  const double xo = i == m ? 0.0 : x(i + 1, j);
+  const double xl = x(i, jl), xr = x(i, jr);
+  const double fo = L.gp_r[i * n + j] * xc - L.gm_r[i * n + j] * xo;
+  const double fi = L.gp_r[row + j] * xi - L.gm_r[row + j] * xc;
+  const double fu = L.gp_t[row + j] * xc - L.gm_t[row + j] * xr;
+  const double fl = L.gp_t[row + jl] * xl - L.gm_t[row + jl] * xc;
+  const double ivV = L.inv_rw[i] * L.inv_dth[j];
+  const double bP = L.has_b ? L.b_node[row + j] : 0.0;
+  return inv_dt * xc + th * (ivV * ((fo - fi) + (fu - fl)) + bP * xc);
+}
+
+// Block sum in a fixed order (wave butterflies, then the waves in turn);
+// every thread of the block calls it and receives the total.
+__device__ __forceinline__ double mg_block_sum(double v) {
+  __shared__ double red[16];
+  __shared__ double tot;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    tot = t;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// (A_l x)_0 at the origin from its faces to ring 1 (the calling block sums).
+template <class X>
+__device__ __forceinline__ double mg_apply_origin(const PdMgLevel &L, double inv_dt, double th, X x, double x0) {
+  double s = 0.0;
+  for (int j = threadIdx.x; j < L.n; j += blockDim.x) s += L.gp_r[j] * x0 - L.gm_r[j] * x(1, j);
+  s = mg_block_sum(s);
+  const double b0 = L.has_b ? L.b_node[L.m * L.n] : 0.0;
+  return inv_dt * x0 + th * (L.inv_V0 * s + b0 * x0);
+}
+
+// Coarse faces, widths and reaction of level l+1 from level l (set-up, once
+// per solve call): one thread per coarse (face row, line).
+__global__ __launch_bounds__(256) void k_mg_faces(const PdMgLevel *lev, int l, double *gp_r, double *gm_r,
+                                                  double *gp_t, double *gm_t, double *inv_dth, double *b_node) {
+  const PdMgLevel F = lev[l];
+  const int m = F.m, nf = F.n, nc = nf / 2;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (m + 1) * nc) return;
+  const int i = gid / nc, J = gid % nc;
+  const int j0 = 2 * J, cnt = J == nc - 1 ? nf - j0 : 2;
+  double sp = 0.0, sm = 0.0, w = 0.0, vb = 0.0;
+  for (int k = 0; k < cnt; ++k) {
+    const int j = j0 + k;
+    sp += F.gp_r[i * nf + j];
+    sm += F.gm_r[i * nf + j];
+    const double dw = 1.0 / F.inv_dth[j];
+    w += dw;
+    if (i >= 1 && F.has_b) vb += dw * F.b_node[(i - 1) * nf + j];
+  }
+  gp_r[i * nc + J] = sp;
+  gm_r[i * nc + J] = sm;
+  if (i == 0) {
+    inv_dth[J] = 1.0 / w;
+    if (F.has_b && J == 0) b_node[m * nc] = F.b_node[m * nf];
+    return;
+  }
+  const int jl = j0 + cnt - 1;   // the line's last fine line: its upper face bounds the merged cell
+  gp_t[(i - 1) * nc + J] = F.gp_t[(i - 1) * nf + jl];
+  gm_t[(i - 1) * nc + J] = F.gm_t[(i - 1) * nf + jl];
+  if (F.has_b) b_node[(i - 1) * nc + J] = vb / w;
+}
+
+// Down: the volume-weighted residual of level lc-1 summed over each coarse
+// cell, as level lc's right-hand side g (per volume) and its sweep input
+// r = g / diag.  Level 0: g = diag y, iterate z; else g and sh of the level.
+// One thread per coarse ring node; the last block takes the origin.
+__global__ __launch_bounds__(256) void k_mg_down(const PdScalars *sc, const PdMgLevel *lev, int lc,
+                                                 const double *y, const double *z) {
+  if (!inner_active(sc)) return;   // the same for the whole grid
+  const PdMgLevel Fl = lev[lc - 1], Cl = lev[lc];
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  const bool top = lc == 1;
+  const double *xf = top ? z : Fl.sh;
+  const int m = Cl.m, nc = Cl.n, nf = Fl.n;
+  const double x0 = xf[m * nf];
+  auto xv = [&](int ii, int jj) { return xf[(ii - 1) * nf + jj]; };
+  if (blockIdx.x == gridDim.x - 1) {
+    const double ax = mg_apply_origin(Fl, inv_dt, th, xv, x0);
+    if (threadIdx.x == 0) {
+      const double g = top ? Fl.diag[m * nf] * y[m * nf] : Fl.g[m * nf];
+      const double gc = g - ax;   // the origin cell is kept: same volume
+      Cl.g[m * nc] = gc;
+      Cl.r[m * nc] = gc * Cl.inv_diag[m * nc];
+    }
+    return;
+  }
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= m * nc) return;
+  const int i = gid / nc + 1, J = gid % nc;
+  const int j0 = 2 * J, cnt = J == nc - 1 ? nf - j0 : 2;
+  double f = 0.0;
+  for (int k = 0; k < cnt; ++k) {
+    const int j = j0 + k, idx = (i - 1) * nf + j;
+    const double g = top ? Fl.diag[idx] * y[idx] : Fl.g[idx];
+    f += (g - mg_apply(Fl, i, j, inv_dt, th, xv, x0)) / (Fl.inv_rw[i] * Fl.inv_dth[j]);
+  }
+  const int cidx = (i - 1) * nc + J;
+  const double gc = f * (Cl.inv_rw[i] * Cl.inv_dth[J]);
+  Cl.g[cidx] = gc;
+  Cl.r[cidx] = gc * Cl.inv_diag[cidx];
+}
+
+// Bottom: ring totals of level lb's volume-weighted residual (tot[i], the
+// origin at tot[0]); one thread per ring (thread 0 of block 0: the origin).
+__global__ __launch_bounds__(256) void k_mg_ringtot(const PdScalars *sc, const PdMgLevel *lev, int lb,
+                                                    const double *y, const double *z, double *tot) {
+  if (!inner_active(sc)) return;
+  const PdMgLevel B = lev[lb];
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  const bool top = lb == 0;
+  const double *xb = top ? z : B.sh;
+  const int m = B.m, n = B.n;
+  const double x0 = xb[m * n];
+  auto xv = [&](int ii, int jj) { return xb[(ii - 1) * n + jj]; };
+  auto gv = [&](int idx) { return top ? B.diag[idx] * y[idx] : B.g[idx]; };
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > m) return;
+  if (i == 0) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += B.gp_r[j] * x0 - B.gm_r[j] * xv(1, j);
+    const double b0 = B.has_b ? B.b_node[m * n] : 0.0;
+    const double ax = inv_dt * x0 + th * (B.inv_V0 * s + b0 * x0);
+    tot[0] = (gv(m * n) - ax) / B.inv_V0;
+    return;
+  }
+  double f = 0.0;
+  for (int j = 0; j < n; ++j)
+    f += (gv((i - 1) * n + j) - mg_apply(B, i, j, inv_dt, th, xv, x0)) / (B.inv_rw[i] * B.inv_dth[j]);
+  tot[i] = f;
+}
+
+// Bottom: the ring-mean system solved for the totals (one block).
+__global__ __launch_bounds__(PD_CC_THREADS) void k_mg_solve(const PdScalars *sc, const double *crs, int m,
+                                                            const double *tot, double *c) {
+  if (!inner_active(sc)) return;
+  ring_solve(crs, m, sc->inv_dt, sc->theta, tot[0], tot, c);
+}
+
+// Up, level l (nlev coarse levels; below level nlev the ring means c): the
+// coarse correction e from level l+1 added to the level's pre-smoothed
+// iterate (x_l, stored for l >= 1), and the post-smoothing sweep input
+// r = (g - A_l x_l) / diag.  Neighbours' x_l are formed on the fly (no
+// thread reads another's store).  The last block takes the origin.
+__global__ __launch_bounds__(256) void k_mg_up(const PdScalars *sc, const PdMgLevel *lev, int l, int nlev,
+                                               const double *cring, const double *y, const double *z) {
+  if (!inner_active(sc)) return;
+  const PdMgLevel L = lev[l];
+  const bool ring = l == nlev;
+  const PdMgLevel E = lev[ring ? l : l + 1];
+  const double inv_dt = sc->inv_dt, th = sc->theta;
+  const bool top = l == 0;
+  const double *base = top ? z : L.sh;
+  const int m = L.m, n = L.n, nc = E.n;
+  auto ev = [&](int ii, int jj) -> double {   // e at the coarse cell of (ii, jj)
+    if (ring) return cring[ii];
+    const int c = (ii - 1) * nc + mg_coarse(jj, nc);
+    return E.x[c] + E.sh[c];
+  };
+  const double e0 = ring ? cring[0] : E.x[m * nc] + E.sh[m * nc];
+  const double x0 = base[m * n] + e0;
+  auto xv = [&](int ii, int jj) { return base[(ii - 1) * n + jj] + ev(ii, jj); };
+  if (blockIdx.x == gridDim.x - 1) {
+    const double ax = mg_apply_origin(L, inv_dt, th, xv, x0);
+    if (threadIdx.x == 0) {
+      const int o = m * n;
+      const double g = top ? L.diag[o] * y[o] : L.g[o];
+      if (!top) L.x[o] = x0;
+      L.r[o] = (g - ax) * L.inv_diag[o];
+    }
+    return;
+  }
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= m * n) return;
+  const int i = gid / n + 1, j = gid % n;
+  const double g = top ? L.diag[gid] * y[gid] : L.g[gid];
+  if (!top) L.x[gid] = xv(i, j);
+  L.r[gid] = (g - mg_apply(L, i, j, inv_dt, th, xv, x0)) * L.inv_diag[gid];
+}
+
+// Level 0's result: z <- z + P e_1 + (its post-smoothing correction).
+__global__ __launch_bounds__(256) void k_mg_fin(const PdScalars *sc, const PdMgLevel *lev, int nlev,
+                                                const double *cring, double *z) {
+  if (!inner_active(sc)) return;
+  const PdMgLevel L = lev[0];
+  const bool ring = nlev == 0;
+  const PdMgLevel E = lev[ring ? 0 : 1];
+  const int m = L.m, n = L.n, nc = E.n;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid > m * n) return;
+  double e;
+  if (gid == m * n) {
+    e = ring ? cring[0] : E.x[m * nc] + E.sh[m * nc];
+  } else {
+    const int i = gid / n + 1, j = gid % n;
+    if (ring) {
+      e = cring[i];
+    } else {
+      const int c = (i - 1) * nc + mg_coarse(j, nc);
+      e = E.x[c] + E.sh[c];
+    }
+  }
+  z[gid] += e + L.sh[gid];
 }
 
 // Origin of a diagnostic operator apply (one thread per instance).
@@ -2960,7 +3212,8 @@ static inline void go(int fam, void (*k)(KArgs...), dim3 grid, dim3 block, hipSt
     k<<<grid, block, 0, s>>>(args...);
 }
 enum { KF_BEGIN = 0, KF_FACTOR = 1, KF_RAD_P = 2, KF_ANG_P = 3, KF_STEN_V = 4, KF_RAD_S = 5,
-       KF_ANG_S = 6, KF_STEN_T = 7, KF_UPDATE = 8, KF_REFINE = 9, KF_CONTROL = 10, KF_LEVEL_END = 11 };
+       KF_ANG_S = 6, KF_STEN_T = 7, KF_UPDATE = 8, KF_REFINE = 9, KF_CONTROL = 10, KF_LEVEL_END = 11,
+       KF_MG = 12 };
 
 void launch_level_begin(const LaunchSet &L, hipStream_t s) {
   go(KF_CONTROL, k_level_begin, dim3((L.ninst + 63) / 64), dim3(64), s, L.insts, L.ninst);
@@ -2985,6 +3238,10 @@ void launch_factor(const LaunchSet &L, hipStream_t s) {
     PD_DISPATCH_BM(L.max_bfrad, (go(KF_FACTOR, k_fact_rad<BM>, g1(L.nb_rad), dim3(PD_RAD_THREADS), s, L.insts, L.map_rad)));
   if (L.nb_ang)
     PD_DISPATCH_BM(L.max_bang, (go(KF_FACTOR, k_fact_ang<BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang)));
+  // the coarse levels of a multigrid preconditioner factor their own lines
+  // (gated, like the instance's, on the instance starting a level)
+  if (L.mg)
+    for (int l = 1; l <= L.mg->nlev; ++l) launch_factor(L.mg->lev[l], s);
 }
 void launch_begin(const LaunchSet &L, hipStream_t s) {
   go(KF_BEGIN, k_sten<double, SM_GRAM>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
@@ -2995,8 +3252,8 @@ void launch_begin(const LaunchSet &L, hipStream_t s) {
 }
 
 template <typename T, int MODE>
-static void rad(const LaunchSet &L, hipStream_t s) {
-  const int fam = MODE == RM_S ? KF_RAD_S : (MODE == RM_P ? KF_RAD_P : KF_CONTROL);
+static void rad(const LaunchSet &L, hipStream_t s, int fam_as = -1) {
+  const int fam = fam_as >= 0 ? fam_as : (MODE == RM_S ? KF_RAD_S : (MODE == RM_P ? KF_RAD_P : KF_CONTROL));
   if (L.nb_rs[0]) {
     PD_DISPATCH_BM(L.max_brs[0], (go(fam, k_rad<T, MODE, BM, 512, 16>, g1(L.nb_rs[0]), dim3(512), s, L.insts, L.map_rs[0])));
   }
@@ -3008,8 +3265,8 @@ static void rad(const LaunchSet &L, hipStream_t s) {
   }
 }
 template <typename T, int MODE>
-static void ang(const LaunchSet &L, hipStream_t s) {
-  const int fam = MODE == AM_S ? KF_ANG_S : KF_ANG_P;
+static void ang(const LaunchSet &L, hipStream_t s, int fam_as = -1) {
+  const int fam = fam_as >= 0 ? fam_as : (MODE == AM_S ? KF_ANG_S : KF_ANG_P);
   if (L.nb_angs[0])
     PD_DISPATCH_BM(L.max_bang1, (go(fam, k_ang<T, MODE, BM>, g1(L.nb_angs[0]), dim3(256), s, L.insts, L.map_angs[0])));
   if (L.nb_angs[1]) go(fam, k_angw<T, MODE>, g1(L.nb_angs[1]), dim3(256), s, L.insts, L.map_angs[1]);
@@ -3018,6 +3275,42 @@ template <typename T, int MODE>
 static void sten(int fam, const LaunchSet &L, hipStream_t s) {
   go(fam, k_sten<T, MODE>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
      (const T *)nullptr, (T *)nullptr);
+}
+
+// The rest of a V-cycle once level 0 holds z = M^{-1} y (the multigrid
+// kernels' comment): down through the coarse levels, the ring means, up.
+static void mg_vcycle(const MgSet &M, const double *y, double *z, hipStream_t s) {
+  const int L = M.nlev, m = M.m;
+  const PdMgLevel *dl = M.dlev;
+  auto blocks = [&](int l) { return g1((m * M.n[l] + 255) / 256 + 1); };   // + the origin's block
+  for (int l = 1; l <= L; ++l) {
+    go(KF_MG, k_mg_down, blocks(l), dim3(256), s, M.sc, dl, l, y, (const double *)z);
+    rad<double, RM_Y>(M.lev[l], s, KF_MG);
+    ang<double, AM_S>(M.lev[l], s, KF_MG);
+  }
+  go(KF_MG, k_mg_ringtot, g1((m + 1 + 255) / 256), dim3(256), s, M.sc, dl, L, y, (const double *)z, M.btot);
+  go(KF_MG, k_mg_solve, g1(1), dim3(PD_CC_THREADS), s, M.sc, M.crs, m, (const double *)M.btot, M.cring);
+  for (int l = L; l >= 0; --l) {
+    go(KF_MG, k_mg_up, blocks(l), dim3(256), s, M.sc, dl, l, L, (const double *)M.cring, y, (const double *)z);
+    rad<double, RM_Y>(M.lev[l], s, KF_MG);
+    ang<double, AM_S>(M.lev[l], s, KF_MG);
+  }
+  go(KF_MG, k_mg_fin, g1((m * M.n[0] + 1 + 255) / 256), dim3(256), s, M.sc, dl, L, (const double *)M.cring, z);
+}
+
+// A Krylov iteration preconditioned by the V-cycle (one FP64 instance): the
+// instance's sweeps give level 0's pre-smoothing, the V-cycle the rest.
+static void cycle_mg(const LaunchSet &L, hipStream_t s) {
+  const MgSet &M = *L.mg;
+  rad<double, RM_P>(L, s);
+  ang<double, AM_P>(L, s);
+  mg_vcycle(M, M.p, M.ph, s);
+  sten<double, SM_V>(KF_STEN_V, L, s);
+  rad<double, RM_S>(L, s);
+  ang<double, AM_S>(L, s);
+  mg_vcycle(M, M.s, M.sh, s);
+  sten<double, SM_T>(KF_STEN_T, L, s);
+  go(KF_UPDATE, k_elem_x<double>, g1(L.nb_elem), dim3(256), s, L.insts, L.map_elem);
 }
 
 template <typename T>
@@ -3066,10 +3359,15 @@ void launch_precond_apply(const LaunchSet &L, int fp32, hipStream_t s) {
   } else {
     rad<double, RM_Y>(L, s);
     ang<double, AM_P>(L, s);
+    if (L.mg) mg_vcycle(*L.mg, L.mg->r, L.mg->ph, s);
   }
 }
 
 void launch_cycle(const LaunchSet &L, hipStream_t s) {
+  if (L.mg) {   // one FP64 instance
+    cycle_mg(L, s);
+    return;
+  }
   if (L.mixed_any) sten<float, SM_UR>(KF_REFINE, L, s);
   if (L.mixed_any && !L.fp64_any) {
     cycle_t<float>(L, s);
@@ -3097,6 +3395,12 @@ void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void 
     go(KF_CONTROL, k_apply_origin<double>, go_orig, dim3(64), s, L.insts, L.ninst, dt, th,
        (const double *)x, (double *)y);
   }
+}
+
+void launch_mg_faces(const PdMgLevel *dlev, int l, int m, int nc, double *gp_r, double *gm_r, double *gp_t,
+                     double *gm_t, double *inv_dth, double *b_node, hipStream_t s) {
+  go(KF_MG, k_mg_faces, g1(((m + 1) * nc + 255) / 256), dim3(256), s, dlev, l, gp_r, gm_r, gp_t, gm_t, inv_dth,
+     b_node);
 }
 
 void launch_begin_origin(const LaunchSet &L, hipStream_t s) {

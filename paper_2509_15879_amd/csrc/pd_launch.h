@@ -5,6 +5,10 @@
 
 namespace pd {
 
+#define PD_MG_MAXLEV 12   // coarse θ-levels of a multigrid preconditioner (2048 lines need 8)
+
+struct MgSet;
+
 // Device-side description of one batched launch: the instance array and,
 // per kernel family, a block map (instance index, block index within it).
 struct LaunchSet {
@@ -27,6 +31,27 @@ struct LaunchSet {
   int2 *map_rs[3] = {nullptr, nullptr, nullptr};
   int nb_rs[3] = {0, 0, 0};
   int max_brs[3] = {1, 1, 1};       // longest radial segment per class
+  // the multigrid preconditioner of the plan's one instance, or null
+  const MgSet *mg = nullptr;
+};
+
+// Launches of a θ-semi-coarsening V-cycle (PdMgLevel) for one FP64
+// instance: per level a launch set of its line sweeps (level 0: the
+// instance's own factors with the V-cycle's vectors; level l: the level's
+// faces and factors), all gated on the instance's scalars.
+struct MgSet {
+  int nlev = 0;                      // coarse θ-levels 1..nlev (the ring means below)
+  int m = 0;
+  int n[PD_MG_MAXLEV + 1] = {};      // θ-lines per level
+  LaunchSet lev[PD_MG_MAXLEV + 1];
+  const PdMgLevel *dlev = nullptr;   // device [nlev + 1]
+  const PdScalars *sc = nullptr;     // the instance's scalars
+  const double *crs = nullptr;       // its ring sums (the ring-mean system)
+  double *btot = nullptr, *cring = nullptr;   // ring totals and ring-mean correction [m + 1]
+  // the instance's Krylov vectors: inputs p, s (and r for a diagnostic
+  // application), outputs p̂, ŝ
+  const double *p = nullptr, *s = nullptr, *r = nullptr;
+  double *ph = nullptr, *sh = nullptr;
 };
 
 // Radial-sweep classes: 512-thread blocks of 16 columns x 32 segments for
@@ -59,6 +84,10 @@ void launch_round(const LaunchSet &L, int cycles, hipStream_t s);
 void launch_factor(const LaunchSet &L, hipStream_t s);
 void launch_begin(const LaunchSet &L, hipStream_t s);
 void launch_begin_origin(const LaunchSet &L, hipStream_t s);
+// Faces, angular widths and reaction of multigrid level l+1 (nc lines) from
+// level l of the device descriptors.
+void launch_mg_faces(const PdMgLevel *dlev, int l, int m, int nc, double *gp_r, double *gm_r, double *gp_t,
+                     double *gm_t, double *inv_dth, double *b_node, hipStream_t s);
 void launch_cycle(const LaunchSet &L, hipStream_t s);
 void launch_precond_apply(const LaunchSet &L, int fp32, hipStream_t s);
 void launch_apply(const LaunchSet &L, double dt, double th, const void *x, void *y, int fp32,

@@ -23,6 +23,7 @@ ERRORS = {-1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EBREAKDOWN", -4: "PD_ENOCONV
 PD_FP64, PD_MIXED = 0, 1
 MESH_UNIFORM, MESH_SINE, MESH_EXPLICIT, MESH_POLY = 0, 1, 2, 3
 LAYOUT_RING, LAYOUT_PAPER = 0, 1
+PRECOND_LINE, PRECOND_MG = 0, 1
 FLUX_CENTRAL, FLUX_UPWIND, FLUX_LITERAL = 0, 1, 2
 TIME_UNIFORM, TIME_SINE, TIME_TABLE, TIME_ADAPTIVE = 0, 1, 2, 3
 
@@ -102,14 +103,14 @@ class Indicator(C.Structure):
 # every entry point declared in include/polardisk.h
 EXPORTS = ("pd_mesh_coords", "pd_time_levels", "pd_mesh_create", "pd_scheme_step", "pd_solve_to_T", "pd_solve_batch",
            "pd_get_solution", "pd_set_solution", "pd_apply_operator", "pd_assemble_rhs",
-           "pd_apply_preconditioner", "pd_set_mobility", "pd_gummel_step",
+           "pd_apply_preconditioner", "pd_set_preconditioner", "pd_set_mobility", "pd_gummel_step",
            "pd_footprint", "pd_destroy", "pd_batch_create", "pd_batch_submit", "pd_batch_poll",
            "pd_batch_stats", "pd_error_indicator", "pd_error_indicator_noalloc", "pd_remesh_transfer", "pd_set_schedule",
            "pd_get_schedule", "pd_get_time",
            "pd_batch_destroy", "pd_kernel_timing", "pd_last_error")
 
 KERNEL_FAMILIES = ("begin", "factor", "rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t",
-                   "update", "refine", "control", "level_end")
+                   "update", "refine", "control", "level_end", "multigrid")
 
 
 def _load():
@@ -131,6 +132,7 @@ def _load():
         "pd_assemble_rhs": [P, D, D, D, P, I32, I32],
         "pd_apply_preconditioner": [P, D, D, P, P, I32, I32],
         "pd_set_mobility": [P, P, P, D, I32],
+        "pd_set_preconditioner": [P, I32],
         "pd_gummel_step": [P, P, P, D, D, D, D, D, I32, C.POINTER(GummelStats)],
         "pd_footprint": [C.POINTER(MeshDesc), I32, I32, C.POINTER(SZ)],
         "pd_destroy": [P],
@@ -473,6 +475,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def set_preconditioner(inst: "Instance", kind: int):
+    """Preconditioner of the instance's later solves: PRECOND_LINE (the
+    alternating line sweeps) or PRECOND_MG (the θ-semi-coarsening V-cycle
+    built on them; FP64 instances solved on their own)."""
+    _check(lib.pd_set_preconditioner(inst.h, int(kind)))
 
 
 def set_mobility(carrier: "Instance", mu_rface, mu_tface, sign: float):
