@@ -393,38 +393,100 @@ def gummel_variant(pdk, stream, m=256, n=512, K=20, dt=1e-3, theta=0.5):
     """The coupled two-carrier system (electrons and holes through a polar
     Poisson problem, Gummel's iteration to a relative potential change of
     1e-10 per level) on a 256 x 512 graded mesh (p = 1.3), K levels of
-    Crank-Nicolson: wall time, Gummel and Krylov iterations per level, and
-    the zero-flux variant's conservation of each carrier."""
+    Crank-Nicolson, with the line sweeps for all three fields, with the
+    multigrid V-cycle for the potential only, and with it for all three:
+    wall time, Gummel and Krylov iterations per level, and the largest
+    difference from the line-sweep run."""
     import torch
     from problems import sample, two_carrier
     out = {"workload": (f"two carriers + polar Poisson (Gummel), {m}x{n} graded p=1.3, {K} levels of "
-                        f"theta {theta}, dt {dt}, FP64")}
+                        f"theta {theta}, dt {dt}, FP64"),
+           "unit_note": "cell-updates/s counts the three fields per level"}
     psi_pb, n_pb, p_pb = two_carrier(3200)
     md = pdk.mesh_desc(m, n, pdk.MESH_SINE, 1.3)
     coords = pdk.mesh_coords(md)
     gd = [sample(pb, *coords) for pb in (psi_pb, n_pb, p_pb)]
-    psi = pdk.Instance(md, gd[0], pdk.PD_FP64, stream=stream)
-    car = [pdk.Instance(md, gd[k], pdk.PD_FP64, stream=stream) for k in (1, 2)]
-    for inst, d, sign in zip(car, gd[1:], (-1.0, 1.0)):
-        pdk.set_mobility(inst, d["D_r"], d["D_t"], sign)
-    pdk.gummel_step(psi, car[0], car[1], 0.0, dt, theta, tol=1e-12)     # warm-up (plans)
-    u = [ring_u0(d) for d in gd]
-    for i, x in zip([psi] + car, u):
-        i.set_solution(x, 0.0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sts = [pdk.gummel_step(psi, car[0], car[1], k * dt, dt, theta, tol=1e-12, gummel_tol=1e-10, max_gummel=40)
-           for k in range(K)]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    cells = 3 * (m * n + 1)
-    out.update({"ms": round(1e3 * el, 1), "value": round(cells * K / el, 1),
-                "unit_note": "cell-updates/s counts the three fields per level",
-                "gummel_iters_per_level": round(float(np.mean([s["gummel_iters"] for s in sts])), 2),
-                "krylov_iters_per_level": round(float(np.mean([s["krylov_iters"] for s in sts])), 1),
-                "last_change": max(s["change"] for s in sts)})
-    for i in [psi] + car:
-        i.close()
+    finals = {}
+    L, MG = pdk.PRECOND_LINE, pdk.PRECOND_MG
+    for name, kinds in (("line", (L, L, L)), ("multigrid_potential", (MG, L, L)), ("multigrid", (MG, MG, MG))):
+        psi = pdk.Instance(md, gd[0], pdk.PD_FP64, stream=stream)
+        car = [pdk.Instance(md, gd[k], pdk.PD_FP64, stream=stream) for k in (1, 2)]
+        for inst, d, sign in zip(car, gd[1:], (-1.0, 1.0)):
+            pdk.set_mobility(inst, d["D_r"], d["D_t"], sign)
+        for inst, kind in zip([psi] + car, kinds):
+            pdk.set_preconditioner(inst, kind)
+        pdk.gummel_step(psi, car[0], car[1], 0.0, dt, theta, tol=1e-12)     # warm-up (plans, levels)
+        u = [ring_u0(d) for d in gd]
+        for i, x in zip([psi] + car, u):
+            i.set_solution(x, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [pdk.gummel_step(psi, car[0], car[1], k * dt, dt, theta, tol=1e-12, gummel_tol=1e-10, max_gummel=40)
+               for k in range(K)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        cells = 3 * (m * n + 1)
+        out[name] = {"ms": round(1e3 * el, 1), "value": round(cells * K / el, 1),
+                     "gummel_iters_per_level": round(float(np.mean([s["gummel_iters"] for s in sts])), 2),
+                     "krylov_iters_per_level": round(float(np.mean([s["krylov_iters"] for s in sts])), 1),
+                     "last_change": max(s["change"] for s in sts)}
+        finals[name] = [i.solution() for i in [psi] + car]
+        for i in [psi] + car:
+            i.close()
+    for name in ("multigrid_potential", "multigrid"):
+        out[name]["max_rel_vs_line"] = max(float(np.max(np.abs(a - b)) / np.max(np.abs(a)))
+                                           for a, b in zip(finals["line"], finals[name]))
+    best = min(("line", "multigrid_potential", "multigrid"), key=lambda k: out[k]["ms"])
+    out["best"] = best
+    out["value"] = out[best]["value"]
+    out["ms"] = out[best]["ms"]
+    return out
+
+
+def multigrid_variant(pdk, stream, sizes=((256, 512), (1024, 2048))):
+    """Line sweeps against the multigrid V-cycle where iterations are many:
+    the steady potential of the coupled system (a Poisson problem with the
+    doping as its source, solved from zero to a scaled tolerance of 1e-10)
+    and one cold continuity level of the headline problem (Crank-Nicolson,
+    dt = 2.5e-4, from the initial state with no earlier levels to guess
+    from, tolerance 3e-12): iterations, wall time of the solve (plans and
+    levels built by an untimed first solve) and the largest difference
+    between the two solutions."""
+    import torch
+    from problems import sample, two_carrier
+    from problems.workloads import cfg3_problem
+    out = {}
+
+    def run(inst, u0, td, kind):
+        pdk.set_preconditioner(inst, kind)
+        inst.set_solution(u0, 0.0)
+        inst.solve(td)                       # untimed: plans, graphs, multigrid levels
+        inst.set_solution(u0, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = inst.solve(td)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0), sum(s["iters"] for s in st), inst.solution()
+
+    for m, n in sizes:
+        md = pdk.mesh_desc(m, n, pdk.MESH_SINE, 1.3)
+        coords = pdk.mesh_coords(md)
+        cases = [("poisson", sample(two_carrier(3200)[0], *coords),
+                  pdk.time_desc(1.0, 1, table=[0.0, 1e30], tol=1e-10))]
+        if (m, n) == (1024, 2048):
+            cases.append(("cold_level", sample(cfg3_problem(), *coords),
+                          pdk.time_desc(0.5, 1, 2.5e-4, pdk.TIME_UNIFORM, tol=3e-12)))
+        for name, data, td in cases:
+            inst = pdk.Instance(md, data, pdk.PD_FP64, stream=stream)
+            u0 = ring_u0(data)
+            rl = run(inst, u0, td, pdk.PRECOND_LINE)
+            rm = run(inst, u0, td, pdk.PRECOND_MG)
+            inst.close()
+            out[f"{name}_{m}x{n}"] = {
+                "line": {"ms": round(rl[0], 2), "iters": rl[1]},
+                "multigrid": {"ms": round(rm[0], 2), "iters": rm[1]},
+                "speedup": round(rl[0] / rm[0], 2),
+                "max_rel_difference": float(np.max(np.abs(rl[2] - rm[2])) / np.max(np.abs(rl[2])))}
     return out
 
 
@@ -854,6 +916,8 @@ def main():
         var["fig_sweeps"] = fig_sweeps_variant(pdk, stream)
         log("two carriers with Gummel coupling ...")
         var["gummel_2carrier"] = gummel_variant(pdk, stream)
+        log("multigrid against the line sweeps ...")
+        var["multigrid"] = multigrid_variant(pdk, stream)
         log("uneven batch of 512 ...")
         var["uneven_512"] = uneven_variant(pdk, stream, 4e-12)
         log(f"serving stream ({args.serving_seconds:g} s) ...")

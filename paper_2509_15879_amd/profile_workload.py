@@ -3,8 +3,9 @@
     python -m paper_2509_15879_amd.profile_workload [--workload W] [--levels L] [--copy-mib M]
 
 Advances the workload (cfg3: the 1024 x 2048 continuity instance of the
-headline; cfg2: the ten 256 x 512 continuity instances) through its first L
-time levels with plain kernel launches (no captured graphs, so every
+headline; cfg2: the ten 256 x 512 continuity instances; poisson: the steady
+potential of the coupled system on the 1024 x 2048 mesh, one level from
+zero) through its first L time levels with plain kernel launches (no captured graphs, so every
 dispatch is counted on its own), then copies an M MiB device buffer, filled
 and then pushed out of the caches, once with torch: a kernel that reads and
 writes exactly M MiB, against which the profiler's byte counters are
@@ -25,7 +26,8 @@ def main():
     ap.add_argument("--levels", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--workload", choices=["cfg3", "cfg2"], default="cfg3")
+    ap.add_argument("--workload", choices=["cfg3", "cfg2", "poisson"], default="cfg3")
+    ap.add_argument("--precond", choices=["line", "mg"], default="line")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--schedule", default=None,
                     help="groups,cycles_per_graph,stencil_rings of the run (e.g. the one bench.py tuned)")
@@ -43,7 +45,15 @@ def main():
         pdk.set_schedule(*(int(v) for v in args.schedule.split(",")))
     prec = pdk.PD_MIXED if args.precision == "mixed" else pdk.PD_FP64
     insts, descs = [], []
-    if args.workload == "cfg2":
+    if args.workload == "poisson":
+        from problems import two_carrier
+        c = CFG3
+        tol = args.tol or 1e-10
+        md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
+        insts.append(pdk.Instance(md, sample(two_carrier(3200)[0], *pdk.mesh_coords(md)), pdk.PD_FP64,
+                                  stream=stream))
+        descs.append(pdk.time_desc(1.0, 1, table=[0.0, 1e30], tol=tol))
+    elif args.workload == "cfg2":
         c = CFG2
         tol = args.tol or 4e-12
         for seed, th, pb in cfg2_batch():
@@ -56,9 +66,12 @@ def main():
         md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
         insts.append(pdk.Instance(md, sample(cfg3_problem(), *pdk.mesh_coords(md)), prec, stream=stream))
         descs.append(pdk.time_desc(c["theta"], c["K"], c["dt"] * c["K"], pdk.TIME_UNIFORM, tol=tol))
-    print(f"[profile] {args.workload}: {len(insts)} instances, {args.levels} levels", flush=True)
-    t = pdk.time_levels(descs[0])[:args.levels + 1]
-    descs = [pdk.time_desc(d.theta, args.levels, table=t, tol=tol) for d in descs]
+    for i in insts:
+        pdk.set_preconditioner(i, pdk.PRECOND_MG if args.precond == "mg" else pdk.PRECOND_LINE)
+    print(f"[profile] {args.workload}: {len(insts)} instances, {args.levels} levels, {args.precond}", flush=True)
+    if args.workload != "poisson":
+        t = pdk.time_levels(descs[0])[:args.levels + 1]
+        descs = [pdk.time_desc(d.theta, args.levels, table=t, tol=tol) for d in descs]
     stats = pdk.solve_batch(insts, descs)
     torch.cuda.synchronize()
     print("[profile] iterations per level:", [[s["iters"] for s in st] for st in stats], flush=True)
