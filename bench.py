@@ -53,9 +53,9 @@ KERNEL_NAMES = {
 # any other source reports traffic null.
 TRAFFIC = {
     "cfg3_fp64": {
-        "sha1": "1481a724b5bd5c2f2ca7468ceee97d62293e7e11",
+        "sha1": "e9b97d6420dcaaa763ad63dd1c7672aa72eb44f1",
         "stencil_rings": 8,
-        "b_per_cell": {"rad_p": 53.03, "ang_p": 32.23, "sten_v": 65.0, "rad_s": 44.16, "ang_s": 32.23,
+        "b_per_cell": {"rad_p": 53.0, "ang_p": 32.23, "sten_v": 65.05, "rad_s": 44.16, "ang_s": 32.23,
                        "sten_t": 64.84, "update": 64.35},
     },
 }
