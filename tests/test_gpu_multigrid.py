@@ -72,6 +72,36 @@ def test_vcycle_with_zero_flux_boundary():
     inst.close()
 
 
+@pytest.mark.parametrize("form", ["reaction", "printed"])
+def test_vcycle_with_a_reaction_term(form):
+    """Levels that carry a reaction (volume-averaged when lines merge; the
+    origin's is kept): a parabolic problem with b(r, θ), and the printed
+    Ch. 3 stencil, whose diagonal beyond its faces is held as a reaction,
+    on the angular and radial stretches (C15)."""
+    from paper_2509_15879_amd import polardisk as pdk
+    from oracle import assemble_literal
+    from problems import paper_continuity_ex1
+    from problems.manufactured import random_positive
+    m, n = 26, 70
+    say(f"[mg] {m}x{n} {form}: GPU V-cycle vs oracle")
+    if form == "reaction":
+        pb, rk, p, tk, q, flux = random_positive(7150, pde=0), 1, 1.3, 0, 1.0, 0
+    else:
+        pb, rk, p, tk, q, flux = paper_continuity_ex1(), 1, 0.5, 1, 1.9, pdk.FLUX_LITERAL
+    me = make_mesh(m, n, rk, p, tk, q)
+    od = sample(pb, *me.sample_points())
+    S = assemble_literal(me, od) if form == "printed" else assemble(me, od)
+    md = pdk.mesh_desc(m, n, rk, p, tk, q)
+    inst = pdk.Instance(md, sample(pb, *pdk.mesh_coords(md)), pdk.PD_FP64, flux=flux)
+    pdk.set_preconditioner(inst, pdk.PRECOND_MG)
+    MG = MultigridPreconditioner(S, 2e-3, 0.5)
+    y = np.random.default_rng(5).standard_normal(S.N)
+    err = max_rel(inst.precondition(y, 2e-3, 0.5, layout=pdk.LAYOUT_PAPER), MG(y))
+    say(f"  levels {[lv.n for lv in MG.levels]}, max-rel {err:.2e}")
+    assert err <= 1e-6
+    inst.close()
+
+
 @pytest.mark.parametrize("theta", [0.5, 1.0])
 def test_solve_matches_the_oracle_with_fewer_iterations(theta):
     """A graded continuity solve (sine-stretched levels) with the V-cycle
