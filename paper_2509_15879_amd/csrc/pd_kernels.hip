@@ -3261,8 +3261,7 @@ static void rad(const LaunchSet &L, hipStream_t s, int fam_as = -1) {
     PD_DISPATCH_BM(L.max_brs[1], (go(fam, k_rad<T, MODE, BM, 1024, 16>, g1(L.nb_rs[1]), dim3(1024), s, L.insts, L.map_rs[1])));
   }
   if (L.nb_rs[2]) {
-    PD_DISPATCH_BM(L.max_brs[2], (go(fam, k_rad<T, MODE, BM, PD_RAD2_NT, PD_RAD2_CW>, g1(L.nb_rs[2]), dim3(PD_RAD2_NT), s,
-                                     L.insts, L.map_rs[2])));
+    PD_DISPATCH_BM(L.max_brs[2], (go(fam, k_rad<T, MODE, BM, 1024, 8>, g1(L.nb_rs[2]), dim3(1024), s, L.insts, L.map_rs[2])));
   }
 }
 template <typename T, int MODE>

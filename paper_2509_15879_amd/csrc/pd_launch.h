@@ -59,14 +59,8 @@ struct MgSet {
 // above, 1024-thread blocks of 8 columns x 128 segments, whose segments stay
 // short enough for registers and which give twice the blocks.
 inline int rad_class(int m) { return m <= 256 ? 0 : (m <= 512 ? 1 : 2); }
-#ifndef PD_RAD2_NT
-#define PD_RAD2_NT 1024   // threads of a class-2 block (PD_RAD2_NT / PD_RAD2_CW segments)
-#endif
-#ifndef PD_RAD2_CW
-#define PD_RAD2_CW 8      // columns of a class-2 block
-#endif
-inline int rad_threads_of(int c) { return c == 0 ? 512 : (c == 2 ? PD_RAD2_NT : 1024); }
-inline int rad_cols_of(int c) { return c == 2 ? PD_RAD2_CW : 16; }
+inline int rad_threads_of(int c) { return c == 0 ? 512 : 1024; }
+inline int rad_cols_of(int c) { return c == 2 ? 8 : 16; }
 inline int rad_rows(int m) {
   const int c = rad_class(m), seg = rad_threads_of(c) / rad_cols_of(c);
   return (m + seg - 1) / seg;
