@@ -471,10 +471,12 @@ int pd_batch_destroy(pd_batch *batch);
  *     iterations per iteration and pays where iterations are many: cold
  *     starts, large steps, steady problems (the potential of
  *     pd_gummel_step is solved with it when its instance has it).
- * The multigrid preconditioner takes FP64 instances, solved on their own
- * (a batch holding one fails with PD_EINVAL); its levels (about 150 bytes
- * per unknown) are allocated by the instance's next solve that needs them
- * and kept until PD_PRECOND_LINE is set again or the instance is destroyed.
+ * The multigrid preconditioner takes FP64 instances.  They batch with other
+ * FP64 instances (each V-cycle runs after the batch's own sweeps in every
+ * Krylov iteration); a batch that also holds a mixed-precision instance
+ * fails with PD_EINVAL.  Its levels (about 150 bytes per unknown) are
+ * allocated by the instance's next solve that needs them and kept until
+ * PD_PRECOND_LINE is set again or the instance is destroyed.
  * Solutions agree with either preconditioner to the solve's tolerance.
  * PD_EINVAL: unknown kind, or PD_PRECOND_MG on a mixed-precision instance;
  * PD_EBUSY while the instance is in use.                                  */

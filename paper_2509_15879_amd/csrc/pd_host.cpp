@@ -513,6 +513,7 @@ EventTimer *g_event_timer = nullptr;
 // allocating or freeing device memory (hipFree waits for the whole device).
 struct Plan {
   pd::LaunchSet L;
+  std::vector<const pd::MgSet *> mg;   // L.mg: the multigrid sets of its instances
   char *dbuf = nullptr, *hbuf = nullptr;   // device data and its pinned staging
   size_t cap = 0;
   int *n_active = nullptr;
@@ -897,6 +898,25 @@ int mg_prepare(pd_instance *I, hipStream_t s, const pd::MgSet **out) {
   return PD_OK;
 }
 
+// The V-cycles of a plan's multigrid instances (built or refreshed for
+// this solve).  They batch with FP64 instances only.
+int attach_mg(std::vector<pd_instance *> const &part, hipStream_t s, Plan &P) {
+  P.mg.clear();
+  bool mixed = false;
+  for (auto *I : part) mixed |= I->precision == PD_MIXED;
+  for (auto *I : part) {
+    if (I->precond != PD_PRECOND_MG) continue;
+    if (mixed) return fail(PD_EINVAL, "a multigrid instance batches with FP64 instances only");
+    const pd::MgSet *ms = nullptr;
+    int rc = mg_prepare(I, s, &ms);
+    if (rc) return rc;
+    P.mg.push_back(ms);
+  }
+  P.L.mg = P.mg.empty() ? nullptr : P.mg.data();
+  P.L.nmg = (int)P.mg.size();
+  return PD_OK;
+}
+
 struct SolveParams {
   double theta, tol, tol_inner;
   int maxit, maxit_inner, max_outer;
@@ -1064,16 +1084,7 @@ struct Engine {
       }
       int rc = make_plan(part, g.s, *g.P, rings);
       if (rc) return rc;
-      // a multigrid instance is solved on its own (its V-cycle launches are
-      // the plan's only instance's)
-      for (auto *I : part) {
-        if (I->precond != PD_PRECOND_MG) continue;
-        if (part.size() != 1)
-          return fail(PD_EINVAL, "an instance with the multigrid preconditioner is solved on its own");
-        const pd::MgSet *ms = nullptr;
-        if ((rc = mg_prepare(I, g.s, &ms))) return rc;
-        g.P->L.mg = ms;
-      }
+      if ((rc = attach_mg(part, g.s, *g.P))) return rc;
       g.P->L.adaptive_any = adaptive ? 1 : 0;
       // every member still has levels to take
       HIPCHK(hipMemsetD32Async((hipDeviceptr_t)g.P->n_active, (int)part.size(), 1, g.s));
@@ -2147,16 +2158,7 @@ int pd_gummel_step(pd_instance *psi, pd_instance *ne, pd_instance *pe, double t_
       C->have_prev = false;
     }
     std::vector<std::vector<double>> sc(2);
-    if (ne->precond == PD_PRECOND_MG || pe->precond == PD_PRECOND_MG) {
-      // a multigrid instance is solved on its own
-      std::vector<std::vector<double>> one(1);
-      if ((rc = solve_many({ne}, {&tdc}, &one))) return rc;
-      sc[0] = one[0];
-      if ((rc = solve_many({pe}, {&tdc}, &one))) return rc;
-      sc[1] = one[0];
-    } else if ((rc = solve_many({ne, pe}, {&tdc, &tdc}, &sc))) {
-      return rc;
-    }
+    if ((rc = solve_many({ne, pe}, {&tdc, &tdc}, &sc))) return rc;
     krylov += (int)sc[0][0] + (int)sc[1][0];
     if (it >= 1 && change <= gummel_tol) {
       ++it;
@@ -2194,11 +2196,7 @@ int pd_apply_preconditioner(pd_instance *I, double dt, double theta, const doubl
   HIPCHK(hipMemcpyAsync(I->t_table, tab, sizeof tab, hipMemcpyHostToDevice, s));
   Plan P;
   if ((rc = make_plan({I}, s, P))) return rc;
-  if (I->precond == PD_PRECOND_MG) {
-    const pd::MgSet *ms = nullptr;
-    if ((rc = mg_prepare(I, s, &ms))) return rc;
-    P.L.mg = ms;
-  }
+  if ((rc = attach_mg({I}, s, P))) return rc;
   SolveParams sp{theta, 1e-300, 1e-3, 1, 1, 1};
   if ((rc = init_scalars(I, sp, 1, s))) return rc;
   pd::launch_level_begin(P.L, s);

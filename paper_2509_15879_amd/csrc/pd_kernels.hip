@@ -3240,8 +3240,8 @@ void launch_factor(const LaunchSet &L, hipStream_t s) {
     PD_DISPATCH_BM(L.max_bang, (go(KF_FACTOR, k_fact_ang<BM>, g1(L.nb_ang), dim3(256), s, L.insts, L.map_ang)));
   // the coarse levels of a multigrid preconditioner factor their own lines
   // (gated, like the instance's, on the instance starting a level)
-  if (L.mg)
-    for (int l = 1; l <= L.mg->nlev; ++l) launch_factor(L.mg->lev[l], s);
+  for (int q = 0; q < L.nmg; ++q)
+    for (int l = 1; l <= L.mg[q]->nlev; ++l) launch_factor(L.mg[q]->lev[l], s);
 }
 void launch_begin(const LaunchSet &L, hipStream_t s) {
   go(KF_BEGIN, k_sten<double, SM_GRAM>, g1(L.nb_sten), dim3(256), s, L.insts, L.map_sten, 0.0, 0.0,
@@ -3298,17 +3298,17 @@ static void mg_vcycle(const MgSet &M, const double *y, double *z, hipStream_t s)
   go(KF_MG, k_mg_fin, g1((m * M.n[0] + 1 + 255) / 256), dim3(256), s, M.sc, dl, L, (const double *)M.cring, z);
 }
 
-// A Krylov iteration preconditioned by the V-cycle (one FP64 instance): the
-// instance's sweeps give level 0's pre-smoothing, the V-cycle the rest.
+// A Krylov iteration of an FP64 batch in which some instances use the
+// V-cycle: the batch's sweeps give their level 0's pre-smoothing (and are
+// the whole preconditioner of the others), each V-cycle the rest.
 static void cycle_mg(const LaunchSet &L, hipStream_t s) {
-  const MgSet &M = *L.mg;
   rad<double, RM_P>(L, s);
   ang<double, AM_P>(L, s);
-  mg_vcycle(M, M.p, M.ph, s);
+  for (int q = 0; q < L.nmg; ++q) mg_vcycle(*L.mg[q], L.mg[q]->p, L.mg[q]->ph, s);
   sten<double, SM_V>(KF_STEN_V, L, s);
   rad<double, RM_S>(L, s);
   ang<double, AM_S>(L, s);
-  mg_vcycle(M, M.s, M.sh, s);
+  for (int q = 0; q < L.nmg; ++q) mg_vcycle(*L.mg[q], L.mg[q]->s, L.mg[q]->sh, s);
   sten<double, SM_T>(KF_STEN_T, L, s);
   go(KF_UPDATE, k_elem_x<double>, g1(L.nb_elem), dim3(256), s, L.insts, L.map_elem);
 }
@@ -3359,12 +3359,12 @@ void launch_precond_apply(const LaunchSet &L, int fp32, hipStream_t s) {
   } else {
     rad<double, RM_Y>(L, s);
     ang<double, AM_P>(L, s);
-    if (L.mg) mg_vcycle(*L.mg, L.mg->r, L.mg->ph, s);
+    for (int q = 0; q < L.nmg; ++q) mg_vcycle(*L.mg[q], L.mg[q]->r, L.mg[q]->ph, s);
   }
 }
 
 void launch_cycle(const LaunchSet &L, hipStream_t s) {
-  if (L.mg) {   // one FP64 instance
+  if (L.nmg) {   // an FP64 batch
     cycle_mg(L, s);
     return;
   }

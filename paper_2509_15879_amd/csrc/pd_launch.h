@@ -31,8 +31,10 @@ struct LaunchSet {
   int2 *map_rs[3] = {nullptr, nullptr, nullptr};
   int nb_rs[3] = {0, 0, 0};
   int max_brs[3] = {1, 1, 1};       // longest radial segment per class
-  // the multigrid preconditioner of the plan's one instance, or null
-  const MgSet *mg = nullptr;
+  // the multigrid preconditioners of the plan's instances that use one
+  // (then every instance of the plan is FP64)
+  const MgSet *const *mg = nullptr;
+  int nmg = 0;
 };
 
 // Launches of a θ-semi-coarsening V-cycle (PdMgLevel) for one FP64

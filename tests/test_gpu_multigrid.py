@@ -165,9 +165,12 @@ def test_gummel_step_in_a_fraction_of_the_iterations():
     assert kry[pdk.PRECOND_MG] * 4 <= kry[pdk.PRECOND_LINE]
 
 
-def test_refused_settings():
+def test_refused_settings_and_batches():
+    """Multigrid instances batch with FP64 instances (each keeps its own
+    result: the same as solving it alone) and are refused next to a
+    mixed-precision one; mixed precision and unknown kinds are refused."""
     from paper_2509_15879_amd import polardisk as pdk
-    say("[mg] refused: mixed precision, an unknown kind, a batch holding a multigrid instance")
+    say("[mg] batches with FP64 instances; refused: mixed precision, an unknown kind")
     pb = continuity_cfg(7140, 16, 40)
     md = pdk.mesh_desc(16, 40)
     data = sample(pb, *pdk.mesh_coords(md))
@@ -176,14 +179,32 @@ def test_refused_settings():
         pdk.set_preconditioner(mixed, pdk.PRECOND_MG)
     with pytest.raises(pdk.PolarDiskError, match="unknown preconditioner"):
         pdk.set_preconditioner(mixed, 7)
-    a, b = pdk.Instance(md, data, pdk.PD_FP64), pdk.Instance(md, data, pdk.PD_FP64)
+    a, b, c = (pdk.Instance(md, data, pdk.PD_FP64) for _ in range(3))
     pdk.set_preconditioner(a, pdk.PRECOND_MG)
-    td = pdk.time_desc(0.5, 2, 0.01, pdk.TIME_UNIFORM, tol=1e-10)
-    with pytest.raises(pdk.PolarDiskError, match="solved on its own"):
-        pdk.solve_batch([a, b], [td, td])
-    # back to the line sweeps, the batch solves
+    pdk.set_preconditioner(c, pdk.PRECOND_MG)
+    td = pdk.time_desc(0.5, 3, 0.01, pdk.TIME_UNIFORM, tol=1e-12)
+    with pytest.raises(pdk.PolarDiskError, match="FP64 instances only"):
+        pdk.solve_batch([a, mixed], [td, td])
+    # a batch of a multigrid, a line and a multigrid instance; each result
+    # equals the same instance solved alone with its own preconditioner
+    for i in (a, b, c):
+        i.set_solution(pdk.ring_vector(data["u0_origin"], data["u0_grid"]), 0.0)
+    st = pdk.solve_batch([a, b, c], [td, td, td])
+    alone = []
+    for kind in (pdk.PRECOND_MG, pdk.PRECOND_LINE):
+        d = pdk.Instance(md, data, pdk.PD_FP64)
+        pdk.set_preconditioner(d, kind)
+        d.solve(td)
+        alone.append(d.solution())
+        d.close()
+    say(f"  batched iterations {[[s['iters'] for s in x] for x in st]}")
+    assert np.array_equal(a.solution(), alone[0]) and np.array_equal(c.solution(), alone[0])
+    assert np.array_equal(b.solution(), alone[1])
+    assert sum(s["iters"] for s in st[0]) < sum(s["iters"] for s in st[1])
+    # back to the line sweeps
     pdk.set_preconditioner(a, pdk.PRECOND_LINE)
-    pdk.solve_batch([a, b], [td, td])
-    assert np.array_equal(a.solution(), b.solution())
-    for i in (mixed, a, b):
+    a.set_solution(pdk.ring_vector(data["u0_origin"], data["u0_grid"]), 0.0)
+    a.solve(td)
+    assert np.array_equal(a.solution(), alone[1])
+    for i in (mixed, a, b, c):
         i.close()
