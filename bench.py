@@ -59,10 +59,10 @@ KERNEL_NAMES = {
 # any other source reports traffic null.
 TRAFFIC = {
     "cfg3_fp64": {
-        "sha1": "e9b97d6420dcaaa763ad63dd1c7672aa72eb44f1",
+        "sha1": "6bc4b8abe6894ef49f1ea3b4c1e356097a1a2160",
         "stencil_rings": 8,
-        "b_per_cell": {"rad_p": 53.0, "ang_p": 32.23, "sten_v": 65.05, "rad_s": 44.16, "ang_s": 32.23,
-                       "sten_t": 64.84, "update": 64.35},
+        "b_per_cell": {"rad_p": 52.95, "ang_p": 32.23, "sten_v": 65.13, "rad_s": 44.16, "ang_s": 32.23,
+                       "sten_t": 64.88, "update": 64.34},
     },
 }
 

@@ -1927,10 +1927,14 @@ __device__ __forceinline__ double mg_apply(const PdMgLevel &L, int i, int j, dou
                                            double x0) {
   const int n = L.n, m = L.m, row = (i - 1) * n;
   const int jl = j == 0 ? n - 1 : j - 1, jr = j == n - 1 ? 0 : j + 1;
+  // every neighbour is loaded (rows clamped into the mesh) and the origin
+  // and the boundary selected afterwards: a load under a per-lane condition
+  // becomes a branch that waits for it
   const double xc = x(i, j);
-  const double xi = i == 1 ? x0 : x(i - 1, j);
-  const double xo = i == m ? 0.0 : x(i + 1, j);
+  const double xiv = x(max(i - 1, 1), j), xov = x(min(i + 1, m), j);
   const double xl = x(i, jl), xr = x(i, jr);
+  const double xi = i == 1 ? x0 : xiv;
+  const double xo = i == m ? 0.0 : xov;
   const double fo = L.gp_r[i * n + j] * xc - L.gm_r[i * n + j] * xo;
   const double fi = L.gp_r[row + j] * xi - L.gm_r[row + j] * xc;
   const double fu = L.gp_t[row + j] * xc - L.gm_t[row + j] * xr;
@@ -2028,11 +2032,14 @@ __global__ __launch_bounds__(256) void k_mg_down(const PdScalars *sc, const PdMg
   if (gid >= m * nc) return;
   const int i = gid / nc + 1, J = gid % nc;
   const int j0 = 2 * J, cnt = J == nc - 1 ? nf - j0 : 2;
+  // three fine lines at most, all loaded (the third clamped) and masked
   double f = 0.0;
-  for (int k = 0; k < cnt; ++k) {
-    const int j = j0 + k, idx = (i - 1) * nf + j;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int j = j0 + min(k, cnt - 1), idx = (i - 1) * nf + j;
     const double g = top ? Fl.diag[idx] * y[idx] : Fl.g[idx];
-    f += (g - mg_apply(Fl, i, j, inv_dt, th, xv, x0)) / (Fl.inv_rw[i] * Fl.inv_dth[j]);
+    const double v = (g - mg_apply(Fl, i, j, inv_dt, th, xv, x0)) / (Fl.inv_rw[i] * Fl.inv_dth[j]);
+    f += k < cnt ? v : 0.0;
   }
   const int cidx = (i - 1) * nc + J;
   const double gc = f * (Cl.inv_rw[i] * Cl.inv_dth[J]);
