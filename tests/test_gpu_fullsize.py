@@ -31,13 +31,14 @@ def metrics(x, ref, level):
     return float(np.max(np.abs(d)) / float(ref[f"maxabs_{level}"])), float(np.linalg.norm(d) / np.linalg.norm(xr))
 
 
-def solve(precision, tol, K, schedule=(1, 8, 4)):
+def solve(precision, tol, K, schedule=(1, 8, 4), precond=0):
     from paper_2509_15879_amd import polardisk as pdk
     from problems import sample
     from problems.workloads import CFG3, cfg3_problem
     c = CFG3
     md = pdk.mesh_desc(c["m"], c["n"], pdk.MESH_SINE, c["p"])
     inst = pdk.Instance(md, sample(cfg3_problem(), *pdk.mesh_coords(md)), precision)
+    pdk.set_preconditioner(inst, precond)
     old = pdk.get_schedule()
     pdk.set_schedule(*schedule)
     try:
@@ -56,6 +57,20 @@ def test_headline_configuration_meets_the_metric_bar(level):
     say(f"[full size] FP64, tol 3e-12, {level} levels vs the oracle's samples")
     ref = reference()
     x, it = solve(0, 3e-12, level)
+    mr, l2 = metrics(x, ref, level)
+    say(f"  iters/level {it:.2f}, max-rel {mr:.3e}, l2-rel {l2:.3e}")
+    assert l2 <= 1e-8 and mr <= 1e-7
+
+
+@pytest.mark.parametrize("level", [20, 200])
+def test_multigrid_preconditioner_meets_the_metric_bar(level):
+    """FP64 with the θ-semi-coarsening V-cycle (eight coarse levels down to 8
+    lines, then the ring means) at the benchmark's tolerance: the same bar
+    against the oracle as the line sweeps."""
+    from paper_2509_15879_amd import polardisk as pdk
+    say(f"[full size] FP64 with the multigrid V-cycle, tol 3e-12, {level} levels vs the oracle's samples")
+    ref = reference()
+    x, it = solve(0, 3e-12, level, schedule=(1, 8, 8), precond=pdk.PRECOND_MG)
     mr, l2 = metrics(x, ref, level)
     say(f"  iters/level {it:.2f}, max-rel {mr:.3e}, l2-rel {l2:.3e}")
     assert l2 <= 1e-8 and mr <= 1e-7
