@@ -347,7 +347,8 @@ def fig_sweeps_variant(pdk, stream):
     from problems.workloads import FIG_EXAMPLES, FIG_SWEEPS, fig_sweep_runs
     with open(os.path.join(ROOT, "tests", "golden", "fig_sweeps.json")) as f:
         golden = json.load(f)["figures"]
-    pbs = {"ch2_ex1": paper_parabolic_ex1(), "ch3_ex1": paper_continuity_ex1()}
+    by_problem = {"ch2": paper_parabolic_ex1(), "ch3": paper_continuity_ex1()}
+    pbs = {k: by_problem[e["problem"]] for k, e in FIG_EXAMPLES.items()}
     runs = fig_sweep_runs()
     insts, tds, coords = [], [], []
     for fig, m, n, prm in runs:
@@ -385,13 +386,15 @@ def fig_sweeps_variant(pdk, stream):
     cells = sum(i.N for i in insts)
     for i in insts:
         i.close()
-    return {"workload": ("Figs 2.9-2.11 and 3.5-3.8 parameter sweeps: 250 runs, m 19..99, n floor(2 pi m), "
-                         "Ch. 2 example 1 (5 levels) and Ch. 3 example 1 with the printed stencil (10 levels), "
-                         "theta 0.5..1"),
+    return {"workload": (f"Figs 2.2, 2.5-2.7, 2.9-2.11 and 3.5-3.8 parameter sweeps: {len(runs)} runs, m 19..99, "
+                         "n floor(2 pi m), Ch. 2 example 1 (5 or 10 levels; stretch (2.4) or (2.13)) and Ch. 3 "
+                         "example 1 with the printed stencil (10 levels), theta 0.5..1"),
             "instances": len(runs), "cells": cells, "ms": round(1e3 * el, 2),
             "value": round(cell_updates / el, 1),
             "best_value_per_figure": {f: {"vary": FIG_SWEEPS[f]["vary"], "by_m": b} for f, b in best.items()},
-            "paper_states": {"fig_2_9": "p ~ 1.1", "fig_2_10": "p ~ 1.1", "fig_2_11": "a ~ 0.4 (dt 0.02)",
+            "paper_states": {"fig_2_2": "p~ ~ 0.6 (stretch (2.13))", "fig_2_5": "p ~ 1.1", "fig_2_6": "p ~ 1.1",
+                             "fig_2_7": "a towards 0.5 (smaller dt)",
+                             "fig_2_9": "p ~ 1.1", "fig_2_10": "p ~ 1.1", "fig_2_11": "a ~ 0.4 (dt 0.02)",
                              "fig_3_5": "p ~ 0.1", "fig_3_6": "q ~ 1.9", "fig_3_7": "l ~ 1.5",
                              "fig_3_8": "a ~ 0.5"},
             "max_rel_error_deviation_vs_oracle_table": dev}

@@ -116,6 +116,15 @@ def cfg5_arrivals(duration, rate=None, seed=None):
 FIG_SWEEP_M = (19, 39, 59, 79, 99)
 _P2 = (0.6, 0.8, 0.9, 1.0, 1.1, 1.2, 1.3, 1.5, 1.8)
 FIG_SWEEPS = {
+    # Ch. 2: Fig 2.2 sweeps the parameter p~ of the stretch (2.13) (a = 0.4,
+    # Δt = 0.01, as Table 2.1); Figs 2.5-2.7 (their captions lost the
+    # parameters) are read as the Δt = 0.01 counterparts of Figs 2.9-2.11
+    "fig_2_2": dict(example="ch2_ex1_213", vary="p", values=(0.2, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0),
+                    fixed=dict(q=1.0, l=1.0, a=0.4)),
+    "fig_2_5": dict(example="ch2_ex1_dt01", vary="p", values=_P2, fixed=dict(q=1.0, l=1.0, a=0.4)),
+    "fig_2_6": dict(example="ch2_ex1_dt01", vary="p", values=_P2, fixed=dict(q=1.0, l=1.0, a=0.5)),
+    "fig_2_7": dict(example="ch2_ex1_dt01", vary="a", values=(0.0, 0.1, 0.2, 0.3, 0.4, 0.45, 0.5),
+                    fixed=dict(p=1.1, q=1.0, l=1.0)),
     "fig_2_9": dict(example="ch2_ex1", vary="p", values=_P2, fixed=dict(q=1.0, l=1.0, a=0.4)),
     "fig_2_10": dict(example="ch2_ex1", vary="p", values=_P2, fixed=dict(q=1.0, l=1.0, a=0.5)),
     "fig_2_11": dict(example="ch2_ex1", vary="a", values=(0.0, 0.1, 0.2, 0.3, 0.4, 0.45, 0.5),
@@ -130,9 +139,14 @@ FIG_SWEEPS = {
                     fixed=dict(p=0.1, q=1.9, l=1.5)),
 }
 FIG_EXAMPLES = {
-    # radial kind, angular kind (1: stretched with q), time kind (1: stretched with l), levels, T
-    "ch2_ex1": dict(r_kind=1, th_kind=0, t_kind=0, K=5, T=0.1, error="max", literal=False),
-    "ch3_ex1": dict(r_kind=1, th_kind=1, t_kind=1, K=10, T=0.1, error="mean", literal=True),
+    # problem (the paper's numerical experiment 1 of Ch. 2 or of Ch. 3),
+    # radial kind (1: the stretch (2.4) with p; 3: the stretch (2.13) with
+    # p~), angular kind (1: stretched with q), time kind (1: stretched with
+    # l), levels, T
+    "ch2_ex1": dict(problem="ch2", r_kind=1, th_kind=0, t_kind=0, K=5, T=0.1, error="max", literal=False),
+    "ch2_ex1_dt01": dict(problem="ch2", r_kind=1, th_kind=0, t_kind=0, K=10, T=0.1, error="max", literal=False),
+    "ch2_ex1_213": dict(problem="ch2", r_kind=3, th_kind=0, t_kind=0, K=10, T=0.1, error="max", literal=False),
+    "ch3_ex1": dict(problem="ch3", r_kind=1, th_kind=1, t_kind=1, K=10, T=0.1, error="mean", literal=True),
 }
 
 

@@ -65,7 +65,8 @@ def hip_runtime():
 
 def fig_problem(example):
     from problems import paper_continuity_ex1, paper_parabolic_ex1
-    return paper_parabolic_ex1() if example == "ch2_ex1" else paper_continuity_ex1()
+    from problems.workloads import FIG_EXAMPLES
+    return paper_parabolic_ex1() if FIG_EXAMPLES[example]["problem"] == "ch2" else paper_continuity_ex1()
 
 
 def fig_errors(x, pb, T, r_nodes, th_nodes):

@@ -1,10 +1,10 @@
-"""The parameter sweeps of the paper's Figs 2.9-2.11 (Ch. 2 §2.3) and
-Figs 3.5-3.8 (Ch. 3 §3.3, printed stencil) on the GPU: every run of the
-seven sweeps at m = 19 and 39 (100 instances of uneven size, both
-examples, θ from 0.5 to 1) is solved as one batch, each run's state is
-held against the oracle element by element, its errors against the
-oracle's stored sweep table, and each sweep's optimum against the
-table's."""
+"""The parameter sweeps of the paper's Figs 2.2, 2.5-2.7, 2.9-2.11 (Ch. 2
+§2.3) and Figs 3.5-3.8 (Ch. 3 §3.3, printed stencil) on the GPU: every run
+of the eleven sweeps at m = 19 and 39 (164 instances of uneven size, both
+examples, both radial stretches, θ from 0.5 to 1) is solved as one batch,
+each run's state is held against the oracle element by element, its
+errors against the oracle's stored sweep table, and each sweep's optimum
+against the table's."""
 
 import json
 import os

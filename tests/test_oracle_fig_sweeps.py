@@ -1,15 +1,19 @@
 """Pins of the oracle by the parameter sweeps of the paper's figures
-(Figs 2.9-2.11 of Ch. 2 §2.3 and Figs 3.5-3.8 of Ch. 3 §3.3): the stored
-sweep table (tests/golden/fig_sweeps.json, written by the oracle) is the
-oracle's current output, and it shows what the paper reports of these
-figures: in Ch. 3 the mean error is smallest at q = 1.9 (Fig 3.6), l = 1.5
-(Fig 3.7) and a = 0.5 (Fig 3.8, after first rising with a), and a small p
-is best (Fig 3.5, about 0.1 on the paper's grid); in Ch. 2 the maximum
-error has an interior optimum in p (Figs 2.9-2.10) and every sweep
-converges as the mesh is refined.  A wrong exponent in the angular or time
-stretch moves these optima; the Ch. 2 optima themselves differ from the
-stated ones (p about 0.9 rather than 1.1, a = 0 rather than 0.4 at
-Δt = 0.02) and are not pinned."""
+(Figs 2.2, 2.5-2.7 and 2.9-2.11 of Ch. 2 §2.3 and Figs 3.5-3.8 of Ch. 3
+§3.3): the stored sweep table (tests/golden/fig_sweeps.json, written by the
+oracle) is the oracle's current output, and it shows what the paper reports
+of these figures: in Ch. 3 the mean error is smallest at q = 1.9 (Fig 3.6),
+l = 1.5 (Fig 3.7) and a = 0.5 (Fig 3.8, after first rising with a), and a
+small p is best (Fig 3.5, about 0.1 on the paper's grid); in Ch. 2 the
+maximum error has an interior optimum in p (Figs 2.5, 2.6, 2.9, 2.10), the
+best a moves up when the step shrinks (Fig 2.7 at Δt = 0.01 against Fig
+2.11 at Δt = 0.02, on the finest swept mesh) and every sweep converges as
+the mesh is refined.  A wrong exponent in the angular or time stretch
+moves these optima; the Ch. 2 optima themselves differ from the stated
+ones (p about 0.9 rather than 1.1; a = 0.45 rather than towards 0.5 at
+Δt = 0.01 and a = 0 rather than 0.4 at Δt = 0.02; for the stretch (2.13)
+of Fig 2.2 the error falls all the way to p~ = 1 rather than having its
+optimum near 0.6) and are not pinned."""
 
 import json
 import os
@@ -70,7 +74,21 @@ def test_ch3_small_p_is_best():
         assert err[v.index(0.1)] < err[v.index(0.2)] < err[v.index(0.4)]
 
 
-@pytest.mark.parametrize("fig", ["fig_2_9", "fig_2_10"])
+def test_ch2_best_a_moves_up_as_the_step_shrinks():
+    """Figs 2.7 (Δt = 0.01) and 2.11 (Δt = 0.02), p = 1.1: on the finest
+    swept mesh the smaller step's best a is larger, and there its error at
+    a = 0.45 is below the one at a = 0; at Δt = 0.02 the error only grows
+    with a."""
+    g = golden()
+    f7, f11 = g["fig_2_7"], g["fig_2_11"]
+    e7, e11 = f7["m"]["59"], f11["m"]["59"]
+    assert e7["argmin"] > e11["argmin"]
+    v = f7["values"]
+    assert e7["max"][v.index(0.45)] < e7["max"][v.index(0.0)]
+    assert all(a < b for a, b in zip(e11["max"], e11["max"][1:]))
+
+
+@pytest.mark.parametrize("fig", ["fig_2_5", "fig_2_6", "fig_2_9", "fig_2_10"])
 def test_ch2_interior_optimum_in_p(fig):
     f = golden()[fig]
     for m, e in f["m"].items():
