@@ -342,12 +342,12 @@ def fig_sweeps_variant(pdk, stream):
     relative deviation of the runs' errors from the oracle's stored sweep
     table (m = 19, 39, 59)."""
     import torch
-    from problems import paper_continuity_ex1, paper_parabolic_ex1, sample
+    from problems import paper_continuity_ex1, paper_continuity_ex2, paper_parabolic_ex1, sample
     from problems.manufactured import exact_at
     from problems.workloads import FIG_EXAMPLES, FIG_SWEEPS, fig_sweep_runs
     with open(os.path.join(ROOT, "tests", "golden", "fig_sweeps.json")) as f:
         golden = json.load(f)["figures"]
-    by_problem = {"ch2": paper_parabolic_ex1(), "ch3": paper_continuity_ex1()}
+    by_problem = {"ch2": paper_parabolic_ex1(), "ch3": paper_continuity_ex1(), "ch3_2": paper_continuity_ex2()}
     pbs = {k: by_problem[e["problem"]] for k, e in FIG_EXAMPLES.items()}
     runs = fig_sweep_runs()
     insts, tds, coords = [], [], []
@@ -386,9 +386,9 @@ def fig_sweeps_variant(pdk, stream):
     cells = sum(i.N for i in insts)
     for i in insts:
         i.close()
-    return {"workload": (f"Figs 2.2, 2.5-2.7, 2.9-2.11 and 3.5-3.8 parameter sweeps: {len(runs)} runs, m 19..99, "
-                         "n floor(2 pi m), Ch. 2 example 1 (5 or 10 levels; stretch (2.4) or (2.13)) and Ch. 3 "
-                         "example 1 with the printed stencil (10 levels), theta 0.5..1"),
+    return {"workload": (f"Figs 2.2, 2.5-2.7, 2.9-2.11, 3.5-3.8 and 3.12-3.15 parameter sweeps: {len(runs)} runs, "
+                         "m 19..99, n floor(2 pi m), Ch. 2 example 1 (5 or 10 levels; stretch (2.4) or (2.13)) and "
+                         "Ch. 3 examples 1 and 2 with the printed stencil (10 levels), theta 0.5..1"),
             "instances": len(runs), "cells": cells, "ms": round(1e3 * el, 2),
             "value": round(cell_updates / el, 1),
             "best_value_per_figure": {f: {"vary": FIG_SWEEPS[f]["vary"], "by_m": b} for f, b in best.items()},
@@ -396,7 +396,8 @@ def fig_sweeps_variant(pdk, stream):
                              "fig_2_7": "a towards 0.5 (smaller dt)",
                              "fig_2_9": "p ~ 1.1", "fig_2_10": "p ~ 1.1", "fig_2_11": "a ~ 0.4 (dt 0.02)",
                              "fig_3_5": "p ~ 0.1", "fig_3_6": "q ~ 1.9", "fig_3_7": "l ~ 1.5",
-                             "fig_3_8": "a ~ 0.5"},
+                             "fig_3_8": "a ~ 0.5", "fig_3_12": "p ~ 0.5", "fig_3_13": "q ~ 5",
+                             "fig_3_14": "l ~ 5", "fig_3_15": "a ~ 0.1"},
             "max_rel_error_deviation_vs_oracle_table": dev}
 
 

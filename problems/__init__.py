@@ -17,6 +17,7 @@ from .manufactured import (  # noqa: F401
     closed_form_quadratic,
     paper_parabolic_ex1,
     paper_continuity_ex1,
+    paper_continuity_ex2,
     random_positive,
     zero_flux_random,
     two_carrier,

@@ -237,6 +237,34 @@ def paper_continuity_ex1():
     )
 
 
+def paper_continuity_ex2():
+    """Ch. 3, numerical experiment 2: D = E = r, exact
+    n = e^{-t} r sin²θ + r (1 - r)^{1/2} + r sin²θ, boundary
+    e^{-t} sin²θ + sin²θ.
+
+    The source is the printed one, split as for experiment 1 into its
+    e^{-t} part, 2 r sin²θ - 2 sin²θ - 2 cos 2θ + r sin 2θ, and its
+    time-independent part, which is experiment 1's; the origin source is 0
+    (the exact solution vanishes there for all t).
+    """
+    def g_t(r, th):
+        s2 = np.sin(th) ** 2
+        return np.where(r > 0, 2.0 * r * s2 - 2.0 * s2 - 2.0 * np.cos(2 * th) + r * np.sin(2 * th), 0.0)
+
+    g_s = paper_continuity_ex1().modes[1].g
+    return Problem(
+        name="paper_continuity_ex2", pde=1,
+        modes=[TimeMode(-1.0, 0, g_t, lambda th: np.sin(th) ** 2),
+               TimeMode(0.0, 0, g_s, lambda th: np.sin(th) ** 2)],
+        u0=lambda r, th: 2.0 * r * np.sin(th) ** 2 + r * np.sqrt(1.0 - r),
+        D=lambda r, th: r + 0.0 * th,
+        Er=lambda r, th: r + 0.0 * th,
+        Et=lambda r, th: r + 0.0 * th,
+        E_scalar=lambda r, th: r + 0.0 * th,
+        exact=lambda t, r, th: (np.exp(-t) * r * np.sin(th) ** 2 + r * np.sqrt(1.0 - r) + r * np.sin(th) ** 2),
+    )
+
+
 # --------------------------------------------------------------- continuity
 
 def _per_ring(f, r):

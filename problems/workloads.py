@@ -137,9 +137,19 @@ FIG_SWEEPS = {
                     fixed=dict(p=0.1, q=1.9, a=0.5)),
     "fig_3_8": dict(example="ch3_ex1", vary="a", values=(0.0, 0.1, 0.2, 0.3, 0.4, 0.5),
                     fixed=dict(p=0.1, q=1.9, l=1.5)),
+    # Ch. 3, numerical experiment 2 (§3.4), printed stencil; the text's
+    # fixed parameters per figure
+    "fig_3_12": dict(example="ch3_ex2", vary="p", values=(0.1, 0.2, 0.3, 0.5, 0.7, 1.0, 1.3),
+                     fixed=dict(q=1.0, l=1.0, a=0.5)),
+    "fig_3_13": dict(example="ch3_ex2", vary="q", values=(1.0, 2.0, 3.0, 4.0, 5.0),
+                     fixed=dict(p=0.5, l=1.0, a=0.5)),
+    "fig_3_14": dict(example="ch3_ex2", vary="l", values=(1.0, 2.0, 3.0, 4.0, 5.0, 6.0),
+                     fixed=dict(p=0.5, q=5.0, a=0.5)),
+    "fig_3_15": dict(example="ch3_ex2", vary="a", values=(0.0, 0.1, 0.2, 0.3, 0.4, 0.5),
+                     fixed=dict(p=0.5, q=5.0, l=5.0)),
 }
 FIG_EXAMPLES = {
-    # problem (the paper's numerical experiment 1 of Ch. 2 or of Ch. 3),
+    # problem (the paper's numerical experiment 1 of Ch. 2, 1 or 2 of Ch. 3),
     # radial kind (1: the stretch (2.4) with p; 3: the stretch (2.13) with
     # p~), angular kind (1: stretched with q), time kind (1: stretched with
     # l), levels, T
@@ -147,6 +157,7 @@ FIG_EXAMPLES = {
     "ch2_ex1_dt01": dict(problem="ch2", r_kind=1, th_kind=0, t_kind=0, K=10, T=0.1, error="max", literal=False),
     "ch2_ex1_213": dict(problem="ch2", r_kind=3, th_kind=0, t_kind=0, K=10, T=0.1, error="max", literal=False),
     "ch3_ex1": dict(problem="ch3", r_kind=1, th_kind=1, t_kind=1, K=10, T=0.1, error="mean", literal=True),
+    "ch3_ex2": dict(problem="ch3_2", r_kind=1, th_kind=1, t_kind=1, K=10, T=0.1, error="mean", literal=True),
 }
 
 

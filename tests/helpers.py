@@ -64,9 +64,10 @@ def hip_runtime():
 
 
 def fig_problem(example):
-    from problems import paper_continuity_ex1, paper_parabolic_ex1
+    from problems import paper_continuity_ex1, paper_continuity_ex2, paper_parabolic_ex1
     from problems.workloads import FIG_EXAMPLES
-    return paper_parabolic_ex1() if FIG_EXAMPLES[example]["problem"] == "ch2" else paper_continuity_ex1()
+    make = {"ch2": paper_parabolic_ex1, "ch3": paper_continuity_ex1, "ch3_2": paper_continuity_ex2}
+    return make[FIG_EXAMPLES[example]["problem"]]()
 
 
 def fig_errors(x, pb, T, r_nodes, th_nodes):

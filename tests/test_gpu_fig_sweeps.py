@@ -1,7 +1,8 @@
 """The parameter sweeps of the paper's Figs 2.2, 2.5-2.7, 2.9-2.11 (Ch. 2
-§2.3) and Figs 3.5-3.8 (Ch. 3 §3.3, printed stencil) on the GPU: every run
-of the eleven sweeps at m = 19 and 39 (164 instances of uneven size, both
-examples, both radial stretches, θ from 0.5 to 1) is solved as one batch,
+§2.3), Figs 3.5-3.8 (Ch. 3 §3.3) and Figs 3.12-3.15 (Ch. 3 §3.4; printed
+stencil for both) on the GPU: every run of the fifteen sweeps at m = 19 and
+39 (212 instances of uneven size, three examples, both radial stretches, θ
+from 0.5 to 1) is solved as one batch,
 each run's state is held against the oracle element by element, its
 errors against the oracle's stored sweep table, and each sweep's optimum
 against the table's."""
@@ -36,6 +37,22 @@ def gpu_run(pdk, fig, m, n, prm):
     return inst, td, coords
 
 
+def state_bar(ex, n, prm):
+    """The FP64 bar of a run's state against the oracle: 1e-10, or 1e-6
+    where the angular stretch makes the first angular cell smaller than
+    1e-6.  That happens in Ch. 3 experiment 2 at q >= 4 (q = 5: 4e-10 at
+    n = 119, 1e-11 at n = 245).  There the angular couplings next to θ = 0
+    reach 1e19 and more, and a scaled residual of 1e-14 leaves state
+    differences of 1e-8 to 1e-7 between the iterative and the direct
+    solve, and the same in the runs' errors (about 0.18) against the
+    oracle's table; elsewhere the errors agree with the table to 1e-8."""
+    if ex["th_kind"] == 1:
+        first = 2 * np.pi * np.sin((1.0 / n) ** prm["q"] * np.pi / 2)
+        if first < 1e-6:
+            return 1e-6
+    return 1e-10
+
+
 def test_sweeps_batched_match_the_oracle():
     from paper_2509_15879_amd import polardisk as pdk
     with open(GOLDEN) as f:
@@ -46,7 +63,7 @@ def test_sweeps_batched_match_the_oracle():
     st = pdk.solve_batch([b[0] for b in built], [b[1] for b in built])
     assert all(s["status"] == 0 for x in st for s in x)
     got = {}
-    worst_state = worst_err = 0.0
+    worst_state = worst_err = worst_regular = 0.0
     for (fig, m, n, prm), (inst, td, coords) in zip(runs, built):
         x = inst.solution(pdk.LAYOUT_PAPER)
         inst.close()
@@ -58,10 +75,13 @@ def test_sweeps_batched_match_the_oracle():
         e = g[fig]["m"][str(m)]
         de = max(abs(mean / e["mean"][k] - 1), abs(mx / e["max"][k] - 1))
         worst_state, worst_err = max(worst_state, d), max(worst_err, de)
-        assert d <= 1e-10, (fig, m, prm, d)
-        assert de <= 1e-8, (fig, m, prm, de)
+        if state_bar(ex, n, prm) == 1e-10:
+            worst_regular = max(worst_regular, d)
+        assert d <= state_bar(ex, n, prm), (fig, m, prm, d)
+        assert de <= max(1e-8, state_bar(ex, n, prm)), (fig, m, prm, de)
         got.setdefault((fig, m), []).append(mean if ex["error"] == "mean" else mx)
-    say(f"  largest state max-rel vs oracle {worst_state:.2e}, largest error deviation {worst_err:.2e}")
+    say(f"  largest state max-rel vs oracle {worst_state:.2e} (regular meshes {worst_regular:.2e}), "
+        f"largest error deviation {worst_err:.2e}")
     for (fig, m), errs in got.items():
         best = FIG_SWEEPS[fig]["values"][int(np.argmin(errs))]
         say(f"  {fig} m={m}: best {FIG_SWEEPS[fig]['vary']} = {best}")
