@@ -72,6 +72,55 @@ def test_vcycle_with_zero_flux_boundary():
     inst.close()
 
 
+def test_vcycle_with_upwind_drift():
+    """Upwind face pairs (gp and gm not symmetric about G): the merged
+    faces and the coarse systems follow them."""
+    from paper_2509_15879_amd import polardisk as pdk
+    m, n = 28, 90
+    say(f"[mg] {m}x{n} upwind continuity: GPU V-cycle vs oracle")
+    pb = continuity_cfg(7160, m, n, 0.5, 1.3)
+    me = make_mesh(m, n, 1, 1.3)
+    S = assemble(me, sample(pb, *me.sample_points()), flux=1)
+    md = pdk.mesh_desc(m, n, pdk.MESH_SINE, 1.3)
+    inst = pdk.Instance(md, sample(pb, *pdk.mesh_coords(md)), pdk.PD_FP64, flux=1)
+    pdk.set_preconditioner(inst, pdk.PRECOND_MG)
+    MG = MultigridPreconditioner(S, 5e-4, 0.75)
+    y = np.random.default_rng(9).standard_normal(S.N)
+    err = max_rel(inst.precondition(y, 5e-4, 0.75, layout=pdk.LAYOUT_PAPER), MG(y))
+    say(f"  levels {[lv.n for lv in MG.levels]}, max-rel {err:.2e}")
+    assert err <= 1e-6
+    inst.close()
+
+
+def test_adaptive_steps_with_the_vcycle():
+    """A-posteriori step control with the V-cycle: its coarse levels are
+    refactored whenever Δt moves (the instance's own gate), and the run
+    takes the same steps as with the line sweeps (the step control reads
+    error estimates of solutions that agree to the solve's tolerance, so
+    the levels agree to about 1e-8 relative) and reaches the same state."""
+    from paper_2509_15879_amd import polardisk as pdk
+    m, n = 40, 100
+    say(f"[mg] adaptive steps {m}x{n}: V-cycle vs line sweeps")
+    pb = continuity_cfg(7170, m, n, 1.0, 1.3)
+    md = pdk.mesh_desc(m, n, pdk.MESH_SINE, 1.3)
+    data = sample(pb, *pdk.mesh_coords(md))
+    runs = {}
+    for kind in (pdk.PRECOND_LINE, pdk.PRECOND_MG):
+        inst = pdk.Instance(md, data, pdk.PD_FP64)
+        pdk.set_preconditioner(inst, kind)
+        st = pdk.taken(inst.solve(pdk.adaptive_time_desc(1.0, 0.02, 1e-5, 1e-6, 1e-6, 2e-3, tol=1e-13)))
+        runs[kind] = (np.array([s["t"] for s in st]), sum(s["iters"] for s in st), inst.solution())
+        say(f"  precond {kind}: {len(st)} steps, {runs[kind][1]} iterations")
+        assert all(s["status"] == 0 for s in st)
+        inst.close()
+    (t0, i0, x0), (t1, i1, x1) = runs[pdk.PRECOND_LINE], runs[pdk.PRECOND_MG]
+    say(f"  levels differ by {np.max(np.abs(t0 - t1)) / t0[-1]:.1e} (relative to T), "
+        f"states by {max_rel(x1, x0):.1e}")
+    assert len(t0) == len(t1) and np.max(np.abs(t0 - t1)) <= 1e-6 * t0[-1]
+    assert max_rel(x1, x0) <= 1e-7
+    assert i1 < i0
+
+
 @pytest.mark.parametrize("form", ["reaction", "printed"])
 def test_vcycle_with_a_reaction_term(form):
     """Levels that carry a reaction (volume-averaged when lines merge; the
