@@ -797,7 +797,7 @@ def batch_variant(pdk, stream, tol):
     return out
 
 
-def main():
+def arg_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -812,7 +812,11 @@ def main():
                     help="groups,cycles_per_graph,stencil_rings: use this schedule instead of tuning "
                          "(e.g. to profile the schedule an un-profiled run chose)")
     ap.add_argument("--cpu-baseline-worker", nargs=2, default=None, help=argparse.SUPPRESS)
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = arg_parser().parse_args()
     if args.cpu_baseline_worker:
         cpu_baseline_worker(int(args.cpu_baseline_worker[0]), args.cpu_baseline_worker[1])
         return

@@ -21,7 +21,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def main():
+def arg_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--levels", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=256)
@@ -31,7 +31,11 @@ def main():
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--schedule", default=None,
                     help="groups,cycles_per_graph,stencil_rings of the run (e.g. the one bench.py tuned)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = arg_parser().parse_args()
     os.environ["PD_NO_GRAPH"] = "1"
 
     import torch
