@@ -117,6 +117,11 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: the HIP library has not been built "
                           "(python -m paper_2509_15879_amd.build)")
+    # One HIP runtime per process: torch's is loaded first, so that the
+    # library binds to it and shares its device, streams and memory (loaded
+    # the other way round, a second runtime comes in beside torch's and
+    # finds no device).
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I32, D, U64, SZ = C.c_void_p, C.c_int32, C.c_double, C.c_uint64, C.c_size_t
     sig = {
