@@ -60,9 +60,18 @@ KERNEL_NAMES = {
 TRAFFIC = {
     "cfg3_fp64": {
         "sha1": "6bc4b8abe6894ef49f1ea3b4c1e356097a1a2160",
+        "w": 8,
         "stencil_rings": 8,
         "b_per_cell": {"rad_p": 52.95, "ang_p": 32.23, "sten_v": 65.13, "rad_s": 44.16, "ang_s": 32.23,
                        "sten_t": 64.88, "update": 64.34},
+    },
+    # the FP32 inner cycle of the same instance in mixed precision
+    "cfg3_mixed": {
+        "sha1": "6bc4b8abe6894ef49f1ea3b4c1e356097a1a2160",
+        "w": 4,
+        "stencil_rings": 8,
+        "b_per_cell": {"rad_p": 32.24, "ang_p": 24.22, "sten_v": 37.96, "rad_s": 28.14, "ang_s": 24.22,
+                       "sten_t": 37.92, "update": 32.26},
     },
 }
 
@@ -155,9 +164,19 @@ def mixed_cfg3_variant(pdk, stream, tol, ref):
         torch.cuda.synchronize()
         best = min(best, time.perf_counter() - t0)
     x = inst.solution(pdk.LAYOUT_PAPER)
+    inner = int(sum(s["iters"] for s in st))
+
+    def run_step():
+        inst.set_solution(u0, 0.0)
+        inst.solve(desc)
+
+    # the FP32 inner cycle's dominant kernel, on one more, event-stamped run
+    roof = roofline_of(pdk, run_step, 4, cells * inner, TRAFFIC.get("cfg3_mixed"), instance_iters=inner,
+                       stencil_rings=tuned["best"][2])
     inst.close()
     return {"value": round(cells * c["K"] / best, 1), "ms": round(1e3 * best, 1), "tol_per_step": tol,
             "schedule": list(tuned["best"]), "autotune_ms_whole_solves": tuned["ms"],
+            "roofline": roof,
             "vs_oracle": vs_oracle_samples(x, ref, c["K"]),
             "inner_iters_per_level": round(float(np.mean([s["iters"] for s in st])), 2),
             "refinements_per_level": round(float(np.mean([s["refinements"] for s in st])), 2)}

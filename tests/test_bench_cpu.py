@@ -43,7 +43,7 @@ def test_traffic_table_covers_every_cycle_kernel():
         assert len(tab["sha1"]) == 40
         for fam, b in tab["b_per_cell"].items():
             # measured bytes are at least the algorithmic ones, and not wildly above
-            alg = bench.bytes_per_cell(fam, 8)
+            alg = bench.bytes_per_cell(fam, tab["w"])
             assert alg <= b <= 1.25 * alg, (name, fam, b, alg)
 
 

@@ -1,8 +1,7 @@
 """The committed profiler summaries stay reproducible (no GPU): every command
 they give runs committed files with options those files accept, each
 summary names the source SHA-1 it was measured on, and the HBM-traffic
-summary of the headline instance is the one bench.py's traffic table was
-taken from."""
+summaries are the ones bench.py's traffic tables were taken from."""
 
 import glob
 import os
@@ -54,9 +53,11 @@ def test_each_summary_names_its_source_sha(path):
     assert SHA.search(open(path).read()), "a summary names the kernel_source_sha1 it was measured on"
 
 
-def test_traffic_table_comes_from_the_headline_traffic_summary():
-    text = open(os.path.join(ROOT, "profiles", "cycle_kernels_cfg3_1024x2048_hbm_traffic.txt")).read()
-    t = bench.TRAFFIC["cfg3_fp64"]
+@pytest.mark.parametrize("key,summary", [("cfg3_fp64", "cycle_kernels_cfg3_1024x2048_hbm_traffic.txt"),
+                                         ("cfg3_mixed", "cycle_kernels_cfg3_mixed_1024x2048_hbm_traffic.txt")])
+def test_traffic_tables_come_from_their_summaries(key, summary):
+    text = open(os.path.join(ROOT, "profiles", summary)).read()
+    t = bench.TRAFFIC[key]
     assert t["sha1"] in SHA.findall(text)
     for fam, b in t["b_per_cell"].items():
         row = re.search(rf"^{fam}\s+\d+\s+[\d.]+\s+[\d.]+\s+[\d.]+\s+([\d.]+)", text, re.M)
