@@ -721,18 +721,28 @@ def cfg3_desc(pdk, tol, K=None):
     return pdk.time_desc(c["theta"], K, c["dt"] * K, pdk.TIME_UNIFORM, tol=tol, max_seconds=120.0)
 
 
-def roofline_of(pdk, run_step, w, cells_iters, traffic_table, instance_iters=None, stencil_rings=None):
-    """Event-stamped extra step: per-family launch times; the dominant
+def roofline_of(pdk, run_step, w, cells_iters, traffic_table, instance_iters=None, stencil_rings=None,
+                repeats=2):
+    """Event-stamped extra steps: per-family launch times; the dominant
     kernel's algorithmic bytes per launch over its average launch time.
-    instance_iters (one instance): the share of the p-sweep launches that
-    found the instance iterating (the rest wait for the next round head).
-    The counter-measured traffic applies only to the sources it was taken
-    on, and a stencil's only to the tile depth it was taken at."""
-    pdk.kernel_timing(True, reset=True)
-    t0 = time.perf_counter()
-    run_step()
-    prof_ms = 1e3 * (time.perf_counter() - t0)
-    kms, kcnt = pdk.kernel_timing(False, reset=True)
+    Of `repeats` such steps the one with the least total cycle-kernel time
+    is kept (a step that something else on the machine slowed down would
+    otherwise stand for the kernels).  instance_iters (one instance): the
+    share of the p-sweep launches that found the instance iterating (the
+    rest wait for the next round head).  The counter-measured traffic
+    applies only to the sources it was taken on, and a stencil's only to
+    the tile depth it was taken at."""
+    best = None
+    for _ in range(max(1, repeats)):
+        pdk.kernel_timing(True, reset=True)
+        t0 = time.perf_counter()
+        run_step()
+        ms = 1e3 * (time.perf_counter() - t0)
+        km, kc = pdk.kernel_timing(False, reset=True)
+        tot = sum(km[f] for f in KERNEL_NAMES)
+        if best is None or tot < best[0]:
+            best = (tot, ms, km, kc)
+    _, prof_ms, kms, kcnt = best
     fam_bytes = {f: cells_iters * bytes_per_cell(f, w) for f in KERNEL_NAMES}
     dom = max(fam_bytes, key=lambda f: kms[f])
     achieved = fam_bytes[dom] / (kms[dom] / 1e3) / 1e9
@@ -751,7 +761,8 @@ def roofline_of(pdk, run_step, w, cells_iters, traffic_table, instance_iters=Non
         "kernel_launches": {f: int(kcnt[f]) for f in kms if kcnt[f] > 0},
         "kernel_ms": {k: round(v, 2) for k, v in kms.items()},
         "profiled_step_ms": round(prof_ms, 1),
-        "measured_on": "an extra step, each launch stamped by its own start/stop events",
+        "measured_on": (f"the faster of {max(1, repeats)} extra steps (total cycle-kernel time), each launch "
+                        "stamped by its own start/stop events"),
         **({"active_launch_fraction": round(instance_iters / max(1, kcnt["rad_p"]), 4)}
            if instance_iters is not None else {}),
     }
