@@ -90,3 +90,37 @@ def test_algorithmic_bytes_of_one_iteration():
     assert sum(bench.bytes_per_cell(f, 8) for f in fams) == 336
     # FP32 inner iteration (the stencils also read their FP32 1/diag copy)
     assert sum(bench.bytes_per_cell(f, 4) for f in fams) == 204
+
+
+class _FakeTiming:
+    """Stands in for the binding's kernel timing: each extra step reports
+    the per-family times given, in turn."""
+
+    FAMS = ("begin", "factor", "rad_p", "ang_p", "sten_v", "rad_s", "ang_s", "sten_t", "update",
+            "refine", "control", "level_end", "multigrid")
+
+    def __init__(self, runs):
+        self.runs = list(runs)
+        self.k = -1
+
+    def kernel_timing(self, enable, reset=False):
+        if enable:
+            self.k += 1
+            return {}, {}
+        ms = {f: self.runs[self.k].get(f, 0.0) for f in self.FAMS}
+        cnt = {f: (100 if ms[f] > 0 else 0) for f in self.FAMS}
+        return ms, cnt
+
+
+def test_roofline_keeps_the_faster_extra_step():
+    fast = {f: 1.0 for f in bench.KERNEL_NAMES}
+    fast["rad_p"] = 2.0
+    slow = dict(fast, rad_p=3.0)
+    for runs in ([slow, fast], [fast, slow]):
+        fake = _FakeTiming(runs)
+        r = bench.roofline_of(fake, lambda: None, 8, 1000000, None, repeats=2)
+        assert r["kernel"] == bench.KERNEL_NAMES["rad_p"]
+        assert r["kernel_ms"]["rad_p"] == 2.0
+        # 52 B per unknown over 2 ms
+        assert abs(r["achieved"] - 52e6 / 2e-3 / 1e9) < 0.1
+        assert r["traffic"] is None
